@@ -1,0 +1,98 @@
+"""Pins of the oracle's Metropolis VMC and fixed-node DMC walks (Sec. 2.3).
+
+VMC energies of one-parameter trial functions have closed forms:
+  H,  exp(-a r^2), a = 8/(9 pi):             E = 3a/2 - 2 sqrt(2a/pi) = -4/(3 pi)
+  He, exp(-z r1 - z r2), z = 27/16:           E = z^2 - 27 z / 8 = -(27/16)^2
+  He, exp(-a r1^2 - a r2^2), optimal a:       E = 3a - (8 sqrt2 - 2) sqrt(a/pi) = -3a
+DMC of a nodeless one-electron problem is exact (no fixed-node error): H with
+a Gaussian trial function projects to -1/2 up to time-step error; with the
+exact trial function every weight stays 1 and the population is constant.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import systems as S
+
+CLOSED = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+def _vmc_mean(o, R0, steps, burn, seed, step_size, all_electron):
+    b = o.vmc(R0, burn, seed, 0, step_size, all_electron)
+    R = b["R"]
+    r = o.vmc(R, steps, seed, burn, step_size, all_electron)
+    per_walker = r["e_sum"] / steps
+    return per_walker.mean(), per_walker.std(ddof=1) / math.sqrt(len(per_walker)), r
+
+
+def test_vmc_hydrogen_gaussian_energy(oracle_mod):
+    a = 8 / (9 * math.pi)
+    o = oracle_mod.Oracle(S.hydrogen_gaussian(a))
+    R0 = np.random.default_rng(1).normal(size=(2000, 1, 3))
+    m, s, r = _vmc_mean(o, R0, 200, 100, 11, 1.0, True)
+    assert abs(m - CLOSED["hydrogen_gaussian_opt_energy"]) < 3 * s, (m, s)
+    assert 0.2 < r["n_acc"].sum() / (2000 * 200) < 0.9
+
+
+def test_vmc_helium_sto_energy(oracle_mod):
+    o = oracle_mod.Oracle(S.helium_sto(CLOSED["helium_sto_opt_zeta"]))
+    R0 = np.random.default_rng(2).normal(scale=0.6, size=(1000, 2, 3))
+    m, s, _ = _vmc_mean(o, R0, 200, 100, 12, 0.6, False)
+    assert abs(m - CLOSED["helium_sto_opt_energy"]) < 3 * s, (m, s)
+
+
+def test_vmc_helium_gaussian_energy(oracle_mod):
+    o = oracle_mod.Oracle(S.helium_gaussian(CLOSED["helium_gaussian_opt_alpha"]))
+    R0 = np.random.default_rng(3).normal(scale=0.6, size=(1000, 2, 3))
+    m, s, _ = _vmc_mean(o, R0, 200, 100, 13, 0.8, False)
+    assert abs(m - CLOSED["helium_gaussian_opt_energy"]) < 3 * s, (m, s)
+
+
+def test_vmc_exact_orbital_zero_variance(oracle_mod):
+    o = oracle_mod.Oracle(S.hydrogen_sto_1s(1.0))
+    R0 = np.random.default_rng(4).normal(size=(200, 1, 3))
+    r = o.vmc(R0, 50, 5, 0, 1.0, True)
+    np.testing.assert_allclose(r["e_sum"] / 50, -0.5, atol=1e-13)
+    np.testing.assert_allclose(r["e2_sum"] / 50 - (r["e_sum"] / 50) ** 2, 0.0, atol=1e-12)
+
+
+def test_vmc_is_deterministic_in_the_seed(oracle_mod):
+    sysd = S.h2_heitler_london()
+    o = oracle_mod.Oracle(sysd)
+    R0 = S.initial_walkers(sysd, 64, seed=3)
+    a = o.vmc(R0, 20, 99, 0, 0.5, True)
+    b = o.vmc(R0, 20, 99, 0, 0.5, True)
+    np.testing.assert_array_equal(a["R"], b["R"])
+    np.testing.assert_array_equal(a["e_sum"], b["e_sum"])
+    c = o.vmc(R0, 20, 98, 0, 0.5, True)
+    assert not np.array_equal(a["R"], c["R"])
+
+
+def test_dmc_exact_trial_function_keeps_population(oracle_mod):
+    o = oracle_mod.Oracle(S.hydrogen_sto_1s(1.0))
+    R0 = np.random.default_rng(5).normal(size=(300, 1, 3))
+    e0 = o.evaluate(R0)["eloc"]
+    r = o.dmc(R0, e0, 40, 21, 0, 0.01, -0.5, 300)
+    assert r["rc"] == 0
+    np.testing.assert_array_equal(r["pop"], 300)
+    np.testing.assert_allclose(r["wsum"], 300, rtol=1e-13)
+    np.testing.assert_allclose(r["wesum"] / r["wsum"], -0.5, atol=1e-13)
+
+
+def test_dmc_nodeless_projection_reaches_exact_energy(oracle_mod):
+    """Gaussian trial (VMC energy -0.424) projects to the exact -0.5 within the time-step error."""
+    o = oracle_mod.Oracle(S.hydrogen_gaussian(0.3))
+    R0 = np.random.default_rng(6).normal(size=(1000, 1, 3))
+    e0 = o.evaluate(R0)["eloc"]
+    r = o.dmc(R0, e0, 200, 31, 0, 0.01, float(e0.mean()), 1000)
+    assert r["rc"] == 0
+    r2 = o.dmc(r["R"], r["eloc"], 300, 31, 200, 0.01, r["e_trial"], 1000)
+    assert r2["rc"] == 0
+    blk = (r2["wesum"] / r2["wsum"]).reshape(30, 10).mean(1)
+    m, s = blk.mean(), blk.std(ddof=1) / math.sqrt(len(blk))
+    assert abs(m + 0.5) < 3 * s + 0.005, (m, s)
+    assert np.all(np.abs(r2["pop"] / 1000 - 1) < 0.1)
