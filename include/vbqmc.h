@@ -1,0 +1,254 @@
+/*
+ * vbqmc.h -- C ABI of the MI355X (gfx950) library for the Jastrow-Valence-Bond
+ * (JVB) quantum Monte Carlo hot path.
+ *
+ * Method: Radenkovic, Domin, Toulouse, Braida, "The Valence-Bond Quantum Monte
+ * Carlo Method" (2022).  Each entry point below names the passage that defines
+ * what it computes.
+ *
+ * Conventions (all entry points)
+ *   - Atomic units: bohr, hartree.
+ *   - Electrons 0 .. n_up-1 are spin up, n_up .. N-1 spin down; spins are
+ *     fixed (Sec. 2.3.1).
+ *   - Device pointers are marked [dev], host pointers [host].  Arrays are
+ *     row-major; positions are [walker][electron][xyz] FP64.
+ *   - The wave function is reported as ln|Psi| plus a sign, never as Psi.
+ *   - Every call is ordered on the given HIP stream (NULL = default stream)
+ *     and may return before the device work finishes; asynchronous device
+ *     faults surface at the next synchronising call.
+ *   - Return value: 0 on success, a negative VBQMC_E* code otherwise; the
+ *     message is available from vbqmc_last_error(ctx).  No C++ exception
+ *     crosses this interface.
+ *   - A context is not re-entrant: use one context per host thread/stream.
+ *   - Ownership: the library copies every host array passed to
+ *     vbqmc_create / vbqmc_set_params; it never frees caller memory.  Device
+ *     memory for walker states, outputs and workspaces is always the
+ *     caller's; the library allocates only its own small constant tables at
+ *     vbqmc_create and frees them at vbqmc_destroy.
+ */
+#ifndef VBQMC_H
+#define VBQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vbqmc_ctx vbqmc_ctx;
+typedef struct ihipStream_t* vbqmc_stream; /* a hipStream_t */
+
+enum {
+  VBQMC_OK = 0,
+  VBQMC_EINVAL = -1,     /* bad argument or unsupported system shape */
+  VBQMC_ENOMEM = -2,     /* host or device allocation failed (create only) */
+  VBQMC_EWORKSPACE = -3, /* caller buffer too small */
+  VBQMC_EHIP = -4,       /* a HIP runtime call failed */
+  VBQMC_ESINGULAR = -5,  /* a reference determinant is exactly singular */
+  VBQMC_ENONFINITE = -6, /* non-finite input or Psi = 0 */
+  VBQMC_EPOPULATION = -7 /* DMC population empty or above capacity */
+};
+
+enum { VBQMC_FP64 = 0, VBQMC_FP32 = 1, VBQMC_BF16 = 2 };
+
+/* Nuclei and electron counts (Sec. 2.1; Hamiltonian of Sec. 2.3.1). */
+typedef struct {
+  int32_t n_nuclei;
+  const double* charge;   /* [host] [n_nuclei] */
+  const double* position; /* [host] [n_nuclei][3] */
+  int32_t n_up, n_dn;
+} vbqmc_system;
+
+/*
+ * The JVB wave function Psi = J * sum_I c_I Phi_I (Sec. 2.1, Eq. PsiJVBSCF).
+ *
+ * Basis (Sec. 2.1): shells of kind 0 (Gaussian: sum_k c_k exp(-a_k r^2)) or
+ * 1 (Slater: sum_k c_k exp(-a_k r)) times the unnormalised angular set
+ * l=0: 1; l=1: x, y, z; l=2: xy, yz, zx, x^2-y^2, 3z^2-r^2.  Basis functions
+ * are numbered shell by shell in that order (M in total).
+ * Orbitals: phi_p = sum_mu lambda[p][mu] chi_mu, lambda is [n_orbitals][M].
+ * Structures (Eq. PhiI): structure I is the unit-weight sum of its HLSP
+ * terms; a term lists inactive (doubly occupied) orbitals, singlet pairs
+ * (i, j) (i == j allowed) and unpaired spin-up orbitals.  term_counts[3t..]
+ * = (n_inactive, n_pairs, n_unpaired) and term_orbitals concatenates, per
+ * term, inactive[], pairs[2*n_pairs], unpaired[].
+ * Jastrow (Sec. 2.1): f_en + f_ee pair terms
+ *   u(r) = a R/(1 + b R) + sum_{p=2..5} q_p R^p,  R = r/(1 + kappa r),
+ * ee = {a_anti, a_par, b_anti, b_par, b3, b4, b5, b6} (a fixed by the cusp
+ * conditions), en = [n_nuclei][6] = {a1, a2, a3, a4, a5, a6}.
+ */
+typedef struct {
+  int32_t n_shells;
+  const int32_t* shell_center; /* [host] nucleus index per shell */
+  const int32_t* shell_kind;   /* [host] 0 Gaussian, 1 Slater */
+  const int32_t* shell_l;      /* [host] 0, 1 or 2 */
+  const int32_t* shell_nprim;  /* [host] primitives per shell */
+  const double* prim_exp;      /* [host] concatenated exponents */
+  const double* prim_coef;     /* [host] concatenated coefficients */
+  int32_t n_orbitals;
+  const double* lambda;        /* [host] [n_orbitals][M] */
+  int32_t n_structures;
+  const double* coef;          /* [host] c_I */
+  int32_t n_terms;
+  const int32_t* term_structure; /* [host] [n_terms] */
+  const int32_t* term_counts;    /* [host] [n_terms][3] */
+  const int32_t* term_orbitals;  /* [host] concatenated, see above */
+  double kappa;
+  double ee[8];
+  const double* en;              /* [host] [n_nuclei][6] */
+} vbqmc_wavefunction;
+
+/* precision: VBQMC_FP64 (all FP64), VBQMC_FP32 or VBQMC_BF16 (basis values
+ * and the basis->orbital contraction in that type with FP32 accumulation;
+ * determinants, inverse refresh, determinant and structure sums in FP64).
+ * refresh_every: accepted single-electron updates per spin after which the
+ * reference inverse is rebuilt by a fresh factorisation (default 32). */
+typedef struct {
+  int32_t precision;
+  int32_t refresh_every;
+} vbqmc_options;
+
+typedef struct {
+  int32_t n_electrons, n_up, n_dn, n_nuclei;
+  int32_t n_basis, n_orbitals, n_structures;
+  int32_t n_determinants;        /* distinct (up, down) determinant pairs */
+  int32_t n_unique_up, n_unique_dn; /* distinct spin determinants */
+  int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei */
+  int32_t block_threads;         /* threads per walker in the walker kernels */
+  int64_t walker_state_bytes;    /* bytes per walker record */
+  int64_t lds_bytes;             /* LDS bytes per walker block */
+} vbqmc_info_t;
+
+/* Build a context: expands the HLSP structures into determinants (Eq. PhiI,
+ * N_det,I = 2^{N_pairs}), picks the reference determinant per spin and
+ * uploads the constant tables.  Errors: EINVAL (inconsistent counts, more than
+ * 3 orbitals of a determinant differing from its spin's reference, sizes
+ * above the kernel limits: 64 electrons per spin, 1024 basis functions),
+ * ENOMEM, EHIP. */
+int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wf, const vbqmc_options* opt,
+                 vbqmc_ctx** out);
+void vbqmc_destroy(vbqmc_ctx* ctx);
+const char* vbqmc_last_error(const vbqmc_ctx* ctx);
+int vbqmc_get_info(const vbqmc_ctx* ctx, vbqmc_info_t* out);
+
+/* Replace the variational parameters p = [c (n_structures) | lambda
+ * (n_orbitals*M, row-major) | b_anti, b_par, b3..b6 | per nucleus a1..a6]
+ * (Sec. 2.2, Eq. PsiJVBp with the orbital coefficients varied directly).
+ * p is [host][n_params].  Existing walker states become stale: re-run
+ * vbqmc_walkers_init. */
+int vbqmc_set_params(vbqmc_ctx* ctx, const double* p);
+int vbqmc_get_params(const vbqmc_ctx* ctx, double* p);
+
+/*
+ * Evaluate ln|Psi|, sign, grad_i ln|Psi|, the local energy E_L = H Psi / Psi
+ * and the structure ratios r_I = Phi_I / sum_J c_J Phi_J for W fixed
+ * configurations (Sec. 2.1 for Psi, Sec. 2.3.1 Eq. Elav for E_L,
+ * Sec. 2.4 for r_I).  Each determinant ratio is computed from a fresh LU of
+ * the reference determinant.  R [dev][W][N][3]; logabs [dev][W];
+ * sign [dev][W] (0 where Psi = 0); grad [dev][W][N][3] or NULL;
+ * eloc [dev][W] or NULL; ratio [dev][W][n_structures] or NULL.
+ */
+int vbqmc_evaluate(vbqmc_ctx* ctx, int64_t W, const double* R, double* logabs, int32_t* sign,
+                   double* grad, double* eloc, double* ratio, vbqmc_stream stream);
+
+/* Walker records: opaque, walker_state_bytes each, caller-allocated [dev].
+ * init fills records from positions R [dev][W][N][3] (fresh factorisations,
+ * local energy); positions copies R back out of the records. */
+int vbqmc_walkers_init(vbqmc_ctx* ctx, int64_t W, const double* R, void* state, vbqmc_stream stream);
+int vbqmc_walkers_positions(vbqmc_ctx* ctx, int64_t W, const void* state, double* R,
+                            vbqmc_stream stream);
+/* Per-walker local energies of the records [dev][W] (the value at the last
+ * init / step). */
+int vbqmc_walkers_eloc(vbqmc_ctx* ctx, int64_t W, const void* state, double* eloc, vbqmc_stream stream);
+
+/* VMC accumulators, all [dev] and accumulated into (+=), per walker:
+ * e_sum/e2_sum: sums of E_L and E_L^2 over steps; n_accept: accepted moves;
+ * e_last: E_L after the last step; sij_sum [W][n_structures]^2 or NULL:
+ * sums of r_I r_J (the estimator of S_IJ, Sec. 2.4). */
+typedef struct {
+  double* e_sum;
+  double* e2_sum;
+  double* n_accept;
+  double* e_last;
+  double* sij_sum;
+} vbqmc_vmc_acc;
+
+/*
+ * Metropolis VMC (Sec. 2.3.1): n_steps steps for W walkers, each step being
+ * one all-electron move (all_electron != 0) or N single-electron moves in
+ * electron order, followed by E_L.  Proposal r' = r + step_size (2u - 1) per
+ * component, accepted iff u' < |Psi'/Psi|^2.  Random numbers: Philox4x32-10,
+ * key = seed, counter = (walker, step0 + s, 4*electron + purpose, draw)
+ * (purpose 0 proposal, 1 acceptance).  Single-electron moves update the
+ * reference inverse and determinant table by Sherman-Morrison; the inverse is
+ * rebuilt every refresh_every accepted updates.  state [dev] is updated in
+ * place.
+ */
+int vbqmc_vmc_advance(vbqmc_ctx* ctx, void* state, int64_t W, int32_t n_steps, uint64_t seed,
+                      uint64_t step0, double step_size, int32_t all_electron, const vbqmc_vmc_acc* acc,
+                      vbqmc_stream stream);
+
+/* DMC per-step records, each [dev][n_steps]: population before branching,
+ * sum of weights, sum of weight * E_L, trial energy used, accepted and
+ * proposed single-electron moves. */
+typedef struct {
+  double* pop;
+  double* wsum;
+  double* wesum;
+  double* etrial;
+  double* n_accept;
+  double* n_prop;
+} vbqmc_dmc_log;
+
+/*
+ * Fixed-node DMC (Sec. 2.3.2, Eq. E0DMCweights): per step each walker makes N
+ * drift-diffusion single-electron moves r' = r + tau v + sqrt(tau) chi with
+ * v = grad_i ln|Psi|, accepted with min(1, |Psi'/Psi|^2 G(r<-r')/G(r'<-r)),
+ * rejected outright if the sign of Psi changes; then weight
+ * w = exp(-tau ((E_L + E_L')/2 - E_T)) with E_L clipped to E_T +- 10/sqrt(tau),
+ * floor(w + u) copies (at most 3, children of weight 1, parents' order kept,
+ * compaction on the device) and E_T = E_est - (0.1/tau) ln(W/W_target) with
+ * E_est the running weighted mean of E_L of this call.  Random numbers as VMC
+ * plus purpose 2 (branching, electron index N); the walker index is the slot
+ * after compaction.  states: two [dev] buffers of capacity records; the
+ * population lives in states[0] on entry and on return.  W_io [host] in/out;
+ * e_trial_io [host] in/out.  workspace [dev] of vbqmc_dmc_workspace_bytes.
+ * Error EPOPULATION if the population reaches 0 or exceeds capacity (the
+ * states are then left at the last good step).
+ */
+int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* ctx, int64_t capacity, int32_t n_steps, size_t* bytes);
+int vbqmc_dmc_advance(vbqmc_ctx* ctx, void* states[2], int64_t* W_io, int64_t capacity, int32_t n_steps,
+                      uint64_t seed, uint64_t step0, double tau, double* e_trial_io, int64_t W_target,
+                      const vbqmc_dmc_log* log, void* workspace, size_t workspace_bytes,
+                      vbqmc_stream stream);
+
+/*
+ * Parameter derivatives for W fixed configurations (Sec. 2.2, Eqs. Hi0, H0j):
+ * dlogpsi[w][j] = d ln|Psi| / d p_j and deloc[w][j] = d E_L / d p_j, parameter
+ * order as vbqmc_set_params.  Computed by a hand-written adjoint (reverse)
+ * pass that recomputes every spin-determinant inverse; the orbital part is an
+ * MFMA contraction of adjoint orbital rows with basis rows.  R [dev][W][N][3];
+ * outputs [dev][W][n_params].  workspace [dev] of vbqmc_param_grad_workspace_bytes.
+ */
+int vbqmc_param_grad_workspace_bytes(const vbqmc_ctx* ctx, int64_t W, size_t* bytes);
+int vbqmc_param_grad(vbqmc_ctx* ctx, int64_t W, const double* R, double* dlogpsi, double* deloc,
+                     void* workspace, size_t workspace_bytes, vbqmc_stream stream);
+
+/* Deterministic fixed-order sum over walkers: out[k] = sum_w in[w][k],
+ * in [dev][W][K], out [dev][K]. */
+int vbqmc_reduce_walkers(vbqmc_ctx* ctx, int64_t W, int32_t K, const double* in, double* out,
+                         vbqmc_stream stream);
+
+/* Structure weights from the overlap estimate S [host][n][n] (Sec. 2.4):
+ * Chirgwin-Coulson w_I = c_I (S c)_I / c.S.c and Loewdin
+ * w_K = cbar_K^2 / |cbar|^2 with cbar = S^{1/2} c (symmetric square root by a
+ * Jacobi eigensolver).  Host-only; EINVAL for n < 1 or a non-positive norm. */
+int vbqmc_weights_chirgwin_coulson(int32_t n, const double* S, const double* c, double* w);
+int vbqmc_weights_lowdin(int32_t n, const double* S, const double* c, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBQMC_H */

@@ -1,0 +1,357 @@
+"""Python binding of libvbqmc (the MI355X JVB QMC library).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI of ``include/vbqmc.h``.  PyTorch supplies device memory and
+the current HIP stream.  The binding refuses to run without the built
+library; there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvbqmc.so")
+
+FP64, FP32, BF16 = 0, 1, 2
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_L_NFUNC = {0: 1, 1: 3, 2: 5}
+
+_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE", -4: "EHIP", -5: "ESINGULAR", -6: "ENONFINITE",
+           -7: "EPOPULATION"}
+
+
+class VBQMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("n_nuclei", ctypes.c_int32), ("charge", ctypes.POINTER(ctypes.c_double)),
+                ("position", ctypes.POINTER(ctypes.c_double)), ("n_up", ctypes.c_int32),
+                ("n_dn", ctypes.c_int32)]
+
+
+class _Wavefunction(ctypes.Structure):
+    _fields_ = [("n_shells", ctypes.c_int32), ("shell_center", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_kind", ctypes.POINTER(ctypes.c_int32)), ("shell_l", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_nprim", ctypes.POINTER(ctypes.c_int32)), ("prim_exp", ctypes.POINTER(ctypes.c_double)),
+                ("prim_coef", ctypes.POINTER(ctypes.c_double)), ("n_orbitals", ctypes.c_int32),
+                ("lambda_", ctypes.POINTER(ctypes.c_double)), ("n_structures", ctypes.c_int32),
+                ("coef", ctypes.POINTER(ctypes.c_double)), ("n_terms", ctypes.c_int32),
+                ("term_structure", ctypes.POINTER(ctypes.c_int32)),
+                ("term_counts", ctypes.POINTER(ctypes.c_int32)),
+                ("term_orbitals", ctypes.POINTER(ctypes.c_int32)), ("kappa", ctypes.c_double),
+                ("ee", ctypes.c_double * 8), ("en", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("refresh_every", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_electrons", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("n_nuclei", ctypes.c_int32), ("n_basis", ctypes.c_int32), ("n_orbitals", ctypes.c_int32),
+                ("n_structures", ctypes.c_int32), ("n_determinants", ctypes.c_int32),
+                ("n_unique_up", ctypes.c_int32), ("n_unique_dn", ctypes.c_int32), ("n_params", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("walker_state_bytes", ctypes.c_int64),
+                ("lds_bytes", ctypes.c_int64)]
+
+
+class _VmcAcc(ctypes.Structure):
+    _fields_ = [("e_sum", ctypes.c_void_p), ("e2_sum", ctypes.c_void_p), ("n_accept", ctypes.c_void_p),
+                ("e_last", ctypes.c_void_p), ("sij_sum", ctypes.c_void_p)]
+
+
+class _DmcLog(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("wesum", ctypes.c_void_p),
+                ("etrial", ctypes.c_void_p), ("n_accept", ctypes.c_void_p), ("n_prop", ctypes.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info", "vbqmc_set_params",
+           "vbqmc_get_params", "vbqmc_evaluate", "vbqmc_walkers_init", "vbqmc_walkers_positions",
+           "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance",
+           "vbqmc_param_grad_workspace_bytes", "vbqmc_param_grad", "vbqmc_reduce_walkers",
+           "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin"]
+
+
+def load_library(path=LIB_PATH):
+    """Load libvbqmc.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libvbqmc.so not found at {path}: build it with "
+                           "`python -m paper_2207_14715_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    lib.vbqmc_create.argtypes = [ctypes.POINTER(_System), ctypes.POINTER(_Wavefunction),
+                                 ctypes.POINTER(_Options), ctypes.POINTER(vp)]
+    lib.vbqmc_destroy.argtypes = [vp]
+    lib.vbqmc_destroy.restype = None
+    lib.vbqmc_last_error.argtypes = [vp]
+    lib.vbqmc_last_error.restype = ctypes.c_char_p
+    lib.vbqmc_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.vbqmc_set_params.argtypes = [vp, ctypes.POINTER(dbl)]
+    lib.vbqmc_get_params.argtypes = [vp, ctypes.POINTER(dbl)]
+    lib.vbqmc_evaluate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.vbqmc_walkers_init.argtypes = [vp, i64, vp, vp, vp]
+    lib.vbqmc_walkers_positions.argtypes = [vp, i64, vp, vp, vp]
+    lib.vbqmc_walkers_eloc.argtypes = [vp, i64, vp, vp, vp]
+    lib.vbqmc_vmc_advance.argtypes = [vp, vp, i64, i32, u64, u64, dbl, i32, ctypes.POINTER(_VmcAcc), vp]
+    lib.vbqmc_dmc_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.vbqmc_dmc_advance.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i64, i32, u64, u64, dbl,
+                                      ctypes.POINTER(dbl), i64, ctypes.POINTER(_DmcLog), vp, ctypes.c_size_t, vp]
+    lib.vbqmc_param_grad_workspace_bytes.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.vbqmc_param_grad.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.vbqmc_reduce_walkers.argtypes = [vp, i64, i32, vp, vp, vp]
+    lib.vbqmc_weights_chirgwin_coulson.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                                   ctypes.POINTER(dbl)]
+    lib.vbqmc_weights_lowdin.argtypes = lib.vbqmc_weights_chirgwin_coulson.argtypes
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_cuda(t, name, dtype=None, shape=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Context:
+    """A vbqmc context for one system dict (see the ``systems`` package)."""
+
+    def __init__(self, system, precision="fp64", refresh_every=32):
+        lib = load_library()
+        self._lib = lib
+        self.system = system
+        nuc = system["nuclei"]
+        self._keep = []
+
+        def keep(a):
+            self._keep.append(a)
+            return a
+
+        Z = keep(np.ascontiguousarray(nuc["Z"], np.float64))
+        pos = keep(np.ascontiguousarray(nuc["pos"], np.float64).reshape(-1))
+        sysc = _System(len(Z), _dp(Z), _dp(pos), int(system["n_up"]), int(system["n_dn"]))
+        sh = system["shells"]
+        cen = keep(np.ascontiguousarray([s["center"] for s in sh], np.int32))
+        kind = keep(np.ascontiguousarray([0 if s["kind"] == "gto" else 1 for s in sh], np.int32))
+        ls = keep(np.ascontiguousarray([s["l"] for s in sh], np.int32))
+        npr = keep(np.ascontiguousarray([len(s["exps"]) for s in sh], np.int32))
+        pe = keep(np.ascontiguousarray(np.concatenate([s["exps"] for s in sh]), np.float64))
+        pc = keep(np.ascontiguousarray(np.concatenate([s["coefs"] for s in sh]), np.float64))
+        lam = keep(np.ascontiguousarray(system["lam"], np.float64))
+        st = system["structures"]
+        c = keep(np.ascontiguousarray([s["c"] for s in st], np.float64))
+        ts, tc, to = [], [], []
+        for I, s in enumerate(st):
+            for t in s["terms"]:
+                ts.append(I)
+                tc += [len(t["inactive"]), len(t["pairs"]), len(t["unpaired"])]
+                to += list(t["inactive"]) + [o for p in t["pairs"] for o in p] + list(t["unpaired"])
+        ts = keep(np.ascontiguousarray(ts, np.int32))
+        tc = keep(np.ascontiguousarray(tc, np.int32))
+        to = keep(np.ascontiguousarray(to if to else [0], np.int32))
+        jas = system["jastrow"]
+        ee = jas["ee"]
+        ee_arr = (ctypes.c_double * 8)(ee["a_anti"], ee["a_par"], ee["b_anti"], ee["b_par"], *ee["poly"])
+        en = keep(np.ascontiguousarray([[e["a1"], e["a2"]] + list(e["poly"]) for e in jas["en"]],
+                                       np.float64).reshape(-1))
+        wfc = _Wavefunction(len(sh), _ip(cen), _ip(kind), _ip(ls), _ip(npr), _dp(pe), _dp(pc), lam.shape[0],
+                            _dp(lam), len(st), _dp(c), len(ts), _ip(ts), _ip(tc), _ip(to), float(jas["kappa"]),
+                            ee_arr, _dp(en))
+        opt = _Options(_PREC[precision] if isinstance(precision, str) else int(precision), int(refresh_every))
+        h = ctypes.c_void_p()
+        rc = lib.vbqmc_create(ctypes.byref(sysc), ctypes.byref(wfc), ctypes.byref(opt), ctypes.byref(h))
+        if rc != 0:
+            raise VBQMCError(rc, "vbqmc_create failed (see stderr)")
+        self._h = h
+        info = _Info()
+        lib.vbqmc_get_info(h, ctypes.byref(info))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.N = info.n_electrons
+        self.n_struct = info.n_structures
+        self.n_params = info.n_params
+        self.rec_doubles = info.walker_state_bytes // 8
+        self.precision = precision
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.vbqmc_destroy(self._h)
+            self._h = None
+
+    def _rc(self, rc):
+        if rc != 0:
+            raise VBQMCError(rc, self._lib.vbqmc_last_error(self._h).decode())
+
+    # ------------------------------------------------------------------
+    def evaluate(self, R, want=("grad", "eloc", "ratio")):
+        import torch
+        W = R.shape[0]
+        _check_cuda(R, "R", torch.float64, (W, self.N, 3))
+        dev = R.device
+        out = {"logabs": torch.empty(W, dtype=torch.float64, device=dev),
+               "sign": torch.empty(W, dtype=torch.int32, device=dev)}
+        out["grad"] = torch.empty(W, self.N, 3, dtype=torch.float64, device=dev) if "grad" in want else None
+        out["eloc"] = torch.empty(W, dtype=torch.float64, device=dev) if "eloc" in want else None
+        out["ratio"] = torch.empty(W, self.n_struct, dtype=torch.float64, device=dev) if "ratio" in want else None
+        self._rc(self._lib.vbqmc_evaluate(self._h, W, _ptr(R), _ptr(out["logabs"]), _ptr(out["sign"]),
+                                          _ptr(out["grad"]), _ptr(out["eloc"]), _ptr(out["ratio"]), _stream()))
+        return out
+
+    def new_state(self, W, device="cuda"):
+        import torch
+        return torch.zeros(W, self.rec_doubles, dtype=torch.float64, device=device)
+
+    def walkers_init(self, R, state=None):
+        import torch
+        W = R.shape[0]
+        _check_cuda(R, "R", torch.float64, (W, self.N, 3))
+        if state is None:
+            state = self.new_state(W, R.device)
+        _check_cuda(state, "state", torch.float64)
+        if state.shape[0] < W or state.shape[1] != self.rec_doubles:
+            raise ValueError("state buffer too small")
+        self._rc(self._lib.vbqmc_walkers_init(self._h, W, _ptr(R), _ptr(state), _stream()))
+        return state
+
+    def positions(self, state, W=None):
+        import torch
+        W = state.shape[0] if W is None else W
+        R = torch.empty(W, self.N, 3, dtype=torch.float64, device=state.device)
+        self._rc(self._lib.vbqmc_walkers_positions(self._h, W, _ptr(state), _ptr(R), _stream()))
+        return R
+
+    def record_eloc(self, state, W=None):
+        import torch
+        W = state.shape[0] if W is None else W
+        e = torch.empty(W, dtype=torch.float64, device=state.device)
+        self._rc(self._lib.vbqmc_walkers_eloc(self._h, W, _ptr(state), _ptr(e), _stream()))
+        return e
+
+    def new_vmc_acc(self, W, device="cuda", sij=False):
+        import torch
+        z = lambda *s: torch.zeros(*s, dtype=torch.float64, device=device)  # noqa: E731
+        acc = {"e_sum": z(W), "e2_sum": z(W), "n_accept": z(W), "e_last": z(W)}
+        acc["sij_sum"] = z(W, self.n_struct, self.n_struct) if sij else None
+        return acc
+
+    def vmc_advance(self, state, n_steps, seed, step0=0, step_size=0.3, all_electron=False, acc=None, W=None):
+        W = state.shape[0] if W is None else W
+        if acc is None:
+            acc = self.new_vmc_acc(W, state.device)
+        a = _VmcAcc(acc["e_sum"].data_ptr(), acc["e2_sum"].data_ptr(), acc["n_accept"].data_ptr(),
+                    acc["e_last"].data_ptr(), acc["sij_sum"].data_ptr() if acc.get("sij_sum") is not None else None)
+        self._rc(self._lib.vbqmc_vmc_advance(self._h, _ptr(state), W, int(n_steps), ctypes.c_uint64(seed),
+                                             ctypes.c_uint64(step0), float(step_size), 1 if all_electron else 0,
+                                             ctypes.byref(a), _stream()))
+        return acc
+
+    def dmc_workspace(self, capacity, n_steps, device="cuda"):
+        import torch
+        nb = ctypes.c_size_t()
+        self._rc(self._lib.vbqmc_dmc_workspace_bytes(self._h, capacity, n_steps, ctypes.byref(nb)))
+        return torch.zeros((nb.value + 7) // 8, dtype=torch.float64, device=device)
+
+    def dmc_advance(self, states, W, n_steps, seed, step0, tau, e_trial, w_target, workspace=None, log=None):
+        import torch
+        cap = states[0].shape[0]
+        dev = states[0].device
+        if workspace is None:
+            workspace = self.dmc_workspace(cap, n_steps, dev)
+        if log is None:
+            log = {k: torch.zeros(n_steps, dtype=torch.float64, device=dev)
+                   for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")}
+        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")])
+        arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
+        Wio = ctypes.c_int64(W)
+        et = ctypes.c_double(e_trial)
+        rc = self._lib.vbqmc_dmc_advance(self._h, arr, ctypes.byref(Wio), cap, int(n_steps), ctypes.c_uint64(seed),
+                                         ctypes.c_uint64(step0), float(tau), ctypes.byref(et), int(w_target),
+                                         ctypes.byref(lg), ctypes.c_void_p(workspace.data_ptr()),
+                                         workspace.numel() * 8, _stream())
+        self._rc(rc)
+        return {"W": Wio.value, "e_trial": et.value, **log}
+
+    def param_grad(self, R, workspace=None):
+        import torch
+        W = R.shape[0]
+        _check_cuda(R, "R", torch.float64, (W, self.N, 3))
+        nb = ctypes.c_size_t()
+        self._rc(self._lib.vbqmc_param_grad_workspace_bytes(self._h, W, ctypes.byref(nb)))
+        if workspace is None and nb.value:
+            workspace = torch.empty((nb.value + 7) // 8, dtype=torch.float64, device=R.device)
+        dl = torch.empty(W, self.n_params, dtype=torch.float64, device=R.device)
+        de = torch.empty(W, self.n_params, dtype=torch.float64, device=R.device)
+        self._rc(self._lib.vbqmc_param_grad(self._h, W, _ptr(R), _ptr(dl), _ptr(de),
+                                            _ptr(workspace) if workspace is not None else None,
+                                            nb.value, _stream()))
+        return dl, de
+
+    def reduce_walkers(self, x):
+        import torch
+        x2 = x.reshape(x.shape[0], -1)
+        _check_cuda(x2, "x", torch.float64)
+        out = torch.empty(x2.shape[1], dtype=torch.float64, device=x.device)
+        self._rc(self._lib.vbqmc_reduce_walkers(self._h, x2.shape[0], x2.shape[1], _ptr(x2), _ptr(out), _stream()))
+        return out.reshape(x.shape[1:])
+
+    def get_params(self):
+        p = np.zeros(self.n_params)
+        self._rc(self._lib.vbqmc_get_params(self._h, _dp(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float64)
+        if p.shape != (self.n_params,):
+            raise ValueError("parameter vector has the wrong length")
+        self._rc(self._lib.vbqmc_set_params(self._h, _dp(p)))
+
+
+def weights_chirgwin_coulson(S, c):
+    lib = load_library()
+    S = np.ascontiguousarray(S, np.float64)
+    c = np.ascontiguousarray(c, np.float64)
+    w = np.zeros(len(c))
+    rc = lib.vbqmc_weights_chirgwin_coulson(len(c), _dp(S), _dp(c), _dp(w))
+    if rc != 0:
+        raise VBQMCError(rc, "weights_chirgwin_coulson")
+    return w
+
+
+def weights_lowdin(S, c):
+    lib = load_library()
+    S = np.ascontiguousarray(S, np.float64)
+    c = np.ascontiguousarray(c, np.float64)
+    w = np.zeros(len(c))
+    rc = lib.vbqmc_weights_lowdin(len(c), _dp(S), _dp(c), _dp(w))
+    if rc != 0:
+        raise VBQMCError(rc, "weights_lowdin")
+    return w

@@ -1,0 +1,805 @@
+// Host side of the JVB library: the C ABI of include/vbqmc.h, the expansion of
+// HLSP structures into a reference-determinant table, the walker-record and
+// LDS layouts, and kernel launches.
+//
+// Method references (Radenkovic, Domin, Toulouse, Braida 2022): Sec. 2.1
+// Eq. (PhiI) for the structures; Sec. 2.3 for the walks; Sec. 2.4 for the
+// structure weights.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/vbqmc.h"
+#include "vbqmc_internal.h"
+
+namespace vbqmc {
+hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* logabs, int32_t* sign,
+                           double* grad, double* eloc, double* ratio, double* state, hipStream_t s);
+hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
+                      double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
+                      hipStream_t s);
+hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
+                           uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
+                           hipStream_t s);
+hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, const int* ncopy, const double* nacc,
+                           int* offs, int64_t cap, int N, int st, double tau, double W_target, double* pop,
+                           double* wsum, double* wesum, double* etrial, double* lacc, double* lprop,
+                           const double* src, double* dst, int rec_len, hipStream_t s);
+hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
+hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
+hipError_t launch_reduce(int64_t W, int K, const double* in, double* out, hipStream_t s);
+hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi, double* deloc,
+                             double* ws, size_t ws_doubles, hipStream_t s);
+size_t param_grad_ws_doubles(const DevWF& wf, int64_t W);
+}  // namespace vbqmc
+
+using namespace vbqmc;
+
+namespace {
+
+int nfunc(int l) { return l == 0 ? 1 : (l == 1 ? 3 : 5); }
+
+int parity_of(const std::vector<int>& v) {
+  int inv = 0;
+  for (size_t a = 0; a < v.size(); ++a)
+    for (size_t b = a + 1; b < v.size(); ++b)
+      if (v[a] > v[b]) ++inv;
+  return inv & 1;
+}
+
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct Term {
+  int I;
+  std::vector<int> inact, pairs, unp;
+};
+
+// One spin determinant in the slot order of Eq. (PhiI): inactive orbitals,
+// then one orbital per pair, then (spin up only) unpaired orbitals.
+struct Product {
+  int I;
+  std::vector<int> up, dn;
+};
+
+void expand(const Term& t, std::vector<Product>& out) {
+  std::vector<int> distinct;
+  int np = (int)t.pairs.size() / 2;
+  for (int k = 0; k < np; ++k)
+    if (t.pairs[2 * k] != t.pairs[2 * k + 1]) distinct.push_back(k);
+  for (int mask = 0; mask < (1 << distinct.size()); ++mask) {
+    Product p;
+    p.I = t.I;
+    p.up = t.inact;
+    p.dn = t.inact;
+    for (int k = 0; k < np; ++k) {
+      int a = t.pairs[2 * k], b = t.pairs[2 * k + 1];
+      int pos = (int)(std::find(distinct.begin(), distinct.end(), k) - distinct.begin());
+      bool flip = pos < (int)distinct.size() && ((mask >> pos) & 1);
+      // a+_{a up} a+_{b dn} - a+_{a dn} a+_{b up} = a+_{a up} a+_{b dn} + a+_{b up} a+_{a dn}
+      p.up.push_back(flip ? b : a);
+      p.dn.push_back(flip ? a : b);
+    }
+    for (int q : t.unp) p.up.push_back(q);
+    out.push_back(p);
+  }
+}
+
+struct SpinHost {
+  int n = 0, e0 = 0;
+  std::vector<int> ref, porb, uinfo, wrow, wother;
+  std::vector<double> wcoef;
+  std::map<std::vector<int>, int> index;
+  std::vector<std::vector<int>> sets;
+  std::vector<int> sgn;  // parity of the aligned order of each unique set
+};
+
+}  // namespace
+
+struct vbqmc_ctx {
+  std::string err;
+  DevWF wf{};
+  int nt = 64;
+  int lds_limit = 65536;
+  // host copies
+  int N = 0, nup = 0, ndn = 0, nnuc = 0, M = 0, Mpad = 0, norb = 0, nop = 0, nstruct = 0, nshell = 0;
+  std::vector<double> nuc, en, pexp, pcoef, lam, c;
+  std::vector<int> shinfo, shprim, fnmap;
+  double ee[8];
+  double kappa = 0;
+  SpinHost sp[2];
+  // determinant pairs k: (u_up, u_dn) and structure links (I, k, d')
+  std::vector<int> pair_up, pair_dn;
+  std::vector<std::vector<std::pair<int, double>>> pair_links;  // per k: (I, d')
+  std::vector<int> srow, slu;
+  std::vector<double> slc;
+  // device arena
+  char* dmem = nullptr;
+  size_t dbytes = 0;
+  // offsets of mutable device tables
+  double* d_lamT = nullptr;
+  float* d_lamT32 = nullptr;
+  uint16_t* d_lamT16 = nullptr;
+  double* d_en = nullptr;
+  double* d_wcoef[2] = {nullptr, nullptr};
+  double* d_slc = nullptr;
+  DevWF* d_wf = nullptr;
+};
+
+namespace {
+
+int fail(vbqmc_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hipfail(vbqmc_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, VBQMC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// (re)compute w_k and structure-link coefficients from c
+void build_coefficients(vbqmc_ctx* x, std::vector<double> (&wcoef)[2], std::vector<double>& slc) {
+  int nk = (int)x->pair_up.size();
+  std::vector<double> wk(nk, 0.0);
+  for (int k = 0; k < nk; ++k)
+    for (auto& pr : x->pair_links[k]) wk[k] += x->c[pr.first] * pr.second;
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    wcoef[s].clear();
+    int nU = (int)h.sets.size();
+    for (int u = 0; u < nU; ++u)
+      for (int k = 0; k < nk; ++k)
+        if ((s == 0 ? x->pair_up[k] : x->pair_dn[k]) == u) wcoef[s].push_back(wk[k]);
+  }
+  slc = x->slc;
+}
+
+template <class T> T* carve(char*& p, size_t n) {
+  T* r = (T*)p;
+  size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
+  p += b;
+  return r;
+}
+
+size_t arena_bytes_for(size_t n, size_t sz) { return (n * sz + 255) & ~(size_t)255; }
+
+int upload_lambda(vbqmc_ctx* x) {
+  std::vector<double> lt((size_t)x->Mpad * x->nop, 0.0);
+  std::vector<float> l32(lt.size(), 0.f);
+  std::vector<uint16_t> l16(lt.size(), 0);
+  for (int p = 0; p < x->norb; ++p)
+    for (int mu = 0; mu < x->M; ++mu) {
+      double v = x->lam[(size_t)p * x->M + mu];
+      size_t k = (size_t)mu * x->nop + p;
+      lt[k] = v;
+      l32[k] = (float)v;
+      l16[k] = to_bf16((float)v);
+    }
+  hipError_t e = hipMemcpy(x->d_lamT, lt.data(), lt.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->d_lamT32, l32.data(), l32.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->d_lamT16, l16.data(), l16.size() * 2, hipMemcpyHostToDevice);
+  return e == hipSuccess ? 0 : hipfail(x, e, "upload lambda");
+}
+
+int upload_coefficients(vbqmc_ctx* x) {
+  std::vector<double> wc[2], slc;
+  build_coefficients(x, wc, slc);
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < 2 && e == hipSuccess; ++s)
+    if (!wc[s].empty()) e = hipMemcpy(x->d_wcoef[s], wc[s].data(), wc[s].size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !slc.empty()) e = hipMemcpy(x->d_slc, slc.data(), slc.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->d_en, x->en.data(), x->en.size() * 8, hipMemcpyHostToDevice);
+  for (int k = 0; k < 8; ++k) x->wf.ee[k] = x->ee[k];
+  if (e == hipSuccess && x->d_wf) e = hipMemcpy(x->d_wf, &x->wf, sizeof(DevWF), hipMemcpyHostToDevice);
+  return e == hipSuccess ? 0 : hipfail(x, e, "upload coefficients");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vbqmc_last_error(const vbqmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const vbqmc_options* opt,
+                 vbqmc_ctx** out) {
+  if (!sys || !wfi || !out) return VBQMC_EINVAL;
+  *out = nullptr;
+  vbqmc_ctx* x = new (std::nothrow) vbqmc_ctx();
+  if (!x) return VBQMC_ENOMEM;
+  auto bad = [&](const std::string& m) {
+    std::fprintf(stderr, "vbqmc_create: %s\n", m.c_str());
+    delete x;
+    return VBQMC_EINVAL;
+  };
+  x->nnuc = sys->n_nuclei;
+  x->nup = sys->n_up;
+  x->ndn = sys->n_dn;
+  x->N = x->nup + x->ndn;
+  if (x->nnuc < 1 || x->nup < 0 || x->ndn < 0 || x->N < 1) return bad("bad electron or nucleus count");
+  if (x->nup > kMaxSpin || x->ndn > kMaxSpin) return bad("more than 64 electrons of one spin");
+  for (int a = 0; a < x->nnuc; ++a) {
+    for (int k = 0; k < 3; ++k) x->nuc.push_back(sys->position[3 * a + k]);
+    x->nuc.push_back(sys->charge[a]);
+  }
+  // basis
+  x->nshell = wfi->n_shells;
+  int off = 0, fn = 0;
+  for (int s = 0; s < x->nshell; ++s) {
+    int cen = wfi->shell_center[s], kind = wfi->shell_kind[s], l = wfi->shell_l[s], np = wfi->shell_nprim[s];
+    if (cen < 0 || cen >= x->nnuc || (kind != 0 && kind != 1) || l < 0 || l > 2 || np < 1 ||
+        (kind == 1 && l > 1))
+      return bad("bad shell description");
+    x->shinfo.insert(x->shinfo.end(), {cen, kind, l, fn});
+    x->shprim.insert(x->shprim.end(), {off, np});
+    for (int k = 0; k < np; ++k) {
+      x->pexp.push_back(wfi->prim_exp[off + k]);
+      x->pcoef.push_back(wfi->prim_coef[off + k]);
+    }
+    for (int m = 0; m < nfunc(l); ++m) x->fnmap.insert(x->fnmap.end(), {s, m});
+    off += np;
+    fn += nfunc(l);
+  }
+  x->M = fn;
+  if (x->M < 1 || x->M > 1024) return bad("basis size outside 1..1024");
+  x->Mpad = (x->M + kChunk - 1) / kChunk * kChunk;
+  for (int mu = x->M; mu < x->Mpad; ++mu) x->fnmap.insert(x->fnmap.end(), {-1, 0});
+  x->norb = wfi->n_orbitals;
+  if (x->norb < 1 || x->norb > 256) return bad("orbital count outside 1..256");
+  x->nop = (x->norb + 15) / 16 * 16;
+  x->lam.assign(wfi->lambda, wfi->lambda + (size_t)x->norb * x->M);
+  // structures
+  x->nstruct = wfi->n_structures;
+  if (x->nstruct < 1) return bad("no structures");
+  x->c.assign(wfi->coef, wfi->coef + x->nstruct);
+  std::vector<Product> prods;
+  int q = 0;
+  for (int t = 0; t < wfi->n_terms; ++t) {
+    Term term;
+    term.I = wfi->term_structure[t];
+    int ni = wfi->term_counts[3 * t], np = wfi->term_counts[3 * t + 1], nu = wfi->term_counts[3 * t + 2];
+    if (term.I < 0 || term.I >= x->nstruct) return bad("term structure index out of range");
+    term.inact.assign(wfi->term_orbitals + q, wfi->term_orbitals + q + ni);
+    term.pairs.assign(wfi->term_orbitals + q + ni, wfi->term_orbitals + q + ni + 2 * np);
+    term.unp.assign(wfi->term_orbitals + q + ni + 2 * np, wfi->term_orbitals + q + ni + 2 * np + nu);
+    q += ni + 2 * np + nu;
+    for (int o : term.inact) if (o < 0 || o >= x->norb) return bad("orbital index out of range");
+    for (int o : term.pairs) if (o < 0 || o >= x->norb) return bad("orbital index out of range");
+    for (int o : term.unp) if (o < 0 || o >= x->norb) return bad("orbital index out of range");
+    if (ni + np + nu != x->nup || ni + np != x->ndn) return bad("term electron counts differ from n_up/n_dn");
+    expand(term, prods);
+  }
+  // spin determinants: sort each slot list, drop identically zero ones,
+  // dedupe by set, align to the reference
+  struct Entry { int I, u0, u1; double d; };
+  std::vector<Entry> entries;
+  for (int s = 0; s < 2; ++s) {
+    x->sp[s].n = s == 0 ? x->nup : x->ndn;
+    x->sp[s].e0 = s == 0 ? 0 : x->nup;
+  }
+  for (auto& p : prods) {
+    Entry en{p.I, 0, 0, 1.0};
+    bool zero = false;
+    for (int s = 0; s < 2 && !zero; ++s) {
+      const std::vector<int>& L = s == 0 ? p.up : p.dn;
+      std::vector<int> srt = L;
+      std::sort(srt.begin(), srt.end());
+      if (std::adjacent_find(srt.begin(), srt.end()) != srt.end()) { zero = true; break; }
+      if (parity_of(L)) en.d = -en.d;
+      SpinHost& h = x->sp[s];
+      auto it = h.index.find(srt);
+      int u;
+      if (it == h.index.end()) {
+        u = (int)h.sets.size();
+        h.index[srt] = u;
+        h.sets.push_back(srt);
+      } else {
+        u = it->second;
+      }
+      (s == 0 ? en.u0 : en.u1) = u;
+    }
+    if (!zero) entries.push_back(en);
+  }
+  if (entries.empty()) return bad("every determinant vanishes identically");
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    h.ref = h.sets[0];
+    std::vector<int> allx;
+    for (auto& st : h.sets)
+      for (int o : st)
+        if (!std::binary_search(h.ref.begin(), h.ref.end(), o)) allx.push_back(o);
+    std::sort(allx.begin(), allx.end());
+    allx.erase(std::unique(allx.begin(), allx.end()), allx.end());
+    h.porb = allx;
+    for (auto& st : h.sets) {
+      std::vector<int> J, ext;
+      for (int j = 0; j < h.n; ++j)
+        if (!std::binary_search(st.begin(), st.end(), h.ref[j])) J.push_back(j);
+      for (int o : st)
+        if (!std::binary_search(h.ref.begin(), h.ref.end(), o)) ext.push_back(o);
+      if (J.size() > (size_t)kMaxExc)
+        return bad("a spin determinant differs from its reference in more than 3 orbitals");
+      std::vector<int> aligned = h.ref;
+      for (size_t r = 0; r < J.size(); ++r) aligned[J[r]] = ext[r];
+      h.sgn.push_back(parity_of(aligned) ? -1 : 1);
+      int ui[8] = {(int)J.size(), 0, 0, 0, 0, 0, 0, 0};
+      for (size_t r = 0; r < J.size(); ++r) {
+        ui[1 + r] = J[r];
+        ui[4 + r] = (int)(std::lower_bound(h.porb.begin(), h.porb.end(), ext[r]) - h.porb.begin());
+      }
+      h.uinfo.insert(h.uinfo.end(), ui, ui + 8);
+    }
+  }
+  // determinant pairs and links
+  std::map<std::pair<int, int>, int> pairidx;
+  for (auto& en : entries) {
+    double d = en.d * x->sp[0].sgn[en.u0] * x->sp[1].sgn[en.u1];
+    auto key = std::make_pair(en.u0, en.u1);
+    auto it = pairidx.find(key);
+    int k;
+    if (it == pairidx.end()) {
+      k = (int)x->pair_up.size();
+      pairidx[key] = k;
+      x->pair_up.push_back(en.u0);
+      x->pair_dn.push_back(en.u1);
+      x->pair_links.emplace_back();
+    } else {
+      k = it->second;
+    }
+    bool merged = false;
+    for (auto& pr : x->pair_links[k])
+      if (pr.first == en.I) { pr.second += d; merged = true; }
+    if (!merged) x->pair_links[k].push_back({en.I, d});
+  }
+  // structure CSR
+  x->srow.assign(x->nstruct + 1, 0);
+  for (int I = 0; I < x->nstruct; ++I) {
+    x->srow[I] = (int)x->slc.size();
+    for (size_t k = 0; k < x->pair_up.size(); ++k)
+      for (auto& pr : x->pair_links[k])
+        if (pr.first == I) {
+          x->slu.push_back(x->pair_up[k]);
+          x->slu.push_back(x->pair_dn[k]);
+          x->slc.push_back(pr.second);
+        }
+  }
+  x->srow[x->nstruct] = (int)x->slc.size();
+  // per-spin CSR of the pairs holding each unique determinant
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    int nU = (int)h.sets.size();
+    h.wrow.assign(nU + 1, 0);
+    for (int u = 0; u < nU; ++u) {
+      h.wrow[u] = (int)h.wother.size();
+      for (size_t k = 0; k < x->pair_up.size(); ++k)
+        if ((s == 0 ? x->pair_up[k] : x->pair_dn[k]) == u) h.wother.push_back(s == 0 ? x->pair_dn[k] : x->pair_up[k]);
+    }
+    h.wrow[nU] = (int)h.wother.size();
+  }
+  // Jastrow
+  x->kappa = wfi->kappa;
+  for (int k = 0; k < 8; ++k) x->ee[k] = wfi->ee[k];
+  x->en.assign(wfi->en, wfi->en + 6 * x->nnuc);
+
+  // ---- layouts ----
+  DevWF& wf = x->wf;
+  wf.N = x->N; wf.nup = x->nup; wf.ndn = x->ndn; wf.nnuc = x->nnuc; wf.nshell = x->nshell;
+  wf.M = x->M; wf.Mpad = x->Mpad; wf.norb = x->norb; wf.nop = x->nop; wf.nstruct = x->nstruct;
+  wf.precision = opt ? opt->precision : VBQMC_FP64;
+  if (wf.precision < 0 || wf.precision > 2) return bad("unknown precision");
+  wf.refresh_every = opt && opt->refresh_every > 0 ? opt->refresh_every : 32;
+  wf.kappa = x->kappa;
+  double vnn = 0;
+  for (int a = 0; a < x->nnuc; ++a)
+    for (int b = a + 1; b < x->nnuc; ++b) {
+      double dx = x->nuc[4 * a] - x->nuc[4 * b], dy = x->nuc[4 * a + 1] - x->nuc[4 * b + 1],
+             dz = x->nuc[4 * a + 2] - x->nuc[4 * b + 2];
+      vnn += x->nuc[4 * a + 3] * x->nuc[4 * b + 3] / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  wf.vnn = vnn;
+  wf.ntiles5 = 5 * x->nop / 16;
+  int waves = (wf.ntiles5 + kMaxTilesPerWave - 1) / kMaxTilesPerWave;
+  x->nt = 64;
+  if (x->nop > 16 || x->N > 24 || waves > 1) x->nt = 128;
+  if (x->nop > 32 || x->N > 48 || waves > 2) x->nt = 256;
+  if (waves > 4) return bad("too many orbitals for the MFMA tile budget");
+
+  int nPm = std::max(x->sp[0].porb.size(), x->sp[1].porb.size());
+  int nUm = std::max(x->sp[0].sets.size(), x->sp[1].sets.size());
+  // walker record
+  int o = 0;
+  auto rec = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
+  wf.r_R = rec(3 * x->N);
+  for (int s = 0; s < 2; ++s) wf.r_B[s] = rec(x->sp[s].n * x->sp[s].n);
+  for (int s = 0; s < 2; ++s) wf.r_T[s] = rec(x->sp[s].n * (int)x->sp[s].porb.size());
+  wf.r_sc = rec(8);
+  wf.hot_len = o;
+  wf.r_gc = rec(3 * x->N * x->nop);
+  wf.rec_len = (o + 31) / 32 * 32;
+  // LDS
+  o = 0;
+  auto lds = [&](int n) { int r = o; o += (std::max(n, 1) + 1) / 2 * 2; return r; };
+  wf.l_R = lds(3 * x->N);
+  wf.l_Rn = lds(3 * x->N);
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    wf.l_B[s] = lds(n * n);
+    wf.l_T[s] = lds(n * nP);
+    wf.l_Bn[s] = lds(n * n);
+    wf.l_Tn[s] = lds(n * nP);
+    wf.l_PP[s] = lds(n * nP);
+    wf.l_Ru[s] = lds((int)x->sp[s].sets.size());
+    wf.l_Wu[s] = lds((int)x->sp[s].sets.size());
+  }
+  wf.l_Qu = lds(nUm);
+  wf.l_sc = lds(SC_COUNT);
+  wf.l_red = lds(kRedSlots);
+  wf.l_ipiv = lds(kMaxSpin / 2);
+  wf.l_f = lds(kMaxSpin);
+  wf.l_gU = lds(3 * x->N);
+  wf.l_lU = lds(x->N);
+  wf.l_gD = lds(3 * x->N);
+  wf.l_lD = lds(x->N);
+  int xsz = std::max({5 * kGroup * kChunk, 5 * kGroup * x->nop, x->nt, 4 * x->nop});
+  wf.l_X = lds(xsz);
+  wf.l_Phi = wf.l_X;
+  wf.l_chi = lds(4 * x->Mpad);
+  wf.l_v = lds(4 * x->nop);
+  wf.l_y = lds(nPm + 1);
+  wf.l_bcol = lds(kMaxSpin);
+  wf.l_z = lds(kMaxSpin);
+  wf.l_yb = lds(64 * (nPm + 1));
+  wf.l_sij = lds(x->nstruct * x->nstruct);
+  wf.l_ratio = lds(x->nstruct);
+  wf.l_scr = 0;
+  wf.lds_doubles = o;
+
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) { delete x; return VBQMC_EHIP; }
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, dev);
+  if (he != hipSuccess) { delete x; return VBQMC_EHIP; }
+  x->lds_limit = (int)prop.sharedMemPerBlock;
+  if ((size_t)wf.lds_doubles * 8 > (size_t)x->lds_limit) {
+    char b[160];
+    std::snprintf(b, sizeof b, "system needs %d bytes of LDS per walker, device allows %d", wf.lds_doubles * 8,
+                  x->lds_limit);
+    return bad(b);
+  }
+
+  // ---- device tables ----
+  size_t bytes = 0;
+  auto add = [&](size_t n, size_t sz) { bytes += arena_bytes_for(n, sz); };
+  add(x->nuc.size(), 8); add(x->en.size(), 8); add(x->shinfo.size(), 4); add(x->shprim.size(), 4);
+  add(x->pexp.size(), 8); add(x->pcoef.size(), 8); add(x->fnmap.size(), 4);
+  add((size_t)x->Mpad * x->nop, 8); add((size_t)x->Mpad * x->nop, 4); add((size_t)x->Mpad * x->nop, 2);
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    add(h.ref.size(), 4); add(h.porb.size(), 4); add(h.uinfo.size(), 4); add(h.wrow.size(), 4);
+    add(h.wother.size(), 4); add(h.wother.size(), 8);
+  }
+  add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1);
+  he = hipMalloc((void**)&x->dmem, bytes);
+  if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
+  x->dbytes = bytes;
+  char* p = x->dmem;
+  auto up = [&](const void* src, size_t n, size_t sz, void* dst) {
+    if (n && he == hipSuccess) he = hipMemcpy(dst, src, n * sz, hipMemcpyHostToDevice);
+  };
+  double* d_nuc = carve<double>(p, x->nuc.size()); up(x->nuc.data(), x->nuc.size(), 8, d_nuc);
+  x->d_en = carve<double>(p, x->en.size());
+  int* d_shinfo = carve<int>(p, x->shinfo.size()); up(x->shinfo.data(), x->shinfo.size(), 4, d_shinfo);
+  int* d_shprim = carve<int>(p, x->shprim.size()); up(x->shprim.data(), x->shprim.size(), 4, d_shprim);
+  double* d_pexp = carve<double>(p, x->pexp.size()); up(x->pexp.data(), x->pexp.size(), 8, d_pexp);
+  double* d_pcoef = carve<double>(p, x->pcoef.size()); up(x->pcoef.data(), x->pcoef.size(), 8, d_pcoef);
+  int* d_fnmap = carve<int>(p, x->fnmap.size()); up(x->fnmap.data(), x->fnmap.size(), 4, d_fnmap);
+  x->d_lamT = carve<double>(p, (size_t)x->Mpad * x->nop);
+  x->d_lamT32 = carve<float>(p, (size_t)x->Mpad * x->nop);
+  x->d_lamT16 = carve<uint16_t>(p, (size_t)x->Mpad * x->nop);
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    SpinTab& t = wf.sp[s];
+    t.n = h.n; t.e0 = h.e0; t.nP = (int)h.porb.size(); t.nU = (int)h.sets.size();
+    int* a = carve<int>(p, h.ref.size()); up(h.ref.data(), h.ref.size(), 4, a); t.ref = a;
+    a = carve<int>(p, h.porb.size()); up(h.porb.data(), h.porb.size(), 4, a); t.porb = a;
+    a = carve<int>(p, h.uinfo.size()); up(h.uinfo.data(), h.uinfo.size(), 4, a); t.uinfo = a;
+    a = carve<int>(p, h.wrow.size()); up(h.wrow.data(), h.wrow.size(), 4, a); t.wrow = a;
+    a = carve<int>(p, h.wother.size()); up(h.wother.data(), h.wother.size(), 4, a); t.wother = a;
+    x->d_wcoef[s] = carve<double>(p, h.wother.size());
+    t.wcoef = x->d_wcoef[s];
+  }
+  int* d_srow = carve<int>(p, x->srow.size()); up(x->srow.data(), x->srow.size(), 4, d_srow);
+  int* d_slu = carve<int>(p, x->slu.size()); up(x->slu.data(), x->slu.size(), 4, d_slu);
+  x->d_slc = carve<double>(p, x->slc.size());
+  x->d_wf = (DevWF*)carve<char>(p, sizeof(DevWF));
+  if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
+  wf.nuc = d_nuc; wf.en = x->d_en; wf.shinfo = d_shinfo; wf.shprim = d_shprim; wf.pexp = d_pexp;
+  wf.pcoef = d_pcoef; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
+  wf.srow = d_srow; wf.slu = d_slu; wf.slc = x->d_slc;
+  if (upload_lambda(x) || upload_coefficients(x)) {
+    hipFree(x->dmem);
+    delete x;
+    return VBQMC_EHIP;
+  }
+  *out = x;
+  return VBQMC_OK;
+}
+
+void vbqmc_destroy(vbqmc_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->dmem) (void)hipFree(ctx->dmem);
+  delete ctx;
+}
+
+int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
+  if (!x || !o) return VBQMC_EINVAL;
+  o->n_electrons = x->N; o->n_up = x->nup; o->n_dn = x->ndn; o->n_nuclei = x->nnuc;
+  o->n_basis = x->M; o->n_orbitals = x->norb; o->n_structures = x->nstruct;
+  o->n_determinants = (int)x->pair_up.size();
+  o->n_unique_up = (int)x->sp[0].sets.size();
+  o->n_unique_dn = (int)x->sp[1].sets.size();
+  o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
+  o->block_threads = x->nt;
+  o->walker_state_bytes = (int64_t)x->wf.rec_len * 8;
+  o->lds_bytes = (int64_t)x->wf.lds_doubles * 8;
+  return VBQMC_OK;
+}
+
+int vbqmc_set_params(vbqmc_ctx* x, const double* p) {
+  if (!x || !p) return VBQMC_EINVAL;
+  int k = 0;
+  for (int I = 0; I < x->nstruct; ++I) x->c[I] = p[k++];
+  for (size_t q = 0; q < x->lam.size(); ++q) x->lam[q] = p[k++];
+  x->ee[2] = p[k++];
+  x->ee[3] = p[k++];
+  for (int j = 4; j < 8; ++j) x->ee[j] = p[k++];
+  for (int a = 0; a < x->nnuc; ++a)
+    for (int j = 0; j < 6; ++j) x->en[6 * a + j] = p[k++];
+  if (upload_lambda(x)) return VBQMC_EHIP;
+  if (upload_coefficients(x)) return VBQMC_EHIP;
+  return VBQMC_OK;
+}
+
+int vbqmc_get_params(const vbqmc_ctx* x, double* p) {
+  if (!x || !p) return VBQMC_EINVAL;
+  int k = 0;
+  for (int I = 0; I < x->nstruct; ++I) p[k++] = x->c[I];
+  for (double v : x->lam) p[k++] = v;
+  p[k++] = x->ee[2];
+  p[k++] = x->ee[3];
+  for (int j = 4; j < 8; ++j) p[k++] = x->ee[j];
+  for (int a = 0; a < x->nnuc; ++a)
+    for (int j = 0; j < 6; ++j) p[k++] = x->en[6 * a + j];
+  return VBQMC_OK;
+}
+
+int vbqmc_evaluate(vbqmc_ctx* x, int64_t W, const double* R, double* logabs, int32_t* sign, double* grad,
+                   double* eloc, double* ratio, vbqmc_stream stream) {
+  if (!x) return VBQMC_EINVAL;
+  if (W < 0 || (W > 0 && (!R || !logabs || !sign))) return fail(x, VBQMC_EINVAL, "evaluate: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "evaluate: too many walkers");
+  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, logabs, sign, grad, eloc, ratio, nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "evaluate");
+}
+
+int vbqmc_walkers_init(vbqmc_ctx* x, int64_t W, const double* R, void* state, vbqmc_stream stream) {
+  if (!x || W < 0 || (W > 0 && (!R || !state))) return fail(x, VBQMC_EINVAL, "walkers_init: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "walkers_init: too many walkers");
+  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)state,
+                                 (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_init");
+}
+
+int vbqmc_walkers_positions(vbqmc_ctx* x, int64_t W, const void* state, double* R, vbqmc_stream stream) {
+  if (!x || W < 0 || (W > 0 && (!R || !state))) return fail(x, VBQMC_EINVAL, "walkers_positions: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  hipError_t e = launch_positions(x->wf, x->d_wf, W, (const double*)state, R, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_positions");
+}
+
+int vbqmc_walkers_eloc(vbqmc_ctx* x, int64_t W, const void* state, double* eloc, vbqmc_stream stream) {
+  if (!x || W < 0 || (W > 0 && (!eloc || !state))) return fail(x, VBQMC_EINVAL, "walkers_eloc: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  hipError_t e = launch_record_eloc(x->wf, x->d_wf, W, (const double*)state, eloc, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_eloc");
+}
+
+int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uint64_t seed, uint64_t step0,
+                      double step_size, int32_t all_electron, const vbqmc_vmc_acc* acc, vbqmc_stream stream) {
+  if (!x || !acc || W < 0 || n_steps < 0 || (W > 0 && !state)) return fail(x, VBQMC_EINVAL, "vmc: bad arguments");
+  if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
+    return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
+  if (!(step_size > 0) || !std::isfinite(step_size)) return fail(x, VBQMC_EINVAL, "vmc: bad step size");
+  if (W == 0 || n_steps == 0) return VBQMC_OK;
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
+  hipError_t e = launch_vmc(x->wf, x->d_wf, x->nt, (double*)state, W, n_steps, seed, step0, step_size, all_electron ? 1 : 0,
+                            acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
+}
+
+// DMC workspace: ctrl (8 doubles) | wts, wel, nacc [cap] | ncopy [cap] | offs [cap+1]
+int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, size_t* bytes) {
+  if (!x || !bytes || cap < 1) return VBQMC_EINVAL;
+  (void)n_steps;
+  *bytes = 64 + 3 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4 + 256;
+  return VBQMC_OK;
+}
+
+int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, int32_t n_steps, uint64_t seed,
+                      uint64_t step0, double tau, double* e_trial_io, int64_t W_target, const vbqmc_dmc_log* lg,
+                      void* ws, size_t ws_bytes, vbqmc_stream stream) {
+  if (!x || !states || !states[0] || !states[1] || !W_io || !e_trial_io || !lg || !ws)
+    return fail(x, VBQMC_EINVAL, "dmc: bad arguments");
+  if (!lg->pop || !lg->wsum || !lg->wesum || !lg->etrial || !lg->n_accept || !lg->n_prop)
+    return fail(x, VBQMC_EINVAL, "dmc: log pointers missing");
+  int64_t W = *W_io;
+  if (W < 1 || W > cap || cap > (int64_t)INT32_MAX || W_target < 1 || !(tau > 0) || n_steps < 0)
+    return fail(x, VBQMC_EINVAL, "dmc: bad population, capacity or time step");
+  size_t need = 0;
+  vbqmc_dmc_workspace_bytes(x, cap, n_steps, &need);
+  if (ws_bytes < need) return fail(x, VBQMC_EWORKSPACE, "dmc: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* p = (char*)ws;
+  double* ctrl = (double*)p; p += 64;
+  double* wts = (double*)p; p += cap * 8;
+  double* wel = (double*)p; p += cap * 8;
+  double* nacc = (double*)p; p += cap * 8;
+  int* ncopy = (int*)p; p += cap * 4;
+  int* offs = (int*)p;
+  double h[DC_COUNT] = {0};
+  h[DC_W] = (double)W;
+  h[DC_ET] = *e_trial_io;
+  hipError_t e = hipMemcpyAsync(ctrl, h, sizeof h, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hipfail(x, e, "dmc: control upload");
+  double* cur = (double*)states[0];
+  double* oth = (double*)states[1];
+  for (int st = 0; st < n_steps; ++st) {
+    uint32_t step = (uint32_t)(step0 + st);
+    e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
+    if (e != hipSuccess) return hipfail(x, e, "dmc: step");
+    e = launch_dmc_tail(ctrl, wts, wel, ncopy, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
+                        lg->wesum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
+    if (e != hipSuccess) return hipfail(x, e, "dmc: branching");
+    std::swap(cur, oth);
+  }
+  e = hipMemcpyAsync(h, ctrl, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hipfail(x, e, "dmc: control download");
+  if (h[DC_ERR] != 0.0) {
+    // the failing step's branching did not run: its walkers (after that
+    // step's moves) are in the buffer that step worked on
+    int64_t Wl = (int64_t)h[DC_W];
+    double* held = (double*)states[((int64_t)h[DC_ERRSTEP]) & 1];
+    if (held != (double*)states[0]) {
+      e = launch_copy_records(held, (double*)states[0], Wl * x->wf.rec_len, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    *W_io = Wl;
+    *e_trial_io = h[DC_ET];
+    return fail(x, h[DC_ERR] == 1.0 ? VBQMC_ENONFINITE : VBQMC_EPOPULATION,
+                h[DC_ERR] == 1.0 ? "dmc: a walker became singular or non-finite"
+                                 : "dmc: population empty or above capacity");
+  }
+  int64_t Wn = (int64_t)h[DC_W];
+  if (cur != (double*)states[0]) {
+    e = launch_copy_records(cur, (double*)states[0], Wn * x->wf.rec_len, s);
+    if (e != hipSuccess) return hipfail(x, e, "dmc: final copy");
+  }
+  *W_io = Wn;
+  *e_trial_io = h[DC_ET];
+  return VBQMC_OK;
+}
+
+int vbqmc_param_grad_workspace_bytes(const vbqmc_ctx* x, int64_t W, size_t* bytes) {
+  if (!x || !bytes || W < 0) return VBQMC_EINVAL;
+  *bytes = param_grad_ws_doubles(x->wf, W) * 8;
+  return VBQMC_OK;
+}
+
+int vbqmc_param_grad(vbqmc_ctx* x, int64_t W, const double* R, double* dlogpsi, double* deloc, void* ws,
+                     size_t ws_bytes, vbqmc_stream stream) {
+  if (!x || W < 0 || (W > 0 && (!R || !dlogpsi || !deloc))) return fail(x, VBQMC_EINVAL, "param_grad: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  size_t need = param_grad_ws_doubles(x->wf, W) * 8;
+  if (need && (!ws || ws_bytes < need)) return fail(x, VBQMC_EWORKSPACE, "param_grad: workspace too small");
+  hipError_t e = launch_param_grad(x->wf, x->d_wf, x->nt, W, R, dlogpsi, deloc, (double*)ws, need / 8, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "param_grad");
+}
+
+int vbqmc_reduce_walkers(vbqmc_ctx* x, int64_t W, int32_t K, const double* in, double* out, vbqmc_stream stream) {
+  if (!x || W < 0 || K < 0 || (K > 0 && (!in || !out))) return fail(x, VBQMC_EINVAL, "reduce: bad arguments");
+  if (K == 0) return VBQMC_OK;
+  hipError_t e = launch_reduce(W, K, in, out, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "reduce");
+}
+
+// ---------------------------------------------------------------------------
+// structure weights (host)
+// ---------------------------------------------------------------------------
+int vbqmc_weights_chirgwin_coulson(int32_t n, const double* S, const double* c, double* w) {
+  if (n < 1 || !S || !c || !w) return VBQMC_EINVAL;
+  double tot = 0;
+  for (int I = 0; I < n; ++I) {
+    double a = 0;
+    for (int J = 0; J < n; ++J) a += S[I * n + J] * c[J];
+    w[I] = c[I] * a;
+    tot += w[I];
+  }
+  if (!(tot > 0)) return VBQMC_EINVAL;
+  for (int I = 0; I < n; ++I) w[I] /= tot;
+  return VBQMC_OK;
+}
+
+// cyclic Jacobi eigen-decomposition of a symmetric n x n matrix
+static void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& V) {
+  V.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double th = (A[q * n + q] - A[p * n + p]) / (2 * apq);
+        double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        double cs = 1 / std::sqrt(t * t + 1), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = cs * akp - sn * akq;
+          A[k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = cs * apk - sn * aqk;
+          A[q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = cs * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+int vbqmc_weights_lowdin(int32_t n, const double* S, const double* c, double* w) {
+  if (n < 1 || !S || !c || !w) return VBQMC_EINVAL;
+  std::vector<double> A(n * n), V;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[i * n + j] = 0.5 * (S[i * n + j] + S[j * n + i]);
+  jacobi_eig(n, A, V);
+  // S^{1/2} = V diag(sqrt(max(ev,0))) V^T ; cbar = S^{1/2} c
+  std::vector<double> tmp(n, 0.0), cb(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double a = 0;
+    for (int i = 0; i < n; ++i) a += V[i * n + k] * c[i];
+    tmp[k] = a * std::sqrt(std::max(A[k * n + k], 0.0));
+  }
+  double tot = 0;
+  for (int i = 0; i < n; ++i) {
+    double a = 0;
+    for (int k = 0; k < n; ++k) a += V[i * n + k] * tmp[k];
+    cb[i] = a;
+    tot += a * a;
+  }
+  if (!(tot > 0)) return VBQMC_EINVAL;
+  for (int i = 0; i < n; ++i) w[i] = cb[i] * cb[i] / tot;
+  return VBQMC_OK;
+}
+
+}  // extern "C"

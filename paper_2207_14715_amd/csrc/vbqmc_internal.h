@@ -1,0 +1,76 @@
+// Internal layout shared by the host code and the gfx950 kernels of the JVB
+// library.  Nothing here is part of the public C ABI (include/vbqmc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vbqmc {
+
+constexpr int kGroup = 16;     // electrons per MFMA row tile
+constexpr int kChunk = 16;     // basis functions per K chunk of an AO tile
+constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
+constexpr int kMaxTilesPerWave = 8;
+constexpr int kMaxSpin = 64;   // electrons per spin
+constexpr int kRedSlots = 64;  // doubles of block-reduction scratch
+
+// One spin's determinant table (reference determinant + replaced columns).
+struct SpinTab {
+  int n;            // electrons of this spin
+  int e0;           // index of its first electron
+  int nP;           // table orbitals: orbitals that replace reference columns
+  int nU;           // distinct spin determinants; u = 0 is the reference
+  const int* ref;   // [n] reference orbitals, ascending
+  const int* porb;  // [nP] table orbitals, ascending
+  const int* uinfo; // [nU][8]: e, J0, J1, J2, Q0, Q1, Q2, 0  (J: slots, Q: table index)
+  const int* wrow;  // [nU + 1] CSR over the determinant pairs holding u
+  const int* wother;     // other spin's determinant of each pair
+  const double* wcoef;   // w_k = sum_I c_I d'_{I,k} of each pair
+};
+
+// Constant description of the wave function plus layouts, passed by value to
+// every kernel.
+struct DevWF {
+  int N, nup, ndn, nnuc, nshell, M, Mpad, norb, nop, nstruct;
+  int precision, refresh_every;
+  int ntiles5;  // 5 * nop / 16 MFMA output tiles of a full group pass
+  double kappa, vnn;
+  double ee[8];
+  const double* nuc;    // [nnuc][4]: x, y, z, Z
+  const double* en;     // [nnuc][6]
+  const int* shinfo;    // [nshell][4]: center, kind, l, first basis function
+  const int* shprim;    // [nshell][2]: first primitive, count
+  const double* pexp;
+  const double* pcoef;
+  const int* fnmap;     // [Mpad][2]: shell (or -1 for padding), angular index m
+  const double* lamT;   // [Mpad][nop] lambda transposed, zero padded
+  const float* lamT32;
+  const uint16_t* lamT16;  // bf16 bit patterns
+  SpinTab sp[2];
+  const int* srow;      // [nstruct + 1] CSR of structure links
+  const int* slu;       // [nlinks][2]: up, down spin determinant
+  const double* slc;    // [nlinks] d'_{I,k}
+  // walker record (doubles)
+  int rec_len, hot_len;
+  int r_R, r_B[2], r_T[2], r_sc, r_gc;
+  // LDS layout (doubles)
+  int l_R, l_Rn, l_B[2], l_T[2], l_Bn[2], l_Tn[2], l_PP[2];
+  int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
+  int l_gU, l_lU, l_gD, l_lD;
+  int l_scr, l_X, l_Phi, l_chi, l_v, l_y, l_bcol, l_z, l_yb, l_sij, l_ratio;
+  int lds_doubles;
+};
+
+// scalar slots in the record's / LDS scalar block
+enum {
+  SC_LOGDET0 = 0, SC_LOGDET1, SC_SGN0, SC_SGN1, SC_NUPD0, SC_NUPD1, SC_ELOC, SC_FLAGS,
+  SC_S, SC_U, SC_V, SC_LOGPSI, SC_SIGN, SC_RATIO, SC_ACC, SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3,
+  SC_COUNT = 32
+};
+
+// DMC device-side control block (doubles), in the caller's workspace.
+enum {
+  DC_W = 0, DC_ET, DC_RUN_NUM, DC_RUN_DEN, DC_ERR, DC_WNEW, DC_ERRSTEP, DC_COUNT = 8
+};
+
+}  // namespace vbqmc

@@ -1,0 +1,1465 @@
+// gfx950 kernels for the Jastrow-Valence-Bond (JVB) QMC hot path.
+//
+// Design: one workgroup owns one walker.  Its hot state (positions, the
+// reference inverse and determinant table of each spin) is held in LDS for the
+// whole call, so a VMC call runs every step of every walker without touching
+// HBM except at entry and exit, and a DMC step reads and writes each record
+// once.  Per move the basis values at the trial position are formed by one
+// lane per shell, contracted to orbital values on the VALU, and turned into
+// determinant ratios with the reference + replaced-column table.  The local
+// energy pass forms basis values/gradients/Laplacians for tiles of 16
+// electrons in LDS and contracts them with the orbital coefficients on MFMA
+// (FP64 16x16x4, FP32 16x16x4 or BF16 16x16x16 by precision form).
+//
+// Method (Radenkovic, Domin, Toulouse, Braida 2022):
+//   Sec. 2.1 Eq. (PsiJVBSCF), Eq. (PhiI): Psi = J sum_I c_I Phi_I with HLSP
+//     structures expanded into spin-determinant products.
+//   Sec. 2.1: orbitals as basis expansions; Jastrow pair terms in
+//     R = r / (1 + kappa r).
+//   Sec. 2.3.1 Eq. (Elav): E_L = H Psi / Psi, Metropolis sampling.
+//   Sec. 2.3.2 Eq. (E0DMCweights): weighted walkers with birth/death.
+//
+// Determinant algebra (exact identities, no approximation): for one spin with
+// reference matrix A0[i][j] = phi_{ref_j}(r_i), B = A0^{-1} and the table
+// T = B Phi[:, P] over the orbitals P that replace reference columns, a
+// determinant replacing slots J by orbitals Q has ratio det(T[J, Q]) to the
+// reference (matrix determinant lemma).  A row operator O on electron i
+// (gradient or Laplacian) or a move of electron i with new row w gives
+//   O_i Delta_u / Delta_0 = rho R_u + y_Q^T adj(T_JQ) B[J, i],
+//   rho = sum_j w[ref_j] B[j][i],  y[q] = w[P_q] - sum_l w[ref_l] T[l][q],
+// and an accepted move updates B and T by Sherman-Morrison rank-1 steps.
+
+#include <type_traits>
+
+#include "vbqmc_internal.h"
+
+namespace vbqmc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the counter layout of the walks:
+// key = seed, counter = (walker slot, step, 4 * electron + purpose, draw).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                            uint32_t c3, double& u0, double& u1) {
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  const double s = 1.0 / 9007199254740992.0;
+  u0 = (double)((((uint64_t)x1 << 32) | x0) >> 11) * s;
+  u1 = (double)((((uint64_t)x3 << 32) | x2) >> 11) * s;
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed order: identical results in every lane)
+// ---------------------------------------------------------------------------
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if constexpr (NT > 64) {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[(threadIdx.x >> 6) * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w * K + k];
+      v[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Jastrow pair function u(r) = a R/(1 + b R) + sum_{p=2..5} q_p R^p with
+// R = r/(1 + kappa r); returns u, u' and u'' in r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_fn(double r, double kappa, double a, double b, const double* q,
+                                        double& u, double& u1, double& u2) {
+  double den = 1.0 + kappa * r;
+  double iden = 1.0 / den;
+  double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
+  double ib = 1.0 / (1.0 + b * R);
+  u = a * R * ib;
+  double uR = a * ib * ib;
+  double uRR = -2.0 * a * b * ib * ib * ib;
+  double Rp2 = 1.0;  // R^(p-2)
+#pragma unroll
+  for (int p = 2; p <= 5; ++p) {
+    double c = q[p - 2];
+    uRR += p * (p - 1) * c * Rp2;
+    uR += p * c * Rp2 * R;
+    u += c * Rp2 * R * R;
+    Rp2 *= R;
+  }
+  u1 = uR * R1;
+  u2 = uRR * R1 * R1 + uR * R2;
+}
+
+__device__ __forceinline__ double pair_val(double r, double kappa, double a, double b, const double* q) {
+  double R = r / (1.0 + kappa * r);
+  double u = a * R / (1.0 + b * R);
+  double Rp = R * R;
+#pragma unroll
+  for (int p = 2; p <= 5; ++p) {
+    u += q[p - 2] * Rp;
+    Rp *= R;
+  }
+  return u;
+}
+
+// ---------------------------------------------------------------------------
+// basis functions: radial sums and the angular set
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T dexp(T x);
+template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+
+// Gaussian (kind 0): g = sum c e^{-a r^2}, g1 = dg/d(r^2), g2 = d2g/d(r^2)^2.
+// Slater (kind 1): g = sum c e^{-a r}, g1 = dg/dr, g2 = d2g/dr2.
+// Primitives with exponent argument above 50 are below 2e-22 of their
+// coefficient and are skipped.
+template <typename T>
+__device__ __forceinline__ void radial(const DevWF& wf, int sh, int kind, T r2, T r, T& g, T& g1, T& g2) {
+  int off = wf.shprim[2 * sh], np = wf.shprim[2 * sh + 1];
+  g = T(0); g1 = T(0); g2 = T(0);
+  for (int k = 0; k < np; ++k) {
+    T a = (T)wf.pexp[off + k];
+    T t = kind == 0 ? a * r2 : a * r;
+    if (t < T(50)) {
+      T e = (T)wf.pcoef[off + k] * dexp<T>(-t);
+      g += e;
+      g1 -= a * e;
+      g2 += a * a * e;
+    }
+  }
+}
+
+// channels of one basis function: 0 value, 1..3 gradient, 4 Laplacian
+template <typename T>
+__device__ __forceinline__ void channels(int kind, int l, int m, T x, T y, T z, T r2, T r, T g, T g1,
+                                         T g2, int nch, T* out) {
+  T P, Px = T(0), Py = T(0), Pz = T(0);
+  if (l == 0) {
+    P = T(1);
+  } else if (l == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? T(1) : T(0);
+    Py = m == 1 ? T(1) : T(0);
+    Pz = m == 2 ? T(1) : T(0);
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = T(2) * x; Py = T(-2) * y; break;
+      default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
+    }
+  }
+  out[0] = P * g;
+  if (nch == 1) return;
+  // grad g = fr * d
+  T fr = kind == 0 ? T(2) * g1 : g1 / r;
+  out[1] = Px * g + P * fr * x;
+  out[2] = Py * g + P * fr * y;
+  out[3] = Pz * g + P * fr * z;
+  if (nch < 5) return;
+  // lap chi = P lap g + 2 grad P . grad g  (lap P = 0, d . grad P = l P)
+  if (kind == 0)
+    out[4] = P * (T(2 * (2 * l + 3)) * g1 + T(4) * r2 * g2);
+  else
+    out[4] = P * (g2 + T(2 * (l + 1)) * g1 / r);
+}
+
+// ---------------------------------------------------------------------------
+// small e x e determinant algebra (e <= 3), matrices row-major with stride 3
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double det_e(int e, const double* m) {
+  if (e == 0) return 1.0;
+  if (e == 1) return m[0];
+  if (e == 2) return m[0] * m[4] - m[1] * m[3];
+  return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+         m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// y^T adj(m) b
+__device__ __forceinline__ double adj_e(int e, const double* m, const double* y, const double* b) {
+  if (e == 0) return 0.0;
+  if (e == 1) return y[0] * b[0];
+  if (e == 2) return y[0] * (m[4] * b[0] - m[1] * b[1]) + y[1] * (-m[3] * b[0] + m[0] * b[1]);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    int r1 = r == 0 ? 1 : 0, r2 = r == 2 ? 1 : 2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int c1 = c == 0 ? 1 : 0, c2 = c == 2 ? 1 : 2;
+      double cof = m[r1 * 3 + c1] * m[r2 * 3 + c2] - m[r1 * 3 + c2] * m[r2 * 3 + c1];
+      if ((r + c) & 1) cof = -cof;
+      s += y[c] * cof * b[r];  // adj[c][r] = cofactor[r][c]
+    }
+  }
+  return s;
+}
+
+// gather T[J, Q] (+ optional rank-1 term bJ yQ / rho) of determinant u
+__device__ __forceinline__ int gather_u(const int* ui, const double* T, int nP, double* m,
+                                        const double* bc, const double* y, double irho) {
+  int e = ui[0];
+  for (int r = 0; r < e; ++r)
+    for (int c = 0; c < e; ++c) {
+      double v = T[ui[1 + r] * nP + ui[4 + c]];
+      if (bc) v += bc[ui[1 + r]] * y[ui[4 + c]] * irho;
+      m[r * 3 + c] = v;
+    }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// LDS views
+// ---------------------------------------------------------------------------
+struct Ld {
+  double* L;
+  const DevWF& wf;
+  __device__ Ld(double* l, const DevWF& w) : L(l), wf(w) {}
+  __device__ double* R() const { return L + wf.l_R; }
+  __device__ double* Rn() const { return L + wf.l_Rn; }
+  __device__ double* B(int s) const { return L + wf.l_B[s]; }
+  __device__ double* T(int s) const { return L + wf.l_T[s]; }
+  __device__ double* Bn(int s) const { return L + wf.l_Bn[s]; }
+  __device__ double* Tn(int s) const { return L + wf.l_Tn[s]; }
+  __device__ double* PP(int s) const { return L + wf.l_PP[s]; }
+  __device__ double* Ru(int s) const { return L + wf.l_Ru[s]; }
+  __device__ double* Wu(int s) const { return L + wf.l_Wu[s]; }
+  __device__ double* Qu() const { return L + wf.l_Qu; }
+  __device__ double* sc() const { return L + wf.l_sc; }
+  __device__ double* red() const { return L + wf.l_red; }
+  __device__ int* ipiv() const { return (int*)(L + wf.l_ipiv); }
+  __device__ double* f() const { return L + wf.l_f; }
+  __device__ double* gU() const { return L + wf.l_gU; }
+  __device__ double* lU() const { return L + wf.l_lU; }
+  __device__ double* gD() const { return L + wf.l_gD; }
+  __device__ double* lD() const { return L + wf.l_lD; }
+  __device__ double* X() const { return L + wf.l_X; }
+  __device__ double* Phi() const { return L + wf.l_Phi; }
+  __device__ double* chi() const { return L + wf.l_chi; }
+  __device__ double* v() const { return L + wf.l_v; }
+  __device__ double* y() const { return L + wf.l_y; }
+  __device__ double* bcol() const { return L + wf.l_bcol; }
+  __device__ double* z() const { return L + wf.l_z; }
+  __device__ double* yb() const { return L + wf.l_yb; }
+  __device__ double* sij() const { return L + wf.l_sij; }
+  __device__ double* ratio() const { return L + wf.l_ratio; }
+};
+
+__device__ __forceinline__ int spin_of(const DevWF& wf, int i) { return i < wf.nup ? 0 : 1; }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// AO -> orbital contraction for a tile of up to 16 electrons on MFMA.
+// Writes Phi[c][e][p] (c < nch, e < 16, p < nop) in LDS as FP64.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void group_pass(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne, int nch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const int nct = wf.nop / 16;
+  const int ntiles = nch * nct;
+  typedef typename std::conditional<PREC == 0, v4d, v4f>::type acc_t;
+  acc_t acc[kMaxTilesPerWave];
+#pragma unroll
+  for (int t = 0; t < kMaxTilesPerWave; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  double* Xd = l.X();
+  float* Xf = (float*)l.X();
+  uint16_t* Xh = (uint16_t*)l.X();
+  for (int k0 = 0; k0 < wf.Mpad; k0 += kChunk) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kGroup * kChunk; idx += NT) {
+      int e = idx / kChunk, kk = idx - e * kChunk, mu = k0 + kk;
+      int sh = wf.fnmap[2 * mu];
+      if constexpr (PREC == 0) {
+        double o[5] = {0, 0, 0, 0, 0};
+        if (e < ne && sh >= 0) {
+          int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2];
+          double x = Rsrc[3 * (g0 + e)] - wf.nuc[4 * a], y = Rsrc[3 * (g0 + e) + 1] - wf.nuc[4 * a + 1],
+                 z = Rsrc[3 * (g0 + e) + 2] - wf.nuc[4 * a + 2];
+          double r2 = x * x + y * y + z * z, r = sqrt(r2), g, g1, g2;
+          radial<double>(wf, sh, kind, r2, r, g, g1, g2);
+          channels<double>(kind, lq, wf.fnmap[2 * mu + 1], x, y, z, r2, r, g, g1, g2, nch, o);
+        }
+        for (int c = 0; c < nch; ++c) Xd[(c * kGroup + e) * kChunk + kk] = o[c];
+      } else {
+        float o[5] = {0, 0, 0, 0, 0};
+        if (e < ne && sh >= 0) {
+          int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2];
+          float x = (float)(Rsrc[3 * (g0 + e)] - wf.nuc[4 * a]);
+          float y = (float)(Rsrc[3 * (g0 + e) + 1] - wf.nuc[4 * a + 1]);
+          float z = (float)(Rsrc[3 * (g0 + e) + 2] - wf.nuc[4 * a + 2]);
+          float r2 = x * x + y * y + z * z, r = sqrtf(r2), g, g1, g2;
+          radial<float>(wf, sh, kind, r2, r, g, g1, g2);
+          channels<float>(kind, lq, wf.fnmap[2 * mu + 1], x, y, z, r2, r, g, g1, g2, nch, o);
+        }
+        if constexpr (PREC == 1)
+          for (int c = 0; c < nch; ++c) Xf[(c * kGroup + e) * kChunk + kk] = o[c];
+        else
+          for (int c = 0; c < nch; ++c) Xh[(c * kGroup + e) * kChunk + kk] = f2bf(o[c]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kMaxTilesPerWave; ++t) {
+      int tile = wave + t * NW;
+      if (tile < ntiles) {
+        int c = tile / nct, ct = tile - c * nct;
+        int col = ct * 16 + (lane & 15);
+        if constexpr (PREC == 0) {
+#pragma unroll
+          for (int s = 0; s < kChunk / 4; ++s) {
+            int k = 4 * s + (lane >> 4);
+            double a = Xd[(c * kGroup + (lane & 15)) * kChunk + k];
+            double b = wf.lamT[(size_t)(k0 + k) * wf.nop + col];
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+          }
+        } else if constexpr (PREC == 1) {
+#pragma unroll
+          for (int s = 0; s < kChunk / 4; ++s) {
+            int k = 4 * s + (lane >> 4);
+            float a = Xf[(c * kGroup + (lane & 15)) * kChunk + k];
+            float b = wf.lamT32[(size_t)(k0 + k) * wf.nop + col];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+          }
+        } else {
+          int kb = 4 * (lane >> 4);
+          v4s a, b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            a[j] = (short)Xh[(c * kGroup + (lane & 15)) * kChunk + kb + j];
+            b[j] = (short)wf.lamT16[(size_t)(k0 + kb + j) * wf.nop + col];
+          }
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();  // every read of X is done before Phi (which may alias X) is written
+  double* Phi = l.Phi();
+#pragma unroll
+  for (int t = 0; t < kMaxTilesPerWave; ++t) {
+    int tile = wave + t * NW;
+    if (tile < ntiles) {
+      int c = tile / nct, ct = tile - c * nct;
+      int col = ct * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // output lane layout: f64 16x16x4 holds row 4r + lane/16, the f32 and
+        // bf16 forms hold row 4(lane/16) + r (column lane%16 in both)
+        int row = PREC == 0 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+        Phi[(c * kGroup + row) * wf.nop + col] = (double)acc[t][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A
+// (rows electrons, columns reference slots) -> A^{-1} (rows slots, columns
+// electrons).  Returns false if a pivot is exactly zero.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ bool gj_invert(const Ld& l, double* A, int n, double& logdet, double& sgn) {
+  int* piv = l.ipiv();
+  double* f = l.f();
+  double* sc = l.sc();
+  logdet = 0.0;
+  sgn = 1.0;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x < 64) {
+      int lane = threadIdx.x;
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        double v = fabs(A[i * n + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        piv[k] = bi;
+        sc[SC_TMP3] = best;
+      }
+    }
+    __syncthreads();
+    int p = piv[k];
+    if (!(sc[SC_TMP3] > 0.0)) {
+      __syncthreads();
+      return false;
+    }
+    if (p != k)
+      for (int j = threadIdx.x; j < n; j += NT) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[p * n + j];
+        A[p * n + j] = t;
+      }
+    __syncthreads();
+    double pv = A[k * n + k];
+    logdet += log(fabs(pv));
+    if (pv < 0) sgn = -sgn;
+    if (p != k) sgn = -sgn;
+    for (int i = threadIdx.x; i < n; i += NT) f[i] = A[i * n + k];
+    __syncthreads();
+    double ip = 1.0 / pv;
+    for (int j = threadIdx.x; j < n; j += NT) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * ip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+      int i = idx / n, j = idx - i * n;
+      if (i != k) A[idx] = (j == k ? 0.0 : A[idx]) - f[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    int p = piv[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < n; i += NT) {
+        double t = A[i * n + k];
+        A[i * n + k] = A[i * n + p];
+        A[i * n + p] = t;
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Determinant-table bookkeeping: R_u = det(T[J,Q]), W_u = sum over the pairs
+// holding u of w_k R_{other}, S = sum_k w_k R_up R_dn = sum_u R_u W_u.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void update_R(const DevWF& wf, const Ld& l, int s) {
+  const SpinTab& st = wf.sp[s];
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double m[9];
+    int e = gather_u(st.uinfo + 8 * u, l.T(s), st.nP, m, nullptr, nullptr, 0.0);
+    l.Ru(s)[u] = det_e(e, m);
+  }
+}
+
+template <int NT>
+__device__ void update_W(const DevWF& wf, const Ld& l, int s) {
+  const SpinTab& st = wf.sp[s];
+  const double* Ro = l.Ru(1 - s);
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double w = 0.0;
+    for (int k = st.wrow[u]; k < st.wrow[u + 1]; ++k) w += st.wcoef[k] * Ro[st.wother[k]];
+    l.Wu(s)[u] = w;
+  }
+}
+
+template <int NT>
+__device__ void update_S(const DevWF& wf, const Ld& l) {
+  double v[1] = {0.0};
+  for (int u = threadIdx.x; u < wf.sp[0].nU; u += NT) v[0] += l.Ru(0)[u] * l.Wu(0)[u];
+  block_sum<NT, 1>(v, l.red());
+  if (threadIdx.x == 0) l.sc()[SC_S] = v[0];
+  __syncthreads();
+}
+
+template <int NT>
+__device__ void compute_RWS(const DevWF& wf, const Ld& l) {
+  update_R<NT>(wf, l, 0);
+  update_R<NT>(wf, l, 1);
+  __syncthreads();
+  update_W<NT>(wf, l, 0);
+  update_W<NT>(wf, l, 1);
+  __syncthreads();
+  update_S<NT>(wf, l);
+}
+
+// ---------------------------------------------------------------------------
+// Fresh reference inverses and tables from positions Rsrc (values pass on
+// MFMA + Gauss-Jordan).  Returns false on an exactly singular reference.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
+  for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
+    int ne = min(kGroup, wf.N - g0);
+    group_pass<NT, PREC>(wf, l, Rsrc, g0, ne, 1);
+    const double* Phi = l.Phi();
+    for (int s = 0; s < 2; ++s) {
+      const SpinTab& st = wf.sp[s];
+      int w = st.n + st.nP;
+      for (int idx = threadIdx.x; idx < ne * w; idx += NT) {
+        int e = idx / w, j = idx - e * w, i = g0 + e;
+        if (spin_of(wf, i) != s) continue;
+        int il = i - st.e0;
+        if (j < st.n)
+          l.B(s)[il * st.n + j] = Phi[e * wf.nop + st.ref[j]];
+        else
+          l.PP(s)[il * st.nP + (j - st.n)] = Phi[e * wf.nop + st.porb[j - st.n]];
+      }
+    }
+    __syncthreads();
+  }
+  bool ok = true;
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    double ld = 0.0, sg = 1.0;
+    if (st.n > 0 && !gj_invert<NT>(l, l.B(s), st.n, ld, sg)) ok = false;
+    if (threadIdx.x == 0) {
+      l.sc()[SC_LOGDET0 + s] = ld;
+      l.sc()[SC_SGN0 + s] = sg;
+      l.sc()[SC_NUPD0 + s] = 0.0;
+    }
+    // T = B PP
+    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+      int j = idx / st.nP, q = idx - j * st.nP;
+      double a = 0.0;
+      for (int i = 0; i < st.n; ++i) a += l.B(s)[j * st.n + i] * l.PP(s)[i * st.nP + q];
+      l.T(s)[idx] = a;
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Jastrow factor and potential for all electrons: U, grad_i U, lap_i U, V.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
+  double part[2] = {0.0, 0.0};  // U, V
+  for (int i = threadIdx.x; i < wf.N; i += NT) {
+    double xi = Rsrc[3 * i], yi = Rsrc[3 * i + 1], zi = Rsrc[3 * i + 2];
+    double gx = 0, gy = 0, gz = 0, lap = 0, Ui = 0, Vi = 0;
+    for (int a = 0; a < wf.nnuc; ++a) {
+      double dx = xi - wf.nuc[4 * a], dy = yi - wf.nuc[4 * a + 1], dz = zi - wf.nuc[4 * a + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      const double* ja = wf.en + 6 * a;
+      pair_fn(r, wf.kappa, ja[0], ja[1], ja + 2, u, u1, u2);
+      Ui += u;
+      double f = u1 / r;
+      gx += f * dx; gy += f * dy; gz += f * dz;
+      lap += u2 + 2.0 * f;
+      Vi -= wf.nuc[4 * a + 3] / r;
+    }
+    int si = spin_of(wf, i);
+    for (int j = 0; j < wf.N; ++j) {
+      if (j == i) continue;
+      double dx = xi - Rsrc[3 * j], dy = yi - Rsrc[3 * j + 1], dz = zi - Rsrc[3 * j + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      bool anti = si != spin_of(wf, j);
+      pair_fn(r, wf.kappa, anti ? wf.ee[0] : wf.ee[1], anti ? wf.ee[2] : wf.ee[3], wf.ee + 4, u, u1, u2);
+      Ui += 0.5 * u;
+      double f = u1 / r;
+      gx += f * dx; gy += f * dy; gz += f * dz;
+      lap += u2 + 2.0 * f;
+      Vi += 0.5 / r;
+    }
+    l.gU()[3 * i] = gx; l.gU()[3 * i + 1] = gy; l.gU()[3 * i + 2] = gz;
+    l.lU()[i] = lap;
+    part[0] += Ui;
+    part[1] += Vi;
+  }
+  block_sum<NT, 2>(part, l.red());
+  if (threadIdx.x == 0) {
+    l.sc()[SC_U] = part[0];
+    l.sc()[SC_V] = part[1] + wf.vnn;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Row-operator ratios of one electron: sum_u (rho R_u + y^T adj(T_JQ) B_J,i) W_u
+// for a row w (length nop in LDS) of electron i.
+// ---------------------------------------------------------------------------
+__device__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf) {
+  const SpinTab& st = wf.sp[s];
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  double rho = 0.0;
+  for (int j = 0; j < st.n; ++j) rho += w[st.ref[j]] * B[j * st.n + il];
+  for (int q = 0; q < st.nP; ++q) {
+    double a = w[st.porb[q]];
+    for (int k = 0; k < st.n; ++k) a -= w[st.ref[k]] * T[k * st.nP + q];
+    ybuf[q] = a;
+  }
+  double tot = 0.0;
+  for (int u = 0; u < st.nU; ++u) {
+    const int* ui = st.uinfo + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
+    for (int r = 0; r < e; ++r) {
+      yy[r] = ybuf[ui[4 + r]];
+      bb[r] = B[ui[1 + r] * st.n + il];
+    }
+    tot += (rho * l.Ru(s)[u] + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
+  }
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// Local energy pass: 5-channel MFMA passes over electron tiles, row-operator
+// ratios, Jastrow, potential.  Fills gD, lD, gU, lU and the scalars
+// SC_ELOC, SC_LOGPSI, SC_SIGN.  gc (DMC gradient cache) may be null.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
+  const double* R = l.R();
+  const double S = l.sc()[SC_S];
+  int nPmax = max(wf.sp[0].nP, wf.sp[1].nP);
+  for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
+    int ne = min(kGroup, wf.N - g0);
+    group_pass<NT, PREC>(wf, l, R, g0, ne, 5);
+    const double* Phi = l.Phi();
+    for (int idx = threadIdx.x; idx < ne * 4; idx += NT) {
+      int e = idx >> 2, c = 1 + (idx & 3), i = g0 + e;
+      int s = spin_of(wf, i), il = i - wf.sp[s].e0;
+      double tot = row_op_sum(wf, l, s, il, Phi + (c * kGroup + e) * wf.nop, l.yb() + idx * (nPmax + 1));
+      if (c < 4)
+        l.gD()[3 * i + c - 1] = tot / S;
+      else
+        l.lD()[i] = tot / S;
+    }
+    if (gc)
+      for (int idx = threadIdx.x; idx < ne * 3 * wf.nop; idx += NT) {
+        int e = idx / (3 * wf.nop), rem = idx - e * 3 * wf.nop;
+        int c = rem / wf.nop, p = rem - c * wf.nop;
+        gc[((g0 + e) * 3 + c) * wf.nop + p] = Phi[((1 + c) * kGroup + e) * wf.nop + p];
+      }
+    __syncthreads();
+  }
+  jastrow_full<NT>(wf, l, R);
+  double part[1] = {0.0};
+  for (int i = threadIdx.x; i < wf.N; i += NT) {
+    double t = l.lU()[i] + l.lD()[i];
+    for (int x = 0; x < 3; ++x) {
+      double gu = l.gU()[3 * i + x];
+      t += gu * gu + 2.0 * gu * l.gD()[3 * i + x];
+    }
+    part[0] += -0.5 * t;
+  }
+  block_sum<NT, 1>(part, l.red());
+  if (threadIdx.x == 0) {
+    double* sc = l.sc();
+    sc[SC_ELOC] = part[0] + sc[SC_V];
+    sc[SC_LOGPSI] = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(S));
+    sc[SC_SIGN] = sc[SC_SGN0] * sc[SC_SGN1] * (S > 0 ? 1.0 : (S < 0 ? -1.0 : 0.0));
+  }
+  __syncthreads();
+}
+
+// structure ratios r_I = sum_links d' R_up R_dn / S into l.ratio()
+template <int NT>
+__device__ void structure_ratios(const DevWF& wf, const Ld& l) {
+  double S = l.sc()[SC_S];
+  for (int I = threadIdx.x; I < wf.nstruct; I += NT) {
+    double a = 0.0;
+    for (int k = wf.srow[I]; k < wf.srow[I + 1]; ++k)
+      a += wf.slc[k] * l.Ru(0)[wf.slu[2 * k]] * l.Ru(1)[wf.slu[2 * k + 1]];
+    l.ratio()[I] = a / S;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// basis values (+ gradients if nch = 4) at one point, one lane per shell, and
+// their contraction to orbital rows v[c][p] (VALU).
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double py, double pz, int nch) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  T* chi = (T*)l.chi();
+  for (int sh = threadIdx.x; sh < wf.nshell; sh += NT) {
+    int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2], f0 = wf.shinfo[4 * sh + 3];
+    T x = (T)(px - wf.nuc[4 * a]), y = (T)(py - wf.nuc[4 * a + 1]), z = (T)(pz - wf.nuc[4 * a + 2]);
+    T r2 = x * x + y * y + z * z, r = sqrt(r2), g, g1, g2;
+    radial<T>(wf, sh, kind, r2, r, g, g1, g2);
+    int nf = lq == 0 ? 1 : (lq == 1 ? 3 : 5);
+    for (int m = 0; m < nf; ++m) {
+      T o[5];
+      channels<T>(kind, lq, m, x, y, z, r2, r, g, g1, g2, nch, o);
+      for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + f0 + m] = o[c];
+    }
+  }
+  for (int mu = wf.M + threadIdx.x; mu < wf.Mpad; mu += NT)
+    for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = T(0);
+  __syncthreads();
+  // v[c][p]: split the basis sum over NPART lanes per output, then reduce
+  const int nout = nch * wf.nop;
+  const int nparts = max(1, NT / nout);
+  double* part = l.X();  // scratch [nparts][nout]
+  for (int idx = threadIdx.x; idx < nout * nparts; idx += NT) {
+    int pt = idx / nout, o = idx - pt * nout, c = o / wf.nop, p = o - c * wf.nop;
+    int m0 = (wf.Mpad * pt) / nparts, m1 = (wf.Mpad * (pt + 1)) / nparts;
+    T a = T(0);
+    if constexpr (PREC == 0) {
+      for (int mu = m0; mu < m1; ++mu) a += chi[c * wf.Mpad + mu] * (T)wf.lamT[(size_t)mu * wf.nop + p];
+    } else {
+      for (int mu = m0; mu < m1; ++mu) a += chi[c * wf.Mpad + mu] * (T)wf.lamT32[(size_t)mu * wf.nop + p];
+    }
+    part[idx] = (double)a;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += NT) {
+    double a = 0.0;
+    for (int pt = 0; pt < nparts; ++pt) a += part[pt * nout + o];
+    l.v()[o] = a;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Single-electron move of electron i to (px,py,pz): ratio of determinant sums
+// S''/S (written to SC_RATIO) and Jastrow change dU (SC_TMP0); fills y (value
+// channel), bcol (old B column) and Qu.  Requires v[0][*] to hold the new
+// orbital values.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
+  int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  int il = i - st.e0;
+  const double* v = l.v();
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  double* y = l.y();
+  double* bc = l.bcol();
+  for (int idx = threadIdx.x; idx <= st.nP + st.n; idx += NT) {
+    if (idx < st.nP) {
+      double a = v[st.porb[idx]];
+      for (int k = 0; k < st.n; ++k) a -= v[st.ref[k]] * T[k * st.nP + idx];
+      y[idx] = a;
+    } else if (idx == st.nP) {
+      double a = 0.0;
+      for (int j = 0; j < st.n; ++j) a += v[st.ref[j]] * B[j * st.n + il];
+      l.sc()[SC_TMP1] = a;  // rho
+    } else {
+      int j = idx - st.nP - 1;
+      bc[j] = B[j * st.n + il];
+    }
+  }
+  __syncthreads();
+  double rho = l.sc()[SC_TMP1];
+  double part[2] = {0.0, 0.0};
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    const int* ui = st.uinfo + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
+    for (int r = 0; r < e; ++r) {
+      yy[r] = y[ui[4 + r]];
+      bb[r] = bc[ui[1 + r]];
+    }
+    double q = rho * l.Ru(s)[u] + adj_e(e, m, yy, bb);
+    l.Qu()[u] = q;
+    part[0] += q * l.Wu(s)[u];
+  }
+  // Jastrow change
+  const double* R = l.R();
+  double xo = R[3 * i], yo = R[3 * i + 1], zo = R[3 * i + 2];
+  for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
+    if (j == i) continue;
+    double xj, yj, zj, a, b;
+    const double* q;
+    if (j < wf.N) {
+      xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
+      bool anti = s != spin_of(wf, j);
+      a = anti ? wf.ee[0] : wf.ee[1];
+      b = anti ? wf.ee[2] : wf.ee[3];
+      q = wf.ee + 4;
+    } else {
+      int n = j - wf.N;
+      xj = wf.nuc[4 * n]; yj = wf.nuc[4 * n + 1]; zj = wf.nuc[4 * n + 2];
+      a = wf.en[6 * n]; b = wf.en[6 * n + 1]; q = wf.en + 6 * n + 2;
+    }
+    double rn = sqrt((px - xj) * (px - xj) + (py - yj) * (py - yj) + (pz - zj) * (pz - zj));
+    double ro = sqrt((xo - xj) * (xo - xj) + (yo - yj) * (yo - yj) + (zo - zj) * (zo - zj));
+    part[1] += pair_val(rn, wf.kappa, a, b, q) - pair_val(ro, wf.kappa, a, b, q);
+  }
+  block_sum<NT, 2>(part, l.red());
+  if (threadIdx.x == 0) {
+    l.sc()[SC_RATIO] = part[0] / l.sc()[SC_S];
+    l.sc()[SC_TMP0] = part[1];
+  }
+  __syncthreads();
+}
+
+// Commit an accepted move of electron i (after move_ratio).
+template <int NT>
+__device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
+  int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  int il = i - st.e0;
+  const double* v = l.v();
+  double* B = l.B(s);
+  double* T = l.T(s);
+  double rho = l.sc()[SC_TMP1];
+  double* z = l.z();
+  for (int m = threadIdx.x; m < st.n; m += NT) {
+    double a = 0.0;
+    for (int k = 0; k < st.n; ++k) a += v[st.ref[k]] * B[k * st.n + m];
+    z[m] = (m == il ? a - 1.0 : a);
+  }
+  __syncthreads();
+  double ir = 1.0 / rho;
+  const double* bc = l.bcol();
+  const double* y = l.y();
+  for (int idx = threadIdx.x; idx < st.n * st.n; idx += NT) {
+    int j = idx / st.n, m = idx - j * st.n;
+    B[idx] -= bc[j] * z[m] * ir;
+  }
+  for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+    int j = idx / st.nP, q = idx - j * st.nP;
+    T[idx] += bc[j] * y[q] * ir;
+  }
+  if (threadIdx.x == 0) {
+    double* sc = l.sc();
+    sc[SC_LOGDET0 + s] += log(fabs(rho));
+    if (rho < 0) sc[SC_SGN0 + s] = -sc[SC_SGN0 + s];
+    sc[SC_NUPD0 + s] += 1.0;
+    double* R = l.R();
+    R[3 * i] = px; R[3 * i + 1] = py; R[3 * i + 2] = pz;
+  }
+  __syncthreads();
+  update_R<NT>(wf, l, s);
+  __syncthreads();
+  update_W<NT>(wf, l, 1 - s);
+  __syncthreads();
+  update_S<NT>(wf, l);
+}
+
+// ---------------------------------------------------------------------------
+// record I/O
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void load_record(const DevWF& wf, const Ld& l, const double* rec) {
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = rec[wf.r_R + k];
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.B(s)[k] = rec[wf.r_B[s] + k];
+    for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.T(s)[k] = rec[wf.r_T[s] + k];
+  }
+  for (int k = threadIdx.x; k < 8; k += NT) l.sc()[k] = rec[wf.r_sc + k];
+  __syncthreads();
+}
+
+template <int NT>
+__device__ void store_record(const DevWF& wf, const Ld& l, double* rec) {
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) rec[wf.r_R + k] = l.R()[k];
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    for (int k = threadIdx.x; k < st.n * st.n; k += NT) rec[wf.r_B[s] + k] = l.B(s)[k];
+    for (int k = threadIdx.x; k < st.n * st.nP; k += NT) rec[wf.r_T[s] + k] = l.T(s)[k];
+  }
+  for (int k = threadIdx.x; k < 8; k += NT) rec[wf.r_sc + k] = l.sc()[k];
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+extern __shared__ double lds_dyn[];
+
+template <int NT, int PREC>
+__global__ __launch_bounds__(NT) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
+                                                 double* logabs, int32_t* sign, double* grad, double* eloc,
+                                                 double* ratio, double* state) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  if (w >= W) return;
+  Ld l(lds_dyn, wf);
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = Rin[w * 3 * wf.N + k];
+  __syncthreads();
+  bool ok = build_state<NT, PREC>(wf, l, l.R());
+  if (ok) {
+    compute_RWS<NT>(wf, l);
+    ok = l.sc()[SC_S] != 0.0;
+  }
+  if (!ok) {
+    if (threadIdx.x == 0) {
+      if (logabs) logabs[w] = -INFINITY;
+      if (sign) sign[w] = 0;
+      if (eloc) eloc[w] = NAN;
+    }
+    if (grad)
+      for (int k = threadIdx.x; k < 3 * wf.N; k += NT) grad[w * 3 * wf.N + k] = NAN;
+    if (ratio)
+      for (int k = threadIdx.x; k < wf.nstruct; k += NT) ratio[w * wf.nstruct + k] = NAN;
+    if (state) {
+      if (threadIdx.x == 0) l.sc()[SC_ELOC] = NAN;
+      __syncthreads();
+      store_record<NT>(wf, l, state + w * wf.rec_len);
+    }
+    return;
+  }
+  local_energy<NT, PREC>(wf, l, state ? state + w * wf.rec_len + wf.r_gc : nullptr);
+  if (ratio) structure_ratios<NT>(wf, l);
+  const double* sc = l.sc();
+  if (threadIdx.x == 0) {
+    if (logabs) logabs[w] = sc[SC_LOGPSI];
+    if (sign) sign[w] = (int32_t)sc[SC_SIGN];
+    if (eloc) eloc[w] = sc[SC_ELOC];
+  }
+  if (grad)
+    for (int k = threadIdx.x; k < 3 * wf.N; k += NT) grad[w * 3 * wf.N + k] = l.gU()[k] + l.gD()[k];
+  if (ratio)
+    for (int k = threadIdx.x; k < wf.nstruct; k += NT) ratio[w * wf.nstruct + k] = l.ratio()[k];
+  if (state) store_record<NT>(wf, l, state + w * wf.rec_len);
+}
+
+// all-electron Metropolis move (one per step)
+template <int NT, int PREC>
+__device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint64_t seed, uint32_t step,
+                                  double step_size) {
+  double* sc = l.sc();
+  // back up the current state
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.Rn()[k] = l.R()[k];
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.Bn(s)[k] = l.B(s)[k];
+    for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.Tn(s)[k] = l.T(s)[k];
+  }
+  double old_log = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(sc[SC_S]));
+  double bk[4] = {sc[SC_LOGDET0], sc[SC_LOGDET1], sc[SC_SGN0], sc[SC_SGN1]};
+  double bkS = sc[SC_S], bkU = sc[SC_U];
+  __syncthreads();
+  for (int e = threadIdx.x; e < wf.N; e += NT) {
+    double a0, a1, b0, b1;
+    philox_pair(seed, (uint32_t)w, step, 4u * e, 0u, a0, a1);
+    philox_pair(seed, (uint32_t)w, step, 4u * e, 1u, b0, b1);
+    l.R()[3 * e] += step_size * (2.0 * a0 - 1.0);
+    l.R()[3 * e + 1] += step_size * (2.0 * a1 - 1.0);
+    l.R()[3 * e + 2] += step_size * (2.0 * b0 - 1.0);
+  }
+  __syncthreads();
+  bool ok = build_state<NT, PREC>(wf, l, l.R());
+  double ua, dummy;
+  philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 1u, 0u, ua, dummy);
+  bool accept = false;
+  if (ok) {
+    compute_RWS<NT>(wf, l);
+    jastrow_full<NT>(wf, l, l.R());
+    if (sc[SC_S] != 0.0) {
+      double new_log = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(sc[SC_S]));
+      accept = ua < exp(2.0 * (new_log - old_log));
+    }
+  }
+  __syncthreads();
+  if (!accept) {
+    for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = l.Rn()[k];
+    for (int s = 0; s < 2; ++s) {
+      const SpinTab& st = wf.sp[s];
+      for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.B(s)[k] = l.Bn(s)[k];
+      for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.T(s)[k] = l.Tn(s)[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sc[SC_LOGDET0] = bk[0]; sc[SC_LOGDET1] = bk[1]; sc[SC_SGN0] = bk[2]; sc[SC_SGN1] = bk[3];
+      sc[SC_S] = bkS; sc[SC_U] = bkU;
+    }
+    __syncthreads();
+    compute_RWS<NT>(wf, l);
+  }
+  return accept;
+}
+
+template <int NT, int PREC>
+__global__ __launch_bounds__(NT) void k_vmc(const DevWF* __restrict__ pwf, double* state, int64_t W, int nsteps, uint64_t seed,
+                                            uint64_t step0, double step_size, int all_electron, double* e_sum,
+                                            double* e2_sum, double* n_acc, double* e_last, double* sij_sum) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  if (w >= W) return;
+  Ld l(lds_dyn, wf);
+  double* rec = state + w * wf.rec_len;
+  load_record<NT>(wf, l, rec);
+  compute_RWS<NT>(wf, l);
+  double* sc = l.sc();
+  if (all_electron) jastrow_full<NT>(wf, l, l.R());
+  const int nv = wf.nstruct;
+  if (sij_sum)
+    for (int k = threadIdx.x; k < nv * nv; k += NT) l.sij()[k] = 0.0;
+  double es = 0.0, e2s = 0.0, na = 0.0;
+  bool bad = !(sc[SC_S] != 0.0);
+  for (int st = 0; st < nsteps && !bad; ++st) {
+    uint32_t step = (uint32_t)(step0 + st);
+    if (all_electron) {
+      if (all_electron_move<NT, PREC>(wf, l, w, seed, step, step_size)) na += 1.0;
+    } else {
+      for (int i = 0; i < wf.N; ++i) {
+        double a0, a1, b0, b1;
+        philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
+        philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
+        const double* R = l.R();
+        double px = R[3 * i] + step_size * (2.0 * a0 - 1.0);
+        double py = R[3 * i + 1] + step_size * (2.0 * a1 - 1.0);
+        double pz = R[3 * i + 2] + step_size * (2.0 * b0 - 1.0);
+        point_orbitals<NT, PREC>(wf, l, px, py, pz, 1);
+        move_ratio<NT>(wf, l, i, px, py, pz);
+        double ratio = sc[SC_RATIO] * exp(sc[SC_TMP0]);
+        double ua, dummy;
+        philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
+        if (ua < ratio * ratio) {
+          accept_move<NT>(wf, l, i, px, py, pz);
+          na += 1.0;
+        }
+      }
+      if (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every) {
+        bool ok = build_state<NT, PREC>(wf, l, l.R());
+        if (!ok) { bad = true; break; }
+        compute_RWS<NT>(wf, l);
+      }
+    }
+    if (!(sc[SC_S] != 0.0)) { bad = true; break; }
+    local_energy<NT, PREC>(wf, l, st == nsteps - 1 ? rec + wf.r_gc : nullptr);
+    double el = sc[SC_ELOC];
+    es += el;
+    e2s += el * el;
+    if (sij_sum) {
+      structure_ratios<NT>(wf, l);
+      for (int k = threadIdx.x; k < nv * nv; k += NT) {
+        int I = k / nv, J = k - I * nv;
+        l.sij()[k] += l.ratio()[I] * l.ratio()[J];
+      }
+    }
+  }
+  __syncthreads();
+  if (bad && threadIdx.x == 0) sc[SC_FLAGS] = 1.0;
+  __syncthreads();
+  store_record<NT>(wf, l, rec);
+  if (threadIdx.x == 0) {
+    e_sum[w] += es;
+    e2_sum[w] += e2s;
+    n_acc[w] += na;
+    e_last[w] = bad ? NAN : sc[SC_ELOC];
+  }
+  if (sij_sum)
+    for (int k = threadIdx.x; k < nv * nv; k += NT) sij_sum[w * nv * nv + k] += l.sij()[k];
+}
+
+// ---------------------------------------------------------------------------
+// DMC
+// ---------------------------------------------------------------------------
+// gradient of ln|Psi| for electron i: det part from row operators on rows
+// w_c (3 rows of nop in `rows`, stride rstride) with the table of the current
+// (or, with bc != null, rank-1-updated) state, Jastrow part at (px,py,pz).
+// Results in SC_TMP0..2 is avoided: returned in g[3] (all lanes).
+template <int NT>
+__device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, int rstride, double px,
+                      double py, double pz, const double* bc, double irho, const double* Qnew,
+                      double Snew, double* g) {
+  int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  int il = i - st.e0;
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  const double* y0 = l.y();
+  double* yb = l.yb();  // [3][nP + 1]: y'^c and rho'^c
+  int ld = st.nP + 1;
+  // y^c[q] = w_c[P_q] - sum_l w_c[ref_l] T'[l][q],  T' = T + bc y0^T irho
+  for (int idx = threadIdx.x; idx < 3 * ld; idx += NT) {
+    int c = idx / ld, q = idx - c * ld;
+    const double* w = rows + c * rstride;
+    if (q < st.nP) {
+      double a = w[st.porb[q]], corr = 0.0;
+      for (int k = 0; k < st.n; ++k) {
+        a -= w[st.ref[k]] * T[k * st.nP + q];
+        if (bc) corr += w[st.ref[k]] * bc[k];
+      }
+      if (bc) a -= corr * y0[q] * irho;
+      yb[c * ld + q] = a;
+    } else {
+      double a = 0.0;
+      for (int j = 0; j < st.n; ++j) a += w[st.ref[j]] * (bc ? bc[j] * irho : B[j * st.n + il]);
+      yb[c * ld + q] = a;  // rho'^c
+    }
+  }
+  __syncthreads();
+  double part[6] = {0, 0, 0, 0, 0, 0};
+  for (int idx = threadIdx.x; idx < 3 * st.nU; idx += NT) {
+    int c = idx / st.nU, u = idx - c * st.nU;
+    const int* ui = st.uinfo + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, st.nP, m, bc, y0, irho);
+    for (int r = 0; r < e; ++r) {
+      yy[r] = yb[c * ld + ui[4 + r]];
+      bb[r] = bc ? bc[ui[1 + r]] * irho : B[ui[1 + r] * st.n + il];
+    }
+    double Rn = bc ? Qnew[u] * irho : l.Ru(s)[u];
+    double t = (yb[c * ld + st.nP] * Rn + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
+    if (c == 0) part[0] += t; else if (c == 1) part[1] += t; else part[2] += t;
+  }
+  // Jastrow gradient at (px,py,pz)
+  const double* R = l.R();
+  for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
+    if (j == i) continue;
+    double xj, yj, zj, a, b;
+    const double* q;
+    if (j < wf.N) {
+      xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
+      bool anti = s != spin_of(wf, j);
+      a = anti ? wf.ee[0] : wf.ee[1];
+      b = anti ? wf.ee[2] : wf.ee[3];
+      q = wf.ee + 4;
+    } else {
+      int n = j - wf.N;
+      xj = wf.nuc[4 * n]; yj = wf.nuc[4 * n + 1]; zj = wf.nuc[4 * n + 2];
+      a = wf.en[6 * n]; b = wf.en[6 * n + 1]; q = wf.en + 6 * n + 2;
+    }
+    double dx = px - xj, dy = py - yj, dz = pz - zj;
+    double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+    pair_fn(r, wf.kappa, a, b, q, u, u1, u2);
+    double f = u1 / r;
+    part[3] += f * dx; part[4] += f * dy; part[5] += f * dz;
+  }
+  block_sum<NT, 6>(part, l.red());
+  double S = bc ? Snew : l.sc()[SC_S];
+  for (int c = 0; c < 3; ++c) g[c] = part[3 + c] + part[c] / S;
+  __syncthreads();
+}
+
+template <int NT, int PREC>
+__global__ __launch_bounds__(NT) void k_dmc_step(const DevWF* __restrict__ pwf, double* state, const double* ctrl, int nsteps_done,
+                                                 uint64_t seed, uint32_t step, double tau, double* wts,
+                                                 double* wel, int* ncopy, double* nacc) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  int64_t W = (int64_t)ctrl[DC_W];
+  if (ctrl[DC_ERR] != 0.0 || w >= W) return;
+  Ld l(lds_dyn, wf);
+  double* rec = state + w * wf.rec_len;
+  double* gc = rec + wf.r_gc;
+  load_record<NT>(wf, l, rec);
+  compute_RWS<NT>(wf, l);
+  double* sc = l.sc();
+  const double ET = ctrl[DC_ET];
+  const double E_old = sc[SC_ELOC];
+  const double sqt = sqrt(tau);
+  double na = 0.0;
+  bool bad = !(sc[SC_S] != 0.0);
+  for (int i = 0; i < wf.N && !bad; ++i) {
+    const double* R = l.R();
+    double rx = R[3 * i], ry = R[3 * i + 1], rz = R[3 * i + 2];
+    double v[3];
+    drift<NT>(wf, l, i, gc + (size_t)i * 3 * wf.nop, wf.nop, rx, ry, rz, nullptr, 0.0, nullptr, 0.0, v);
+    double a0, a1, b0, b1;
+    philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
+    philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
+    const double two_pi = 6.283185307179586476925286766559;
+    double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
+    double zx = r0 * cos(two_pi * a1), zy = r0 * sin(two_pi * a1), zz = r1 * cos(two_pi * b1);
+    double px = rx + tau * v[0] + sqt * zx, py = ry + tau * v[1] + sqt * zy, pz = rz + tau * v[2] + sqt * zz;
+    point_orbitals<NT, PREC>(wf, l, px, py, pz, 4);
+    move_ratio<NT>(wf, l, i, px, py, pz);
+    double rdet = sc[SC_RATIO];
+    double dU = sc[SC_TMP0];
+    double rho = sc[SC_TMP1];
+    bool accept = false;
+    if (rdet > 0.0 && rho != 0.0) {
+      double vn[3];
+      double Snew = sc[SC_S] * rdet / rho;  // S' relative to the updated reference
+      drift<NT>(wf, l, i, l.v() + wf.nop, wf.nop, px, py, pz, l.bcol(), 1.0 / rho, l.Qu(), Snew, vn);
+      double fwd = 0.0, bwd = 0.0;
+      double d[3] = {px - rx, py - ry, pz - rz};
+      for (int x = 0; x < 3; ++x) {
+        double fa = d[x] - tau * v[x];
+        double ba = -d[x] - tau * vn[x];
+        fwd += fa * fa;
+        bwd += ba * ba;
+      }
+      double p = rdet * rdet * exp(2.0 * dU + (fwd - bwd) / (2.0 * tau));
+      double ua, dummy;
+      philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
+      accept = ua < p;
+    }
+    if (accept) {
+      accept_move<NT>(wf, l, i, px, py, pz);
+      for (int k = threadIdx.x; k < 3 * wf.nop; k += NT) gc[(size_t)i * 3 * wf.nop + k] = l.v()[wf.nop + k];
+      na += 1.0;
+      __syncthreads();
+    }
+    if (!(sc[SC_S] != 0.0)) bad = true;
+  }
+  if (!bad && (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every)) {
+    if (!build_state<NT, PREC>(wf, l, l.R())) bad = true;
+    else compute_RWS<NT>(wf, l);
+  }
+  if (!bad) local_energy<NT, PREC>(wf, l, gc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double En = bad ? NAN : sc[SC_ELOC];
+    double cap = 10.0 / sqt;
+    double eo = fmin(fmax(E_old, ET - cap), ET + cap);
+    double en = fmin(fmax(En, ET - cap), ET + cap);
+    double wt = exp(-tau * (0.5 * (eo + en) - ET));
+    double ub, dummy;
+    philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 2u, 0u, ub, dummy);
+    int nc = bad ? -1 : min(3, (int)floor(wt + ub));
+    wts[w] = bad ? NAN : wt;
+    wel[w] = bad ? NAN : wt * En;
+    ncopy[w] = nc;
+    nacc[w] = na;
+    if (bad) sc[SC_FLAGS] = 1.0;
+  }
+  __syncthreads();
+  store_record<NT>(wf, l, rec);
+}
+
+// Single-workgroup scan / reduction / trial-energy update of one DMC step.
+// Fixed summation order, so the result is independent of timing.
+__global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* wts, const double* wel,
+                                                   const int* ncopy, const double* nacc, int* offs,
+                                                   int64_t capacity, int N, int st, double tau,
+                                                   double W_target, double* pop, double* wsum,
+                                                   double* wesum, double* etrial, double* lacc, double* lprop) {
+  __shared__ double sw[1024], swe[1024], sa[1024];
+  __shared__ int sc_[1024];
+  __shared__ int bad;
+  int t = threadIdx.x;
+  if (ctrl[DC_ERR] != 0.0) return;
+  int64_t W = (int64_t)ctrl[DC_W];
+  int64_t per = (W + 1023) / 1024;
+  int64_t b = t * per, e = min(W, b + per);
+  double a = 0, ae = 0, aa = 0;
+  int cnt = 0, nbad = 0;
+  for (int64_t k = b; k < e; ++k) {
+    if (ncopy[k] < 0) { ++nbad; continue; }
+    a += wts[k];
+    ae += wel[k];
+    aa += nacc[k];
+    cnt += ncopy[k];
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  if (nbad) atomicAdd(&bad, nbad);
+  sw[t] = a; swe[t] = ae; sa[t] = aa; sc_[t] = cnt;
+  __syncthreads();
+  // inclusive scan of copy counts (Hillis-Steele) and tree sums
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? sc_[t - off] : 0;
+    __syncthreads();
+    sc_[t] += v;
+    __syncthreads();
+  }
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) {
+      sw[t] += sw[t + off];
+      swe[t] += swe[t + off];
+      sa[t] += sa[t + off];
+    }
+    __syncthreads();
+  }
+  int base = t > 0 ? sc_[t - 1] : 0;
+  for (int64_t k = b; k < e; ++k) {
+    offs[k] = base;
+    base += ncopy[k] > 0 ? ncopy[k] : 0;
+  }
+  if (t == 0) {
+    int64_t Wn = sc_[1023];
+    offs[W] = (int)Wn;
+    pop[st] = (double)W;
+    wsum[st] = sw[0];
+    wesum[st] = swe[0];
+    etrial[st] = ctrl[DC_ET];
+    lacc[st] = sa[0];
+    lprop[st] = (double)W * N;
+    if (bad || Wn <= 0 || Wn > capacity) {
+      ctrl[DC_ERR] = bad ? 1.0 : 2.0;
+      ctrl[DC_ERRSTEP] = (double)st;
+      ctrl[DC_WNEW] = (double)Wn;
+    } else {
+      ctrl[DC_RUN_NUM] += swe[0];
+      ctrl[DC_RUN_DEN] += sw[0];
+      ctrl[DC_WNEW] = (double)Wn;
+      ctrl[DC_ET] = ctrl[DC_RUN_NUM] / ctrl[DC_RUN_DEN] - (0.1 / tau) * log((double)Wn / W_target);
+    }
+  }
+}
+
+// copy record of each destination slot from its parent (binary search in offs)
+__global__ void k_dmc_copy(const double* ctrl, const double* src, double* dst, const int* offs, int rec_len) {
+  if (ctrl[DC_ERR] != 0.0) return;
+  int64_t W = (int64_t)ctrl[DC_W];
+  int64_t Wn = (int64_t)ctrl[DC_WNEW];
+  int64_t d = blockIdx.x;
+  if (d >= Wn) return;
+  int64_t lo = 0, hi = W - 1;  // largest parent p with offs[p] <= d
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    if (offs[mid] <= d) lo = mid; else hi = mid - 1;
+  }
+  const double* s = src + lo * rec_len;
+  double* o = dst + d * rec_len;
+  for (int k = threadIdx.x; k < rec_len; k += blockDim.x) o[k] = s[k];
+}
+
+__global__ void k_dmc_commit(double* ctrl) {
+  if (ctrl[DC_ERR] != 0.0) return;
+  ctrl[DC_W] = ctrl[DC_WNEW];
+}
+
+__global__ void k_copy_records(const double* src, double* dst, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_positions(const DevWF* __restrict__ pwf, int64_t W, const double* state, double* R) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  if (w >= W) return;
+  for (int k = threadIdx.x; k < 3 * wf.N; k += blockDim.x) R[w * 3 * wf.N + k] = state[w * wf.rec_len + wf.r_R + k];
+}
+
+__global__ void k_record_eloc(const DevWF* __restrict__ pwf, int64_t W, const double* state, double* e) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (w < W) e[w] = state[w * wf.rec_len + wf.r_sc + SC_ELOC];
+}
+
+// out[k] = sum_w in[w][k], fixed order: each block owns columns, each lane a
+// strided slice of walkers, then a lane tree.
+__global__ __launch_bounds__(256) void k_reduce(int64_t W, int K, const double* in, double* out) {
+  __shared__ double s[256];
+  int k = blockIdx.x;
+  double a = 0.0;
+  for (int64_t w = threadIdx.x; w < W; w += 256) a += in[w * K + k];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+static hipError_t set_lds(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int NT, int PREC>
+static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, double* logabs, int32_t* sign,
+                                    double* grad, double* eloc, double* ratio, double* state, hipStream_t s) {
+  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_evaluate<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, logabs, sign, grad,
+                     eloc, ratio, state);
+  return hipGetLastError();
+}
+
+template <int NT, int PREC>
+static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
+                               uint64_t step0, double step_size, int all_e, double* es, double* e2s,
+                               double* na, double* el, double* sij, hipStream_t s) {
+  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_vmc<NT, PREC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_vmc<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, state, W, nsteps, seed, step0,
+                     step_size, all_e, es, e2s, na, el, sij);
+  return hipGetLastError();
+}
+
+template <int NT, int PREC>
+static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap, uint64_t seed,
+                                    uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
+                                    hipStream_t s) {
+  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_dmc_step<NT, PREC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_dmc_step<NT, PREC>), dim3((unsigned)cap), dim3(NT), lds, s, dwf, state, ctrl, 0, seed, step,
+                     tau, wts, wel, ncopy, nacc);
+  return hipGetLastError();
+}
+
+#define VB_DISPATCH(NTV, FN, ...)                                              \
+  switch (wf.precision) {                                                      \
+    case 0: return FN<NTV, 0>(__VA_ARGS__);                                    \
+    case 1: return FN<NTV, 1>(__VA_ARGS__);                                    \
+    default: return FN<NTV, 2>(__VA_ARGS__);                                   \
+  }
+
+#define VB_DISPATCH_NT(NT, FN, ...)                                            \
+  switch (NT) {                                                                \
+    case 64: VB_DISPATCH(64, FN, __VA_ARGS__)                                  \
+    case 128: VB_DISPATCH(128, FN, __VA_ARGS__)                                \
+    default: VB_DISPATCH(256, FN, __VA_ARGS__)                                 \
+  }
+
+hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* logabs, int32_t* sign,
+                           double* grad, double* eloc, double* ratio, double* state, hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, logabs, sign, grad, eloc, ratio, state, s)
+}
+
+hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
+                      double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
+                      hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
+}
+
+hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
+                           uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
+                           hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s)
+}
+
+hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, const int* ncopy, const double* nacc,
+                           int* offs, int64_t cap, int N, int st, double tau, double W_target, double* pop,
+                           double* wsum, double* wesum, double* etrial, double* lacc, double* lprop,
+                           const double* src, double* dst, int rec_len, hipStream_t s) {
+  hipLaunchKernelGGL(k_dmc_scan, dim3(1), dim3(1024), 0, s, ctrl, wts, wel, ncopy, nacc, offs, cap, N, st, tau,
+                     W_target, pop, wsum, wesum, etrial, lacc, lprop);
+  hipLaunchKernelGGL(k_dmc_copy, dim3((unsigned)cap), dim3(256), 0, s, ctrl, src, dst, offs, rec_len);
+  hipLaunchKernelGGL(k_dmc_commit, dim3(1), dim3(1), 0, s, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_records, dim3(1024), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_positions, dim3((unsigned)W), dim3(64), 0, s, dwf, W, state, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s) {
+  hipLaunchKernelGGL(k_record_eloc, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s, dwf, W, state, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int64_t W, int K, const double* in, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)K), dim3(256), 0, s, W, K, in, out);
+  return hipGetLastError();
+}
+
+}  // namespace vbqmc

@@ -1,0 +1,122 @@
+"""GPU VMC and DMC against the oracle's walks with the same Philox streams.
+
+Proposals and acceptance draws are counter-based and identical on both
+sides, so short walks agree draw by draw: final positions, per-walker energy
+sums, acceptance counts, DMC populations and weighted energies.  An
+acceptance decision can flip only when u falls within rounding of |Psi'/Psi|^2
+(probability ~1e-13 per move); the tests allow no flips at these sizes."""
+
+import numpy as np
+import pytest
+
+import systems as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2207_14715_amd as vb
+    vb.load_library()
+    return vb
+
+
+def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=4242, step0=17, sij=False):
+    import torch
+    R0 = S.initial_walkers(sysd, W, seed=5)
+    o = oracle_mod.Oracle(sysd)
+    ref = o.vmc(R0, steps, seed, step0, step_size, all_electron, want_sij=sij)
+    ctx = lib.Context(sysd)
+    print(f"[vmc] {sysd['name']} W={W} steps={steps} all_electron={all_electron}", flush=True)
+    state = ctx.walkers_init(torch.from_numpy(R0).cuda())
+    acc = ctx.vmc_advance(state, steps, seed, step0, step_size, all_electron, acc=ctx.new_vmc_acc(W, sij=sij))
+    R = ctx.positions(state).cpu().numpy()
+    torch.cuda.synchronize()
+    return ref, acc, R, ctx
+
+
+def _check_vmc(ref, acc, R, steps, tol=1e-9):
+    same = np.all(np.abs(R - ref["R"]) <= 1e-9 * (1 + np.abs(ref["R"])), axis=(1, 2))
+    assert same.all(), f"{(~same).sum()} walkers diverged"
+    np.testing.assert_array_equal(acc["n_accept"].cpu().numpy(), ref["n_acc"])
+    es = acc["e_sum"].cpu().numpy()
+    scale = np.maximum(1.0, np.abs(ref["e2_sum"] / steps) ** 0.5 * steps)
+    assert np.max(np.abs(es - ref["e_sum"]) / scale) < tol
+
+
+def test_vmc_h2_all_electron(lib, oracle_mod):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, True)
+    _check_vmc(ref, acc, R, 30)
+
+
+def test_vmc_h2_single_electron(lib, oracle_mod):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, False)
+    _check_vmc(ref, acc, R, 30)
+
+
+def test_vmc_small_random_with_sij(lib, oracle_mod):
+    sysd = S.small_random_system(211, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 64, 20, 0.4, False, sij=True)
+    _check_vmc(ref, acc, R, 20)
+    np.testing.assert_allclose(acc["sij_sum"].cpu().numpy(), ref["sij_sum"], rtol=1e-8, atol=1e-8)
+
+
+def test_vmc_f2_sherman_morrison(lib, oracle_mod):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.f2_shaped(), 64, 12, 0.3, False)
+    _check_vmc(ref, acc, R, 12)
+
+
+def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3):
+    import torch
+    o = oracle_mod.Oracle(sysd)
+    R0 = S.initial_walkers(sysd, W, seed=8)
+    e0 = o.evaluate(R0)["eloc"]
+    et = float(np.mean(e0))
+    ref = o.dmc(R0, e0, steps, seed, step0, tau, et, W, capacity=4 * W)
+    ctx = lib.Context(sysd)
+    print(f"[dmc] {sysd['name']} W={W} steps={steps}", flush=True)
+    st0 = ctx.new_state(4 * W)
+    st1 = ctx.new_state(4 * W)
+    ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
+    out = ctx.dmc_advance([st0, st1], W, steps, seed, step0, tau, et, W)
+    R = ctx.positions(st0, out["W"]).cpu().numpy()
+    torch.cuda.synchronize()
+    return ref, out, R
+
+
+def _check_dmc(ref, out, R):
+    assert ref["rc"] == 0
+    np.testing.assert_array_equal(out["pop"].cpu().numpy(), ref["pop"])
+    assert out["W"] == ref["W"]
+    np.testing.assert_allclose(out["wsum"].cpu().numpy(), ref["wsum"], rtol=1e-9)
+    np.testing.assert_allclose(out["wesum"].cpu().numpy(), ref["wesum"], rtol=1e-8, atol=1e-8)
+    np.testing.assert_array_equal(out["n_accept"].cpu().numpy(), ref["acc"])
+    np.testing.assert_allclose(R, ref["R"], rtol=1e-8, atol=1e-8)
+
+
+def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod):
+    import torch
+    sysd = S.hydrogen_sto_1s(1.0)
+    ctx = lib.Context(sysd)
+    W = 512
+    R0 = torch.from_numpy(np.random.default_rng(3).normal(size=(W, 1, 3))).cuda()
+    st0, st1 = ctx.new_state(2 * W), ctx.new_state(2 * W)
+    ctx.walkers_init(R0, st0)
+    out = ctx.dmc_advance([st0, st1], W, 20, 5, 0, 0.01, -0.5, W)
+    assert out["W"] == W
+    np.testing.assert_array_equal(out["pop"].cpu().numpy(), W)
+    np.testing.assert_allclose(out["wesum"].cpu().numpy() / out["wsum"].cpu().numpy(), -0.5, atol=1e-12)
+
+
+def test_dmc_h2_trajectory(lib, oracle_mod):
+    ref, out, R = _dmc_pair(lib, oracle_mod, S.h2_heitler_london(), 128, 8, 0.01)
+    _check_dmc(ref, out, R)
+
+
+def test_dmc_small_random_trajectory(lib, oracle_mod):
+    sysd = S.small_random_system(311, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
+    ref, out, R = _dmc_pair(lib, oracle_mod, sysd, 64, 5, 0.005)
+    _check_dmc(ref, out, R)
