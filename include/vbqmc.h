@@ -114,6 +114,7 @@ typedef struct {
   int32_t n_basis, n_orbitals, n_structures;
   int32_t n_determinants;        /* distinct (up, down) determinant pairs */
   int32_t n_unique_up, n_unique_dn; /* distinct spin determinants */
+  int32_t n_table_up, n_table_dn;   /* orbitals replacing reference columns */
   int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei */
   int32_t block_threads;         /* threads per walker in the walker kernels */
   int64_t walker_state_bytes;    /* bytes per walker record */

@@ -55,7 +55,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("n_electrons", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
                 ("n_nuclei", ctypes.c_int32), ("n_basis", ctypes.c_int32), ("n_orbitals", ctypes.c_int32),
                 ("n_structures", ctypes.c_int32), ("n_determinants", ctypes.c_int32),
-                ("n_unique_up", ctypes.c_int32), ("n_unique_dn", ctypes.c_int32), ("n_params", ctypes.c_int32),
+                ("n_unique_up", ctypes.c_int32), ("n_unique_dn", ctypes.c_int32), ("n_table_up", ctypes.c_int32),
+                ("n_table_dn", ctypes.c_int32), ("n_params", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("walker_state_bytes", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int64)]
 

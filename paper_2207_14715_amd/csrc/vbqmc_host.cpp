@@ -114,7 +114,7 @@ struct vbqmc_ctx {
   // host copies
   int N = 0, nup = 0, ndn = 0, nnuc = 0, M = 0, Mpad = 0, norb = 0, nop = 0, nstruct = 0, nshell = 0;
   std::vector<double> nuc, en, pexp, pcoef, lam, c;
-  std::vector<int> shinfo, shprim, fnmap;
+  std::vector<int> shtab, fnmap, pshell;
   double ee[8];
   double kappa = 0;
   SpinHost sp[2];
@@ -239,11 +239,11 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     if (cen < 0 || cen >= x->nnuc || (kind != 0 && kind != 1) || l < 0 || l > 2 || np < 1 ||
         (kind == 1 && l > 1))
       return bad("bad shell description");
-    x->shinfo.insert(x->shinfo.end(), {cen, kind, l, fn});
-    x->shprim.insert(x->shprim.end(), {off, np});
+    x->shtab.insert(x->shtab.end(), {cen, kind, l, fn, off, np, 0, 0});
     for (int k = 0; k < np; ++k) {
       x->pexp.push_back(wfi->prim_exp[off + k]);
       x->pcoef.push_back(wfi->prim_coef[off + k]);
+      x->pshell.push_back(s);
     }
     for (int m = 0; m < nfunc(l); ++m) x->fnmap.insert(x->fnmap.end(), {s, m});
     off += np;
@@ -406,12 +406,14 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
       vnn += x->nuc[4 * a + 3] * x->nuc[4 * b + 3] / std::sqrt(dx * dx + dy * dy + dz * dz);
     }
   wf.vnn = vnn;
-  wf.ntiles5 = 5 * x->nop / 16;
-  int waves = (wf.ntiles5 + kMaxTilesPerWave - 1) / kMaxTilesPerWave;
+  wf.nprim = (int)x->pexp.size();
+  wf.nlinks = (int)x->slc.size();
+  for (int s = 0; s < 2; ++s) wf.nwl[s] = (int)x->sp[s].wother.size();
+  // threads per walker: one wave for small systems, more waves as the
+  // electron count and orbital tiles grow
   x->nt = 64;
-  if (x->nop > 16 || x->N > 24 || waves > 1) x->nt = 128;
-  if (x->nop > 32 || x->N > 48 || waves > 2) x->nt = 256;
-  if (waves > 4) return bad("too many orbitals for the MFMA tile budget");
+  if (x->nop > 16 || x->N > 24) x->nt = 128;
+  if (x->nop > 32 || x->N > 48) x->nt = 256;
 
   int nPm = std::max(x->sp[0].porb.size(), x->sp[1].porb.size());
   int nUm = std::max(x->sp[0].sets.size(), x->sp[1].sets.size());
@@ -424,18 +426,42 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.r_sc = rec(8);
   wf.hot_len = o;
   wf.r_gc = rec(3 * x->N * x->nop);
+  wf.r_bk = rec(wf.hot_len);
   wf.rec_len = (o + 31) / 32 * 32;
-  // LDS
+  // LDS: constant tables, walker state, scratch (offsets in doubles, each
+  // region 16-byte aligned; int tables use half a double per entry)
   o = 0;
   auto lds = [&](int n) { int r = o; o += (std::max(n, 1) + 1) / 2 * 2; return r; };
+  auto ilds = [&](int n) { return lds((n + 1) / 2); };
+  wf.l_fn = ilds(2 * x->Mpad);
+  wf.l_sh = ilds(8 * x->nshell);
+  wf.l_pe = lds(wf.nprim);
+  wf.l_pc = lds(wf.nprim);
+  wf.l_psh = ilds(wf.nprim);
+  wf.l_nuc = lds(4 * x->nnuc);
+  wf.l_en = lds(6 * x->nnuc);
+  for (int s = 0; s < 2; ++s) {
+    SpinHost& h = x->sp[s];
+    wf.l_ref[s] = ilds((int)h.ref.size());
+    wf.l_porb[s] = ilds((int)h.porb.size());
+    wf.l_ui[s] = ilds((int)h.uinfo.size());
+    wf.l_wrow[s] = ilds((int)h.wrow.size());
+    wf.l_woth[s] = ilds((int)h.wother.size());
+    wf.l_wcoef[s] = lds((int)h.wother.size());
+  }
+  wf.l_srow = ilds((int)x->srow.size());
+  wf.l_slu = ilds((int)x->slu.size());
+  wf.l_slc = lds((int)x->slc.size());
+  int lam_elems = x->Mpad * x->nop;
+  int lam_doubles = wf.precision == 0 ? lam_elems : (wf.precision == 1 ? (lam_elems + 1) / 2 : (lam_elems + 3) / 4);
+  // orbital coefficients go to LDS when they take at most 16 KiB
+  wf.lam_in_lds = lam_doubles * 8 <= 16384 ? 1 : 0;
+  wf.l_lam = wf.lam_in_lds ? lds(lam_doubles) : 0;
   wf.l_R = lds(3 * x->N);
-  wf.l_Rn = lds(3 * x->N);
   for (int s = 0; s < 2; ++s) {
     int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
     wf.l_B[s] = lds(n * n);
     wf.l_T[s] = lds(n * nP);
-    wf.l_Bn[s] = lds(n * n);
-    wf.l_Tn[s] = lds(n * nP);
     wf.l_PP[s] = lds(n * nP);
     wf.l_Ru[s] = lds((int)x->sp[s].sets.size());
     wf.l_Wu[s] = lds((int)x->sp[s].sets.size());
@@ -443,24 +469,25 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_Qu = lds(nUm);
   wf.l_sc = lds(SC_COUNT);
   wf.l_red = lds(kRedSlots);
-  wf.l_ipiv = lds(kMaxSpin / 2);
-  wf.l_f = lds(kMaxSpin);
+  int nmax = std::max(x->nup, x->ndn);
+  wf.l_ipiv = ilds(nmax);
+  wf.l_f = lds(nmax);
   wf.l_gU = lds(3 * x->N);
   wf.l_lU = lds(x->N);
   wf.l_gD = lds(3 * x->N);
   wf.l_lD = lds(x->N);
-  int xsz = std::max({5 * kGroup * kChunk, 5 * kGroup * x->nop, x->nt, 4 * x->nop});
-  wf.l_X = lds(xsz);
-  wf.l_Phi = wf.l_X;
+  wf.l_disp = lds(kGroup * x->nnuc * 4);
+  wf.l_gtab = lds(std::max(kGroup * x->nshell * 3, 3 * wf.nprim));
+  wf.l_Phi = lds(kGroup * x->nop);
+  wf.l_part = lds(std::max(x->nt, 4 * x->nop));
   wf.l_chi = lds(4 * x->Mpad);
   wf.l_v = lds(4 * x->nop);
   wf.l_y = lds(nPm + 1);
-  wf.l_bcol = lds(kMaxSpin);
-  wf.l_z = lds(kMaxSpin);
-  wf.l_yb = lds(64 * (nPm + 1));
+  wf.l_bcol = lds(nmax);
+  wf.l_z = lds(2 * nmax);
+  wf.l_yb = lds(kGroup * (nPm + 1));
   wf.l_sij = lds(x->nstruct * x->nstruct);
   wf.l_ratio = lds(x->nstruct);
-  wf.l_scr = 0;
   wf.lds_doubles = o;
 
   int dev = 0;
@@ -480,8 +507,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // ---- device tables ----
   size_t bytes = 0;
   auto add = [&](size_t n, size_t sz) { bytes += arena_bytes_for(n, sz); };
-  add(x->nuc.size(), 8); add(x->en.size(), 8); add(x->shinfo.size(), 4); add(x->shprim.size(), 4);
-  add(x->pexp.size(), 8); add(x->pcoef.size(), 8); add(x->fnmap.size(), 4);
+  add(x->nuc.size(), 8); add(x->en.size(), 8); add(x->shtab.size(), 4);
+  add(x->pexp.size(), 8); add(x->pcoef.size(), 8); add(x->pshell.size(), 4); add(x->fnmap.size(), 4);
   add((size_t)x->Mpad * x->nop, 8); add((size_t)x->Mpad * x->nop, 4); add((size_t)x->Mpad * x->nop, 2);
   for (int s = 0; s < 2; ++s) {
     SpinHost& h = x->sp[s];
@@ -498,10 +525,10 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   };
   double* d_nuc = carve<double>(p, x->nuc.size()); up(x->nuc.data(), x->nuc.size(), 8, d_nuc);
   x->d_en = carve<double>(p, x->en.size());
-  int* d_shinfo = carve<int>(p, x->shinfo.size()); up(x->shinfo.data(), x->shinfo.size(), 4, d_shinfo);
-  int* d_shprim = carve<int>(p, x->shprim.size()); up(x->shprim.data(), x->shprim.size(), 4, d_shprim);
+  int* d_shtab = carve<int>(p, x->shtab.size()); up(x->shtab.data(), x->shtab.size(), 4, d_shtab);
   double* d_pexp = carve<double>(p, x->pexp.size()); up(x->pexp.data(), x->pexp.size(), 8, d_pexp);
   double* d_pcoef = carve<double>(p, x->pcoef.size()); up(x->pcoef.data(), x->pcoef.size(), 8, d_pcoef);
+  int* d_pshell = carve<int>(p, x->pshell.size()); up(x->pshell.data(), x->pshell.size(), 4, d_pshell);
   int* d_fnmap = carve<int>(p, x->fnmap.size()); up(x->fnmap.data(), x->fnmap.size(), 4, d_fnmap);
   x->d_lamT = carve<double>(p, (size_t)x->Mpad * x->nop);
   x->d_lamT32 = carve<float>(p, (size_t)x->Mpad * x->nop);
@@ -523,8 +550,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_slc = carve<double>(p, x->slc.size());
   x->d_wf = (DevWF*)carve<char>(p, sizeof(DevWF));
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
-  wf.nuc = d_nuc; wf.en = x->d_en; wf.shinfo = d_shinfo; wf.shprim = d_shprim; wf.pexp = d_pexp;
-  wf.pcoef = d_pcoef; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
+  wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
+  wf.pcoef = d_pcoef; wf.pshell = d_pshell; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
   wf.srow = d_srow; wf.slu = d_slu; wf.slc = x->d_slc;
   if (upload_lambda(x) || upload_coefficients(x)) {
     hipFree(x->dmem);
@@ -548,6 +575,8 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->n_determinants = (int)x->pair_up.size();
   o->n_unique_up = (int)x->sp[0].sets.size();
   o->n_unique_dn = (int)x->sp[1].sets.size();
+  o->n_table_up = (int)x->sp[0].porb.size();
+  o->n_table_dn = (int)x->sp[1].porb.size();
   o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
   o->block_threads = x->nt;
   o->walker_state_bytes = (int64_t)x->wf.rec_len * 8;

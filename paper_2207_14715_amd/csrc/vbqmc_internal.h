@@ -8,9 +8,8 @@
 namespace vbqmc {
 
 constexpr int kGroup = 16;     // electrons per MFMA row tile
-constexpr int kChunk = 16;     // basis functions per K chunk of an AO tile
+constexpr int kChunk = 16;     // basis functions are padded to a multiple of this
 constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
-constexpr int kMaxTilesPerWave = 8;
 constexpr int kMaxSpin = 64;   // electrons per spin
 constexpr int kRedSlots = 64;  // doubles of block-reduction scratch
 
@@ -31,33 +30,37 @@ struct SpinTab {
 // Constant description of the wave function plus layouts, passed by value to
 // every kernel.
 struct DevWF {
-  int N, nup, ndn, nnuc, nshell, M, Mpad, norb, nop, nstruct;
+  int N, nup, ndn, nnuc, nshell, M, Mpad, norb, nop, nstruct, nprim, nlinks;
   int precision, refresh_every;
-  int ntiles5;  // 5 * nop / 16 MFMA output tiles of a full group pass
   double kappa, vnn;
   double ee[8];
   const double* nuc;    // [nnuc][4]: x, y, z, Z
   const double* en;     // [nnuc][6]
-  const int* shinfo;    // [nshell][4]: center, kind, l, first basis function
-  const int* shprim;    // [nshell][2]: first primitive, count
+  const int* shtab;     // [nshell][8]: center, kind, l, first function, first primitive, count, 0, 0
   const double* pexp;
   const double* pcoef;
+  const int* pshell;    // [nprim] shell of each primitive
   const int* fnmap;     // [Mpad][2]: shell (or -1 for padding), angular index m
   const double* lamT;   // [Mpad][nop] lambda transposed, zero padded
   const float* lamT32;
   const uint16_t* lamT16;  // bf16 bit patterns
   SpinTab sp[2];
+  int nwl[2];           // CSR lengths of the per-spin pair lists
   const int* srow;      // [nstruct + 1] CSR of structure links
   const int* slu;       // [nlinks][2]: up, down spin determinant
   const double* slc;    // [nlinks] d'_{I,k}
   // walker record (doubles)
   int rec_len, hot_len;
-  int r_R, r_B[2], r_T[2], r_sc, r_gc;
-  // LDS layout (doubles)
-  int l_R, l_Rn, l_B[2], l_T[2], l_Bn[2], l_Tn[2], l_PP[2];
+  int r_R, r_B[2], r_T[2], r_sc, r_gc, r_bk;
+  // LDS layout (offsets in doubles): constant tables staged once per block
+  int lam_in_lds;
+  int l_fn, l_sh, l_pe, l_pc, l_psh, l_nuc, l_en, l_lam;
+  int l_ref[2], l_porb[2], l_ui[2], l_wrow[2], l_woth[2], l_wcoef[2], l_srow, l_slu, l_slc;
+  // walker state and scratch
+  int l_R, l_B[2], l_T[2], l_PP[2];
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
   int l_gU, l_lU, l_gD, l_lD;
-  int l_scr, l_X, l_Phi, l_chi, l_v, l_y, l_bcol, l_z, l_yb, l_sij, l_ratio;
+  int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_yb, l_sij, l_ratio;
   int lds_doubles;
 };
 

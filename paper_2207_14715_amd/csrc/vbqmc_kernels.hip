@@ -130,25 +130,10 @@ template <typename T> __device__ __forceinline__ T dexp(T x);
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 
-// Gaussian (kind 0): g = sum c e^{-a r^2}, g1 = dg/d(r^2), g2 = d2g/d(r^2)^2.
-// Slater (kind 1): g = sum c e^{-a r}, g1 = dg/dr, g2 = d2g/dr2.
-// Primitives with exponent argument above 50 are below 2e-22 of their
-// coefficient and are skipped.
-template <typename T>
-__device__ __forceinline__ void radial(const DevWF& wf, int sh, int kind, T r2, T r, T& g, T& g1, T& g2) {
-  int off = wf.shprim[2 * sh], np = wf.shprim[2 * sh + 1];
-  g = T(0); g1 = T(0); g2 = T(0);
-  for (int k = 0; k < np; ++k) {
-    T a = (T)wf.pexp[off + k];
-    T t = kind == 0 ? a * r2 : a * r;
-    if (t < T(50)) {
-      T e = (T)wf.pcoef[off + k] * dexp<T>(-t);
-      g += e;
-      g1 -= a * e;
-      g2 += a * a * e;
-    }
-  }
-}
+// Radial sums of a shell: Gaussian (kind 0) g = sum c e^{-a r^2} with
+// g1 = dg/d(r^2), g2 = d2g/d(r^2)^2; Slater (kind 1) g = sum c e^{-a r} with
+// g1 = dg/dr, g2 = d2g/dr2.  Primitives whose exponent argument exceeds 50 are
+// below 2e-22 of their coefficient and are skipped.
 
 // channels of one basis function: 0 value, 1..3 gradient, 4 Laplacian
 template <typename T>
@@ -217,32 +202,55 @@ __device__ __forceinline__ double adj_e(int e, const double* m, const double* y,
   return s;
 }
 
-// gather T[J, Q] (+ optional rank-1 term bJ yQ / rho) of determinant u
+// gather T[J, Q] (+ optional rank-1 term bJ yQ / rho) of determinant u into m
+// (stride 3).  Loops run to 3 with guards so that m stays in registers.
 __device__ __forceinline__ int gather_u(const int* ui, const double* T, int nP, double* m,
                                         const double* bc, const double* y, double irho) {
   int e = ui[0];
-  for (int r = 0; r < e; ++r)
-    for (int c = 0; c < e; ++c) {
-      double v = T[ui[1 + r] * nP + ui[4 + c]];
-      if (bc) v += bc[ui[1 + r]] * y[ui[4 + c]] * irho;
-      m[r * 3 + c] = v;
-    }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (r < e && c < e) {
+        double v = T[ui[1 + r] * nP + ui[4 + c]];
+        if (bc) v += bc[ui[1 + r]] * y[ui[4 + c]] * irho;
+        m[r * 3 + c] = v;
+      }
   return e;
 }
 
 // ---------------------------------------------------------------------------
-// LDS views
+// LDS views.  The constant tables (basis, orbital coefficients when they fit,
+// determinant tables) are staged once per block; the walker state and the
+// scratch of each phase follow.
 // ---------------------------------------------------------------------------
 struct Ld {
   double* L;
   const DevWF& wf;
+  double* bk = nullptr;  // backup area of the walker record (all-electron moves)
   __device__ Ld(double* l, const DevWF& w) : L(l), wf(w) {}
+  // constant tables
+  __device__ const int* fn() const { return (const int*)(L + wf.l_fn); }      // [Mpad][2]
+  __device__ const int* sh() const { return (const int*)(L + wf.l_sh); }      // [nshell][8]
+  __device__ const double* pe() const { return L + wf.l_pe; }
+  __device__ const double* pc() const { return L + wf.l_pc; }
+  __device__ const double* nuc() const { return L + wf.l_nuc; }
+  __device__ const double* en() const { return L + wf.l_en; }
+  __device__ const int* psh() const { return (const int*)(L + wf.l_psh); }
+  __device__ const int* ref(int s) const { return (const int*)(L + wf.l_ref[s]); }
+  __device__ const int* porb(int s) const { return (const int*)(L + wf.l_porb[s]); }
+  __device__ const int* ui(int s) const { return (const int*)(L + wf.l_ui[s]); }
+  __device__ const int* wrow(int s) const { return (const int*)(L + wf.l_wrow[s]); }
+  __device__ const int* woth(int s) const { return (const int*)(L + wf.l_woth[s]); }
+  __device__ const double* wcoef(int s) const { return L + wf.l_wcoef[s]; }
+  __device__ const int* srow() const { return (const int*)(L + wf.l_srow); }
+  __device__ const int* slu() const { return (const int*)(L + wf.l_slu); }
+  __device__ const double* slc() const { return L + wf.l_slc; }
+  template <typename T> __device__ const T* lam() const;
+  // walker state
   __device__ double* R() const { return L + wf.l_R; }
-  __device__ double* Rn() const { return L + wf.l_Rn; }
   __device__ double* B(int s) const { return L + wf.l_B[s]; }
   __device__ double* T(int s) const { return L + wf.l_T[s]; }
-  __device__ double* Bn(int s) const { return L + wf.l_Bn[s]; }
-  __device__ double* Tn(int s) const { return L + wf.l_Tn[s]; }
   __device__ double* PP(int s) const { return L + wf.l_PP[s]; }
   __device__ double* Ru(int s) const { return L + wf.l_Ru[s]; }
   __device__ double* Wu(int s) const { return L + wf.l_Wu[s]; }
@@ -255,8 +263,10 @@ struct Ld {
   __device__ double* lU() const { return L + wf.l_lU; }
   __device__ double* gD() const { return L + wf.l_gD; }
   __device__ double* lD() const { return L + wf.l_lD; }
-  __device__ double* X() const { return L + wf.l_X; }
+  __device__ double* disp() const { return L + wf.l_disp; }
+  __device__ double* gtab() const { return L + wf.l_gtab; }
   __device__ double* Phi() const { return L + wf.l_Phi; }
+  __device__ double* part() const { return L + wf.l_part; }
   __device__ double* chi() const { return L + wf.l_chi; }
   __device__ double* v() const { return L + wf.l_v; }
   __device__ double* y() const { return L + wf.l_y; }
@@ -266,6 +276,15 @@ struct Ld {
   __device__ double* sij() const { return L + wf.l_sij; }
   __device__ double* ratio() const { return L + wf.l_ratio; }
 };
+template <> __device__ const double* Ld::lam<double>() const {
+  return wf.lam_in_lds ? (const double*)(L + wf.l_lam) : wf.lamT;
+}
+template <> __device__ const float* Ld::lam<float>() const {
+  return wf.lam_in_lds ? (const float*)(L + wf.l_lam) : wf.lamT32;
+}
+template <> __device__ const uint16_t* Ld::lam<uint16_t>() const {
+  return wf.lam_in_lds ? (const uint16_t*)(L + wf.l_lam) : wf.lamT16;
+}
 
 __device__ __forceinline__ int spin_of(const DevWF& wf, int i) { return i < wf.nup ? 0 : 1; }
 
@@ -275,107 +294,188 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
+template <int NT, typename T>
+__device__ __forceinline__ void stage(T* dst, const T* src, int n) {
+  for (int k = threadIdx.x; k < n; k += NT) dst[k] = src[k];
+}
+
+// copy the constant tables into LDS (once per block)
+template <int NT, int PREC>
+__device__ void stage_tables(const DevWF& wf, const Ld& l) {
+  double* L = l.L;
+  stage<NT>((int*)(L + wf.l_fn), wf.fnmap, 2 * wf.Mpad);
+  stage<NT>((int*)(L + wf.l_sh), wf.shtab, 8 * wf.nshell);
+  stage<NT>(L + wf.l_pe, wf.pexp, wf.nprim);
+  stage<NT>(L + wf.l_pc, wf.pcoef, wf.nprim);
+  stage<NT>((int*)(L + wf.l_psh), wf.pshell, wf.nprim);
+  stage<NT>(L + wf.l_nuc, wf.nuc, 4 * wf.nnuc);
+  stage<NT>(L + wf.l_en, wf.en, 6 * wf.nnuc);
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    stage<NT>((int*)(L + wf.l_ref[s]), st.ref, st.n);
+    stage<NT>((int*)(L + wf.l_porb[s]), st.porb, st.nP);
+    stage<NT>((int*)(L + wf.l_ui[s]), st.uinfo, 8 * st.nU);
+    stage<NT>((int*)(L + wf.l_wrow[s]), st.wrow, st.nU + 1);
+    stage<NT>((int*)(L + wf.l_woth[s]), st.wother, wf.nwl[s]);
+    stage<NT>(L + wf.l_wcoef[s], st.wcoef, wf.nwl[s]);
+  }
+  stage<NT>((int*)(L + wf.l_srow), wf.srow, wf.nstruct + 1);
+  stage<NT>((int*)(L + wf.l_slu), wf.slu, 2 * wf.nlinks);
+  stage<NT>(L + wf.l_slc, wf.slc, wf.nlinks);
+  if (wf.lam_in_lds) {
+    int n = wf.Mpad * wf.nop;
+    if constexpr (PREC == 0) stage<NT>(L + wf.l_lam, wf.lamT, n);
+    else if constexpr (PREC == 1) stage<NT>((float*)(L + wf.l_lam), wf.lamT32, n);
+    else stage<NT>((uint16_t*)(L + wf.l_lam), wf.lamT16, n);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // AO -> orbital contraction for a tile of up to 16 electrons on MFMA.
-// Writes Phi[c][e][p] (c < nch, e < 16, p < nop) in LDS as FP64.
+// group_radial fills, per electron of the tile, the displacement to every
+// nucleus and the radial sums of every shell; group_channel then builds the
+// A operand (basis channel c at electron e, function mu) on the fly from those
+// tables and contracts it with lambda^T, one 16x16 output tile at a time,
+// writing Phi[e][p] (FP64) for channel c.
 // ---------------------------------------------------------------------------
 template <int NT, int PREC>
-__device__ void group_pass(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne, int nch) {
+__device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  T* disp = (T*)l.disp();  // [16][nnuc][4]: x, y, z, r2
+  T* gt = (T*)l.gtab();    // [16][nshell][3]: g, g1, g2
+  for (int idx = threadIdx.x; idx < kGroup * wf.nnuc; idx += NT) {
+    int e = idx / wf.nnuc, a = idx - e * wf.nnuc;
+    T x = 0, y = 0, z = 0;
+    if (e < ne) {
+      x = (T)(Rsrc[3 * (g0 + e)] - l.nuc()[4 * a]);
+      y = (T)(Rsrc[3 * (g0 + e) + 1] - l.nuc()[4 * a + 1]);
+      z = (T)(Rsrc[3 * (g0 + e) + 2] - l.nuc()[4 * a + 2]);
+    }
+    disp[4 * idx] = x; disp[4 * idx + 1] = y; disp[4 * idx + 2] = z;
+    disp[4 * idx + 3] = x * x + y * y + z * z;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
+    int e = idx / wf.nshell, sh = idx - e * wf.nshell;
+    const int* si = l.sh() + 8 * sh;
+    T r2 = disp[4 * (e * wf.nnuc + si[0]) + 3], r = sqrt(r2);
+    T g = 0, g1 = 0, g2 = 0;
+    if (e < ne) {
+      for (int k = 0; k < si[5]; ++k) {
+        T a = (T)l.pe()[si[4] + k];
+        T t = si[1] == 0 ? a * r2 : a * r;
+        if (t < T(50)) {
+          T ex = (T)l.pc()[si[4] + k] * dexp<T>(-t);
+          g += ex;
+          g1 -= a * ex;
+          g2 += a * a * ex;
+        }
+      }
+    }
+    gt[3 * idx] = g; gt[3 * idx + 1] = g1; gt[3 * idx + 2] = g2;
+  }
+  __syncthreads();
+}
+
+// basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function mu at
+// electron e of the tile, from the radial tables
+template <typename T>
+__device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
+  const int* fn = l.fn();
+  int sh = fn[2 * mu];
+  if (sh < 0) return T(0);
+  int m = fn[2 * mu + 1];
+  const int* si = l.sh() + 8 * sh;
+  int kind = si[1], lq = si[2];
+  const T* d = (const T*)l.disp() + 4 * (e * wf.nnuc + si[0]);
+  const T* gg = (const T*)l.gtab() + 3 * (e * wf.nshell + sh);
+  T x = d[0], y = d[1], z = d[2], r2 = d[3];
+  T g = gg[0], g1 = gg[1], g2 = gg[2];
+  T P, Px = T(0), Py = T(0), Pz = T(0);
+  if (lq == 0) {
+    P = T(1);
+  } else if (lq == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? T(1) : T(0);
+    Py = m == 1 ? T(1) : T(0);
+    Pz = m == 2 ? T(1) : T(0);
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = T(2) * x; Py = T(-2) * y; break;
+      default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
+    }
+  }
+  if (c == 0) return P * g;
+  if (kind == 0) {
+    if (c == 4) return P * (T(2 * (2 * lq + 3)) * g1 + T(4) * r2 * g2);
+    T fr = T(2) * g1;
+    if (c == 1) return Px * g + P * fr * x;
+    if (c == 2) return Py * g + P * fr * y;
+    return Pz * g + P * fr * z;
+  }
+  T r = sqrt(r2);
+  if (c == 4) return P * (g2 + T(2 * (lq + 1)) * g1 / r);
+  T fr = g1 / r;
+  if (c == 1) return Px * g + P * fr * x;
+  if (c == 2) return Py * g + P * fr * y;
+  return Pz * g + P * fr * z;
+}
+
+template <int NT, int PREC>
+__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
   const int nct = wf.nop / 16;
-  const int ntiles = nch * nct;
-  typedef typename std::conditional<PREC == 0, v4d, v4f>::type acc_t;
-  acc_t acc[kMaxTilesPerWave];
-#pragma unroll
-  for (int t = 0; t < kMaxTilesPerWave; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  double* Xd = l.X();
-  float* Xf = (float*)l.X();
-  uint16_t* Xh = (uint16_t*)l.X();
-  for (int k0 = 0; k0 < wf.Mpad; k0 += kChunk) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kGroup * kChunk; idx += NT) {
-      int e = idx / kChunk, kk = idx - e * kChunk, mu = k0 + kk;
-      int sh = wf.fnmap[2 * mu];
-      if constexpr (PREC == 0) {
-        double o[5] = {0, 0, 0, 0, 0};
-        if (e < ne && sh >= 0) {
-          int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2];
-          double x = Rsrc[3 * (g0 + e)] - wf.nuc[4 * a], y = Rsrc[3 * (g0 + e) + 1] - wf.nuc[4 * a + 1],
-                 z = Rsrc[3 * (g0 + e) + 2] - wf.nuc[4 * a + 2];
-          double r2 = x * x + y * y + z * z, r = sqrt(r2), g, g1, g2;
-          radial<double>(wf, sh, kind, r2, r, g, g1, g2);
-          channels<double>(kind, lq, wf.fnmap[2 * mu + 1], x, y, z, r2, r, g, g1, g2, nch, o);
-        }
-        for (int c = 0; c < nch; ++c) Xd[(c * kGroup + e) * kChunk + kk] = o[c];
-      } else {
-        float o[5] = {0, 0, 0, 0, 0};
-        if (e < ne && sh >= 0) {
-          int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2];
-          float x = (float)(Rsrc[3 * (g0 + e)] - wf.nuc[4 * a]);
-          float y = (float)(Rsrc[3 * (g0 + e) + 1] - wf.nuc[4 * a + 1]);
-          float z = (float)(Rsrc[3 * (g0 + e) + 2] - wf.nuc[4 * a + 2]);
-          float r2 = x * x + y * y + z * z, r = sqrtf(r2), g, g1, g2;
-          radial<float>(wf, sh, kind, r2, r, g, g1, g2);
-          channels<float>(kind, lq, wf.fnmap[2 * mu + 1], x, y, z, r2, r, g, g1, g2, nch, o);
-        }
-        if constexpr (PREC == 1)
-          for (int c = 0; c < nch; ++c) Xf[(c * kGroup + e) * kChunk + kk] = o[c];
-        else
-          for (int c = 0; c < nch; ++c) Xh[(c * kGroup + e) * kChunk + kk] = f2bf(o[c]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kMaxTilesPerWave; ++t) {
-      int tile = wave + t * NW;
-      if (tile < ntiles) {
-        int c = tile / nct, ct = tile - c * nct;
-        int col = ct * 16 + (lane & 15);
-        if constexpr (PREC == 0) {
-#pragma unroll
-          for (int s = 0; s < kChunk / 4; ++s) {
-            int k = 4 * s + (lane >> 4);
-            double a = Xd[(c * kGroup + (lane & 15)) * kChunk + k];
-            double b = wf.lamT[(size_t)(k0 + k) * wf.nop + col];
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-          }
-        } else if constexpr (PREC == 1) {
-#pragma unroll
-          for (int s = 0; s < kChunk / 4; ++s) {
-            int k = 4 * s + (lane >> 4);
-            float a = Xf[(c * kGroup + (lane & 15)) * kChunk + k];
-            float b = wf.lamT32[(size_t)(k0 + k) * wf.nop + col];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-          }
-        } else {
-          int kb = 4 * (lane >> 4);
-          v4s a, b;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            a[j] = (short)Xh[(c * kGroup + (lane & 15)) * kChunk + kb + j];
-            b[j] = (short)wf.lamT16[(size_t)(k0 + kb + j) * wf.nop + col];
-          }
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-        }
-      }
-    }
-  }
-  __syncthreads();  // every read of X is done before Phi (which may alias X) is written
   double* Phi = l.Phi();
-#pragma unroll
-  for (int t = 0; t < kMaxTilesPerWave; ++t) {
-    int tile = wave + t * NW;
-    if (tile < ntiles) {
-      int c = tile / nct, ct = tile - c * nct;
-      int col = ct * 16 + (lane & 15);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // output lane layout: f64 16x16x4 holds row 4r + lane/16, the f32 and
-        // bf16 forms hold row 4(lane/16) + r (column lane%16 in both)
-        int row = PREC == 0 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
-        Phi[(c * kGroup + row) * wf.nop + col] = (double)acc[t][r];
+  for (int ct = wave; ct < nct; ct += NW) {
+    const int col = ct * 16 + (lane & 15);
+    const int e = lane & 15;
+    const bool live = e < ne;
+    if constexpr (PREC == 0) {
+      const double* lam = l.lam<double>();
+      v4d acc = {0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        double a = live ? chan_value<double>(wf, l, e, k, c) : 0.0;
+        double b = lam[(size_t)k * wf.nop + col];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
+      // f64 16x16x4 output: register r of lane l holds row 4r + l/16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * r + (lane >> 4)) * wf.nop + col] = acc[r];
+    } else if constexpr (PREC == 1) {
+      const float* lam = l.lam<float>();
+      v4f acc = {0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        float a = live ? chan_value<float>(wf, l, e, k, c) : 0.f;
+        float b = lam[(size_t)k * wf.nop + col];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+      // f32 output: register r of lane l holds row 4(l/16) + r
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+    } else {
+      const uint16_t* lam = l.lam<uint16_t>();
+      v4f acc = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        int kb = k0 + 4 * (lane >> 4);
+        v4s a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[j] = (short)(live ? f2bf(chan_value<float>(wf, l, e, kb + j, c)) : (uint16_t)0);
+          b[j] = (short)lam[(size_t)(kb + j) * wf.nop + col];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
     }
   }
   __syncthreads();
@@ -463,7 +563,7 @@ __device__ void update_R(const DevWF& wf, const Ld& l, int s) {
   const SpinTab& st = wf.sp[s];
   for (int u = threadIdx.x; u < st.nU; u += NT) {
     double m[9];
-    int e = gather_u(st.uinfo + 8 * u, l.T(s), st.nP, m, nullptr, nullptr, 0.0);
+    int e = gather_u(l.ui(s) + 8 * u, l.T(s), st.nP, m, nullptr, nullptr, 0.0);
     l.Ru(s)[u] = det_e(e, m);
   }
 }
@@ -472,9 +572,12 @@ template <int NT>
 __device__ void update_W(const DevWF& wf, const Ld& l, int s) {
   const SpinTab& st = wf.sp[s];
   const double* Ro = l.Ru(1 - s);
+  const int* wr = l.wrow(s);
+  const int* wo = l.woth(s);
+  const double* wc = l.wcoef(s);
   for (int u = threadIdx.x; u < st.nU; u += NT) {
     double w = 0.0;
-    for (int k = st.wrow[u]; k < st.wrow[u + 1]; ++k) w += st.wcoef[k] * Ro[st.wother[k]];
+    for (int k = wr[u]; k < wr[u + 1]; ++k) w += wc[k] * Ro[wo[k]];
     l.Wu(s)[u] = w;
   }
 }
@@ -507,7 +610,8 @@ template <int NT, int PREC>
 __device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
   for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
     int ne = min(kGroup, wf.N - g0);
-    group_pass<NT, PREC>(wf, l, Rsrc, g0, ne, 1);
+    group_radial<NT, PREC>(wf, l, Rsrc, g0, ne);
+    group_channel<NT, PREC>(wf, l, ne, 0);
     const double* Phi = l.Phi();
     for (int s = 0; s < 2; ++s) {
       const SpinTab& st = wf.sp[s];
@@ -517,9 +621,9 @@ __device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
         if (spin_of(wf, i) != s) continue;
         int il = i - st.e0;
         if (j < st.n)
-          l.B(s)[il * st.n + j] = Phi[e * wf.nop + st.ref[j]];
+          l.B(s)[il * st.n + j] = Phi[e * wf.nop + l.ref(s)[j]];
         else
-          l.PP(s)[il * st.nP + (j - st.n)] = Phi[e * wf.nop + st.porb[j - st.n]];
+          l.PP(s)[il * st.nP + (j - st.n)] = Phi[e * wf.nop + l.porb(s)[j - st.n]];
       }
     }
     __syncthreads();
@@ -552,19 +656,20 @@ __device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
 template <int NT>
 __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
   double part[2] = {0.0, 0.0};  // U, V
+  const double* nuc = l.nuc();
   for (int i = threadIdx.x; i < wf.N; i += NT) {
     double xi = Rsrc[3 * i], yi = Rsrc[3 * i + 1], zi = Rsrc[3 * i + 2];
     double gx = 0, gy = 0, gz = 0, lap = 0, Ui = 0, Vi = 0;
     for (int a = 0; a < wf.nnuc; ++a) {
-      double dx = xi - wf.nuc[4 * a], dy = yi - wf.nuc[4 * a + 1], dz = zi - wf.nuc[4 * a + 2];
+      double dx = xi - nuc[4 * a], dy = yi - nuc[4 * a + 1], dz = zi - nuc[4 * a + 2];
       double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
-      const double* ja = wf.en + 6 * a;
+      const double* ja = l.en() + 6 * a;
       pair_fn(r, wf.kappa, ja[0], ja[1], ja + 2, u, u1, u2);
       Ui += u;
       double f = u1 / r;
       gx += f * dx; gy += f * dy; gz += f * dz;
       lap += u2 + 2.0 * f;
-      Vi -= wf.nuc[4 * a + 3] / r;
+      Vi -= nuc[4 * a + 3] / r;
     }
     int si = spin_of(wf, i);
     for (int j = 0; j < wf.N; ++j) {
@@ -593,64 +698,74 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
 }
 
 // ---------------------------------------------------------------------------
-// Row-operator ratios of one electron: sum_u (rho R_u + y^T adj(T_JQ) B_J,i) W_u
-// for a row w (length nop in LDS) of electron i.
+// Row-operator ratio of one electron: sum_u (rho R_u + y^T adj(T_JQ) B_J,i) W_u
+// for a row w (length nop) of electron il of spin s.
 // ---------------------------------------------------------------------------
 __device__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf) {
   const SpinTab& st = wf.sp[s];
   const double* B = l.B(s);
   const double* T = l.T(s);
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
   double rho = 0.0;
-  for (int j = 0; j < st.n; ++j) rho += w[st.ref[j]] * B[j * st.n + il];
+#pragma unroll 4
+  for (int j = 0; j < st.n; ++j) rho += w[ref[j]] * B[j * st.n + il];
   for (int q = 0; q < st.nP; ++q) {
-    double a = w[st.porb[q]];
-    for (int k = 0; k < st.n; ++k) a -= w[st.ref[k]] * T[k * st.nP + q];
+    double a = w[porb[q]];
+#pragma unroll 4
+    for (int k = 0; k < st.n; ++k) a -= w[ref[k]] * T[k * st.nP + q];
     ybuf[q] = a;
   }
   double tot = 0.0;
+  const int* uit = l.ui(s);
   for (int u = 0; u < st.nU; ++u) {
-    const int* ui = st.uinfo + 8 * u;
+    const int* ui = uit + 8 * u;
     double m[9], yy[3], bb[3];
     int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
-    for (int r = 0; r < e; ++r) {
-      yy[r] = ybuf[ui[4 + r]];
-      bb[r] = B[ui[1 + r] * st.n + il];
-    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = ybuf[ui[4 + r]];
+        bb[r] = B[ui[1 + r] * st.n + il];
+      }
     tot += (rho * l.Ru(s)[u] + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
   }
   return tot;
 }
 
 // ---------------------------------------------------------------------------
-// Local energy pass: 5-channel MFMA passes over electron tiles, row-operator
-// ratios, Jastrow, potential.  Fills gD, lD, gU, lU and the scalars
-// SC_ELOC, SC_LOGPSI, SC_SIGN.  gc (DMC gradient cache) may be null.
+// Local energy pass: per tile of electrons, MFMA channels 1..4 (gradient and
+// Laplacian rows), row-operator ratios, then the Jastrow and potential.
+// Fills gD, lD, gU, lU and SC_ELOC, SC_LOGPSI, SC_SIGN.  gc (the DMC
+// gradient cache in the walker record) may be null.
 // ---------------------------------------------------------------------------
 template <int NT, int PREC>
 __device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
   const double* R = l.R();
   const double S = l.sc()[SC_S];
-  int nPmax = max(wf.sp[0].nP, wf.sp[1].nP);
+  const int nPmax = max(wf.sp[0].nP, wf.sp[1].nP);
   for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
     int ne = min(kGroup, wf.N - g0);
-    group_pass<NT, PREC>(wf, l, R, g0, ne, 5);
-    const double* Phi = l.Phi();
-    for (int idx = threadIdx.x; idx < ne * 4; idx += NT) {
-      int e = idx >> 2, c = 1 + (idx & 3), i = g0 + e;
-      int s = spin_of(wf, i), il = i - wf.sp[s].e0;
-      double tot = row_op_sum(wf, l, s, il, Phi + (c * kGroup + e) * wf.nop, l.yb() + idx * (nPmax + 1));
-      if (c < 4)
-        l.gD()[3 * i + c - 1] = tot / S;
-      else
-        l.lD()[i] = tot / S;
-    }
-    if (gc)
-      for (int idx = threadIdx.x; idx < ne * 3 * wf.nop; idx += NT) {
-        int e = idx / (3 * wf.nop), rem = idx - e * 3 * wf.nop;
-        int c = rem / wf.nop, p = rem - c * wf.nop;
-        gc[((g0 + e) * 3 + c) * wf.nop + p] = Phi[((1 + c) * kGroup + e) * wf.nop + p];
+    group_radial<NT, PREC>(wf, l, R, g0, ne);
+    for (int c = 1; c <= 4; ++c) {
+      group_channel<NT, PREC>(wf, l, ne, c);
+      const double* Phi = l.Phi();
+      for (int e = threadIdx.x; e < ne; e += NT) {
+        int i = g0 + e;
+        int s = spin_of(wf, i), il = i - wf.sp[s].e0;
+        double tot = row_op_sum(wf, l, s, il, Phi + e * wf.nop, l.yb() + e * (nPmax + 1));
+        if (c < 4)
+          l.gD()[3 * i + c - 1] = tot / S;
+        else
+          l.lD()[i] = tot / S;
       }
-    __syncthreads();
+      if (gc && c < 4)
+        for (int idx = threadIdx.x; idx < ne * wf.nop; idx += NT) {
+          int e = idx / wf.nop, p = idx - e * wf.nop;
+          gc[((g0 + e) * 3 + c - 1) * wf.nop + p] = Phi[idx];
+        }
+      __syncthreads();
+    }
   }
   jastrow_full<NT>(wf, l, R);
   double part[1] = {0.0};
@@ -676,58 +791,99 @@ __device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
 template <int NT>
 __device__ void structure_ratios(const DevWF& wf, const Ld& l) {
   double S = l.sc()[SC_S];
+  const int* srow = l.srow();
+  const int* slu = l.slu();
+  const double* slc = l.slc();
   for (int I = threadIdx.x; I < wf.nstruct; I += NT) {
     double a = 0.0;
-    for (int k = wf.srow[I]; k < wf.srow[I + 1]; ++k)
-      a += wf.slc[k] * l.Ru(0)[wf.slu[2 * k]] * l.Ru(1)[wf.slu[2 * k + 1]];
+    for (int k = srow[I]; k < srow[I + 1]; ++k) a += slc[k] * l.Ru(0)[slu[2 * k]] * l.Ru(1)[slu[2 * k + 1]];
     l.ratio()[I] = a / S;
   }
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// basis values (+ gradients if nch = 4) at one point, one lane per shell, and
-// their contraction to orbital rows v[c][p] (VALU).
+// Basis values (+ gradients if nch = 4) at one point and their contraction to
+// orbital rows v[c][p] on the VALU.  One lane per primitive forms the
+// exponentials, one lane per basis function sums its shell's primitives and
+// applies the angular factor, then lanes split the basis sum of each output
+// and reduce with cross-lane shuffles.
 // ---------------------------------------------------------------------------
 template <int NT, int PREC>
 __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double py, double pz, int nch) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   T* chi = (T*)l.chi();
-  for (int sh = threadIdx.x; sh < wf.nshell; sh += NT) {
-    int a = wf.shinfo[4 * sh], kind = wf.shinfo[4 * sh + 1], lq = wf.shinfo[4 * sh + 2], f0 = wf.shinfo[4 * sh + 3];
-    T x = (T)(px - wf.nuc[4 * a]), y = (T)(py - wf.nuc[4 * a + 1]), z = (T)(pz - wf.nuc[4 * a + 2]);
-    T r2 = x * x + y * y + z * z, r = sqrt(r2), g, g1, g2;
-    radial<T>(wf, sh, kind, r2, r, g, g1, g2);
-    int nf = lq == 0 ? 1 : (lq == 1 ? 3 : 5);
-    for (int m = 0; m < nf; ++m) {
-      T o[5];
-      channels<T>(kind, lq, m, x, y, z, r2, r, g, g1, g2, nch, o);
-      for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + f0 + m] = o[c];
-    }
+  T* pt = (T*)l.gtab();  // [nprim][3] primitive terms (the radial table is free during moves)
+  const double* nuc = l.nuc();
+  const int* psh = l.psh();
+  for (int q = threadIdx.x; q < wf.nprim; q += NT) {
+    const int* si = l.sh() + 8 * psh[q];
+    int a = si[0];
+    T x = (T)(px - nuc[4 * a]), y = (T)(py - nuc[4 * a + 1]), z = (T)(pz - nuc[4 * a + 2]);
+    T r2 = x * x + y * y + z * z;
+    T al = (T)l.pe()[q];
+    T t = si[1] == 0 ? al * r2 : al * sqrt(r2);
+    T ex = t < T(50) ? (T)l.pc()[q] * dexp<T>(-t) : T(0);
+    pt[3 * q] = ex;
+    pt[3 * q + 1] = -al * ex;
   }
-  for (int mu = wf.M + threadIdx.x; mu < wf.Mpad; mu += NT)
-    for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = T(0);
   __syncthreads();
-  // v[c][p]: split the basis sum over NPART lanes per output, then reduce
+  for (int mu = threadIdx.x; mu < wf.Mpad; mu += NT) {
+    int sh = l.fn()[2 * mu];
+    if (sh < 0) {
+      for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = T(0);
+      continue;
+    }
+    const int* si = l.sh() + 8 * sh;
+    int a = si[0], kind = si[1], lq = si[2], p0 = si[4], np = si[5];
+    T x = (T)(px - nuc[4 * a]), y = (T)(py - nuc[4 * a + 1]), z = (T)(pz - nuc[4 * a + 2]);
+    T r2 = x * x + y * y + z * z, r = sqrt(r2);
+    T g = 0, g1 = 0;
+#pragma unroll 4
+    for (int k = 0; k < np; ++k) {
+      g += pt[3 * (p0 + k)];
+      g1 += pt[3 * (p0 + k) + 1];
+    }
+    T o[5];
+    channels<T>(kind, lq, l.fn()[2 * mu + 1], x, y, z, r2, r, g, g1, T(0), nch, o);
+    for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = o[c];
+  }
+  __syncthreads();
+  typedef typename std::conditional<PREC == 0, double, float>::type LT;
+  const LT* lam = l.lam<LT>();
   const int nout = nch * wf.nop;
-  const int nparts = max(1, NT / nout);
-  double* part = l.X();  // scratch [nparts][nout]
-  for (int idx = threadIdx.x; idx < nout * nparts; idx += NT) {
-    int pt = idx / nout, o = idx - pt * nout, c = o / wf.nop, p = o - c * wf.nop;
-    int m0 = (wf.Mpad * pt) / nparts, m1 = (wf.Mpad * (pt + 1)) / nparts;
-    T a = T(0);
-    if constexpr (PREC == 0) {
-      for (int mu = m0; mu < m1; ++mu) a += chi[c * wf.Mpad + mu] * (T)wf.lamT[(size_t)mu * wf.nop + p];
-    } else {
-      for (int mu = m0; mu < m1; ++mu) a += chi[c * wf.Mpad + mu] * (T)wf.lamT32[(size_t)mu * wf.nop + p];
+  if (nout <= 64) {
+    // one wave: lane = part * nout + o, parts reduced with shuffles
+    if (threadIdx.x < 64) {
+      // lane = o * nparts + part (nparts a power of two): adjacent lanes
+      // split one output's basis sum and are combined with xor shuffles
+      int lg = 0;
+      while ((2 << lg) * nout <= 64) ++lg;
+      const int nparts = 1 << lg;
+      const int lane = threadIdx.x, o = lane >> lg, pt_ = lane & (nparts - 1);
+      const int chunk = wf.Mpad >> lg;  // Mpad is a multiple of 16 and nparts <= 64 / 16
+      T acc = T(0);
+      if (o < nout) {
+        int c = (o >= wf.nop) + (o >= 2 * wf.nop) + (o >= 3 * wf.nop);
+        int p = o - c * wf.nop;
+        const T* ch = chi + c * wf.Mpad + pt_ * chunk;
+        const LT* lp = lam + (size_t)pt_ * chunk * wf.nop + p;
+#pragma unroll 4
+        for (int k = 0; k < chunk; ++k) acc += ch[k] * (T)lp[(size_t)k * wf.nop];
+      }
+      double a = (double)acc;
+      for (int off = 1; off < nparts; off <<= 1) a += __shfl_xor(a, off, 64);
+      if (o < nout && pt_ == 0) l.v()[o] = a;
     }
-    part[idx] = (double)a;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += NT) {
-    double a = 0.0;
-    for (int pt = 0; pt < nparts; ++pt) a += part[pt * nout + o];
-    l.v()[o] = a;
+  } else {
+    for (int o = threadIdx.x; o < nout; o += NT) {
+      int c = o / wf.nop, p = o - c * wf.nop;
+      const T* ch = chi + c * wf.Mpad;
+      T acc = T(0);
+#pragma unroll 4
+      for (int mu = 0; mu < wf.Mpad; ++mu) acc += ch[mu] * (T)lam[(size_t)mu * wf.nop + p];
+      l.v()[o] = (double)acc;
+    }
   }
   __syncthreads();
 }
@@ -735,50 +891,45 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
 // ---------------------------------------------------------------------------
 // Single-electron move of electron i to (px,py,pz): ratio of determinant sums
 // S''/S (written to SC_RATIO) and Jastrow change dU (SC_TMP0); fills y (value
-// channel), bcol (old B column) and Qu.  Requires v[0][*] to hold the new
-// orbital values.
+// channel), bcol (old B column), rho (SC_TMP1) and Qu.  Requires v[0][*] to
+// hold the new orbital values.
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
   int s = spin_of(wf, i);
   const SpinTab& st = wf.sp[s];
+  const int n = st.n, nP = st.nP;
   int il = i - st.e0;
   const double* v = l.v();
   const double* B = l.B(s);
   const double* T = l.T(s);
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
   double* y = l.y();
   double* bc = l.bcol();
-  for (int idx = threadIdx.x; idx <= st.nP + st.n; idx += NT) {
-    if (idx < st.nP) {
-      double a = v[st.porb[idx]];
-      for (int k = 0; k < st.n; ++k) a -= v[st.ref[k]] * T[k * st.nP + idx];
-      y[idx] = a;
-    } else if (idx == st.nP) {
-      double a = 0.0;
-      for (int j = 0; j < st.n; ++j) a += v[st.ref[j]] * B[j * st.n + il];
-      l.sc()[SC_TMP1] = a;  // rho
-    } else {
-      int j = idx - st.nP - 1;
-      bc[j] = B[j * st.n + il];
-    }
+  double* vr = l.z() + n;  // gathered v[ref[j]] (z holds n more entries used on accept)
+  // phase 1: gather v[ref], old B column, rho = sum_j v[ref_j] B[j][i]
+  double prod = 0.0;
+  for (int j = threadIdx.x; j < n; j += NT) {
+    double a = v[ref[j]], b = B[j * n + il];
+    vr[j] = a;
+    bc[j] = b;
+    prod += a * b;
   }
+  double rr[1] = {prod};
+  block_sum<NT, 1>(rr, l.red());
+  const double rho = rr[0];
   __syncthreads();
-  double rho = l.sc()[SC_TMP1];
-  double part[2] = {0.0, 0.0};
-  for (int u = threadIdx.x; u < st.nU; u += NT) {
-    const int* ui = st.uinfo + 8 * u;
-    double m[9], yy[3], bb[3];
-    int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
-    for (int r = 0; r < e; ++r) {
-      yy[r] = y[ui[4 + r]];
-      bb[r] = bc[ui[1 + r]];
-    }
-    double q = rho * l.Ru(s)[u] + adj_e(e, m, yy, bb);
-    l.Qu()[u] = q;
-    part[0] += q * l.Wu(s)[u];
+  // phase 2: y[q] = v[P_q] - sum_k v[ref_k] T[k][q]; Jastrow change in parallel
+  for (int q = threadIdx.x; q < nP; q += NT) {
+    double a = v[porb[q]];
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) a -= vr[k] * T[k * nP + q];
+    y[q] = a;
   }
-  // Jastrow change
+  double part[2] = {0.0, 0.0};
   const double* R = l.R();
+  const double* nuc = l.nuc();
   double xo = R[3 * i], yo = R[3 * i + 1], zo = R[3 * i + 2];
   for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
     if (j == i) continue;
@@ -791,18 +942,36 @@ __device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, doubl
       b = anti ? wf.ee[2] : wf.ee[3];
       q = wf.ee + 4;
     } else {
-      int n = j - wf.N;
-      xj = wf.nuc[4 * n]; yj = wf.nuc[4 * n + 1]; zj = wf.nuc[4 * n + 2];
-      a = wf.en[6 * n]; b = wf.en[6 * n + 1]; q = wf.en + 6 * n + 2;
+      int nn = j - wf.N;
+      xj = nuc[4 * nn]; yj = nuc[4 * nn + 1]; zj = nuc[4 * nn + 2];
+      a = l.en()[6 * nn]; b = l.en()[6 * nn + 1]; q = l.en() + 6 * nn + 2;
     }
     double rn = sqrt((px - xj) * (px - xj) + (py - yj) * (py - yj) + (pz - zj) * (pz - zj));
     double ro = sqrt((xo - xj) * (xo - xj) + (yo - yj) * (yo - yj) + (zo - zj) * (zo - zj));
     part[1] += pair_val(rn, wf.kappa, a, b, q) - pair_val(ro, wf.kappa, a, b, q);
   }
+  __syncthreads();
+  // phase 3: Q_u = rho R_u + y^T adj(T_JQ) B_J,i and S'' = sum_u Q_u W_u
+  const int* uit = l.ui(s);
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    const int* ui = uit + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = y[ui[4 + r]];
+        bb[r] = bc[ui[1 + r]];
+      }
+    double q = rho * l.Ru(s)[u] + adj_e(e, m, yy, bb);
+    l.Qu()[u] = q;
+    part[0] += q * l.Wu(s)[u];
+  }
   block_sum<NT, 2>(part, l.red());
   if (threadIdx.x == 0) {
     l.sc()[SC_RATIO] = part[0] / l.sc()[SC_S];
     l.sc()[SC_TMP0] = part[1];
+    l.sc()[SC_TMP1] = rho;
   }
   __syncthreads();
 }
@@ -813,27 +982,41 @@ __device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, doub
   int s = spin_of(wf, i);
   const SpinTab& st = wf.sp[s];
   int il = i - st.e0;
-  const double* v = l.v();
   double* B = l.B(s);
   double* T = l.T(s);
   double rho = l.sc()[SC_TMP1];
   double* z = l.z();
+  const double* vr = l.z() + st.n;  // v[ref[k]], gathered by move_ratio
   for (int m = threadIdx.x; m < st.n; m += NT) {
     double a = 0.0;
-    for (int k = 0; k < st.n; ++k) a += v[st.ref[k]] * B[k * st.n + m];
+#pragma unroll 4
+    for (int k = 0; k < st.n; ++k) a += vr[k] * B[k * st.n + m];
     z[m] = (m == il ? a - 1.0 : a);
   }
   __syncthreads();
   double ir = 1.0 / rho;
   const double* bc = l.bcol();
   const double* y = l.y();
-  for (int idx = threadIdx.x; idx < st.n * st.n; idx += NT) {
-    int j = idx / st.n, m = idx - j * st.n;
-    B[idx] -= bc[j] * z[m] * ir;
-  }
-  for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
-    int j = idx / st.nP, q = idx - j * st.nP;
-    T[idx] += bc[j] * y[q] * ir;
+  if (st.n <= NT) {
+    // lane m owns column m of B; rows j in sequence (no integer division)
+    const int m = threadIdx.x;
+    if (m < st.n) {
+      double zm = z[m] * ir;
+      for (int j = 0; j < st.n; ++j) B[j * st.n + m] -= bc[j] * zm;
+    }
+    if (m < st.nP) {
+      double yq = y[m] * ir;
+      for (int j = 0; j < st.n; ++j) T[j * st.nP + m] += bc[j] * yq;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < st.n * st.n; idx += NT) {
+      int j = idx / st.n, m = idx - j * st.n;
+      B[idx] -= bc[j] * z[m] * ir;
+    }
+    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+      int j = idx / st.nP, q = idx - j * st.nP;
+      T[idx] += bc[j] * y[q] * ir;
+    }
   }
   if (threadIdx.x == 0) {
     double* sc = l.sc();
@@ -844,11 +1027,21 @@ __device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, doub
     R[3 * i] = px; R[3 * i + 1] = py; R[3 * i + 2] = pz;
   }
   __syncthreads();
-  update_R<NT>(wf, l, s);
+  // R_u of this spin, and S = sum_u R_u W_u (W of this spin does not depend
+  // on this spin's R), then the other spin's W
+  double vS[1] = {0.0};
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double m[9];
+    int e = gather_u(l.ui(s) + 8 * u, T, st.nP, m, nullptr, nullptr, 0.0);
+    double r = det_e(e, m);
+    l.Ru(s)[u] = r;
+    vS[0] += r * l.Wu(s)[u];
+  }
+  block_sum<NT, 1>(vS, l.red());
+  if (threadIdx.x == 0) l.sc()[SC_S] = vS[0];
   __syncthreads();
   update_W<NT>(wf, l, 1 - s);
   __syncthreads();
-  update_S<NT>(wf, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -883,13 +1076,14 @@ __device__ void store_record(const DevWF& wf, const Ld& l, double* rec) {
 extern __shared__ double lds_dyn[];
 
 template <int NT, int PREC>
-__global__ __launch_bounds__(NT) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
                                                  double* logabs, int32_t* sign, double* grad, double* eloc,
                                                  double* ratio, double* state) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   if (w >= W) return;
   Ld l(lds_dyn, wf);
+  stage_tables<NT, PREC>(wf, l);
   for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = Rin[w * 3 * wf.N + k];
   __syncthreads();
   bool ok = build_state<NT, PREC>(wf, l, l.R());
@@ -934,15 +1128,16 @@ template <int NT, int PREC>
 __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint64_t seed, uint32_t step,
                                   double step_size) {
   double* sc = l.sc();
-  // back up the current state
-  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.Rn()[k] = l.R()[k];
+  // back up the current state in the record's backup area
+  double* bk = l.bk;
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) bk[wf.r_R + k] = l.R()[k];
   for (int s = 0; s < 2; ++s) {
     const SpinTab& st = wf.sp[s];
-    for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.Bn(s)[k] = l.B(s)[k];
-    for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.Tn(s)[k] = l.T(s)[k];
+    for (int k = threadIdx.x; k < st.n * st.n; k += NT) bk[wf.r_B[s] + k] = l.B(s)[k];
+    for (int k = threadIdx.x; k < st.n * st.nP; k += NT) bk[wf.r_T[s] + k] = l.T(s)[k];
   }
   double old_log = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(sc[SC_S]));
-  double bk[4] = {sc[SC_LOGDET0], sc[SC_LOGDET1], sc[SC_SGN0], sc[SC_SGN1]};
+  double bks[4] = {sc[SC_LOGDET0], sc[SC_LOGDET1], sc[SC_SGN0], sc[SC_SGN1]};
   double bkS = sc[SC_S], bkU = sc[SC_U];
   __syncthreads();
   for (int e = threadIdx.x; e < wf.N; e += NT) {
@@ -968,15 +1163,16 @@ __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint6
   }
   __syncthreads();
   if (!accept) {
-    for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = l.Rn()[k];
+    __threadfence_block();
+    for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = bk[wf.r_R + k];
     for (int s = 0; s < 2; ++s) {
       const SpinTab& st = wf.sp[s];
-      for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.B(s)[k] = l.Bn(s)[k];
-      for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.T(s)[k] = l.Tn(s)[k];
+      for (int k = threadIdx.x; k < st.n * st.n; k += NT) l.B(s)[k] = bk[wf.r_B[s] + k];
+      for (int k = threadIdx.x; k < st.n * st.nP; k += NT) l.T(s)[k] = bk[wf.r_T[s] + k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      sc[SC_LOGDET0] = bk[0]; sc[SC_LOGDET1] = bk[1]; sc[SC_SGN0] = bk[2]; sc[SC_SGN1] = bk[3];
+      sc[SC_LOGDET0] = bks[0]; sc[SC_LOGDET1] = bks[1]; sc[SC_SGN0] = bks[2]; sc[SC_SGN1] = bks[3];
       sc[SC_S] = bkS; sc[SC_U] = bkU;
     }
     __syncthreads();
@@ -986,14 +1182,16 @@ __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint6
 }
 
 template <int NT, int PREC>
-__global__ __launch_bounds__(NT) void k_vmc(const DevWF* __restrict__ pwf, double* state, int64_t W, int nsteps, uint64_t seed,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_vmc(const DevWF* __restrict__ pwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                             uint64_t step0, double step_size, int all_electron, double* e_sum,
                                             double* e2_sum, double* n_acc, double* e_last, double* sij_sum) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   if (w >= W) return;
   Ld l(lds_dyn, wf);
+  stage_tables<NT, PREC>(wf, l);
   double* rec = state + w * wf.rec_len;
+  l.bk = rec + wf.r_bk;
   load_record<NT>(wf, l, rec);
   compute_RWS<NT>(wf, l);
   double* sc = l.sc();
@@ -1076,6 +1274,10 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
   const double* B = l.B(s);
   const double* T = l.T(s);
   const double* y0 = l.y();
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  const int* uit = l.ui(s);
+  const double* nuc = l.nuc();
   double* yb = l.yb();  // [3][nP + 1]: y'^c and rho'^c
   int ld = st.nP + 1;
   // y^c[q] = w_c[P_q] - sum_l w_c[ref_l] T'[l][q],  T' = T + bc y0^T irho
@@ -1083,16 +1285,16 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
     int c = idx / ld, q = idx - c * ld;
     const double* w = rows + c * rstride;
     if (q < st.nP) {
-      double a = w[st.porb[q]], corr = 0.0;
+      double a = w[porb[q]], corr = 0.0;
       for (int k = 0; k < st.n; ++k) {
-        a -= w[st.ref[k]] * T[k * st.nP + q];
-        if (bc) corr += w[st.ref[k]] * bc[k];
+        a -= w[ref[k]] * T[k * st.nP + q];
+        if (bc) corr += w[ref[k]] * bc[k];
       }
       if (bc) a -= corr * y0[q] * irho;
       yb[c * ld + q] = a;
     } else {
       double a = 0.0;
-      for (int j = 0; j < st.n; ++j) a += w[st.ref[j]] * (bc ? bc[j] * irho : B[j * st.n + il]);
+      for (int j = 0; j < st.n; ++j) a += w[ref[j]] * (bc ? bc[j] * irho : B[j * st.n + il]);
       yb[c * ld + q] = a;  // rho'^c
     }
   }
@@ -1100,13 +1302,15 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
   double part[6] = {0, 0, 0, 0, 0, 0};
   for (int idx = threadIdx.x; idx < 3 * st.nU; idx += NT) {
     int c = idx / st.nU, u = idx - c * st.nU;
-    const int* ui = st.uinfo + 8 * u;
+    const int* ui = uit + 8 * u;
     double m[9], yy[3], bb[3];
     int e = gather_u(ui, T, st.nP, m, bc, y0, irho);
-    for (int r = 0; r < e; ++r) {
-      yy[r] = yb[c * ld + ui[4 + r]];
-      bb[r] = bc ? bc[ui[1 + r]] * irho : B[ui[1 + r] * st.n + il];
-    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = yb[c * ld + ui[4 + r]];
+        bb[r] = bc ? bc[ui[1 + r]] * irho : B[ui[1 + r] * st.n + il];
+      }
     double Rn = bc ? Qnew[u] * irho : l.Ru(s)[u];
     double t = (yb[c * ld + st.nP] * Rn + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
     if (c == 0) part[0] += t; else if (c == 1) part[1] += t; else part[2] += t;
@@ -1125,8 +1329,8 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
       q = wf.ee + 4;
     } else {
       int n = j - wf.N;
-      xj = wf.nuc[4 * n]; yj = wf.nuc[4 * n + 1]; zj = wf.nuc[4 * n + 2];
-      a = wf.en[6 * n]; b = wf.en[6 * n + 1]; q = wf.en + 6 * n + 2;
+      xj = nuc[4 * n]; yj = nuc[4 * n + 1]; zj = nuc[4 * n + 2];
+      a = l.en()[6 * n]; b = l.en()[6 * n + 1]; q = l.en() + 6 * n + 2;
     }
     double dx = px - xj, dy = py - yj, dz = pz - zj;
     double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
@@ -1141,7 +1345,7 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
 }
 
 template <int NT, int PREC>
-__global__ __launch_bounds__(NT) void k_dmc_step(const DevWF* __restrict__ pwf, double* state, const double* ctrl, int nsteps_done,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_dmc_step(const DevWF* __restrict__ pwf, double* state, const double* ctrl, int nsteps_done,
                                                  uint64_t seed, uint32_t step, double tau, double* wts,
                                                  double* wel, int* ncopy, double* nacc) {
   const DevWF& wf = *pwf;
@@ -1149,6 +1353,7 @@ __global__ __launch_bounds__(NT) void k_dmc_step(const DevWF* __restrict__ pwf, 
   int64_t W = (int64_t)ctrl[DC_W];
   if (ctrl[DC_ERR] != 0.0 || w >= W) return;
   Ld l(lds_dyn, wf);
+  stage_tables<NT, PREC>(wf, l);
   double* rec = state + w * wf.rec_len;
   double* gc = rec + wf.r_gc;
   load_record<NT>(wf, l, rec);
