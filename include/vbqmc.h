@@ -236,10 +236,12 @@ int vbqmc_param_grad_workspace_bytes(const vbqmc_ctx* ctx, int64_t W, size_t* by
 int vbqmc_param_grad(vbqmc_ctx* ctx, int64_t W, const double* R, double* dlogpsi, double* deloc,
                      void* workspace, size_t workspace_bytes, vbqmc_stream stream);
 
-/* Deterministic fixed-order sum over walkers: out[k] = sum_w in[w][k],
- * in [dev][W][K], out [dev][K]. */
-int vbqmc_reduce_walkers(vbqmc_ctx* ctx, int64_t W, int32_t K, const double* in, double* out,
-                         vbqmc_stream stream);
+/* Deterministic fixed-order weighted sum over walkers (the sample averages
+ * of Sec. 2.3.1 and the contraction of per-walker derivatives with an
+ * upstream gradient): out[k] = sum_w weights[w] in[w][k]; weights [dev][W]
+ * or NULL for unit weights, in [dev][W][K], out [dev][K]. */
+int vbqmc_reduce_walkers(vbqmc_ctx* ctx, int64_t W, int32_t K, const double* weights, const double* in,
+                         double* out, vbqmc_stream stream);
 
 /* Structure weights from the overlap estimate S [host][n][n] (Sec. 2.4):
  * Chirgwin-Coulson w_I = c_I (S c)_I / c.S.c and Loewdin

@@ -109,7 +109,7 @@ def load_library(path=LIB_PATH):
                                       ctypes.POINTER(dbl), i64, ctypes.POINTER(_DmcLog), vp, ctypes.c_size_t, vp]
     lib.vbqmc_param_grad_workspace_bytes.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.vbqmc_param_grad.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
-    lib.vbqmc_reduce_walkers.argtypes = [vp, i64, i32, vp, vp, vp]
+    lib.vbqmc_reduce_walkers.argtypes = [vp, i64, i32, vp, vp, vp, vp]
     lib.vbqmc_weights_chirgwin_coulson.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                                    ctypes.POINTER(dbl)]
     lib.vbqmc_weights_lowdin.argtypes = lib.vbqmc_weights_chirgwin_coulson.argtypes
@@ -316,12 +316,16 @@ class Context:
                                             nb.value, _stream()))
         return dl, de
 
-    def reduce_walkers(self, x):
+    def reduce_walkers(self, x, weights=None):
+        """Fixed-order sum over the walker axis (optionally weighted)."""
         import torch
         x2 = x.reshape(x.shape[0], -1)
         _check_cuda(x2, "x", torch.float64)
+        if weights is not None:
+            _check_cuda(weights, "weights", torch.float64, (x2.shape[0],))
         out = torch.empty(x2.shape[1], dtype=torch.float64, device=x.device)
-        self._rc(self._lib.vbqmc_reduce_walkers(self._h, x2.shape[0], x2.shape[1], _ptr(x2), _ptr(out), _stream()))
+        self._rc(self._lib.vbqmc_reduce_walkers(self._h, x2.shape[0], x2.shape[1], _ptr(weights), _ptr(x2),
+                                                _ptr(out), _stream()))
         return out.reshape(x.shape[1:])
 
     def get_params(self):
@@ -356,3 +360,46 @@ def weights_lowdin(S, c):
     if rc != 0:
         raise VBQMCError(rc, "weights_lowdin")
     return w
+
+
+def _jvb_function():
+    import torch
+
+    class JVBFunction(torch.autograd.Function):
+        """(ln|Psi|, E_L) of fixed configurations as a differentiable function
+        of the parameter vector p = [c | lambda | Jastrow].
+
+        forward: sets p on the context and runs vbqmc_evaluate.
+        backward: runs the hand-written adjoint (vbqmc_param_grad, which
+        recomputes every determinant inverse from R) and contracts the
+        per-walker derivatives with the upstream gradients by the library's
+        fixed-order walker reduction."""
+
+        @staticmethod
+        def forward(ctx_, p, R, vbctx):
+            vbctx.set_params(p.detach().double().cpu().numpy())
+            out = vbctx.evaluate(R, want=("eloc",))
+            ctx_.save_for_backward(R)
+            ctx_.vb = vbctx
+            ctx_.p_device = p.device
+            return out["logabs"], out["eloc"]
+
+        @staticmethod
+        def backward(ctx_, g_logpsi, g_eloc):
+            (R,) = ctx_.saved_tensors
+            vb = ctx_.vb
+            dl, de = vb.param_grad(R)
+            gp = None
+            if g_logpsi is not None:
+                gp = vb.reduce_walkers(dl, g_logpsi.double().contiguous())
+            if g_eloc is not None:
+                ge = vb.reduce_walkers(de, g_eloc.double().contiguous())
+                gp = ge if gp is None else gp + ge
+            return gp.to(ctx_.p_device), None, None
+
+    return JVBFunction
+
+
+def jvb_apply(p, R, vbctx):
+    """Differentiable (ln|Psi|, E_L) for parameters p and configurations R."""
+    return _jvb_function().apply(p, R, vbctx)

@@ -1,7 +1,397 @@
-// Parameter-derivative (adjoint) kernels of the JVB library.
-#include "vbqmc_internal.h"
+// Parameter derivatives of ln|Psi| and E_L (the adjoint form) for gfx950.
+//
+// For fixed configurations this computes, per walker, d ln|Psi| / dp and
+// d E_L / dp for p = [c (structure coefficients) | lambda (orbital
+// coefficients) | Jastrow pair parameters]: the per-sample quantities that
+// the linear optimisation method consumes (Radenkovic, Domin, Toulouse,
+// Braida 2022, Sec. 2.2, Eq. (PsiJVBp) and the gradient estimators of
+// Eqs. (Hi0), (H0j) with E_{L,j} = d E_L / d p_j).
+//
+// Reverse-mode derivation (no stored per-electron intermediates; every spin
+// determinant inverse is recomputed in each of the two passes):
+//   E_L = -1/2 sum_i [lap_i U + |grad_i U|^2] + V + sum_k W_k e_k,
+//   W_k = w_k Delta_k / D,  e_k = sum_spins tr(A_u^{-1} K_u),
+// with A_u[i][j] = phi_{o_j}(r_i) the spin-determinant matrix in the slot
+// order of its table entry and K_u[i][j] = -grad_i U . grad phi_{o_j}(r_i)
+// - 1/2 lap phi_{o_j}(r_i) the "kinetic row" matrix.  With
+// omega_u = sum_{k holding u} W_k and lbar_u = sum_{k holding u} W_k (e_k - ebar):
+//   dE_L/dA_u = lbar_u A_u^{-T} - omega_u (A_u^{-1} K_u A_u^{-1})^T,
+//   dE_L/dK_u = omega_u A_u^{-T},   d ln|D| / dA_u = omega_u A_u^{-T}.
+// Scattering these onto orbital rows gives Gamma0[i][p] (value rows) and
+// G[i][p] (gradient/Laplacian rows enter through K), and then
+//   d E_L / d lambda[p][mu] = sum_i Gamma0[i][p] chi_mu(r_i) + G[i][p] kappa_mu(r_i),
+//   d ln|Psi| / d lambda[p][mu] = sum_i G[i][p] chi_mu(r_i),
+// kappa_mu = -grad U . grad chi_mu - 1/2 lap chi_mu: two contractions over
+// electrons done on MFMA.  Structure coefficients and Jastrow parameters use
+// their closed forms (Euler form in c; pair-function derivatives).
+
+#include "vbqmc_device.h"
 
 namespace vbqmc {
+
+extern __shared__ double lds_adj[];
+
+// all five basis channels of function mu at electron e of the current tile
+template <typename T>
+__device__ __forceinline__ void chan_all(const DevWF& wf, const Ld& l, int e, int mu, T* out) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) out[c] = chan_value<T>(wf, l, e, mu, c);
+}
+
+// derivatives (du, du', du'') of a pair function with respect to one of its
+// parameters: kind 0 numerator a, 1 denominator b, 2..5 coefficient of R^kind
+__device__ __forceinline__ void pair_param(double r, double kappa, double a, double b, int kind, double& du,
+                                           double& du1, double& du2) {
+  double den = 1.0 + kappa * r, iden = 1.0 / den;
+  double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
+  double f, fR, fRR;
+  if (kind == 0) {
+    double ib = 1.0 / (1.0 + b * R);
+    f = R * ib; fR = ib * ib; fRR = -2.0 * b * ib * ib * ib;
+  } else if (kind == 1) {
+    double ib = 1.0 / (1.0 + b * R);
+    double ib3 = ib * ib * ib;
+    f = -a * R * R * ib * ib; fR = -2.0 * a * R * ib3; fRR = -2.0 * a * ib3 + 6.0 * a * b * R * ib3 * ib;
+  } else {
+    int p = kind;
+    double Rp2 = 1.0;
+    for (int k = 0; k < p - 2; ++k) Rp2 *= R;
+    f = Rp2 * R * R; fR = p * Rp2 * R; fRR = p * (p - 1) * Rp2;
+  }
+  du = f;
+  du1 = fR * R1;
+  du2 = fRR * R1 * R1 + fR * R2;
+}
+
+// orbital of slot j of unique determinant u (slots in reference order with the
+// replaced slots J taking the table orbitals Q)
+__device__ __forceinline__ int slot_orbital(const Ld& l, int s, const int* ui, int j) {
+  int e = ui[0];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    if (r < e && ui[1 + r] == j) return l.porb(s)[ui[4 + r]];
+  return l.ref(s)[j];
+}
+
+template <int NT, int PREC>
+__global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf, int64_t W,
+                                                   const double* __restrict__ Rin, double* dlog, double* del) {
+  const DevWF& wf = *pwf;
+  const int64_t w = blockIdx.x;
+  if (w >= W) return;
+  Ld l(lds_adj, wf);
+  stage_tables<NT, PREC>(wf, l);
+  const int N = wf.N, nop = wf.nop, M = wf.M;
+  const int np = wf.nstruct + wf.norb * M + 6 + 6 * wf.nnuc;
+  double* oL = dlog + w * np;
+  double* oE = del + w * np;
+  for (int k = threadIdx.x; k < 3 * N; k += NT) l.R()[k] = Rin[w * 3 * N + k];
+  __syncthreads();
+  double* aPhi = l.L + wf.l_aPhi;  // [5][N][nop]
+  double* G0 = l.L + wf.l_aG0;     // [N][nop]
+  double* G = l.L + wf.l_aG;       // [N][nop]
+  double* A = l.L + wf.l_aA;
+  double* K = l.L + wf.l_aP;
+  double* M1 = l.L + wf.l_aM;
+  double* sc = l.sc();
+
+  // A. orbital rows and their derivatives at every electron
+  for (int g0 = 0; g0 < N; g0 += kGroup) {
+    int ne = min(kGroup, N - g0);
+    group_radial<NT, PREC>(wf, l, l.R(), g0, ne);
+    for (int c = 0; c < 5; ++c) {
+      group_channel<NT, PREC>(wf, l, ne, c);
+      for (int idx = threadIdx.x; idx < ne * nop; idx += NT) aPhi[(c * N + g0) * nop + idx] = l.Phi()[idx];
+      __syncthreads();
+    }
+  }
+  for (int idx = threadIdx.x; idx < N * nop; idx += NT) {
+    G0[idx] = 0.0;
+    G[idx] = 0.0;
+  }
+  // B. Jastrow factor, its gradients and Laplacians, potential
+  jastrow_full<NT>(wf, l, l.R());
+
+  // C. first pass over the spin determinants: ln|Delta_u|, sign, e_u
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    const int n = st.n;
+    double* uinf = l.L + wf.l_aU[s];  // [nU][5]: L, sign, e, omega, lbar
+    for (int u = 0; u < st.nU; ++u) {
+      const int* ui = l.ui(s) + 8 * u;
+      for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+        int i = idx / n, j = idx - i * n;
+        int o = slot_orbital(l, s, ui, j), e = st.e0 + i;
+        A[idx] = aPhi[(0 * N + e) * nop + o];
+        const double* gu = l.gU() + 3 * e;
+        K[idx] = -(gu[0] * aPhi[(1 * N + e) * nop + o] + gu[1] * aPhi[(2 * N + e) * nop + o] +
+                   gu[2] * aPhi[(3 * N + e) * nop + o]) - 0.5 * aPhi[(4 * N + e) * nop + o];
+      }
+      __syncthreads();
+      double ld = 0.0, sg = 1.0;
+      bool ok = n == 0 || gj_invert<NT>(l, A, n, ld, sg);
+      // e_u = tr(A^{-1} K) = sum_{i,j} K[i][j] Ainv[j][i]
+      double tr[1] = {0.0};
+      if (ok)
+        for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+          int i = idx / n, j = idx - i * n;
+          tr[0] += K[idx] * A[j * n + i];
+        }
+      block_sum<NT, 1>(tr, l.red());
+      if (threadIdx.x == 0) {
+        uinf[5 * u + 0] = ok ? ld : -INFINITY;
+        uinf[5 * u + 1] = ok ? sg : 0.0;
+        uinf[5 * u + 2] = ok ? tr[0] : 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  // D. combine over determinant pairs (spin-up CSR lists every pair once)
+  {
+    const double* U0 = l.L + wf.l_aU[0];
+    const double* U1 = l.L + wf.l_aU[1];
+    double lmax = -INFINITY;
+    for (int u = 0; u < wf.sp[0].nU; ++u)
+      for (int k = l.wrow(0)[u]; k < l.wrow(0)[u + 1]; ++k) {
+        int ub = l.woth(0)[k];
+        if (l.wcoef(0)[k] != 0.0) lmax = fmax(lmax, U0[5 * u] + U1[5 * ub]);
+      }
+    double acc[2] = {0.0, 0.0};  // D~, sum t_k e_k
+    for (int u = threadIdx.x; u < wf.sp[0].nU; u += NT)
+      for (int k = l.wrow(0)[u]; k < l.wrow(0)[u + 1]; ++k) {
+        int ub = l.woth(0)[k];
+        double t = l.wcoef(0)[k] * U0[5 * u + 1] * U1[5 * ub + 1] * exp(U0[5 * u] + U1[5 * ub] - lmax);
+        acc[0] += t;
+        acc[1] += t * (U0[5 * u + 2] + U1[5 * ub + 2]);
+      }
+    block_sum<NT, 2>(acc, l.red());
+    if (threadIdx.x == 0) {
+      sc[SC_TMP0] = lmax;
+      sc[SC_S] = acc[0];
+      sc[SC_TMP1] = acc[1] / acc[0];  // ebar
+    }
+    __syncthreads();
+  }
+  const double lmax = sc[SC_TMP0], Dt = sc[SC_S], ebar = sc[SC_TMP1];
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    double* us = l.L + wf.l_aU[s];
+    const double* uo = l.L + wf.l_aU[1 - s];
+    for (int u = threadIdx.x; u < st.nU; u += NT) {
+      double om = 0.0, lb = 0.0;
+      for (int k = l.wrow(s)[u]; k < l.wrow(s)[u + 1]; ++k) {
+        int ub = l.woth(s)[k];
+        double Wk = l.wcoef(s)[k] * us[5 * u + 1] * uo[5 * ub + 1] * exp(us[5 * u] + uo[5 * ub] - lmax) / Dt;
+        om += Wk;
+        lb += Wk * (us[5 * u + 2] + uo[5 * ub + 2] - ebar);
+      }
+      us[5 * u + 3] = om;
+      us[5 * u + 4] = lb;
+    }
+  }
+  for (int k = threadIdx.x; k < 4 * N; k += NT) {
+    if (k < 3 * N) l.gD()[k] = 0.0; else l.lD()[k - 3 * N] = 0.0;
+  }
+  __syncthreads();
+
+  // E. second pass: recompute each inverse, accumulate the drift and
+  // Laplacian ratios and scatter the adjoint onto orbital rows
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    const int n = st.n;
+    const double* uinf = l.L + wf.l_aU[s];
+    for (int u = 0; u < st.nU; ++u) {
+      const double om = uinf[5 * u + 3], lb = uinf[5 * u + 4];
+      if (uinf[5 * u + 1] == 0.0 || n == 0) continue;  // singular: no contribution
+      const int* ui = l.ui(s) + 8 * u;
+      for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+        int i = idx / n, j = idx - i * n;
+        int o = slot_orbital(l, s, ui, j), e = st.e0 + i;
+        A[idx] = aPhi[(0 * N + e) * nop + o];
+        const double* gu = l.gU() + 3 * e;
+        K[idx] = -(gu[0] * aPhi[(1 * N + e) * nop + o] + gu[1] * aPhi[(2 * N + e) * nop + o] +
+                   gu[2] * aPhi[(3 * N + e) * nop + o]) - 0.5 * aPhi[(4 * N + e) * nop + o];
+      }
+      __syncthreads();
+      double ld, sg;
+      gj_invert<NT>(l, A, n, ld, sg);
+      // drift and Laplacian ratios of this determinant, weighted by omega
+      for (int idx = threadIdx.x; idx < 4 * n; idx += NT) {
+        int i = idx >> 2, c = 1 + (idx & 3), e = st.e0 + i;
+        double g = 0.0;
+        for (int j = 0; j < n; ++j) g += aPhi[(c * N + e) * nop + slot_orbital(l, s, ui, j)] * A[j * n + i];
+        if (c < 4) l.gD()[3 * e + c - 1] += om * g; else l.lD()[e] += om * g;
+      }
+      // M1 = K A^{-1}
+      for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+        int i = idx / n, a = idx - i * n;
+        double t = 0.0;
+        for (int j = 0; j < n; ++j) t += K[i * n + j] * A[j * n + a];
+        M1[idx] = t;
+      }
+      __syncthreads();
+      // Abar[a][b] = lbar Ainv[b][a] - omega sum_i Ainv[b][i] M1[i][a]; scatter
+      for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+        int a = idx / n, b = idx - a * n;
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += A[b * n + i] * M1[i * n + a];
+        int o = slot_orbital(l, s, ui, b), e = st.e0 + a;
+        G0[e * nop + o] += lb * A[b * n + a] - om * t;
+        G[e * nop + o] += om * A[b * n + a];
+      }
+      __syncthreads();
+    }
+  }
+
+  // F. local energy (as a by-product), structure and Jastrow derivatives
+  {
+    double part[1] = {0.0};
+    for (int i = threadIdx.x; i < N; i += NT) {
+      double t = l.lU()[i] + l.lD()[i];
+      for (int x = 0; x < 3; ++x) {
+        double gu = l.gU()[3 * i + x];
+        t += gu * gu + 2.0 * gu * l.gD()[3 * i + x];
+      }
+      part[0] += -0.5 * t;
+    }
+    block_sum<NT, 1>(part, l.red());
+    if (threadIdx.x == 0) sc[SC_ELOC] = part[0] + sc[SC_V];
+  }
+  {
+    const double* U0 = l.L + wf.l_aU[0];
+    const double* U1 = l.L + wf.l_aU[1];
+    for (int I = threadIdx.x; I < wf.nstruct; I += NT) {
+      double r = 0.0, re = 0.0;
+      for (int k = l.srow()[I]; k < l.srow()[I + 1]; ++k) {
+        int u0 = l.slu()[2 * k], u1 = l.slu()[2 * k + 1];
+        double t = l.slc()[k] * U0[5 * u0 + 1] * U1[5 * u1 + 1] * exp(U0[5 * u0] + U1[5 * u1] - lmax) / Dt;
+        r += t;
+        re += t * (U0[5 * u0 + 2] + U1[5 * u1 + 2]);
+      }
+      oL[I] = r;
+      oE[I] = re - r * ebar;
+    }
+  }
+  // Jastrow: electron-electron parameters [b_anti, b_par, b3..b6]
+  const int jb = wf.nstruct + wf.norb * M;
+  {
+    double acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    const double* R = l.R();
+    for (int i = threadIdx.x; i < N; i += NT) {
+      for (int j = i + 1; j < N; ++j) {
+        double dx = R[3 * i] - R[3 * j], dy = R[3 * i + 1] - R[3 * j + 1], dz = R[3 * i + 2] - R[3 * j + 2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        bool anti = spin_of(wf, i) != spin_of(wf, j);
+        double a = anti ? wf.ee[0] : wf.ee[1], b = anti ? wf.ee[2] : wf.ee[3];
+        double proj = 0.0;
+        {
+          const double* gi = l.gU() + 3 * i;
+          const double* gj = l.gU() + 3 * j;
+          const double* di = l.gD() + 3 * i;
+          const double* dj = l.gD() + 3 * j;
+          proj = (dx * (gi[0] + di[0] - gj[0] - dj[0]) + dy * (gi[1] + di[1] - gj[1] - dj[1]) +
+                  dz * (gi[2] + di[2] - gj[2] - dj[2])) / r;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          if (q == 0 && !anti) continue;
+          if (q == 1 && anti) continue;
+          double du, du1, du2;
+          pair_param(r, wf.kappa, a, b, q < 2 ? 1 : q, du, du1, du2);
+          acc[q] += du;
+          acc[6 + q] += -0.5 * (2.0 * (du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
+        }
+      }
+    }
+    block_sum<NT, 12>(acc, l.red());
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 6; ++q) {
+        oL[jb + q] = acc[q];
+        oE[jb + q] = acc[6 + q];
+      }
+  }
+  // electron-nucleus parameters [a1..a6] per nucleus
+  for (int al = 0; al < wf.nnuc; ++al) {
+    double acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    const double* ja = l.en() + 6 * al;
+    const double* nu = l.nuc() + 4 * al;
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const double* R = l.R() + 3 * i;
+      double dx = R[0] - nu[0], dy = R[1] - nu[1], dz = R[2] - nu[2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double* gi = l.gU() + 3 * i;
+      const double* di = l.gD() + 3 * i;
+      double proj = (dx * (gi[0] + di[0]) + dy * (gi[1] + di[1]) + dz * (gi[2] + di[2])) / r;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        double du, du1, du2;
+        pair_param(r, wf.kappa, ja[0], ja[1], q, du, du1, du2);
+        acc[q] += du;
+        acc[6 + q] += -0.5 * ((du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
+      }
+    }
+    block_sum<NT, 12>(acc, l.red());
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 6; ++q) {
+        oL[jb + 6 + 6 * al + q] = acc[q];
+        oE[jb + 6 + 6 * al + q] = acc[6 + q];
+      }
+    __syncthreads();
+  }
+
+  // G. orbital-coefficient derivatives: contractions over electrons on MFMA,
+  // one 16 (orbital) x 16 (basis function) output tile per wave at a time
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const int npt = nop / 16, nmt = wf.Mpad / 16;
+  double* oLl = oL + wf.nstruct;
+  double* oEl = oE + wf.nstruct;
+  for (int g0 = 0; g0 < N; g0 += kGroup) {
+    int ne = min(kGroup, N - g0);
+    group_radial<NT, 0>(wf, l, l.R(), g0, ne);  // FP64 basis rows for the contraction
+    for (int tile = wave; tile < npt * nmt; tile += NW) {
+      int pt = tile / nmt, mt = tile - pt * nmt;
+      int pcol = pt * 16 + (lane & 15), mcol = mt * 16 + (lane & 15);
+      v4d accE = {0, 0, 0, 0}, accL = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < kGroup; k0 += 4) {
+        int e = k0 + (lane >> 4);
+        double a0 = 0.0, aG = 0.0, bv = 0.0, bk = 0.0;
+        if (e < ne) {
+          a0 = G0[(g0 + e) * nop + pcol];
+          aG = G[(g0 + e) * nop + pcol];
+          double ch[5];
+          chan_all<double>(wf, l, e, mcol, ch);
+          const double* gu = l.gU() + 3 * (g0 + e);
+          bv = ch[0];
+          bk = -(gu[0] * ch[1] + gu[1] * ch[2] + gu[2] * ch[3]) - 0.5 * ch[4];
+        }
+        accE = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, accE, 0, 0, 0);
+        accE = __builtin_amdgcn_mfma_f64_16x16x4f64(aG, bk, accE, 0, 0, 0);
+        accL = __builtin_amdgcn_mfma_f64_16x16x4f64(aG, bv, accL, 0, 0, 0);
+      }
+      // f64 output layout: register r of lane l holds row 4r + l/16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int p = pt * 16 + 4 * r + (lane >> 4), mu = mt * 16 + (lane & 15);
+        if (p < wf.norb && mu < M) {
+          size_t o = (size_t)p * M + mu;
+          if (g0 == 0) {
+            oEl[o] = accE[r];
+            oLl[o] = accL[r];
+          } else {
+            oEl[o] += accE[r];
+            oLl[o] += accL[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 
 size_t param_grad_ws_doubles(const DevWF& wf, int64_t W) {
   (void)wf;
@@ -9,10 +399,33 @@ size_t param_grad_ws_doubles(const DevWF& wf, int64_t W) {
   return 0;
 }
 
-hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi, double* deloc,
-                             double* ws, size_t ws_doubles, hipStream_t s) {
-  (void)wf; (void)dwf; (void)nt; (void)W; (void)R; (void)dlogpsi; (void)deloc; (void)ws; (void)ws_doubles; (void)s;
-  return hipErrorNotSupported;
+template <int NT, int PREC>
+static hipError_t launch_pg(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, double* dl, double* de,
+                            hipStream_t s) {
+  size_t lds = (size_t)wf.lds_adj_doubles * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_param_grad<NT, PREC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_param_grad<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, dl, de);
+  return hipGetLastError();
+}
+
+hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi,
+                             double* deloc, double* ws, size_t ws_doubles, hipStream_t s) {
+  (void)ws;
+  (void)ws_doubles;
+  // the adjoint runs its determinant algebra and contractions in FP64 for
+  // every precision form; the orbital rows follow the context's precision
+  if (nt == 64) {
+    if (wf.precision == 0) return launch_pg<64, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
+    return launch_pg<64, 1>(wf, dwf, W, R, dlogpsi, deloc, s);
+  }
+  if (nt == 128) {
+    if (wf.precision == 0) return launch_pg<128, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
+    return launch_pg<128, 1>(wf, dwf, W, R, dlogpsi, deloc, s);
+  }
+  if (wf.precision == 0) return launch_pg<256, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
+  return launch_pg<256, 1>(wf, dwf, W, R, dlogpsi, deloc, s);
 }
 
 }  // namespace vbqmc

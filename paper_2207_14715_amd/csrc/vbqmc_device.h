@@ -1,0 +1,1019 @@
+// Device building blocks shared by the walker kernels and the adjoint kernel
+// of the JVB library (gfx950).  See vbqmc_kernels.hip for the design notes.
+#pragma once
+#include <type_traits>
+
+#include "vbqmc_internal.h"
+
+namespace vbqmc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the counter layout of the walks:
+// key = seed, counter = (walker slot, step, 4 * electron + purpose, draw).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                            uint32_t c3, double& u0, double& u1) {
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  const double s = 1.0 / 9007199254740992.0;
+  u0 = (double)((((uint64_t)x1 << 32) | x0) >> 11) * s;
+  u1 = (double)((((uint64_t)x3 << 32) | x2) >> 11) * s;
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed order: identical results in every lane)
+// ---------------------------------------------------------------------------
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  if constexpr (NT > 64) {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[(threadIdx.x >> 6) * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w * K + k];
+      v[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Jastrow pair function u(r) = a R/(1 + b R) + sum_{p=2..5} q_p R^p with
+// R = r/(1 + kappa r); returns u, u' and u'' in r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_fn(double r, double kappa, double a, double b, const double* q,
+                                        double& u, double& u1, double& u2) {
+  double den = 1.0 + kappa * r;
+  double iden = 1.0 / den;
+  double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
+  double ib = 1.0 / (1.0 + b * R);
+  u = a * R * ib;
+  double uR = a * ib * ib;
+  double uRR = -2.0 * a * b * ib * ib * ib;
+  double Rp2 = 1.0;  // R^(p-2)
+#pragma unroll
+  for (int p = 2; p <= 5; ++p) {
+    double c = q[p - 2];
+    uRR += p * (p - 1) * c * Rp2;
+    uR += p * c * Rp2 * R;
+    u += c * Rp2 * R * R;
+    Rp2 *= R;
+  }
+  u1 = uR * R1;
+  u2 = uRR * R1 * R1 + uR * R2;
+}
+
+__device__ __forceinline__ double pair_val(double r, double kappa, double a, double b, const double* q) {
+  double R = r / (1.0 + kappa * r);
+  double u = a * R / (1.0 + b * R);
+  double Rp = R * R;
+#pragma unroll
+  for (int p = 2; p <= 5; ++p) {
+    u += q[p - 2] * Rp;
+    Rp *= R;
+  }
+  return u;
+}
+
+// ---------------------------------------------------------------------------
+// basis functions: radial sums and the angular set
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T dexp(T x);
+template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+
+// Radial sums of a shell: Gaussian (kind 0) g = sum c e^{-a r^2} with
+// g1 = dg/d(r^2), g2 = d2g/d(r^2)^2; Slater (kind 1) g = sum c e^{-a r} with
+// g1 = dg/dr, g2 = d2g/dr2.  Primitives whose exponent argument exceeds 50 are
+// below 2e-22 of their coefficient and are skipped.
+
+// channels of one basis function: 0 value, 1..3 gradient, 4 Laplacian
+template <typename T>
+__device__ __forceinline__ void channels(int kind, int l, int m, T x, T y, T z, T r2, T r, T g, T g1,
+                                         T g2, int nch, T* out) {
+  T P, Px = T(0), Py = T(0), Pz = T(0);
+  if (l == 0) {
+    P = T(1);
+  } else if (l == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? T(1) : T(0);
+    Py = m == 1 ? T(1) : T(0);
+    Pz = m == 2 ? T(1) : T(0);
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = T(2) * x; Py = T(-2) * y; break;
+      default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
+    }
+  }
+  out[0] = P * g;
+  if (nch == 1) return;
+  // grad g = fr * d
+  T fr = kind == 0 ? T(2) * g1 : g1 / r;
+  out[1] = Px * g + P * fr * x;
+  out[2] = Py * g + P * fr * y;
+  out[3] = Pz * g + P * fr * z;
+  if (nch < 5) return;
+  // lap chi = P lap g + 2 grad P . grad g  (lap P = 0, d . grad P = l P)
+  if (kind == 0)
+    out[4] = P * (T(2 * (2 * l + 3)) * g1 + T(4) * r2 * g2);
+  else
+    out[4] = P * (g2 + T(2 * (l + 1)) * g1 / r);
+}
+
+// ---------------------------------------------------------------------------
+// small e x e determinant algebra (e <= 3), matrices row-major with stride 3
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double det_e(int e, const double* m) {
+  if (e == 0) return 1.0;
+  if (e == 1) return m[0];
+  if (e == 2) return m[0] * m[4] - m[1] * m[3];
+  return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+         m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// y^T adj(m) b
+__device__ __forceinline__ double adj_e(int e, const double* m, const double* y, const double* b) {
+  if (e == 0) return 0.0;
+  if (e == 1) return y[0] * b[0];
+  if (e == 2) return y[0] * (m[4] * b[0] - m[1] * b[1]) + y[1] * (-m[3] * b[0] + m[0] * b[1]);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    int r1 = r == 0 ? 1 : 0, r2 = r == 2 ? 1 : 2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int c1 = c == 0 ? 1 : 0, c2 = c == 2 ? 1 : 2;
+      double cof = m[r1 * 3 + c1] * m[r2 * 3 + c2] - m[r1 * 3 + c2] * m[r2 * 3 + c1];
+      if ((r + c) & 1) cof = -cof;
+      s += y[c] * cof * b[r];  // adj[c][r] = cofactor[r][c]
+    }
+  }
+  return s;
+}
+
+// gather T[J, Q] (+ optional rank-1 term bJ yQ / rho) of determinant u into m
+// (stride 3).  Loops run to 3 with guards so that m stays in registers.
+__device__ __forceinline__ int gather_u(const int* ui, const double* T, int nP, double* m,
+                                        const double* bc, const double* y, double irho) {
+  int e = ui[0];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (r < e && c < e) {
+        double v = T[ui[1 + r] * nP + ui[4 + c]];
+        if (bc) v += bc[ui[1 + r]] * y[ui[4 + c]] * irho;
+        m[r * 3 + c] = v;
+      }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// LDS views.  The constant tables (basis, orbital coefficients when they fit,
+// determinant tables) are staged once per block; the walker state and the
+// scratch of each phase follow.
+// ---------------------------------------------------------------------------
+struct Ld {
+  double* L;
+  const DevWF& wf;
+  double* bk = nullptr;  // backup area of the walker record (all-electron moves)
+  __device__ Ld(double* l, const DevWF& w) : L(l), wf(w) {}
+  // constant tables
+  __device__ const int* fn() const { return (const int*)(L + wf.l_fn); }      // [Mpad][2]
+  __device__ const int* sh() const { return (const int*)(L + wf.l_sh); }      // [nshell][8]
+  __device__ const double* pe() const { return L + wf.l_pe; }
+  __device__ const double* pc() const { return L + wf.l_pc; }
+  __device__ const double* nuc() const { return L + wf.l_nuc; }
+  __device__ const double* en() const { return L + wf.l_en; }
+  __device__ const int* psh() const { return (const int*)(L + wf.l_psh); }
+  __device__ const int* ref(int s) const { return (const int*)(L + wf.l_ref[s]); }
+  __device__ const int* porb(int s) const { return (const int*)(L + wf.l_porb[s]); }
+  __device__ const int* ui(int s) const { return (const int*)(L + wf.l_ui[s]); }
+  __device__ const int* wrow(int s) const { return (const int*)(L + wf.l_wrow[s]); }
+  __device__ const int* woth(int s) const { return (const int*)(L + wf.l_woth[s]); }
+  __device__ const double* wcoef(int s) const { return L + wf.l_wcoef[s]; }
+  __device__ const int* srow() const { return (const int*)(L + wf.l_srow); }
+  __device__ const int* slu() const { return (const int*)(L + wf.l_slu); }
+  __device__ const double* slc() const { return L + wf.l_slc; }
+  template <typename T> __device__ const T* lam() const;
+  // walker state
+  __device__ double* R() const { return L + wf.l_R; }
+  __device__ double* B(int s) const { return L + wf.l_B[s]; }
+  __device__ double* T(int s) const { return L + wf.l_T[s]; }
+  __device__ double* PP(int s) const { return L + wf.l_PP[s]; }
+  __device__ double* Ru(int s) const { return L + wf.l_Ru[s]; }
+  __device__ double* Wu(int s) const { return L + wf.l_Wu[s]; }
+  __device__ double* Qu() const { return L + wf.l_Qu; }
+  __device__ double* sc() const { return L + wf.l_sc; }
+  __device__ double* red() const { return L + wf.l_red; }
+  __device__ int* ipiv() const { return (int*)(L + wf.l_ipiv); }
+  __device__ double* f() const { return L + wf.l_f; }
+  __device__ double* gU() const { return L + wf.l_gU; }
+  __device__ double* lU() const { return L + wf.l_lU; }
+  __device__ double* gD() const { return L + wf.l_gD; }
+  __device__ double* lD() const { return L + wf.l_lD; }
+  __device__ double* disp() const { return L + wf.l_disp; }
+  __device__ double* gtab() const { return L + wf.l_gtab; }
+  __device__ double* Phi() const { return L + wf.l_Phi; }
+  __device__ double* part() const { return L + wf.l_part; }
+  __device__ double* chi() const { return L + wf.l_chi; }
+  __device__ double* v() const { return L + wf.l_v; }
+  __device__ double* y() const { return L + wf.l_y; }
+  __device__ double* bcol() const { return L + wf.l_bcol; }
+  __device__ double* z() const { return L + wf.l_z; }
+  __device__ double* yb() const { return L + wf.l_yb; }
+  __device__ double* sij() const { return L + wf.l_sij; }
+  __device__ double* ratio() const { return L + wf.l_ratio; }
+};
+template <> __device__ const double* Ld::lam<double>() const {
+  return wf.lam_in_lds ? (const double*)(L + wf.l_lam) : wf.lamT;
+}
+template <> __device__ const float* Ld::lam<float>() const {
+  return wf.lam_in_lds ? (const float*)(L + wf.l_lam) : wf.lamT32;
+}
+template <> __device__ const uint16_t* Ld::lam<uint16_t>() const {
+  return wf.lam_in_lds ? (const uint16_t*)(L + wf.l_lam) : wf.lamT16;
+}
+
+__device__ __forceinline__ int spin_of(const DevWF& wf, int i) { return i < wf.nup ? 0 : 1; }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ void stage(T* dst, const T* src, int n) {
+  for (int k = threadIdx.x; k < n; k += NT) dst[k] = src[k];
+}
+
+// copy the constant tables into LDS (once per block)
+template <int NT, int PREC>
+__device__ void stage_tables(const DevWF& wf, const Ld& l) {
+  double* L = l.L;
+  stage<NT>((int*)(L + wf.l_fn), wf.fnmap, 2 * wf.Mpad);
+  stage<NT>((int*)(L + wf.l_sh), wf.shtab, 8 * wf.nshell);
+  stage<NT>(L + wf.l_pe, wf.pexp, wf.nprim);
+  stage<NT>(L + wf.l_pc, wf.pcoef, wf.nprim);
+  stage<NT>((int*)(L + wf.l_psh), wf.pshell, wf.nprim);
+  stage<NT>(L + wf.l_nuc, wf.nuc, 4 * wf.nnuc);
+  stage<NT>(L + wf.l_en, wf.en, 6 * wf.nnuc);
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    stage<NT>((int*)(L + wf.l_ref[s]), st.ref, st.n);
+    stage<NT>((int*)(L + wf.l_porb[s]), st.porb, st.nP);
+    stage<NT>((int*)(L + wf.l_ui[s]), st.uinfo, 8 * st.nU);
+    stage<NT>((int*)(L + wf.l_wrow[s]), st.wrow, st.nU + 1);
+    stage<NT>((int*)(L + wf.l_woth[s]), st.wother, wf.nwl[s]);
+    stage<NT>(L + wf.l_wcoef[s], st.wcoef, wf.nwl[s]);
+  }
+  stage<NT>((int*)(L + wf.l_srow), wf.srow, wf.nstruct + 1);
+  stage<NT>((int*)(L + wf.l_slu), wf.slu, 2 * wf.nlinks);
+  stage<NT>(L + wf.l_slc, wf.slc, wf.nlinks);
+  if (wf.lam_in_lds) {
+    int n = wf.Mpad * wf.nop;
+    if constexpr (PREC == 0) stage<NT>(L + wf.l_lam, wf.lamT, n);
+    else if constexpr (PREC == 1) stage<NT>((float*)(L + wf.l_lam), wf.lamT32, n);
+    else stage<NT>((uint16_t*)(L + wf.l_lam), wf.lamT16, n);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// AO -> orbital contraction for a tile of up to 16 electrons on MFMA.
+// group_radial fills, per electron of the tile, the displacement to every
+// nucleus and the radial sums of every shell; group_channel then builds the
+// A operand (basis channel c at electron e, function mu) on the fly from those
+// tables and contracts it with lambda^T, one 16x16 output tile at a time,
+// writing Phi[e][p] (FP64) for channel c.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  T* disp = (T*)l.disp();  // [16][nnuc][4]: x, y, z, r2
+  T* gt = (T*)l.gtab();    // [16][nshell][3]: g, g1, g2
+  for (int idx = threadIdx.x; idx < kGroup * wf.nnuc; idx += NT) {
+    int e = idx / wf.nnuc, a = idx - e * wf.nnuc;
+    T x = 0, y = 0, z = 0;
+    if (e < ne) {
+      x = (T)(Rsrc[3 * (g0 + e)] - l.nuc()[4 * a]);
+      y = (T)(Rsrc[3 * (g0 + e) + 1] - l.nuc()[4 * a + 1]);
+      z = (T)(Rsrc[3 * (g0 + e) + 2] - l.nuc()[4 * a + 2]);
+    }
+    disp[4 * idx] = x; disp[4 * idx + 1] = y; disp[4 * idx + 2] = z;
+    disp[4 * idx + 3] = x * x + y * y + z * z;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
+    int e = idx / wf.nshell, sh = idx - e * wf.nshell;
+    const int* si = l.sh() + 8 * sh;
+    T r2 = disp[4 * (e * wf.nnuc + si[0]) + 3], r = sqrt(r2);
+    T g = 0, g1 = 0, g2 = 0;
+    if (e < ne) {
+      for (int k = 0; k < si[5]; ++k) {
+        T a = (T)l.pe()[si[4] + k];
+        T t = si[1] == 0 ? a * r2 : a * r;
+        if (t < T(50)) {
+          T ex = (T)l.pc()[si[4] + k] * dexp<T>(-t);
+          g += ex;
+          g1 -= a * ex;
+          g2 += a * a * ex;
+        }
+      }
+    }
+    gt[3 * idx] = g; gt[3 * idx + 1] = g1; gt[3 * idx + 2] = g2;
+  }
+  __syncthreads();
+}
+
+// basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function mu at
+// electron e of the tile, from the radial tables
+template <typename T>
+__device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
+  const int* fn = l.fn();
+  int sh = fn[2 * mu];
+  if (sh < 0) return T(0);
+  int m = fn[2 * mu + 1];
+  const int* si = l.sh() + 8 * sh;
+  int kind = si[1], lq = si[2];
+  const T* d = (const T*)l.disp() + 4 * (e * wf.nnuc + si[0]);
+  const T* gg = (const T*)l.gtab() + 3 * (e * wf.nshell + sh);
+  T x = d[0], y = d[1], z = d[2], r2 = d[3];
+  T g = gg[0], g1 = gg[1], g2 = gg[2];
+  T P, Px = T(0), Py = T(0), Pz = T(0);
+  if (lq == 0) {
+    P = T(1);
+  } else if (lq == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? T(1) : T(0);
+    Py = m == 1 ? T(1) : T(0);
+    Pz = m == 2 ? T(1) : T(0);
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = T(2) * x; Py = T(-2) * y; break;
+      default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
+    }
+  }
+  if (c == 0) return P * g;
+  if (kind == 0) {
+    if (c == 4) return P * (T(2 * (2 * lq + 3)) * g1 + T(4) * r2 * g2);
+    T fr = T(2) * g1;
+    if (c == 1) return Px * g + P * fr * x;
+    if (c == 2) return Py * g + P * fr * y;
+    return Pz * g + P * fr * z;
+  }
+  T r = sqrt(r2);
+  if (c == 4) return P * (g2 + T(2 * (lq + 1)) * g1 / r);
+  T fr = g1 / r;
+  if (c == 1) return Px * g + P * fr * x;
+  if (c == 2) return Py * g + P * fr * y;
+  return Pz * g + P * fr * z;
+}
+
+template <int NT, int PREC>
+__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const int nct = wf.nop / 16;
+  double* Phi = l.Phi();
+  for (int ct = wave; ct < nct; ct += NW) {
+    const int col = ct * 16 + (lane & 15);
+    const int e = lane & 15;
+    const bool live = e < ne;
+    if constexpr (PREC == 0) {
+      const double* lam = l.lam<double>();
+      v4d acc = {0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        double a = live ? chan_value<double>(wf, l, e, k, c) : 0.0;
+        double b = lam[(size_t)k * wf.nop + col];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+      // f64 16x16x4 output: register r of lane l holds row 4r + l/16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * r + (lane >> 4)) * wf.nop + col] = acc[r];
+    } else if constexpr (PREC == 1) {
+      const float* lam = l.lam<float>();
+      v4f acc = {0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        float a = live ? chan_value<float>(wf, l, e, k, c) : 0.f;
+        float b = lam[(size_t)k * wf.nop + col];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+      // f32 output: register r of lane l holds row 4(l/16) + r
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+    } else {
+      const uint16_t* lam = l.lam<uint16_t>();
+      v4f acc = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        int kb = k0 + 4 * (lane >> 4);
+        v4s a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[j] = (short)(live ? f2bf(chan_value<float>(wf, l, e, kb + j, c)) : (uint16_t)0);
+          b[j] = (short)lam[(size_t)(kb + j) * wf.nop + col];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A
+// (rows electrons, columns reference slots) -> A^{-1} (rows slots, columns
+// electrons).  Returns false if a pivot is exactly zero.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ bool gj_invert(const Ld& l, double* A, int n, double& logdet, double& sgn) {
+  int* piv = l.ipiv();
+  double* f = l.f();
+  double* sc = l.sc();
+  logdet = 0.0;
+  sgn = 1.0;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x < 64) {
+      int lane = threadIdx.x;
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        double v = fabs(A[i * n + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        piv[k] = bi;
+        sc[SC_TMP3] = best;
+      }
+    }
+    __syncthreads();
+    int p = piv[k];
+    if (!(sc[SC_TMP3] > 0.0)) {
+      __syncthreads();
+      return false;
+    }
+    if (p != k)
+      for (int j = threadIdx.x; j < n; j += NT) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[p * n + j];
+        A[p * n + j] = t;
+      }
+    __syncthreads();
+    double pv = A[k * n + k];
+    logdet += log(fabs(pv));
+    if (pv < 0) sgn = -sgn;
+    if (p != k) sgn = -sgn;
+    for (int i = threadIdx.x; i < n; i += NT) f[i] = A[i * n + k];
+    __syncthreads();
+    double ip = 1.0 / pv;
+    for (int j = threadIdx.x; j < n; j += NT) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * ip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+      int i = idx / n, j = idx - i * n;
+      if (i != k) A[idx] = (j == k ? 0.0 : A[idx]) - f[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    int p = piv[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < n; i += NT) {
+        double t = A[i * n + k];
+        A[i * n + k] = A[i * n + p];
+        A[i * n + p] = t;
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Determinant-table bookkeeping: R_u = det(T[J,Q]), W_u = sum over the pairs
+// holding u of w_k R_{other}, S = sum_k w_k R_up R_dn = sum_u R_u W_u.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void update_R(const DevWF& wf, const Ld& l, int s) {
+  const SpinTab& st = wf.sp[s];
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double m[9];
+    int e = gather_u(l.ui(s) + 8 * u, l.T(s), st.nP, m, nullptr, nullptr, 0.0);
+    l.Ru(s)[u] = det_e(e, m);
+  }
+}
+
+template <int NT>
+__device__ void update_W(const DevWF& wf, const Ld& l, int s) {
+  const SpinTab& st = wf.sp[s];
+  const double* Ro = l.Ru(1 - s);
+  const int* wr = l.wrow(s);
+  const int* wo = l.woth(s);
+  const double* wc = l.wcoef(s);
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double w = 0.0;
+    for (int k = wr[u]; k < wr[u + 1]; ++k) w += wc[k] * Ro[wo[k]];
+    l.Wu(s)[u] = w;
+  }
+}
+
+template <int NT>
+__device__ void update_S(const DevWF& wf, const Ld& l) {
+  double v[1] = {0.0};
+  for (int u = threadIdx.x; u < wf.sp[0].nU; u += NT) v[0] += l.Ru(0)[u] * l.Wu(0)[u];
+  block_sum<NT, 1>(v, l.red());
+  if (threadIdx.x == 0) l.sc()[SC_S] = v[0];
+  __syncthreads();
+}
+
+template <int NT>
+__device__ void compute_RWS(const DevWF& wf, const Ld& l) {
+  update_R<NT>(wf, l, 0);
+  update_R<NT>(wf, l, 1);
+  __syncthreads();
+  update_W<NT>(wf, l, 0);
+  update_W<NT>(wf, l, 1);
+  __syncthreads();
+  update_S<NT>(wf, l);
+}
+
+// ---------------------------------------------------------------------------
+// Fresh reference inverses and tables from positions Rsrc (values pass on
+// MFMA + Gauss-Jordan).  Returns false on an exactly singular reference.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
+  for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
+    int ne = min(kGroup, wf.N - g0);
+    group_radial<NT, PREC>(wf, l, Rsrc, g0, ne);
+    group_channel<NT, PREC>(wf, l, ne, 0);
+    const double* Phi = l.Phi();
+    for (int s = 0; s < 2; ++s) {
+      const SpinTab& st = wf.sp[s];
+      int w = st.n + st.nP;
+      for (int idx = threadIdx.x; idx < ne * w; idx += NT) {
+        int e = idx / w, j = idx - e * w, i = g0 + e;
+        if (spin_of(wf, i) != s) continue;
+        int il = i - st.e0;
+        if (j < st.n)
+          l.B(s)[il * st.n + j] = Phi[e * wf.nop + l.ref(s)[j]];
+        else
+          l.PP(s)[il * st.nP + (j - st.n)] = Phi[e * wf.nop + l.porb(s)[j - st.n]];
+      }
+    }
+    __syncthreads();
+  }
+  bool ok = true;
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    double ld = 0.0, sg = 1.0;
+    if (st.n > 0 && !gj_invert<NT>(l, l.B(s), st.n, ld, sg)) ok = false;
+    if (threadIdx.x == 0) {
+      l.sc()[SC_LOGDET0 + s] = ld;
+      l.sc()[SC_SGN0 + s] = sg;
+      l.sc()[SC_NUPD0 + s] = 0.0;
+    }
+    // T = B PP
+    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+      int j = idx / st.nP, q = idx - j * st.nP;
+      double a = 0.0;
+      for (int i = 0; i < st.n; ++i) a += l.B(s)[j * st.n + i] * l.PP(s)[i * st.nP + q];
+      l.T(s)[idx] = a;
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Jastrow factor and potential for all electrons: U, grad_i U, lap_i U, V.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
+  double part[2] = {0.0, 0.0};  // U, V
+  const double* nuc = l.nuc();
+  for (int i = threadIdx.x; i < wf.N; i += NT) {
+    double xi = Rsrc[3 * i], yi = Rsrc[3 * i + 1], zi = Rsrc[3 * i + 2];
+    double gx = 0, gy = 0, gz = 0, lap = 0, Ui = 0, Vi = 0;
+    for (int a = 0; a < wf.nnuc; ++a) {
+      double dx = xi - nuc[4 * a], dy = yi - nuc[4 * a + 1], dz = zi - nuc[4 * a + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      const double* ja = l.en() + 6 * a;
+      pair_fn(r, wf.kappa, ja[0], ja[1], ja + 2, u, u1, u2);
+      Ui += u;
+      double f = u1 / r;
+      gx += f * dx; gy += f * dy; gz += f * dz;
+      lap += u2 + 2.0 * f;
+      Vi -= nuc[4 * a + 3] / r;
+    }
+    int si = spin_of(wf, i);
+    for (int j = 0; j < wf.N; ++j) {
+      if (j == i) continue;
+      double dx = xi - Rsrc[3 * j], dy = yi - Rsrc[3 * j + 1], dz = zi - Rsrc[3 * j + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      bool anti = si != spin_of(wf, j);
+      pair_fn(r, wf.kappa, anti ? wf.ee[0] : wf.ee[1], anti ? wf.ee[2] : wf.ee[3], wf.ee + 4, u, u1, u2);
+      Ui += 0.5 * u;
+      double f = u1 / r;
+      gx += f * dx; gy += f * dy; gz += f * dz;
+      lap += u2 + 2.0 * f;
+      Vi += 0.5 / r;
+    }
+    l.gU()[3 * i] = gx; l.gU()[3 * i + 1] = gy; l.gU()[3 * i + 2] = gz;
+    l.lU()[i] = lap;
+    part[0] += Ui;
+    part[1] += Vi;
+  }
+  block_sum<NT, 2>(part, l.red());
+  if (threadIdx.x == 0) {
+    l.sc()[SC_U] = part[0];
+    l.sc()[SC_V] = part[1] + wf.vnn;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Row-operator ratio of one electron: sum_u (rho R_u + y^T adj(T_JQ) B_J,i) W_u
+// for a row w (length nop) of electron il of spin s.
+// ---------------------------------------------------------------------------
+__device__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf) {
+  const SpinTab& st = wf.sp[s];
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  double rho = 0.0;
+#pragma unroll 4
+  for (int j = 0; j < st.n; ++j) rho += w[ref[j]] * B[j * st.n + il];
+  for (int q = 0; q < st.nP; ++q) {
+    double a = w[porb[q]];
+#pragma unroll 4
+    for (int k = 0; k < st.n; ++k) a -= w[ref[k]] * T[k * st.nP + q];
+    ybuf[q] = a;
+  }
+  double tot = 0.0;
+  const int* uit = l.ui(s);
+  for (int u = 0; u < st.nU; ++u) {
+    const int* ui = uit + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = ybuf[ui[4 + r]];
+        bb[r] = B[ui[1 + r] * st.n + il];
+      }
+    tot += (rho * l.Ru(s)[u] + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
+  }
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// Local energy pass: per tile of electrons, MFMA channels 1..4 (gradient and
+// Laplacian rows), row-operator ratios, then the Jastrow and potential.
+// Fills gD, lD, gU, lU and SC_ELOC, SC_LOGPSI, SC_SIGN.  gc (the DMC
+// gradient cache in the walker record) may be null.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
+  const double* R = l.R();
+  const double S = l.sc()[SC_S];
+  const int nPmax = max(wf.sp[0].nP, wf.sp[1].nP);
+  for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
+    int ne = min(kGroup, wf.N - g0);
+    group_radial<NT, PREC>(wf, l, R, g0, ne);
+    for (int c = 1; c <= 4; ++c) {
+      group_channel<NT, PREC>(wf, l, ne, c);
+      const double* Phi = l.Phi();
+      for (int e = threadIdx.x; e < ne; e += NT) {
+        int i = g0 + e;
+        int s = spin_of(wf, i), il = i - wf.sp[s].e0;
+        double tot = row_op_sum(wf, l, s, il, Phi + e * wf.nop, l.yb() + e * (nPmax + 1));
+        if (c < 4)
+          l.gD()[3 * i + c - 1] = tot / S;
+        else
+          l.lD()[i] = tot / S;
+      }
+      if (gc && c < 4)
+        for (int idx = threadIdx.x; idx < ne * wf.nop; idx += NT) {
+          int e = idx / wf.nop, p = idx - e * wf.nop;
+          gc[((g0 + e) * 3 + c - 1) * wf.nop + p] = Phi[idx];
+        }
+      __syncthreads();
+    }
+  }
+  jastrow_full<NT>(wf, l, R);
+  double part[1] = {0.0};
+  for (int i = threadIdx.x; i < wf.N; i += NT) {
+    double t = l.lU()[i] + l.lD()[i];
+    for (int x = 0; x < 3; ++x) {
+      double gu = l.gU()[3 * i + x];
+      t += gu * gu + 2.0 * gu * l.gD()[3 * i + x];
+    }
+    part[0] += -0.5 * t;
+  }
+  block_sum<NT, 1>(part, l.red());
+  if (threadIdx.x == 0) {
+    double* sc = l.sc();
+    sc[SC_ELOC] = part[0] + sc[SC_V];
+    sc[SC_LOGPSI] = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(S));
+    sc[SC_SIGN] = sc[SC_SGN0] * sc[SC_SGN1] * (S > 0 ? 1.0 : (S < 0 ? -1.0 : 0.0));
+  }
+  __syncthreads();
+}
+
+// structure ratios r_I = sum_links d' R_up R_dn / S into l.ratio()
+template <int NT>
+__device__ void structure_ratios(const DevWF& wf, const Ld& l) {
+  double S = l.sc()[SC_S];
+  const int* srow = l.srow();
+  const int* slu = l.slu();
+  const double* slc = l.slc();
+  for (int I = threadIdx.x; I < wf.nstruct; I += NT) {
+    double a = 0.0;
+    for (int k = srow[I]; k < srow[I + 1]; ++k) a += slc[k] * l.Ru(0)[slu[2 * k]] * l.Ru(1)[slu[2 * k + 1]];
+    l.ratio()[I] = a / S;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Basis values (+ gradients if nch = 4) at one point and their contraction to
+// orbital rows v[c][p] on the VALU.  One lane per primitive forms the
+// exponentials, one lane per basis function sums its shell's primitives and
+// applies the angular factor, then lanes split the basis sum of each output
+// and reduce with cross-lane shuffles.
+// ---------------------------------------------------------------------------
+template <int NT, int PREC>
+__device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double py, double pz, int nch) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  T* chi = (T*)l.chi();
+  T* pt = (T*)l.gtab();  // [nprim][3] primitive terms (the radial table is free during moves)
+  const double* nuc = l.nuc();
+  const int* psh = l.psh();
+  for (int q = threadIdx.x; q < wf.nprim; q += NT) {
+    const int* si = l.sh() + 8 * psh[q];
+    int a = si[0];
+    T x = (T)(px - nuc[4 * a]), y = (T)(py - nuc[4 * a + 1]), z = (T)(pz - nuc[4 * a + 2]);
+    T r2 = x * x + y * y + z * z;
+    T al = (T)l.pe()[q];
+    T t = si[1] == 0 ? al * r2 : al * sqrt(r2);
+    T ex = t < T(50) ? (T)l.pc()[q] * dexp<T>(-t) : T(0);
+    pt[3 * q] = ex;
+    pt[3 * q + 1] = -al * ex;
+  }
+  __syncthreads();
+  for (int mu = threadIdx.x; mu < wf.Mpad; mu += NT) {
+    int sh = l.fn()[2 * mu];
+    if (sh < 0) {
+      for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = T(0);
+      continue;
+    }
+    const int* si = l.sh() + 8 * sh;
+    int a = si[0], kind = si[1], lq = si[2], p0 = si[4], np = si[5];
+    T x = (T)(px - nuc[4 * a]), y = (T)(py - nuc[4 * a + 1]), z = (T)(pz - nuc[4 * a + 2]);
+    T r2 = x * x + y * y + z * z, r = sqrt(r2);
+    T g = 0, g1 = 0;
+#pragma unroll 4
+    for (int k = 0; k < np; ++k) {
+      g += pt[3 * (p0 + k)];
+      g1 += pt[3 * (p0 + k) + 1];
+    }
+    T o[5];
+    channels<T>(kind, lq, l.fn()[2 * mu + 1], x, y, z, r2, r, g, g1, T(0), nch, o);
+    for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = o[c];
+  }
+  __syncthreads();
+  typedef typename std::conditional<PREC == 0, double, float>::type LT;
+  const LT* lam = l.lam<LT>();
+  const int nout = nch * wf.nop;
+  if (nout <= 64) {
+    // one wave: lane = part * nout + o, parts reduced with shuffles
+    if (threadIdx.x < 64) {
+      // lane = o * nparts + part (nparts a power of two): adjacent lanes
+      // split one output's basis sum and are combined with xor shuffles
+      int lg = 0;
+      while ((2 << lg) * nout <= 64) ++lg;
+      const int nparts = 1 << lg;
+      const int lane = threadIdx.x, o = lane >> lg, pt_ = lane & (nparts - 1);
+      const int chunk = wf.Mpad >> lg;  // Mpad is a multiple of 16 and nparts <= 64 / 16
+      T acc = T(0);
+      if (o < nout) {
+        int c = (o >= wf.nop) + (o >= 2 * wf.nop) + (o >= 3 * wf.nop);
+        int p = o - c * wf.nop;
+        const T* ch = chi + c * wf.Mpad + pt_ * chunk;
+        const LT* lp = lam + (size_t)pt_ * chunk * wf.nop + p;
+#pragma unroll 4
+        for (int k = 0; k < chunk; ++k) acc += ch[k] * (T)lp[(size_t)k * wf.nop];
+      }
+      double a = (double)acc;
+      for (int off = 1; off < nparts; off <<= 1) a += __shfl_xor(a, off, 64);
+      if (o < nout && pt_ == 0) l.v()[o] = a;
+    }
+  } else {
+    for (int o = threadIdx.x; o < nout; o += NT) {
+      int c = o / wf.nop, p = o - c * wf.nop;
+      const T* ch = chi + c * wf.Mpad;
+      T acc = T(0);
+#pragma unroll 4
+      for (int mu = 0; mu < wf.Mpad; ++mu) acc += ch[mu] * (T)lam[(size_t)mu * wf.nop + p];
+      l.v()[o] = (double)acc;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Single-electron move of electron i to (px,py,pz): ratio of determinant sums
+// S''/S (written to SC_RATIO) and Jastrow change dU (SC_TMP0); fills y (value
+// channel), bcol (old B column), rho (SC_TMP1) and Qu.  Requires v[0][*] to
+// hold the new orbital values.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
+  int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  const int n = st.n, nP = st.nP;
+  int il = i - st.e0;
+  const double* v = l.v();
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  double* y = l.y();
+  double* bc = l.bcol();
+  double* vr = l.z() + n;  // gathered v[ref[j]] (z holds n more entries used on accept)
+  // phase 1: gather v[ref], old B column, rho = sum_j v[ref_j] B[j][i]
+  double prod = 0.0;
+  for (int j = threadIdx.x; j < n; j += NT) {
+    double a = v[ref[j]], b = B[j * n + il];
+    vr[j] = a;
+    bc[j] = b;
+    prod += a * b;
+  }
+  double rr[1] = {prod};
+  block_sum<NT, 1>(rr, l.red());
+  const double rho = rr[0];
+  __syncthreads();
+  // phase 2: y[q] = v[P_q] - sum_k v[ref_k] T[k][q]; Jastrow change in parallel
+  for (int q = threadIdx.x; q < nP; q += NT) {
+    double a = v[porb[q]];
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) a -= vr[k] * T[k * nP + q];
+    y[q] = a;
+  }
+  double part[2] = {0.0, 0.0};
+  const double* R = l.R();
+  const double* nuc = l.nuc();
+  double xo = R[3 * i], yo = R[3 * i + 1], zo = R[3 * i + 2];
+  for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
+    if (j == i) continue;
+    double xj, yj, zj, a, b;
+    const double* q;
+    if (j < wf.N) {
+      xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
+      bool anti = s != spin_of(wf, j);
+      a = anti ? wf.ee[0] : wf.ee[1];
+      b = anti ? wf.ee[2] : wf.ee[3];
+      q = wf.ee + 4;
+    } else {
+      int nn = j - wf.N;
+      xj = nuc[4 * nn]; yj = nuc[4 * nn + 1]; zj = nuc[4 * nn + 2];
+      a = l.en()[6 * nn]; b = l.en()[6 * nn + 1]; q = l.en() + 6 * nn + 2;
+    }
+    double rn = sqrt((px - xj) * (px - xj) + (py - yj) * (py - yj) + (pz - zj) * (pz - zj));
+    double ro = sqrt((xo - xj) * (xo - xj) + (yo - yj) * (yo - yj) + (zo - zj) * (zo - zj));
+    part[1] += pair_val(rn, wf.kappa, a, b, q) - pair_val(ro, wf.kappa, a, b, q);
+  }
+  __syncthreads();
+  // phase 3: Q_u = rho R_u + y^T adj(T_JQ) B_J,i and S'' = sum_u Q_u W_u
+  const int* uit = l.ui(s);
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    const int* ui = uit + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = y[ui[4 + r]];
+        bb[r] = bc[ui[1 + r]];
+      }
+    double q = rho * l.Ru(s)[u] + adj_e(e, m, yy, bb);
+    l.Qu()[u] = q;
+    part[0] += q * l.Wu(s)[u];
+  }
+  block_sum<NT, 2>(part, l.red());
+  if (threadIdx.x == 0) {
+    l.sc()[SC_RATIO] = part[0] / l.sc()[SC_S];
+    l.sc()[SC_TMP0] = part[1];
+    l.sc()[SC_TMP1] = rho;
+  }
+  __syncthreads();
+}
+
+// Commit an accepted move of electron i (after move_ratio).
+template <int NT>
+__device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
+  int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  int il = i - st.e0;
+  double* B = l.B(s);
+  double* T = l.T(s);
+  double rho = l.sc()[SC_TMP1];
+  double* z = l.z();
+  const double* vr = l.z() + st.n;  // v[ref[k]], gathered by move_ratio
+  for (int m = threadIdx.x; m < st.n; m += NT) {
+    double a = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < st.n; ++k) a += vr[k] * B[k * st.n + m];
+    z[m] = (m == il ? a - 1.0 : a);
+  }
+  __syncthreads();
+  double ir = 1.0 / rho;
+  const double* bc = l.bcol();
+  const double* y = l.y();
+  if (st.n <= NT) {
+    // lane m owns column m of B; rows j in sequence (no integer division)
+    const int m = threadIdx.x;
+    if (m < st.n) {
+      double zm = z[m] * ir;
+      for (int j = 0; j < st.n; ++j) B[j * st.n + m] -= bc[j] * zm;
+    }
+    if (m < st.nP) {
+      double yq = y[m] * ir;
+      for (int j = 0; j < st.n; ++j) T[j * st.nP + m] += bc[j] * yq;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < st.n * st.n; idx += NT) {
+      int j = idx / st.n, m = idx - j * st.n;
+      B[idx] -= bc[j] * z[m] * ir;
+    }
+    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+      int j = idx / st.nP, q = idx - j * st.nP;
+      T[idx] += bc[j] * y[q] * ir;
+    }
+  }
+  if (threadIdx.x == 0) {
+    double* sc = l.sc();
+    sc[SC_LOGDET0 + s] += log(fabs(rho));
+    if (rho < 0) sc[SC_SGN0 + s] = -sc[SC_SGN0 + s];
+    sc[SC_NUPD0 + s] += 1.0;
+    double* R = l.R();
+    R[3 * i] = px; R[3 * i + 1] = py; R[3 * i + 2] = pz;
+  }
+  __syncthreads();
+  // R_u of this spin, and S = sum_u R_u W_u (W of this spin does not depend
+  // on this spin's R), then the other spin's W
+  double vS[1] = {0.0};
+  for (int u = threadIdx.x; u < st.nU; u += NT) {
+    double m[9];
+    int e = gather_u(l.ui(s) + 8 * u, T, st.nP, m, nullptr, nullptr, 0.0);
+    double r = det_e(e, m);
+    l.Ru(s)[u] = r;
+    vS[0] += r * l.Wu(s)[u];
+  }
+  block_sum<NT, 1>(vS, l.red());
+  if (threadIdx.x == 0) l.sc()[SC_S] = vS[0];
+  __syncthreads();
+  update_W<NT>(wf, l, 1 - s);
+  __syncthreads();
+}
+
+}  // namespace vbqmc

@@ -33,7 +33,7 @@ hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, c
 hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
-hipError_t launch_reduce(int64_t W, int K, const double* in, double* out, hipStream_t s);
+hipError_t launch_reduce(int64_t W, int K, const double* wts, const double* in, double* out, hipStream_t s);
 hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi, double* deloc,
                              double* ws, size_t ws_doubles, hipStream_t s);
 size_t param_grad_ws_doubles(const DevWF& wf, int64_t W);
@@ -457,16 +457,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // orbital coefficients go to LDS when they take at most 16 KiB
   wf.lam_in_lds = lam_doubles * 8 <= 16384 ? 1 : 0;
   wf.l_lam = wf.lam_in_lds ? lds(lam_doubles) : 0;
+  // regions used by both the walker kernels and the adjoint kernel
   wf.l_R = lds(3 * x->N);
-  for (int s = 0; s < 2; ++s) {
-    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
-    wf.l_B[s] = lds(n * n);
-    wf.l_T[s] = lds(n * nP);
-    wf.l_PP[s] = lds(n * nP);
-    wf.l_Ru[s] = lds((int)x->sp[s].sets.size());
-    wf.l_Wu[s] = lds((int)x->sp[s].sets.size());
-  }
-  wf.l_Qu = lds(nUm);
   wf.l_sc = lds(SC_COUNT);
   wf.l_red = lds(kRedSlots);
   int nmax = std::max(x->nup, x->ndn);
@@ -479,6 +471,17 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_disp = lds(kGroup * x->nnuc * 4);
   wf.l_gtab = lds(std::max(kGroup * x->nshell * 3, 3 * wf.nprim));
   wf.l_Phi = lds(kGroup * x->nop);
+  const int shared_end = o;
+  // walker-kernel regions
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    wf.l_B[s] = lds(n * n);
+    wf.l_T[s] = lds(n * nP);
+    wf.l_PP[s] = lds(n * nP);
+    wf.l_Ru[s] = lds((int)x->sp[s].sets.size());
+    wf.l_Wu[s] = lds((int)x->sp[s].sets.size());
+  }
+  wf.l_Qu = lds(nUm);
   wf.l_part = lds(std::max(x->nt, 4 * x->nop));
   wf.l_chi = lds(4 * x->Mpad);
   wf.l_v = lds(4 * x->nop);
@@ -488,6 +491,19 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_yb = lds(kGroup * (nPm + 1));
   wf.l_sij = lds(x->nstruct * x->nstruct);
   wf.l_ratio = lds(x->nstruct);
+  const int walker_end = o;
+  // adjoint-kernel regions (alias the walker-kernel regions)
+  o = shared_end;
+  wf.l_aPhi = lds(5 * x->N * x->nop);
+  wf.l_aG0 = lds(x->N * x->nop);
+  wf.l_aG = lds(x->N * x->nop);
+  wf.l_aA = lds(nmax * nmax);
+  wf.l_aP = lds(nmax * nmax);
+  wf.l_aM = lds(nmax * nmax);
+  wf.l_aU[0] = lds(5 * (int)x->sp[0].sets.size());
+  wf.l_aU[1] = lds(5 * (int)x->sp[1].sets.size());
+  wf.lds_adj_doubles = o;
+  o = walker_end;
   wf.lds_doubles = o;
 
   int dev = 0;
@@ -743,14 +759,18 @@ int vbqmc_param_grad(vbqmc_ctx* x, int64_t W, const double* R, double* dlogpsi, 
   if (W == 0) return VBQMC_OK;
   size_t need = param_grad_ws_doubles(x->wf, W) * 8;
   if (need && (!ws || ws_bytes < need)) return fail(x, VBQMC_EWORKSPACE, "param_grad: workspace too small");
+  if ((size_t)x->wf.lds_adj_doubles * 8 > (size_t)x->lds_limit)
+    return fail(x, VBQMC_EINVAL, "param_grad: system too large for the adjoint kernel's LDS budget");
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "param_grad: too many walkers");
   hipError_t e = launch_param_grad(x->wf, x->d_wf, x->nt, W, R, dlogpsi, deloc, (double*)ws, need / 8, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "param_grad");
 }
 
-int vbqmc_reduce_walkers(vbqmc_ctx* x, int64_t W, int32_t K, const double* in, double* out, vbqmc_stream stream) {
+int vbqmc_reduce_walkers(vbqmc_ctx* x, int64_t W, int32_t K, const double* weights, const double* in, double* out,
+                         vbqmc_stream stream) {
   if (!x || W < 0 || K < 0 || (K > 0 && (!in || !out))) return fail(x, VBQMC_EINVAL, "reduce: bad arguments");
   if (K == 0) return VBQMC_OK;
-  hipError_t e = launch_reduce(W, K, in, out, (hipStream_t)stream);
+  hipError_t e = launch_reduce(W, K, weights, in, out, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "reduce");
 }
 

@@ -61,7 +61,9 @@ struct DevWF {
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
   int l_gU, l_lU, l_gD, l_lD;
   int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_yb, l_sij, l_ratio;
-  int lds_doubles;
+  // adjoint kernel
+  int l_aPhi, l_aG0, l_aG, l_aA, l_aP, l_aM, l_aU[2];
+  int lds_doubles, lds_adj_doubles;
 };
 
 // scalar slots in the record's / LDS scalar block
