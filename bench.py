@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
+# HBM bytes per k_vmc launch (4096 walkers, 10 steps) from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the copy-kernel calibration; None until measured for
+# the current kernel (see the k_vmc profile summary under profiles/).
+TRAFFIC_BYTES_PER_LAUNCH = 18.70e6
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
@@ -61,7 +65,25 @@ def vmc_flops_per_walker_move(ctx, system, accept_rate):
     return total
 
 
-def cpu_baseline(system, step_size, steps=40, walkers=256, seed=11):
+def adjoint_flops_per_gradient(ctx, system):
+    """Algorithmic FLOPs of one walker's full gradient: 5-channel basis values
+    (per primitive 6 flops + one exp, per function 16) and contraction for all
+    electrons, per spin determinant two inversions (2 n^3 each), the kinetic
+    rows (8 n^2), A^-1 K A^-1 (4 n^3) and the scatter (4 n^2), the Jastrow
+    pair derivatives (12 parameters x 12 flops per pair), and the two
+    orbital-coefficient contractions (3 x 2 N N_orb M)."""
+    info = ctx.info
+    N, M, norb, nnuc = info["n_electrons"], info["n_basis"], info["n_orbitals"], info["n_nuclei"]
+    P = sum(len(s["exps"]) for s in system["shells"])
+    total = N * (P * (6 + EXP_FLOPS) + 16 * M) + 2 * 5 * N * M * norb
+    for n, u in ((info["n_up"], info["n_unique_up"]), (info["n_dn"], info["n_unique_dn"])):
+        total += u * (2 * 2 * n ** 3 + 8 * n * n + 4 * n ** 3 + 4 * n * n)
+    total += (N * (N - 1) / 2 + N * nnuc) * 12 * 12
+    total += 3 * 2 * N * norb * M
+    return total
+
+
+def cpu_baseline(system, step_size, steps=300, walkers=1024, seed=11):
     """The oracle (plain FP64 CPU code, OpenMP over walkers) on a bounded
     sample of the same workload: `walkers` walkers x `steps` steps."""
     import oracle
@@ -82,10 +104,15 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--steps-per-launch", type=int, default=10,
+                    help="VMC steps per k_vmc launch (warmup and timed launches are the same size)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--form", default="plain", choices=["plain", "precision", "adjoint"],
+                    help="plain: the headline VMC line; precision: FP32/BF16 basis+contraction form on the "
+                         "10-nucleus molecule; adjoint: parameter gradients on the 6-nucleus molecule")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the walker-parallel path would shard "
@@ -98,6 +125,10 @@ def main():
     import systems as S
 
     torch.cuda.set_device(0)
+    if args.form == "precision":
+        return precision_form(args)
+    if args.form == "adjoint":
+        return adjoint_form(args)
     if args.calibrate_copy:
         n = 256 * 1024 * 1024 // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -113,16 +144,24 @@ def main():
     state = ctx.walkers_init(R0)
     acc = ctx.new_vmc_acc(W)
     seed = 20220728
-    if args.warmup:
-        ctx.vmc_advance(state, args.warmup, seed, 0, step_size, False, acc)
+    spl = max(1, min(args.steps_per_launch, args.steps))
+    if args.steps % spl:
+        raise SystemExit("--steps must be a multiple of --steps-per-launch")
+    step = 0
+    for _ in range(0, args.warmup, spl):
+        ctx.vmc_advance(state, spl, seed, step, step_size, False, acc)
+        step += spl
     torch.cuda.synchronize()
     acc = ctx.new_vmc_acc(W)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    launches = args.steps // spl
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    ctx.vmc_advance(state, args.steps, seed, args.warmup, step_size, False, acc)
+    for _ in range(launches):
+        ctx.vmc_advance(state, spl, seed, step, step_size, False, acc)
+        step += spl
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -153,13 +192,113 @@ def main():
         "acceptance": accept_rate,
         "mean_eloc": e_mean,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_vmc", "kernel_ms": kernel_s * 1e3,
-                     "flops_per_walker_move": flops / moves},
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                     "kernel": "k_vmc", "kernel_avg_ms_per_launch": kernel_s * 1e3 / launches,
+                     "steps_per_launch": spl, "flops_per_walker_move": flops / moves,
+                     "flops_per_launch": flops / launches},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(system, step_size)
     print(json.dumps(line))
+
+
+def _timed(fn):
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    out = fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return out, ev0.elapsed_time(ev1) / 1e3
+
+
+def precision_form(args):
+    """Mixed-precision form on the 10-nucleus, 40-electron, 150-function,
+    20-structure / 64-determinant molecule: walker-moves/s of FP64, FP32 and
+    BF16 basis values + contraction (determinants in FP64 throughout),
+    per-walker |E_L(mixed) - E_L(FP64)| at identical configurations, and the
+    mean-energy shift by correlated sampling (FP64 re-evaluation of the
+    mixed-precision chain's configurations)."""
+    import numpy as np
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    system = S.precision_molecule()
+    W = args.walkers if args.walkers != 4096 else 16384
+    steps, step_size, seed = args.steps if args.steps != 200 else 20, 0.3, 777
+    R0 = torch.from_numpy(S.initial_walkers(system, W, seed=9)).cuda()
+    c64 = vb.Context(system, precision="fp64")
+    st = c64.walkers_init(R0)
+    c64.vmc_advance(st, args.warmup, seed, 0, step_size)  # burn-in in FP64
+    Rb = c64.positions(st)
+    ref = c64.evaluate(Rb, want=("eloc",))["eloc"]
+    res = {"metric": "walker-moves/sec incl. E_L (precision forms)", "unit": "walker-moves/s", "n_gpus": 1,
+           "walkers": W, "steps": steps, "data": "synthetic",
+           "config": {"workload": "10 nuclei (Z in {1,6,7,8}), 40 electrons, 150 Gaussian basis functions, "
+                                  "20 VB structures / 64 determinants, VMC single-electron moves 0.3 bohr, "
+                                  "E_L every step, inverse refresh every 32 updates"}, "forms": {}}
+    for prec in ("fp64", "fp32", "bf16"):
+        ctx = c64 if prec == "fp64" else vb.Context(system, precision=prec, refresh_every=32)
+        ev = ctx.evaluate(Rb, want=("eloc",))["eloc"]
+        d = (ev - ref).abs().cpu().numpy()
+        stp = ctx.walkers_init(Rb.clone())
+        acc = ctx.new_vmc_acc(W)
+        _, t = _timed(lambda: ctx.vmc_advance(stp, steps, seed, 1000, step_size, False, acc))
+        # correlated sampling: FP64 E_L on the final configurations of this chain
+        Rm = ctx.positions(stp)
+        e_mixed = acc["e_last"]
+        e_64 = c64.evaluate(Rm, want=("eloc",))["eloc"]
+        shift = (e_mixed - e_64).cpu().numpy()
+        rate = float(acc["n_accept"].sum().item()) / (W * steps * ctx.N)
+        fl = vmc_flops_per_walker_move(ctx, system, rate) * W * steps / t / 1e12
+        res["forms"][prec] = {"value": W * steps / t, "ms_per_step": t / steps * 1e3,
+                              "roofline": {"bound": "alu", "achieved": fl, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                                           "unit": "TFLOP/s", "frac": fl / FP64_VECTOR_PEAK_TFLOPS},
+                              "abs_dEL_max": float(np.nanmax(d)), "abs_dEL_p99": float(np.nanpercentile(d, 99)),
+                              "abs_dEL_median": float(np.nanmedian(d)),
+                              "mean_shift": float(np.nanmean(shift)),
+                              "mean_shift_stderr": float(np.nanstd(shift) / np.sqrt(W)),
+                              "meets_1e-5": bool(np.nanmax(d) <= 1e-5)}
+    print(json.dumps(res))
+
+
+def adjoint_form(args):
+    """Parameter gradients (d lnPsi/dp and d E_L/dp, all ~3054 parameters) for
+    8192 walkers of the 6-nucleus, 30-electron, 120-function, 12-structure /
+    40-determinant molecule, against the plain-FP64 alternative of central
+    finite differences (2 N_p + 1 evaluations per gradient), timed as
+    single evaluate calls of the same batch."""
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    system = S.adjoint_molecule()
+    W = args.walkers if args.walkers != 4096 else 8192
+    ctx = vb.Context(system)
+    R0 = torch.from_numpy(S.initial_walkers(system, W, seed=3)).cuda()
+    st = ctx.walkers_init(R0)
+    ctx.vmc_advance(st, max(args.warmup, 1), 5, 0, 0.3)
+    R = ctx.positions(st)
+    ctx.param_grad(R)  # warm-up
+    reps = 3
+    _, t = _timed(lambda: [ctx.param_grad(R) for _ in range(reps)])
+    t /= reps
+    _, te = _timed(lambda: [ctx.evaluate(R, want=("eloc",)) for _ in range(reps)])
+    te /= reps
+    npar = ctx.n_params
+    fd = W / (te * (2 * npar + 1))
+    gfl = adjoint_flops_per_gradient(ctx, system) * W / t / 1e12
+    print(json.dumps({"metric": "walker-gradients/s (d lnPsi/dp and d E_L/dp)", "value": W / t,
+                      "unit": "gradients/s", "n_gpus": 1, "walkers": W, "n_params": npar,
+                      "ms_per_call": t * 1e3, "fp64_central_difference_gradients_per_s": fd,
+                      "speedup_vs_fd": (W / t) / fd, "evaluate_ms": te * 1e3,
+                      "roofline": {"bound": "alu", "achieved": gfl, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": gfl / FP64_VECTOR_PEAK_TFLOPS,
+                                   "flops_per_gradient": adjoint_flops_per_gradient(ctx, system)},
+                      "config": {"workload": "6 nuclei, 30 electrons, 120 Gaussian basis functions, 12 VB "
+                                             "structures / 40 determinants, kappa = 0.8 Jastrow with polynomials"}}))
 
 
 if __name__ == "__main__":

@@ -18,8 +18,9 @@
 #include "vbqmc_internal.h"
 
 namespace vbqmc {
-hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* logabs, int32_t* sign,
-                           double* grad, double* eloc, double* ratio, double* state, hipStream_t s);
+hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, int64_t rstride,
+                           double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio, double* state,
+                           hipStream_t s);
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
                       hipStream_t s);
@@ -634,7 +635,8 @@ int vbqmc_evaluate(vbqmc_ctx* x, int64_t W, const double* R, double* logabs, int
   if (W < 0 || (W > 0 && (!R || !logabs || !sign))) return fail(x, VBQMC_EINVAL, "evaluate: bad arguments");
   if (W == 0) return VBQMC_OK;
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "evaluate: too many walkers");
-  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, logabs, sign, grad, eloc, ratio, nullptr, (hipStream_t)stream);
+  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, 3 * x->N, logabs, sign, grad, eloc, ratio, nullptr,
+                                 (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "evaluate");
 }
 
@@ -642,7 +644,7 @@ int vbqmc_walkers_init(vbqmc_ctx* x, int64_t W, const double* R, void* state, vb
   if (!x || W < 0 || (W > 0 && (!R || !state))) return fail(x, VBQMC_EINVAL, "walkers_init: bad arguments");
   if (W == 0) return VBQMC_OK;
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "walkers_init: too many walkers");
-  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)state,
+  hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, 3 * x->N, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)state,
                                  (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_init");
 }
@@ -664,10 +666,10 @@ int vbqmc_walkers_eloc(vbqmc_ctx* x, int64_t W, const void* state, double* eloc,
 int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uint64_t seed, uint64_t step0,
                       double step_size, int32_t all_electron, const vbqmc_vmc_acc* acc, vbqmc_stream stream) {
   if (!x || !acc || W < 0 || n_steps < 0 || (W > 0 && !state)) return fail(x, VBQMC_EINVAL, "vmc: bad arguments");
-  if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
-    return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (!(step_size > 0) || !std::isfinite(step_size)) return fail(x, VBQMC_EINVAL, "vmc: bad step size");
   if (W == 0 || n_steps == 0) return VBQMC_OK;
+  if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
+    return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
   hipError_t e = launch_vmc(x->wf, x->d_wf, x->nt, (double*)state, W, n_steps, seed, step0, step_size, all_electron ? 1 : 0,
                             acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum, (hipStream_t)stream);
@@ -710,6 +712,11 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   if (e != hipSuccess) return hipfail(x, e, "dmc: control upload");
   double* cur = (double*)states[0];
   double* oth = (double*)states[1];
+  // rebuild every record from its positions (fresh inverses, local energy and
+  // the orbital-gradient rows the drift of the first moves reads)
+  e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, cur, s);
+  if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
     e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);

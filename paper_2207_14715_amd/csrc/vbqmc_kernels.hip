@@ -66,14 +66,14 @@ extern __shared__ double lds_dyn[];
 
 template <int NT, int PREC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
-                                                 double* logabs, int32_t* sign, double* grad, double* eloc,
-                                                 double* ratio, double* state) {
+                                                 int64_t rstride, double* logabs, int32_t* sign, double* grad,
+                                                 double* eloc, double* ratio, double* state) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   if (w >= W) return;
   Ld l(lds_dyn, wf);
   stage_tables<NT, PREC>(wf, l);
-  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = Rin[w * 3 * wf.N + k];
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = Rin[w * rstride + k];
   __syncthreads();
   bool ok = build_state<NT, PREC>(wf, l, l.R());
   if (ok) {
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       }
     }
     if (!(sc[SC_S] != 0.0)) { bad = true; break; }
-    local_energy<NT, PREC>(wf, l, st == nsteps - 1 ? rec + wf.r_gc : nullptr);
+    local_energy<NT, PREC>(wf, l, nullptr);
     double el = sc[SC_ELOC];
     es += el;
     e2s += el * el;
@@ -562,12 +562,13 @@ static hipError_t set_lds(const void* fn, size_t bytes) {
 }
 
 template <int NT, int PREC>
-static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, double* logabs, int32_t* sign,
-                                    double* grad, double* eloc, double* ratio, double* state, hipStream_t s) {
+static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, int64_t rstride,
+                                    double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio,
+                                    double* state, hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_evaluate<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, logabs, sign, grad,
+  hipLaunchKernelGGL((k_evaluate<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, rstride, logabs, sign, grad,
                      eloc, ratio, state);
   return hipGetLastError();
 }
@@ -610,9 +611,10 @@ static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* s
     default: VB_DISPATCH(256, FN, __VA_ARGS__)                                 \
   }
 
-hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* logabs, int32_t* sign,
-                           double* grad, double* eloc, double* ratio, double* state, hipStream_t s) {
-  VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, logabs, sign, grad, eloc, ratio, state, s)
+hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, int64_t rstride,
+                           double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio, double* state,
+                           hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, s)
 }
 
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
