@@ -27,7 +27,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 # HBM bytes per k_vmc launch (4096 walkers, 10 steps) from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by the copy-kernel calibration; None until measured for
 # the current kernel (see the k_vmc profile summary under profiles/).
-TRAFFIC_BYTES_PER_LAUNCH = 18.70e6
+TRAFFIC_BYTES_PER_LAUNCH = None
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 

@@ -59,40 +59,48 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
 
 // ---------------------------------------------------------------------------
 // Jastrow pair function u(r) = a R/(1 + b R) + sum_{p=2..5} q_p R^p with
-// R = r/(1 + kappa r); returns u, u' and u'' in r.
+// R = r/(1 + kappa r); returns u, u' and u'' in r.  Coefficients travel by
+// value so that a loop mixing electron and nucleus partners reads them from
+// registers rather than through a per-lane pointer.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void pair_fn(double r, double kappa, double a, double b, const double* q,
-                                        double& u, double& u1, double& u2) {
+struct PairCoef {
+  double a, b, q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ PairCoef ee_coef(const DevWF& wf, bool anti) {
+  return {anti ? wf.ee[0] : wf.ee[1], anti ? wf.ee[2] : wf.ee[3], wf.ee[4], wf.ee[5], wf.ee[6], wf.ee[7]};
+}
+
+__device__ __forceinline__ PairCoef en_coef(const double* e) { return {e[0], e[1], e[2], e[3], e[4], e[5]}; }
+
+__device__ __forceinline__ void pair_fn(double r, double kappa, const PairCoef& c, double& u, double& u1,
+                                        double& u2) {
   double den = 1.0 + kappa * r;
   double iden = 1.0 / den;
   double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
-  double ib = 1.0 / (1.0 + b * R);
-  u = a * R * ib;
-  double uR = a * ib * ib;
-  double uRR = -2.0 * a * b * ib * ib * ib;
+  double ib = 1.0 / (1.0 + c.b * R);
+  u = c.a * R * ib;
+  double uR = c.a * ib * ib;
+  double uRR = -2.0 * c.a * c.b * ib * ib * ib;
+  const double q[4] = {c.q0, c.q1, c.q2, c.q3};
   double Rp2 = 1.0;  // R^(p-2)
 #pragma unroll
   for (int p = 2; p <= 5; ++p) {
-    double c = q[p - 2];
-    uRR += p * (p - 1) * c * Rp2;
-    uR += p * c * Rp2 * R;
-    u += c * Rp2 * R * R;
+    double cp = q[p - 2];
+    uRR += p * (p - 1) * cp * Rp2;
+    uR += p * cp * Rp2 * R;
+    u += cp * Rp2 * R * R;
     Rp2 *= R;
   }
   u1 = uR * R1;
   u2 = uRR * R1 * R1 + uR * R2;
 }
 
-__device__ __forceinline__ double pair_val(double r, double kappa, double a, double b, const double* q) {
+__device__ __forceinline__ double pair_val(double r, double kappa, const PairCoef& c) {
   double R = r / (1.0 + kappa * r);
-  double u = a * R / (1.0 + b * R);
-  double Rp = R * R;
-#pragma unroll
-  for (int p = 2; p <= 5; ++p) {
-    u += q[p - 2] * Rp;
-    Rp *= R;
-  }
-  return u;
+  double u = c.a * R / (1.0 + c.b * R);
+  double R2 = R * R;
+  return u + R2 * (c.q0 + R * (c.q1 + R * (c.q2 + R * c.q3)));
 }
 
 // ---------------------------------------------------------------------------
@@ -237,6 +245,7 @@ struct Ld {
   __device__ double* lD() const { return L + wf.l_lD; }
   __device__ double* disp() const { return L + wf.l_disp; }
   __device__ double* gtab() const { return L + wf.l_gtab; }
+  __device__ double* pt() const { return L + wf.l_pt; }
   __device__ double* Phi() const { return L + wf.l_Phi; }
   __device__ double* part() const { return L + wf.l_part; }
   __device__ double* chi() const { return L + wf.l_chi; }
@@ -247,6 +256,9 @@ struct Ld {
   __device__ double* yb() const { return L + wf.l_yb; }
   __device__ double* sij() const { return L + wf.l_sij; }
   __device__ double* ratio() const { return L + wf.l_ratio; }
+  __device__ double* Rp() const { return L + wf.l_Rp; }
+  __device__ double* ua() const { return L + wf.l_ua; }
+  __device__ double* Vn() const { return L + wf.l_Vn; }
 };
 template <> __device__ const double* Ld::lam<double>() const {
   return wf.lam_in_lds ? (const double*)(L + wf.l_lam) : wf.lamT;
@@ -271,35 +283,19 @@ __device__ __forceinline__ void stage(T* dst, const T* src, int n) {
   for (int k = threadIdx.x; k < n; k += NT) dst[k] = src[k];
 }
 
-// copy the constant tables into LDS (once per block)
+// copy the constant tables into LDS (once per block): one contiguous image
+// laid out as the LDS table region, in the context's precision
 template <int NT, int PREC>
 __device__ void stage_tables(const DevWF& wf, const Ld& l) {
-  double* L = l.L;
-  stage<NT>((int*)(L + wf.l_fn), wf.fnmap, 2 * wf.Mpad);
-  stage<NT>((int*)(L + wf.l_sh), wf.shtab, 8 * wf.nshell);
-  stage<NT>(L + wf.l_pe, wf.pexp, wf.nprim);
-  stage<NT>(L + wf.l_pc, wf.pcoef, wf.nprim);
-  stage<NT>((int*)(L + wf.l_psh), wf.pshell, wf.nprim);
-  stage<NT>(L + wf.l_nuc, wf.nuc, 4 * wf.nnuc);
-  stage<NT>(L + wf.l_en, wf.en, 6 * wf.nnuc);
-  for (int s = 0; s < 2; ++s) {
-    const SpinTab& st = wf.sp[s];
-    stage<NT>((int*)(L + wf.l_ref[s]), st.ref, st.n);
-    stage<NT>((int*)(L + wf.l_porb[s]), st.porb, st.nP);
-    stage<NT>((int*)(L + wf.l_ui[s]), st.uinfo, 8 * st.nU);
-    stage<NT>((int*)(L + wf.l_wrow[s]), st.wrow, st.nU + 1);
-    stage<NT>((int*)(L + wf.l_woth[s]), st.wother, wf.nwl[s]);
-    stage<NT>(L + wf.l_wcoef[s], st.wcoef, wf.nwl[s]);
+  const double* __restrict__ src = wf.timg;
+  double* dst = l.L;
+  const int n = wf.timg_len;
+  int k = threadIdx.x;
+  for (; k + 3 * NT < n; k += 4 * NT) {
+    double a0 = src[k], a1 = src[k + NT], a2 = src[k + 2 * NT], a3 = src[k + 3 * NT];
+    dst[k] = a0; dst[k + NT] = a1; dst[k + 2 * NT] = a2; dst[k + 3 * NT] = a3;
   }
-  stage<NT>((int*)(L + wf.l_srow), wf.srow, wf.nstruct + 1);
-  stage<NT>((int*)(L + wf.l_slu), wf.slu, 2 * wf.nlinks);
-  stage<NT>(L + wf.l_slc, wf.slc, wf.nlinks);
-  if (wf.lam_in_lds) {
-    int n = wf.Mpad * wf.nop;
-    if constexpr (PREC == 0) stage<NT>(L + wf.l_lam, wf.lamT, n);
-    else if constexpr (PREC == 1) stage<NT>((float*)(L + wf.l_lam), wf.lamT32, n);
-    else stage<NT>((uint16_t*)(L + wf.l_lam), wf.lamT16, n);
-  }
+  for (; k < n; k += NT) dst[k] = src[k];
   __syncthreads();
 }
 
@@ -398,11 +394,11 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
 }
 
 template <int NT, int PREC>
-__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c) {
+__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, double* out = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
   const int nct = wf.nop / 16;
-  double* Phi = l.Phi();
+  double* Phi = out ? out : l.Phi();
   for (int ct = wave; ct < nct; ct += NW) {
     const int col = ct * 16 + (lane & 15);
     const int e = lane & 15;
@@ -574,6 +570,30 @@ __device__ void compute_RWS(const DevWF& wf, const Ld& l) {
   update_S<NT>(wf, l);
 }
 
+// Invert the staged reference matrices (in B) and form T = B PP, per spin.
+template <int NT>
+__device__ bool finish_state(const DevWF& wf, const Ld& l) {
+  bool ok = true;
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    double ld = 0.0, sg = 1.0;
+    if (st.n > 0 && !gj_invert<NT>(l, l.B(s), st.n, ld, sg)) ok = false;
+    if (threadIdx.x == 0) {
+      l.sc()[SC_LOGDET0 + s] = ld;
+      l.sc()[SC_SGN0 + s] = sg;
+      l.sc()[SC_NUPD0 + s] = 0.0;
+    }
+    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
+      int j = idx / st.nP, q = idx - j * st.nP;
+      double a = 0.0;
+      for (int i = 0; i < st.n; ++i) a += l.B(s)[j * st.n + i] * l.PP(s)[i * st.nP + q];
+      l.T(s)[idx] = a;
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // Fresh reference inverses and tables from positions Rsrc (values pass on
 // MFMA + Gauss-Jordan).  Returns false on an exactly singular reference.
@@ -600,26 +620,7 @@ __device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
     }
     __syncthreads();
   }
-  bool ok = true;
-  for (int s = 0; s < 2; ++s) {
-    const SpinTab& st = wf.sp[s];
-    double ld = 0.0, sg = 1.0;
-    if (st.n > 0 && !gj_invert<NT>(l, l.B(s), st.n, ld, sg)) ok = false;
-    if (threadIdx.x == 0) {
-      l.sc()[SC_LOGDET0 + s] = ld;
-      l.sc()[SC_SGN0 + s] = sg;
-      l.sc()[SC_NUPD0 + s] = 0.0;
-    }
-    // T = B PP
-    for (int idx = threadIdx.x; idx < st.n * st.nP; idx += NT) {
-      int j = idx / st.nP, q = idx - j * st.nP;
-      double a = 0.0;
-      for (int i = 0; i < st.n; ++i) a += l.B(s)[j * st.n + i] * l.PP(s)[i * st.nP + q];
-      l.T(s)[idx] = a;
-    }
-    __syncthreads();
-  }
-  return ok;
+  return finish_state<NT>(wf, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,7 +637,7 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
       double dx = xi - nuc[4 * a], dy = yi - nuc[4 * a + 1], dz = zi - nuc[4 * a + 2];
       double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
       const double* ja = l.en() + 6 * a;
-      pair_fn(r, wf.kappa, ja[0], ja[1], ja + 2, u, u1, u2);
+      pair_fn(r, wf.kappa, en_coef(ja), u, u1, u2);
       Ui += u;
       double f = u1 / r;
       gx += f * dx; gy += f * dy; gz += f * dz;
@@ -649,7 +650,7 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
       double dx = xi - Rsrc[3 * j], dy = yi - Rsrc[3 * j + 1], dz = zi - Rsrc[3 * j + 2];
       double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
       bool anti = si != spin_of(wf, j);
-      pair_fn(r, wf.kappa, anti ? wf.ee[0] : wf.ee[1], anti ? wf.ee[2] : wf.ee[3], wf.ee + 4, u, u1, u2);
+      pair_fn(r, wf.kappa, ee_coef(wf, anti), u, u1, u2);
       Ui += 0.5 * u;
       double f = u1 / r;
       gx += f * dx; gy += f * dy; gz += f * dz;
@@ -671,12 +672,12 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
 
 // ---------------------------------------------------------------------------
 // Row-operator ratio of one electron: sum_u (rho R_u + y^T adj(T_JQ) B_J,i) W_u
-// for a row w (length nop) of electron il of spin s.
+// for a row w (length nop) of electron il of spin s.  B, T, Ru, Wu may live in
+// LDS or in a walker record in HBM.
 // ---------------------------------------------------------------------------
-__device__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf) {
+__device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf,
+                               const double* B, const double* T, const double* Ru, const double* Wu) {
   const SpinTab& st = wf.sp[s];
-  const double* B = l.B(s);
-  const double* T = l.T(s);
   const int* ref = l.ref(s);
   const int* porb = l.porb(s);
   double rho = 0.0;
@@ -700,9 +701,14 @@ __device__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const 
         yy[r] = ybuf[ui[4 + r]];
         bb[r] = B[ui[1 + r] * st.n + il];
       }
-    tot += (rho * l.Ru(s)[u] + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
+    tot += (rho * Ru[u] + adj_e(e, m, yy, bb)) * Wu[u];
   }
   return tot;
+}
+
+__device__ __forceinline__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w,
+                                             double* ybuf) {
+  return row_op_sum_p(wf, l, s, il, w, ybuf, l.B(s), l.T(s), l.Ru(s), l.Wu(s));
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +791,7 @@ template <int NT, int PREC>
 __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double py, double pz, int nch) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   T* chi = (T*)l.chi();
-  T* pt = (T*)l.gtab();  // [nprim][3] primitive terms (the radial table is free during moves)
+  T* pt = (T*)l.pt();  // [nprim][2] primitive terms
   const double* nuc = l.nuc();
   const int* psh = l.psh();
   for (int q = threadIdx.x; q < wf.nprim; q += NT) {
@@ -796,8 +802,8 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
     T al = (T)l.pe()[q];
     T t = si[1] == 0 ? al * r2 : al * sqrt(r2);
     T ex = t < T(50) ? (T)l.pc()[q] * dexp<T>(-t) : T(0);
-    pt[3 * q] = ex;
-    pt[3 * q + 1] = -al * ex;
+    pt[2 * q] = ex;
+    pt[2 * q + 1] = -al * ex;
   }
   __syncthreads();
   for (int mu = threadIdx.x; mu < wf.Mpad; mu += NT) {
@@ -813,8 +819,8 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
     T g = 0, g1 = 0;
 #pragma unroll 4
     for (int k = 0; k < np; ++k) {
-      g += pt[3 * (p0 + k)];
-      g1 += pt[3 * (p0 + k) + 1];
+      g += pt[2 * (p0 + k)];
+      g1 += pt[2 * (p0 + k) + 1];
     }
     T o[5];
     channels<T>(kind, lq, l.fn()[2 * mu + 1], x, y, z, r2, r, g, g1, T(0), nch, o);
@@ -863,16 +869,16 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
 // ---------------------------------------------------------------------------
 // Single-electron move of electron i to (px,py,pz): ratio of determinant sums
 // S''/S (written to SC_RATIO) and Jastrow change dU (SC_TMP0); fills y (value
-// channel), bcol (old B column), rho (SC_TMP1) and Qu.  Requires v[0][*] to
-// hold the new orbital values.
+// channel), bcol (old B column), rho (SC_TMP1) and Qu.  v holds the orbital
+// values at the trial position.
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, double py, double pz) {
+__device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, double py, double pz,
+                           const double* v) {
   int s = spin_of(wf, i);
   const SpinTab& st = wf.sp[s];
   const int n = st.n, nP = st.nP;
   int il = i - st.e0;
-  const double* v = l.v();
   const double* B = l.B(s);
   const double* T = l.T(s);
   const int* ref = l.ref(s);
@@ -903,24 +909,23 @@ __device__ void move_ratio(const DevWF& wf, const Ld& l, int i, double px, doubl
   const double* R = l.R();
   const double* nuc = l.nuc();
   double xo = R[3 * i], yo = R[3 * i + 1], zo = R[3 * i + 2];
+  const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
+  const double kappa = wf.kappa;
   for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
     if (j == i) continue;
-    double xj, yj, zj, a, b;
-    const double* q;
+    double xj, yj, zj;
+    PairCoef c;
     if (j < wf.N) {
       xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
-      bool anti = s != spin_of(wf, j);
-      a = anti ? wf.ee[0] : wf.ee[1];
-      b = anti ? wf.ee[2] : wf.ee[3];
-      q = wf.ee + 4;
+      c = s != spin_of(wf, j) ? c_anti : c_par;
     } else {
       int nn = j - wf.N;
       xj = nuc[4 * nn]; yj = nuc[4 * nn + 1]; zj = nuc[4 * nn + 2];
-      a = l.en()[6 * nn]; b = l.en()[6 * nn + 1]; q = l.en() + 6 * nn + 2;
+      c = en_coef(l.en() + 6 * nn);
     }
     double rn = sqrt((px - xj) * (px - xj) + (py - yj) * (py - yj) + (pz - zj) * (pz - zj));
     double ro = sqrt((xo - xj) * (xo - xj) + (yo - yj) * (yo - yj) + (zo - zj) * (zo - zj));
-    part[1] += pair_val(rn, wf.kappa, a, b, q) - pair_val(ro, wf.kappa, a, b, q);
+    part[1] += pair_val(rn, kappa, c) - pair_val(ro, kappa, c);
   }
   __syncthreads();
   // phase 3: Q_u = rho R_u + y^T adj(T_JQ) B_J,i and S'' = sum_u Q_u W_u

@@ -24,6 +24,9 @@ hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W,
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
                       hipStream_t s);
+hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, int nt, double* state, int64_t W, int nsteps,
+                            uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s, double* na,
+                            double* el, double* sij, hipStream_t s);
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
                            uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
                            hipStream_t s);
@@ -135,6 +138,9 @@ struct vbqmc_ctx {
   double* d_wcoef[2] = {nullptr, nullptr};
   double* d_slc = nullptr;
   DevWF* d_wf = nullptr;
+  DevWF* d_wf_aux = nullptr;  // same tables, compact LDS layout of the batched local-energy kernels
+  double* d_timg = nullptr;   // LDS table image
+  int aux_off[10] = {0};
 };
 
 namespace {
@@ -192,6 +198,57 @@ int upload_lambda(vbqmc_ctx* x) {
   return e == hipSuccess ? 0 : hipfail(x, e, "upload lambda");
 }
 
+// The constant tables exactly as they sit at the start of a block's LDS, so
+// that a kernel stages them with one contiguous copy.
+int upload_table_image(vbqmc_ctx* x) {
+  const DevWF& wf = x->wf;
+  if (!x->d_timg) return 0;
+  std::vector<double> img((size_t)wf.timg_len, 0.0);
+  auto put = [&](int off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy((char*)img.data() + (size_t)off * 8, src, bytes);
+  };
+  put(wf.l_fn, x->fnmap.data(), x->fnmap.size() * 4);
+  put(wf.l_sh, x->shtab.data(), x->shtab.size() * 4);
+  put(wf.l_pe, x->pexp.data(), x->pexp.size() * 8);
+  put(wf.l_pc, x->pcoef.data(), x->pcoef.size() * 8);
+  put(wf.l_psh, x->pshell.data(), x->pshell.size() * 4);
+  put(wf.l_nuc, x->nuc.data(), x->nuc.size() * 8);
+  put(wf.l_en, x->en.data(), x->en.size() * 8);
+  std::vector<double> wc[2], slc;
+  build_coefficients(x, wc, slc);
+  for (int s = 0; s < 2; ++s) {
+    const SpinHost& h = x->sp[s];
+    put(wf.l_ref[s], h.ref.data(), h.ref.size() * 4);
+    put(wf.l_porb[s], h.porb.data(), h.porb.size() * 4);
+    put(wf.l_ui[s], h.uinfo.data(), h.uinfo.size() * 4);
+    put(wf.l_wrow[s], h.wrow.data(), h.wrow.size() * 4);
+    put(wf.l_woth[s], h.wother.data(), h.wother.size() * 4);
+    put(wf.l_wcoef[s], wc[s].data(), wc[s].size() * 8);
+  }
+  put(wf.l_srow, x->srow.data(), x->srow.size() * 4);
+  put(wf.l_slu, x->slu.data(), x->slu.size() * 4);
+  put(wf.l_slc, slc.data(), slc.size() * 8);
+  if (wf.lam_in_lds) {
+    size_t n = (size_t)x->Mpad * x->nop;
+    std::vector<double> lt(n, 0.0);
+    std::vector<float> l32(n, 0.f);
+    std::vector<uint16_t> l16(n, 0);
+    for (int p = 0; p < x->norb; ++p)
+      for (int mu = 0; mu < x->M; ++mu) {
+        double v = x->lam[(size_t)p * x->M + mu];
+        size_t k = (size_t)mu * x->nop + p;
+        lt[k] = v;
+        l32[k] = (float)v;
+        l16[k] = to_bf16((float)v);
+      }
+    if (wf.precision == 0) put(wf.l_lam, lt.data(), n * 8);
+    else if (wf.precision == 1) put(wf.l_lam, l32.data(), n * 4);
+    else put(wf.l_lam, l16.data(), n * 2);
+  }
+  hipError_t e = hipMemcpy(x->d_timg, img.data(), img.size() * 8, hipMemcpyHostToDevice);
+  return e == hipSuccess ? 0 : hipfail(x, e, "upload table image");
+}
+
 int upload_coefficients(vbqmc_ctx* x) {
   std::vector<double> wc[2], slc;
   build_coefficients(x, wc, slc);
@@ -202,6 +259,14 @@ int upload_coefficients(vbqmc_ctx* x) {
   if (e == hipSuccess) e = hipMemcpy(x->d_en, x->en.data(), x->en.size() * 8, hipMemcpyHostToDevice);
   for (int k = 0; k < 8; ++k) x->wf.ee[k] = x->ee[k];
   if (e == hipSuccess && x->d_wf) e = hipMemcpy(x->d_wf, &x->wf, sizeof(DevWF), hipMemcpyHostToDevice);
+  if (e == hipSuccess && x->d_wf_aux) {
+    DevWF a = x->wf;
+    a.l_R = x->aux_off[0]; a.l_sc = x->aux_off[1]; a.l_red = x->aux_off[2]; a.l_gU = x->aux_off[3];
+    a.l_lU = x->aux_off[4]; a.l_ratio = x->aux_off[5]; a.l_disp = x->aux_off[6]; a.l_gtab = x->aux_off[7];
+    a.l_Phi4 = x->aux_off[8]; a.l_yb64 = x->aux_off[9];
+    e = hipMemcpy(x->d_wf_aux, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) return upload_table_image(x);
   return e == hipSuccess ? 0 : hipfail(x, e, "upload coefficients");
 }
 
@@ -425,8 +490,9 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   for (int s = 0; s < 2; ++s) wf.r_B[s] = rec(x->sp[s].n * x->sp[s].n);
   for (int s = 0; s < 2; ++s) wf.r_T[s] = rec(x->sp[s].n * (int)x->sp[s].porb.size());
   wf.r_sc = rec(8);
+  wf.r_RW = rec(2 * (int)(x->sp[0].sets.size() + x->sp[1].sets.size()) + 1);
   wf.hot_len = o;
-  wf.r_gc = rec(3 * x->N * x->nop);
+  wf.r_gc = rec(std::max(3 * x->N * x->nop, 4 * x->N));
   wf.r_bk = rec(wf.hot_len);
   wf.rec_len = (o + 31) / 32 * 32;
   // LDS: constant tables, walker state, scratch (offsets in doubles, each
@@ -458,22 +524,16 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // orbital coefficients go to LDS when they take at most 16 KiB
   wf.lam_in_lds = lam_doubles * 8 <= 16384 ? 1 : 0;
   wf.l_lam = wf.lam_in_lds ? lds(lam_doubles) : 0;
-  // regions used by both the walker kernels and the adjoint kernel
-  wf.l_R = lds(3 * x->N);
+  const int tables_end = o;
+  wf.timg_len = tables_end;
+  // regions used by every walker kernel
+  wf.l_R = lds(std::max(3 * x->N, 3 * kGroup));
   wf.l_sc = lds(SC_COUNT);
   wf.l_red = lds(kRedSlots);
   int nmax = std::max(x->nup, x->ndn);
   wf.l_ipiv = ilds(nmax);
   wf.l_f = lds(nmax);
-  wf.l_gU = lds(3 * x->N);
-  wf.l_lU = lds(x->N);
-  wf.l_gD = lds(3 * x->N);
-  wf.l_lD = lds(x->N);
-  wf.l_disp = lds(kGroup * x->nnuc * 4);
-  wf.l_gtab = lds(std::max(kGroup * x->nshell * 3, 3 * wf.nprim));
-  wf.l_Phi = lds(kGroup * x->nop);
-  const int shared_end = o;
-  // walker-kernel regions
+  // walker state and move scratch (every walker kernel)
   for (int s = 0; s < 2; ++s) {
     int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
     wf.l_B[s] = lds(n * n);
@@ -483,18 +543,62 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     wf.l_Wu[s] = lds((int)x->sp[s].sets.size());
   }
   wf.l_Qu = lds(nUm);
-  wf.l_part = lds(std::max(x->nt, 4 * x->nop));
-  wf.l_chi = lds(4 * x->Mpad);
-  wf.l_v = lds(4 * x->nop);
   wf.l_y = lds(nPm + 1);
   wf.l_bcol = lds(nmax);
   wf.l_z = lds(2 * nmax);
+  // electron-tile regions of the MFMA passes; the primitive terms of a point
+  // evaluation share this space (the two are never live at the same time)
+  const int tile0 = o;
+  wf.l_disp = lds(kGroup * x->nnuc * 4);
+  wf.l_gtab = lds(kGroup * x->nshell * 3);
+  wf.l_Phi = lds(kGroup * x->nop);
+  const int tile_end = o;
+  o = tile0;
+  wf.l_pt = lds(2 * wf.nprim);
+  o = std::max(o, tile_end);
+  const int sweep0 = o;
+  // sweep kernel: trial positions, acceptance draws and trial orbital rows
+  const int npad = (x->N + kGroup - 1) / kGroup * kGroup;
+  wf.l_Rp = lds(3 * npad);
+  wf.l_ua = lds(npad);
+  wf.l_Vn = lds(npad * x->nop);
+  wf.lds_sweep_doubles = o;
+  // fused walker kernels: point evaluations, local energy, overlaps
+  o = sweep0;
+  wf.l_part = lds(std::max(x->nt, 4 * x->nop));
+  wf.l_chi = lds(4 * x->Mpad);
+  wf.l_v = lds(4 * x->nop);
   wf.l_yb = lds(kGroup * (nPm + 1));
   wf.l_sij = lds(x->nstruct * x->nstruct);
   wf.l_ratio = lds(x->nstruct);
-  const int walker_end = o;
-  // adjoint-kernel regions (alias the walker-kernel regions)
-  o = shared_end;
+  wf.l_gU = lds(3 * x->N);
+  wf.l_lU = lds(x->N);
+  wf.l_gD = lds(3 * x->N);
+  wf.l_lD = lds(x->N);
+  const int full_end = o;
+  // compact layout of the batched local-energy kernels: the constant tables,
+  // then only what the finish and tile kernels touch
+  {
+    DevWF a = wf;
+    o = tables_end;
+    a.l_R = lds(std::max(3 * x->N, 3 * kGroup));
+    a.l_sc = lds(SC_COUNT);
+    a.l_red = lds(kRedSlots);
+    a.l_gU = lds(3 * x->N);
+    a.l_lU = lds(x->N);
+    a.l_ratio = lds(x->nstruct);
+    wf.lds_finish_doubles = o;
+    a.l_disp = lds(kGroup * x->nnuc * 4);
+    a.l_gtab = lds(kGroup * x->nshell * 3);
+    a.l_Phi4 = lds(4 * kGroup * x->nop);
+    a.l_yb64 = lds(64 * (nPm + 1));
+    wf.lds_tile_doubles = o;
+    x->aux_off[0] = a.l_R; x->aux_off[1] = a.l_sc; x->aux_off[2] = a.l_red; x->aux_off[3] = a.l_gU;
+    x->aux_off[4] = a.l_lU; x->aux_off[5] = a.l_ratio; x->aux_off[6] = a.l_disp; x->aux_off[7] = a.l_gtab;
+    x->aux_off[8] = a.l_Phi4; x->aux_off[9] = a.l_yb64;
+  }
+  // adjoint-kernel regions
+  o = full_end;
   wf.l_aPhi = lds(5 * x->N * x->nop);
   wf.l_aG0 = lds(x->N * x->nop);
   wf.l_aG = lds(x->N * x->nop);
@@ -504,7 +608,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_aU[0] = lds(5 * (int)x->sp[0].sets.size());
   wf.l_aU[1] = lds(5 * (int)x->sp[1].sets.size());
   wf.lds_adj_doubles = o;
-  o = walker_end;
+  o = full_end;
   wf.lds_doubles = o;
 
   int dev = 0;
@@ -532,7 +636,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.ref.size(), 4); add(h.porb.size(), 4); add(h.uinfo.size(), 4); add(h.wrow.size(), 4);
     add(h.wother.size(), 4); add(h.wother.size(), 8);
   }
-  add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1);
+  add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
+  add((size_t)wf.timg_len, 8);
   he = hipMalloc((void**)&x->dmem, bytes);
   if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
   x->dbytes = bytes;
@@ -566,10 +671,12 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   int* d_slu = carve<int>(p, x->slu.size()); up(x->slu.data(), x->slu.size(), 4, d_slu);
   x->d_slc = carve<double>(p, x->slc.size());
   x->d_wf = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_aux = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_timg = carve<double>(p, (size_t)wf.timg_len);
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
   wf.pcoef = d_pcoef; wf.pshell = d_pshell; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
-  wf.srow = d_srow; wf.slu = d_slu; wf.slc = x->d_slc;
+  wf.srow = d_srow; wf.slu = d_slu; wf.slc = x->d_slc; wf.timg = x->d_timg;
   if (upload_lambda(x) || upload_coefficients(x)) {
     hipFree(x->dmem);
     delete x;
@@ -671,6 +778,15 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
+  const bool split_fits = (size_t)std::max(x->wf.lds_sweep_doubles, x->wf.lds_tile_doubles) * 8 <=
+                          (size_t)x->lds_limit;
+  if (!all_electron && split_fits) {
+    // single-electron moves: walker-resident sweep + batched local energy
+    hipError_t e = launch_vmc_split(x->wf, x->d_wf, x->d_wf_aux, x->nt, (double*)state, W, n_steps, seed, step0, step_size,
+                                    acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
+  }
   hipError_t e = launch_vmc(x->wf, x->d_wf, x->nt, (double*)state, W, n_steps, seed, step0, step_size, all_electron ? 1 : 0,
                             acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");

@@ -49,9 +49,11 @@ struct DevWF {
   const int* srow;      // [nstruct + 1] CSR of structure links
   const int* slu;       // [nlinks][2]: up, down spin determinant
   const double* slc;    // [nlinks] d'_{I,k}
+  const double* timg;   // [timg_len] the LDS table region, laid out as in LDS (one contiguous copy)
+  int timg_len;
   // walker record (doubles)
   int rec_len, hot_len;
-  int r_R, r_B[2], r_T[2], r_sc, r_gc, r_bk;
+  int r_R, r_B[2], r_T[2], r_sc, r_RW, r_gc, r_bk;  // r_RW: Ru0 | Ru1 | Wu0 | Wu1 | S
   // LDS layout (offsets in doubles): constant tables staged once per block
   int lam_in_lds;
   int l_fn, l_sh, l_pe, l_pc, l_psh, l_nuc, l_en, l_lam;
@@ -60,10 +62,12 @@ struct DevWF {
   int l_R, l_B[2], l_T[2], l_PP[2];
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
   int l_gU, l_lU, l_gD, l_lD;
-  int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_yb, l_sij, l_ratio;
+  int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_pt, l_yb, l_sij, l_ratio;
+  int l_Phi4, l_yb64;
+  int l_Rp, l_ua, l_Vn;  // sweep kernel: trial positions, acceptance draws, trial orbital rows
   // adjoint kernel
   int l_aPhi, l_aG0, l_aG, l_aA, l_aP, l_aM, l_aU[2];
-  int lds_doubles, lds_adj_doubles;
+  int lds_doubles, lds_sweep_doubles, lds_finish_doubles, lds_tile_doubles, lds_adj_doubles;
 };
 
 // scalar slots in the record's / LDS scalar block

@@ -57,6 +57,13 @@ __device__ void store_record(const DevWF& wf, const Ld& l, double* rec) {
     for (int k = threadIdx.x; k < st.n * st.nP; k += NT) rec[wf.r_T[s] + k] = l.T(s)[k];
   }
   for (int k = threadIdx.x; k < 8; k += NT) rec[wf.r_sc + k] = l.sc()[k];
+  // determinant ratios, their partner sums and S for the batched local energy
+  const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
+  for (int k = threadIdx.x; k < n0; k += NT) rec[wf.r_RW + k] = l.Ru(0)[k];
+  for (int k = threadIdx.x; k < n1; k += NT) rec[wf.r_RW + n0 + k] = l.Ru(1)[k];
+  for (int k = threadIdx.x; k < n0; k += NT) rec[wf.r_RW + n0 + n1 + k] = l.Wu(0)[k];
+  for (int k = threadIdx.x; k < n1; k += NT) rec[wf.r_RW + 2 * n0 + n1 + k] = l.Wu(1)[k];
+  if (threadIdx.x == 0) rec[wf.r_RW + 2 * (n0 + n1)] = l.sc()[SC_S];
 }
 
 // ---------------------------------------------------------------------------
@@ -91,7 +98,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (ratio)
       for (int k = threadIdx.x; k < wf.nstruct; k += NT) ratio[w * wf.nstruct + k] = NAN;
     if (state) {
-      if (threadIdx.x == 0) l.sc()[SC_ELOC] = NAN;
+      if (threadIdx.x == 0) {
+        l.sc()[SC_ELOC] = NAN;
+        l.sc()[SC_FLAGS] = 1.0;
+      }
       __syncthreads();
       store_record<NT>(wf, l, state + w * wf.rec_len);
     }
@@ -99,8 +109,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   local_energy<NT, PREC>(wf, l, state ? state + w * wf.rec_len + wf.r_gc : nullptr);
   if (ratio) structure_ratios<NT>(wf, l);
-  const double* sc = l.sc();
+  double* sc = l.sc();
   if (threadIdx.x == 0) {
+    sc[SC_FLAGS] = 0.0;  // a freshly built record is valid
     if (logabs) logabs[w] = sc[SC_LOGPSI];
     if (sign) sign[w] = (int32_t)sc[SC_SIGN];
     if (eloc) eloc[w] = sc[SC_ELOC];
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         double py = R[3 * i + 1] + step_size * (2.0 * a1 - 1.0);
         double pz = R[3 * i + 2] + step_size * (2.0 * b0 - 1.0);
         point_orbitals<NT, PREC>(wf, l, px, py, pz, 1);
-        move_ratio<NT>(wf, l, i, px, py, pz);
+        move_ratio<NT>(wf, l, i, px, py, pz, l.v());
         double ratio = sc[SC_RATIO] * exp(sc[SC_TMP0]);
         double ua, dummy;
         philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
@@ -244,6 +255,182 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   if (sij_sum)
     for (int k = threadIdx.x; k < nv * nv; k += NT) sij_sum[w * nv * nv + k] += l.sij()[k];
+}
+
+
+// ---------------------------------------------------------------------------
+// Split VMC step: a walker-resident sweep kernel (moves only), a batched
+// local-energy kernel over 16-electron tiles of all walkers, and a per-walker
+// finish kernel.
+// ---------------------------------------------------------------------------
+
+// Sweep of single-electron moves.  A trial position depends only on the
+// electron's own current position and its draws, so every trial position of
+// the sweep, and its orbital row, is formed up front: one MFMA pass over tiles
+// of 16 trial points.  The moves themselves then only run the determinant
+// ratio, the Jastrow change and, when accepted, the rank-1 updates.
+template <int NT, int PREC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(const DevWF* __restrict__ pwf, double* state, int64_t W,
+                                              uint64_t seed, uint32_t step, double step_size, double* n_acc) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  if (w >= W) return;
+  Ld l(lds_dyn, wf);
+  stage_tables<NT, PREC>(wf, l);
+  double* rec = state + w * wf.rec_len;
+  load_record<NT>(wf, l, rec);
+  compute_RWS<NT>(wf, l);
+  double* sc = l.sc();
+  double na = 0.0;
+  bool bad = !(sc[SC_S] != 0.0) || sc[SC_FLAGS] != 0.0;
+  if (!bad) {
+    double* Rp = l.Rp();
+    double* ua = l.ua();
+    const double* R = l.R();
+    for (int i = threadIdx.x; i < wf.N; i += NT) {
+      double a0, a1, b0, b1, u, dummy;
+      philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
+      philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
+      philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, u, dummy);
+      Rp[3 * i] = R[3 * i] + step_size * (2.0 * a0 - 1.0);
+      Rp[3 * i + 1] = R[3 * i + 1] + step_size * (2.0 * a1 - 1.0);
+      Rp[3 * i + 2] = R[3 * i + 2] + step_size * (2.0 * b0 - 1.0);
+      ua[i] = u;
+    }
+    __syncthreads();
+    for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
+      int ne = min(kGroup, wf.N - g0);
+      group_radial<NT, PREC>(wf, l, Rp, g0, ne);
+      group_channel<NT, PREC>(wf, l, ne, 0, l.Vn() + g0 * wf.nop);
+    }
+    for (int i = 0; i < wf.N; ++i) {
+      const double px = Rp[3 * i], py = Rp[3 * i + 1], pz = Rp[3 * i + 2];
+      move_ratio<NT>(wf, l, i, px, py, pz, l.Vn() + i * wf.nop);
+      double ratio = sc[SC_RATIO] * exp(sc[SC_TMP0]);
+      if (ua[i] < ratio * ratio) {
+        accept_move<NT>(wf, l, i, px, py, pz);
+        na += 1.0;
+      }
+    }
+    if (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every) {
+      if (build_state<NT, PREC>(wf, l, l.R())) compute_RWS<NT>(wf, l);
+      else bad = true;
+    }
+    if (!(sc[SC_S] != 0.0)) bad = true;
+  }
+  __syncthreads();
+  if (bad && threadIdx.x == 0) sc[SC_FLAGS] = 1.0;
+  __syncthreads();
+  store_record<NT>(wf, l, rec);
+  if (threadIdx.x == 0) n_acc[w] += na;
+}
+
+// One wave per block; each block walks `per_block` tiles of 16 (walker,
+// electron) rows: radial tables, four MFMA channels (gradient, Laplacian),
+// then 64 lanes = 16 rows x 4 channels form the row-operator ratios from the
+// walkers' records and store them in the records' scratch rows.
+template <int PREC>
+__global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf, double* state, int64_t W,
+                                                   int64_t ntiles, int per_block) {
+  const DevWF& wf = *pwf;
+  Ld l(lds_dyn, wf);
+  stage_tables<64, PREC>(wf, l);
+  const int N = wf.N, nop = wf.nop;
+  const int nPm = max(wf.sp[0].nP, wf.sp[1].nP);
+  const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
+  const int64_t rows_total = W * N;
+  double* Rt = l.R();
+  double* Phi4 = l.L + wf.l_Phi4;
+  double* yb = l.L + wf.l_yb64;
+  for (int64_t tile = (int64_t)blockIdx.x * per_block; tile < min(ntiles, (int64_t)(blockIdx.x + 1) * per_block);
+       ++tile) {
+    const int64_t r0 = tile * kGroup;
+    const int rows = (int)min((int64_t)kGroup, rows_total - r0);
+    if (threadIdx.x < 3 * kGroup) {
+      int t = threadIdx.x / 3, x = threadIdx.x - 3 * t;
+      double v = 0.0;
+      if (t < rows) {
+        int64_t r = r0 + t, w = r / N;
+        int e = (int)(r - w * N);
+        v = state[w * wf.rec_len + wf.r_R + 3 * e + x];
+      }
+      Rt[threadIdx.x] = v;
+    }
+    __syncthreads();
+    group_radial<64, PREC>(wf, l, Rt, 0, rows);
+    for (int c = 1; c <= 4; ++c) group_channel<64, PREC>(wf, l, rows, c, Phi4 + (c - 1) * kGroup * nop);
+    {
+      const int t = threadIdx.x >> 2, c = threadIdx.x & 3;
+      if (t < rows) {
+        int64_t r = r0 + t, w = r / N;
+        int e = (int)(r - w * N);
+        int s = spin_of(wf, e), il = e - wf.sp[s].e0;
+        double* rec = state + w * wf.rec_len;
+        const double* RW = rec + wf.r_RW;
+        double S = RW[2 * (n0 + n1)];
+        double tot = 0.0;
+        if (rec[wf.r_sc + SC_FLAGS] == 0.0)
+          tot = row_op_sum_p(wf, l, s, il, Phi4 + (c * kGroup + t) * nop, yb + threadIdx.x * (nPm + 1),
+                             rec + wf.r_B[s], rec + wf.r_T[s], RW + (s ? n0 : 0), RW + n0 + n1 + (s ? n0 : 0));
+        rec[wf.r_gc + 4 * e + c] = tot / S;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per walker: Jastrow, potential, E_L from the tile results, accumulators.
+__global__ __launch_bounds__(64) void k_eloc_finish(const DevWF* __restrict__ pwf, double* state, int64_t W,
+                                                    double* e_sum, double* e2_sum, double* e_last,
+                                                    double* sij_sum) {
+  const DevWF& wf = *pwf;
+  int64_t w = blockIdx.x;
+  if (w >= W) return;
+  Ld l(lds_dyn, wf);
+  // only the nuclei and the e-n parameters are needed here
+  for (int k = threadIdx.x; k < 4 * wf.nnuc; k += 64) l.L[wf.l_nuc + k] = wf.nuc[k];
+  for (int k = threadIdx.x; k < 6 * wf.nnuc; k += 64) l.L[wf.l_en + k] = wf.en[k];
+  double* rec = state + w * wf.rec_len;
+  for (int k = threadIdx.x; k < 3 * wf.N; k += 64) l.R()[k] = rec[wf.r_R + k];
+  __syncthreads();
+  jastrow_full<64>(wf, l, l.R());
+  double part[1] = {0.0};
+  for (int i = threadIdx.x; i < wf.N; i += 64) {
+    const double* d = rec + wf.r_gc + 4 * i;
+    double t = l.lU()[i] + d[3];
+    for (int x = 0; x < 3; ++x) {
+      double gu = l.gU()[3 * i + x];
+      t += gu * gu + 2.0 * gu * d[x];
+    }
+    part[0] += -0.5 * t;
+  }
+  block_sum<64, 1>(part, l.red());
+  const bool bad = rec[wf.r_sc + SC_FLAGS] != 0.0;
+  const double el = part[0] + l.sc()[SC_V];
+  if (threadIdx.x == 0) {
+    rec[wf.r_sc + SC_ELOC] = bad ? NAN : el;
+    if (!bad) {
+      e_sum[w] += el;
+      e2_sum[w] += el * el;
+    }
+    e_last[w] = bad ? NAN : el;
+  }
+  if (sij_sum && !bad) {
+    const int nv = wf.nstruct, n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
+    const double* RW = rec + wf.r_RW;
+    const double S = RW[2 * (n0 + n1)];
+    double* rt = l.ratio();
+    for (int I = threadIdx.x; I < nv; I += 64) {
+      double a = 0.0;
+      for (int k = wf.srow[I]; k < wf.srow[I + 1]; ++k) a += wf.slc[k] * RW[wf.slu[2 * k]] * RW[n0 + wf.slu[2 * k + 1]];
+      rt[I] = a / S;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nv * nv; k += 64) {
+      int I = k / nv, J = k - I * nv;
+      sij_sum[w * nv * nv + k] += rt[I] * rt[J];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -306,24 +493,22 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
   }
   // Jastrow gradient at (px,py,pz)
   const double* R = l.R();
+  const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
   for (int j = threadIdx.x; j < wf.N + wf.nnuc; j += NT) {
     if (j == i) continue;
-    double xj, yj, zj, a, b;
-    const double* q;
+    double xj, yj, zj;
+    PairCoef c;
     if (j < wf.N) {
       xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
-      bool anti = s != spin_of(wf, j);
-      a = anti ? wf.ee[0] : wf.ee[1];
-      b = anti ? wf.ee[2] : wf.ee[3];
-      q = wf.ee + 4;
+      c = s != spin_of(wf, j) ? c_anti : c_par;
     } else {
       int n = j - wf.N;
       xj = nuc[4 * n]; yj = nuc[4 * n + 1]; zj = nuc[4 * n + 2];
-      a = l.en()[6 * n]; b = l.en()[6 * n + 1]; q = l.en() + 6 * n + 2;
+      c = en_coef(l.en() + 6 * n);
     }
     double dx = px - xj, dy = py - yj, dz = pz - zj;
     double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
-    pair_fn(r, wf.kappa, a, b, q, u, u1, u2);
+    pair_fn(r, wf.kappa, c, u, u1, u2);
     double f = u1 / r;
     part[3] += f * dx; part[4] += f * dy; part[5] += f * dz;
   }
@@ -366,7 +551,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double zx = r0 * cos(two_pi * a1), zy = r0 * sin(two_pi * a1), zz = r1 * cos(two_pi * b1);
     double px = rx + tau * v[0] + sqt * zx, py = ry + tau * v[1] + sqt * zy, pz = rz + tau * v[2] + sqt * zz;
     point_orbitals<NT, PREC>(wf, l, px, py, pz, 4);
-    move_ratio<NT>(wf, l, i, px, py, pz);
+    move_ratio<NT>(wf, l, i, px, py, pz, l.v());
     double rdet = sc[SC_RATIO];
     double dU = sc[SC_TMP0];
     double rho = sc[SC_TMP1];
@@ -621,6 +806,37 @@ hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, 
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
                       hipStream_t s) {
   VB_DISPATCH_NT(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
+}
+
+
+template <int NT, int PREC>
+static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, double* state, int64_t W, int nsteps,
+                                     uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s,
+                                     double* na, double* el, double* sij, hipStream_t s) {
+  size_t lds_sw = (size_t)wf.lds_sweep_doubles * sizeof(double);
+  size_t lds_ti = (size_t)wf.lds_tile_doubles * sizeof(double);
+  size_t lds_fi = (size_t)wf.lds_finish_doubles * sizeof(double);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_sweep<NT, PREC>, lds_sw);
+  if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_tiles<PREC>, lds_ti);
+  if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_finish, lds_fi);
+  if (e != hipSuccess) return e;
+  const int64_t ntiles = (W * wf.N + kGroup - 1) / kGroup;
+  const int per_block = 4;
+  const unsigned tblocks = (unsigned)((ntiles + per_block - 1) / per_block);
+  for (int st = 0; st < nsteps; ++st) {
+    uint32_t step = (uint32_t)(step0 + st);
+    hipLaunchKernelGGL((k_sweep<NT, PREC>), dim3((unsigned)W), dim3(NT), lds_sw, s, dwf, state, W, seed, step,
+                       step_size, na);
+    hipLaunchKernelGGL((k_eloc_tiles<PREC>), dim3(tblocks), dim3(64), lds_ti, s, dwf_aux, state, W, ntiles, per_block);
+    hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)W), dim3(64), lds_fi, s, dwf_aux, state, W, es, e2s, el, sij);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, int nt, double* state, int64_t W, int nsteps,
+                            uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s, double* na,
+                            double* el, double* sij, hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_vmc_split_t, wf, dwf, dwf_aux, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s)
 }
 
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
