@@ -24,45 +24,57 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
-# HBM bytes per k_vmc launch (4096 walkers, 10 steps) from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by the copy-kernel calibration; None until measured for
-# the current kernel (see the k_vmc profile summary under profiles/).
+# HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker)
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+# calibration; None until measured for the current kernel.
 TRAFFIC_BYTES_PER_LAUNCH = None
+TRAFFIC_LANES = 32
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
-def vmc_flops_per_walker_move(ctx, system, accept_rate):
-    """Algorithmic FLOPs of one VMC step of one walker (N single-electron
-    moves + one local energy), from the system's dimensions.
-
-    Counted: basis values (per primitive 4 flops + one exp; per function 2),
-    the basis->orbital contraction (2 M N_orb per row), the determinant-table
-    ratio of each move (2n + 2 n nP + 6U), the Jastrow change (2 pair
-    functions of 12 flops per partner), the Sherman-Morrison update of each
-    accepted move (4n^2 + 3 n nP + 8U), and the local energy pass (5-channel
-    basis values: per primitive 6 flops + one exp, per function 16; the
-    5-channel contraction; 4 row-operator ratios per electron of
-    2n + 2 n nP + 8U each; Jastrow gradients/Laplacians of 30 flops per pair
-    and 10 per electron)."""
+def _dims(ctx, system):
     info = ctx.info
-    N, M, norb = info["n_electrons"], info["n_basis"], info["n_orbitals"]
-    nnuc = info["n_nuclei"]
     P = sum(len(s["exps"]) for s in system["shells"])
-    spins = []
-    nP_by_spin = (info["n_table_up"], info["n_table_dn"])
-    U = (info["n_unique_up"], info["n_unique_dn"])
-    for s, n in enumerate((info["n_up"], info["n_dn"])):
-        spins.append((n, nP_by_spin[s], U[s]))
+    spins = [(info["n_up"], info["n_table_up"], info["n_unique_up"]),
+             (info["n_dn"], info["n_table_dn"], info["n_unique_dn"])]
+    return info["n_electrons"], info["n_basis"], info["n_orbitals"], info["n_nuclei"], P, spins
+
+
+def sweep_flops_per_walker_move(ctx, system, accept_rate):
+    """Algorithmic FLOPs of one sweep of one walker (N single-electron moves,
+    no local energy), from the system's dimensions.
+
+    Counted per move: basis values at the trial point (per primitive 4 flops
+    + one exp; per function 2), the basis->orbital contraction (2 M N_orb),
+    the determinant-table ratio (2n + 2 n nP + 6U) and the Jastrow change
+    (2 pair functions of 12 flops per partner); per accepted move the
+    Sherman-Morrison update (4n^2 + 3 n nP + 8U)."""
+    N, M, norb, nnuc, P, spins = _dims(ctx, system)
     total = 0.0
-    for s, (n, nP, u) in enumerate(spins):
+    for n, nP, u in spins:
         per_move = (P * (4 + EXP_FLOPS) + 2 * M) + 2 * M * norb + (2 * n + 2 * n * nP + 6 * u) \
             + (N - 1 + nnuc) * 2 * 12
         per_accept = 4 * n * n + 3 * n * nP + 8 * u
         total += n * (per_move + accept_rate * per_accept)
-        total += n * (4 * (2 * n + 2 * n * nP + 8 * u))
-    total += N * (P * (6 + EXP_FLOPS) + 16 * M) + 2 * 5 * N * M * norb
+    return total
+
+
+def measure_flops_per_walker(ctx, system):
+    """Algorithmic FLOPs of one local energy of one walker from its stored
+    inverse and table: basis gradients and Laplacians (per primitive 6 flops
+    + one exp, per function 16), their contraction (4 channels, 2 M N_orb
+    each), 4 row-operator ratios per electron (2n + 2 n nP + 8U each), the
+    Jastrow gradients and Laplacians (30 flops per pair, 10 per electron)."""
+    N, M, norb, nnuc, P, spins = _dims(ctx, system)
+    total = sum(n * 4 * (2 * n + 2 * n * nP + 8 * u) for n, nP, u in spins)
+    total += N * (P * (6 + EXP_FLOPS) + 16 * M) + 2 * 4 * N * M * norb
     total += (N * (N - 1) / 2 + N * nnuc) * 30 + 10 * N
     return total
+
+
+def vmc_flops_per_walker_move(ctx, system, accept_rate):
+    """One VMC step of one walker: a sweep and one local energy."""
+    return sweep_flops_per_walker_move(ctx, system, accept_rate) + measure_flops_per_walker(ctx, system)
 
 
 def adjoint_flops_per_gradient(ctx, system):
@@ -104,9 +116,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--walkers", type=int, default=4096)
-    ap.add_argument("--steps-per-launch", type=int, default=10,
-                    help="VMC steps per k_vmc launch (warmup and timed launches are the same size)")
+    ap.add_argument("--steps-per-launch", type=int, default=10, help="VMC steps per warmup call")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--walker-lanes", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="lanes per walker in the single-electron sweep (0: library choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
@@ -139,38 +152,45 @@ def main():
         return
     system = S.f2_shaped()
     W, step_size = args.walkers, 0.3
-    ctx = vb.Context(system, precision=args.precision)
+    ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes)
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=5)).cuda()
     state = ctx.walkers_init(R0)
     acc = ctx.new_vmc_acc(W)
     seed = 20220728
-    spl = max(1, min(args.steps_per_launch, args.steps))
-    if args.steps % spl:
-        raise SystemExit("--steps must be a multiple of --steps-per-launch")
+    spl = max(1, args.steps_per_launch)
     step = 0
-    for _ in range(0, args.warmup, spl):
-        ctx.vmc_advance(state, spl, seed, step, step_size, False, acc)
-        step += spl
+    while step < args.warmup:
+        k = min(spl, args.warmup - step)
+        ctx.vmc_advance(state, k, seed, step, step_size, False, acc)
+        step += k
     torch.cuda.synchronize()
     acc = ctx.new_vmc_acc(W)
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    launches = args.steps // spl
+    # timed region: per step one sweep (the dominant kernel, bracketed by
+    # events on the launch stream) and one measurement of E_L
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(launches):
-        ctx.vmc_advance(state, spl, seed, step, step_size, False, acc)
-        step += spl
-    ev1.record(stream)
+    for k in range(args.steps):
+        ev[2 * k].record(stream)
+        ctx.vmc_sweep(state, seed, step, step_size, acc["n_accept"])
+        ev[2 * k + 1].record(stream)
+        ctx.vmc_measure(state, acc)
+        step += 1
+    ev[2 * args.steps].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_s = ev0.elapsed_time(ev1) / 1e3
+    sweep_s = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)) / 1e3
+    measure_s = sum(ev[2 * k + 1].elapsed_time(ev[2 * k + 2]) for k in range(args.steps)) / 1e3
     moves = W * args.steps
     accept_rate = float(acc["n_accept"].sum().item()) / (moves * ctx.N)
     e_mean = float(acc["e_sum"].sum().item()) / moves
-    flops = vmc_flops_per_walker_move(ctx, system, accept_rate) * moves
-    achieved = flops / kernel_s / 1e12
+    sweep_flops = sweep_flops_per_walker_move(ctx, system, accept_rate) * W
+    measure_flops = measure_flops_per_walker(ctx, system) * W
+    sweep_avg = sweep_s / args.steps
+    achieved = sweep_flops / sweep_avg / 1e12
+    lanes = ctx.info["sweep_lanes"]
+    sweep_kernel = f"k_sweep_g<{lanes}, 0>" if lanes < 64 else "k_sweep<64, 0>"
     line = {
         "metric": "walker-moves/sec incl. E_L",
         "value": moves / wall,
@@ -187,15 +207,18 @@ def main():
         "config": {"workload": "F2-shaped diatomic VMC: 18 electrons (9 up, 9 down), 28 Gaussian basis "
                                "functions, 3 VB structures / 4 determinants, 4096 walkers, single-electron "
                                "moves of 0.3 bohr with Sherman-Morrison updates, E_L every step",
-                   "walkers": W, "electrons": ctx.N, "precision": args.precision},
+                   "walkers": W, "electrons": ctx.N, "precision": args.precision, "sweep_lanes": lanes},
         "electron_moves_per_s": moves * ctx.N / wall,
         "acceptance": accept_rate,
         "mean_eloc": e_mean,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-                     "kernel": "k_vmc", "kernel_avg_ms_per_launch": kernel_s * 1e3 / launches,
-                     "steps_per_launch": spl, "flops_per_walker_move": flops / moves,
-                     "flops_per_launch": flops / launches},
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES else None,
+                     "kernel": sweep_kernel, "kernel_avg_ms_per_launch": sweep_avg * 1e3,
+                     "flops_per_launch": sweep_flops, "walkers_per_launch": W},
+        "measure": {"kernels": "k_eloc_tiles<0> + k_eloc_finish", "avg_ms_per_step": measure_s / args.steps * 1e3,
+                    "flops_per_step": measure_flops,
+                    "achieved_tflops": measure_flops / (measure_s / args.steps) / 1e12},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(system, step_size)

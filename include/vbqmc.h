@@ -103,10 +103,16 @@ typedef struct {
  * and the basis->orbital contraction in that type with FP32 accumulation;
  * determinants, inverse refresh, determinant and structure sums in FP64).
  * refresh_every: accepted single-electron updates per spin after which the
- * reference inverse is rebuilt by a fresh factorisation (default 32). */
+ * reference inverse is rebuilt by a fresh factorisation (default 32).
+ * walker_lanes: lanes of a 64-lane wavefront given to one walker in the
+ * single-electron VMC sweep: 16 or 32 (several walkers per wavefront, if
+ * their state fits in LDS), 64 (one walker per workgroup), or 0 to let the
+ * library choose from the spin-determinant size.  Results do not depend on
+ * it beyond rounding. */
 typedef struct {
   int32_t precision;
   int32_t refresh_every;
+  int32_t walker_lanes;
 } vbqmc_options;
 
 typedef struct {
@@ -117,6 +123,7 @@ typedef struct {
   int32_t n_table_up, n_table_dn;   /* orbitals replacing reference columns */
   int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei */
   int32_t block_threads;         /* threads per walker in the walker kernels */
+  int32_t sweep_lanes;           /* lanes per walker in the single-electron sweep */
   int64_t walker_state_bytes;    /* bytes per walker record */
   int64_t lds_bytes;             /* LDS bytes per walker block */
 } vbqmc_info_t;
@@ -189,6 +196,23 @@ typedef struct {
 int vbqmc_vmc_advance(vbqmc_ctx* ctx, void* state, int64_t W, int32_t n_steps, uint64_t seed,
                       uint64_t step0, double step_size, int32_t all_electron, const vbqmc_vmc_acc* acc,
                       vbqmc_stream stream);
+
+/*
+ * The two halves of a single-electron VMC step (Sec. 2.3.1), for callers that
+ * measure E_L less often than they move.  vbqmc_vmc_sweep does the N
+ * single-electron moves of step `step` for every walker exactly as
+ * vbqmc_vmc_advance (same draws, same updates) and adds the accepted moves to
+ * n_accept [dev][W]; vbqmc_vmc_measure computes E_L (Eq. Elav) of every
+ * walker at its current configuration from its record and accumulates it
+ * into acc (e_sum, e2_sum, e_last and, if set, sij_sum; n_accept is not
+ * used).  vbqmc_vmc_advance with all_electron = 0 equals, per step, a sweep
+ * followed by a measure.  Both need the system to fit the sweep and
+ * local-energy kernels (EINVAL otherwise, where vbqmc_vmc_advance still
+ * runs); state [dev] is any record written by this library.
+ */
+int vbqmc_vmc_sweep(vbqmc_ctx* ctx, void* state, int64_t W, uint64_t seed, uint64_t step, double step_size,
+                    double* n_accept, vbqmc_stream stream);
+int vbqmc_vmc_measure(vbqmc_ctx* ctx, void* state, int64_t W, const vbqmc_vmc_acc* acc, vbqmc_stream stream);
 
 /* DMC per-step records, each [dev][n_steps]: population before branching,
  * sum of weights, sum of weight * E_L, trial energy used, accepted and

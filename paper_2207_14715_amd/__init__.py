@@ -48,7 +48,8 @@ class _Wavefunction(ctypes.Structure):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("refresh_every", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
+                ("walker_lanes", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -57,7 +58,8 @@ class _Info(ctypes.Structure):
                 ("n_structures", ctypes.c_int32), ("n_determinants", ctypes.c_int32),
                 ("n_unique_up", ctypes.c_int32), ("n_unique_dn", ctypes.c_int32), ("n_table_up", ctypes.c_int32),
                 ("n_table_dn", ctypes.c_int32), ("n_params", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("walker_state_bytes", ctypes.c_int64),
+                ("block_threads", ctypes.c_int32), ("sweep_lanes", ctypes.c_int32),
+                ("walker_state_bytes", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int64)]
 
 
@@ -75,7 +77,8 @@ _lib = None
 
 EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info", "vbqmc_set_params",
            "vbqmc_get_params", "vbqmc_evaluate", "vbqmc_walkers_init", "vbqmc_walkers_positions",
-           "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance",
+           "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_vmc_sweep", "vbqmc_vmc_measure",
+           "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance",
            "vbqmc_param_grad_workspace_bytes", "vbqmc_param_grad", "vbqmc_reduce_walkers",
            "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin"]
 
@@ -104,6 +107,8 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_walkers_positions.argtypes = [vp, i64, vp, vp, vp]
     lib.vbqmc_walkers_eloc.argtypes = [vp, i64, vp, vp, vp]
     lib.vbqmc_vmc_advance.argtypes = [vp, vp, i64, i32, u64, u64, dbl, i32, ctypes.POINTER(_VmcAcc), vp]
+    lib.vbqmc_vmc_sweep.argtypes = [vp, vp, i64, u64, u64, dbl, vp, vp]
+    lib.vbqmc_vmc_measure.argtypes = [vp, vp, i64, ctypes.POINTER(_VmcAcc), vp]
     lib.vbqmc_dmc_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.vbqmc_dmc_advance.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i64, i32, u64, u64, dbl,
                                       ctypes.POINTER(dbl), i64, ctypes.POINTER(_DmcLog), vp, ctypes.c_size_t, vp]
@@ -147,7 +152,7 @@ def _check_cuda(t, name, dtype=None, shape=None):
 class Context:
     """A vbqmc context for one system dict (see the ``systems`` package)."""
 
-    def __init__(self, system, precision="fp64", refresh_every=32):
+    def __init__(self, system, precision="fp64", refresh_every=32, walker_lanes=0):
         lib = load_library()
         self._lib = lib
         self.system = system
@@ -188,7 +193,8 @@ class Context:
         wfc = _Wavefunction(len(sh), _ip(cen), _ip(kind), _ip(ls), _ip(npr), _dp(pe), _dp(pc), lam.shape[0],
                             _dp(lam), len(st), _dp(c), len(ts), _ip(ts), _ip(tc), _ip(to), float(jas["kappa"]),
                             ee_arr, _dp(en))
-        opt = _Options(_PREC[precision] if isinstance(precision, str) else int(precision), int(refresh_every))
+        opt = _Options(_PREC[precision] if isinstance(precision, str) else int(precision), int(refresh_every),
+                       int(walker_lanes))
         h = ctypes.c_void_p()
         rc = lib.vbqmc_create(ctypes.byref(sysc), ctypes.byref(wfc), ctypes.byref(opt), ctypes.byref(h))
         if rc != 0:
@@ -273,6 +279,22 @@ class Context:
         self._rc(self._lib.vbqmc_vmc_advance(self._h, _ptr(state), W, int(n_steps), ctypes.c_uint64(seed),
                                              ctypes.c_uint64(step0), float(step_size), 1 if all_electron else 0,
                                              ctypes.byref(a), _stream()))
+        return acc
+
+    def vmc_sweep(self, state, seed, step, step_size, n_accept, W=None):
+        """One sweep of single-electron moves of every walker (no E_L)."""
+        W = state.shape[0] if W is None else W
+        import torch
+        _check_cuda(n_accept, "n_accept", torch.float64, (W,))
+        self._rc(self._lib.vbqmc_vmc_sweep(self._h, _ptr(state), W, ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                           float(step_size), _ptr(n_accept), _stream()))
+
+    def vmc_measure(self, state, acc, W=None):
+        """E_L of every walker from its record, accumulated into acc."""
+        W = state.shape[0] if W is None else W
+        a = _VmcAcc(acc["e_sum"].data_ptr(), acc["e2_sum"].data_ptr(), acc["n_accept"].data_ptr(),
+                    acc["e_last"].data_ptr(), acc["sij_sum"].data_ptr() if acc.get("sij_sum") is not None else None)
+        self._rc(self._lib.vbqmc_vmc_measure(self._h, _ptr(state), W, ctypes.byref(a), _stream()))
         return acc
 
     def dmc_workspace(self, capacity, n_steps, device="cuda"):

@@ -307,11 +307,11 @@ __device__ void stage_tables(const DevWF& wf, const Ld& l) {
 // tables and contracts it with lambda^T, one 16x16 output tile at a time,
 // writing Phi[e][p] (FP64) for channel c.
 // ---------------------------------------------------------------------------
-template <int NT, int PREC>
+template <int NT, int PREC, int GS = 3>
 __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   T* disp = (T*)l.disp();  // [16][nnuc][4]: x, y, z, r2
-  T* gt = (T*)l.gtab();    // [16][nshell][3]: g, g1, g2
+  T* gt = (T*)l.gtab();    // [16][nshell][GS]: g (and g1, g2 when GS = 3)
   for (int idx = threadIdx.x; idx < kGroup * wf.nnuc; idx += NT) {
     int e = idx / wf.nnuc, a = idx - e * wf.nnuc;
     T x = 0, y = 0, z = 0;
@@ -336,19 +336,25 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
         if (t < T(50)) {
           T ex = (T)l.pc()[si[4] + k] * dexp<T>(-t);
           g += ex;
-          g1 -= a * ex;
-          g2 += a * a * ex;
+          if constexpr (GS == 3) {
+            g1 -= a * ex;
+            g2 += a * a * ex;
+          }
         }
       }
     }
-    gt[3 * idx] = g; gt[3 * idx + 1] = g1; gt[3 * idx + 2] = g2;
+    gt[GS * idx] = g;
+    if constexpr (GS == 3) {
+      gt[3 * idx + 1] = g1;
+      gt[3 * idx + 2] = g2;
+    }
   }
   __syncthreads();
 }
 
 // basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function mu at
 // electron e of the tile, from the radial tables
-template <typename T>
+template <typename T, int GS = 3>
 __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
   const int* fn = l.fn();
   int sh = fn[2 * mu];
@@ -357,9 +363,13 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
   const int* si = l.sh() + 8 * sh;
   int kind = si[1], lq = si[2];
   const T* d = (const T*)l.disp() + 4 * (e * wf.nnuc + si[0]);
-  const T* gg = (const T*)l.gtab() + 3 * (e * wf.nshell + sh);
+  const T* gg = (const T*)l.gtab() + GS * (e * wf.nshell + sh);
   T x = d[0], y = d[1], z = d[2], r2 = d[3];
-  T g = gg[0], g1 = gg[1], g2 = gg[2];
+  T g = gg[0], g1 = T(0), g2 = T(0);
+  if constexpr (GS == 3) {
+    g1 = gg[1];
+    g2 = gg[2];
+  }
   T P, Px = T(0), Py = T(0), Pz = T(0);
   if (lq == 0) {
     P = T(1);
@@ -393,8 +403,10 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
   return Pz * g + P * fr * z;
 }
 
-template <int NT, int PREC>
-__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, double* out = nullptr) {
+// Writes rows e < nout_rows of the tile (all 16 by default).
+template <int NT, int PREC, int GS = 3>
+__device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, double* out = nullptr,
+                              int nout_rows = kGroup) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
   const int nct = wf.nop / 16;
@@ -409,26 +421,28 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
 #pragma unroll 4
       for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
         int k = k0 + (lane >> 4);
-        double a = live ? chan_value<double>(wf, l, e, k, c) : 0.0;
+        double a = live ? chan_value<double, GS>(wf, l, e, k, c) : 0.0;
         double b = lam[(size_t)k * wf.nop + col];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
       // f64 16x16x4 output: register r of lane l holds row 4r + l/16
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Phi[(4 * r + (lane >> 4)) * wf.nop + col] = acc[r];
+      for (int r = 0; r < 4; ++r)
+        if (4 * r + (lane >> 4) < nout_rows) Phi[(4 * r + (lane >> 4)) * wf.nop + col] = acc[r];
     } else if constexpr (PREC == 1) {
       const float* lam = l.lam<float>();
       v4f acc = {0, 0, 0, 0};
 #pragma unroll 4
       for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
         int k = k0 + (lane >> 4);
-        float a = live ? chan_value<float>(wf, l, e, k, c) : 0.f;
+        float a = live ? chan_value<float, GS>(wf, l, e, k, c) : 0.f;
         float b = lam[(size_t)k * wf.nop + col];
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
       }
       // f32 output: register r of lane l holds row 4(l/16) + r
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+      for (int r = 0; r < 4; ++r)
+        if (4 * (lane >> 4) + r < nout_rows) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
     } else {
       const uint16_t* lam = l.lam<uint16_t>();
       v4f acc = {0, 0, 0, 0};
@@ -437,13 +451,14 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
         v4s a, b;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          a[j] = (short)(live ? f2bf(chan_value<float>(wf, l, e, kb + j, c)) : (uint16_t)0);
+          a[j] = (short)(live ? f2bf(chan_value<float, GS>(wf, l, e, kb + j, c)) : (uint16_t)0);
           b[j] = (short)lam[(size_t)(kb + j) * wf.nop + col];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+      for (int r = 0; r < 4; ++r)
+        if (4 * (lane >> 4) + r < nout_rows) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
     }
   }
   __syncthreads();
@@ -598,13 +613,13 @@ __device__ bool finish_state(const DevWF& wf, const Ld& l) {
 // Fresh reference inverses and tables from positions Rsrc (values pass on
 // MFMA + Gauss-Jordan).  Returns false on an exactly singular reference.
 // ---------------------------------------------------------------------------
-template <int NT, int PREC>
-__device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc) {
+template <int NT, int PREC, int GS = 3>
+__device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc, double* rows = nullptr) {
+  double* Phi = rows ? rows : l.Phi();  // 16 x nop scratch rows
   for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
     int ne = min(kGroup, wf.N - g0);
-    group_radial<NT, PREC>(wf, l, Rsrc, g0, ne);
-    group_channel<NT, PREC>(wf, l, ne, 0);
-    const double* Phi = l.Phi();
+    group_radial<NT, PREC, GS>(wf, l, Rsrc, g0, ne);
+    group_channel<NT, PREC, GS>(wf, l, ne, 0, Phi, ne);
     for (int s = 0; s < 2; ++s) {
       const SpinTab& st = wf.sp[s];
       int w = st.n + st.nP;
@@ -675,14 +690,17 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
 // for a row w (length nop) of electron il of spin s.  B, T, Ru, Wu may live in
 // LDS or in a walker record in HBM.
 // ---------------------------------------------------------------------------
-__device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, int il, const double* w, double* ybuf,
-                               const double* B, const double* T, const double* Ru, const double* Wu) {
+// B[j * bstride + bcol] is B[j][il]: the full inverse (bstride = n, bcol = il)
+// or a staged copy of its column il (bstride = 1, bcol = 0).
+__device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, const double* w, double* ybuf,
+                               const double* B, int bstride, int bcol, const double* T, const double* Ru,
+                               const double* Wu) {
   const SpinTab& st = wf.sp[s];
   const int* ref = l.ref(s);
   const int* porb = l.porb(s);
   double rho = 0.0;
 #pragma unroll 4
-  for (int j = 0; j < st.n; ++j) rho += w[ref[j]] * B[j * st.n + il];
+  for (int j = 0; j < st.n; ++j) rho += w[ref[j]] * B[j * bstride + bcol];
   for (int q = 0; q < st.nP; ++q) {
     double a = w[porb[q]];
 #pragma unroll 4
@@ -699,7 +717,7 @@ __device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, int il, cons
     for (int r = 0; r < 3; ++r)
       if (r < e) {
         yy[r] = ybuf[ui[4 + r]];
-        bb[r] = B[ui[1 + r] * st.n + il];
+        bb[r] = B[ui[1 + r] * bstride + bcol];
       }
     tot += (rho * Ru[u] + adj_e(e, m, yy, bb)) * Wu[u];
   }
@@ -708,7 +726,7 @@ __device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, int il, cons
 
 __device__ __forceinline__ double row_op_sum(const DevWF& wf, const Ld& l, int s, int il, const double* w,
                                              double* ybuf) {
-  return row_op_sum_p(wf, l, s, il, w, ybuf, l.B(s), l.T(s), l.Ru(s), l.Wu(s));
+  return row_op_sum_p(wf, l, s, w, ybuf, l.B(s), wf.sp[s].n, il, l.T(s), l.Ru(s), l.Wu(s));
 }
 
 // ---------------------------------------------------------------------------

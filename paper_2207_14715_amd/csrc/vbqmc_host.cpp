@@ -24,9 +24,10 @@ hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W,
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
                       hipStream_t s);
-hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, int nt, double* state, int64_t W, int nsteps,
-                            uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s, double* na,
-                            double* el, double* sij, hipStream_t s);
+hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_g, int G, const DevWF* dwf_aux,
+                            int nt, int phases, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
+                            double step_size, double* es, double* e2s, double* na, double* el, double* sij,
+                            hipStream_t s);
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
                            uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
                            hipStream_t s);
@@ -138,9 +139,11 @@ struct vbqmc_ctx {
   double* d_wcoef[2] = {nullptr, nullptr};
   double* d_slc = nullptr;
   DevWF* d_wf = nullptr;
-  DevWF* d_wf_aux = nullptr;  // same tables, compact LDS layout of the batched local-energy kernels
-  double* d_timg = nullptr;   // LDS table image
-  int aux_off[10] = {0};
+  DevWF* d_wf_sweep = nullptr;  // same tables, compact LDS layout of the sweep kernel
+  DevWF* d_wf_sweepg = nullptr; // same tables, layout of the wavefront sweep (several walkers per wavefront)
+  int sweep_g = 64;             // lanes per walker in the single-electron sweep
+  DevWF* d_wf_aux = nullptr;    // same tables, compact LDS layout of the batched local-energy kernels
+  double* d_timg = nullptr;     // LDS table image
 };
 
 namespace {
@@ -196,6 +199,126 @@ int upload_lambda(vbqmc_ctx* x) {
   if (e == hipSuccess) e = hipMemcpy(x->d_lamT32, l32.data(), l32.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(x->d_lamT16, l16.data(), l16.size() * 2, hipMemcpyHostToDevice);
   return e == hipSuccess ? 0 : hipfail(x, e, "upload lambda");
+}
+
+// LDS allocator: offsets in doubles, each region 16-byte aligned
+struct LdsAlloc {
+  int o;
+  int operator()(int n) { int r = o; o += (std::max(n, 1) + 1) / 2 * 2; return r; }
+  int ints(int n) { return (*this)((n + 1) / 2); }
+};
+
+// Sweep kernel: the tables without the orbital coefficients (read from global
+// memory there), the walker state, value-only tile tables and the trial
+// positions, draws and orbital rows.
+DevWF sweep_layout(const vbqmc_ctx* x) {
+  DevWF a = x->wf;
+  const int nmax = std::max(x->nup, x->ndn);
+  int nUm = 1, nPm = 1;
+  for (int s = 0; s < 2; ++s) {
+    nUm = std::max(nUm, (int)x->sp[s].sets.size());
+    nPm = std::max(nPm, (int)x->sp[s].porb.size());
+  }
+  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
+  a.l_R = lds(3 * x->N);
+  a.l_sc = lds(SC_COUNT);
+  a.l_red = lds(x->nt > 64 ? kRedSlots : 1);
+  a.l_ipiv = lds.ints(nmax);
+  a.l_f = lds(nmax);
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    a.l_B[s] = lds(n * n);
+    a.l_T[s] = lds(n * nP);
+    a.l_PP[s] = lds(n * nP);
+    a.l_Ru[s] = lds((int)x->sp[s].sets.size());
+    a.l_Wu[s] = lds((int)x->sp[s].sets.size());
+  }
+  a.l_Qu = lds(nUm);
+  a.l_y = lds(nPm + 1);
+  a.l_bcol = lds(nmax);
+  a.l_z = lds(2 * nmax);
+  a.l_disp = lds(kGroup * x->nnuc * 4);
+  a.l_gtab = lds(kGroup * x->nshell);
+  a.l_Rp = lds(3 * x->N);
+  a.l_ua = lds(x->N);
+  a.l_Vn = lds(x->N * x->nop);
+  a.lds_sweep_doubles = lds.o;
+  return a;
+}
+
+// Wavefront sweep with G lanes per walker: the tables without the orbital
+// coefficients, value-only tile tables, the trial positions, draws and
+// orbital rows of all 64 / G walkers, then one state block per walker.
+DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
+  DevWF a = x->wf;
+  const int NG = 64 / G;
+  const int nmax = std::max(x->nup, x->ndn);
+  int nUm = 1, nPm = 1;
+  for (int s = 0; s < 2; ++s) {
+    nUm = std::max(nUm, (int)x->sp[s].sets.size());
+    nPm = std::max(nPm, (int)x->sp[s].porb.size());
+  }
+  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
+  a.l_disp = lds(kGroup * x->nnuc * 4);
+  a.l_gtab = lds(kGroup * x->nshell);
+  a.l_Rp = lds(3 * NG * x->N);
+  a.l_ua = lds(NG * x->N);
+  a.l_Vn = lds(NG * x->N * x->nop);
+  a.gw_base = lds.o;
+  LdsAlloc w{0};
+  a.l_R = w(3 * x->N);
+  a.l_sc = w(SC_COUNT);
+  a.l_ipiv = w.ints(nmax);
+  a.l_f = w(nmax);
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    a.l_B[s] = w(n * n);
+    a.l_T[s] = w(n * nP);
+    a.l_PP[s] = w(n * nP);
+    a.l_Ru[s] = w((int)x->sp[s].sets.size());
+    a.l_Wu[s] = w((int)x->sp[s].sets.size());
+  }
+  a.l_Qu = w(nUm);
+  a.l_y = w(nPm + 1);
+  a.l_bcol = w(nmax);
+  a.l_z = w(2 * nmax);
+  a.gw_stride = w.o;
+  a.lds_sweepg_doubles = a.gw_base + NG * a.gw_stride;
+  return a;
+}
+
+// Batched local-energy kernels: the tables, then only what the finish and
+// tile kernels touch.
+DevWF aux_layout(const vbqmc_ctx* x) {
+  DevWF a = x->wf;
+  int nPm = 1;
+  for (int s = 0; s < 2; ++s) nPm = std::max(nPm, (int)x->sp[s].porb.size());
+  LdsAlloc lds{a.timg_len};
+  a.l_R = lds(std::max(3 * x->N, 3 * kGroup));
+  a.l_sc = lds(SC_COUNT);
+  a.l_red = lds(kRedSlots);
+  a.l_gU = lds(3 * x->N);
+  a.l_lU = lds(x->N);
+  a.l_ratio = lds(x->nstruct);
+  a.lds_finish_doubles = lds.o;
+  a.l_disp = lds(kGroup * x->nnuc * 4);
+  a.l_gtab = lds(kGroup * x->nshell * 3);
+  a.l_Phi4 = lds(4 * kGroup * x->nop);
+  a.l_yb64 = lds(64 * (nPm + 1));
+  // per walker of a tile: inverse column, table, R_u, W_u, S, valid flag
+  int row = 0;
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size(), nU = (int)x->sp[s].sets.size();
+    row = std::max(row, n + n * nP + 2 * nU + 2);
+  }
+  a.tstage_row = row;
+  a.l_tstage = lds(kGroup * row);
+  a.lds_tile_doubles = lds.o;
+  return a;
 }
 
 // The constant tables exactly as they sit at the start of a block's LDS, so
@@ -259,11 +382,16 @@ int upload_coefficients(vbqmc_ctx* x) {
   if (e == hipSuccess) e = hipMemcpy(x->d_en, x->en.data(), x->en.size() * 8, hipMemcpyHostToDevice);
   for (int k = 0; k < 8; ++k) x->wf.ee[k] = x->ee[k];
   if (e == hipSuccess && x->d_wf) e = hipMemcpy(x->d_wf, &x->wf, sizeof(DevWF), hipMemcpyHostToDevice);
+  if (e == hipSuccess && x->d_wf_sweep) {
+    DevWF a = sweep_layout(x);
+    e = hipMemcpy(x->d_wf_sweep, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && x->d_wf_sweepg && x->sweep_g < 64) {
+    DevWF a = sweepg_layout(x, x->sweep_g);
+    e = hipMemcpy(x->d_wf_sweepg, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess && x->d_wf_aux) {
-    DevWF a = x->wf;
-    a.l_R = x->aux_off[0]; a.l_sc = x->aux_off[1]; a.l_red = x->aux_off[2]; a.l_gU = x->aux_off[3];
-    a.l_lU = x->aux_off[4]; a.l_ratio = x->aux_off[5]; a.l_disp = x->aux_off[6]; a.l_gtab = x->aux_off[7];
-    a.l_Phi4 = x->aux_off[8]; a.l_yb64 = x->aux_off[9];
+    DevWF a = aux_layout(x);
     e = hipMemcpy(x->d_wf_aux, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) return upload_table_image(x);
@@ -556,15 +684,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   o = tile0;
   wf.l_pt = lds(2 * wf.nprim);
   o = std::max(o, tile_end);
-  const int sweep0 = o;
-  // sweep kernel: trial positions, acceptance draws and trial orbital rows
-  const int npad = (x->N + kGroup - 1) / kGroup * kGroup;
-  wf.l_Rp = lds(3 * npad);
-  wf.l_ua = lds(npad);
-  wf.l_Vn = lds(npad * x->nop);
-  wf.lds_sweep_doubles = o;
   // fused walker kernels: point evaluations, local energy, overlaps
-  o = sweep0;
   wf.l_part = lds(std::max(x->nt, 4 * x->nop));
   wf.l_chi = lds(4 * x->Mpad);
   wf.l_v = lds(4 * x->nop);
@@ -576,27 +696,6 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_gD = lds(3 * x->N);
   wf.l_lD = lds(x->N);
   const int full_end = o;
-  // compact layout of the batched local-energy kernels: the constant tables,
-  // then only what the finish and tile kernels touch
-  {
-    DevWF a = wf;
-    o = tables_end;
-    a.l_R = lds(std::max(3 * x->N, 3 * kGroup));
-    a.l_sc = lds(SC_COUNT);
-    a.l_red = lds(kRedSlots);
-    a.l_gU = lds(3 * x->N);
-    a.l_lU = lds(x->N);
-    a.l_ratio = lds(x->nstruct);
-    wf.lds_finish_doubles = o;
-    a.l_disp = lds(kGroup * x->nnuc * 4);
-    a.l_gtab = lds(kGroup * x->nshell * 3);
-    a.l_Phi4 = lds(4 * kGroup * x->nop);
-    a.l_yb64 = lds(64 * (nPm + 1));
-    wf.lds_tile_doubles = o;
-    x->aux_off[0] = a.l_R; x->aux_off[1] = a.l_sc; x->aux_off[2] = a.l_red; x->aux_off[3] = a.l_gU;
-    x->aux_off[4] = a.l_lU; x->aux_off[5] = a.l_ratio; x->aux_off[6] = a.l_disp; x->aux_off[7] = a.l_gtab;
-    x->aux_off[8] = a.l_Phi4; x->aux_off[9] = a.l_yb64;
-  }
   // adjoint-kernel regions
   o = full_end;
   wf.l_aPhi = lds(5 * x->N * x->nop);
@@ -610,6 +709,12 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.lds_adj_doubles = o;
   o = full_end;
   wf.lds_doubles = o;
+  wf.lds_sweep_doubles = sweep_layout(x).lds_sweep_doubles;
+  {
+    DevWF a = aux_layout(x);
+    wf.lds_finish_doubles = a.lds_finish_doubles;
+    wf.lds_tile_doubles = a.lds_tile_doubles;
+  }
 
   int dev = 0;
   hipError_t he = hipGetDevice(&dev);
@@ -624,6 +729,27 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
                   x->lds_limit);
     return bad(b);
   }
+  // lanes per walker of the single-electron sweep
+  {
+    const int req = opt ? opt->walker_lanes : 0;
+    auto fits = [&](int G) {
+      return (size_t)sweepg_layout(x, G).lds_sweepg_doubles * 8 <= (size_t)x->lds_limit;
+    };
+    const int nmax = std::max(x->nup, x->ndn);
+    if (req == 16 || req == 32) {
+      if (!fits(req)) return bad("walker_lanes: the walkers of one wavefront do not fit in LDS");
+      x->sweep_g = req;
+    } else if (req == 64) {
+      x->sweep_g = 64;
+    } else if (req == 0) {
+      // two walkers per wavefront for small spin determinants; larger ones
+      // keep a workgroup per walker
+      x->sweep_g = nmax <= 16 && fits(32) ? 32 : 64;
+    } else {
+      return bad("walker_lanes must be 0, 16, 32 or 64");
+    }
+    if (x->sweep_g < 64) wf.lds_sweepg_doubles = sweepg_layout(x, x->sweep_g).lds_sweepg_doubles;
+  }
 
   // ---- device tables ----
   size_t bytes = 0;
@@ -637,7 +763,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.wother.size(), 4); add(h.wother.size(), 8);
   }
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
-  add((size_t)wf.timg_len, 8);
+  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add((size_t)wf.timg_len, 8);
   he = hipMalloc((void**)&x->dmem, bytes);
   if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
   x->dbytes = bytes;
@@ -672,6 +798,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_slc = carve<double>(p, x->slc.size());
   x->d_wf = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_aux = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_sweep = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_sweepg = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_timg = carve<double>(p, (size_t)wf.timg_len);
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
@@ -703,6 +831,7 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->n_table_dn = (int)x->sp[1].porb.size();
   o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
   o->block_threads = x->nt;
+  o->sweep_lanes = x->sweep_g;
   o->walker_state_bytes = (int64_t)x->wf.rec_len * 8;
   o->lds_bytes = (int64_t)x->wf.lds_doubles * 8;
   return VBQMC_OK;
@@ -770,6 +899,43 @@ int vbqmc_walkers_eloc(vbqmc_ctx* x, int64_t W, const void* state, double* eloc,
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_eloc");
 }
 
+}  // extern "C"
+
+namespace {
+// the sweep + batched local-energy kernels fit the device's LDS
+bool split_fits(const vbqmc_ctx* x) {
+  return (size_t)std::max(x->wf.lds_sweep_doubles, x->wf.lds_tile_doubles) * 8 <= (size_t)x->lds_limit;
+}
+}  // namespace
+
+extern "C" {
+
+int vbqmc_vmc_sweep(vbqmc_ctx* x, void* state, int64_t W, uint64_t seed, uint64_t step, double step_size,
+                    double* n_accept, vbqmc_stream stream) {
+  if (!x || W < 0 || (W > 0 && (!state || !n_accept))) return fail(x, VBQMC_EINVAL, "vmc_sweep: bad arguments");
+  if (!(step_size > 0) || !std::isfinite(step_size)) return fail(x, VBQMC_EINVAL, "vmc_sweep: bad step size");
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_sweep: too many walkers");
+  if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_sweep: system too large for the sweep kernels");
+  if (W == 0) return VBQMC_OK;
+  hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 1,
+                                  (double*)state, W, 1, seed, step, step_size, nullptr, nullptr, n_accept, nullptr,
+                                  nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc_sweep");
+}
+
+int vbqmc_vmc_measure(vbqmc_ctx* x, void* state, int64_t W, const vbqmc_vmc_acc* acc, vbqmc_stream stream) {
+  if (!x || !acc || W < 0 || (W > 0 && !state)) return fail(x, VBQMC_EINVAL, "vmc_measure: bad arguments");
+  if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_measure: too many walkers");
+  if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_measure: system too large for the local-energy kernels");
+  if (W == 0) return VBQMC_OK;
+  if (!acc->e_sum || !acc->e2_sum || !acc->e_last)
+    return fail(x, VBQMC_EINVAL, "vmc_measure: accumulator pointers missing");
+  hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 2,
+                                  (double*)state, W, 1, 0, 0, 1.0, acc->e_sum, acc->e2_sum, nullptr, acc->e_last,
+                                  acc->sij_sum, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc_measure");
+}
+
 int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uint64_t seed, uint64_t step0,
                       double step_size, int32_t all_electron, const vbqmc_vmc_acc* acc, vbqmc_stream stream) {
   if (!x || !acc || W < 0 || n_steps < 0 || (W > 0 && !state)) return fail(x, VBQMC_EINVAL, "vmc: bad arguments");
@@ -778,13 +944,11 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
-  const bool split_fits = (size_t)std::max(x->wf.lds_sweep_doubles, x->wf.lds_tile_doubles) * 8 <=
-                          (size_t)x->lds_limit;
-  if (!all_electron && split_fits) {
+  if (!all_electron && split_fits(x)) {
     // single-electron moves: walker-resident sweep + batched local energy
-    hipError_t e = launch_vmc_split(x->wf, x->d_wf, x->d_wf_aux, x->nt, (double*)state, W, n_steps, seed, step0, step_size,
-                                    acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum,
-                                    (hipStream_t)stream);
+    hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 3,
+                                    (double*)state, W, n_steps, seed, step0, step_size, acc->e_sum, acc->e2_sum,
+                                    acc->n_accept, acc->e_last, acc->sij_sum, (hipStream_t)stream);
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
   hipError_t e = launch_vmc(x->wf, x->d_wf, x->nt, (double*)state, W, n_steps, seed, step0, step_size, all_electron ? 1 : 0,

@@ -63,11 +63,15 @@ struct DevWF {
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
   int l_gU, l_lU, l_gD, l_lD;
   int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_pt, l_yb, l_sij, l_ratio;
-  int l_Phi4, l_yb64;
+  int l_Phi4, l_yb64, l_tstage, tstage_row;
   int l_Rp, l_ua, l_Vn;  // sweep kernel: trial positions, acceptance draws, trial orbital rows
   // adjoint kernel
   int l_aPhi, l_aG0, l_aG, l_aA, l_aP, l_aM, l_aU[2];
   int lds_doubles, lds_sweep_doubles, lds_finish_doubles, lds_tile_doubles, lds_adj_doubles;
+  // wavefront sweep (several walkers per wavefront): walker g's state starts
+  // at gw_base + g * gw_stride, and the state offsets of that layout are
+  // relative to it
+  int gw_base, gw_stride, lds_sweepg_doubles;
 };
 
 // scalar slots in the record's / LDS scalar block

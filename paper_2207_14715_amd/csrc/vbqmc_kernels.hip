@@ -300,8 +300,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __syncthreads();
     for (int g0 = 0; g0 < wf.N; g0 += kGroup) {
       int ne = min(kGroup, wf.N - g0);
-      group_radial<NT, PREC>(wf, l, Rp, g0, ne);
-      group_channel<NT, PREC>(wf, l, ne, 0, l.Vn() + g0 * wf.nop);
+      group_radial<NT, PREC, 1>(wf, l, Rp, g0, ne);
+      group_channel<NT, PREC, 1>(wf, l, ne, 0, l.Vn() + g0 * wf.nop, ne);
     }
     for (int i = 0; i < wf.N; ++i) {
       const double px = Rp[3 * i], py = Rp[3 * i + 1], pz = Rp[3 * i + 2];
@@ -313,7 +313,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     if (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every) {
-      if (build_state<NT, PREC>(wf, l, l.R())) compute_RWS<NT>(wf, l);
+      // the trial rows are dead here: they serve as the tile scratch
+      if (build_state<NT, PREC, 1>(wf, l, l.R(), l.Vn())) compute_RWS<NT>(wf, l);
       else bad = true;
     }
     if (!(sc[SC_S] != 0.0)) bad = true;
@@ -325,36 +326,57 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (threadIdx.x == 0) n_acc[w] += na;
 }
 
-// One wave per block; each block walks `per_block` tiles of 16 (walker,
-// electron) rows: radial tables, four MFMA channels (gradient, Laplacian),
-// then 64 lanes = 16 rows x 4 channels form the row-operator ratios from the
-// walkers' records and store them in the records' scratch rows.
+// Local-energy rows of one electron across 16 walkers.  One wave per block;
+// each block walks `per_block` tiles.  A tile stages, per walker, the
+// electron's position, column il of the spin's inverse, the table T, the
+// determinant ratios, their partner sums, S and the valid flag; then forms
+// the radial tables and the four MFMA channels (gradient, Laplacian) of the
+// 16 positions, and 64 lanes = 16 walkers x 4 channels form the row-operator
+// ratios and store them in the walkers' scratch rows.
 template <int PREC>
 __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf, double* state, int64_t W,
-                                                   int64_t ntiles, int per_block) {
+                                                   int per_block) {
   const DevWF& wf = *pwf;
   Ld l(lds_dyn, wf);
   stage_tables<64, PREC>(wf, l);
   const int N = wf.N, nop = wf.nop;
   const int nPm = max(wf.sp[0].nP, wf.sp[1].nP);
   const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
-  const int64_t rows_total = W * N;
+  const int64_t nwb = (W + kGroup - 1) / kGroup;
+  const int64_t ntiles = nwb * N;
   double* Rt = l.R();
   double* Phi4 = l.L + wf.l_Phi4;
   double* yb = l.L + wf.l_yb64;
+  double* stg = l.L + wf.l_tstage;
+  const int rowsz = wf.tstage_row;
   for (int64_t tile = (int64_t)blockIdx.x * per_block; tile < min(ntiles, (int64_t)(blockIdx.x + 1) * per_block);
        ++tile) {
-    const int64_t r0 = tile * kGroup;
-    const int rows = (int)min((int64_t)kGroup, rows_total - r0);
-    if (threadIdx.x < 3 * kGroup) {
-      int t = threadIdx.x / 3, x = threadIdx.x - 3 * t;
-      double v = 0.0;
-      if (t < rows) {
-        int64_t r = r0 + t, w = r / N;
-        int e = (int)(r - w * N);
-        v = state[w * wf.rec_len + wf.r_R + 3 * e + x];
+    const int64_t wb = tile / N;
+    const int e = (int)(tile - wb * N);
+    const int64_t w0 = wb * kGroup;
+    const int rows = (int)min((int64_t)kGroup, W - w0);
+    const int s = spin_of(wf, e);
+    const SpinTab& st = wf.sp[s];
+    const int il = e - st.e0, n = st.n, nP = st.nP, nU = st.nU;
+    const int oT = n, oRu = n + n * nP, oWu = oRu + nU, oS = oWu + nU;
+    const int per_row = 3 + oS + 2;
+    const int ru0 = wf.r_RW + (s ? n0 : 0), wu0 = wf.r_RW + n0 + n1 + (s ? n0 : 0);
+    for (int idx = threadIdx.x; idx < rows * per_row; idx += 64) {
+      const int t = idx / per_row, k = idx - t * per_row;
+      const double* rec = state + (w0 + t) * wf.rec_len;
+      if (k < 3) {
+        Rt[3 * t + k] = rec[wf.r_R + 3 * e + k];
+      } else {
+        const int q = k - 3;
+        double v;
+        if (q < oT) v = rec[wf.r_B[s] + q * n + il];
+        else if (q < oRu) v = rec[wf.r_T[s] + (q - oT)];
+        else if (q < oWu) v = rec[ru0 + (q - oRu)];
+        else if (q < oS) v = rec[wu0 + (q - oWu)];
+        else if (q == oS) v = rec[wf.r_RW + 2 * (n0 + n1)];
+        else v = rec[wf.r_sc + SC_FLAGS];
+        stg[t * rowsz + q] = v;
       }
-      Rt[threadIdx.x] = v;
     }
     __syncthreads();
     group_radial<64, PREC>(wf, l, Rt, 0, rows);
@@ -362,17 +384,12 @@ __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf
     {
       const int t = threadIdx.x >> 2, c = threadIdx.x & 3;
       if (t < rows) {
-        int64_t r = r0 + t, w = r / N;
-        int e = (int)(r - w * N);
-        int s = spin_of(wf, e), il = e - wf.sp[s].e0;
-        double* rec = state + w * wf.rec_len;
-        const double* RW = rec + wf.r_RW;
-        double S = RW[2 * (n0 + n1)];
+        const double* sr = stg + t * rowsz;
         double tot = 0.0;
-        if (rec[wf.r_sc + SC_FLAGS] == 0.0)
-          tot = row_op_sum_p(wf, l, s, il, Phi4 + (c * kGroup + t) * nop, yb + threadIdx.x * (nPm + 1),
-                             rec + wf.r_B[s], rec + wf.r_T[s], RW + (s ? n0 : 0), RW + n0 + n1 + (s ? n0 : 0));
-        rec[wf.r_gc + 4 * e + c] = tot / S;
+        if (sr[oS + 1] == 0.0)
+          tot = row_op_sum_p(wf, l, s, Phi4 + (c * kGroup + t) * nop, yb + threadIdx.x * (nPm + 1), sr, 1, 0,
+                             sr + oT, sr + oRu, sr + oWu);
+        state[(w0 + t) * wf.rec_len + wf.r_gc + 4 * e + c] = tot / sr[oS];
       }
     }
     __syncthreads();
@@ -809,8 +826,12 @@ hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, 
 }
 
 
+hipError_t launch_sweep_g(const DevWF& wf, const DevWF* dwf, int G, double* state, int64_t W, uint64_t seed,
+                          uint32_t step, double step_size, double* n_acc, hipStream_t s);
+
 template <int NT, int PREC>
-static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, double* state, int64_t W, int nsteps,
+static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_g, int G,
+                                     const DevWF* dwf_aux, int phases, double* state, int64_t W, int nsteps,
                                      uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s,
                                      double* na, double* el, double* sij, hipStream_t s) {
   size_t lds_sw = (size_t)wf.lds_sweep_doubles * sizeof(double);
@@ -820,23 +841,33 @@ static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const De
   if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_tiles<PREC>, lds_ti);
   if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_finish, lds_fi);
   if (e != hipSuccess) return e;
-  const int64_t ntiles = (W * wf.N + kGroup - 1) / kGroup;
-  const int per_block = 4;
+  const int64_t ntiles = (W + kGroup - 1) / kGroup * wf.N;
+  const int per_block = 2;
   const unsigned tblocks = (unsigned)((ntiles + per_block - 1) / per_block);
   for (int st = 0; st < nsteps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
-    hipLaunchKernelGGL((k_sweep<NT, PREC>), dim3((unsigned)W), dim3(NT), lds_sw, s, dwf, state, W, seed, step,
-                       step_size, na);
-    hipLaunchKernelGGL((k_eloc_tiles<PREC>), dim3(tblocks), dim3(64), lds_ti, s, dwf_aux, state, W, ntiles, per_block);
-    hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)W), dim3(64), lds_fi, s, dwf_aux, state, W, es, e2s, el, sij);
+    if ((phases & 1) && G < 64) {
+      hipError_t e2 = launch_sweep_g(wf, dwf_g, G, state, W, seed, step, step_size, na, s);
+      if (e2 != hipSuccess) return e2;
+    } else if (phases & 1) {
+      hipLaunchKernelGGL((k_sweep<NT, PREC>), dim3((unsigned)W), dim3(NT), lds_sw, s, dwf, state, W, seed, step,
+                         step_size, na);
+    }
+    if (phases & 2) {
+      hipLaunchKernelGGL((k_eloc_tiles<PREC>), dim3(tblocks), dim3(64), lds_ti, s, dwf_aux, state, W, per_block);
+      hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)W), dim3(64), lds_fi, s, dwf_aux, state, W, es, e2s, el,
+                         sij);
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_aux, int nt, double* state, int64_t W, int nsteps,
-                            uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s, double* na,
-                            double* el, double* sij, hipStream_t s) {
-  VB_DISPATCH_NT(nt, launch_vmc_split_t, wf, dwf, dwf_aux, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s)
+// phases: 1 = sweep (moves), 2 = measure (local energy), 3 = both, per step
+hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_g, int G, const DevWF* dwf_aux,
+                            int nt, int phases, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
+                            double step_size, double* es, double* e2s, double* na, double* el, double* sij,
+                            hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_vmc_split_t, wf, dwf, dwf_g, G, dwf_aux, phases, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s)
 }
 
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,

@@ -24,13 +24,15 @@ def lib():
     return vb
 
 
-def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=4242, step0=17, sij=False):
+def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=4242, step0=17, sij=False,
+              lanes=0):
     import torch
     R0 = S.initial_walkers(sysd, W, seed=5)
     o = oracle_mod.Oracle(sysd)
     ref = o.vmc(R0, steps, seed, step0, step_size, all_electron, want_sij=sij)
-    ctx = lib.Context(sysd)
-    print(f"[vmc] {sysd['name']} W={W} steps={steps} all_electron={all_electron}", flush=True)
+    ctx = lib.Context(sysd, walker_lanes=lanes)
+    print(f"[vmc] {sysd['name']} W={W} steps={steps} all_electron={all_electron} "
+          f"lanes={ctx.info['sweep_lanes']}", flush=True)
     state = ctx.walkers_init(torch.from_numpy(R0).cuda())
     acc = ctx.vmc_advance(state, steps, seed, step0, step_size, all_electron, acc=ctx.new_vmc_acc(W, sij=sij))
     R = ctx.positions(state).cpu().numpy()
@@ -52,21 +54,54 @@ def test_vmc_h2_all_electron(lib, oracle_mod):
     _check_vmc(ref, acc, R, 30)
 
 
-def test_vmc_h2_single_electron(lib, oracle_mod):
-    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, False)
+# single-electron sweeps run with 16 or 32 lanes per walker (several walkers
+# per wavefront) or one walker per workgroup; all three must give the walks
+LANES = [16, 32, 64]
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_vmc_h2_single_electron(lib, oracle_mod, lanes):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, False, lanes=lanes)
     _check_vmc(ref, acc, R, 30)
 
 
-def test_vmc_small_random_with_sij(lib, oracle_mod):
+@pytest.mark.parametrize("lanes", LANES)
+def test_vmc_small_random_with_sij(lib, oracle_mod, lanes):
     sysd = S.small_random_system(211, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
-    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 64, 20, 0.4, False, sij=True)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 64, 20, 0.4, False, sij=True, lanes=lanes)
     _check_vmc(ref, acc, R, 20)
     np.testing.assert_allclose(acc["sij_sum"].cpu().numpy(), ref["sij_sum"], rtol=1e-8, atol=1e-8)
 
 
-def test_vmc_f2_sherman_morrison(lib, oracle_mod):
-    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.f2_shaped(), 64, 12, 0.3, False)
+@pytest.mark.parametrize("lanes", LANES)
+def test_vmc_f2_sherman_morrison(lib, oracle_mod, lanes):
+    # 12 sweeps at ~57 % acceptance pass the 32-update refresh of both spins;
+    # 61 walkers leave a partly filled last wavefront for 16 and 32 lanes
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.f2_shaped(), 61, 12, 0.3, False, lanes=lanes)
     _check_vmc(ref, acc, R, 12)
+
+
+@pytest.mark.parametrize("lanes", [32, 64])
+def test_vmc_sweep_then_measure_equals_advance(lib, lanes):
+    # a step of vbqmc_vmc_advance is a sweep followed by a measurement: the
+    # split calls give bit-identical walks and accumulators
+    import torch
+    sysd = S.f2_shaped()
+    ctx = lib.Context(sysd, walker_lanes=lanes)
+    W, steps, seed, step0 = 61, 5, 99, 3
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=6)).cuda()
+    print(f"[sweep+measure] f2 W={W} lanes={lanes}", flush=True)
+    st_a = ctx.walkers_init(R0)
+    acc_a = ctx.vmc_advance(st_a, steps, seed, step0, 0.3)
+    st_b = ctx.walkers_init(R0)
+    acc_b = ctx.new_vmc_acc(W)
+    for k in range(steps):
+        ctx.vmc_sweep(st_b, seed, step0 + k, 0.3, acc_b["n_accept"])
+        ctx.vmc_measure(st_b, acc_b)
+    torch.cuda.synchronize()
+    assert torch.equal(ctx.positions(st_a), ctx.positions(st_b))
+    for key in ("e_sum", "e2_sum", "n_accept", "e_last"):
+        assert torch.equal(acc_a[key], acc_b[key]), key
 
 
 def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3):
