@@ -307,11 +307,18 @@ __device__ void stage_tables(const DevWF& wf, const Ld& l) {
 // tables and contracts it with lambda^T, one 16x16 output tile at a time,
 // writing Phi[e][p] (FP64) for channel c.
 // ---------------------------------------------------------------------------
+// Row strides of the tile tables, odd so that the 16 rows of a tile fall in
+// distinct LDS banks.
+__device__ __forceinline__ int disp_stride(const DevWF& wf) { return 4 * wf.nnuc + 1; }
+template <int GS>
+__device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.nshell) | 1; }
+
 template <int NT, int PREC, int GS = 3>
 __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
-  T* disp = (T*)l.disp();  // [16][nnuc][4]: x, y, z, r2
-  T* gt = (T*)l.gtab();    // [16][nshell][GS]: g (and g1, g2 when GS = 3)
+  T* disp = (T*)l.disp();  // [16][stride]: per nucleus x, y, z, r2
+  T* gt = (T*)l.gtab();    // [16][stride]: per shell g (and g1, g2 when GS = 3)
+  const int ds = disp_stride(wf), gs = gtab_stride<GS>(wf);
   for (int idx = threadIdx.x; idx < kGroup * wf.nnuc; idx += NT) {
     int e = idx / wf.nnuc, a = idx - e * wf.nnuc;
     T x = 0, y = 0, z = 0;
@@ -320,14 +327,15 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
       y = (T)(Rsrc[3 * (g0 + e) + 1] - l.nuc()[4 * a + 1]);
       z = (T)(Rsrc[3 * (g0 + e) + 2] - l.nuc()[4 * a + 2]);
     }
-    disp[4 * idx] = x; disp[4 * idx + 1] = y; disp[4 * idx + 2] = z;
-    disp[4 * idx + 3] = x * x + y * y + z * z;
+    T* d = disp + e * ds + 4 * a;
+    d[0] = x; d[1] = y; d[2] = z;
+    d[3] = x * x + y * y + z * z;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
     int e = idx / wf.nshell, sh = idx - e * wf.nshell;
     const int* si = l.sh() + 8 * sh;
-    T r2 = disp[4 * (e * wf.nnuc + si[0]) + 3], r = sqrt(r2);
+    T r2 = disp[e * ds + 4 * si[0] + 3], r = sqrt(r2);
     T g = 0, g1 = 0, g2 = 0;
     if (e < ne) {
       for (int k = 0; k < si[5]; ++k) {
@@ -343,10 +351,11 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
         }
       }
     }
-    gt[GS * idx] = g;
+    T* o = gt + e * gs + GS * sh;
+    o[0] = g;
     if constexpr (GS == 3) {
-      gt[3 * idx + 1] = g1;
-      gt[3 * idx + 2] = g2;
+      o[1] = g1;
+      o[2] = g2;
     }
   }
   __syncthreads();
@@ -362,8 +371,8 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
   int m = fn[2 * mu + 1];
   const int* si = l.sh() + 8 * sh;
   int kind = si[1], lq = si[2];
-  const T* d = (const T*)l.disp() + 4 * (e * wf.nnuc + si[0]);
-  const T* gg = (const T*)l.gtab() + GS * (e * wf.nshell + sh);
+  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * si[0];
+  const T* gg = (const T*)l.gtab() + e * gtab_stride<GS>(wf) + GS * sh;
   T x = d[0], y = d[1], z = d[2], r2 = d[3];
   T g = gg[0], g1 = T(0), g2 = T(0);
   if constexpr (GS == 3) {
@@ -459,6 +468,136 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (4 * (lane >> 4) + r < nout_rows) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Channels 1..4 (gradient x, y, z and Laplacian) of function mu at electron e
+// of the tile, from the radial tables (GS = 3), sharing the table reads.
+template <typename T>
+__device__ __forceinline__ void chan_value4(const DevWF& wf, const Ld& l, int e, int mu, T (&o)[4]) {
+  const int* fn = l.fn();
+  int sh = fn[2 * mu];
+  if (sh < 0) {
+    o[0] = o[1] = o[2] = o[3] = T(0);
+    return;
+  }
+  int m = fn[2 * mu + 1];
+  const int* si = l.sh() + 8 * sh;
+  int kind = si[1], lq = si[2];
+  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * si[0];
+  const T* gg = (const T*)l.gtab() + e * gtab_stride<3>(wf) + 3 * sh;
+  T x = d[0], y = d[1], z = d[2], r2 = d[3];
+  T g = gg[0], g1 = gg[1], g2 = gg[2];
+  T P, Px = T(0), Py = T(0), Pz = T(0);
+  if (lq == 0) {
+    P = T(1);
+  } else if (lq == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? T(1) : T(0);
+    Py = m == 1 ? T(1) : T(0);
+    Pz = m == 2 ? T(1) : T(0);
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = T(2) * x; Py = T(-2) * y; break;
+      default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
+    }
+  }
+  T fr, lap;
+  if (kind == 0) {
+    fr = T(2) * g1;
+    lap = P * (T(2 * (2 * lq + 3)) * g1 + T(4) * r2 * g2);
+  } else {
+    T r = sqrt(r2);
+    fr = g1 / r;
+    lap = P * (g2 + T(2 * (lq + 1)) * g1 / r);
+  }
+  o[0] = Px * g + P * fr * x;
+  o[1] = Py * g + P * fr * y;
+  o[2] = Pz * g + P * fr * z;
+  o[3] = lap;
+}
+
+// All four derivative channels of a tile in one pass: out[c][e][p] for
+// c = 0..3 (gradient x, y, z, Laplacian), rows e < ne.
+template <int NT, int PREC>
+__device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const int nct = wf.nop / 16;
+  const size_t cst = (size_t)kGroup * wf.nop;
+  for (int ct = wave; ct < nct; ct += NW) {
+    const int col = ct * 16 + (lane & 15);
+    const int e = lane & 15;
+    const bool live = e < ne;
+    if constexpr (PREC == 0) {
+      const double* lam = l.lam<double>();
+      v4d acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live) chan_value4<double>(wf, l, e, k, a);
+        double b = lam[(size_t)k * wf.nop + col];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], b, acc[c], 0, 0, 0);
+      }
+      // f64 16x16x4 output: register r of lane l holds row 4r + l/16
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * r + (lane >> 4) < ne) out[c * cst + (4 * r + (lane >> 4)) * wf.nop + col] = acc[c][r];
+    } else if constexpr (PREC == 1) {
+      const float* lam = l.lam<float>();
+      v4f acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = v4f{0, 0, 0, 0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
+        int k = k0 + (lane >> 4);
+        float a[4] = {0.f, 0.f, 0.f, 0.f};
+        if (live) chan_value4<float>(wf, l, e, k, a);
+        float b = lam[(size_t)k * wf.nop + col];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b, acc[c], 0, 0, 0);
+      }
+      // f32 output: register r of lane l holds row 4(l/16) + r
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * (lane >> 4) + r < ne) out[c * cst + (4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[c][r];
+    } else {
+      const uint16_t* lam = l.lam<uint16_t>();
+      v4f acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = v4f{0, 0, 0, 0};
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        int kb = k0 + 4 * (lane >> 4);
+        v4s a[4], b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v[4] = {0.f, 0.f, 0.f, 0.f};
+          if (live) chan_value4<float>(wf, l, e, kb + j, v);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a[c][j] = (short)f2bf(v[c]);
+          b[j] = (short)lam[(size_t)(kb + j) * wf.nop + col];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b, acc[c], 0, 0, 0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * (lane >> 4) + r < ne) out[c * cst + (4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[c][r];
     }
   }
   __syncthreads();

@@ -239,8 +239,8 @@ DevWF sweep_layout(const vbqmc_ctx* x) {
   a.l_y = lds(nPm + 1);
   a.l_bcol = lds(nmax);
   a.l_z = lds(2 * nmax);
-  a.l_disp = lds(kGroup * x->nnuc * 4);
-  a.l_gtab = lds(kGroup * x->nshell);
+  a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  a.l_gtab = lds(kGroup * (x->nshell | 1));
   a.l_Rp = lds(3 * x->N);
   a.l_ua = lds(x->N);
   a.l_Vn = lds(x->N * x->nop);
@@ -263,8 +263,8 @@ DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
   LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
-  a.l_disp = lds(kGroup * x->nnuc * 4);
-  a.l_gtab = lds(kGroup * x->nshell);
+  a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  a.l_gtab = lds(kGroup * (x->nshell | 1));
   a.l_Rp = lds(3 * NG * x->N);
   a.l_ua = lds(NG * x->N);
   a.l_Vn = lds(NG * x->N * x->nop);
@@ -305,8 +305,8 @@ DevWF aux_layout(const vbqmc_ctx* x) {
   a.l_lU = lds(x->N);
   a.l_ratio = lds(x->nstruct);
   a.lds_finish_doubles = lds.o;
-  a.l_disp = lds(kGroup * x->nnuc * 4);
-  a.l_gtab = lds(kGroup * x->nshell * 3);
+  a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  a.l_gtab = lds(kGroup * ((3 * x->nshell) | 1));
   a.l_Phi4 = lds(4 * kGroup * x->nop);
   a.l_yb64 = lds(64 * (nPm + 1));
   // per walker of a tile: inverse column, table, R_u, W_u, S, valid flag
@@ -620,7 +620,9 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.r_sc = rec(8);
   wf.r_RW = rec(2 * (int)(x->sp[0].sets.size() + x->sp[1].sets.size()) + 1);
   wf.hot_len = o;
-  wf.r_gc = rec(std::max(3 * x->N * x->nop, 4 * x->N));
+  // gradient cache of the DMC kernel, or the per-electron local-energy terms
+  // and structure ratios of the batched local energy
+  wf.r_gc = rec(std::max(3 * x->N * x->nop, 4 * x->N + x->nstruct));
   wf.r_bk = rec(wf.hot_len);
   wf.rec_len = (o + 31) / 32 * 32;
   // LDS: constant tables, walker state, scratch (offsets in doubles, each
@@ -677,8 +679,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // electron-tile regions of the MFMA passes; the primitive terms of a point
   // evaluation share this space (the two are never live at the same time)
   const int tile0 = o;
-  wf.l_disp = lds(kGroup * x->nnuc * 4);
-  wf.l_gtab = lds(kGroup * x->nshell * 3);
+  wf.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  wf.l_gtab = lds(kGroup * ((3 * x->nshell) | 1));
   wf.l_Phi = lds(kGroup * x->nop);
   const int tile_end = o;
   o = tile0;

@@ -12,6 +12,7 @@ constexpr int kChunk = 16;     // basis functions are padded to a multiple of th
 constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
 constexpr int kMaxSpin = 64;   // electrons per spin
 constexpr int kRedSlots = 64;  // doubles of block-reduction scratch
+constexpr int kMaxFinishN = 128;  // electrons per walker (2 x kMaxSpin)
 
 // One spin's determinant table (reference determinant + replaced columns).
 struct SpinTab {
@@ -63,7 +64,7 @@ struct DevWF {
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;
   int l_gU, l_lU, l_gD, l_lD;
   int l_disp, l_gtab, l_Phi, l_part, l_chi, l_v, l_y, l_bcol, l_z, l_pt, l_yb, l_sij, l_ratio;
-  int l_Phi4, l_yb64, l_tstage, tstage_row;
+  int l_Phi4, l_yb64, l_tstage, tstage_row, l_Rall;
   int l_Rp, l_ua, l_Vn;  // sweep kernel: trial positions, acceptance draws, trial orbital rows
   // adjoint kernel
   int l_aPhi, l_aG0, l_aG, l_aA, l_aP, l_aM, l_aU[2];

@@ -332,7 +332,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // determinant ratios, their partner sums, S and the valid flag; then forms
 // the radial tables and the four MFMA channels (gradient, Laplacian) of the
 // 16 positions, and 64 lanes = 16 walkers x 4 channels form the row-operator
-// ratios and store them in the walkers' scratch rows.
+// ratios grad_e D / D, lap_e D / D and store them in the walkers' scratch
+// rows.
 template <int PREC>
 __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf, double* state, int64_t W,
                                                    int per_block) {
@@ -361,26 +362,42 @@ __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf
     const int oT = n, oRu = n + n * nP, oWu = oRu + nU, oS = oWu + nU;
     const int per_row = 3 + oS + 2;
     const int ru0 = wf.r_RW + (s ? n0 : 0), wu0 = wf.r_RW + n0 + n1 + (s ? n0 : 0);
-    for (int idx = threadIdx.x; idx < rows * per_row; idx += 64) {
-      const int t = idx / per_row, k = idx - t * per_row;
-      const double* rec = state + (w0 + t) * wf.rec_len;
-      if (k < 3) {
-        Rt[3 * t + k] = rec[wf.r_R + 3 * e + k];
-      } else {
-        const int q = k - 3;
-        double v;
-        if (q < oT) v = rec[wf.r_B[s] + q * n + il];
-        else if (q < oRu) v = rec[wf.r_T[s] + (q - oT)];
-        else if (q < oWu) v = rec[ru0 + (q - oRu)];
-        else if (q < oS) v = rec[wu0 + (q - oWu)];
-        else if (q == oS) v = rec[wf.r_RW + 2 * (n0 + n1)];
-        else v = rec[wf.r_sc + SC_FLAGS];
-        stg[t * rowsz + q] = v;
+    // gather: 8 independent loads per lane in flight, then the LDS stores
+    const int total = rows * per_row;
+    for (int base = threadIdx.x; base < total; base += 64 * 8) {
+      double v[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + 64 * u;
+        dst[u] = -1;
+        if (idx < total) {
+          const int t = idx / per_row, k = idx - t * per_row;
+          const double* rec = state + (w0 + t) * wf.rec_len;
+          int off;
+          if (k < 3) {
+            off = wf.r_R + 3 * e + k;
+            dst[u] = wf.l_R + 3 * t + k;
+          } else {
+            const int q = k - 3;
+            if (q < oT) off = wf.r_B[s] + q * n + il;
+            else if (q < oRu) off = wf.r_T[s] + (q - oT);
+            else if (q < oWu) off = ru0 + (q - oRu);
+            else if (q < oS) off = wu0 + (q - oWu);
+            else if (q == oS) off = wf.r_RW + 2 * (n0 + n1);
+            else off = wf.r_sc + SC_FLAGS;
+            dst[u] = wf.l_tstage + t * rowsz + q;
+          }
+          v[u] = rec[off];
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dst[u] >= 0) l.L[dst[u]] = v[u];
     }
     __syncthreads();
     group_radial<64, PREC>(wf, l, Rt, 0, rows);
-    for (int c = 1; c <= 4; ++c) group_channel<64, PREC>(wf, l, rows, c, Phi4 + (c - 1) * kGroup * nop);
+    group_channels4<64, PREC>(wf, l, rows, Phi4);
     {
       const int t = threadIdx.x >> 2, c = threadIdx.x & 3;
       if (t < rows) {
@@ -396,55 +413,101 @@ __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf
   }
 }
 
-// Per walker: Jastrow, potential, E_L from the tile results, accumulators.
+// Per walker: Jastrow gradients and Laplacians and the potential, E_L from
+// the tile results (Eq. Elav with Psi = e^U D), accumulators, and the
+// structure-ratio products r_I r_J (Sec. 2.4) when requested.  Lanes are
+// (electron i, part p) with the partners of i split P ways; every global
+// read is issued at the start.
 __global__ __launch_bounds__(64) void k_eloc_finish(const DevWF* __restrict__ pwf, double* state, int64_t W,
                                                     double* e_sum, double* e2_sum, double* e_last,
                                                     double* sij_sum) {
+  __shared__ double sR[3 * kMaxFinishN];
+  __shared__ double sred[4];
   const DevWF& wf = *pwf;
-  int64_t w = blockIdx.x;
+  const int64_t w = blockIdx.x;
   if (w >= W) return;
-  Ld l(lds_dyn, wf);
-  // only the nuclei and the e-n parameters are needed here
-  for (int k = threadIdx.x; k < 4 * wf.nnuc; k += 64) l.L[wf.l_nuc + k] = wf.nuc[k];
-  for (int k = threadIdx.x; k < 6 * wf.nnuc; k += 64) l.L[wf.l_en + k] = wf.en[k];
-  double* rec = state + w * wf.rec_len;
-  for (int k = threadIdx.x; k < 3 * wf.N; k += 64) l.R()[k] = rec[wf.r_R + k];
-  __syncthreads();
-  jastrow_full<64>(wf, l, l.R());
-  double part[1] = {0.0};
-  for (int i = threadIdx.x; i < wf.N; i += 64) {
-    const double* d = rec + wf.r_gc + 4 * i;
-    double t = l.lU()[i] + d[3];
-    for (int x = 0; x < 3; ++x) {
-      double gu = l.gU()[3 * i + x];
-      t += gu * gu + 2.0 * gu * d[x];
-    }
-    part[0] += -0.5 * t;
-  }
-  block_sum<64, 1>(part, l.red());
+  const int N = wf.N, nn = wf.nnuc;
+  const double* rec = state + w * wf.rec_len;
+  // per lane: positions, then its electrons' gD / lD
+  const int P = N <= 16 ? 4 : (N <= 32 ? 2 : 1);
+  const int lanes_e = 64 / P;
+  const int p = threadIdx.x % P;
+  for (int k = threadIdx.x; k < 3 * N; k += 64) sR[k] = rec[wf.r_R + k];
   const bool bad = rec[wf.r_sc + SC_FLAGS] != 0.0;
-  const double el = part[0] + l.sc()[SC_V];
+  const double es0 = threadIdx.x == 0 ? e_sum[w] : 0.0, e2s0 = threadIdx.x == 0 ? e2_sum[w] : 0.0;
+  __syncthreads();
+  const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
+  double tsum = 0.0, vsum = 0.0;
+  for (int i0 = 0; i0 < N; i0 += lanes_e) {
+    const int i = i0 + threadIdx.x / P;
+    double gx = 0.0, gy = 0.0, gz = 0.0, lap = 0.0, V = 0.0;
+    double gD[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < N) {
+      if (p == 0)
+        for (int c = 0; c < 4; ++c) gD[c] = rec[wf.r_gc + 4 * i + c];
+      const double xi = sR[3 * i], yi = sR[3 * i + 1], zi = sR[3 * i + 2];
+      const int si = spin_of(wf, i);
+      for (int j = p; j < N + nn; j += P) {
+        if (j == i) continue;
+        double xj, yj, zj, wv;
+        PairCoef cf;
+        if (j < N) {
+          xj = sR[3 * j]; yj = sR[3 * j + 1]; zj = sR[3 * j + 2];
+          cf = si != spin_of(wf, j) ? c_anti : c_par;
+          wv = 0.5;
+        } else {
+          const int a = j - N;
+          xj = wf.nuc[4 * a]; yj = wf.nuc[4 * a + 1]; zj = wf.nuc[4 * a + 2];
+          cf = en_coef(wf.en + 6 * a);
+          wv = -wf.nuc[4 * a + 3];
+        }
+        const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double u, u1, u2;
+        pair_fn(r, wf.kappa, cf, u, u1, u2);
+        const double f = u1 / r;
+        gx += f * dx; gy += f * dy; gz += f * dz;
+        lap += u2 + 2.0 * f;
+        V += wv / r;
+      }
+    }
+    for (int off = 1; off < P; off <<= 1) {
+      gx += __shfl_xor(gx, off, 64);
+      gy += __shfl_xor(gy, off, 64);
+      gz += __shfl_xor(gz, off, 64);
+      lap += __shfl_xor(lap, off, 64);
+      V += __shfl_xor(V, off, 64);
+    }
+    if (i < N && p == 0) {
+      tsum += lap + gD[3] + gx * gx + gy * gy + gz * gz + 2.0 * (gx * gD[0] + gy * gD[1] + gz * gD[2]);
+      vsum += V;
+    }
+  }
+  double part[2] = {tsum, vsum};
+  block_sum<64, 2>(part, sred);
   if (threadIdx.x == 0) {
-    rec[wf.r_sc + SC_ELOC] = bad ? NAN : el;
+    double* r = state + w * wf.rec_len;
+    const double el = -0.5 * part[0] + part[1] + wf.vnn;
+    r[wf.r_sc + SC_ELOC] = bad ? NAN : el;
     if (!bad) {
-      e_sum[w] += el;
-      e2_sum[w] += el * el;
+      e_sum[w] = es0 + el;
+      e2_sum[w] = e2s0 + el * el;
     }
     e_last[w] = bad ? NAN : el;
   }
   if (sij_sum && !bad) {
     const int nv = wf.nstruct, n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
     const double* RW = rec + wf.r_RW;
-    const double S = RW[2 * (n0 + n1)];
-    double* rt = l.ratio();
+    const double iS = 1.0 / RW[2 * (n0 + n1)];
+    double* rt = state + w * wf.rec_len + wf.r_gc + 4 * N;  // r_I, after the tile results
     for (int I = threadIdx.x; I < nv; I += 64) {
       double a = 0.0;
       for (int k = wf.srow[I]; k < wf.srow[I + 1]; ++k) a += wf.slc[k] * RW[wf.slu[2 * k]] * RW[n0 + wf.slu[2 * k + 1]];
-      rt[I] = a / S;
+      rt[I] = a * iS;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nv * nv; k += 64) {
-      int I = k / nv, J = k - I * nv;
+      const int I = k / nv, J = k - I * nv;
       sij_sum[w * nv * nv + k] += rt[I] * rt[J];
     }
   }
@@ -836,10 +899,8 @@ static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const De
                                      double* na, double* el, double* sij, hipStream_t s) {
   size_t lds_sw = (size_t)wf.lds_sweep_doubles * sizeof(double);
   size_t lds_ti = (size_t)wf.lds_tile_doubles * sizeof(double);
-  size_t lds_fi = (size_t)wf.lds_finish_doubles * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_sweep<NT, PREC>, lds_sw);
   if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_tiles<PREC>, lds_ti);
-  if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_finish, lds_fi);
   if (e != hipSuccess) return e;
   const int64_t ntiles = (W + kGroup - 1) / kGroup * wf.N;
   const int per_block = 2;
@@ -855,8 +916,7 @@ static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const De
     }
     if (phases & 2) {
       hipLaunchKernelGGL((k_eloc_tiles<PREC>), dim3(tblocks), dim3(64), lds_ti, s, dwf_aux, state, W, per_block);
-      hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)W), dim3(64), lds_fi, s, dwf_aux, state, W, es, e2s, el,
-                         sij);
+      hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)W), dim3(64), 0, s, dwf_aux, state, W, es, e2s, el, sij);
     }
   }
   return hipGetLastError();
