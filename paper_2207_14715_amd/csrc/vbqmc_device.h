@@ -338,6 +338,7 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
     T r2 = disp[e * ds + 4 * si[0] + 3], r = sqrt(r2);
     T g = 0, g1 = 0, g2 = 0;
     if (e < ne) {
+#pragma unroll 2
       for (int k = 0; k < si[5]; ++k) {
         T a = (T)l.pe()[si[4] + k];
         T t = si[1] == 0 ? a * r2 : a * r;

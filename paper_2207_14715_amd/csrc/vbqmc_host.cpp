@@ -272,8 +272,8 @@ DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
   LdsAlloc w{0};
   a.l_R = w(3 * x->N);
   a.l_sc = w(SC_COUNT);
-  a.l_ipiv = w.ints(nmax);
-  a.l_f = w(nmax);
+  a.l_ipiv = w.ints(2 * nmax);  // one pivot list and column per spin
+  a.l_f = w(2 * nmax);
   for (int s = 0; s < 2; ++s) {
     int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
     a.l_B[s] = w(n * n);

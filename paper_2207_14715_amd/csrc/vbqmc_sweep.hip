@@ -35,10 +35,31 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// floor(idx / d) for 0 <= idx < 2^20, given rd = 1.0f / d: (idx + 0.5) / d lies
+// at least 0.5 / d from an integer, far beyond the float rounding of the product
+__device__ __forceinline__ int div_small(int idx, float rd) { return (int)(((float)idx + 0.5f) * rd); }
+
+// DPP move of a double within 16-lane rows (ctrl: a GFX9 DPP control word)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the G lanes of a group, the same bits in every lane: a butterfly
+// whose in-row steps are DPP row rotations by 8 and 4 (equal to xor 8 and
+// xor 4 once the previous steps have made the values symmetric) and quad
+// permutations for xor 2 and xor 1; the step across 16-lane rows (G = 32)
+// is a lane permute.
 template <int G>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  static_assert(G == 16 || G == 32, "group of 16 or 32 lanes");
+  if constexpr (G == 32) v += __shfl_xor(v, 16, 32);
+  v += dpp_mov<0x128>(v);  // row_ror:8
+  v += dpp_mov<0x124>(v);  // row_ror:4
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
   return v;
 }
 
@@ -106,50 +127,53 @@ __device__ void compute_RWS_g(const DevWF& wf, const Lg& l) {
   wave_sync();
 }
 
-// In-place Gauss-Jordan inverse with partial pivoting of one walker's n x n
-// matrix A (rows electrons, columns reference slots) -> A^{-1}.  Returns false
-// if a pivot is exactly zero.
-template <int G>
-__device__ bool gj_invert_g(const Lg& l, double* A, int n, double& logdet, double& sgn) {
-  int* piv = l.ipiv();
-  double* f = l.f();
-  const int q = l.q;
-  logdet = 0.0;
+// In-place Gauss-Jordan inverse with partial pivoting of an n x n matrix A
+// (rows electrons, columns reference slots) -> A^{-1} by the H lanes qh of a
+// half group.  log|det A| is accumulated as a mantissa product and an
+// exponent sum (one log at the end).  Returns false if a pivot is exactly
+// zero.
+template <int H>
+__device__ bool gj_invert_h(double* A, int n, int qh, int* piv, double* f, double& logdet, double& sgn) {
+  const float rn = 1.0f / (float)n;
+  double mant = 1.0;
+  int ex = 0;
   sgn = 1.0;
   for (int k = 0; k < n; ++k) {
     double best = -1.0;
     int bi = n;
-    for (int i = k + q; i < n; i += G) {
+    for (int i = k + qh; i < n; i += H) {
       double v = fabs(A[i * n + k]);
       if (v > best) { best = v; bi = i; }
     }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-      double ob = __shfl_xor(best, off, G);
-      int oi = __shfl_xor(bi, off, G);
+    for (int off = H / 2; off > 0; off >>= 1) {
+      double ob = __shfl_xor(best, off, H);
+      int oi = __shfl_xor(bi, off, H);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
     if (!(best > 0.0)) return false;
     const int p = bi;
-    if (q == 0) piv[k] = p;
+    if (qh == 0) piv[k] = p;
     if (p != k)
-      for (int j = q; j < n; j += G) {
+      for (int j = qh; j < n; j += H) {
         double t = A[k * n + j];
         A[k * n + j] = A[p * n + j];
         A[p * n + j] = t;
       }
     wave_sync();
-    double pv = A[k * n + k];
-    logdet += log(fabs(pv));
+    const double pv = A[k * n + k];
+    int e2;
+    mant = frexp(mant * fabs(pv), &e2);
+    ex += e2;
     if (pv < 0) sgn = -sgn;
     if (p != k) sgn = -sgn;
-    for (int i = q; i < n; i += G) f[i] = A[i * n + k];
+    for (int i = qh; i < n; i += H) f[i] = A[i * n + k];
     wave_sync();
-    double ip = 1.0 / pv;
-    for (int j = q; j < n; j += G) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * ip;
+    const double ip = 1.0 / pv;
+    for (int j = qh; j < n; j += H) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * ip;
     wave_sync();
-    for (int idx = q; idx < n * n; idx += G) {
-      int i = idx / n, j = idx - i * n;
+    for (int idx = qh; idx < n * n; idx += H) {
+      int i = div_small(idx, rn), j = idx - i * n;
       if (i != k) A[idx] = (j == k ? 0.0 : A[idx]) - f[i] * A[k * n + j];
     }
     wave_sync();
@@ -157,37 +181,48 @@ __device__ bool gj_invert_g(const Lg& l, double* A, int n, double& logdet, doubl
   for (int k = n - 1; k >= 0; --k) {
     int p = piv[k];
     if (p != k)
-      for (int i = q; i < n; i += G) {
+      for (int i = qh; i < n; i += H) {
         double t = A[i * n + k];
         A[i * n + k] = A[i * n + p];
         A[i * n + p] = t;
       }
     wave_sync();
   }
+  logdet = log(mant) + (double)ex * 0.69314718055994530942;
   return true;
 }
 
-// invert the staged reference matrices (in B) and form T = B PP
+// Invert the staged reference matrices (in B) and form T = B PP.  The two
+// halves of the group take one spin each.
 template <int G>
 __device__ bool finish_state_g(const DevWF& wf, const Lg& l) {
+  constexpr int H = G / 2;
+  const int s = l.q / H, qh = l.q - s * H;
+  const int nmax = max(wf.sp[0].n, wf.sp[1].n);
+  const SpinTab& st = wf.sp[s];
+  double ld = 0.0, sg = 1.0;
   bool ok = true;
-  for (int s = 0; s < 2; ++s) {
-    const SpinTab& st = wf.sp[s];
-    double ld = 0.0, sg = 1.0;
-    if (st.n > 0 && !gj_invert_g<G>(l, l.B(s), st.n, ld, sg)) ok = false;
-    if (l.q == 0) {
-      l.sc()[SC_LOGDET0 + s] = ld;
-      l.sc()[SC_SGN0 + s] = sg;
-      l.sc()[SC_NUPD0 + s] = 0.0;
-    }
-    for (int idx = l.q; idx < st.n * st.nP; idx += G) {
-      int j = idx / st.nP, c = idx - j * st.nP;
-      double a = 0.0;
-      for (int i = 0; i < st.n; ++i) a += l.B(s)[j * st.n + i] * l.PP(s)[i * st.nP + c];
-      l.T(s)[idx] = a;
-    }
-    wave_sync();
+  if (st.n > 0) ok = gj_invert_h<H>(l.B(s), st.n, qh, l.ipiv() + s * nmax, l.f() + s * nmax, ld, sg);
+  if (qh == 0) {
+    l.sc()[SC_LOGDET0 + s] = ld;
+    l.sc()[SC_SGN0 + s] = sg;
+    l.sc()[SC_NUPD0 + s] = 0.0;
   }
+  // both halves must have succeeded
+  const bool ok_other = __shfl_xor((int)ok, H, G) != 0;
+  ok = ok && ok_other;
+  wave_sync();
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const SpinTab& t2 = wf.sp[s2];
+    const float rp = 1.0f / (float)max(t2.nP, 1);
+    for (int idx = l.q; idx < t2.n * t2.nP; idx += G) {
+      int j = div_small(idx, rp), c = idx - j * t2.nP;
+      double a = 0.0;
+      for (int i = 0; i < t2.n; ++i) a += l.B(s2)[j * t2.n + i] * l.PP(s2)[i * t2.nP + c];
+      l.T(s2)[idx] = a;
+    }
+  }
+  wave_sync();
   return ok;
 }
 
@@ -287,12 +322,13 @@ __device__ void accept_move_g(const DevWF& wf, const Lg& l, int i, double px, do
   const double ir = 1.0 / rho;
   const double* bc = l.bcol();
   const double* y = l.y();
+  const float rn = 1.0f / (float)n, rp = 1.0f / (float)max(nP, 1);
   for (int idx = q; idx < n * n; idx += G) {
-    int j = idx / n, m = idx - j * n;
+    int j = div_small(idx, rn), m = idx - j * n;
     B[idx] -= bc[j] * (z[m] * ir);
   }
   for (int idx = q; idx < n * nP; idx += G) {
-    int j = idx / nP, c = idx - j * nP;
+    int j = div_small(idx, rp), c = idx - j * nP;
     T[idx] += bc[j] * (y[c] * ir);
   }
   if (q == 0) {
@@ -360,6 +396,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   __syncthreads();
   double* sc = lg.sc();
+  const double na0 = live && q == 0 ? n_acc[w] : 0.0;  // read early: the tail then only stores
   bool bad = true;
   if (live) {
     compute_RWS_g<G>(wf, lg);
@@ -410,14 +447,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // refresh the walkers that reached the update limit: reference and table
   // rows at the current positions on MFMA (trial rows are dead here)
   const bool need = live && !bad && (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every);
-  if (__any(need)) {
-    {
+  const unsigned long long lead = __ballot(need && q == 0);  // one bit per group that refreshes
+  if (lead) {
+    // rows of the refreshing walkers only, packed in group order
+    const int slot = __popcll(lead & ((1ull << (g * G)) - 1ull));
+    const int nrows = __popcll(lead) * N;
+    if (need) {
       const double* R = lg.R();
-      for (int k = q; k < 3 * N; k += G) Rp[3 * g * N + k] = need ? R[k] : 0.0;
+      for (int k = q; k < 3 * N; k += G) Rp[3 * slot * N + k] = R[k];
     }
     __syncthreads();
-    for (int g0 = 0; g0 < NG * N; g0 += kGroup) {
-      const int ne = min(kGroup, NG * N - g0);
+    for (int g0 = 0; g0 < nrows; g0 += kGroup) {
+      const int ne = min(kGroup, nrows - g0);
       group_radial<64, PREC, 1>(wf, l, Rp, g0, ne);
       group_channel<64, PREC, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
     }
@@ -427,9 +468,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int wdt = st.n + st.nP;
         const int* ref = lg.ref(s);
         const int* porb = lg.porb(s);
+        const float rw = 1.0f / (float)wdt;
         for (int idx = q; idx < st.n * wdt; idx += G) {
-          const int il = idx / wdt, j = idx - il * wdt;
-          const double* row = Vn + (size_t)(g * N + st.e0 + il) * wf.nop;
+          const int il = div_small(idx, rw), j = idx - il * wdt;
+          const double* row = Vn + (size_t)(slot * N + st.e0 + il) * wf.nop;
           if (j < st.n) lg.B(s)[il * st.n + j] = row[ref[j]];
           else lg.PP(s)[il * st.nP + (j - st.n)] = row[porb[j - st.n]];
         }
@@ -466,7 +508,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       rec[wf.r_RW + k] = v;
     }
   }
-  if (live && q == 0) n_acc[w] += na;
+  if (live && q == 0) n_acc[w] = na0 + na;
 }
 
 template <int G, int PREC>
