@@ -350,10 +350,18 @@ __global__ __launch_bounds__(64) void k_eloc_tiles(const DevWF* __restrict__ pwf
   double* yb = l.L + wf.l_yb64;
   double* stg = l.L + wf.l_tstage;
   const int rowsz = wf.tstage_row;
-  for (int64_t tile = (int64_t)blockIdx.x * per_block; tile < min(ntiles, (int64_t)(blockIdx.x + 1) * per_block);
-       ++tile) {
-    const int64_t wb = tile / N;
-    const int e = (int)(tile - wb * N);
+  // Workgroups go to the 8 XCDs round-robin (block b -> XCD b mod 8), each XCD
+  // with its own L2.  Block b works on the walker blocks wb = x (mod 8) of
+  // its XCD x, so all N tiles of a walker block read its records through
+  // one L2.
+  const int x = blockIdx.x & (kXcds - 1);
+  const int64_t jb = blockIdx.x / kXcds;
+  const int64_t nwb_x = nwb > x ? (nwb - x + kXcds - 1) / kXcds : 0;
+  const int64_t ntiles_x = nwb_x * N;
+  (void)ntiles;
+  for (int64_t tl = jb * per_block; tl < min(ntiles_x, (jb + 1) * per_block); ++tl) {
+    const int64_t wb = (tl / N) * kXcds + x;
+    const int e = (int)(tl - (tl / N) * N);
     const int64_t w0 = wb * kGroup;
     const int rows = (int)min((int64_t)kGroup, W - w0);
     const int s = spin_of(wf, e);
@@ -902,9 +910,11 @@ static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const De
   hipError_t e = set_lds<NT, PREC>((const void*)k_sweep<NT, PREC>, lds_sw);
   if (e == hipSuccess) e = set_lds<64, PREC>((const void*)k_eloc_tiles<PREC>, lds_ti);
   if (e != hipSuccess) return e;
-  const int64_t ntiles = (W + kGroup - 1) / kGroup * wf.N;
+  // tiles per XCD (walker blocks wb = x mod 8), rounded up to whole blocks
+  const int64_t nwb = (W + kGroup - 1) / kGroup;
   const int per_block = 2;
-  const unsigned tblocks = (unsigned)((ntiles + per_block - 1) / per_block);
+  const int64_t per_xcd = ((nwb + kXcds - 1) / kXcds * wf.N + per_block - 1) / per_block;
+  const unsigned tblocks = (unsigned)(per_xcd * kXcds);
   for (int st = 0; st < nsteps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
     if ((phases & 1) && G < 64) {
