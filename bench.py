@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--form", default="plain", choices=["plain", "precision", "adjoint"],
+    ap.add_argument("--form", default="plain", choices=["plain", "precision", "adjoint", "dmc"],
                     help="plain: the headline VMC line; precision: FP32/BF16 basis+contraction form on the "
                          "10-nucleus molecule; adjoint: parameter gradients on the 6-nucleus molecule")
     args = ap.parse_args()
@@ -142,6 +142,8 @@ def main():
         return precision_form(args)
     if args.form == "adjoint":
         return adjoint_form(args)
+    if args.form == "dmc":
+        return dmc_form(args)
     if args.calibrate_copy:
         n = 256 * 1024 * 1024 // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -252,18 +254,19 @@ def precision_form(args):
     W = args.walkers if args.walkers != 4096 else 16384
     steps, step_size, seed = args.steps if args.steps != 200 else 20, 0.3, 777
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=9)).cuda()
-    c64 = vb.Context(system, precision="fp64")
+    c64 = vb.Context(system, precision="fp64", walker_lanes=args.walker_lanes)
     st = c64.walkers_init(R0)
     c64.vmc_advance(st, args.warmup, seed, 0, step_size)  # burn-in in FP64
     Rb = c64.positions(st)
     ref = c64.evaluate(Rb, want=("eloc",))["eloc"]
     res = {"metric": "walker-moves/sec incl. E_L (precision forms)", "unit": "walker-moves/s", "n_gpus": 1,
-           "walkers": W, "steps": steps, "data": "synthetic",
+           "walkers": W, "steps": steps, "data": "synthetic", "sweep_lanes": c64.info["sweep_lanes"],
            "config": {"workload": "10 nuclei (Z in {1,6,7,8}), 40 electrons, 150 Gaussian basis functions, "
                                   "20 VB structures / 64 determinants, VMC single-electron moves 0.3 bohr, "
                                   "E_L every step, inverse refresh every 32 updates"}, "forms": {}}
     for prec in ("fp64", "fp32", "bf16"):
-        ctx = c64 if prec == "fp64" else vb.Context(system, precision=prec, refresh_every=32)
+        ctx = c64 if prec == "fp64" else vb.Context(system, precision=prec, refresh_every=32,
+                                                     walker_lanes=args.walker_lanes)
         ev = ctx.evaluate(Rb, want=("eloc",))["eloc"]
         d = (ev - ref).abs().cpu().numpy()
         stp = ctx.walkers_init(Rb.clone())
@@ -322,6 +325,51 @@ def adjoint_form(args):
                                    "flops_per_gradient": adjoint_flops_per_gradient(ctx, system)},
                       "config": {"workload": "6 nuclei, 30 electrons, 120 Gaussian basis functions, 12 VB "
                                              "structures / 40 determinants, kappa = 0.8 Jastrow with polynomials"}}))
+
+
+def dmc_form(args):
+    """Fixed-node DMC on the 16-nucleus, 64-electron, 240-function,
+    32-structure / 128-determinant molecule: 32768 target walkers,
+    tau = 0.005, per-electron drift-diffusion moves with Metropolis
+    acceptance, branching with population control and on-device compaction.
+    Walkers start from a short FP64 VMC burn-in; walker-moves/s counts the
+    walkers present at each timed step."""
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    system = S.dmc_molecule()
+    W = args.walkers if args.walkers != 4096 else 32768
+    steps = args.steps if args.steps != 200 else 4
+    warm = args.warmup if args.warmup != 20 else 1
+    tau = 0.005
+    ctx = vb.Context(system)
+    cap = 3 * W
+    st = [ctx.new_state(cap), ctx.new_state(cap)]
+    R0 = torch.from_numpy(S.initial_walkers(system, W, seed=13)).cuda()
+    ctx.walkers_init(R0, st[0])
+    ctx.vmc_advance(st[0], 3, 17, 0, 0.3, False, None, W)  # burn-in
+    # the synthetic trial function has a wide E_L distribution: start E_T at
+    # the median so that the population does not run away in the first steps
+    et = float(ctx.record_eloc(st[0], W).median().item())
+    out = ctx.dmc_advance(st, W, warm, 2022, 0, tau, et, W)
+    Wc, et = out["W"], out["e_trial"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.dmc_advance(st, Wc, steps, 2022, warm, tau, et, W)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    pop = out["pop"].cpu().numpy()
+    moves = float(pop.sum())
+    print(json.dumps({"metric": "walker-moves/sec incl. E_L (DMC)", "value": moves / t, "unit": "walker-moves/s",
+                      "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": t / steps * 1e3,
+                      "population": [int(p) for p in pop], "e_trial": out["e_trial"],
+                      "acceptance": float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1)),
+                      "data": "synthetic", "dtype": "f64",
+                      "config": {"workload": "16 nuclei (Z in {1,6,8}), 64 electrons, 240 Gaussian basis functions, "
+                                             "32 VB structures / 128 determinants, tau = 0.005, per-electron "
+                                             "drift-diffusion moves, branching and compaction",
+                                 "target_walkers": W}}))
 
 
 if __name__ == "__main__":

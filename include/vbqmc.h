@@ -107,8 +107,8 @@ typedef struct {
  * walker_lanes: lanes of a 64-lane wavefront given to one walker in the
  * single-electron VMC sweep: 16 or 32 (several walkers per wavefront, if
  * their state fits in LDS), 64 (one walker per workgroup), or 0 to let the
- * library choose from the spin-determinant size.  Results do not depend on
- * it beyond rounding. */
+ * library choose (32 when a spin has at most 32 electrons and two walkers
+ * fit in LDS, else 64).  Results do not depend on it beyond rounding. */
 typedef struct {
   int32_t precision;
   int32_t refresh_every;

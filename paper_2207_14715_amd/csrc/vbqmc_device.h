@@ -1012,11 +1012,12 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
       if (o < nout && pt_ == 0) l.v()[o] = a;
     }
   } else {
+    // lam may be in global memory here: 16 loads in flight per thread
     for (int o = threadIdx.x; o < nout; o += NT) {
       int c = o / wf.nop, p = o - c * wf.nop;
       const T* ch = chi + c * wf.Mpad;
       T acc = T(0);
-#pragma unroll 4
+#pragma unroll 16
       for (int mu = 0; mu < wf.Mpad; ++mu) acc += ch[mu] * (T)lam[(size_t)mu * wf.nop + p];
       l.v()[o] = (double)acc;
     }

@@ -744,9 +744,9 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     } else if (req == 64) {
       x->sweep_g = 64;
     } else if (req == 0) {
-      // two walkers per wavefront for small spin determinants; larger ones
-      // keep a workgroup per walker
-      x->sweep_g = nmax <= 16 && fits(32) ? 32 : 64;
+      // two walkers per wavefront (measured best for 9 and 20 electrons per
+      // spin); a workgroup per walker when that does not fit LDS
+      x->sweep_g = nmax <= 32 && fits(32) ? 32 : 64;
     } else {
       return bad("walker_lanes must be 0, 16, 32 or 64");
     }

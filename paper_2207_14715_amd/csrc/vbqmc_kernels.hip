@@ -630,7 +630,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const double* R = l.R();
     double rx = R[3 * i], ry = R[3 * i + 1], rz = R[3 * i + 2];
     double v[3];
-    drift<NT>(wf, l, i, gc + (size_t)i * 3 * wf.nop, wf.nop, rx, ry, rz, nullptr, 0.0, nullptr, 0.0, v);
+    // the cached gradient rows of electron i, staged into LDS in one copy
+    double* grow = l.part();
+    for (int k = threadIdx.x; k < 3 * wf.nop; k += NT) grow[k] = gc[(size_t)i * 3 * wf.nop + k];
+    __syncthreads();
+    drift<NT>(wf, l, i, grow, wf.nop, rx, ry, rz, nullptr, 0.0, nullptr, 0.0, v);
     double a0, a1, b0, b1;
     philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
     philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
