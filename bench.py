@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--walker-lanes", type=int, default=0, choices=[0, 16, 32, 64],
                     help="lanes per walker in the single-electron sweep (0: library choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-exponent", type=float, default=1e4,
+                    help="precision form: cap on the Gaussian exponents of the molecule (default: the workload's 1e4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--form", default="plain", choices=["plain", "precision", "adjoint", "dmc"],
@@ -250,7 +252,7 @@ def precision_form(args):
 
     import paper_2207_14715_amd as vb
     import systems as S
-    system = S.precision_molecule()
+    system = S.precision_molecule(max_exponent=args.max_exponent)
     W = args.walkers if args.walkers != 4096 else 16384
     steps, step_size, seed = args.steps if args.steps != 200 else 20, 0.3, 777
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=9)).cuda()
@@ -263,7 +265,8 @@ def precision_form(args):
            "walkers": W, "steps": steps, "data": "synthetic", "sweep_lanes": c64.info["sweep_lanes"],
            "config": {"workload": "10 nuclei (Z in {1,6,7,8}), 40 electrons, 150 Gaussian basis functions, "
                                   "20 VB structures / 64 determinants, VMC single-electron moves 0.3 bohr, "
-                                  "E_L every step, inverse refresh every 32 updates"}, "forms": {}}
+                                  "E_L every step, inverse refresh every 32 updates",
+                      "max_exponent": args.max_exponent}, "forms": {}}
     for prec in ("fp64", "fp32", "bf16"):
         ctx = c64 if prec == "fp64" else vb.Context(system, precision=prec, refresh_every=32,
                                                      walker_lanes=args.walker_lanes)

@@ -186,13 +186,13 @@ def f2_shaped(seed=1001):
 
 def _molecule(seed, name, n_nuc, zchoices, ztotal, side, shell_spec, n_inactive,
               n_active_per_atom, active_atoms, struct_counts, jastrow_kind,
-              delocal_sigma=0.1, active_perturb=0.0):
+              delocal_sigma=0.1, active_perturb=0.0, max_exponent=1e4):
     rng = np.random.default_rng(seed)
     pos = _place_nuclei(rng, n_nuc, side, 2.0)
     Z = _charges(rng, n_nuc, zchoices, ztotal).astype(float)
     shells = []
     for a in range(n_nuc):
-        shells += _gto_shells(rng, a, shell_spec, 3, 8, 0.05, 1e4)
+        shells += _gto_shells(rng, a, shell_spec, 3, 8, 0.05, max_exponent)
     blocks = _atom_blocks(shells, n_nuc)
     M = sum(_L_NFUNC[s["l"]] for s in shells)
     n_act = n_active_per_atom * len(active_atoms)
@@ -234,14 +234,18 @@ def _molecule(seed, name, n_nuc, zchoices, ztotal, side, shell_spec, n_inactive,
             "structures": structures, "jastrow": jas}
 
 
-def precision_molecule(seed=1002):
+def precision_molecule(seed=1002, max_exponent=1e4):
     """10 nuclei (Z in {1,6,7,8}, sum 40) in a 12-bohr box, 4s2p1d per atom
     (150 functions), 18 delocalised inactive orbitals + 8 active on 8 distinct
-    atoms, 20 structures (14 two-pair, 2 pair+self, 4 self+self) = 64 dets."""
+    atoms, 20 structures (14 two-pair, 2 pair+self, 4 self+self) = 64 dets.
+    max_exponent caps the Gaussian exponents (log-uniform from 0.05); every
+    other draw is the same for any cap."""
     rng = np.random.default_rng(seed + 7)
     act_atoms = sorted(rng.choice(10, size=8, replace=False).tolist())
-    return _molecule(seed, "precision_molecule", 10, [1, 6, 7, 8], 40, 12.0,
-                     [(0, 4), (1, 2), (2, 1)], 18, 1, act_atoms, (14, 2, 4), "pade")
+    name = "precision_molecule" if max_exponent == 1e4 else f"precision_molecule_amax{max_exponent:g}"
+    return _molecule(seed, name, 10, [1, 6, 7, 8], 40, 12.0,
+                     [(0, 4), (1, 2), (2, 1)], 18, 1, act_atoms, (14, 2, 4), "pade",
+                     max_exponent=max_exponent)
 
 
 def adjoint_molecule(seed=1003):
