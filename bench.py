@@ -27,7 +27,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 # HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker)
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
 # calibration; None until measured for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = 17.71e6
+TRAFFIC_BYTES_PER_LAUNCH = None
 TRAFFIC_LANES = 32
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 

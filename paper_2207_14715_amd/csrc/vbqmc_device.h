@@ -73,12 +73,15 @@ __device__ __forceinline__ PairCoef ee_coef(const DevWF& wf, bool anti) {
 
 __device__ __forceinline__ PairCoef en_coef(const double* e) { return {e[0], e[1], e[2], e[3], e[4], e[5]}; }
 
+// 1 + bR = (den + b r) / den with den = 1 + kappa r, so the two reciprocals
+// below are independent (they overlap instead of chaining)
 __device__ __forceinline__ void pair_fn(double r, double kappa, const PairCoef& c, double& u, double& u1,
                                         double& u2) {
   double den = 1.0 + kappa * r;
   double iden = 1.0 / den;
+  double id2 = 1.0 / (den + c.b * r);
   double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
-  double ib = 1.0 / (1.0 + c.b * R);
+  double ib = den * id2;
   u = c.a * R * ib;
   double uR = c.a * ib * ib;
   double uRR = -2.0 * c.a * c.b * ib * ib * ib;
@@ -97,8 +100,9 @@ __device__ __forceinline__ void pair_fn(double r, double kappa, const PairCoef& 
 }
 
 __device__ __forceinline__ double pair_val(double r, double kappa, const PairCoef& c) {
-  double R = r / (1.0 + kappa * r);
-  double u = c.a * R / (1.0 + c.b * R);
+  double den = 1.0 + kappa * r;
+  double R = r / den;
+  double u = c.a * r / (den + c.b * r);  // a R / (1 + b R), independent of the division above
   double R2 = R * R;
   return u + R2 * (c.q0 + R * (c.q1 + R * (c.q2 + R * c.q3)));
 }
@@ -790,27 +794,27 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
     double gx = 0, gy = 0, gz = 0, lap = 0, Ui = 0, Vi = 0;
     for (int a = 0; a < wf.nnuc; ++a) {
       double dx = xi - nuc[4 * a], dy = yi - nuc[4 * a + 1], dz = zi - nuc[4 * a + 2];
-      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      double r = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / r, u, u1, u2;
       const double* ja = l.en() + 6 * a;
       pair_fn(r, wf.kappa, en_coef(ja), u, u1, u2);
       Ui += u;
-      double f = u1 / r;
+      double f = u1 * ir;
       gx += f * dx; gy += f * dy; gz += f * dz;
       lap += u2 + 2.0 * f;
-      Vi -= nuc[4 * a + 3] / r;
+      Vi -= nuc[4 * a + 3] * ir;
     }
     int si = spin_of(wf, i);
     for (int j = 0; j < wf.N; ++j) {
       if (j == i) continue;
       double dx = xi - Rsrc[3 * j], dy = yi - Rsrc[3 * j + 1], dz = zi - Rsrc[3 * j + 2];
-      double r = sqrt(dx * dx + dy * dy + dz * dz), u, u1, u2;
+      double r = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / r, u, u1, u2;
       bool anti = si != spin_of(wf, j);
       pair_fn(r, wf.kappa, ee_coef(wf, anti), u, u1, u2);
       Ui += 0.5 * u;
-      double f = u1 / r;
+      double f = u1 * ir;
       gx += f * dx; gy += f * dy; gz += f * dz;
       lap += u2 + 2.0 * f;
-      Vi += 0.5 / r;
+      Vi += 0.5 * ir;
     }
     l.gU()[3 * i] = gx; l.gU()[3 * i + 1] = gy; l.gU()[3 * i + 2] = gz;
     l.lU()[i] = lap;

@@ -297,7 +297,11 @@ DevWF aux_layout(const vbqmc_ctx* x) {
   DevWF a = x->wf;
   int nPm = 1;
   for (int s = 0; s < 2; ++s) nPm = std::max(nPm, (int)x->sp[s].porb.size());
-  LdsAlloc lds{a.timg_len};
+  // the orbital coefficients are read from global memory here (more tiles
+  // resident per CU); the rest of the table image is staged
+  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
   a.l_R = lds(std::max(3 * x->N, 3 * kGroup));
   a.l_sc = lds(SC_COUNT);
   a.l_red = lds(kRedSlots);

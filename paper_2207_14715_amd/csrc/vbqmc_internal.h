@@ -14,6 +14,7 @@ constexpr int kMaxSpin = 64;   // electrons per spin
 constexpr int kRedSlots = 64;  // doubles of block-reduction scratch
 constexpr int kMaxFinishN = 128;  // electrons per walker (2 x kMaxSpin)
 constexpr int kXcds = 8;          // accelerator dies (each with its own L2) on MI355X
+constexpr int kCus = 256;         // compute units on MI355X
 
 // One spin's determinant table (reference determinant + replaced columns).
 struct SpinTab {

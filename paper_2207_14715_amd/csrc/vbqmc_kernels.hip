@@ -470,13 +470,13 @@ __global__ __launch_bounds__(64) void k_eloc_finish(const DevWF* __restrict__ pw
           wv = -wf.nuc[4 * a + 3];
         }
         const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / r;
         double u, u1, u2;
         pair_fn(r, wf.kappa, cf, u, u1, u2);
-        const double f = u1 / r;
+        const double f = u1 * ir;
         gx += f * dx; gy += f * dy; gz += f * dz;
         lap += u2 + 2.0 * f;
-        V += wv / r;
+        V += wv * ir;
       }
     }
     for (int off = 1; off < P; off <<= 1) {
@@ -916,8 +916,12 @@ static hipError_t launch_vmc_split_t(const DevWF& wf, const DevWF* dwf, const De
   if (e != hipSuccess) return e;
   // tiles per XCD (walker blocks wb = x mod 8), rounded up to whole blocks
   const int64_t nwb = (W + kGroup - 1) / kGroup;
-  const int per_block = 2;
-  const int64_t per_xcd = ((nwb + kXcds - 1) / kXcds * wf.N + per_block - 1) / per_block;
+  // tiles per block: just enough for every block to be resident at once
+  // (workgroups per CU from the LDS footprint, at most 8 one-wave blocks)
+  const int64_t tiles_xcd = (nwb + kXcds - 1) / kXcds * wf.N;
+  const int64_t slots_xcd = (int64_t)(kCus / kXcds) * std::max(1, std::min(8, (int)(163840 / std::max<size_t>(lds_ti, 1))));
+  const int per_block = (int)std::max<int64_t>(1, (tiles_xcd + slots_xcd - 1) / slots_xcd);
+  const int64_t per_xcd = (tiles_xcd + per_block - 1) / per_block;
   const unsigned tblocks = (unsigned)(per_xcd * kXcds);
   for (int st = 0; st < nsteps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
