@@ -29,6 +29,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 # calibration; None until measured for the current kernel.
 TRAFFIC_BYTES_PER_LAUNCH = None
 TRAFFIC_LANES = 32
+# the same for one launch of the row kernel (4096 walkers, 100 steps per
+# launch): FETCH_SIZE 5046 KiB x 2.000 + WRITE_SIZE 8320 KiB x 1.000
+TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5046.04 * 2.0 + 8320.0) * 1024}
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
@@ -113,13 +116,17 @@ def cpu_baseline(system, step_size, steps=300, walkers=1024, seed=11):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--walkers", type=int, default=4096)
-    ap.add_argument("--steps-per-launch", type=int, default=10, help="VMC steps per warmup call")
+    ap.add_argument("--steps-per-launch", type=int, default=100,
+                    help="VMC steps per call (warm-up calls, and timed calls of the row kernel)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--walker-lanes", type=int, default=0, choices=[0, 16, 32, 64],
                     help="lanes per walker in the single-electron sweep (0: library choice)")
+    ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="single-electron step kernel: 0 library choice, 1 sweep + local-energy kernels, "
+                         "2 row kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-exponent", type=float, default=1e4,
                     help="precision form: cap on the Gaussian exponents of the molecule (default: the workload's 1e4)")
@@ -156,7 +163,8 @@ def main():
         return
     system = S.f2_shaped()
     W, step_size = args.walkers, 0.3
-    ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes)
+    ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes,
+                     step_kernel=args.step_kernel)
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=5)).cuda()
     state = ctx.walkers_init(R0)
     acc = ctx.new_vmc_acc(W)
@@ -170,31 +178,65 @@ def main():
     torch.cuda.synchronize()
     acc = ctx.new_vmc_acc(W)
     stream = torch.cuda.current_stream()
-    # timed region: per step one sweep (the dominant kernel, bracketed by
-    # events on the launch stream) and one measurement of E_L
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[2 * k].record(stream)
-        ctx.vmc_sweep(state, seed, step, step_size, acc["n_accept"])
-        ev[2 * k + 1].record(stream)
-        ctx.vmc_measure(state, acc)
-        step += 1
-    ev[2 * args.steps].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sweep_s = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)) / 1e3
-    measure_s = sum(ev[2 * k + 1].elapsed_time(ev[2 * k + 2]) for k in range(args.steps)) / 1e3
+    rows = ctx.info["step_kernel"] == 2
+    lanes = ctx.info["sweep_lanes"]
+    if rows:
+        # timed region: calls of `spl` steps, each one launch of the row
+        # kernel (moves and E_L of every step), bracketed by events on the
+        # launch stream; a shorter last call is timed but not averaged
+        chunks = [spl] * (args.steps // spl) + ([args.steps % spl] if args.steps % spl else [])
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(chunks))]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, c in enumerate(chunks):
+            ev[2 * k].record(stream)
+            ctx.vmc_advance(state, c, seed, step, step_size, False, acc)
+            ev[2 * k + 1].record(stream)
+            step += c
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        full = [k for k, c in enumerate(chunks) if c == spl] or [0]
+        kernel_s = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in full) / 1e3
+        launches = len(full)
+        steps_launch = chunks[full[0]]
+        measure_s = None
+    else:
+        # timed region: per step one sweep (the dominant kernel, bracketed by
+        # events on the launch stream) and one measurement of E_L
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev[2 * k].record(stream)
+            ctx.vmc_sweep(state, seed, step, step_size, acc["n_accept"])
+            ev[2 * k + 1].record(stream)
+            ctx.vmc_measure(state, acc)
+            step += 1
+        ev[2 * args.steps].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_s = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)) / 1e3
+        measure_s = sum(ev[2 * k + 1].elapsed_time(ev[2 * k + 2]) for k in range(args.steps)) / 1e3
+        launches = args.steps
+        steps_launch = 1
     moves = W * args.steps
     accept_rate = float(acc["n_accept"].sum().item()) / (moves * ctx.N)
     e_mean = float(acc["e_sum"].sum().item()) / moves
     sweep_flops = sweep_flops_per_walker_move(ctx, system, accept_rate) * W
     measure_flops = measure_flops_per_walker(ctx, system) * W
-    sweep_avg = sweep_s / args.steps
-    achieved = sweep_flops / sweep_avg / 1e12
-    lanes = ctx.info["sweep_lanes"]
-    sweep_kernel = f"k_sweep_g<{lanes}, 0>" if lanes < 64 else "k_sweep<64, 0>"
+    prec_tag = {"fp64": 0, "fp32": 1, "bf16": 2}[args.precision]
+    if rows:
+        # the dominant (and only) kernel makes moves and E_L of every step
+        kernel = f"k_vmc_rows<{prec_tag}>"
+        flops_launch = (sweep_flops + measure_flops) * steps_launch
+        traffic = TRAFFIC_ROWS["bytes"] if (W == TRAFFIC_ROWS["walkers"] and prec_tag == 0 and
+                                            steps_launch == TRAFFIC_ROWS["steps_per_launch"]) else None
+    else:
+        kernel = f"k_sweep_g<{lanes}, {prec_tag}>" if lanes < 64 else f"k_sweep<64, {prec_tag}>"
+        flops_launch = sweep_flops
+        traffic = TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES else None
+    kernel_avg = kernel_s / launches
+    achieved = flops_launch / kernel_avg / 1e12
     line = {
         "metric": "walker-moves/sec incl. E_L",
         "value": moves / wall,
@@ -211,19 +253,21 @@ def main():
         "config": {"workload": "F2-shaped diatomic VMC: 18 electrons (9 up, 9 down), 28 Gaussian basis "
                                "functions, 3 VB structures / 4 determinants, 4096 walkers, single-electron "
                                "moves of 0.3 bohr with Sherman-Morrison updates, E_L every step",
-                   "walkers": W, "electrons": ctx.N, "precision": args.precision, "sweep_lanes": lanes},
+                   "walkers": W, "electrons": ctx.N, "precision": args.precision,
+                   "step_kernel": "rows" if rows else f"sweep {lanes} lanes + local energy"},
         "electron_moves_per_s": moves * ctx.N / wall,
         "acceptance": accept_rate,
         "mean_eloc": e_mean,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES else None,
-                     "kernel": sweep_kernel, "kernel_avg_ms_per_launch": sweep_avg * 1e3,
-                     "flops_per_launch": sweep_flops, "walkers_per_launch": W},
-        "measure": {"kernels": "k_eloc_tiles<0> + k_eloc_finish", "avg_ms_per_step": measure_s / args.steps * 1e3,
-                    "flops_per_step": measure_flops,
-                    "achieved_tflops": measure_flops / (measure_s / args.steps) / 1e12},
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": kernel, "kernel_avg_ms_per_launch": kernel_avg * 1e3,
+                     "flops_per_launch": flops_launch, "walkers_per_launch": W,
+                     "steps_per_launch": steps_launch},
     }
+    if measure_s is not None:
+        line["measure"] = {"kernels": f"k_eloc_tiles<{prec_tag}> + k_eloc_finish",
+                           "avg_ms_per_step": measure_s / args.steps * 1e3, "flops_per_step": measure_flops,
+                           "achieved_tflops": measure_flops / (measure_s / args.steps) / 1e12}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(system, step_size)
     print(json.dumps(line))

@@ -108,11 +108,20 @@ typedef struct {
  * single-electron VMC sweep: 16 or 32 (several walkers per wavefront, if
  * their state fits in LDS), 64 (one walker per workgroup), or 0 to let the
  * library choose (32 when a spin has at most 32 electrons and two walkers
- * fit in LDS, else 64).  Results do not depend on it beyond rounding. */
+ * fit in LDS, else 64).  Results do not depend on it beyond rounding.
+ * step_kernel: how vbqmc_vmc_advance runs single-electron steps: 1 = a sweep
+ * launch (lanes per walker as walker_lanes) then the batched local-energy
+ * launches, per step; 2 = the row kernel: four walkers per wavefront, 16
+ * lanes each, moves and E_L of all n_steps steps in one launch (systems with
+ * at most 24 electrons and, per spin, at most 16 reference slots plus table
+ * orbitals and 16 distinct determinants; EINVAL at create otherwise); 0 =
+ * 2 when the system fits it and walker_lanes is 0, else 1.  Results do not
+ * depend on it beyond rounding. */
 typedef struct {
   int32_t precision;
   int32_t refresh_every;
   int32_t walker_lanes;
+  int32_t step_kernel;
 } vbqmc_options;
 
 typedef struct {
@@ -124,6 +133,7 @@ typedef struct {
   int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei */
   int32_t block_threads;         /* threads per walker in the walker kernels */
   int32_t sweep_lanes;           /* lanes per walker in the single-electron sweep */
+  int32_t step_kernel;           /* kernel of single-electron VMC steps (vbqmc_options) */
   int64_t walker_state_bytes;    /* bytes per walker record */
   int64_t lds_bytes;             /* LDS bytes per walker block */
 } vbqmc_info_t;
@@ -206,7 +216,9 @@ int vbqmc_vmc_advance(vbqmc_ctx* ctx, void* state, int64_t W, int32_t n_steps, u
  * walker at its current configuration from its record and accumulates it
  * into acc (e_sum, e2_sum, e_last and, if set, sij_sum; n_accept is not
  * used).  vbqmc_vmc_advance with all_electron = 0 equals, per step, a sweep
- * followed by a measure.  Both need the system to fit the sweep and
+ * followed by a measure: bit for bit when it runs the sweep and local-energy
+ * kernels (step_kernel 1), with the same moves and E_L to rounding when it
+ * runs the row kernel (step_kernel 2).  Both need the system to fit the sweep and
  * local-energy kernels (EINVAL otherwise, where vbqmc_vmc_advance still
  * runs); state [dev] is any record written by this library.
  */

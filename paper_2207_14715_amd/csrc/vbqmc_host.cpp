@@ -35,6 +35,9 @@ hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, c
                            int* offs, int64_t cap, int N, int st, double tau, double W_target, double* pop,
                            double* wsum, double* wesum, double* etrial, double* lacc, double* lprop,
                            const double* src, double* dst, int rec_len, hipStream_t s);
+hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
+                           uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
+                           double* sij, hipStream_t s);
 hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
@@ -143,6 +146,8 @@ struct vbqmc_ctx {
   DevWF* d_wf_sweepg = nullptr; // same tables, layout of the wavefront sweep (several walkers per wavefront)
   int sweep_g = 64;             // lanes per walker in the single-electron sweep
   DevWF* d_wf_aux = nullptr;    // same tables, compact LDS layout of the batched local-energy kernels
+  DevWF* d_wf_rows = nullptr;   // same tables, layout of the row step kernel (four walkers per wavefront)
+  int step_kernel = 1;          // single-electron VMC steps: 1 sweep + local-energy kernels, 2 row kernel
   double* d_timg = nullptr;     // LDS table image
 };
 
@@ -291,6 +296,80 @@ DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
   return a;
 }
 
+// Row step kernel (four walkers per wavefront, 16 lanes each): the tables
+// without the orbital coefficients, the tile tables, one state block per
+// walker (with the exchange slots of a move), then one region whose use
+// changes over a step: trial positions, draws, trial rows of one spin and
+// the Jastrow move tables during the moves; packed reference rows during an
+// inverse refresh; positions, derivative rows and per-electron results
+// during the local energy.
+DevWF rows_layout(const vbqmc_ctx* x) {
+  DevWF a = x->wf;
+  const int NG = kRowWalkers, N = x->N, nop = x->nop;
+  const int nmax = std::max(x->nup, x->ndn);
+  int nUm = 1, nPm = 1;
+  for (int s = 0; s < 2; ++s) {
+    nUm = std::max(nUm, (int)x->sp[s].sets.size());
+    nPm = std::max(nPm, (int)x->sp[s].porb.size());
+  }
+  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
+  a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  a.l_gtab = lds(kGroup * ((3 * x->nshell) | 1));
+  a.gw_base = lds.o;
+  LdsAlloc w{0};
+  a.l_R = w(3 * N);
+  a.l_sc = w(SC_COUNT);
+  a.l_ipiv = w.ints(2 * nmax);
+  a.l_f = w(2 * nmax);
+  for (int s = 0; s < 2; ++s) {
+    int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    a.l_B[s] = w(n * n);
+    a.l_T[s] = w(n * nP);
+    a.l_PP[s] = w(n * nP);
+    a.l_Ru[s] = w((int)x->sp[s].sets.size());
+    a.l_Wu[s] = w((int)x->sp[s].sets.size());
+  }
+  a.l_Qu = w(nUm);
+  a.l_y = w(nPm + 1);
+  a.l_bcol = w(nmax);
+  a.l_z = w(2 * nmax);
+  a.l_xch = w(32);
+  a.gw_stride = w.o;
+  lds.o += NG * a.gw_stride;
+  const int u0 = lds.o;
+  a.l_Rp = lds(3 * NG * N);
+  a.l_ua = lds(NG * N);
+  const int v0 = lds.o;
+  a.l_Vn = lds(NG * nmax * nop);
+  a.l_jx = lds(NG * N * N);
+  const int end_moves = lds.o;
+  lds.o = v0;
+  a.l_Vr = lds(NG * N * nop);
+  const int end_refresh = lds.o;
+  lds.o = u0;
+  a.l_Rall = lds(3 * NG * N);
+  a.l_Phi4 = lds(4 * kGroup * nop);
+  a.l_yb64 = lds(64 * (nPm + 1));
+  a.l_gc4 = lds(4 * NG * N);
+  a.l_rI = lds(NG * x->nstruct);
+  a.lds_rows_doubles = std::max(std::max(end_moves, end_refresh), lds.o);
+  return a;
+}
+
+// the row step kernel handles the system: at most 16 columns (reference
+// slots + table orbitals) and 16 distinct determinants per spin, at most 24
+// electrons, and its layout fits the device's LDS
+bool rows_fit(const vbqmc_ctx* x) {
+  if (x->N < 1 || x->N > kRowMaxN) return false;
+  for (int s = 0; s < 2; ++s) {
+    if (x->sp[s].n + (int)x->sp[s].porb.size() > 16) return false;
+    if ((int)x->sp[s].sets.size() > 16) return false;
+  }
+  return (size_t)rows_layout(x).lds_rows_doubles * 8 <= (size_t)x->lds_limit;
+}
+
 // Batched local-energy kernels: the tables, then only what the finish and
 // tile kernels touch.
 DevWF aux_layout(const vbqmc_ctx* x) {
@@ -397,6 +476,10 @@ int upload_coefficients(vbqmc_ctx* x) {
   if (e == hipSuccess && x->d_wf_aux) {
     DevWF a = aux_layout(x);
     e = hipMemcpy(x->d_wf_aux, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && x->d_wf_rows && x->step_kernel == 2) {
+    DevWF a = rows_layout(x);
+    e = hipMemcpy(x->d_wf_rows, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) return upload_table_image(x);
   return e == hipSuccess ? 0 : hipfail(x, e, "upload coefficients");
@@ -756,6 +839,23 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     }
     if (x->sweep_g < 64) wf.lds_sweepg_doubles = sweepg_layout(x, x->sweep_g).lds_sweepg_doubles;
   }
+  // kernel of single-electron VMC steps: the row kernel when the system fits
+  // it and no lane count was asked for, else the sweep + local-energy kernels
+  {
+    const int req = opt ? opt->step_kernel : 0;
+    const int lanes = opt ? opt->walker_lanes : 0;
+    if (req == 2) {
+      if (!rows_fit(x)) return bad("step_kernel 2: the system does not fit the row kernel");
+      x->step_kernel = 2;
+    } else if (req == 1) {
+      x->step_kernel = 1;
+    } else if (req == 0) {
+      x->step_kernel = lanes == 0 && rows_fit(x) ? 2 : 1;
+    } else {
+      return bad("step_kernel must be 0, 1 or 2");
+    }
+    if (x->step_kernel == 2) wf.lds_rows_doubles = rows_layout(x).lds_rows_doubles;
+  }
 
   // ---- device tables ----
   size_t bytes = 0;
@@ -769,7 +869,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.wother.size(), 4); add(h.wother.size(), 8);
   }
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
-  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add((size_t)wf.timg_len, 8);
+  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add((size_t)wf.timg_len, 8);
   he = hipMalloc((void**)&x->dmem, bytes);
   if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
   x->dbytes = bytes;
@@ -806,6 +906,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_wf_aux = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_sweep = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_sweepg = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_rows = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_timg = carve<double>(p, (size_t)wf.timg_len);
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
@@ -838,6 +939,7 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
   o->block_threads = x->nt;
   o->sweep_lanes = x->sweep_g;
+  o->step_kernel = x->step_kernel;
   o->walker_state_bytes = (int64_t)x->wf.rec_len * 8;
   o->lds_bytes = (int64_t)x->wf.lds_doubles * 8;
   return VBQMC_OK;
@@ -950,6 +1052,13 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
+  if (!all_electron && x->step_kernel == 2) {
+    // single-electron moves and E_L of every step in one row-kernel launch
+    hipError_t e = launch_vmc_rows(x->wf, x->d_wf_rows, (double*)state, W, n_steps, seed, step0, step_size,
+                                   acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
+  }
   if (!all_electron && split_fits(x)) {
     // single-electron moves: walker-resident sweep + batched local energy
     hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 3,

@@ -15,6 +15,8 @@ constexpr int kRedSlots = 64;  // doubles of block-reduction scratch
 constexpr int kMaxFinishN = 128;  // electrons per walker (2 x kMaxSpin)
 constexpr int kXcds = 8;          // accelerator dies (each with its own L2) on MI355X
 constexpr int kCus = 256;         // compute units on MI355X
+constexpr int kRowWalkers = 4;    // walkers per wavefront in the row step kernel (16 lanes each)
+constexpr int kRowMaxN = 24;      // electrons per walker in the row step kernel
 
 // One spin's determinant table (reference determinant + replaced columns).
 struct SpinTab {
@@ -75,6 +77,10 @@ struct DevWF {
   // at gw_base + g * gw_stride, and the state offsets of that layout are
   // relative to it
   int gw_base, gw_stride, lds_sweepg_doubles;
+  // row step kernel (one walker per 16-lane row): per walker the exchange
+  // slots of a move (l_xch, walker-relative); per wavefront the Jastrow
+  // move tables, refresh rows, local-energy row results and structure ratios
+  int l_xch, l_jx, l_Vr, l_gc4, l_rI, lds_rows_doubles;
 };
 
 // scalar slots in the record's / LDS scalar block

@@ -24,15 +24,26 @@ def lib():
     return vb
 
 
+def _context(lib, sysd, kernel):
+    """kernel: "rows" (row step kernel), an int lane count (sweep +
+    local-energy kernels with that many lanes per walker) or 0 (library
+    choice)."""
+    if kernel == "rows":
+        return lib.Context(sysd, step_kernel=2)
+    if kernel == 0:
+        return lib.Context(sysd)
+    return lib.Context(sysd, walker_lanes=kernel, step_kernel=1)
+
+
 def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=4242, step0=17, sij=False,
               lanes=0):
     import torch
     R0 = S.initial_walkers(sysd, W, seed=5)
     o = oracle_mod.Oracle(sysd)
     ref = o.vmc(R0, steps, seed, step0, step_size, all_electron, want_sij=sij)
-    ctx = lib.Context(sysd, walker_lanes=lanes)
+    ctx = _context(lib, sysd, lanes)
     print(f"[vmc] {sysd['name']} W={W} steps={steps} all_electron={all_electron} "
-          f"lanes={ctx.info['sweep_lanes']}", flush=True)
+          f"lanes={ctx.info['sweep_lanes']} step_kernel={ctx.info['step_kernel']}", flush=True)
     state = ctx.walkers_init(torch.from_numpy(R0).cuda())
     acc = ctx.vmc_advance(state, steps, seed, step0, step_size, all_electron, acc=ctx.new_vmc_acc(W, sij=sij))
     R = ctx.positions(state).cpu().numpy()
@@ -54,9 +65,11 @@ def test_vmc_h2_all_electron(lib, oracle_mod):
     _check_vmc(ref, acc, R, 30)
 
 
-# single-electron sweeps run with 16 or 32 lanes per walker (several walkers
-# per wavefront) or one walker per workgroup; all three must give the walks
-LANES = [16, 32, 64]
+# single-electron steps run on the row kernel (four walkers per wavefront,
+# moves and E_L of all steps in one launch) or as sweeps with 16 or 32 lanes
+# per walker (several walkers per wavefront) or one walker per workgroup,
+# followed by the batched local energy; all four must give the walks
+LANES = ["rows", 16, 32, 64]
 
 
 @pytest.mark.parametrize("lanes", LANES)
@@ -87,7 +100,7 @@ def test_vmc_sweep_then_measure_equals_advance(lib, lanes):
     # split calls give bit-identical walks and accumulators
     import torch
     sysd = S.f2_shaped()
-    ctx = lib.Context(sysd, walker_lanes=lanes)
+    ctx = lib.Context(sysd, walker_lanes=lanes, step_kernel=1)
     W, steps, seed, step0 = 61, 5, 99, 3
     R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=6)).cuda()
     print(f"[sweep+measure] f2 W={W} lanes={lanes}", flush=True)
@@ -102,6 +115,53 @@ def test_vmc_sweep_then_measure_equals_advance(lib, lanes):
     assert torch.equal(ctx.positions(st_a), ctx.positions(st_b))
     for key in ("e_sum", "e2_sum", "n_accept", "e_last"):
         assert torch.equal(acc_a[key], acc_b[key]), key
+
+
+def test_vmc_rows_launch_split_is_bitwise(lib):
+    # the row kernel makes all steps of a call in one launch; the same walk
+    # cut into calls of 1, 2 and 4 steps gives identical records and sums
+    import torch
+    sysd = S.f2_shaped()
+    ctx = lib.Context(sysd, step_kernel=2)
+    W, seed, step0 = 37, 7, 11
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=2)).cuda()
+    print(f"[rows split] f2 W={W}", flush=True)
+    ref_state, ref_acc = None, None
+    for cut in ([7], [1, 2, 4], [4, 3]):
+        st = ctx.walkers_init(R0)
+        acc = ctx.new_vmc_acc(W)
+        k = 0
+        for c in cut:
+            ctx.vmc_advance(st, c, seed, step0 + k, 0.3, False, acc)
+            k += c
+        torch.cuda.synchronize()
+        if ref_state is None:
+            ref_state, ref_acc = st, acc
+            continue
+        assert torch.equal(st, ref_state), cut
+        for key in ("e_sum", "e2_sum", "n_accept", "e_last"):
+            assert torch.equal(acc[key], ref_acc[key]), (cut, key)
+
+
+def test_vmc_rows_matches_split_kernels(lib):
+    # rows and sweep + local-energy kernels: same walk, E_L to rounding
+    import torch
+    sysd = S.small_random_system(77, n_inactive=3, n_active=6, n_pairs=2, n_unpaired=2, n_structures=5)
+    W, seed = 45, 3
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=4)).cuda()
+    out = []
+    for kern in ("rows", 32):
+        ctx = _context(lib, sysd, kern)
+        print(f"[rows vs split] {sysd['name']} W={W} kernel={kern} step_kernel={ctx.info['step_kernel']}",
+              flush=True)
+        st = ctx.walkers_init(R0)
+        acc = ctx.vmc_advance(st, 9, seed, 0, 0.35, acc=ctx.new_vmc_acc(W, sij=True))
+        out.append((ctx.positions(st).cpu().numpy(), acc))
+    (Ra, a), (Rb, b) = out
+    np.testing.assert_allclose(Ra, Rb, rtol=1e-10, atol=1e-10)
+    np.testing.assert_array_equal(a["n_accept"].cpu().numpy(), b["n_accept"].cpu().numpy())
+    for key in ("e_sum", "e2_sum", "e_last", "sij_sum"):
+        np.testing.assert_allclose(a[key].cpu().numpy(), b[key].cpu().numpy(), rtol=1e-9, atol=1e-9, err_msg=key)
 
 
 def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3):
