@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2],
                     help="single-electron step kernel: 0 library choice, 1 sweep + local-energy kernels, "
                          "2 row kernel")
+    ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="DMC form: 0 library choice, 1 one workgroup per walker, 2 electron-major launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-exponent", type=float, default=1e4,
                     help="precision form: cap on the Gaussian exponents of the molecule (default: the workload's 1e4)")
@@ -390,7 +392,7 @@ def dmc_form(args):
     steps = args.steps if args.steps != 200 else 4
     warm = args.warmup if args.warmup != 20 else 1
     tau = 0.005
-    ctx = vb.Context(system)
+    ctx = vb.Context(system, dmc_kernel=args.dmc_kernel)
     cap = 3 * W
     st = [ctx.new_state(cap), ctx.new_state(cap)]
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=13)).cuda()
@@ -413,6 +415,7 @@ def dmc_form(args):
                       "population": [int(p) for p in pop], "e_trial": out["e_trial"],
                       "acceptance": float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1)),
                       "data": "synthetic", "dtype": "f64",
+                      "dmc_kernel": "electron-major" if ctx.info["dmc_kernel"] == 2 else "workgroup per walker",
                       "config": {"workload": "16 nuclei (Z in {1,6,8}), 64 electrons, 240 Gaussian basis functions, "
                                              "32 VB structures / 128 determinants, tau = 0.005, per-electron "
                                              "drift-diffusion moves, branching and compaction",

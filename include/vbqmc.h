@@ -116,12 +116,21 @@ typedef struct {
  * at most 24 electrons and, per spin, at most 16 reference slots plus table
  * orbitals and 16 distinct determinants; EINVAL at create otherwise); 0 =
  * 2 when the system fits it and walker_lanes is 0, else 1.  Results do not
- * depend on it beyond rounding. */
+ * depend on it beyond rounding.
+ * dmc_kernel: how vbqmc_dmc_advance runs a step: 1 = one workgroup per walker
+ * makes all of the walker's moves, E_L and weight; 2 = electron-major: for
+ * each electron a proposal launch, an MFMA launch for the orbital rows at
+ * the proposals and an acceptance launch, each over all walkers, then one
+ * per-walker launch for refresh, E_L and weight (spins with at most 64
+ * reference slots plus table orbitals; EINVAL at create otherwise); 0 = 2
+ * when one workgroup per walker would need more than 40 KiB of LDS and the
+ * system fits it, else 1.  Results do not depend on it beyond rounding. */
 typedef struct {
   int32_t precision;
   int32_t refresh_every;
   int32_t walker_lanes;
   int32_t step_kernel;
+  int32_t dmc_kernel;
 } vbqmc_options;
 
 typedef struct {
@@ -134,6 +143,7 @@ typedef struct {
   int32_t block_threads;         /* threads per walker in the walker kernels */
   int32_t sweep_lanes;           /* lanes per walker in the single-electron sweep */
   int32_t step_kernel;           /* kernel of single-electron VMC steps (vbqmc_options) */
+  int32_t dmc_kernel;            /* kernel of DMC steps (vbqmc_options) */
   int64_t walker_state_bytes;    /* bytes per walker record */
   int64_t lds_bytes;             /* LDS bytes per walker block */
 } vbqmc_info_t;

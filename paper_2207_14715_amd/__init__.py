@@ -49,7 +49,8 @@ class _Wavefunction(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
-                ("walker_lanes", ctypes.c_int32), ("step_kernel", ctypes.c_int32)]
+                ("walker_lanes", ctypes.c_int32), ("step_kernel", ctypes.c_int32),
+                ("dmc_kernel", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -59,7 +60,7 @@ class _Info(ctypes.Structure):
                 ("n_unique_up", ctypes.c_int32), ("n_unique_dn", ctypes.c_int32), ("n_table_up", ctypes.c_int32),
                 ("n_table_dn", ctypes.c_int32), ("n_params", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("sweep_lanes", ctypes.c_int32),
-                ("step_kernel", ctypes.c_int32),
+                ("step_kernel", ctypes.c_int32), ("dmc_kernel", ctypes.c_int32),
                 ("walker_state_bytes", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int64)]
 
@@ -153,7 +154,7 @@ def _check_cuda(t, name, dtype=None, shape=None):
 class Context:
     """A vbqmc context for one system dict (see the ``systems`` package)."""
 
-    def __init__(self, system, precision="fp64", refresh_every=32, walker_lanes=0, step_kernel=0):
+    def __init__(self, system, precision="fp64", refresh_every=32, walker_lanes=0, step_kernel=0, dmc_kernel=0):
         lib = load_library()
         self._lib = lib
         self.system = system
@@ -195,7 +196,7 @@ class Context:
                             _dp(lam), len(st), _dp(c), len(ts), _ip(ts), _ip(tc), _ip(to), float(jas["kappa"]),
                             ee_arr, _dp(en))
         opt = _Options(_PREC[precision] if isinstance(precision, str) else int(precision), int(refresh_every),
-                       int(walker_lanes), int(step_kernel))
+                       int(walker_lanes), int(step_kernel), int(dmc_kernel))
         h = ctypes.c_void_p()
         rc = lib.vbqmc_create(ctypes.byref(sysc), ctypes.byref(wfc), ctypes.byref(opt), ctypes.byref(h))
         if rc != 0:

@@ -38,6 +38,12 @@ hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, c
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s);
+hipError_t launch_dmc_finish(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl,
+                             int64_t cap, uint64_t seed, uint32_t step, double tau, double* wts, double* wel,
+                             int* ncopy, hipStream_t s);
+hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds, double* state,
+                            double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
+                            double* V, double* Vp, double* nacc, hipStream_t s);
 hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
@@ -148,6 +154,8 @@ struct vbqmc_ctx {
   DevWF* d_wf_aux = nullptr;    // same tables, compact LDS layout of the batched local-energy kernels
   DevWF* d_wf_rows = nullptr;   // same tables, layout of the row step kernel (four walkers per wavefront)
   int step_kernel = 1;          // single-electron VMC steps: 1 sweep + local-energy kernels, 2 row kernel
+  DevWF* d_wf_dmcb = nullptr;   // same tables, layout of the electron-major DMC row tiles
+  int dmc_kernel = 1;           // DMC steps: 1 one workgroup per walker, 2 electron-major launches
   double* d_timg = nullptr;     // LDS table image
 };
 
@@ -358,6 +366,27 @@ DevWF rows_layout(const vbqmc_ctx* x) {
   return a;
 }
 
+// Electron-major DMC row tiles: the tables without the orbital
+// coefficients and the tile tables (radial sums with both derivatives).
+DevWF dmcb_layout(const vbqmc_ctx* x) {
+  DevWF a = x->wf;
+  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
+  a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
+  a.l_gtab = lds(kGroup * ((3 * x->nshell) | 1));
+  a.lds_tile_doubles = lds.o;
+  return a;
+}
+
+// electron-major DMC handles the system: every spin's reference slots plus
+// table orbitals fit the 64 lanes of a wavefront, and the row tiles fit LDS
+bool dmcb_fit(const vbqmc_ctx* x) {
+  for (int s = 0; s < 2; ++s)
+    if (x->sp[s].n + (int)x->sp[s].porb.size() > 64) return false;
+  return (size_t)dmcb_layout(x).lds_tile_doubles * 8 <= (size_t)x->lds_limit;
+}
+
 // the row step kernel handles the system: at most 16 columns (reference
 // slots + table orbitals) and 16 distinct determinants per spin, at most 24
 // electrons, and its layout fits the device's LDS
@@ -476,6 +505,10 @@ int upload_coefficients(vbqmc_ctx* x) {
   if (e == hipSuccess && x->d_wf_aux) {
     DevWF a = aux_layout(x);
     e = hipMemcpy(x->d_wf_aux, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && x->d_wf_dmcb && x->dmc_kernel == 2) {
+    DevWF a = dmcb_layout(x);
+    e = hipMemcpy(x->d_wf_dmcb, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess && x->d_wf_rows && x->step_kernel == 2) {
     DevWF a = rows_layout(x);
@@ -856,6 +889,21 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     }
     if (x->step_kernel == 2) wf.lds_rows_doubles = rows_layout(x).lds_rows_doubles;
   }
+  // kernel of DMC steps: electron-major launches when fewer than four walkers
+  // fit a CU in the one-workgroup-per-walker kernel, else that kernel
+  {
+    const int req = opt ? opt->dmc_kernel : 0;
+    if (req == 2) {
+      if (!dmcb_fit(x)) return bad("dmc_kernel 2: the system does not fit the electron-major DMC kernels");
+      x->dmc_kernel = 2;
+    } else if (req == 1) {
+      x->dmc_kernel = 1;
+    } else if (req == 0) {
+      x->dmc_kernel = (size_t)wf.lds_doubles * 8 > 40960 && dmcb_fit(x) ? 2 : 1;
+    } else {
+      return bad("dmc_kernel must be 0, 1 or 2");
+    }
+  }
 
   // ---- device tables ----
   size_t bytes = 0;
@@ -869,7 +917,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.wother.size(), 4); add(h.wother.size(), 8);
   }
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
-  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add((size_t)wf.timg_len, 8);
+  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
+  add((size_t)wf.timg_len, 8);
   he = hipMalloc((void**)&x->dmem, bytes);
   if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
   x->dbytes = bytes;
@@ -907,6 +956,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_wf_sweep = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_sweepg = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_rows = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_dmcb = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_timg = carve<double>(p, (size_t)wf.timg_len);
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
@@ -940,6 +990,7 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->block_threads = x->nt;
   o->sweep_lanes = x->sweep_g;
   o->step_kernel = x->step_kernel;
+  o->dmc_kernel = x->dmc_kernel;
   o->walker_state_bytes = (int64_t)x->wf.rec_len * 8;
   o->lds_bytes = (int64_t)x->wf.lds_doubles * 8;
   return VBQMC_OK;
@@ -1071,11 +1122,18 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
 }
 
-// DMC workspace: ctrl (8 doubles) | wts, wel, nacc [cap] | ncopy [cap] | offs [cap+1]
+// DMC workspace: ctrl (8 doubles) | wts, wel, nacc [cap] | ncopy [cap] |
+// offs [cap+1] | (electron-major kernels) P, V [cap][3], Vp [cap][4][nop]
+namespace {
+size_t dmc_ws_base(int64_t cap) { return 64 + 3 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
+}  // namespace
+
 int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, size_t* bytes) {
   if (!x || !bytes || cap < 1) return VBQMC_EINVAL;
   (void)n_steps;
-  *bytes = 64 + 3 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4 + 256;
+  size_t b = dmc_ws_base(cap) + 256;
+  if (x->dmc_kernel == 2) b += (size_t)cap * (6 + 4 * (size_t)x->nop) * 8 + 256;
+  *bytes = b;
   return VBQMC_OK;
 }
 
@@ -1112,9 +1170,23 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr, nullptr,
                       nullptr, cur, s);
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
+  // electron-major scratch (8-byte aligned after the integer arrays)
+  char* pb = (char*)ws + ((dmc_ws_base(cap) + 255) & ~(size_t)255);
+  double* Pw = (double*)pb;
+  double* Vw = Pw + 3 * cap;
+  double* Vpw = Vw + 3 * cap;
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
-    e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
+    if (x->dmc_kernel == 2) {
+      const size_t rows_lds = (size_t)dmcb_layout(x).lds_tile_doubles * 8;
+      for (int i = 0; i < x->N && e == hipSuccess; ++i)
+        e = launch_dmcb_move(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, i, seed, step, tau, Pw, Vw,
+                             Vpw, nacc, s);
+      if (e == hipSuccess)
+        e = launch_dmc_finish(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, s);
+    } else {
+      e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
+    }
     if (e != hipSuccess) return hipfail(x, e, "dmc: step");
     e = launch_dmc_tail(ctrl, wts, wel, ncopy, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
                         lg->wesum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);

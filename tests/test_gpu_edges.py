@@ -67,9 +67,11 @@ def test_invalid_system_rejected(lib):
         lib.Context(bad)
 
 
-def test_dmc_multideterminant_molecule_trajectory(lib, oracle_mod):
-    """DMC with the 10-nucleus, 64-determinant molecule (two waves per walker)
-    against the oracle for a few steps."""
+@pytest.mark.parametrize("kern", [1, 2])
+def test_dmc_multideterminant_molecule_trajectory(lib, oracle_mod, kern):
+    """DMC with the 10-nucleus, 64-determinant molecule against the oracle for
+    a few steps, with one workgroup per walker (two waves) and with the
+    electron-major launches."""
     import torch
     sysd = S.precision_molecule()
     W = 16
@@ -78,7 +80,8 @@ def test_dmc_multideterminant_molecule_trajectory(lib, oracle_mod):
     e0 = o.evaluate(R0)["eloc"]
     et = float(np.median(e0))
     ref = o.dmc(R0, e0, 3, 5, 0, 0.002, et, W, capacity=4 * W)
-    ctx = lib.Context(sysd)
+    ctx = lib.Context(sysd, dmc_kernel=kern)
+    print(f"[dmc molecule] dmc_kernel={ctx.info['dmc_kernel']}", flush=True)
     st0, st1 = ctx.new_state(4 * W), ctx.new_state(4 * W)
     ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
     out = ctx.dmc_advance([st0, st1], W, 3, 5, 0, 0.002, et, W)

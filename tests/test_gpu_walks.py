@@ -164,15 +164,20 @@ def test_vmc_rows_matches_split_kernels(lib):
         np.testing.assert_allclose(a[key].cpu().numpy(), b[key].cpu().numpy(), rtol=1e-9, atol=1e-9, err_msg=key)
 
 
-def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3):
+# DMC steps run with one workgroup per walker (1) or as electron-major
+# launches over all walkers (2); both must give the oracle's walks
+DMC_KERNELS = [1, 2]
+
+
+def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3, dmc_kernel=0, et_median=False):
     import torch
     o = oracle_mod.Oracle(sysd)
     R0 = S.initial_walkers(sysd, W, seed=8)
     e0 = o.evaluate(R0)["eloc"]
-    et = float(np.mean(e0))
+    et = float(np.median(e0) if et_median else np.mean(e0))
     ref = o.dmc(R0, e0, steps, seed, step0, tau, et, W, capacity=4 * W)
-    ctx = lib.Context(sysd)
-    print(f"[dmc] {sysd['name']} W={W} steps={steps}", flush=True)
+    ctx = lib.Context(sysd, dmc_kernel=dmc_kernel)
+    print(f"[dmc] {sysd['name']} W={W} steps={steps} dmc_kernel={ctx.info['dmc_kernel']}", flush=True)
     st0 = ctx.new_state(4 * W)
     st1 = ctx.new_state(4 * W)
     ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
@@ -192,10 +197,12 @@ def _check_dmc(ref, out, R):
     np.testing.assert_allclose(R, ref["R"], rtol=1e-8, atol=1e-8)
 
 
-def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod):
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod, kern):
     import torch
     sysd = S.hydrogen_sto_1s(1.0)
-    ctx = lib.Context(sysd)
+    ctx = lib.Context(sysd, dmc_kernel=kern)
+    print(f"[dmc exact H] dmc_kernel={kern}", flush=True)
     W = 512
     R0 = torch.from_numpy(np.random.default_rng(3).normal(size=(W, 1, 3))).cuda()
     st0, st1 = ctx.new_state(2 * W), ctx.new_state(2 * W)
@@ -206,12 +213,24 @@ def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod):
     np.testing.assert_allclose(out["wesum"].cpu().numpy() / out["wsum"].cpu().numpy(), -0.5, atol=1e-12)
 
 
-def test_dmc_h2_trajectory(lib, oracle_mod):
-    ref, out, R = _dmc_pair(lib, oracle_mod, S.h2_heitler_london(), 128, 8, 0.01)
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_h2_trajectory(lib, oracle_mod, kern):
+    ref, out, R = _dmc_pair(lib, oracle_mod, S.h2_heitler_london(), 128, 8, 0.01, dmc_kernel=kern)
     _check_dmc(ref, out, R)
 
 
-def test_dmc_small_random_trajectory(lib, oracle_mod):
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_small_random_trajectory(lib, oracle_mod, kern):
     sysd = S.small_random_system(311, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
-    ref, out, R = _dmc_pair(lib, oracle_mod, sysd, 64, 5, 0.005)
+    ref, out, R = _dmc_pair(lib, oracle_mod, sysd, 64, 5, 0.005, dmc_kernel=kern)
+    _check_dmc(ref, out, R)
+
+
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_f2_trajectory(lib, oracle_mod, kern):
+    # 18 electrons, 9 per spin, four determinant pairs; 45 walkers leave a
+    # partly filled last row tile.  The synthetic molecule's E_L spreads over
+    # thousands of hartree: a short time step and the median as trial energy
+    # keep the population within the capacity.
+    ref, out, R = _dmc_pair(lib, oracle_mod, S.f2_shaped(), 45, 3, 0.002, dmc_kernel=kern, et_median=True)
     _check_dmc(ref, out, R)
