@@ -116,8 +116,9 @@ def cpu_baseline(system, step_size, steps=300, walkers=1024, seed=11):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 2000 for the headline, the form's own for the others)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default: 100, or the form's own)")
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--steps-per-launch", type=int, default=100,
                     help="VMC steps per call (warm-up calls, and timed calls of the row kernel)")
@@ -149,6 +150,9 @@ def main():
     import systems as S
 
     torch.cuda.set_device(0)
+    if args.form == "plain":
+        args.steps = 2000 if args.steps is None else args.steps
+        args.warmup = 100 if args.warmup is None else args.warmup
     if args.form == "precision":
         return precision_form(args)
     if args.form == "adjoint":
@@ -300,11 +304,11 @@ def precision_form(args):
     import systems as S
     system = S.precision_molecule(max_exponent=args.max_exponent)
     W = args.walkers if args.walkers != 4096 else 16384
-    steps, step_size, seed = args.steps if args.steps != 200 else 20, 0.3, 777
+    steps, step_size, seed = args.steps if args.steps is not None else 20, 0.3, 777
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=9)).cuda()
     c64 = vb.Context(system, precision="fp64", walker_lanes=args.walker_lanes)
     st = c64.walkers_init(R0)
-    c64.vmc_advance(st, args.warmup, seed, 0, step_size)  # burn-in in FP64
+    c64.vmc_advance(st, args.warmup if args.warmup is not None else 20, seed, 0, step_size)  # burn-in in FP64
     Rb = c64.positions(st)
     ref = c64.evaluate(Rb, want=("eloc",))["eloc"]
     res = {"metric": "walker-moves/sec incl. E_L (precision forms)", "unit": "walker-moves/s", "n_gpus": 1,
@@ -354,7 +358,7 @@ def adjoint_form(args):
     ctx = vb.Context(system)
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=3)).cuda()
     st = ctx.walkers_init(R0)
-    ctx.vmc_advance(st, max(args.warmup, 1), 5, 0, 0.3)
+    ctx.vmc_advance(st, max(args.warmup if args.warmup is not None else 20, 1), 5, 0, 0.3)
     R = ctx.positions(st)
     ctx.param_grad(R)  # warm-up
     reps = 3
@@ -389,8 +393,8 @@ def dmc_form(args):
     import systems as S
     system = S.dmc_molecule()
     W = args.walkers if args.walkers != 4096 else 32768
-    steps = args.steps if args.steps != 200 else 4
-    warm = args.warmup if args.warmup != 20 else 1
+    steps = args.steps if args.steps is not None else 4
+    warm = args.warmup if args.warmup is not None else 1
     tau = 0.005
     ctx = vb.Context(system, dmc_kernel=args.dmc_kernel)
     cap = 3 * W

@@ -19,11 +19,9 @@
 // has.  Inverse refresh, the local energy and the branching weight follow in
 // a per-walker kernel after the last electron.
 
-#include "vbqmc_device.h"
+#include "vbqmc_group.h"
 
 namespace vbqmc {
-
-extern __shared__ double lds_dyn[];
 
 // sum over the 64 lanes of a wavefront, the same bits in every lane
 template <int K>
@@ -219,97 +217,140 @@ __device__ __forceinline__ void chan_vg(const DevWF& wf, const Ld& l, int e, int
   o[3] = Pz * g + P * fr * z;
 }
 
-// Tile of 16 walkers (rows e < ne): out[(w0 + e) * 4 * nop + c * nop + p].
-template <int PREC>
-__global__ __launch_bounds__(64) void k_dmcb_rows(const DevWF* __restrict__ pwf, const double* ctrl,
-                                                  const double* P, double* out) {
+// Row tiles of 16 walkers (rows e < ne), three uses:
+//   MODE 0  value and gradient rows at the proposals P:
+//           out[(w0 + e) * 4 * nop + c * nop + p], c = value, x, y, z;
+//   MODE 1  value rows at electron i of walkers whose spin-s reference inverse
+//           is due for a refresh, scattered into the record: reference
+//           columns into the matrix A (the B area, inverted in place later),
+//           table columns into PP (the backup area's T slot);
+//   MODE 2  gradient and Laplacian rows at electron i:
+//           out[(w0 + e) * 4 * nop + c * nop + p], c = x, y, z, Laplacian.
+// A tile is one workgroup of NT threads (NT / 64 wavefronts): the wavefronts
+// share the staged basis tables and split the radial sums, then take the
+// 16-column output tiles in turn.
+template <int PREC, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_dmcb_rows(const DevWF* __restrict__ pwf, const double* ctrl,
+                                                  const double* P, double* out, double* state, int i) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  constexpr int NW = NT / 64;
   const DevWF& wf = *pwf;
   const int64_t W = (int64_t)ctrl[DC_W];
   const int64_t w0 = (int64_t)blockIdx.x * kGroup;
   if (ctrl[DC_ERR] != 0.0 || w0 >= W) return;
   const int ne = (int)min((int64_t)kGroup, W - w0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = spin_of(wf, i);
+  const SpinTab& sp = wf.sp[s];
+  const int il = i - sp.e0;
+  if constexpr (MODE == 1) {
+    bool need = false;  // walker threadIdx.x (< ne) refreshes spin s
+    if (threadIdx.x < ne) {
+      const double* sc = state + (w0 + threadIdx.x) * wf.rec_len + wf.r_sc;
+      need = sc[SC_FLAGS] == 0.0 && sc[SC_NUPD0 + s] >= wf.refresh_every;
+    }
+    if (!__syncthreads_or(need)) return;
+  }
   Ld l(lds_dyn, wf);
-  stage_tables<64, PREC>(wf, l);
-  group_radial<64, PREC, 3>(wf, l, P + 3 * w0, 0, ne);
-  const int lane = threadIdx.x;
+  stage_tables<NT, PREC>(wf, l);
+  const double* Rsrc = P + 3 * w0;
+  if constexpr (MODE != 0) {
+    double* Rt = l.R();
+    if (threadIdx.x < 3 * ne)
+      Rt[threadIdx.x] = state[(w0 + threadIdx.x / 3) * wf.rec_len + wf.r_R + 3 * i + threadIdx.x % 3];
+    Rsrc = Rt;
+    __syncthreads();
+  }
+  group_radial<NT, PREC, 3>(wf, l, Rsrc, 0, ne);
   const int nct = wf.nop / 16;
   const size_t ost = (size_t)4 * wf.nop;
   double* o = out + (size_t)w0 * ost;
-  for (int ct = 0; ct < nct; ++ct) {
+  const int e = lane & 15;
+  const bool live = e < ne;
+  constexpr int NC = MODE == 1 ? 1 : 4;
+  typedef typename std::conditional<PREC == 0, v4d, v4f>::type acc_t;
+  for (int ct = wave; ct < nct; ct += NW) {
     const int col = ct * 16 + (lane & 15);
-    const int e = lane & 15;
-    const bool live = e < ne;
-    if constexpr (PREC == 0) {
-      const double* lam = wf.lamT;
-      v4d acc[4];
+    acc_t acc[NC];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        const int k = k0 + (lane >> 4);
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        if (live) chan_vg<double>(wf, l, e, k, a);
-        const double b = lam[(size_t)k * wf.nop + col];
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], b, acc[c], 0, 0, 0);
+      for (int r = 0; r < 4; ++r) acc[c][r] = 0;
+    if constexpr (PREC != 2) {
+      const T* lam = PREC == 0 ? (const T*)wf.lamT : (const T*)wf.lamT32;
+      // Mpad is a multiple of 16: four k-steps of 4 functions per pass, their
+      // coefficient loads and A operands formed before the MFMAs
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        T a[4][4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          b[u] = lam[(size_t)k * wf.nop + col];
+          a[u][0] = a[u][1] = a[u][2] = a[u][3] = T(0);
+          if (live) {
+            if constexpr (MODE == 0) chan_vg<T>(wf, l, e, k, a[u]);
+            else if constexpr (MODE == 1) a[u][0] = chan_value<T, 3>(wf, l, e, k, 0);
+            else chan_value4<T>(wf, l, e, k, a[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            if constexpr (PREC == 0) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][c], b[u], acc[c], 0, 0, 0);
+            else acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c], b[u], acc[c], 0, 0, 0);
+          }
       }
-      // f64 16x16x4 output: register r of lane l holds row 4r + l/16
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * r + (lane >> 4) < ne) o[(4 * r + (lane >> 4)) * ost + c * wf.nop + col] = acc[c][r];
-    } else if constexpr (PREC == 1) {
-      const float* lam = wf.lamT32;
-      v4f acc[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = v4f{0, 0, 0, 0};
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        const int k = k0 + (lane >> 4);
-        float a[4] = {0.f, 0.f, 0.f, 0.f};
-        if (live) chan_vg<float>(wf, l, e, k, a);
-        const float b = lam[(size_t)k * wf.nop + col];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b, acc[c], 0, 0, 0);
-      }
-      // f32 output: register r of lane l holds row 4(l/16) + r
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * (lane >> 4) + r < ne) o[(4 * (lane >> 4) + r) * ost + c * wf.nop + col] = (double)acc[c][r];
     } else {
       const uint16_t* lam = wf.lamT16;
-      v4f acc[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = v4f{0, 0, 0, 0};
       for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
         const int kb = k0 + 4 * (lane >> 4);
-        v4s a[4], b;
+        v4s a[NC], b;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float v[4] = {0.f, 0.f, 0.f, 0.f};
-          if (live) chan_vg<float>(wf, l, e, kb + j, v);
+          if (live) {
+            if constexpr (MODE == 0) chan_vg<float>(wf, l, e, kb + j, v);
+            else if constexpr (MODE == 1) v[0] = chan_value<float, 3>(wf, l, e, kb + j, 0);
+            else chan_value4<float>(wf, l, e, kb + j, v);
+          }
 #pragma unroll
-          for (int c = 0; c < 4; ++c) a[c][j] = (short)f2bf(v[c]);
+          for (int c = 0; c < NC; ++c) a[c][j] = (short)f2bf(v[c]);
           b[j] = (short)lam[(size_t)(kb + j) * wf.nop + col];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b, acc[c], 0, 0, 0);
+        for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b, acc[c], 0, 0, 0);
       }
+    }
+    // output rows of register r: f64 16x16x4 holds row 4r + lane/16, the
+    // f32 and bf16 forms row 4(lane/16) + r
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+    for (int r = 0; r < 4; ++r) {
+      const int row = PREC == 0 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+      if (row >= ne) continue;
+      if constexpr (MODE == 1) {
+        const int m = sp.omap[col];
+        if (m < 0) continue;
+        double* rec = state + (w0 + row) * wf.rec_len;
+        const double* sc = rec + wf.r_sc;
+        if (!(sc[SC_FLAGS] == 0.0 && sc[SC_NUPD0 + s] >= wf.refresh_every)) continue;
+        if (m < sp.n) rec[wf.r_B[s] + il * sp.n + m] = (double)acc[0][r];
+        else rec[wf.r_bk + wf.r_T[s] - wf.r_R + il * sp.nP + (m - sp.n)] = (double)acc[0][r];
+      } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * (lane >> 4) + r < ne) o[(4 * (lane >> 4) + r) * ost + c * wf.nop + col] = (double)acc[c][r];
+        for (int c = 0; c < 4; ++c) o[row * ost + c * wf.nop + col] = (double)acc[c][r];
+      }
     }
   }
 }
+
+constexpr int kRowsNT = 256;  // threads of a row tile
 
 // ---------------------------------------------------------------------------
 // accept: ratio, node check, drift at r', Green's function, Metropolis,
 // Sherman-Morrison update
 // ---------------------------------------------------------------------------
-// LDS (doubles): bcol [64] | y0 [64] | yc [3][64] | Qn [nUmax] | Rn [nUmax]
+// LDS (doubles): bcol [64] | y0 [64] | yc [3][64] | Qn [nUmax] | Rn [nUmax] | T [n nP]
 template <int NB>
 __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pwf, double* state,
                                                     const double* ctrl, int i, uint64_t seed, uint32_t step,
@@ -331,6 +372,7 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
   double* yc = lds_dyn + 128;
   double* Qn = lds_dyn + 320;
   double* Rn = Qn + nUm;
+  double* Tl = Rn + nUm;  // the table T, for the minors of the distinct determinants
   const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
   double* RW = rec + wf.r_RW;
   double* Ru = RW + (s ? n0 : 0);
@@ -365,14 +407,19 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
     for (int j = 0; j < NB; ++j)
       if (j < n) bcol[j] = C[j];
   }
-  if (tl) y0[lane - n] = y;
+  if (tl) {
+    y0[lane - n] = y;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < n) Tl[j * nP + (lane - n)] = C[j];
+  }
   __syncthreads();
   // Q_u = rho R_u + y_Q^T adj(T_JQ) B_J,il ; S'' = sum_u Q_u W_u ; Jastrow change
   double part[2] = {0.0, 0.0};
   for (int u = lane; u < nU; u += 64) {
     const int* ui = sp.uinfo + 8 * u;
     double m[9], yy[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
-    const int e = gather_u(ui, Tg, nP, m, nullptr, nullptr, 0.0);
+    const int e = gather_u(ui, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
       if (r < e) {
@@ -431,7 +478,7 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
     for (int u = lane; u < nU; u += 64) {
       const int* ui = sp.uinfo + 8 * u;
       double m[9], bb[3] = {0, 0, 0};
-      const int e = gather_u(ui, Tg, nP, m, bcol, y0, ir);
+      const int e = gather_u(ui, Tl, nP, m, bcol, y0, ir);
 #pragma unroll
       for (int r = 0; r < 3; ++r)
         if (r < e) bb[r] = bcol[ui[1 + r]] * ir;
@@ -473,7 +520,7 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
   for (int u = lane; u < nU; u += 64) {
     const int* ui = sp.uinfo + 8 * u;
     double m[9];
-    const int e = gather_u(ui, Tg, nP, m, nullptr, nullptr, 0.0);
+    const int e = gather_u(ui, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -527,20 +574,274 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
 }
 
 // ---------------------------------------------------------------------------
+// end of a step: inverse refresh, local energy, branching weight
+// ---------------------------------------------------------------------------
+// Refresh of the walkers whose spin reached refresh_every updates: the value
+// rows were scattered into the record as A (B area) and PP (backup T slot);
+// the two half-waves invert the two spins' A in LDS at the same time, then
+// T = B PP, and R_u, W_u and S of both spins are rebuilt.
+// LDS (doubles): per spin A [n^2], PP [n nP], T [n nP]; pivots and columns.
+__global__ __launch_bounds__(64) void k_dmcb_refresh(const DevWF* __restrict__ pwf, double* state,
+                                                     const double* ctrl) {
+  const DevWF& wf = *pwf;
+  const int64_t w = blockIdx.x;
+  const int64_t W = (int64_t)ctrl[DC_W];
+  if (ctrl[DC_ERR] != 0.0 || w >= W) return;
+  double* rec = state + w * wf.rec_len;
+  double* sc = rec + wf.r_sc;
+  if (sc[SC_FLAGS] != 0.0) return;
+  bool need[2];
+  for (int s = 0; s < 2; ++s) need[s] = wf.sp[s].n > 0 && sc[SC_NUPD0 + s] >= wf.refresh_every;
+  if (!need[0] && !need[1]) return;
+  const int lane = threadIdx.x;
+  const int nmax = max(wf.sp[0].n, wf.sp[1].n);
+  double* A[2];
+  double* PP[2];
+  double* Tl[2];
+  {
+    double* p = lds_dyn;
+    for (int s = 0; s < 2; ++s) {
+      const int n = wf.sp[s].n, nP = wf.sp[s].nP;
+      A[s] = p; p += n * n;
+      PP[s] = p; p += n * nP;
+      Tl[s] = p; p += n * nP;
+    }
+    // pivots (2 nmax ints in nmax doubles) and the pivot columns of both spins
+    int* piv = (int*)p;
+    double* f = p + nmax;
+    for (int s = 0; s < 2; ++s) {
+      const SpinTab& sp = wf.sp[s];
+      const int n = sp.n, nP = sp.nP;
+      if (need[s]) {
+        for (int k = lane; k < n * n; k += 64) A[s][k] = rec[wf.r_B[s] + k];
+        for (int k = lane; k < n * nP; k += 64) PP[s][k] = rec[wf.r_bk + wf.r_T[s] - wf.r_R + k];
+      } else {
+        for (int k = lane; k < n * nP; k += 64) Tl[s][k] = rec[wf.r_T[s] + k];
+      }
+    }
+    __syncthreads();
+    // half-wave h inverts spin h
+    const int h = lane >> 5, qh = lane & 31;
+    bool ok = true;
+    double ld = 0.0, sg = 1.0;
+    if (need[h]) ok = gj_invert_h<32>(A[h], wf.sp[h].n, qh, piv + h * nmax, f + h * nmax, ld, sg);
+    const bool ok_other = __shfl_xor((int)ok, 32, 64) != 0;
+    ok = ok && ok_other;
+    if (qh == 0 && need[h]) {
+      sc[SC_LOGDET0 + h] = ld;
+      sc[SC_SGN0 + h] = sg;
+      sc[SC_NUPD0 + h] = 0.0;
+    }
+    __syncthreads();
+    if (!ok) {
+      if (lane == 0) sc[SC_FLAGS] = 1.0;
+      return;
+    }
+  }
+  // T = B PP of the refreshed spins; B and T back to the record
+  for (int s = 0; s < 2; ++s) {
+    if (!need[s]) continue;
+    const int n = wf.sp[s].n, nP = wf.sp[s].nP;
+    for (int idx = lane; idx < n * nP; idx += 64) {
+      const int j = idx / max(nP, 1), c = idx - j * nP;
+      double a = 0.0;
+      for (int k = 0; k < n; ++k) a += A[s][j * n + k] * PP[s][k * nP + c];
+      Tl[s][idx] = a;
+      rec[wf.r_T[s] + idx] = a;
+    }
+    for (int k = lane; k < n * n; k += 64) rec[wf.r_B[s] + k] = A[s][k];
+  }
+  __syncthreads();
+  // R_u of both spins, W_u from the other spin's R, S
+  const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
+  double* RW = rec + wf.r_RW;
+  double* Rl = lds_dyn + (A[1] - lds_dyn) + wf.sp[1].n * (wf.sp[1].n + 2 * wf.sp[1].nP) + 3 * nmax;  // R_u, both spins
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& sp = wf.sp[s];
+    for (int u = lane; u < sp.nU; u += 64) {
+      double m[9];
+      const int e = gather_u(sp.uinfo + 8 * u, Tl[s], sp.nP, m, nullptr, nullptr, 0.0);
+      Rl[(s ? n0 : 0) + u] = det_e(e, m);
+    }
+  }
+  __syncthreads();
+  double vs[1] = {0.0};
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& sp = wf.sp[s];
+    const double* Ro = Rl + (s ? 0 : n0);
+    for (int u = lane; u < sp.nU; u += 64) {
+      double a = 0.0;
+      for (int k = sp.wrow[u]; k < sp.wrow[u + 1]; ++k) a += sp.wcoef[k] * Ro[sp.wother[k]];
+      const double r = Rl[(s ? n0 : 0) + u];
+      RW[(s ? n0 : 0) + u] = r;
+      RW[n0 + n1 + (s ? n0 : 0) + u] = a;
+      if (s == 0) vs[0] += r * a;
+    }
+  }
+  wave_sum<1>(vs);
+  if (lane == 0) {
+    RW[2 * (n0 + n1)] = vs[0];
+    if (!(vs[0] != 0.0)) sc[SC_FLAGS] = 1.0;
+  }
+}
+
+// Local-energy terms of electron i (Eq. Elav with Psi = e^U D) from its
+// gradient and Laplacian rows (MODE 2 tiles): grad_i D / D and lap_i D / D by
+// the row-operator formula of the moves, the Jastrow gradient and Laplacian
+// and the potential of electron i (e-e terms halved); kinetic and potential
+// sums per walker in ek, ep (overwritten for i = 0).
+__global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf, const double* state,
+                                                   const double* ctrl, int i, const double* Vp, double* ek,
+                                                   double* ep) {
+  __shared__ double bcol[64], yc[4 * 64];
+  const DevWF& wf = *pwf;
+  const int64_t w = blockIdx.x;
+  const int64_t W = (int64_t)ctrl[DC_W];
+  if (ctrl[DC_ERR] != 0.0 || w >= W) return;
+  const double* rec = state + w * wf.rec_len;
+  if (rec[wf.r_sc + SC_FLAGS] != 0.0) return;
+  const int lane = threadIdx.x;
+  const int s = spin_of(wf, i);
+  const SpinTab& sp = wf.sp[s];
+  const int n = sp.n, nP = sp.nP, il = i - sp.e0;
+  const RecRW rw = rec_rw(wf, rec, s);
+  const double* B = rec + wf.r_B[s];
+  const double* T = rec + wf.r_T[s];
+  const double* vr = Vp + (size_t)w * 4 * wf.nop;
+  const int* ref = sp.ref;
+  const int* porb = sp.porb;
+  double rp[4] = {0.0, 0.0, 0.0, 0.0};
+  if (lane < n) {
+    const double b = B[lane * n + il];
+    bcol[lane] = b;
+    const int rj = ref[lane];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rp[c] = vr[c * wf.nop + rj] * b;
+  }
+  if (lane < nP) {
+    const int pq = porb[lane];
+    double a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = vr[c * wf.nop + pq];
+    for (int l = 0; l < n; ++l) {
+      const double t = T[l * nP + lane];
+      const int rl = ref[l];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] -= vr[c * wf.nop + rl] * t;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) yc[c * 64 + lane] = a[c];
+  }
+  wave_sum<4>(rp);
+  __syncthreads();
+  double part[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int u = lane; u < sp.nU; u += 64) {
+    const int* ui = sp.uinfo + 8 * u;
+    double m[9], bb[3] = {0, 0, 0};
+    const int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) bb[r] = bcol[ui[1 + r]];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double yy[3] = {0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        if (r < e) yy[r] = yc[c * 64 + ui[4 + r]];
+      part[c] += (rp[c] * rw.Ru[u] + adj_e(e, m, yy, bb)) * rw.Wu[u];
+    }
+  }
+  // Jastrow gradient, Laplacian and potential of electron i
+  {
+    const double* R = rec + wf.r_R;
+    const double xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
+    const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
+    for (int j = lane; j < wf.N + wf.nnuc; j += 64) {
+      if (j == i) continue;
+      double xj, yj, zj, wv;
+      PairCoef cf;
+      if (j < wf.N) {
+        xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
+        cf = s != spin_of(wf, j) ? c_anti : c_par;
+        wv = 0.5;
+      } else {
+        const int a = j - wf.N;
+        xj = wf.nuc[4 * a]; yj = wf.nuc[4 * a + 1]; zj = wf.nuc[4 * a + 2];
+        cf = en_coef(wf.en + 6 * a);
+        wv = -wf.nuc[4 * a + 3];
+      }
+      const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / r;
+      double u, u1, u2;
+      pair_fn(r, wf.kappa, cf, u, u1, u2);
+      const double f = u1 * ir;
+      part[4] += f * dx;
+      part[5] += f * dy;
+      part[6] += f * dz;
+      part[7] += u2 + 2.0 * f;
+      part[8] += wv * ir;
+    }
+  }
+  wave_sum<9>(part);
+  if (lane == 0) {
+    const double iS = 1.0 / rw.S;
+    const double gx = part[4], gy = part[5], gz = part[6];
+    const double t = part[7] + part[3] * iS + gx * gx + gy * gy + gz * gz +
+                     2.0 * (gx * part[0] + gy * part[1] + gz * part[2]) * iS;
+    ek[w] = i == 0 ? t : ek[w] + t;
+    ep[w] = i == 0 ? part[8] : ep[w] + part[8];
+  }
+}
+
+// E_L = -1/2 sum_i T_i + V + V_nn, the branching weight
+// w = exp(-tau ((E_L + E_L') / 2 - E_T)) (E_L clipped to E_T +- 10 / sqrt(tau))
+// and floor(w + u) copies, as at the end of k_dmc_step.
+__global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ pwf, double* state,
+                                                     const double* ctrl, uint64_t seed, uint32_t step, double tau,
+                                                     const double* ek, const double* ep, double* wts, double* wel,
+                                                     int* ncopy) {
+  const DevWF& wf = *pwf;
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t W = (int64_t)ctrl[DC_W];
+  if (ctrl[DC_ERR] != 0.0 || w >= W) return;
+  double* sc = state + w * wf.rec_len + wf.r_sc;
+  const bool bad = sc[SC_FLAGS] != 0.0;
+  const double ET = ctrl[DC_ET];
+  const double E_old = sc[SC_ELOC];
+  const double En = bad ? NAN : -0.5 * ek[w] + ep[w] + wf.vnn;
+  const double cap = 10.0 / sqrt(tau);
+  const double eo = fmin(fmax(E_old, ET - cap), ET + cap);
+  const double en = fmin(fmax(En, ET - cap), ET + cap);
+  const double wt = exp(-tau * (0.5 * (eo + en) - ET));
+  double ub, dummy;
+  philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 2u, 0u, ub, dummy);
+  const int nc = bad ? -1 : min(3, (int)floor(wt + ub));
+  wts[w] = bad ? NAN : wt;
+  wel[w] = bad ? NAN : wt * En;
+  ncopy[w] = nc;
+  sc[SC_ELOC] = En;
+}
+
+// ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
+// the dynamic LDS limit of a row-tile kernel, raised to what this launch needs
+// (the kernels' static LDS counts against the device maximum)
+static hipError_t rows_lds_attr(const void* fn, size_t lds, size_t& cur) {
+  if (lds <= cur) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) cur = lds;
+  return e;
+}
+
 template <int PREC>
 static hipError_t launch_rows_t(size_t lds, const DevWF* dwf_rows, const double* ctrl, int64_t cap,
                                 const double* P, double* Vp, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dmcb_rows<PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       163840);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((k_dmcb_rows<PREC>), dim3((unsigned)((cap + kGroup - 1) / kGroup)), dim3(64), lds, s, dwf_rows,
-                     ctrl, P, Vp);
+  static size_t cur = 0;
+  hipError_t e = rows_lds_attr((const void*)k_dmcb_rows<PREC, 0, kRowsNT>, lds, cur);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_dmcb_rows<PREC, 0, kRowsNT>), dim3((unsigned)((cap + kGroup - 1) / kGroup)), dim3(kRowsNT),
+                     lds, s, dwf_rows, ctrl, P, Vp, nullptr, 0);
   return hipSuccess;
 }
 
@@ -549,7 +850,8 @@ static hipError_t launch_accept_t(const DevWF& wf, const DevWF* dwf, double* sta
                                   int i, uint64_t seed, uint32_t step, double tau, const double* P, const double* V,
                                   const double* Vp, double* nacc, hipStream_t s) {
   const int nUm = std::max(wf.sp[0].nU, wf.sp[1].nU);
-  const size_t lds = (size_t)(320 + 2 * nUm) * sizeof(double);
+  const int nT = std::max(wf.sp[0].n * wf.sp[0].nP, wf.sp[1].n * wf.sp[1].nP);
+  const size_t lds = (size_t)(320 + 2 * nUm + nT) * sizeof(double);
   hipLaunchKernelGGL((k_dmcb_accept<NB>), dim3((unsigned)cap), dim3(64), lds, s, dwf, state, ctrl, i, seed, step,
                      tau, P, V, Vp, nacc);
   return hipSuccess;
@@ -575,6 +877,52 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
   else if (nmax <= 32) e = launch_accept_t<32>(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
   else e = launch_accept_t<64>(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
   if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// End of an electron-major step: refresh rows and inversions, E_L rows and
+// terms per electron, weights.  ek, ep [cap] are workspace.
+hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
+                              double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
+                              double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
+                              hipStream_t s) {
+  const unsigned tiles = (unsigned)((cap + kGroup - 1) / kGroup);
+  static size_t cur[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  auto rows = [&](auto kern, int prec, int mi, int i) -> hipError_t {
+    hipError_t e = rows_lds_attr((const void*)kern, rows_lds, cur[prec][mi]);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kRowsNT), rows_lds, s, dwf_rows, ctrl, nullptr, Vp, state, i);
+    return hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < wf.N && e == hipSuccess; ++i) {
+    switch (wf.precision) {
+      case 0: e = rows(k_dmcb_rows<0, 1, kRowsNT>, 0, 0, i); break;
+      case 1: e = rows(k_dmcb_rows<1, 1, kRowsNT>, 1, 0, i); break;
+      default: e = rows(k_dmcb_rows<2, 1, kRowsNT>, 2, 0, i); break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  size_t rl = 0;
+  const int nmax = std::max(wf.sp[0].n, wf.sp[1].n);
+  for (int sp = 0; sp < 2; ++sp) rl += (size_t)wf.sp[sp].n * (wf.sp[sp].n + 2 * wf.sp[sp].nP);
+  rl += 3 * (size_t)nmax + (size_t)(wf.sp[0].nU + wf.sp[1].nU);
+  static size_t cur_ref = 0;
+  e = rows_lds_attr((const void*)k_dmcb_refresh, rl * sizeof(double), cur_ref);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dmcb_refresh, dim3((unsigned)cap), dim3(64), rl * sizeof(double), s, dwf, state, ctrl);
+  for (int i = 0; i < wf.N && e == hipSuccess; ++i) {
+    switch (wf.precision) {
+      case 0: e = rows(k_dmcb_rows<0, 2, kRowsNT>, 0, 1, i); break;
+      case 1: e = rows(k_dmcb_rows<1, 2, kRowsNT>, 1, 1, i); break;
+      default: e = rows(k_dmcb_rows<2, 2, kRowsNT>, 2, 1, i); break;
+    }
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(k_dmcb_eterm, dim3((unsigned)cap), dim3(64), 0, s, dwf, state, ctrl, i, Vp, ek, ep);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dmcb_weight, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, dwf, state, ctrl, seed,
+                     step, tau, ek, ep, wts, wel, ncopy);
   return hipGetLastError();
 }
 

@@ -38,9 +38,10 @@ hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, c
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s);
-hipError_t launch_dmc_finish(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl,
-                             int64_t cap, uint64_t seed, uint32_t step, double tau, double* wts, double* wel,
-                             int* ncopy, hipStream_t s);
+hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
+                              double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
+                              double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
+                              hipStream_t s);
 hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds, double* state,
                             double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
                             double* V, double* Vp, double* nacc, hipStream_t s);
@@ -366,13 +367,15 @@ DevWF rows_layout(const vbqmc_ctx* x) {
   return a;
 }
 
-// Electron-major DMC row tiles: the tables without the orbital
-// coefficients and the tile tables (radial sums with both derivatives).
+// Electron-major DMC row tiles: only the basis tables (the first part of
+// the table image, up to the Jastrow coefficients) and the tile tables
+// (positions, radial sums with both derivatives).
 DevWF dmcb_layout(const vbqmc_ctx* x) {
   DevWF a = x->wf;
-  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  LdsAlloc lds{a.l_en};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
+  a.l_R = lds(3 * kGroup);
   a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
   a.l_gtab = lds(kGroup * ((3 * x->nshell) | 1));
   a.lds_tile_doubles = lds.o;
@@ -382,9 +385,14 @@ DevWF dmcb_layout(const vbqmc_ctx* x) {
 // electron-major DMC handles the system: every spin's reference slots plus
 // table orbitals fit the 64 lanes of a wavefront, and the row tiles fit LDS
 bool dmcb_fit(const vbqmc_ctx* x) {
-  for (int s = 0; s < 2; ++s)
-    if (x->sp[s].n + (int)x->sp[s].porb.size() > 64) return false;
-  return (size_t)dmcb_layout(x).lds_tile_doubles * 8 <= (size_t)x->lds_limit;
+  size_t refresh = 3 * (size_t)std::max(x->nup, x->ndn);  // LDS of the refresh kernel (doubles)
+  for (int s = 0; s < 2; ++s) {
+    const int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+    if (n + nP > 64) return false;
+    refresh += (size_t)n * (n + 2 * nP) + x->sp[s].sets.size();
+  }
+  return (size_t)dmcb_layout(x).lds_tile_doubles * 8 <= (size_t)x->lds_limit &&
+         refresh * 8 <= (size_t)x->lds_limit;
 }
 
 // the row step kernel handles the system: at most 16 columns (reference
@@ -914,7 +922,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   for (int s = 0; s < 2; ++s) {
     SpinHost& h = x->sp[s];
     add(h.ref.size(), 4); add(h.porb.size(), 4); add(h.uinfo.size(), 4); add(h.wrow.size(), 4);
-    add(h.wother.size(), 4); add(h.wother.size(), 8);
+    add(h.wother.size(), 4); add(h.wother.size(), 8); add((size_t)x->nop, 4);
   }
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
   add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
@@ -947,6 +955,10 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     a = carve<int>(p, h.wother.size()); up(h.wother.data(), h.wother.size(), 4, a); t.wother = a;
     x->d_wcoef[s] = carve<double>(p, h.wother.size());
     t.wcoef = x->d_wcoef[s];
+    std::vector<int> om(x->nop, -1);
+    for (int j = 0; j < (int)h.ref.size(); ++j) om[h.ref[j]] = j;
+    for (int q = 0; q < (int)h.porb.size(); ++q) om[h.porb[q]] = h.n + q;
+    a = carve<int>(p, om.size()); up(om.data(), om.size(), 4, a); t.omap = a;
   }
   int* d_srow = carve<int>(p, x->srow.size()); up(x->srow.data(), x->srow.size(), 4, d_srow);
   int* d_slu = carve<int>(p, x->slu.size()); up(x->slu.data(), x->slu.size(), 4, d_slu);
@@ -1123,7 +1135,7 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
 }
 
 // DMC workspace: ctrl (8 doubles) | wts, wel, nacc [cap] | ncopy [cap] |
-// offs [cap+1] | (electron-major kernels) P, V [cap][3], Vp [cap][4][nop]
+// offs [cap+1] | (electron-major kernels) P, V [cap][3], Vp [cap][4][nop], ek, ep [cap]
 namespace {
 size_t dmc_ws_base(int64_t cap) { return 64 + 3 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
 }  // namespace
@@ -1132,7 +1144,7 @@ int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, 
   if (!x || !bytes || cap < 1) return VBQMC_EINVAL;
   (void)n_steps;
   size_t b = dmc_ws_base(cap) + 256;
-  if (x->dmc_kernel == 2) b += (size_t)cap * (6 + 4 * (size_t)x->nop) * 8 + 256;
+  if (x->dmc_kernel == 2) b += (size_t)cap * (8 + 4 * (size_t)x->nop) * 8 + 256;
   *bytes = b;
   return VBQMC_OK;
 }
@@ -1175,6 +1187,8 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   double* Pw = (double*)pb;
   double* Vw = Pw + 3 * cap;
   double* Vpw = Vw + 3 * cap;
+  double* ekw = Vpw + 4 * (size_t)x->nop * cap;
+  double* epw = ekw + cap;
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
     if (x->dmc_kernel == 2) {
@@ -1183,7 +1197,8 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
         e = launch_dmcb_move(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, i, seed, step, tau, Pw, Vw,
                              Vpw, nacc, s);
       if (e == hipSuccess)
-        e = launch_dmc_finish(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, s);
+        e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, seed, step, tau, Vpw, ekw,
+                               epw, wts, wel, ncopy, s);
     } else {
       e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
     }

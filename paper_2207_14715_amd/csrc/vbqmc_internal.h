@@ -30,6 +30,7 @@ struct SpinTab {
   const int* wrow;  // [nU + 1] CSR over the determinant pairs holding u
   const int* wother;     // other spin's determinant of each pair
   const double* wcoef;   // w_k = sum_I c_I d'_{I,k} of each pair
+  const int* omap;       // [nop] per orbital: its reference slot j, or n + its table index q, or -1
 };
 
 // Constant description of the wave function plus layouts, passed by value to

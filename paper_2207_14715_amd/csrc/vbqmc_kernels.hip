@@ -698,54 +698,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   store_record<NT>(wf, l, rec);
 }
 
-// End of an electron-major DMC step (the moves ran as per-electron launches
-// over all walkers): inverse refresh when due, the local energy (which also
-// rewrites the cached gradient rows), and the branching weight and copy
-// count, exactly as at the end of k_dmc_step.  nacc already holds the step's
-// accepted moves.
-template <int NT, int PREC>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_dmc_finish(
-    const DevWF* __restrict__ pwf, double* state, const double* ctrl, uint64_t seed, uint32_t step, double tau,
-    double* wts, double* wel, int* ncopy) {
-  const DevWF& wf = *pwf;
-  const int64_t w = blockIdx.x;
-  const int64_t W = (int64_t)ctrl[DC_W];
-  if (ctrl[DC_ERR] != 0.0 || w >= W) return;
-  Ld l(lds_dyn, wf);
-  stage_tables<NT, PREC>(wf, l);
-  double* rec = state + w * wf.rec_len;
-  double* gc = rec + wf.r_gc;
-  load_record<NT>(wf, l, rec);
-  compute_RWS<NT>(wf, l);
-  double* sc = l.sc();
-  const double ET = ctrl[DC_ET];
-  const double E_old = sc[SC_ELOC];
-  const double sqt = sqrt(tau);
-  bool bad = sc[SC_FLAGS] != 0.0 || !(sc[SC_S] != 0.0);
-  if (!bad && (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every)) {
-    if (!build_state<NT, PREC>(wf, l, l.R())) bad = true;
-    else compute_RWS<NT>(wf, l);
-  }
-  if (!bad) local_energy<NT, PREC>(wf, l, gc);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double En = bad ? NAN : sc[SC_ELOC];
-    double cap = 10.0 / sqt;
-    double eo = fmin(fmax(E_old, ET - cap), ET + cap);
-    double en = fmin(fmax(En, ET - cap), ET + cap);
-    double wt = exp(-tau * (0.5 * (eo + en) - ET));
-    double ub, dummy;
-    philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 2u, 0u, ub, dummy);
-    int nc = bad ? -1 : min(3, (int)floor(wt + ub));
-    wts[w] = bad ? NAN : wt;
-    wel[w] = bad ? NAN : wt * En;
-    ncopy[w] = nc;
-    if (bad) sc[SC_FLAGS] = 1.0;
-  }
-  __syncthreads();
-  store_record<NT>(wf, l, rec);
-}
-
 // Single-workgroup scan / reduction / trial-energy update of one DMC step.
 // Fixed summation order, so the result is independent of timing.
 __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* wts, const double* wel,
@@ -1000,24 +952,6 @@ hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* st
                            uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
                            hipStream_t s) {
   VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s)
-}
-
-template <int NT, int PREC>
-static hipError_t launch_dmc_finish_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl,
-                                      int64_t cap, uint64_t seed, uint32_t step, double tau, double* wts,
-                                      double* wel, int* ncopy, hipStream_t s) {
-  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
-  hipError_t e = set_lds<NT, PREC>((const void*)k_dmc_finish<NT, PREC>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dmc_finish<NT, PREC>), dim3((unsigned)cap), dim3(NT), lds, s, dwf, state, ctrl, seed, step,
-                     tau, wts, wel, ncopy);
-  return hipGetLastError();
-}
-
-hipError_t launch_dmc_finish(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl,
-                             int64_t cap, uint64_t seed, uint32_t step, double tau, double* wts, double* wel,
-                             int* ncopy, hipStream_t s) {
-  VB_DISPATCH_NT(nt, launch_dmc_finish_t, wf, dwf, state, ctrl, cap, seed, step, tau, wts, wel, ncopy, s)
 }
 
 hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, const int* ncopy, const double* nacc,
