@@ -13,7 +13,8 @@
 //            replaced-column table, as in the VMC kernels), node check, drift
 //            at r' from the rank-1-updated state, Green's-function ratio,
 //            Metropolis decision and, when accepted, the Sherman-Morrison
-//            update with lane k owning column k of [B | T] in registers.
+//            update, lane k owning column k of [B | T] (streamed from the
+//            record, the table also kept in LDS for the minors).
 // The walker records stay in HBM between launches and each launch streams
 // what it needs, so occupancy no longer depends on how much state a walker
 // has.  Inverse refresh, the local energy and the branching weight follow in
@@ -74,14 +75,62 @@ __device__ __forceinline__ void jastrow_grad_part(const DevWF& wf, const double*
   }
 }
 
+// Distinct determinants u = lane and u = lane + 64 of a wavefront: replaced
+// slots J, table indices Q, R_u and W_u held in registers for the whole
+// kernel (at most 128 distinct determinants per spin).
+struct DetLanes {
+  int e[2], J[2][3], Q[2][3];
+  double R[2], W[2];
+};
+
+__device__ __forceinline__ void load_det_lanes(const SpinTab& sp, const double* Ru, const double* Wu, int lane,
+                                               DetLanes& d) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = lane + 64 * h;
+    d.e[h] = 0;
+    d.R[h] = 0.0;
+    d.W[h] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) d.J[h][r] = d.Q[h][r] = 0;
+    if (u < sp.nU) {
+      const int* ui = sp.uinfo + 8 * u;
+      d.e[h] = ui[0];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        d.J[h][r] = ui[1 + r];
+        d.Q[h][r] = ui[4 + r];
+      }
+      d.R[h] = Ru[u];
+      d.W[h] = Wu[u];
+    }
+  }
+}
+
+// the e x e minor T[J, Q] (+ bc_J y_Q^T * irho when bc is set) from a table in LDS
+__device__ __forceinline__ void minor_of(const DetLanes& d, int h, const double* T, int nP, double* m,
+                                         const double* bc, const double* y, double irho) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (r < d.e[h] && c < d.e[h]) {
+        double v = T[d.J[h][r] * nP + d.Q[h][c]];
+        if (bc) v += bc[d.J[h][r]] * y[d.Q[h][c]] * irho;
+        m[r * 3 + c] = v;
+      }
+}
+
 // ---------------------------------------------------------------------------
 // propose: drift at the current point and the drift-diffusion proposal
 // ---------------------------------------------------------------------------
-// LDS (doubles): bcol [64] | yc [3][64]
+// LDS (doubles): bcol [64] | yc [4][64] | T [n nP]
 __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ pwf, double* state,
                                                      double* ctrl, int i, uint64_t seed, uint32_t step,
                                                      double tau, double* P, double* V, double* nacc) {
-  __shared__ double bcol[64], yc[3 * 64];
+  double* bcol = lds_dyn;
+  double* yc = lds_dyn + 64;
+  double* Tl = lds_dyn + 320;
   const DevWF& wf = *pwf;
   const int64_t w = blockIdx.x;
   const int64_t W = (int64_t)ctrl[DC_W];
@@ -107,6 +156,8 @@ __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ p
   const double* gr = rec + wf.r_gc + (size_t)i * 3 * wf.nop;  // gradient rows of electron i
   const int* ref = sp.ref;
   const int* porb = sp.porb;
+  DetLanes d;
+  load_det_lanes(sp, rw.Ru, rw.Wu, lane, d);
   // column il of B and the three table-row corrections y^c
   double rp[3] = {0.0, 0.0, 0.0};
   if (lane < n) {
@@ -121,6 +172,7 @@ __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ p
     double a[3] = {gr[pq], gr[wf.nop + pq], gr[2 * wf.nop + pq]};
     for (int l = 0; l < n; ++l) {
       const double t = T[l * nP + lane];
+      Tl[l * nP + lane] = t;
       const int rl = ref[l];
 #pragma unroll
       for (int c = 0; c < 3; ++c) a[c] -= gr[c * wf.nop + rl] * t;
@@ -131,20 +183,21 @@ __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ p
   wave_sum<3>(rp);
   __syncthreads();
   double part[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = lane; u < sp.nU; u += 64) {
-    const int* ui = sp.uinfo + 8 * u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (lane + 64 * h >= sp.nU) continue;
     double m[9], bb[3] = {0, 0, 0};
-    const int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+    minor_of(d, h, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      if (r < e) bb[r] = bcol[ui[1 + r]];
+      if (r < d.e[h]) bb[r] = bcol[d.J[h][r]];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double yy[3] = {0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        if (r < e) yy[r] = yc[c * 64 + ui[4 + r]];
-      part[c] += (rp[c] * rw.Ru[u] + adj_e(e, m, yy, bb)) * rw.Wu[u];
+        if (r < d.e[h]) yy[r] = yc[c * 64 + d.Q[h][r]];
+      part[c] += (rp[c] * d.R[h] + adj_e(d.e[h], m, yy, bb)) * d.W[h];
     }
   }
   const double* R = rec + wf.r_R;
@@ -350,12 +403,12 @@ constexpr int kRowsNT = 256;  // threads of a row tile
 // accept: ratio, node check, drift at r', Green's function, Metropolis,
 // Sherman-Morrison update
 // ---------------------------------------------------------------------------
-// LDS (doubles): bcol [64] | y0 [64] | yc [3][64] | Qn [nUmax] | Rn [nUmax] | T [n nP]
-template <int NB>
+// LDS (doubles): bcol [64] | y0 [64] | yc [3][64] | Qn [128] | Rn [128] | T [n nP]
 __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pwf, double* state,
-                                                    const double* ctrl, int i, uint64_t seed, uint32_t step,
-                                                    double tau, const double* P, const double* V,
-                                                    const double* Vp, double* nacc) {
+                                                    const double* __restrict__ ctrl, int i, uint64_t seed,
+                                                    uint32_t step, double tau, const double* __restrict__ P,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ Vp, double* nacc) {
   const DevWF& wf = *pwf;
   const int64_t w = blockIdx.x;
   const int64_t W = (int64_t)ctrl[DC_W];
@@ -366,13 +419,12 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
   const int s = spin_of(wf, i);
   const SpinTab& sp = wf.sp[s];
   const int n = sp.n, nP = sp.nP, nU = sp.nU, il = i - sp.e0;
-  const int nUm = max(wf.sp[0].nU, wf.sp[1].nU);
   double* bcol = lds_dyn;
   double* y0 = lds_dyn + 64;
   double* yc = lds_dyn + 128;
   double* Qn = lds_dyn + 320;
-  double* Rn = Qn + nUm;
-  double* Tl = Rn + nUm;  // the table T, for the minors of the distinct determinants
+  double* Rn = Qn + 128;
+  double* Tl = Rn + 128;  // the table T, for the minors of the distinct determinants
   const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
   double* RW = rec + wf.r_RW;
   double* Ru = RW + (s ? n0 : 0);
@@ -384,51 +436,43 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
   const int* porb = sp.porb;
   const double* vp = Vp + (size_t)w * 4 * wf.nop;
   const bool bl = lane < n, tl = lane >= n && lane < n + nP;
-  // column lane of [B | T]
-  double C[NB];
+  DetLanes d;
+  load_det_lanes(sp, Ru, Wu, lane, d);
+  // t^c_k = sum_j w_c[ref_j] C[j][k] for the value (c = 0) and gradient rows,
+  // C = [B | T] streamed column by column: u = v_ref^T B on B lanes,
+  // v_ref^T T on table lanes
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < n; ++j) {
+    double cj = 0.0;
+    if (bl) cj = Bg[j * n + lane];
+    else if (tl) cj = Tg[j * nP + (lane - n)];
+    const int rj = ref[j];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    double v = 0.0;
-    if (j < n) {
-      if (bl) v = Bg[j * n + lane];
-      else if (tl) v = Tg[j * nP + (lane - n)];
-    }
-    C[j] = v;
+    for (int c = 0; c < 4; ++c) t[c] += vp[c * wf.nop + rj] * cj;
+    if (lane == il) bcol[j] = cj;
+    if (tl) Tl[j * nP + (lane - n)] = cj;
   }
-  // t_k = sum_j v[ref_j] C[j][k]: u = v_ref^T B on B lanes, v_ref^T T on table lanes
-  double t = 0.0;
-#pragma unroll
-  for (int j = 0; j < NB; ++j)
-    if (j < n) t += vp[ref[j]] * C[j];
-  const double rho = __shfl(t, il, 64);
-  const double y = tl ? vp[porb[lane - n]] - t : 0.0;
-  if (lane == il) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < n) bcol[j] = C[j];
-  }
-  if (tl) {
-    y0[lane - n] = y;
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < n) Tl[j * nP + (lane - n)] = C[j];
-  }
+  const double rho = __shfl(t[0], il, 64);
+  const double y = tl ? vp[porb[lane - n]] - t[0] : 0.0;
+  if (tl) y0[lane - n] = y;
   __syncthreads();
   // Q_u = rho R_u + y_Q^T adj(T_JQ) B_J,il ; S'' = sum_u Q_u W_u ; Jastrow change
   double part[2] = {0.0, 0.0};
-  for (int u = lane; u < nU; u += 64) {
-    const int* ui = sp.uinfo + 8 * u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = lane + 64 * h;
+    if (u >= nU) continue;
     double m[9], yy[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
-    const int e = gather_u(ui, Tl, nP, m, nullptr, nullptr, 0.0);
+    minor_of(d, h, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      if (r < e) {
-        yy[r] = y0[ui[4 + r]];
-        bb[r] = bcol[ui[1 + r]];
+      if (r < d.e[h]) {
+        yy[r] = y0[d.Q[h][r]];
+        bb[r] = bcol[d.J[h][r]];
       }
-    const double q = rho * Ru[u] + adj_e(e, m, yy, bb);
+    const double q = rho * d.R[h] + adj_e(d.e[h], m, yy, bb);
     Qn[u] = q;
-    part[0] += q * Wu[u];
+    part[0] += q * d.W[h];
   }
   const double* R = rec + wf.r_R;
   const double p[3] = {P[3 * w], P[3 * w + 1], P[3 * w + 2]};
@@ -465,31 +509,28 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
     double a[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double* wc = vp + (1 + c) * wf.nop;
-      double tc = 0.0;
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < n) tc += wc[ref[j]] * C[j];
-      a[c] = __shfl(tc, il, 64);  // sum_j w_c[ref_j] bcol_j
-      if (tl) yc[c * 64 + (lane - n)] = wc[porb[lane - n]] - tc - a[c] * y * ir;
+      a[c] = __shfl(t[1 + c], il, 64);  // sum_j w_c[ref_j] bcol_j
+      if (tl) yc[c * 64 + (lane - n)] = vp[(1 + c) * wf.nop + porb[lane - n]] - t[1 + c] - a[c] * y * ir;
     }
     __syncthreads();
     double dp[6] = {0, 0, 0, 0, 0, 0};
-    for (int u = lane; u < nU; u += 64) {
-      const int* ui = sp.uinfo + 8 * u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = lane + 64 * h;
+      if (u >= nU) continue;
       double m[9], bb[3] = {0, 0, 0};
-      const int e = gather_u(ui, Tl, nP, m, bcol, y0, ir);
+      minor_of(d, h, Tl, nP, m, bcol, y0, ir);
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        if (r < e) bb[r] = bcol[ui[1 + r]] * ir;
+        if (r < d.e[h]) bb[r] = bcol[d.J[h][r]] * ir;
       const double Rnew = Qn[u] * ir;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double yy[3] = {0, 0, 0};
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-          if (r < e) yy[r] = yc[c * 64 + ui[4 + r]];
-        dp[c] += (a[c] * ir * Rnew + adj_e(e, m, yy, bb)) * Wu[u];
+          if (r < d.e[h]) yy[r] = yc[c * 64 + d.Q[h][r]];
+        dp[c] += (a[c] * ir * Rnew + adj_e(d.e[h], m, yy, bb)) * d.W[h];
       }
     }
     double g[3] = {0, 0, 0};
@@ -502,9 +543,9 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double vn = dp[3 + c] + dp[c] / Snew;
-      const double d = p[c] - x[c];
-      const double fa = d - tau * V[3 * w + c];
-      const double ba = -d - tau * vn;
+      const double dd = p[c] - x[c];
+      const double fa = dd - tau * V[3 * w + c];
+      const double ba = -dd - tau * vn;
       fwd += fa * fa;
       bwd += ba * ba;
     }
@@ -515,35 +556,35 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
   }
   if (!accept) return;
   // R_u from the updated minors (old table + bcol y^T / rho, as the column
-  // update below forms it) and S, read before any table entry is rewritten
+  // update below forms it) and S
   double vs[1] = {0.0};
-  for (int u = lane; u < nU; u += 64) {
-    const int* ui = sp.uinfo + 8 * u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = lane + 64 * h;
+    if (u >= nU) continue;
     double m[9];
-    const int e = gather_u(ui, Tl, nP, m, nullptr, nullptr, 0.0);
+    minor_of(d, h, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        if (r < e && c < e) m[r * 3 + c] = m[r * 3 + c] + bcol[ui[1 + r]] * (y0[ui[4 + c]] * ir);
-    const double r = det_e(e, m);
+        if (r < d.e[h] && c < d.e[h]) m[r * 3 + c] = m[r * 3 + c] + bcol[d.J[h][r]] * (y0[d.Q[h][c]] * ir);
+    const double r = det_e(d.e[h], m);
     Rn[u] = r;
-    vs[0] += r * Wu[u];
+    vs[0] += r * d.W[h];
   }
   wave_sum<1>(vs);
   __syncthreads();
   // Sherman-Morrison: B'[j][k] = B[j][k] - bcol_j (u_k - delta_k,il) / rho,
-  // T' = T + bcol y^T / rho
+  // T' = T + bcol y^T / rho, column by column
   double f = 0.0;
-  if (bl) f = -(t - (lane == il ? 1.0 : 0.0)) * ir;
+  if (bl) f = -(t[0] - (lane == il ? 1.0 : 0.0)) * ir;
   else if (tl) f = y * ir;
-#pragma unroll
-  for (int j = 0; j < NB; ++j)
-    if (j < n) {
-      const double v = C[j] + bcol[j] * f;
-      if (bl) Bg[j * n + lane] = v;
-      else if (tl) Tg[j * nP + (lane - n)] = v;
-    }
+  if (bl) {
+    for (int j = 0; j < n; ++j) Bg[j * n + lane] += bcol[j] * f;
+  } else if (tl) {
+    for (int j = 0; j < n; ++j) Tg[j * nP + (lane - n)] = Tl[j * nP + (lane - n)] + bcol[j] * f;
+  }
   for (int u = lane; u < nU; u += 64) Ru[u] = Rn[u];
   {
     const int o = 1 - s;
@@ -691,9 +732,11 @@ __global__ __launch_bounds__(64) void k_dmcb_refresh(const DevWF* __restrict__ p
 // and the potential of electron i (e-e terms halved); kinetic and potential
 // sums per walker in ek, ep (overwritten for i = 0).
 __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf, const double* state,
-                                                   const double* ctrl, int i, const double* Vp, double* ek,
-                                                   double* ep) {
-  __shared__ double bcol[64], yc[4 * 64];
+                                                   const double* ctrl, int i, const double* __restrict__ Vp,
+                                                   double* ek, double* ep) {
+  double* bcol = lds_dyn;
+  double* yc = lds_dyn + 64;
+  double* Tl = lds_dyn + 320;
   const DevWF& wf = *pwf;
   const int64_t w = blockIdx.x;
   const int64_t W = (int64_t)ctrl[DC_W];
@@ -710,6 +753,8 @@ __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf
   const double* vr = Vp + (size_t)w * 4 * wf.nop;
   const int* ref = sp.ref;
   const int* porb = sp.porb;
+  DetLanes d;
+  load_det_lanes(sp, rw.Ru, rw.Wu, lane, d);
   double rp[4] = {0.0, 0.0, 0.0, 0.0};
   if (lane < n) {
     const double b = B[lane * n + il];
@@ -725,6 +770,7 @@ __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf
     for (int c = 0; c < 4; ++c) a[c] = vr[c * wf.nop + pq];
     for (int l = 0; l < n; ++l) {
       const double t = T[l * nP + lane];
+      Tl[l * nP + lane] = t;
       const int rl = ref[l];
 #pragma unroll
       for (int c = 0; c < 4; ++c) a[c] -= vr[c * wf.nop + rl] * t;
@@ -735,20 +781,21 @@ __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf
   wave_sum<4>(rp);
   __syncthreads();
   double part[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int u = lane; u < sp.nU; u += 64) {
-    const int* ui = sp.uinfo + 8 * u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (lane + 64 * h >= sp.nU) continue;
     double m[9], bb[3] = {0, 0, 0};
-    const int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+    minor_of(d, h, Tl, nP, m, nullptr, nullptr, 0.0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      if (r < e) bb[r] = bcol[ui[1 + r]];
+      if (r < d.e[h]) bb[r] = bcol[d.J[h][r]];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       double yy[3] = {0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        if (r < e) yy[r] = yc[c * 64 + ui[4 + r]];
-      part[c] += (rp[c] * rw.Ru[u] + adj_e(e, m, yy, bb)) * rw.Wu[u];
+        if (r < d.e[h]) yy[r] = yc[c * 64 + d.Q[h][r]];
+      part[c] += (rp[c] * d.R[h] + adj_e(d.e[h], m, yy, bb)) * d.W[h];
     }
   }
   // Jastrow gradient, Laplacian and potential of electron i
@@ -845,15 +892,13 @@ static hipError_t launch_rows_t(size_t lds, const DevWF* dwf_rows, const double*
   return hipSuccess;
 }
 
-template <int NB>
-static hipError_t launch_accept_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
-                                  int i, uint64_t seed, uint32_t step, double tau, const double* P, const double* V,
-                                  const double* Vp, double* nacc, hipStream_t s) {
-  const int nUm = std::max(wf.sp[0].nU, wf.sp[1].nU);
+static hipError_t launch_accept(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                                int i, uint64_t seed, uint32_t step, double tau, const double* P, const double* V,
+                                const double* Vp, double* nacc, hipStream_t s) {
   const int nT = std::max(wf.sp[0].n * wf.sp[0].nP, wf.sp[1].n * wf.sp[1].nP);
-  const size_t lds = (size_t)(320 + 2 * nUm + nT) * sizeof(double);
-  hipLaunchKernelGGL((k_dmcb_accept<NB>), dim3((unsigned)cap), dim3(64), lds, s, dwf, state, ctrl, i, seed, step,
-                     tau, P, V, Vp, nacc);
+  const size_t lds = (size_t)(320 + 256 + nT) * sizeof(double);
+  hipLaunchKernelGGL(k_dmcb_accept, dim3((unsigned)cap), dim3(64), lds, s, dwf, state, ctrl, i, seed, step, tau, P,
+                     V, Vp, nacc);
   return hipSuccess;
 }
 
@@ -863,8 +908,9 @@ static hipError_t launch_accept_t(const DevWF& wf, const DevWF* dwf, double* sta
 hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds, double* state,
                             double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
                             double* V, double* Vp, double* nacc, hipStream_t s) {
-  hipLaunchKernelGGL(k_dmcb_propose, dim3((unsigned)cap), dim3(64), 0, s, dwf, state, ctrl, i, seed, step, tau, P,
-                     V, nacc);
+  const size_t lds_pe = (size_t)(320 + std::max(wf.sp[0].n * wf.sp[0].nP, wf.sp[1].n * wf.sp[1].nP)) * 8;
+  hipLaunchKernelGGL(k_dmcb_propose, dim3((unsigned)cap), dim3(64), lds_pe, s, dwf, state, ctrl, i, seed, step, tau,
+                     P, V, nacc);
   hipError_t e;
   switch (wf.precision) {
     case 0: e = launch_rows_t<0>(rows_lds, dwf_rows, ctrl, cap, P, Vp, s); break;
@@ -872,10 +918,7 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
     default: e = launch_rows_t<2>(rows_lds, dwf_rows, ctrl, cap, P, Vp, s); break;
   }
   if (e != hipSuccess) return e;
-  const int nmax = std::max(wf.sp[0].n, wf.sp[1].n);
-  if (nmax <= 16) e = launch_accept_t<16>(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
-  else if (nmax <= 32) e = launch_accept_t<32>(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
-  else e = launch_accept_t<64>(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
+  e = launch_accept(wf, dwf, state, ctrl, cap, i, seed, step, tau, P, V, Vp, nacc, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -895,6 +938,7 @@ hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dw
     return hipSuccess;
   };
   hipError_t e = hipSuccess;
+  const size_t lds_pe = (size_t)(320 + std::max(wf.sp[0].n * wf.sp[0].nP, wf.sp[1].n * wf.sp[1].nP)) * 8;
   for (int i = 0; i < wf.N && e == hipSuccess; ++i) {
     switch (wf.precision) {
       case 0: e = rows(k_dmcb_rows<0, 1, kRowsNT>, 0, 0, i); break;
@@ -918,7 +962,7 @@ hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dw
       default: e = rows(k_dmcb_rows<2, 2, kRowsNT>, 2, 1, i); break;
     }
     if (e == hipSuccess)
-      hipLaunchKernelGGL(k_dmcb_eterm, dim3((unsigned)cap), dim3(64), 0, s, dwf, state, ctrl, i, Vp, ek, ep);
+      hipLaunchKernelGGL(k_dmcb_eterm, dim3((unsigned)cap), dim3(64), lds_pe, s, dwf, state, ctrl, i, Vp, ek, ep);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dmcb_weight, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, dwf, state, ctrl, seed,

@@ -388,7 +388,7 @@ bool dmcb_fit(const vbqmc_ctx* x) {
   size_t refresh = 3 * (size_t)std::max(x->nup, x->ndn);  // LDS of the refresh kernel (doubles)
   for (int s = 0; s < 2; ++s) {
     const int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
-    if (n + nP > 64) return false;
+    if (n + nP > 64 || x->sp[s].sets.size() > 128) return false;
     refresh += (size_t)n * (n + 2 * nP) + x->sp[s].sets.size();
   }
   return (size_t)dmcb_layout(x).lds_tile_doubles * 8 <= (size_t)x->lds_limit &&
