@@ -278,13 +278,15 @@ __device__ __forceinline__ void chan_vg(const DevWF& wf, const Ld& l, int e, int
 //           columns into the matrix A (the B area, inverted in place later),
 //           table columns into PP (the backup area's T slot);
 //   MODE 2  gradient and Laplacian rows at electron i:
-//           out[(w0 + e) * 4 * nop + c * nop + p], c = x, y, z, Laplacian.
+//           out[(w0 + e) * 4 * nop + c * nop + p], c = x, y, z, Laplacian;
+//           with write_gc also the gradient rows into the record's cache.
 // A tile is one workgroup of NT threads (NT / 64 wavefronts): the wavefronts
 // share the staged basis tables and split the radial sums, then take the
 // 16-column output tiles in turn.
 template <int PREC, int MODE, int NT>
 __global__ __launch_bounds__(NT) void k_dmcb_rows(const DevWF* __restrict__ pwf, const double* ctrl,
-                                                  const double* P, double* out, double* state, int i) {
+                                                  const double* P, double* out, double* state, int i,
+                                                  int write_gc) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   constexpr int NW = NT / 64;
   const DevWF& wf = *pwf;
@@ -392,6 +394,11 @@ __global__ __launch_bounds__(NT) void k_dmcb_rows(const DevWF* __restrict__ pwf,
       } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) o[row * ost + c * wf.nop + col] = (double)acc[c][r];
+        if (MODE == 2 && write_gc) {
+          double* gr = state + (w0 + row) * wf.rec_len + wf.r_gc + (size_t)i * 3 * wf.nop;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gr[c * wf.nop + col] = (double)acc[c][r];
+        }
       }
     }
   }
@@ -846,7 +853,7 @@ __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf
 __global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ pwf, double* state,
                                                      const double* ctrl, uint64_t seed, uint32_t step, double tau,
                                                      const double* ek, const double* ep, double* wts, double* wel,
-                                                     int* ncopy) {
+                                                     int* ncopy, int only_eloc) {
   const DevWF& wf = *pwf;
   const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t W = (int64_t)ctrl[DC_W];
@@ -856,6 +863,10 @@ __global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ p
   const double ET = ctrl[DC_ET];
   const double E_old = sc[SC_ELOC];
   const double En = bad ? NAN : -0.5 * ek[w] + ep[w] + wf.vnn;
+  if (only_eloc) {
+    sc[SC_ELOC] = En;
+    return;
+  }
   const double cap = 10.0 / sqrt(tau);
   const double eo = fmin(fmax(E_old, ET - cap), ET + cap);
   const double en = fmin(fmax(En, ET - cap), ET + cap);
@@ -867,6 +878,20 @@ __global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ p
   wel[w] = bad ? NAN : wt * En;
   ncopy[w] = nc;
   sc[SC_ELOC] = En;
+}
+
+// Rebuild of every record from its positions before a DMC call: clears the
+// invalid flag and marks both spins due for a refresh, so that the refresh
+// launches rebuild the inverses, tables and ratios from fresh rows.
+__global__ __launch_bounds__(256) void k_dmcb_prep(const DevWF* __restrict__ pwf, double* state,
+                                                   const double* ctrl) {
+  const DevWF& wf = *pwf;
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= (int64_t)ctrl[DC_W]) return;
+  double* sc = state + w * wf.rec_len + wf.r_sc;
+  sc[SC_FLAGS] = 0.0;
+  sc[SC_NUPD0] = wf.refresh_every;
+  sc[SC_NUPD1] = wf.refresh_every;
 }
 
 // ---------------------------------------------------------------------------
@@ -888,7 +913,7 @@ static hipError_t launch_rows_t(size_t lds, const DevWF* dwf_rows, const double*
   hipError_t e = rows_lds_attr((const void*)k_dmcb_rows<PREC, 0, kRowsNT>, lds, cur);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dmcb_rows<PREC, 0, kRowsNT>), dim3((unsigned)((cap + kGroup - 1) / kGroup)), dim3(kRowsNT),
-                     lds, s, dwf_rows, ctrl, P, Vp, nullptr, 0);
+                     lds, s, dwf_rows, ctrl, P, Vp, nullptr, 0, 0);
   return hipSuccess;
 }
 
@@ -925,20 +950,26 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
 
 // End of an electron-major step: refresh rows and inversions, E_L rows and
 // terms per electron, weights.  ek, ep [cap] are workspace.
+// With rebuild set (before the first step of a call), every record is
+// rebuilt from its positions: inverses, tables, ratios, the gradient-row cache
+// and E_L, and no weight is formed.
 hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
                               double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
                               double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
-                              hipStream_t s) {
+                              int rebuild, hipStream_t s) {
   const unsigned tiles = (unsigned)((cap + kGroup - 1) / kGroup);
   static size_t cur[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   auto rows = [&](auto kern, int prec, int mi, int i) -> hipError_t {
     hipError_t e = rows_lds_attr((const void*)kern, rows_lds, cur[prec][mi]);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kRowsNT), rows_lds, s, dwf_rows, ctrl, nullptr, Vp, state, i);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(kRowsNT), rows_lds, s, dwf_rows, ctrl, nullptr, Vp, state, i,
+                       rebuild);
     return hipSuccess;
   };
   hipError_t e = hipSuccess;
   const size_t lds_pe = (size_t)(320 + std::max(wf.sp[0].n * wf.sp[0].nP, wf.sp[1].n * wf.sp[1].nP)) * 8;
+  if (rebuild)
+    hipLaunchKernelGGL(k_dmcb_prep, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, dwf, state, ctrl);
   for (int i = 0; i < wf.N && e == hipSuccess; ++i) {
     switch (wf.precision) {
       case 0: e = rows(k_dmcb_rows<0, 1, kRowsNT>, 0, 0, i); break;
@@ -966,7 +997,7 @@ hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dw
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dmcb_weight, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, dwf, state, ctrl, seed,
-                     step, tau, ek, ep, wts, wel, ncopy);
+                     step, tau, ek, ep, wts, wel, ncopy, rebuild);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int
 hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
                               double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
                               double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
-                              hipStream_t s);
+                              int rebuild, hipStream_t s);
 hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds, double* state,
                             double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
                             double* V, double* Vp, double* nacc, hipStream_t s);
@@ -1177,11 +1177,6 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   if (e != hipSuccess) return hipfail(x, e, "dmc: control upload");
   double* cur = (double*)states[0];
   double* oth = (double*)states[1];
-  // rebuild every record from its positions (fresh inverses, local energy and
-  // the orbital-gradient rows the drift of the first moves reads)
-  e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, cur, s);
-  if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   // electron-major scratch (8-byte aligned after the integer arrays)
   char* pb = (char*)ws + ((dmc_ws_base(cap) + 255) & ~(size_t)255);
   double* Pw = (double*)pb;
@@ -1189,6 +1184,15 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   double* Vpw = Vw + 3 * cap;
   double* ekw = Vpw + 4 * (size_t)x->nop * cap;
   double* epw = ekw + cap;
+  // rebuild every record from its positions (fresh inverses, local energy and
+  // the orbital-gradient rows the drift of the first moves reads)
+  if (x->dmc_kernel == 2)
+    e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, (size_t)dmcb_layout(x).lds_tile_doubles * 8, cur, ctrl, cap,
+                           seed, 0, tau, Vpw, ekw, epw, wts, wel, ncopy, 1, s);
+  else
+    e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, cur, s);
+  if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
     if (x->dmc_kernel == 2) {
@@ -1198,7 +1202,7 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
                              Vpw, nacc, s);
       if (e == hipSuccess)
         e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, seed, step, tau, Vpw, ekw,
-                               epw, wts, wel, ncopy, s);
+                               epw, wts, wel, ncopy, 0, s);
     } else {
       e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
     }
