@@ -50,7 +50,7 @@ enum {
   VBQMC_EPOPULATION = -7 /* DMC population empty or above capacity */
 };
 
-enum { VBQMC_FP64 = 0, VBQMC_FP32 = 1, VBQMC_BF16 = 2 };
+enum { VBQMC_FP64 = 0, VBQMC_FP32 = 1, VBQMC_BF16 = 2, VBQMC_MIXED = 3 };
 
 /* Nuclei and electron counts (Sec. 2.1; Hamiltonian of Sec. 2.3.1). */
 typedef struct {
@@ -101,7 +101,14 @@ typedef struct {
 
 /* precision: VBQMC_FP64 (all FP64), VBQMC_FP32 or VBQMC_BF16 (basis values
  * and the basis->orbital contraction in that type with FP32 accumulation;
- * determinants, inverse refresh, determinant and structure sums in FP64).
+ * determinants, inverse refresh, determinant and structure sums in FP64),
+ * or VBQMC_MIXED: the orbital rows of trial points and DMC proposals in FP32
+ * (they decide acceptance and the drift only), while the reference inverse
+ * is rebuilt from FP64 rows before every local energy and the local-energy
+ * rows are FP64, so E_L is the FP64 value at the sampled configuration.
+ * VBQMC_MIXED applies to the row kernel (step_kernel 2), the wavefront
+ * sweep (16 or 32 lanes per walker) and electron-major DMC (dmc_kernel 2);
+ * every other path runs it in FP64.
  * refresh_every: accepted single-electron updates per spin after which the
  * reference inverse is rebuilt by a fresh factorisation (default 32).
  * walker_lanes: lanes of a 64-lane wavefront given to one walker in the

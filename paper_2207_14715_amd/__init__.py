@@ -14,8 +14,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvbqmc.so")
 
-FP64, FP32, BF16 = 0, 1, 2
-_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+FP64, FP32, BF16, MIXED = 0, 1, 2, 3
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "mixed": MIXED}
 _L_NFUNC = {0: 1, 1: 3, 2: 5}
 
 _ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EWORKSPACE", -4: "EHIP", -5: "ESINGULAR", -6: "ENONFINITE",

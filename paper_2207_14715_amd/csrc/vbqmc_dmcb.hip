@@ -302,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_dmcb_rows(const DevWF* __restrict__ pwf,
     bool need = false;  // walker threadIdx.x (< ne) refreshes spin s
     if (threadIdx.x < ne) {
       const double* sc = state + (w0 + threadIdx.x) * wf.rec_len + wf.r_sc;
-      need = sc[SC_FLAGS] == 0.0 && sc[SC_NUPD0 + s] >= wf.refresh_every;
+      need = sc[SC_FLAGS] == 0.0 && (wf.refresh_each_step || sc[SC_NUPD0 + s] >= wf.refresh_every);
     }
     if (!__syncthreads_or(need)) return;
   }
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_dmcb_rows(const DevWF* __restrict__ pwf,
         if (m < 0) continue;
         double* rec = state + (w0 + row) * wf.rec_len;
         const double* sc = rec + wf.r_sc;
-        if (!(sc[SC_FLAGS] == 0.0 && sc[SC_NUPD0 + s] >= wf.refresh_every)) continue;
+        if (!(sc[SC_FLAGS] == 0.0 && (wf.refresh_each_step || sc[SC_NUPD0 + s] >= wf.refresh_every))) continue;
         if (m < sp.n) rec[wf.r_B[s] + il * sp.n + m] = (double)acc[0][r];
         else rec[wf.r_bk + wf.r_T[s] - wf.r_R + il * sp.nP + (m - sp.n)] = (double)acc[0][r];
       } else {
@@ -639,7 +639,8 @@ __global__ __launch_bounds__(64) void k_dmcb_refresh(const DevWF* __restrict__ p
   double* sc = rec + wf.r_sc;
   if (sc[SC_FLAGS] != 0.0) return;
   bool need[2];
-  for (int s = 0; s < 2; ++s) need[s] = wf.sp[s].n > 0 && sc[SC_NUPD0 + s] >= wf.refresh_every;
+  for (int s = 0; s < 2; ++s)
+    need[s] = wf.sp[s].n > 0 && (wf.refresh_each_step || sc[SC_NUPD0 + s] >= wf.refresh_every);
   if (!need[0] && !need[1]) return;
   const int lane = threadIdx.x;
   const int nmax = max(wf.sp[0].n, wf.sp[1].n);
@@ -937,7 +938,7 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
   hipLaunchKernelGGL(k_dmcb_propose, dim3((unsigned)cap), dim3(64), lds_pe, s, dwf, state, ctrl, i, seed, step, tau,
                      P, V, nacc);
   hipError_t e;
-  switch (wf.precision) {
+  switch (wf.trial_prec) {  // proposal rows: the mixed form takes them in FP32
     case 0: e = launch_rows_t<0>(rows_lds, dwf_rows, ctrl, cap, P, Vp, s); break;
     case 1: e = launch_rows_t<1>(rows_lds, dwf_rows, ctrl, cap, P, Vp, s); break;
     default: e = launch_rows_t<2>(rows_lds, dwf_rows, ctrl, cap, P, Vp, s); break;

@@ -717,7 +717,12 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.N = x->N; wf.nup = x->nup; wf.ndn = x->ndn; wf.nnuc = x->nnuc; wf.nshell = x->nshell;
   wf.M = x->M; wf.Mpad = x->Mpad; wf.norb = x->norb; wf.nop = x->nop; wf.nstruct = x->nstruct;
   wf.precision = opt ? opt->precision : VBQMC_FP64;
-  if (wf.precision < 0 || wf.precision > 2) return bad("unknown precision");
+  if (wf.precision < 0 || wf.precision > 3) return bad("unknown precision");
+  // the mixed form: FP32 trial rows, everything else (including the rows of
+  // the local energy and of the per-step refresh) FP64
+  wf.trial_prec = wf.precision == VBQMC_MIXED ? VBQMC_FP32 : wf.precision;
+  wf.refresh_each_step = wf.precision == VBQMC_MIXED ? 1 : 0;
+  if (wf.precision == VBQMC_MIXED) wf.precision = VBQMC_FP64;
   wf.refresh_every = opt && opt->refresh_every > 0 ? opt->refresh_every : 32;
   wf.kappa = x->kappa;
   double vnn = 0;

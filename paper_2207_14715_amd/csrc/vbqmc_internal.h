@@ -38,6 +38,9 @@ struct SpinTab {
 struct DevWF {
   int N, nup, ndn, nnuc, nshell, M, Mpad, norb, nop, nstruct, nprim, nlinks;
   int precision, refresh_every;
+  // mixed form: trial / proposal rows in trial_prec (FP32), the reference
+  // inverse rebuilt from rows in `precision` before every local energy
+  int trial_prec, refresh_each_step;
   double kappa, vnn;
   double ee[8];
   const double* nuc;    // [nnuc][4]: x, y, z, Z

@@ -51,7 +51,8 @@ __device__ __forceinline__ void unrank_pair(int p, int& i, int& j) {
   j = p - a * (a - 1) / 2;
 }
 
-template <int PREC>
+// PT: precision of the trial rows; PE: of the refresh and local-energy rows
+template <int PT, int PE>
 __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, double* state, int64_t W,
                                                  int nsteps, uint64_t seed, uint64_t step0, double step_size,
                                                  double* e_sum, double* e2_sum, double* n_acc, double* e_last,
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
   const int nlive = (int)min((int64_t)kRowWalkers, W - wbase);
   const int N = wf.N, nn = wf.nnuc;
   Ld l(lds_dyn, wf);
-  stage_tables<64, PREC>(wf, l);
+  stage_tables<64, PE>(wf, l);
   Lg lg(lds_dyn, g, wf, q);
   double* sc = lg.sc();
   // records of the wavefront's walkers
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double* Rs = Rp + 3 * kRowWalkers * e0;
         for (int g0 = 0; g0 < kRowWalkers * n; g0 += kGroup) {
           const int ne = min(kGroup, kRowWalkers * n - g0);
-          group_radial<64, PREC, 1>(wf, l, Rs, g0, ne);
-          group_channel<64, PREC, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
+          group_radial<64, PT, 1>(wf, l, Rs, g0, ne);
+          group_channel<64, PT, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
         }
       }
       const int* ref = l.ref(s);
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       wave_sync();
     }
     // ---- inverse refresh of walkers that reached the update limit ----
-    const bool need = live && !bad && (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every);
+    const bool need = live && !bad && (wf.refresh_each_step || sc[SC_NUPD0] >= wf.refresh_every ||
+                                       sc[SC_NUPD1] >= wf.refresh_every);
     const unsigned long long lead = __ballot(need && q == 0);
     if (lead) {
       const int slot = __popcll(lead & ((1ull << (g * 16)) - 1ull));
@@ -357,8 +359,8 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       __syncthreads();
       for (int g0 = 0; g0 < nrows; g0 += kGroup) {
         const int ne = min(kGroup, nrows - g0);
-        group_radial<64, PREC, 1>(wf, l, Rr, g0, ne);
-        group_channel<64, PREC, 1>(wf, l, ne, 0, Vr + g0 * wf.nop, ne);
+        group_radial<64, PE, 1>(wf, l, Rr, g0, ne);
+        group_channel<64, PE, 1>(wf, l, ne, 0, Vr + g0 * wf.nop, ne);
       }
       if (need) {
         for (int s = 0; s < 2; ++s) {
@@ -398,8 +400,8 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       const int nrows = nlive * N;
       for (int g0 = 0; g0 < nrows; g0 += kGroup) {
         const int ne = min(kGroup, nrows - g0);
-        group_radial<64, PREC, 3>(wf, l, Rall, g0, ne);
-        group_channels4<64, PREC>(wf, l, ne, Phi4);
+        group_radial<64, PE, 3>(wf, l, Rall, g0, ne);
+        group_channels4<64, PE>(wf, l, ne, Phi4);
         const int t = lane >> 2, c = lane & 3;
         if (t < ne) {
           const int rr = g0 + t, g2 = div_small(rr, rN), i = rr - g2 * N;
@@ -530,20 +532,20 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
   }
 }
 
-template <int PREC>
+template <int PT, int PE>
 static hipError_t launch_vmc_rows_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps,
                                     uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s,
                                     double* na, double* el, double* sij, hipStream_t s) {
   const size_t lds = (size_t)wf.lds_rows_doubles * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_vmc_rows<PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_vmc_rows<PT, PE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        163840);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const unsigned blocks = (unsigned)((W + kRowWalkers - 1) / kRowWalkers);
-  hipLaunchKernelGGL((k_vmc_rows<PREC>), dim3(blocks), dim3(64), lds, s, dwf, state, W, nsteps, seed, step0,
+  hipLaunchKernelGGL((k_vmc_rows<PT, PE>), dim3(blocks), dim3(64), lds, s, dwf, state, W, nsteps, seed, step0,
                      step_size, es, e2s, na, el, sij);
   return hipGetLastError();
 }
@@ -552,10 +554,12 @@ static hipError_t launch_vmc_rows_t(const DevWF& wf, const DevWF* dwf, double* s
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s) {
+  if (wf.trial_prec != wf.precision)  // the mixed form
+    return launch_vmc_rows_t<1, 0>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
   switch (wf.precision) {
-    case 0: return launch_vmc_rows_t<0>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-    case 1: return launch_vmc_rows_t<1>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-    default: return launch_vmc_rows_t<2>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+    case 0: return launch_vmc_rows_t<0, 0>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+    case 1: return launch_vmc_rows_t<1, 1>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+    default: return launch_vmc_rows_t<2, 2>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
   }
 }
 

@@ -165,7 +165,8 @@ __device__ void accept_move_g(const DevWF& wf, const Lg& l, int i, double px, do
 }
 
 // one wavefront, NG = 64 / G walkers
-template <int G, int PREC>
+// PT: precision of the trial rows; PE: of the refresh rows
+template <int G, int PT, int PE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_g(
     const DevWF* __restrict__ pwf, double* state, int64_t W, uint64_t seed, uint32_t step, double step_size,
     double* n_acc) {
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const bool live = w < W;
   const int N = wf.N;
   Ld l(lds_dyn, wf);
-  stage_tables<64, PREC>(wf, l);
+  stage_tables<64, PE>(wf, l);
   Lg lg(lds_dyn, g, wf, q);
   // records of the wavefront's walkers, read by all 64 lanes
   for (int gg = 0; gg < NG; ++gg) {
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __syncthreads();
   for (int g0 = 0; g0 < NG * N; g0 += kGroup) {
     const int ne = min(kGroup, NG * N - g0);
-    group_radial<64, PREC, 1>(wf, l, Rp, g0, ne);
-    group_channel<64, PREC, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
+    group_radial<64, PT, 1>(wf, l, Rp, g0, ne);
+    group_channel<64, PT, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
   }
   double na = 0.0;
   if (live && !bad) {
@@ -244,7 +245,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   // refresh the walkers that reached the update limit: reference and table
   // rows at the current positions on MFMA (trial rows are dead here)
-  const bool need = live && !bad && (sc[SC_NUPD0] >= wf.refresh_every || sc[SC_NUPD1] >= wf.refresh_every);
+  const bool need = live && !bad && (wf.refresh_each_step || sc[SC_NUPD0] >= wf.refresh_every ||
+                                       sc[SC_NUPD1] >= wf.refresh_every);
   const unsigned long long lead = __ballot(need && q == 0);  // one bit per group that refreshes
   if (lead) {
     // rows of the refreshing walkers only, packed in group order
@@ -257,8 +259,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __syncthreads();
     for (int g0 = 0; g0 < nrows; g0 += kGroup) {
       const int ne = min(kGroup, nrows - g0);
-      group_radial<64, PREC, 1>(wf, l, Rp, g0, ne);
-      group_channel<64, PREC, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
+      group_radial<64, PE, 1>(wf, l, Rp, g0, ne);
+      group_channel<64, PE, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
     }
     if (need) {
       for (int s = 0; s < 2; ++s) {
@@ -309,38 +311,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (live && q == 0) n_acc[w] = na0 + na;
 }
 
-template <int G, int PREC>
+template <int G, int PT, int PE>
 static hipError_t launch_sweep_g_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, uint64_t seed,
                                    uint32_t step, double step_size, double* n_acc, hipStream_t s) {
   constexpr int NG = 64 / G;
   size_t lds = (size_t)wf.lds_sweepg_doubles * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sweep_g<G, PREC>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sweep_g<G, PT, PE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_sweep_g<G, PREC>), dim3((unsigned)((W + NG - 1) / NG)), dim3(64), lds, s, dwf, state, W,
+  hipLaunchKernelGGL((k_sweep_g<G, PT, PE>), dim3((unsigned)((W + NG - 1) / NG)), dim3(64), lds, s, dwf, state, W,
                      seed, step, step_size, n_acc);
   return hipSuccess;
 }
 
-// wavefront sweep with G lanes per walker (G = 16 or 32)
+// wavefront sweep with G lanes per walker (G = 16 or 32); the mixed form takes
+// the trial rows in FP32 and the refresh rows in FP64
+template <int G>
+static hipError_t launch_sweep_g_p(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, uint64_t seed,
+                                   uint32_t step, double step_size, double* n_acc, hipStream_t s) {
+  if (wf.trial_prec != wf.precision)
+    return launch_sweep_g_t<G, 1, 0>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
+  switch (wf.precision) {
+    case 0: return launch_sweep_g_t<G, 0, 0>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
+    case 1: return launch_sweep_g_t<G, 1, 1>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
+    default: return launch_sweep_g_t<G, 2, 2>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
+  }
+}
+
 hipError_t launch_sweep_g(const DevWF& wf, const DevWF* dwf, int G, double* state, int64_t W, uint64_t seed,
                           uint32_t step, double step_size, double* n_acc, hipStream_t s) {
-  if (G == 16) {
-    switch (wf.precision) {
-      case 0: return launch_sweep_g_t<16, 0>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-      case 1: return launch_sweep_g_t<16, 1>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-      default: return launch_sweep_g_t<16, 2>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-    }
-  }
-  switch (wf.precision) {
-    case 0: return launch_sweep_g_t<32, 0>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-    case 1: return launch_sweep_g_t<32, 1>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-    default: return launch_sweep_g_t<32, 2>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
-  }
+  if (G == 16) return launch_sweep_g_p<16>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
+  return launch_sweep_g_p<32>(wf, dwf, state, W, seed, step, step_size, n_acc, s);
 }
 
 }  // namespace vbqmc

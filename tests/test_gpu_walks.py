@@ -234,3 +234,52 @@ def test_dmc_f2_trajectory(lib, oracle_mod, kern):
     # keep the population within the capacity.
     ref, out, R = _dmc_pair(lib, oracle_mod, S.f2_shaped(), 45, 3, 0.002, dmc_kernel=kern, et_median=True)
     _check_dmc(ref, out, R)
+
+
+def _eloc_scale(ref):
+    return np.maximum(1.0, np.abs(ref["kin"]) + np.abs(ref["eloc"] - ref["kin"]))
+
+
+def test_vmc_mixed_form_eloc_is_fp64(lib, oracle_mod):
+    # the mixed form moves with FP32 trial rows but rebuilds the inverse from
+    # FP64 rows before every E_L: E_L after the last step equals the oracle's
+    # FP64 E_L at the walkers' final configurations (the per-walker bound of
+    # the precision form, here to 1e-10), and the walk itself agrees with the
+    # FP64 walk except where FP32 rounding flips an acceptance decision
+    import torch
+    sysd = S.f2_shaped()
+    W, steps, seed = 45, 6, 21
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=3)).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ctx = lib.Context(sysd, precision=prec, step_kernel=2)
+        print(f"[vmc mixed] f2 W={W} precision={prec}", flush=True)
+        st = ctx.walkers_init(R0)
+        acc = ctx.vmc_advance(st, steps, seed, 0, 0.3)
+        out[prec] = (ctx.positions(st).cpu().numpy(), acc["e_last"].cpu().numpy())
+    R, e = out["mixed"]
+    ref = oracle_mod.Oracle(sysd).evaluate(R)
+    assert np.max(np.abs(e - ref["eloc"]) / _eloc_scale(ref)) < 1e-10
+    same = np.all(np.abs(R - out["fp64"][0]) <= 1e-9 * (1 + np.abs(R)), axis=(1, 2))
+    assert same.mean() >= 0.9, f"{(~same).sum()} of {W} walks differ from FP64"
+
+
+def test_dmc_mixed_form_eloc_is_fp64(lib, oracle_mod):
+    # electron-major DMC in the mixed form: every surviving walker's E_L equals
+    # the oracle's FP64 E_L at its configuration
+    import torch
+    sysd = S.small_random_system(311, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
+    W = 64
+    o = oracle_mod.Oracle(sysd)
+    R0 = S.initial_walkers(sysd, W, seed=8)
+    et = float(np.mean(o.evaluate(R0)["eloc"]))
+    ctx = lib.Context(sysd, precision="mixed", dmc_kernel=2)
+    print(f"[dmc mixed] {sysd['name']} W={W}", flush=True)
+    st0, st1 = ctx.new_state(4 * W), ctx.new_state(4 * W)
+    ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
+    res = ctx.dmc_advance([st0, st1], W, 4, 77, 3, 0.005, et, W)
+    Wn = res["W"]
+    R = ctx.positions(st0, Wn).cpu().numpy()
+    e = ctx.record_eloc(st0, Wn).cpu().numpy()
+    ref = o.evaluate(R)
+    assert np.max(np.abs(e - ref["eloc"]) / _eloc_scale(ref)) < 1e-10
