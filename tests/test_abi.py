@@ -47,3 +47,31 @@ def test_host_weight_helpers_match_definitions():
     ev, U = np.linalg.eigh(Smat)
     cb = (U * np.sqrt(ev)) @ U.T @ c
     np.testing.assert_allclose(vb.weights_lowdin(Smat, c), cb ** 2 / (cb @ cb), rtol=1e-10)
+
+
+def _struct_fields(name):
+    """(type, field) pairs of a typedef struct of the header, in order."""
+    src = open(os.path.join(ROOT, "include", "vbqmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(int32_t|int64_t|double)\s+(.*)", decl)
+        assert m, decl
+        for f in m.group(2).split(","):
+            out.append((m.group(1), f.strip()))
+    return out
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of vbqmc_options and vbqmc_info_t list the header's
+    fields in the header's order with the same integer widths."""
+    import ctypes as ct
+    import paper_2207_14715_amd as vb
+    width = {"int32_t": ct.c_int32, "int64_t": ct.c_int64, "double": ct.c_double}
+    for cname, pycls in (("vbqmc_options", vb._Options), ("vbqmc_info_t", vb._Info)):
+        want = [(f, width[t]) for t, f in _struct_fields(cname)]
+        assert [(f, t) for f, t in pycls._fields_] == want, cname

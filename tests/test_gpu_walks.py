@@ -240,7 +240,8 @@ def _eloc_scale(ref):
     return np.maximum(1.0, np.abs(ref["kin"]) + np.abs(ref["eloc"] - ref["kin"]))
 
 
-def test_vmc_mixed_form_eloc_is_fp64(lib, oracle_mod):
+@pytest.mark.parametrize("kern", ["rows", 32])
+def test_vmc_mixed_form_eloc_is_fp64(lib, oracle_mod, kern):
     # the mixed form moves with FP32 trial rows but rebuilds the inverse from
     # FP64 rows before every E_L: E_L after the last step equals the oracle's
     # FP64 E_L at the walkers' final configurations (the per-walker bound of
@@ -252,8 +253,11 @@ def test_vmc_mixed_form_eloc_is_fp64(lib, oracle_mod):
     R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=3)).cuda()
     out = {}
     for prec in ("fp64", "mixed"):
-        ctx = lib.Context(sysd, precision=prec, step_kernel=2)
-        print(f"[vmc mixed] f2 W={W} precision={prec}", flush=True)
+        if kern == "rows":
+            ctx = lib.Context(sysd, precision=prec, step_kernel=2)
+        else:
+            ctx = lib.Context(sysd, precision=prec, walker_lanes=kern, step_kernel=1)
+        print(f"[vmc mixed] f2 W={W} precision={prec} kernel={kern}", flush=True)
         st = ctx.walkers_init(R0)
         acc = ctx.vmc_advance(st, steps, seed, 0, 0.3)
         out[prec] = (ctx.positions(st).cpu().numpy(), acc["e_last"].cpu().numpy())
