@@ -110,9 +110,27 @@ __device__ __forceinline__ double pair_val(double r, double kappa, const PairCoe
 // ---------------------------------------------------------------------------
 // basis functions: radial sums and the angular set
 // ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ T dexp(T x);
-template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
-template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+// e^{-t}, t >= 0, by Tang's table-driven method (ACM TOMS 15, 1989): with
+// n = rint(-64 t / ln 2) = 64 m + j (0 <= j < 64), e^{-t} = 2^m 2^{j/64} e^r
+// where r = -t - n ln2/64 (Cody-Waite, ln 2/64 in two parts) lies in
+// [-ln2/128, ln2/128]; 2^{j/64} comes from the staged 64-entry table and
+// e^r - 1 from its degree-5 Taylor polynomial (truncation below 4e-17
+// relative), about 1.3 ulp in all.  Arguments past the range of a 32-bit n
+// give 0 and NaN gives NaN; the table index always lies in 0..63.
+template <typename T> __device__ __forceinline__ T exp_neg(T t, const double* etab);
+template <> __device__ __forceinline__ double exp_neg<double>(double t, const double* etab) {
+  const double n = __builtin_rint(t * -92.33248261689366);  // -64 / ln 2
+  double r = __builtin_fma(-n, 0.010830424696249145, -t);  // ln 2 / 64, high part
+  r = __builtin_fma(-n, 3.623510646634843e-19, r);          // low part
+  const int k = (int)n;
+  const double T2 = etab[k & 63];
+  double q = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  q = __builtin_fma(q, r, 1.0 / 6.0);
+  q = __builtin_fma(q, r, 0.5);
+  q = __builtin_fma(q, r, 1.0);
+  return __builtin_ldexp(__builtin_fma(T2, q * r, T2), k >> 6);
+}
+template <> __device__ __forceinline__ float exp_neg<float>(float t, const double*) { return expf(-t); }
 
 // Radial sums of a shell: Gaussian (kind 0) g = sum c e^{-a r^2} with
 // g1 = dg/d(r^2), g2 = d2g/d(r^2)^2; Slater (kind 1) g = sum c e^{-a r} with
@@ -317,6 +335,73 @@ __device__ __forceinline__ int disp_stride(const DevWF& wf) { return 4 * wf.nnuc
 template <int GS>
 __device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.nshell) | 1; }
 
+// Radial sums of a row tile on one 64-lane block, from the staged radial
+// schedule: lane l takes electron l % 16 and bin l / 16 and walks the bin's
+// primitives two at a time in a loop of fixed length.  The two exponentials
+// of a step are independent (arguments past the cutoff are clamped and their
+// terms dropped afterwards), and the schedule entries and operands of the
+// next step are loaded while they are evaluated.  Each shell's sum is
+// accumulated in the order of its primitives and stored at its last one;
+// rows of electrons past ne get zeros.
+template <int PREC, int GS, bool STO>
+__device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne) {
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  const int e = threadIdx.x & 15;
+  const bool live = e < ne;
+  const T* de = (const T*)l.disp() + e * disp_stride(wf);
+  T* o = (T*)l.gtab() + e * gtab_stride<GS>(wf);
+  const uint2* sc = (const uint2*)(l.L + wf.l_rsched) + (threadIdx.x >> 4);
+  const double* pe = l.pe();
+  const double* pc = l.pc();
+  const double* etab = l.L + wf.l_etab;
+  uint2 n0 = sc[0], n1 = sc[4], m0 = sc[8], m1 = sc[12];
+  double a0 = pe[n0.x & kRsPrim], c0 = pc[n0.x & kRsPrim];
+  double a1 = pe[n1.x & kRsPrim], c1 = pc[n1.x & kRsPrim];
+  T d0 = de[4 * (n0.y >> 16) + 3], d1 = de[4 * (n1.y >> 16) + 3];
+  T g = 0, g1 = 0, g2 = 0;
+  auto add = [&](T ex, T a, unsigned f, unsigned sh) {
+    g += ex;
+    if constexpr (GS == 3) {
+      g1 -= a * ex;
+      g2 += a * a * ex;
+    }
+    if (f & kRsLast) {
+      T* q = o + GS * sh;
+      q[0] = live ? g : T(0);
+      if constexpr (GS == 3) {
+        q[1] = live ? g1 : T(0);
+        q[2] = live ? g2 : T(0);
+      }
+      g = 0;
+      g1 = 0;
+      g2 = 0;
+    }
+  };
+  for (int j = 0; j < wf.rsched_len; j += 2) {
+    const unsigned f0 = n0.x, f1 = n1.x, h0 = n0.y & 0xFFFFu, h1 = n1.y & 0xFFFFu;
+    const T A0 = (T)a0, C0 = (T)c0, R0 = d0, A1 = (T)a1, C1 = (T)c1, R1 = d1;
+    n0 = m0;
+    n1 = m1;
+    m0 = sc[4 * (j + 4)];
+    m1 = sc[4 * (j + 5)];
+    a0 = pe[n0.x & kRsPrim];
+    c0 = pc[n0.x & kRsPrim];
+    a1 = pe[n1.x & kRsPrim];
+    c1 = pc[n1.x & kRsPrim];
+    d0 = de[4 * (n0.y >> 16) + 3];
+    d1 = de[4 * (n1.y >> 16) + 3];
+    T t0 = A0 * R0, t1 = A1 * R1;
+    if constexpr (STO) {
+      if (f0 & kRsSto) t0 = A0 * (T)sqrt(R0);
+      if (f1 & kRsSto) t1 = A1 * (T)sqrt(R1);
+    }
+    const T x0 = C0 * exp_neg<T>(fmin(t0, T(64)), etab);
+    const T x1 = C1 * exp_neg<T>(fmin(t1, T(64)), etab);
+    add(((f0 & kRsLive) && t0 < T(50)) ? x0 : T(0), A0, f0, h0);
+    add(((f1 & kRsLive) && t1 < T(50)) ? x1 : T(0), A1, f1, h1);
+  }
+}
+
 template <int NT, int PREC, int GS = 3>
 __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, int g0, int ne) {
   typedef typename std::conditional<PREC == 0, double, float>::type T;
@@ -336,6 +421,14 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
     d[3] = x * x + y * y + z * z;
   }
   __syncthreads();
+  if constexpr (NT == 64) {
+    if (wf.rsched_len > 0 && wf.l_rsched < wf.timg_len) {
+      if (wf.rsched_sto) radial_bins<PREC, GS, true>(wf, l, ne);
+      else radial_bins<PREC, GS, false>(wf, l, ne);
+      __syncthreads();
+      return;
+    }
+  }
   for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
     int e = idx / wf.nshell, sh = idx - e * wf.nshell;
     const int* si = l.sh() + 8 * sh;
@@ -347,7 +440,7 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
         T a = (T)l.pe()[si[4] + k];
         T t = si[1] == 0 ? a * r2 : a * r;
         if (t < T(50)) {
-          T ex = (T)l.pc()[si[4] + k] * dexp<T>(-t);
+          T ex = (T)l.pc()[si[4] + k] * exp_neg<T>(t, l.L + wf.l_etab);
           g += ex;
           if constexpr (GS == 3) {
             g1 -= a * ex;
@@ -432,12 +525,18 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
     if constexpr (PREC == 0) {
       const double* lam = l.lam<double>();
       v4d acc = {0, 0, 0, 0};
-#pragma unroll 4
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        int k = k0 + (lane >> 4);
-        double a = live ? chan_value<double, GS>(wf, l, e, k, c) : 0.0;
-        double b = lam[(size_t)k * wf.nop + col];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      // Mpad is a multiple of 16: four k-steps per pass, their table lookups
+      // and coefficient loads issued before the MFMAs (same accumulation order)
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          a[u] = live ? chan_value<double, GS>(wf, l, e, k, c) : 0.0;
+          b[u] = lam[(size_t)k * wf.nop + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
       }
       // f64 16x16x4 output: register r of lane l holds row 4r + l/16
 #pragma unroll
@@ -446,12 +545,16 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
     } else if constexpr (PREC == 1) {
       const float* lam = l.lam<float>();
       v4f acc = {0, 0, 0, 0};
-#pragma unroll 4
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        int k = k0 + (lane >> 4);
-        float a = live ? chan_value<float, GS>(wf, l, e, k, c) : 0.f;
-        float b = lam[(size_t)k * wf.nop + col];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        float a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          a[u] = live ? chan_value<float, GS>(wf, l, e, k, c) : 0.f;
+          b[u] = lam[(size_t)k * wf.nop + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
       }
       // f32 output: register r of lane l holds row 4(l/16) + r
 #pragma unroll
@@ -544,14 +647,19 @@ __device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* ou
       v4d acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
-#pragma unroll 2
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        int k = k0 + (lane >> 4);
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        if (live) chan_value4<double>(wf, l, e, k, a);
-        double b = lam[(size_t)k * wf.nop + col];
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        double a[4][4], b[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], b, acc[c], 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
+          if (live) chan_value4<double>(wf, l, e, k, a[u]);
+          b[u] = lam[(size_t)k * wf.nop + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][c], b[u], acc[c], 0, 0, 0);
       }
       // f64 16x16x4 output: register r of lane l holds row 4r + l/16
 #pragma unroll
@@ -564,14 +672,19 @@ __device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* ou
       v4f acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = v4f{0, 0, 0, 0};
-#pragma unroll 2
-      for (int k0 = 0; k0 < wf.Mpad; k0 += 4) {
-        int k = k0 + (lane >> 4);
-        float a[4] = {0.f, 0.f, 0.f, 0.f};
-        if (live) chan_value4<float>(wf, l, e, k, a);
-        float b = lam[(size_t)k * wf.nop + col];
+      for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+        float a[4][4], b[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b, acc[c], 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.f;
+          if (live) chan_value4<float>(wf, l, e, k, a[u]);
+          b[u] = lam[(size_t)k * wf.nop + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c], b[u], acc[c], 0, 0, 0);
       }
       // f32 output: register r of lane l holds row 4(l/16) + r
 #pragma unroll
@@ -963,7 +1076,7 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
     T r2 = x * x + y * y + z * z;
     T al = (T)l.pe()[q];
     T t = si[1] == 0 ? al * r2 : al * sqrt(r2);
-    T ex = t < T(50) ? (T)l.pc()[q] * dexp<T>(-t) : T(0);
+    T ex = t < T(50) ? (T)l.pc()[q] * exp_neg<T>(t, l.L + wf.l_etab) : T(0);
     pt[2 * q] = ex;
     pt[2 * q + 1] = -al * ex;
   }

@@ -130,6 +130,8 @@ struct vbqmc_ctx {
   int N = 0, nup = 0, ndn = 0, nnuc = 0, M = 0, Mpad = 0, norb = 0, nop = 0, nstruct = 0, nshell = 0;
   std::vector<double> nuc, en, pexp, pcoef, lam, c;
   std::vector<int> shtab, fnmap, pshell;
+  std::vector<unsigned> rsched;  // radial schedule of 64-lane blocks, [rows + 2][4][2]
+  int rsched_len = 0;
   double ee[8];
   double kappa = 0;
   SpinHost sp[2];
@@ -221,6 +223,54 @@ struct LdsAlloc {
   int operator()(int n) { int r = o; o += (std::max(n, 1) + 1) / 2 * 2; return r; }
   int ints(int n) { return (*this)((n + 1) / 2); }
 };
+
+// Radial schedule of the 64-lane blocks.  Lane l takes electron l % 16 of a
+// row tile and bin l / 16; the shells are dealt to the four bins longest
+// first, each to the bin with the fewest primitives so far, so every lane
+// walks about a quarter of the primitives in one fixed-length loop.  A bin
+// lists its shells' primitives in shell order (the order of the contraction
+// sums), flags the last primitive of each shell, and is padded with empty
+// entries to the longest bin rounded up to even, plus four rows read ahead.
+void build_radial_schedule(vbqmc_ctx* x) {
+  x->rsched.clear();
+  x->rsched_len = 0;
+  const int nprim = (int)x->pexp.size();
+  if (nprim >= (int)kRsPrim || x->nshell > 0xFFFF || x->nnuc > 0xFFFF) return;
+  std::vector<int> order(x->nshell);
+  for (int s = 0; s < x->nshell; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return x->shtab[8 * a + 5] > x->shtab[8 * b + 5]; });
+  std::vector<int> bins[4];
+  int load[4] = {0, 0, 0, 0};
+  for (int s : order) {
+    int b = 0;
+    for (int k = 1; k < 4; ++k)
+      if (load[k] < load[b]) b = k;
+    bins[b].push_back(s);
+    load[b] += x->shtab[8 * s + 5];
+  }
+  int L = 0;
+  for (int b = 0; b < 4; ++b) {
+    std::sort(bins[b].begin(), bins[b].end());
+    L = std::max(L, load[b]);
+  }
+  L += L & 1;  // walked two entries at a time, with two steps loaded ahead
+  x->rsched.assign((size_t)8 * (L + 4), 0u);
+  for (int b = 0; b < 4; ++b) {
+    int j = 0;
+    for (int s : bins[b]) {
+      const int* si = &x->shtab[8 * s];
+      for (int k = 0; k < si[5]; ++k, ++j) {
+        unsigned f = (unsigned)(si[4] + k) | kRsLive;
+        if (si[1] == 1) f |= kRsSto;
+        if (k == si[5] - 1) f |= kRsLast;
+        x->rsched[(size_t)2 * (4 * j + b)] = f;
+        x->rsched[(size_t)2 * (4 * j + b) + 1] = (unsigned)s | ((unsigned)si[0] << 16);
+      }
+    }
+  }
+  x->rsched_len = L;
+}
 
 // Sweep kernel: the tables without the orbital coefficients (read from global
 // memory there), the walker state, value-only tile tables and the trial
@@ -455,6 +505,10 @@ int upload_table_image(vbqmc_ctx* x) {
   put(wf.l_pe, x->pexp.data(), x->pexp.size() * 8);
   put(wf.l_pc, x->pcoef.data(), x->pcoef.size() * 8);
   put(wf.l_psh, x->pshell.data(), x->pshell.size() * 4);
+  put(wf.l_rsched, x->rsched.data(), x->rsched.size() * 4);
+  double etab[64];
+  for (int j = 0; j < 64; ++j) etab[j] = (double)exp2l((long double)j / 64.0L);
+  put(wf.l_etab, etab, sizeof(etab));
   put(wf.l_nuc, x->nuc.data(), x->nuc.size() * 8);
   put(wf.l_en, x->en.data(), x->en.size() * 8);
   std::vector<double> wc[2], slc;
@@ -573,6 +627,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   }
   x->M = fn;
   if (x->M < 1 || x->M > 1024) return bad("basis size outside 1..1024");
+  build_radial_schedule(x);
   x->Mpad = (x->M + kChunk - 1) / kChunk * kChunk;
   for (int mu = x->M; mu < x->Mpad; ++mu) x->fnmap.insert(x->fnmap.end(), {-1, 0});
   x->norb = wfi->n_orbitals;
@@ -767,6 +822,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_sh = ilds(8 * x->nshell);
   wf.l_pe = lds(wf.nprim);
   wf.l_pc = lds(wf.nprim);
+  wf.l_etab = lds(64);
   wf.l_psh = ilds(wf.nprim);
   wf.l_nuc = lds(4 * x->nnuc);
   wf.l_en = lds(6 * x->nnuc);
@@ -782,6 +838,10 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_srow = ilds((int)x->srow.size());
   wf.l_slu = ilds((int)x->slu.size());
   wf.l_slc = lds((int)x->slc.size());
+  wf.rsched_len = x->rsched_len;
+  wf.rsched_sto = 0;
+  for (int s = 0; s < x->nshell; ++s) wf.rsched_sto |= x->shtab[8 * s + 1] == 1;
+  wf.l_rsched = ilds((int)x->rsched.size());
   int lam_elems = x->Mpad * x->nop;
   int lam_doubles = wf.precision == 0 ? lam_elems : (wf.precision == 1 ? (lam_elems + 1) / 2 : (lam_elems + 3) / 4);
   // orbital coefficients go to LDS when they take at most 16 KiB

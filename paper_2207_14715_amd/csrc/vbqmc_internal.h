@@ -8,6 +8,9 @@
 namespace vbqmc {
 
 constexpr int kGroup = 16;     // electrons per MFMA row tile
+// radial schedule entry flags (first int of an entry; the primitive index
+// takes the low 24 bits)
+constexpr unsigned kRsPrim = 0x00FFFFFFu, kRsSto = 1u << 24, kRsLast = 1u << 25, kRsLive = 1u << 26;
 constexpr int kChunk = 16;     // basis functions are padded to a multiple of this
 constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
 constexpr int kMaxSpin = 64;   // electrons per spin
@@ -67,6 +70,11 @@ struct DevWF {
   int lam_in_lds;
   int l_fn, l_sh, l_pe, l_pc, l_psh, l_nuc, l_en, l_lam;
   int l_ref[2], l_porb[2], l_ui[2], l_wrow[2], l_woth[2], l_wcoef[2], l_srow, l_slu, l_slc;
+  // radial schedule of a 64-lane block: the shells dealt to four bins, entry j
+  // of bin b at [j][b] (two ints: primitive | flags, shell | nucleus << 16);
+  // rsched_len rows (even) plus four padding rows, none when rsched_len is 0
+  int l_rsched, rsched_len, rsched_sto;
+  int l_etab;  // 2^(j/64), j = 0..63, for the exponentials of the radial sums
   // walker state and scratch
   int l_R, l_B[2], l_T[2], l_PP[2];
   int l_Ru[2], l_Wu[2], l_Qu, l_sc, l_red, l_ipiv, l_f;

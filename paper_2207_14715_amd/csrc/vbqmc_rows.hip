@@ -30,11 +30,9 @@ namespace vbqmc {
 constexpr int kRowMaxRounds = 18;  // pair tasks per lane: 4 walkers x N (N - 1) / 2 pairs over 64 lanes
 
 // row of (walker g, electron i) in the trial tables: spins are blocked, then
-// walkers, then the spin's electrons
-__device__ __forceinline__ int trial_row(const DevWF& wf, int g, int i) {
-  const int s = spin_of(wf, i);
-  const SpinTab& sp = wf.sp[s];
-  return kRowWalkers * sp.e0 + g * sp.n + (i - sp.e0);
+// walkers, then the spin's electrons (spin 0 holds electrons 0..nup-1)
+__device__ __forceinline__ int trial_row(int nup, int ndn, int g, int i) {
+  return i < nup ? g * nup + i : kRowWalkers * nup + g * ndn + (i - nup);
 }
 
 __device__ __forceinline__ double dist3(const double* a, const double* b) {
@@ -63,7 +61,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
   const int64_t w = wbase + g;
   const bool live = w < W;
   const int nlive = (int)min((int64_t)kRowWalkers, W - wbase);
-  const int N = wf.N, nn = wf.nnuc;
+  const int N = wf.N, nn = wf.nnuc, Nup = wf.nup, Ndn = wf.ndn;
   Ld l(lds_dyn, wf);
   stage_tables<64, PE>(wf, l);
   Lg lg(lds_dyn, g, wf, q);
@@ -116,7 +114,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
           py = R[3 * i + 1] + step_size * (2.0 * a1 - 1.0);
           pz = R[3 * i + 2] + step_size * (2.0 * b0 - 1.0);
         }
-        const int r = trial_row(wf, g, i);
+        const int r = trial_row(Nup, Ndn, g, i);
         Rp[3 * r] = px; Rp[3 * r + 1] = py; Rp[3 * r + 2] = pz;
         ua[r] = u;
       }
@@ -138,9 +136,9 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double* R2 = lds_dyn + wf.gw_base + g2 * wf.gw_stride + wf.l_R;
         const double* ri = R2 + 3 * i;
         const double* rj = R2 + 3 * j;
-        const double* pi = Rp + 3 * trial_row(wf, g2, i);
-        const double* pj = Rp + 3 * trial_row(wf, g2, j);
-        const PairCoef c = spin_of(wf, i) != spin_of(wf, j) ? c_anti : c_par;
+        const double* pi = Rp + 3 * trial_row(Nup, Ndn, g2, i);
+        const double* pj = Rp + 3 * trial_row(Nup, Ndn, g2, j);
+        const PairCoef c = (i < Nup ? 0 : 1) != (j < Nup ? 0 : 1) ? c_anti : c_par;
         const double o = pair_val(dist3(ri, rj), kappa, c);
         const double aij = pair_val(dist3(pi, rj), kappa, c);
         const double aji = pair_val(dist3(pj, ri), kappa, c);
@@ -162,7 +160,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       for (int k = 0; k < 2; ++k) {
         const int i = q + 16 * k;
         if (i < N && live) {
-          const double* pi = Rp + 3 * trial_row(wf, g, i);
+          const double* pi = Rp + 3 * trial_row(Nup, Ndn, g, i);
           double a = 0.0;
           for (int b = 0; b < nn; ++b) {
             const PairCoef c = en_coef(l.en() + 6 * b);
@@ -239,17 +237,31 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       int ex = 0;
       double* xch = lg.S + wf.l_xch;  // [0, 16): old column il of B; [16, 32): y
       const double* X = Xj + g * N * N;
+      // Every load of a move is issued unconditionally (padding slots read
+      // index 0 and meet zero coefficients), so that the loads of a step are
+      // in flight together; the exponential of the Jastrow change, the
+      // acceptance draw and the Jastrow table entries do not depend on the
+      // determinant ratio and are started first.
       for (int il = 0; il < n; ++il) {
         const int i = e0 + il;
         const double* Vrow = Vn + (g * n + il) * wf.nop;
+        const int r = kRowWalkers * e0 + g * n + il;  // trial row of (walker g, electron i)
+        const double u_r = ua[r];
+        const double xr0 = X[min(q, N - 1) * N + i];
+        const double xr1 = X[min(q + 16, N - 1) * N + i];
+        double vr[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) vr[j] = Vrow[refj[j]];
+        const double vo = Vrow[own >= 0 ? own : 0];
+        const double eU = exp(row_bcast(i < 16 ? run0 : run1, i & 15));
         double t0 = 0.0, t1 = 0.0;
 #pragma unroll
         for (int j = 0; j < 16; j += 2) {
-          if (j < n) t0 += Vrow[refj[j]] * C[j];
-          if (j + 1 < n) t1 += Vrow[refj[j + 1]] * C[j + 1];
+          t0 += vr[j] * C[j];
+          t1 += vr[j + 1] * C[j + 1];
         }
         const double t = t0 + t1;
-        const double y = (own >= 0 ? Vrow[own] : 0.0) - t;
+        const double y = (own >= 0 ? vo : 0.0) - t;
         const double rho = row_bcast(t, il);
         if (q == il) {
 #pragma unroll
@@ -260,27 +272,28 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         wave_sync();
         double bc[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) bc[j] = j < n ? xch[j] : 0.0;
-        double yy[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0}, part = 0.0;
+        for (int j = 0; j < 16; ++j) bc[j] = xch[j];
+        double yy[3], bb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          yy[a] = xch[16 + Qx[a]];
+          bb[a] = xch[Ju[a]];
+        }
+        const double ir = 1.0 / rho;
+        double part = 0.0;
         if (q < nU) {
 #pragma unroll
           for (int a = 0; a < 3; ++a)
-            if (a < eu) {
-              yy[a] = xch[16 + Qx[a]];
-              bb[a] = xch[Ju[a]];
-            }
+            if (a >= eu) yy[a] = bb[a] = 0.0;
           part = (rho * Ru + adj_e(eu, m, yy, bb)) * Wu;
         }
         const double Snew = gsum<16>(part);
-        const double dU = row_bcast(i < 16 ? run0 : run1, i & 15);
-        const int r = trial_row(wf, g, i);
-        const double ratio = Snew / S * exp(dU);
-        const bool accept = live && !bad && ua[r] < ratio * ratio;
+        const double ratio = Snew / S * eU;
+        const bool accept = live && !bad && u_r < ratio * ratio;
         if (accept) {
           // later electrons see electron i at its new point
-          if (q > i && q < N) run0 += X[q * N + i];
-          if (q + 16 > i && q + 16 < N) run1 += X[(q + 16) * N + i];
-          const double ir = 1.0 / rho;
+          if (q > i && q < N) run0 += xr0;
+          if (q + 16 > i && q + 16 < N) run1 += xr1;
           double f = 0.0;
           if (q < n) f = -(t - (q == il ? 1.0 : 0.0)) * ir;
           else if (own >= 0) f = y * ir;
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         if (t < ne) {
           const int rr = g0 + t, g2 = div_small(rr, rN), i = rr - g2 * N;
           const double* S2 = lds_dyn + wf.gw_base + g2 * wf.gw_stride;
-          const int s = spin_of(wf, i);
+          const int s = (i < Nup ? 0 : 1);
           double tot = 0.0;
           if (S2[wf.l_sc + SC_FLAGS] == 0.0)
             tot = row_op_sum_p(wf, l, s, Phi4 + (c * kGroup + t) * wf.nop, yb + lane * (nPm + 1), S2 + wf.l_B[s],
@@ -427,14 +440,14 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         double gx = 0.0, gy = 0.0, gz = 0.0, lap = 0.0, V = 0.0;
         if (i < N && live) {
           const double xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
-          const int si = spin_of(wf, i);
+          const int si = (i < Nup ? 0 : 1);
           for (int j = p; j < N + nn; j += 4) {
             if (j == i) continue;
             double xj, yj, zj, wv;
             PairCoef cf;
             if (j < N) {
               xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
-              cf = si != spin_of(wf, j) ? c_anti : c_par;
+              cf = si != (j < Nup ? 0 : 1) ? c_anti : c_par;
               wv = 0.5;
             } else {
               const int a = j - N;
