@@ -30,8 +30,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 TRAFFIC_BYTES_PER_LAUNCH = None
 TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
-# launch): FETCH_SIZE 8095 KiB x 2.000 + WRITE_SIZE 17035 KiB x 1.000
-TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (8095.1 * 2.0 + 17035.6) * 1024}
+# launch): FETCH_SIZE 5566 KiB x 2.000 + WRITE_SIZE 10136 KiB x 1.000
+TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5565.9 * 2.0 + 10135.7) * 1024}
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
@@ -234,7 +234,8 @@ def main():
     prec_tag = {"fp64": 0, "fp32": 1, "bf16": 2, "mixed": 0}[args.precision]
     if rows:
         # the dominant (and only) kernel makes moves and E_L of every step
-        kernel = "k_vmc_rows<1, 0>" if args.precision == "mixed" else f"k_vmc_rows<{prec_tag}, {prec_tag}>"
+        ne = 10 if max(ctx.info["n_up"], ctx.info["n_dn"]) <= 10 else 16  # register columns per lane
+        kernel = f"k_vmc_rows<1, 0, {ne}>" if args.precision == "mixed" else f"k_vmc_rows<{prec_tag}, {prec_tag}, {ne}>"
         flops_launch = (sweep_flops + measure_flops) * steps_launch
         traffic = TRAFFIC_ROWS["bytes"] if (W == TRAFFIC_ROWS["walkers"] and args.precision == "fp64" and
                                             steps_launch == TRAFFIC_ROWS["steps_per_launch"]) else None

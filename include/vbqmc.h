@@ -110,7 +110,9 @@ typedef struct {
  * sweep (16 or 32 lanes per walker) and electron-major DMC (dmc_kernel 2);
  * every other path runs it in FP64.
  * refresh_every: accepted single-electron updates per spin after which the
- * reference inverse is rebuilt by a fresh factorisation (default 32).
+ * reference inverse is rebuilt by a fresh factorisation (default 32).  The
+ * row step kernel rebuilds the four walkers of a wavefront together as soon
+ * as one of them has reached the limit.
  * walker_lanes: lanes of a 64-lane wavefront given to one walker in the
  * single-electron VMC sweep: 16 or 32 (several walkers per wavefront, if
  * their state fits in LDS), 64 (one walker per workgroup), or 0 to let the

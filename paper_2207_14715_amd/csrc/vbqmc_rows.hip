@@ -50,7 +50,7 @@ __device__ __forceinline__ void unrank_pair(int p, int& i, int& j) {
 }
 
 // PT: precision of the trial rows; PE: of the refresh and local-energy rows
-template <int PT, int PE>
+template <int PT, int PE, int NE>
 __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, double* state, int64_t W,
                                                  int nsteps, uint64_t seed, uint64_t step0, double step_size,
                                                  double* e_sum, double* e2_sum, double* n_acc, double* e_last,
@@ -200,16 +200,16 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         }
       }
       const int* ref = l.ref(s);
-      int refj[16];
+      int refj[NE];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) refj[j] = j < n ? ref[j] : 0;
+      for (int j = 0; j < NE; ++j) refj[j] = j < n ? ref[j] : 0;
       const int own = (q >= n && q < n + nP) ? l.porb(s)[q - n] : -1;
-      double C[16];
+      double C[NE];
       {
         const double* B = lg.B(s);
         const double* T = lg.T(s);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < NE; ++j) {
           double v = 0.0;
           if (j < n) {
             if (q < n) v = B[j * n + q];
@@ -249,14 +249,14 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double u_r = ua[r];
         const double xr0 = X[min(q, N - 1) * N + i];
         const double xr1 = X[min(q + 16, N - 1) * N + i];
-        double vr[16];
+        double vr[NE];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) vr[j] = Vrow[refj[j]];
+        for (int j = 0; j < NE; ++j) vr[j] = Vrow[refj[j]];
         const double vo = Vrow[own >= 0 ? own : 0];
         const double eU = exp(row_bcast(i < 16 ? run0 : run1, i & 15));
         double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-        for (int j = 0; j < 16; j += 2) {
+        for (int j = 0; j < NE; j += 2) {
           t0 += vr[j] * C[j];
           t1 += vr[j + 1] * C[j + 1];
         }
@@ -265,14 +265,14 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double rho = row_bcast(t, il);
         if (q == il) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
+          for (int j = 0; j < NE; ++j)
             if (j < n) xch[j] = C[j];
         }
         if (own >= 0) xch[16 + (q - n)] = y;
         wave_sync();
-        double bc[16];
+        double bc[NE];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) bc[j] = xch[j];
+        for (int j = 0; j < NE; ++j) bc[j] = xch[j];
         double yy[3], bb[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
           if (q < n) f = -(t - (q == il ? 1.0 : 0.0)) * ir;
           else if (own >= 0) f = y * ir;
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
+          for (int j = 0; j < NE; ++j)
             if (j < n) C[j] += bc[j] * f;
           double pr = 0.0;
           if (q < nU) {
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         double* B = lg.B(s);
         double* T = lg.T(s);
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < NE; ++j)
           if (j < n) {
             if (q < n) B[j * n + q] = C[j];
             else if (own >= 0) T[j * nP + (q - n)] = C[j];
@@ -355,9 +355,14 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       }
       wave_sync();
     }
-    // ---- inverse refresh of walkers that reached the update limit ----
-    const bool need = live && !bad && (wf.refresh_each_step || sc[SC_NUPD0] >= wf.refresh_every ||
-                                       sc[SC_NUPD1] >= wf.refresh_every);
+    // ---- inverse refresh ----
+    // Once one walker of the wavefront has reached the update limit, every
+    // walker of the wavefront is rebuilt: the row tiles of the refresh are then
+    // full (4N rows instead of N), and an earlier rebuild only makes an inverse
+    // fresher.
+    const bool due = live && !bad && (wf.refresh_each_step || sc[SC_NUPD0] >= wf.refresh_every ||
+                                      sc[SC_NUPD1] >= wf.refresh_every);
+    const bool need = live && !bad && __ballot(due) != 0;
     const unsigned long long lead = __ballot(need && q == 0);
     if (lead) {
       const int slot = __popcll(lead & ((1ull << (g * 16)) - 1ull));
@@ -545,35 +550,45 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
   }
 }
 
-template <int PT, int PE>
+template <int PT, int PE, int NE>
 static hipError_t launch_vmc_rows_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps,
                                     uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s,
                                     double* na, double* el, double* sij, hipStream_t s) {
   const size_t lds = (size_t)wf.lds_rows_doubles * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_vmc_rows<PT, PE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_vmc_rows<PT, PE, NE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        163840);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const unsigned blocks = (unsigned)((W + kRowWalkers - 1) / kRowWalkers);
-  hipLaunchKernelGGL((k_vmc_rows<PT, PE>), dim3(blocks), dim3(64), lds, s, dwf, state, W, nsteps, seed, step0,
+  hipLaunchKernelGGL((k_vmc_rows<PT, PE, NE>), dim3(blocks), dim3(64), lds, s, dwf, state, W, nsteps, seed, step0,
                      step_size, es, e2s, na, el, sij);
   return hipGetLastError();
 }
 
-// single-electron VMC steps with the row kernel (one launch for all steps)
+// single-electron VMC steps with the row kernel (one launch for all steps);
+// NE: register columns per lane, 10 when no spin has more than 10 electrons
+template <int NE>
+static hipError_t launch_vmc_rows_n(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps,
+                                    uint64_t seed, uint64_t step0, double step_size, double* es, double* e2s,
+                                    double* na, double* el, double* sij, hipStream_t s) {
+  if (wf.trial_prec != wf.precision)  // the mixed form
+    return launch_vmc_rows_t<1, 0, NE>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+  switch (wf.precision) {
+    case 0: return launch_vmc_rows_t<0, 0, NE>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+    case 1: return launch_vmc_rows_t<1, 1, NE>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+    default: return launch_vmc_rows_t<2, 2, NE>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+  }
+}
+
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s) {
-  if (wf.trial_prec != wf.precision)  // the mixed form
-    return launch_vmc_rows_t<1, 0>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-  switch (wf.precision) {
-    case 0: return launch_vmc_rows_t<0, 0>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-    case 1: return launch_vmc_rows_t<1, 1>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-    default: return launch_vmc_rows_t<2, 2>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
-  }
+  if (wf.nup <= 10 && wf.ndn <= 10)
+    return launch_vmc_rows_n<10>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
+  return launch_vmc_rows_n<16>(wf, dwf, state, W, nsteps, seed, step0, step_size, es, e2s, na, el, sij, s);
 }
 
 }  // namespace vbqmc
