@@ -345,6 +345,9 @@ __device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.ns
 // rows of electrons past ne get zeros.
 template <int PREC, int GS, bool STO>
 __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne) {
+  // each term is rounded before it is added, in every kernel: the value rows
+  // of an inverse refresh and of the local energy then agree bit for bit
+#pragma clang fp contract(off)
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   const int e = threadIdx.x & 15;
   const bool live = e < ne;
@@ -429,31 +432,34 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
       return;
     }
   }
-  for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
-    int e = idx / wf.nshell, sh = idx - e * wf.nshell;
-    const int* si = l.sh() + 8 * sh;
-    T r2 = disp[e * ds + 4 * si[0] + 3], r = sqrt(r2);
-    T g = 0, g1 = 0, g2 = 0;
-    if (e < ne) {
+  {
+#pragma clang fp contract(off)
+    for (int idx = threadIdx.x; idx < kGroup * wf.nshell; idx += NT) {
+      int e = idx / wf.nshell, sh = idx - e * wf.nshell;
+      const int* si = l.sh() + 8 * sh;
+      T r2 = disp[e * ds + 4 * si[0] + 3], r = sqrt(r2);
+      T g = 0, g1 = 0, g2 = 0;
+      if (e < ne) {
 #pragma unroll 2
-      for (int k = 0; k < si[5]; ++k) {
-        T a = (T)l.pe()[si[4] + k];
-        T t = si[1] == 0 ? a * r2 : a * r;
-        if (t < T(50)) {
-          T ex = (T)l.pc()[si[4] + k] * exp_neg<T>(t, l.L + wf.l_etab);
-          g += ex;
-          if constexpr (GS == 3) {
-            g1 -= a * ex;
-            g2 += a * a * ex;
+        for (int k = 0; k < si[5]; ++k) {
+          T a = (T)l.pe()[si[4] + k];
+          T t = si[1] == 0 ? a * r2 : a * r;
+          if (t < T(50)) {
+            T ex = (T)l.pc()[si[4] + k] * exp_neg<T>(t, l.L + wf.l_etab);
+            g += ex;
+            if constexpr (GS == 3) {
+              g1 -= a * ex;
+              g2 += a * a * ex;
+            }
           }
         }
       }
-    }
-    T* o = gt + e * gs + GS * sh;
-    o[0] = g;
-    if constexpr (GS == 3) {
-      o[1] = g1;
-      o[2] = g2;
+      T* o = gt + e * gs + GS * sh;
+      o[0] = g;
+      if constexpr (GS == 3) {
+        o[1] = g1;
+        o[2] = g2;
+      }
     }
   }
   __syncthreads();

@@ -283,7 +283,7 @@ DevWF sweep_layout(const vbqmc_ctx* x) {
     nUm = std::max(nUm, (int)x->sp[s].sets.size());
     nPm = std::max(nPm, (int)x->sp[s].porb.size());
   }
-  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  LdsAlloc lds{a.l_rsched};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
   a.l_R = lds(3 * x->N);
@@ -324,7 +324,7 @@ DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
     nUm = std::max(nUm, (int)x->sp[s].sets.size());
     nPm = std::max(nPm, (int)x->sp[s].porb.size());
   }
-  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  LdsAlloc lds{a.l_rsched};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
   a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
@@ -371,7 +371,7 @@ DevWF rows_layout(const vbqmc_ctx* x) {
     nUm = std::max(nUm, (int)x->sp[s].sets.size());
     nPm = std::max(nPm, (int)x->sp[s].porb.size());
   }
-  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  LdsAlloc lds{a.l_psh};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
   a.l_disp = lds(kGroup * (4 * x->nnuc + 1));
@@ -465,7 +465,7 @@ DevWF aux_layout(const vbqmc_ctx* x) {
   for (int s = 0; s < 2; ++s) nPm = std::max(nPm, (int)x->sp[s].porb.size());
   // the orbital coefficients are read from global memory here (more tiles
   // resident per CU); the rest of the table image is staged
-  LdsAlloc lds{a.lam_in_lds ? a.l_lam : a.timg_len};
+  LdsAlloc lds{a.l_rsched};
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
   a.l_R = lds(std::max(3 * x->N, 3 * kGroup));
@@ -823,7 +823,6 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_pe = lds(wf.nprim);
   wf.l_pc = lds(wf.nprim);
   wf.l_etab = lds(64);
-  wf.l_psh = ilds(wf.nprim);
   wf.l_nuc = lds(4 * x->nnuc);
   wf.l_en = lds(6 * x->nnuc);
   for (int s = 0; s < 2; ++s) {
@@ -841,7 +840,11 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.rsched_len = x->rsched_len;
   wf.rsched_sto = 0;
   for (int s = 0; s < x->nshell; ++s) wf.rsched_sto |= x->shtab[8 * s + 1] == 1;
+  // the radial schedule and the primitive-to-shell map close the table
+  // image: a layout stages the prefix it needs (the row kernel up to the
+  // schedule, the sweeps and the tile kernel only the tables before it)
   wf.l_rsched = ilds((int)x->rsched.size());
+  wf.l_psh = ilds(wf.nprim);
   int lam_elems = x->Mpad * x->nop;
   int lam_doubles = wf.precision == 0 ? lam_elems : (wf.precision == 1 ? (lam_elems + 1) / 2 : (lam_elems + 3) / 4);
   // orbital coefficients go to LDS when they take at most 16 KiB

@@ -268,6 +268,33 @@ def test_vmc_mixed_form_eloc_is_fp64(lib, oracle_mod, kern):
     assert same.mean() >= 0.9, f"{(~same).sum()} of {W} walks differ from FP64"
 
 
+def test_refreshed_walkers_match_a_fresh_evaluation(lib):
+    # a walker rebuilt by the sweep's inverse refresh and measured by the
+    # local-energy kernels has the E_L that a fresh evaluation of its
+    # configuration gives, to rounding: the value rows of the refresh, of the
+    # local energy and of the evaluation agree bit for bit.  On the 40-electron
+    # molecule a few near-singular walkers amplify a last-bit difference in
+    # those rows by 1e4-1e5, so this checks the absolute E_L difference of all
+    # 4096 walkers after one step in which every walker with an accepted move
+    # is rebuilt (refresh_every = 1).
+    import torch
+    sysd = S.precision_molecule()
+    W = 4096
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=9)).cuda()
+    c64 = lib.Context(sysd)
+    print(f"[refresh vs evaluate] {sysd['name']} W={W}", flush=True)
+    st = c64.walkers_init(R0)
+    c64.vmc_advance(st, 20, 777, 0, 0.3)
+    R = c64.positions(st)
+    ctx = lib.Context(sysd, refresh_every=1)
+    s1 = ctx.walkers_init(R.clone())
+    acc = ctx.new_vmc_acc(W)
+    ctx.vmc_advance(s1, 1, 777, 1001, 0.3, False, acc)
+    e = c64.evaluate(ctx.positions(s1), want=("eloc",))["eloc"]
+    d = (acc["e_last"] - e).abs()
+    assert float(d.max()) < 1e-9, (float(d.max()), int(d.argmax()))
+
+
 def test_dmc_mixed_form_eloc_is_fp64(lib, oracle_mod):
     # electron-major DMC in the mixed form: every surviving walker's E_L equals
     # the oracle's FP64 E_L at its configuration
