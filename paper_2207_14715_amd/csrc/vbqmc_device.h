@@ -516,10 +516,13 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
   return Pz * g + P * fr * z;
 }
 
-// Writes rows e < nout_rows of the tile (all 16 by default).
+// Writes rows e < nout_rows of the tile (all 16 by default).  With a column
+// map (cmap[spin][orbital] = position or -1, rows grow0 + e below rsplit of
+// spin 0) only the mapped columns are stored, row e at out + e * ostride.
 template <int NT, int PREC, int GS = 3>
 __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, double* out = nullptr,
-                              int nout_rows = kGroup) {
+                              int nout_rows = kGroup, const int* cmap = nullptr, int ostride = 0, int grow0 = 0,
+                              int rsplit = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
   const int nct = wf.nop / 16;
@@ -528,6 +531,15 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
     const int col = ct * 16 + (lane & 15);
     const int e = lane & 15;
     const bool live = e < ne;
+    auto put = [&](int row, double v) {
+      if (row >= nout_rows) return;
+      if (cmap) {
+        const int p = cmap[(grow0 + row < rsplit ? 0 : wf.nop) + col];
+        if (p >= 0) Phi[row * ostride + p] = v;
+      } else {
+        Phi[row * wf.nop + col] = v;
+      }
+    };
     if constexpr (PREC == 0) {
       const double* lam = l.lam<double>();
       v4d acc = {0, 0, 0, 0};
@@ -546,8 +558,7 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
       }
       // f64 16x16x4 output: register r of lane l holds row 4r + l/16
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * r + (lane >> 4) < nout_rows) Phi[(4 * r + (lane >> 4)) * wf.nop + col] = acc[r];
+      for (int r = 0; r < 4; ++r) put(4 * r + (lane >> 4), acc[r]);
     } else if constexpr (PREC == 1) {
       const float* lam = l.lam<float>();
       v4f acc = {0, 0, 0, 0};
@@ -564,8 +575,7 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
       }
       // f32 output: register r of lane l holds row 4(l/16) + r
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * (lane >> 4) + r < nout_rows) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+      for (int r = 0; r < 4; ++r) put(4 * (lane >> 4) + r, (double)acc[r]);
     } else {
       const uint16_t* lam = l.lam<uint16_t>();
       v4f acc = {0, 0, 0, 0};
@@ -580,8 +590,7 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * (lane >> 4) + r < nout_rows) Phi[(4 * (lane >> 4) + r) * wf.nop + col] = (double)acc[r];
+      for (int r = 0; r < 4; ++r) put(4 * (lane >> 4) + r, (double)acc[r]);
     }
   }
   __syncthreads();

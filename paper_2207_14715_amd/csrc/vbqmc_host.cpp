@@ -362,6 +362,9 @@ DevWF sweepg_layout(const vbqmc_ctx* x, int G) {
 // the Jastrow move tables during the moves; packed reference rows during an
 // inverse refresh; positions, derivative rows and per-electron results
 // during the local energy.
+// register columns per lane of the row kernel (its NE template argument)
+int rows_columns(const vbqmc_ctx* x) { return x->nup <= 10 && x->ndn <= 10 ? 10 : 16; }
+
 DevWF rows_layout(const vbqmc_ctx* x) {
   DevWF a = x->wf;
   const int NG = kRowWalkers, N = x->N, nop = x->nop;
@@ -397,11 +400,15 @@ DevWF rows_layout(const vbqmc_ctx* x) {
   a.l_xch = w(32);
   a.gw_stride = w.o;
   lds.o += NG * a.gw_stride;
+  a.l_cmap = lds.ints(2 * nop);
+  int vw = 1;
+  for (int s = 0; s < 2; ++s) vw = std::max(vw, x->sp[s].n + (int)x->sp[s].porb.size());
+  a.rows_vw = std::max(vw, rows_columns(x));
   const int u0 = lds.o;
   a.l_Rp = lds(3 * NG * N);
   a.l_ua = lds(NG * N);
   const int v0 = lds.o;
-  a.l_Vn = lds(NG * nmax * nop);
+  a.l_Vn = lds(NG * N * a.rows_vw);
   a.l_jx = lds(NG * N * N);
   const int end_moves = lds.o;
   lds.o = v0;

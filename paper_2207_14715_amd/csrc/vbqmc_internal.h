@@ -93,6 +93,10 @@ struct DevWF {
   // slots of a move (l_xch, walker-relative); per wavefront the Jastrow
   // move tables, refresh rows, local-energy row results and structure ratios
   int l_xch, l_jx, l_Vr, l_gc4, l_rI, lds_rows_doubles;
+  // row kernel: trial rows of both spins keep only the columns a move reads
+  // (reference slots, then table orbitals), rows_vw doubles per row, placed
+  // by the column map l_cmap ([spin][orbital] -> position or -1)
+  int l_cmap, rows_vw;
 };
 
 // scalar slots in the record's / LDS scalar block

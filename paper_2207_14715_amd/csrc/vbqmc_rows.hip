@@ -86,7 +86,18 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
   double es = live && q == 0 ? e_sum[w] : 0.0, e2s = live && q == 0 ? e2_sum[w] : 0.0;
   double* Rp = l.L + wf.l_Rp;  // trial positions [spin][walker][electron of spin][3]
   double* ua = l.L + wf.l_ua;  // acceptance draws, same rows
-  double* Vn = l.L + wf.l_Vn;  // trial orbital rows of the spin being moved [walker][electron][nop]
+  double* Vn = l.L + wf.l_Vn;  // trial orbital rows [spin][walker][electron of spin][VW]
+  const int VW = wf.rows_vw;
+  // column map of the trial rows: orbital ref_j of a spin to position j,
+  // table orbital p to n + p, every other orbital to -1
+  int* cmap = (int*)(l.L + wf.l_cmap);
+  for (int k = lane; k < 2 * wf.nop; k += 64) cmap[k] = -1;
+  __syncthreads();
+  for (int s = 0; s < 2; ++s) {
+    const int n = wf.sp[s].n, w2 = n + wf.sp[s].nP;
+    for (int j = lane; j < w2; j += 64) cmap[s * wf.nop + (j < n ? l.ref(s)[j] : l.porb(s)[j - n])] = j;
+  }
+  __syncthreads();
   double* Xj = l.L + wf.l_jx;  // Jastrow move tables [walker][N][N]
   const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
   const double kappa = wf.kappa;
@@ -185,25 +196,19 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       }
     }
     __syncthreads();
+    // ---- trial orbital rows of all electrons of the four walkers ----
+    // (rows in the order of Rp; only the columns a move reads are kept)
+    for (int g0 = 0; g0 < kRowWalkers * N; g0 += kGroup) {
+      const int ne = min(kGroup, kRowWalkers * N - g0);
+      group_radial<64, PT, 1>(wf, l, Rp, g0, ne);
+      group_channel<64, PT, 1>(wf, l, ne, 0, Vn + g0 * VW, ne, cmap, VW, g0, kRowWalkers * Nup);
+    }
     // ---- the moves, spin by spin ----
     for (int s = 0; s < 2; ++s) {
       const SpinTab& sp = wf.sp[s];
       const int n = sp.n, nP = sp.nP, nU = sp.nU, e0 = sp.e0;
       if (n == 0) continue;
-      // trial orbital rows of this spin's electrons of all four walkers
-      {
-        const double* Rs = Rp + 3 * kRowWalkers * e0;
-        for (int g0 = 0; g0 < kRowWalkers * n; g0 += kGroup) {
-          const int ne = min(kGroup, kRowWalkers * n - g0);
-          group_radial<64, PT, 1>(wf, l, Rs, g0, ne);
-          group_channel<64, PT, 1>(wf, l, ne, 0, Vn + g0 * wf.nop, ne);
-        }
-      }
-      const int* ref = l.ref(s);
-      int refj[NE];
-#pragma unroll
-      for (int j = 0; j < NE; ++j) refj[j] = j < n ? ref[j] : 0;
-      const int own = (q >= n && q < n + nP) ? l.porb(s)[q - n] : -1;
+      const bool own = q >= n && q < n + nP;  // lane of a table orbital
       double C[NE];
       {
         const double* B = lg.B(s);
@@ -244,15 +249,15 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       // determinant ratio and are started first.
       for (int il = 0; il < n; ++il) {
         const int i = e0 + il;
-        const double* Vrow = Vn + (g * n + il) * wf.nop;
+        const double* Vrow = Vn + (kRowWalkers * e0 + g * n + il) * VW;
         const int r = kRowWalkers * e0 + g * n + il;  // trial row of (walker g, electron i)
         const double u_r = ua[r];
         const double xr0 = X[min(q, N - 1) * N + i];
         const double xr1 = X[min(q + 16, N - 1) * N + i];
         double vr[NE];
 #pragma unroll
-        for (int j = 0; j < NE; ++j) vr[j] = Vrow[refj[j]];
-        const double vo = Vrow[own >= 0 ? own : 0];
+        for (int j = 0; j < NE; ++j) vr[j] = Vrow[j < n ? j : 0];
+        const double vo = Vrow[own ? q : 0];
         const double eU = exp(row_bcast(i < 16 ? run0 : run1, i & 15));
         double t0 = 0.0, t1 = 0.0;
 #pragma unroll
@@ -261,14 +266,14 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
           t1 += vr[j + 1] * C[j + 1];
         }
         const double t = t0 + t1;
-        const double y = (own >= 0 ? vo : 0.0) - t;
+        const double y = (own ? vo : 0.0) - t;
         const double rho = row_bcast(t, il);
         if (q == il) {
 #pragma unroll
           for (int j = 0; j < NE; ++j)
             if (j < n) xch[j] = C[j];
         }
-        if (own >= 0) xch[16 + (q - n)] = y;
+        if (own) xch[16 + (q - n)] = y;
         wave_sync();
         double bc[NE];
 #pragma unroll
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
           if (q + 16 > i && q + 16 < N) run1 += xr1;
           double f = 0.0;
           if (q < n) f = -(t - (q == il ? 1.0 : 0.0)) * ir;
-          else if (own >= 0) f = y * ir;
+          else if (own) f = y * ir;
 #pragma unroll
           for (int j = 0; j < NE; ++j)
             if (j < n) C[j] += bc[j] * f;
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         for (int j = 0; j < NE; ++j)
           if (j < n) {
             if (q < n) B[j * n + q] = C[j];
-            else if (own >= 0) T[j * nP + (q - n)] = C[j];
+            else if (own) T[j * nP + (q - n)] = C[j];
           }
         if (q < nU) lg.Ru(s)[q] = Ru;
         if (q == 0) {
