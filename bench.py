@@ -24,10 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
-# HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker)
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
-# calibration; None until measured for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker,
+# FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+# calibration: FETCH_SIZE 4570 KiB x 2.000 + WRITE_SIZE 8256 KiB x 1.000
+TRAFFIC_BYTES_PER_LAUNCH = (4570.2 * 2.0 + 8256.0) * 1024
 TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
 # launch): FETCH_SIZE 5738 KiB x 2.000 + WRITE_SIZE 11157 KiB x 1.000
@@ -240,9 +240,11 @@ def main():
         traffic = TRAFFIC_ROWS["bytes"] if (W == TRAFFIC_ROWS["walkers"] and args.precision == "fp64" and
                                             steps_launch == TRAFFIC_ROWS["steps_per_launch"]) else None
     else:
-        kernel = f"k_sweep_g<{lanes}, {prec_tag}>" if lanes < 64 else f"k_sweep<64, {prec_tag}>"
+        pt = 1 if args.precision == "mixed" else prec_tag
+        kernel = f"k_sweep_g<{lanes}, {pt}, {prec_tag}>" if lanes < 64 else f"k_sweep<64, {prec_tag}>"
         flops_launch = sweep_flops
-        traffic = TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES else None
+        traffic = (TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES and W == 4096 and args.precision == "fp64"
+                   else None)
     kernel_avg = kernel_s / launches
     achieved = flops_launch / kernel_avg / 1e12
     line = {
