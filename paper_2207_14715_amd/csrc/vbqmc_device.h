@@ -232,7 +232,7 @@ struct Ld {
   double* bk = nullptr;  // backup area of the walker record (all-electron moves)
   __device__ Ld(double* l, const DevWF& w) : L(l), wf(w) {}
   // constant tables
-  __device__ const int* fn() const { return (const int*)(L + wf.l_fn); }      // [Mpad][2]
+  __device__ const int* fn() const { return (const int*)(L + wf.l_fn); }      // [Mpad][2], see FnInfo
   __device__ const int* sh() const { return (const int*)(L + wf.l_sh); }      // [nshell][8]
   __device__ const double* pe() const { return L + wf.l_pe; }
   __device__ const double* pc() const { return L + wf.l_pc; }
@@ -282,6 +282,16 @@ struct Ld {
   __device__ double* ua() const { return L + wf.l_ua; }
   __device__ double* Vn() const { return L + wf.l_Vn; }
 };
+// basis function mu of the staged function table: shell (-1 for padding),
+// angular index m, l, kind (0 Gaussian, 1 Slater) and center, from one load
+struct FnInfo {
+  int sh, m, lq, kind, nuc;
+};
+__device__ __forceinline__ FnInfo fn_info(const Ld& l, int mu) {
+  const int2 w = ((const int2*)l.fn())[mu];
+  return {w.x, w.y & 15, (w.y >> 4) & 3, (w.y >> 6) & 1, w.y >> 8};
+}
+
 template <> __device__ const double* Ld::lam<double>() const {
   return wf.lam_in_lds ? (const double*)(L + wf.l_lam) : wf.lamT;
 }
@@ -469,13 +479,11 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
 // electron e of the tile, from the radial tables
 template <typename T, int GS = 3>
 __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
-  const int* fn = l.fn();
-  int sh = fn[2 * mu];
+  const FnInfo fi = fn_info(l, mu);
+  const int sh = fi.sh;
   if (sh < 0) return T(0);
-  int m = fn[2 * mu + 1];
-  const int* si = l.sh() + 8 * sh;
-  int kind = si[1], lq = si[2];
-  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * si[0];
+  const int m = fi.m, kind = fi.kind, lq = fi.lq;
+  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * fi.nuc;
   const T* gg = (const T*)l.gtab() + e * gtab_stride<GS>(wf) + GS * sh;
   T x = d[0], y = d[1], z = d[2], r2 = d[3];
   T g = gg[0], g1 = T(0), g2 = T(0);
@@ -600,16 +608,14 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
 // of the tile, from the radial tables (GS = 3), sharing the table reads.
 template <typename T>
 __device__ __forceinline__ void chan_value4(const DevWF& wf, const Ld& l, int e, int mu, T (&o)[4]) {
-  const int* fn = l.fn();
-  int sh = fn[2 * mu];
+  const FnInfo fi = fn_info(l, mu);
+  const int sh = fi.sh;
   if (sh < 0) {
     o[0] = o[1] = o[2] = o[3] = T(0);
     return;
   }
-  int m = fn[2 * mu + 1];
-  const int* si = l.sh() + 8 * sh;
-  int kind = si[1], lq = si[2];
-  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * si[0];
+  const int m = fi.m, kind = fi.kind, lq = fi.lq;
+  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * fi.nuc;
   const T* gg = (const T*)l.gtab() + e * gtab_stride<3>(wf) + 3 * sh;
   T x = d[0], y = d[1], z = d[2], r2 = d[3];
   T g = gg[0], g1 = gg[1], g2 = gg[2];
@@ -1113,7 +1119,7 @@ __device__ void point_orbitals(const DevWF& wf, const Ld& l, double px, double p
       g1 += pt[2 * (p0 + k) + 1];
     }
     T o[5];
-    channels<T>(kind, lq, l.fn()[2 * mu + 1], x, y, z, r2, r, g, g1, T(0), nch, o);
+    channels<T>(kind, lq, l.fn()[2 * mu + 1] & 15, x, y, z, r2, r, g, g1, T(0), nch, o);
     for (int c = 0; c < nch; ++c) chi[c * wf.Mpad + mu] = o[c];
   }
   __syncthreads();

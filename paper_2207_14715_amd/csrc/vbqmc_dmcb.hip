@@ -233,16 +233,14 @@ __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ p
 // value, x, y, z channels of function mu at electron e of the tile (GS = 3 tables)
 template <typename T>
 __device__ __forceinline__ void chan_vg(const DevWF& wf, const Ld& l, int e, int mu, T (&o)[4]) {
-  const int* fn = l.fn();
-  const int sh = fn[2 * mu];
+  const FnInfo fi = fn_info(l, mu);
+  const int sh = fi.sh;
   if (sh < 0) {
     o[0] = o[1] = o[2] = o[3] = T(0);
     return;
   }
-  const int m = fn[2 * mu + 1];
-  const int* si = l.sh() + 8 * sh;
-  const int kind = si[1], lq = si[2];
-  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * si[0];
+  const int m = fi.m, kind = fi.kind, lq = fi.lq;
+  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * fi.nuc;
   const T* gg = (const T*)l.gtab() + e * gtab_stride<3>(wf) + 3 * sh;
   const T x = d[0], y = d[1], z = d[2], r2 = d[3];
   const T g = gg[0], g1 = gg[1];

@@ -628,7 +628,9 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
       x->pcoef.push_back(wfi->prim_coef[off + k]);
       x->pshell.push_back(s);
     }
-    for (int m = 0; m < nfunc(l); ++m) x->fnmap.insert(x->fnmap.end(), {s, m});
+    // per function: shell, and m | l << 4 | kind << 6 | center << 8 (one load
+    // gives a tile pass everything it needs to find the radial tables)
+    for (int m = 0; m < nfunc(l); ++m) x->fnmap.insert(x->fnmap.end(), {s, m | (l << 4) | (kind << 6) | (cen << 8)});
     off += np;
     fn += nfunc(l);
   }

@@ -52,7 +52,7 @@ struct DevWF {
   const double* pexp;
   const double* pcoef;
   const int* pshell;    // [nprim] shell of each primitive
-  const int* fnmap;     // [Mpad][2]: shell (or -1 for padding), angular index m
+  const int* fnmap;     // [Mpad][2]: shell (or -1 for padding), m | l << 4 | kind << 6 | center << 8
   const double* lamT;   // [Mpad][nop] lambda transposed, zero padded
   const float* lamT32;
   const uint16_t* lamT16;  // bf16 bit patterns
