@@ -4,8 +4,9 @@
 // orbitals) a walker's single-electron moves (Sec. 2.3.1) fit one 16-lane row
 // of a wavefront: lane k keeps column k of [B | T] (the reference inverse and
 // the replaced-column table of the spin being moved) in registers, so that
-// with the trial orbital row v of a move
-//   t_k = sum_j v[ref_j] C[j][k]
+// with the trial orbital row of a move, kept compact as v_j = orbital ref_j at
+// the trial point (j < n) followed by the table orbitals v_P,
+//   t_k = sum_{j<n} v_j C[j][k]
 // is at once the Sherman-Morrison vector u = v_ref^T B (lanes k < n), the
 // determinant ratio rho = u_il of the reference, and y = v_P - v_ref^T T
 // (table lanes).  An accepted move is one register FMA per column entry with
@@ -17,7 +18,8 @@
 // y_ij (j already moved) for every pair, the change for electron i is the
 // running sum of x_ij over the later electrons and x_ij or y_ij over the
 // earlier ones, so a move only adds one table entry per lane when it is
-// accepted.  Four walkers share a wavefront; trial rows, the reference rows
+// accepted.  Four walkers share a wavefront; the trial rows of all their
+// electrons (formed once per step, both spins together), the reference rows
 // of an inverse refresh and the local-energy rows of the four walkers are
 // formed on MFMA in tiles of 16 (walker, electron) rows, and the local energy
 // (Eq. Elav) is evaluated in the same launch, so that a walker's record
