@@ -287,10 +287,9 @@ struct Ld {
 struct FnInfo {
   int sh, m, lq, kind, nuc;
 };
-__device__ __forceinline__ FnInfo fn_info(const Ld& l, int mu) {
-  const int2 w = ((const int2*)l.fn())[mu];
-  return {w.x, w.y & 15, (w.y >> 4) & 3, (w.y >> 6) & 1, w.y >> 8};
-}
+__device__ __forceinline__ FnInfo fn_decode(int2 w) { return {w.x, w.y & 15, (w.y >> 4) & 3, (w.y >> 6) & 1, w.y >> 8}; }
+__device__ __forceinline__ int2 fn_word(const Ld& l, int mu) { return ((const int2*)l.fn())[mu]; }
+__device__ __forceinline__ FnInfo fn_info(const Ld& l, int mu) { return fn_decode(fn_word(l, mu)); }
 
 template <> __device__ const double* Ld::lam<double>() const {
   return wf.lam_in_lds ? (const double*)(L + wf.l_lam) : wf.lamT;
@@ -478,8 +477,7 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
 // basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function mu at
 // electron e of the tile, from the radial tables
 template <typename T, int GS = 3>
-__device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
-  const FnInfo fi = fn_info(l, mu);
+__device__ __forceinline__ T chan_value_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, int c) {
   const int sh = fi.sh;
   if (sh < 0) return T(0);
   const int m = fi.m, kind = fi.kind, lq = fi.lq;
@@ -524,6 +522,11 @@ __device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int
   return Pz * g + P * fr * z;
 }
 
+template <typename T, int GS = 3>
+__device__ __forceinline__ T chan_value(const DevWF& wf, const Ld& l, int e, int mu, int c) {
+  return chan_value_fi<T, GS>(wf, l, e, fn_info(l, mu), c);
+}
+
 // Writes rows e < nout_rows of the tile (all 16 by default).  With a column
 // map (cmap[spin][orbital] = position or -1, rows grow0 + e below rsplit of
 // spin 0) only the mapped columns are stored, row e at out + e * ostride.
@@ -552,13 +555,23 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
       const double* lam = l.lam<double>();
       v4d acc = {0, 0, 0, 0};
       // Mpad is a multiple of 16: four k-steps per pass, their table lookups
-      // and coefficient loads issued before the MFMAs (same accumulation order)
+      // and coefficient loads issued before the MFMAs (same accumulation
+      // order); the function words of the next pass are loaded one pass ahead
+      int2 wd[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wd[u] = fn_word(l, 4 * u + (lane >> 4));
       for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
         double a[4], b[4];
+        FnInfo fi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          fi[u] = fn_decode(wd[u]);
+          wd[u] = fn_word(l, min(k0 + 16, wf.Mpad - 16) + 4 * u + (lane >> 4));
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + 4 * u + (lane >> 4);
-          a[u] = live ? chan_value<double, GS>(wf, l, e, k, c) : 0.0;
+          a[u] = live ? chan_value_fi<double, GS>(wf, l, e, fi[u], c) : 0.0;
           b[u] = lam[(size_t)k * wf.nop + col];
         }
 #pragma unroll
@@ -607,8 +620,7 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
 // Channels 1..4 (gradient x, y, z and Laplacian) of function mu at electron e
 // of the tile, from the radial tables (GS = 3), sharing the table reads.
 template <typename T>
-__device__ __forceinline__ void chan_value4(const DevWF& wf, const Ld& l, int e, int mu, T (&o)[4]) {
-  const FnInfo fi = fn_info(l, mu);
+__device__ __forceinline__ void chan_value4_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, T (&o)[4]) {
   const int sh = fi.sh;
   if (sh < 0) {
     o[0] = o[1] = o[2] = o[3] = T(0);
@@ -651,6 +663,11 @@ __device__ __forceinline__ void chan_value4(const DevWF& wf, const Ld& l, int e,
   o[3] = lap;
 }
 
+template <typename T>
+__device__ __forceinline__ void chan_value4(const DevWF& wf, const Ld& l, int e, int mu, T (&o)[4]) {
+  chan_value4_fi<T>(wf, l, e, fn_info(l, mu), o);
+}
+
 // All four derivative channels of a tile in one pass: out[c][e][p] for
 // c = 0..3 (gradient x, y, z, Laplacian), rows e < ne.
 template <int NT, int PREC>
@@ -668,13 +685,22 @@ __device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* ou
       v4d acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
+      int2 wd[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wd[u] = fn_word(l, 4 * u + (lane >> 4));
       for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
         double a[4][4], b[4];
+        FnInfo fi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          fi[u] = fn_decode(wd[u]);
+          wd[u] = fn_word(l, min(k0 + 16, wf.Mpad - 16) + 4 * u + (lane >> 4));
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + 4 * u + (lane >> 4);
           a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
-          if (live) chan_value4<double>(wf, l, e, k, a[u]);
+          if (live) chan_value4_fi<double>(wf, l, e, fi[u], a[u]);
           b[u] = lam[(size_t)k * wf.nop + col];
         }
 #pragma unroll
