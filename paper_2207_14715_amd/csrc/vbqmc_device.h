@@ -132,6 +132,33 @@ template <> __device__ __forceinline__ double exp_neg<double>(double t, const do
 }
 template <> __device__ __forceinline__ float exp_neg<float>(float t, const double*) { return expf(-t); }
 
+// Two independent exp_neg evaluations with the same operations, arranged so
+// that both table reads are in flight before either polynomial needs them.
+template <typename T>
+__device__ __forceinline__ void exp_neg2(T t0, T t1, const double* etab, T& e0, T& e1) {
+  e0 = exp_neg<T>(t0, etab);
+  e1 = exp_neg<T>(t1, etab);
+}
+template <>
+__device__ __forceinline__ void exp_neg2<double>(double t0, double t1, const double* etab, double& e0, double& e1) {
+  const double n0 = __builtin_rint(t0 * -92.33248261689366), n1 = __builtin_rint(t1 * -92.33248261689366);
+  const int k0 = (int)n0, k1 = (int)n1;
+  const double T0 = etab[k0 & 63], T1 = etab[k1 & 63];
+  double r0 = __builtin_fma(-n0, 0.010830424696249145, -t0), r1 = __builtin_fma(-n1, 0.010830424696249145, -t1);
+  r0 = __builtin_fma(-n0, 3.623510646634843e-19, r0);
+  r1 = __builtin_fma(-n1, 3.623510646634843e-19, r1);
+  double q0 = __builtin_fma(r0, 1.0 / 120.0, 1.0 / 24.0), q1 = __builtin_fma(r1, 1.0 / 120.0, 1.0 / 24.0);
+  q0 = __builtin_fma(q0, r0, 1.0 / 6.0);
+  q1 = __builtin_fma(q1, r1, 1.0 / 6.0);
+  q0 = __builtin_fma(q0, r0, 0.5);
+  q1 = __builtin_fma(q1, r1, 0.5);
+  q0 = __builtin_fma(q0, r0, 1.0);
+  q1 = __builtin_fma(q1, r1, 1.0);
+  const double p0 = q0 * r0, p1 = q1 * r1;
+  e0 = __builtin_ldexp(__builtin_fma(T0, p0, T0), k0 >> 6);
+  e1 = __builtin_ldexp(__builtin_fma(T1, p1, T1), k1 >> 6);
+}
+
 // Radial sums of a shell: Gaussian (kind 0) g = sum c e^{-a r^2} with
 // g1 = dg/d(r^2), g2 = d2g/d(r^2)^2; Slater (kind 1) g = sum c e^{-a r} with
 // g1 = dg/dr, g2 = d2g/dr2.  Primitives whose exponent argument exceeds 50 are
@@ -407,8 +434,9 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
       if (f0 & kRsSto) t0 = A0 * (T)sqrt(R0);
       if (f1 & kRsSto) t1 = A1 * (T)sqrt(R1);
     }
-    const T x0 = C0 * exp_neg<T>(fmin(t0, T(64)), etab);
-    const T x1 = C1 * exp_neg<T>(fmin(t1, T(64)), etab);
+    T ex0, ex1;
+    exp_neg2<T>(fmin(t0, T(64)), fmin(t1, T(64)), etab, ex0, ex1);
+    const T x0 = C0 * ex0, x1 = C1 * ex1;
     add(((f0 & kRsLive) && t0 < T(50)) ? x0 : T(0), A0, f0, h0);
     add(((f1 & kRsLive) && t1 < T(50)) ? x1 : T(0), A1, f1, h1);
   }

@@ -32,26 +32,14 @@ __device__ __forceinline__ double dpp_mov(double v) {
 }
 
 // Lane k (0..15, the same in every lane) of each 16-lane row, to every lane
-// of that row: DPP row_newbcast.  Every lane of the row must be active.
+// of that row, through the LDS crossbar (ds_bpermute; a DPP row broadcast
+// would need k as an immediate, and a switch over k costs more than the
+// crossbar and splits the code around it into basic blocks).
 __device__ __forceinline__ double row_bcast(double v, int k) {
-  switch (k) {
-    case 0: return dpp_mov<0x150>(v);
-    case 1: return dpp_mov<0x151>(v);
-    case 2: return dpp_mov<0x152>(v);
-    case 3: return dpp_mov<0x153>(v);
-    case 4: return dpp_mov<0x154>(v);
-    case 5: return dpp_mov<0x155>(v);
-    case 6: return dpp_mov<0x156>(v);
-    case 7: return dpp_mov<0x157>(v);
-    case 8: return dpp_mov<0x158>(v);
-    case 9: return dpp_mov<0x159>(v);
-    case 10: return dpp_mov<0x15A>(v);
-    case 11: return dpp_mov<0x15B>(v);
-    case 12: return dpp_mov<0x15C>(v);
-    case 13: return dpp_mov<0x15D>(v);
-    case 14: return dpp_mov<0x15E>(v);
-    default: return dpp_mov<0x15F>(v);
-  }
+  const int src = (((int)(threadIdx.x & 63) & ~15) | k) << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
 // Sum over the 4 lanes of a quad (DPP quad permutations), the same bits in
