@@ -30,8 +30,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 TRAFFIC_BYTES_PER_LAUNCH = (4570.2 * 2.0 + 8256.0) * 1024
 TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
-# launch): FETCH_SIZE 5776 KiB x 2.000 + WRITE_SIZE 11425 KiB x 1.000
-TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5776.4 * 2.0 + 11424.7) * 1024}
+# launch): FETCH_SIZE 5592 KiB x 2.000 + WRITE_SIZE 10902 KiB x 1.000
+TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5592.1 * 2.0 + 10901.8) * 1024}
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 

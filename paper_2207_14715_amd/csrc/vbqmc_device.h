@@ -74,11 +74,14 @@ __device__ __forceinline__ PairCoef ee_coef(const DevWF& wf, bool anti) {
 __device__ __forceinline__ PairCoef en_coef(const double* e) { return {e[0], e[1], e[2], e[3], e[4], e[5]}; }
 
 // 1 + bR = (den + b r) / den with den = 1 + kappa r, so the two reciprocals
-// below are independent (they overlap instead of chaining)
+// below are independent (they overlap instead of chaining).  K0: kappa is 0,
+// so den = 1 and the first reciprocal is 1 (the same values, one division
+// fewer).
+template <bool K0 = false>
 __device__ __forceinline__ void pair_fn(double r, double kappa, const PairCoef& c, double& u, double& u1,
                                         double& u2) {
-  double den = 1.0 + kappa * r;
-  double iden = 1.0 / den;
+  double den = K0 ? 1.0 : 1.0 + kappa * r;
+  double iden = K0 ? 1.0 : 1.0 / den;
   double id2 = 1.0 / (den + c.b * r);
   double R = r * iden, R1 = iden * iden, R2 = -2.0 * kappa * R1 * iden;
   double ib = den * id2;
@@ -99,9 +102,10 @@ __device__ __forceinline__ void pair_fn(double r, double kappa, const PairCoef& 
   u2 = uRR * R1 * R1 + uR * R2;
 }
 
+template <bool K0 = false>
 __device__ __forceinline__ double pair_val(double r, double kappa, const PairCoef& c) {
-  double den = 1.0 + kappa * r;
-  double R = r / den;
+  double den = K0 ? 1.0 : 1.0 + kappa * r;
+  double R = K0 ? r : r / den;
   double u = c.a * r / (den + c.b * r);  // a R / (1 + b R), independent of the division above
   double R2 = R * R;
   return u + R2 * (c.q0 + R * (c.q1 + R * (c.q2 + R * c.q3)));
@@ -1037,6 +1041,51 @@ __device__ double row_op_sum_p(const DevWF& wf, const Ld& l, int s, const double
     double a = w[porb[q]];
 #pragma unroll 4
     for (int k = 0; k < st.n; ++k) a -= w[ref[k]] * T[k * st.nP + q];
+    ybuf[q] = a;
+  }
+  double tot = 0.0;
+  const int* uit = l.ui(s);
+  for (int u = 0; u < st.nU; ++u) {
+    const int* ui = uit + 8 * u;
+    double m[9], yy[3], bb[3];
+    int e = gather_u(ui, T, st.nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (r < e) {
+        yy[r] = ybuf[ui[4 + r]];
+        bb[r] = B[ui[1 + r] * bstride + bcol];
+      }
+    tot += (rho * Ru[u] + adj_e(e, m, yy, bb)) * Wu[u];
+  }
+  return tot;
+}
+
+// row_op_sum_p for spins of at most NE electrons, with every load of the
+// reference part issued before the sums (same sums, same order)
+template <int NE>
+__device__ double row_op_sum_r(const DevWF& wf, const Ld& l, int s, const double* w, double* ybuf,
+                               const double* B, int bstride, int bcol, const double* T, const double* Ru,
+                               const double* Wu) {
+  const SpinTab& st = wf.sp[s];
+  const int n = st.n;
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  double wv[NE], bv[NE];
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    const int jj = j < n ? j : 0;
+    wv[j] = j < n ? w[ref[jj]] : 0.0;
+    bv[j] = j < n ? B[jj * bstride + bcol] : 0.0;
+  }
+  double rho = 0.0;
+#pragma unroll
+  for (int j = 0; j < NE; ++j)
+    if (j < n) rho += wv[j] * bv[j];
+  for (int q = 0; q < st.nP; ++q) {
+    double a = w[porb[q]];
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (k < n) a -= wv[k] * T[k * st.nP + q];
     ybuf[q] = a;
   }
   double tot = 0.0;

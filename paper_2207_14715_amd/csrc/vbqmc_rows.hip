@@ -152,10 +152,19 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double* pi = Rp + 3 * trial_row(Nup, Ndn, g2, i);
         const double* pj = Rp + 3 * trial_row(Nup, Ndn, g2, j);
         const PairCoef c = (i < Nup ? 0 : 1) != (j < Nup ? 0 : 1) ? c_anti : c_par;
-        const double o = pair_val(dist3(ri, rj), kappa, c);
-        const double aij = pair_val(dist3(pi, rj), kappa, c);
-        const double aji = pair_val(dist3(pj, ri), kappa, c);
-        const double nw = pair_val(dist3(pi, pj), kappa, c);
+        // (kappa = 0, the plain Pade form, skips a division per pair function)
+        double o, aij, aji, nw;
+        if (kappa == 0.0) {
+          o = pair_val<true>(dist3(ri, rj), kappa, c);
+          aij = pair_val<true>(dist3(pi, rj), kappa, c);
+          aji = pair_val<true>(dist3(pj, ri), kappa, c);
+          nw = pair_val<true>(dist3(pi, pj), kappa, c);
+        } else {
+          o = pair_val(dist3(ri, rj), kappa, c);
+          aij = pair_val(dist3(pi, rj), kappa, c);
+          aji = pair_val(dist3(pj, ri), kappa, c);
+          nw = pair_val(dist3(pi, pj), kappa, c);
+        }
         double* X = Xj + g2 * N * N;
         X[i * N + j] = aij - o;
         X[j * N + i] = aji - o;
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
           const int s = (i < Nup ? 0 : 1);
           double tot = 0.0;
           if (S2[wf.l_sc + SC_FLAGS] == 0.0)
-            tot = row_op_sum_p(wf, l, s, Phi4 + (c * kGroup + t) * wf.nop, yb + lane * (nPm + 1), S2 + wf.l_B[s],
+            tot = row_op_sum_r<NE>(wf, l, s, Phi4 + (c * kGroup + t) * wf.nop, yb + lane * (nPm + 1), S2 + wf.l_B[s],
                                wf.sp[s].n, i - wf.sp[s].e0, S2 + wf.l_T[s], S2 + wf.l_Ru[s], S2 + wf.l_Wu[s]);
           gc4[4 * rr + c] = tot / S2[wf.l_sc + SC_S];
         }
@@ -471,7 +480,8 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
             const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
             const double rij = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / rij;
             double u, u1, u2;
-            pair_fn(rij, kappa, cf, u, u1, u2);
+            if (kappa == 0.0) pair_fn<true>(rij, kappa, cf, u, u1, u2);
+            else pair_fn<false>(rij, kappa, cf, u, u1, u2);
             const double f = u1 * ir;
             gx += f * dx; gy += f * dy; gz += f * dz;
             lap += u2 + 2.0 * f;
