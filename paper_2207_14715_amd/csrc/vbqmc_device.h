@@ -381,8 +381,11 @@ __device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.ns
 // of a step are independent (arguments past the cutoff are clamped and their
 // terms dropped afterwards), and the schedule entries and operands of the
 // next step are loaded while they are evaluated.  Each shell's sum is
-// accumulated in the order of its primitives and stored at its last one;
-// rows of electrons past ne get zeros.
+// accumulated in the order of its primitives, restarting at its first one,
+// and the running sum is stored at every entry, so that the loop body has no
+// branch: the last store of a shell holds its whole sum (padding entries
+// repeat the bin's last shell and add nothing).  Rows of electrons past ne get
+// zeros.
 template <int PREC, int GS, bool STO>
 __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne) {
   // each term is rounded before it is added, in every kernel: the value rows
@@ -403,21 +406,17 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
   T d0 = de[4 * (n0.y >> 16) + 3], d1 = de[4 * (n1.y >> 16) + 3];
   T g = 0, g1 = 0, g2 = 0;
   auto add = [&](T ex, T a, unsigned f, unsigned sh) {
-    g += ex;
+    const bool first = f & kRsFirst;
+    g = (first ? T(0) : g) + ex;
     if constexpr (GS == 3) {
-      g1 -= a * ex;
-      g2 += a * a * ex;
+      g1 = (first ? T(0) : g1) - a * ex;
+      g2 = (first ? T(0) : g2) + a * a * ex;
     }
-    if (f & kRsLast) {
-      T* q = o + GS * sh;
-      q[0] = live ? g : T(0);
-      if constexpr (GS == 3) {
-        q[1] = live ? g1 : T(0);
-        q[2] = live ? g2 : T(0);
-      }
-      g = 0;
-      g1 = 0;
-      g2 = 0;
+    T* q = o + GS * sh;
+    q[0] = live ? g : T(0);
+    if constexpr (GS == 3) {
+      q[1] = live ? g1 : T(0);
+      q[2] = live ? g2 : T(0);
     }
   };
   for (int j = 0; j < wf.rsched_len; j += 2) {

@@ -229,13 +229,15 @@ struct LdsAlloc {
 // first, each to the bin with the fewest primitives so far, so every lane
 // walks about a quarter of the primitives in one fixed-length loop.  A bin
 // lists its shells' primitives in shell order (the order of the contraction
-// sums), flags the last primitive of each shell, and is padded with empty
-// entries to the longest bin rounded up to even, plus four rows read ahead.
+// sums) and flags the first primitive of each shell.  It is padded to the
+// longest bin rounded up to even, plus four rows read ahead, with empty
+// entries (no primitive term) of its last shell, which store that shell's sum
+// again; with fewer than four shells there is no schedule.
 void build_radial_schedule(vbqmc_ctx* x) {
   x->rsched.clear();
   x->rsched_len = 0;
   const int nprim = (int)x->pexp.size();
-  if (nprim >= (int)kRsPrim || x->nshell > 0xFFFF || x->nnuc > 0xFFFF) return;
+  if (nprim >= (int)kRsPrim || x->nshell > 0xFFFF || x->nnuc > 0xFFFF || x->nshell < 4) return;
   std::vector<int> order(x->nshell);
   for (int s = 0; s < x->nshell; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(),
@@ -263,11 +265,13 @@ void build_radial_schedule(vbqmc_ctx* x) {
       for (int k = 0; k < si[5]; ++k, ++j) {
         unsigned f = (unsigned)(si[4] + k) | kRsLive;
         if (si[1] == 1) f |= kRsSto;
-        if (k == si[5] - 1) f |= kRsLast;
+        if (k == 0) f |= kRsFirst;
         x->rsched[(size_t)2 * (4 * j + b)] = f;
         x->rsched[(size_t)2 * (4 * j + b) + 1] = (unsigned)s | ((unsigned)si[0] << 16);
       }
     }
+    const int s = bins[b].back();
+    for (; j < L + 4; ++j) x->rsched[(size_t)2 * (4 * j + b) + 1] = (unsigned)s | ((unsigned)x->shtab[8 * s] << 16);
   }
   x->rsched_len = L;
 }

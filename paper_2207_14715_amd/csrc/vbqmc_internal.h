@@ -10,7 +10,7 @@ namespace vbqmc {
 constexpr int kGroup = 16;     // electrons per MFMA row tile
 // radial schedule entry flags (first int of an entry; the primitive index
 // takes the low 24 bits)
-constexpr unsigned kRsPrim = 0x00FFFFFFu, kRsSto = 1u << 24, kRsLast = 1u << 25, kRsLive = 1u << 26;
+constexpr unsigned kRsPrim = 0x00FFFFFFu, kRsSto = 1u << 24, kRsFirst = 1u << 25, kRsLive = 1u << 26;
 constexpr int kChunk = 16;     // basis functions are padded to a multiple of this
 constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
 constexpr int kMaxSpin = 64;   // electrons per spin
