@@ -419,6 +419,7 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
       q[2] = live ? g2 : T(0);
     }
   };
+#pragma unroll 2
   for (int j = 0; j < wf.rsched_len; j += 2) {
     const unsigned f0 = n0.x, f1 = n1.x, h0 = n0.y & 0xFFFFu, h1 = n1.y & 0xFFFFu;
     const T A0 = (T)a0, C0 = (T)c0, R0 = d0, A1 = (T)a1, C1 = (T)c1, R1 = d1;
