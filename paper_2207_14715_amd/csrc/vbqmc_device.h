@@ -506,21 +506,33 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
   __syncthreads();
 }
 
-// basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function mu at
-// electron e of the tile, from the radial tables
+// operands of basis function fi at electron e of the tile: displacement from
+// its center and the radial sums of its shell (padding functions read shell 0
+// and evaluate to zero), loaded apart from the arithmetic so that a pass can
+// issue the loads of all its functions first
+template <typename T>
+struct ChanIn {
+  T x, y, z, r2, g, g1, g2;
+};
 template <typename T, int GS = 3>
-__device__ __forceinline__ T chan_value_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, int c) {
-  const int sh = fi.sh;
-  if (sh < 0) return T(0);
-  const int m = fi.m, kind = fi.kind, lq = fi.lq;
+__device__ __forceinline__ ChanIn<T> chan_load(const DevWF& wf, const Ld& l, int e, const FnInfo& fi) {
   const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * fi.nuc;
-  const T* gg = (const T*)l.gtab() + e * gtab_stride<GS>(wf) + GS * sh;
-  T x = d[0], y = d[1], z = d[2], r2 = d[3];
-  T g = gg[0], g1 = T(0), g2 = T(0);
+  const T* gg = (const T*)l.gtab() + e * gtab_stride<GS>(wf) + GS * max(fi.sh, 0);
+  ChanIn<T> in{d[0], d[1], d[2], d[3], gg[0], T(0), T(0)};
   if constexpr (GS == 3) {
-    g1 = gg[1];
-    g2 = gg[2];
+    in.g1 = gg[1];
+    in.g2 = gg[2];
   }
+  return in;
+}
+
+// basis channel c (0 value, 1..3 gradient, 4 Laplacian) of function fi from
+// its operands
+template <typename T>
+__device__ __forceinline__ T chan_eval(const FnInfo& fi, const ChanIn<T>& in, int c) {
+  if (fi.sh < 0) return T(0);
+  const int m = fi.m, kind = fi.kind, lq = fi.lq;
+  const T x = in.x, y = in.y, z = in.z, r2 = in.r2, g = in.g, g1 = in.g1, g2 = in.g2;
   T P, Px = T(0), Py = T(0), Pz = T(0);
   if (lq == 0) {
     P = T(1);
@@ -552,6 +564,13 @@ __device__ __forceinline__ T chan_value_fi(const DevWF& wf, const Ld& l, int e, 
   if (c == 1) return Px * g + P * fr * x;
   if (c == 2) return Py * g + P * fr * y;
   return Pz * g + P * fr * z;
+}
+
+// basis channel c of function fi at electron e of the tile
+template <typename T, int GS = 3>
+__device__ __forceinline__ T chan_value_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, int c) {
+  if (fi.sh < 0) return T(0);
+  return chan_eval<T>(fi, chan_load<T, GS>(wf, l, e, fi), c);
 }
 
 template <typename T, int GS = 3>
@@ -600,12 +619,15 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
           fi[u] = fn_decode(wd[u]);
           wd[u] = fn_word(l, min(k0 + 16, wf.Mpad - 16) + 4 * u + (lane >> 4));
         }
+        ChanIn<double> in[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + 4 * u + (lane >> 4);
-          a[u] = live ? chan_value_fi<double, GS>(wf, l, e, fi[u], c) : 0.0;
+          in[u] = chan_load<double, GS>(wf, l, e, fi[u]);
           b[u] = lam[(size_t)k * wf.nop + col];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = live ? chan_eval<double>(fi[u], in[u], c) : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
       }
@@ -649,20 +671,16 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
   __syncthreads();
 }
 
-// Channels 1..4 (gradient x, y, z and Laplacian) of function mu at electron e
-// of the tile, from the radial tables (GS = 3), sharing the table reads.
+// Channels 1..4 (gradient x, y, z and Laplacian) of function fi from its
+// operands (radial sums with both derivatives).
 template <typename T>
-__device__ __forceinline__ void chan_value4_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, T (&o)[4]) {
-  const int sh = fi.sh;
-  if (sh < 0) {
+__device__ __forceinline__ void chan_eval4(const FnInfo& fi, const ChanIn<T>& in, T (&o)[4]) {
+  if (fi.sh < 0) {
     o[0] = o[1] = o[2] = o[3] = T(0);
     return;
   }
   const int m = fi.m, kind = fi.kind, lq = fi.lq;
-  const T* d = (const T*)l.disp() + e * disp_stride(wf) + 4 * fi.nuc;
-  const T* gg = (const T*)l.gtab() + e * gtab_stride<3>(wf) + 3 * sh;
-  T x = d[0], y = d[1], z = d[2], r2 = d[3];
-  T g = gg[0], g1 = gg[1], g2 = gg[2];
+  const T x = in.x, y = in.y, z = in.z, r2 = in.r2, g = in.g, g1 = in.g1, g2 = in.g2;
   T P, Px = T(0), Py = T(0), Pz = T(0);
   if (lq == 0) {
     P = T(1);
@@ -693,6 +711,14 @@ __device__ __forceinline__ void chan_value4_fi(const DevWF& wf, const Ld& l, int
   o[1] = Py * g + P * fr * y;
   o[2] = Pz * g + P * fr * z;
   o[3] = lap;
+}
+template <typename T>
+__device__ __forceinline__ void chan_value4_fi(const DevWF& wf, const Ld& l, int e, const FnInfo& fi, T (&o)[4]) {
+  if (fi.sh < 0) {
+    o[0] = o[1] = o[2] = o[3] = T(0);
+    return;
+  }
+  chan_eval4<T>(fi, chan_load<T, 3>(wf, l, e, fi), o);
 }
 
 template <typename T>
@@ -728,12 +754,17 @@ __device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* ou
           fi[u] = fn_decode(wd[u]);
           wd[u] = fn_word(l, min(k0 + 16, wf.Mpad - 16) + 4 * u + (lane >> 4));
         }
+        ChanIn<double> in[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + 4 * u + (lane >> 4);
-          a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
-          if (live) chan_value4_fi<double>(wf, l, e, fi[u], a[u]);
+          in[u] = chan_load<double, 3>(wf, l, e, fi[u]);
           b[u] = lam[(size_t)k * wf.nop + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
+          if (live) chan_eval4<double>(fi[u], in[u], a[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
