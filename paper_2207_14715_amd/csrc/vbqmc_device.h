@@ -530,9 +530,22 @@ __device__ __forceinline__ ChanIn<T> chan_load(const DevWF& wf, const Ld& l, int
 // its operands
 template <typename T>
 __device__ __forceinline__ T chan_eval(const FnInfo& fi, const ChanIn<T>& in, int c) {
-  if (fi.sh < 0) return T(0);
   const int m = fi.m, kind = fi.kind, lq = fi.lq;
   const T x = in.x, y = in.y, z = in.z, r2 = in.r2, g = in.g, g1 = in.g1, g2 = in.g2;
+  if (c == 0) {
+    // the value by selects, without a branch: angular factor 1 (s); x, y, z
+    // (p); xy, yz, zx, x^2 - y^2, 2z^2 - x^2 - y^2 (d) as u v (doubled for
+    // m = 4) less the squares that apply
+    const T p1 = m == 0 ? x : (m == 1 ? y : z);
+    const T u = m == 1 ? y : ((m == 2 || m == 4) ? z : x);
+    const T v = m == 0 ? y : ((m == 1 || m == 4) ? z : x);
+    T p2 = m == 4 ? T(2) * (u * v) : u * v;
+    p2 = p2 - (m == 4 ? x * x : T(0));
+    p2 = p2 - (m >= 3 ? y * y : T(0));
+    const T P = lq == 0 ? T(1) : (lq == 1 ? p1 : p2);
+    return fi.sh < 0 ? T(0) : P * g;
+  }
+  if (fi.sh < 0) return T(0);
   T P, Px = T(0), Py = T(0), Pz = T(0);
   if (lq == 0) {
     P = T(1);
@@ -550,7 +563,6 @@ __device__ __forceinline__ T chan_eval(const FnInfo& fi, const ChanIn<T>& in, in
       default: P = T(2) * z * z - x * x - y * y; Px = T(-2) * x; Py = T(-2) * y; Pz = T(4) * z;
     }
   }
-  if (c == 0) return P * g;
   if (kind == 0) {
     if (c == 4) return P * (T(2 * (2 * lq + 3)) * g1 + T(4) * r2 * g2);
     T fr = T(2) * g1;
