@@ -280,9 +280,9 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double y = (own ? vo : 0.0) - t;
         const double rho = row_bcast(t, il);
         if (q == il) {
+          // (columns past n hold zeros: no test needed)
 #pragma unroll
-          for (int j = 0; j < NE; ++j)
-            if (j < n) xch[j] = C[j];
+          for (int j = 0; j < NE; ++j) xch[j] = C[j];
         }
         if (own) xch[16 + (q - n)] = y;
         wave_sync();
