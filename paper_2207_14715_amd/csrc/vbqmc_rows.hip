@@ -214,6 +214,15 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       group_radial<64, PT, 1>(wf, l, Rp, g0, ne);
       group_channel<64, PT, 1>(wf, l, ne, 0, Vn + g0 * VW, ne, cmap, VW, g0, kRowWalkers * Nup);
     }
+    // a move of spin s reads the first NE columns of its row against zero
+    // coefficients past n: the columns past the spin's own n + nP get zeros
+    for (int s = 0; s < 2; ++s) {
+      const int w0 = wf.sp[s].n + wf.sp[s].nP, nz = NE - w0;
+      if (wf.sp[s].n == 0 || nz <= 0) continue;
+      const int r0 = kRowWalkers * wf.sp[s].e0, nr = kRowWalkers * wf.sp[s].n;
+      for (int k = lane; k < nr * nz; k += 64) Vn[(r0 + k / nz) * VW + w0 + k % nz] = 0.0;
+    }
+    wave_sync();
     // ---- the moves, spin by spin ----
     for (int s = 0; s < 2; ++s) {
       const SpinTab& sp = wf.sp[s];
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
       double* xch = lg.S + wf.l_xch;  // [0, 16): old column il of B; [16, 32): y
       const double* X = Xj + g * N * N;
       // Every load of a move is issued unconditionally (padding slots read
-      // index 0 and meet zero coefficients), so that the loads of a step are
+      // zeros or meet zero coefficients), so that the loads of a step are
       // in flight together; the exponential of the Jastrow change, the
       // acceptance draw and the Jastrow table entries do not depend on the
       // determinant ratio and are started first.
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
         const double xr1 = X[min(q + 16, N - 1) * N + i];
         double vr[NE];
 #pragma unroll
-        for (int j = 0; j < NE; ++j) vr[j] = Vrow[j < n ? j : 0];
+        for (int j = 0; j < NE; ++j) vr[j] = Vrow[j];
         const double vo = Vrow[own ? q : 0];
         const double eU = exp(row_bcast(i < 16 ? run0 : run1, i & 15));
         double t0 = 0.0, t1 = 0.0;
