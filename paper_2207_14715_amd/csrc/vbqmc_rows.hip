@@ -188,8 +188,12 @@ __global__ __launch_bounds__(64) void k_vmc_rows(const DevWF* __restrict__ pwf, 
             const PairCoef c = en_coef(l.en() + 6 * b);
             a += pair_val(dist3(pi, l.nuc() + 4 * b), kappa, c) - pair_val(dist3(R + 3 * i, l.nuc() + 4 * b), kappa, c);
           }
-          for (int j = 0; j < N; ++j)
-            if (j != i) a += X[i * N + j];
+          // (every entry loaded, the diagonal one dropped by a select: the
+          // loads of the row are in flight together)
+          for (int j = 0; j < N; ++j) {
+            const double x = X[i * N + j];
+            a += j != i ? x : 0.0;
+          }
           if (k == 0) run0 = a;
           else run1 = a;
         }
