@@ -384,8 +384,9 @@ __device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.ns
 // accumulated in the order of its primitives, restarting at its first one,
 // and the running sum is stored at every entry, so that the loop body has no
 // branch: the last store of a shell holds its whole sum (padding entries
-// repeat the bin's last shell and add nothing).  Rows of electrons past ne get
-// zeros.
+// repeat the bin's last shell and add nothing).  Rows of electrons past ne hold
+// the sums at their (zero) displacements, which the tile passes never read (their
+// basis values are set to zero by the passes themselves).
 template <int PREC, int GS, bool STO>
 __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne) {
   // each term is rounded before it is added, in every kernel: the value rows
@@ -393,7 +394,7 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
 #pragma clang fp contract(off)
   typedef typename std::conditional<PREC == 0, double, float>::type T;
   const int e = threadIdx.x & 15;
-  const bool live = e < ne;
+  (void)ne;
   const T* de = (const T*)l.disp() + e * disp_stride(wf);
   T* o = (T*)l.gtab() + e * gtab_stride<GS>(wf);
   const uint2* sc = (const uint2*)(l.L + wf.l_rsched) + (threadIdx.x >> 4);
@@ -413,10 +414,10 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
       g2 = (first ? T(0) : g2) + a * a * ex;
     }
     T* q = o + GS * sh;
-    q[0] = live ? g : T(0);
+    q[0] = g;
     if constexpr (GS == 3) {
-      q[1] = live ? g1 : T(0);
-      q[2] = live ? g2 : T(0);
+      q[1] = g1;
+      q[2] = g2;
     }
   };
 #pragma unroll 2
