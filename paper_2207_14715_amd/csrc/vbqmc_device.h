@@ -774,11 +774,9 @@ __device__ void group_channels4(const DevWF& wf, const Ld& l, int ne, double* ou
           in[u] = chan_load<double, 3>(wf, l, e, fi[u]);
           b[u] = lam[(size_t)k * wf.nop + col];
         }
+        // (rows past ne are evaluated too: their outputs are not stored)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
-          if (live) chan_eval4<double>(fi[u], in[u], a[u]);
-        }
+        for (int u = 0; u < 4; ++u) chan_eval4<double>(fi[u], in[u], a[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
