@@ -27,11 +27,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
 # HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker,
 # FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
 # calibration: FETCH_SIZE 4570 KiB x 2.000 + WRITE_SIZE 8256 KiB x 1.000
-TRAFFIC_BYTES_PER_LAUNCH = (4548.4 * 2.0 + 8256.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (4552.9 * 2.0 + 8256.0) * 1024
 TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
 # launch): FETCH_SIZE 5592 KiB x 2.000 + WRITE_SIZE 10902 KiB x 1.000
-TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5540.4 * 2.0 + 9373.3) * 1024}
+TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5533.7 * 2.0 + 9385.7) * 1024}
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
