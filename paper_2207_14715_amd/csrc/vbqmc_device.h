@@ -375,45 +375,49 @@ __device__ __forceinline__ int disp_stride(const DevWF& wf) { return 4 * wf.nnuc
 template <int GS>
 __device__ __forceinline__ int gtab_stride(const DevWF& wf) { return (GS * wf.nshell) | 1; }
 
-// Radial sums of a row tile on one 64-lane block, from the staged radial
-// schedule: lane l takes electron l % 16 and bin l / 16 and walks the bin's
-// primitives two at a time in a loop of fixed length.  The two exponentials
-// of a step are independent (arguments past the cutoff are clamped and their
-// terms dropped afterwards), and the schedule entries and operands of the
-// next step are loaded while they are evaluated.  Each shell's sum is
-// accumulated in the order of its primitives, restarting at its first one,
-// and the running sum is stored at every entry, so that the loop body has no
+// Radial sums of a row tile on one 64-lane block, from a staged radial
+// schedule of NB bins: lane l takes electron l % (64 / NB) and bin
+// l / (64 / NB) and walks the bin's primitives two at a time in a loop of
+// fixed length (16 electrons per pass with four bins; eight bins serve a tile
+// of at most 8 rows in about half the steps).  The two exponentials of a step
+// are independent (arguments past the cutoff are clamped and their terms
+// dropped afterwards), and the schedule entries and operands of the next step
+// are loaded while they are evaluated.  Each shell's sum is accumulated in the
+// order of its primitives, restarting at its first one, whatever the bin, and
+// the running sum is stored at every entry, so that the loop body has no
 // branch: the last store of a shell holds its whole sum (padding entries
-// repeat the bin's last shell and add nothing).  Rows of electrons past ne hold
-// the sums at their (zero) displacements, which the tile passes never read (their
-// basis values are set to zero by the passes themselves).
-template <int PREC, int GS, bool STO>
-__device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne) {
+// repeat the bin's last shell and add nothing).  Rows past the electrons of
+// the pass hold sums the tile passes never read (their basis values are set
+// to zero, or their outputs dropped, by the passes themselves).
+template <int PREC, int GS, bool STO, int NB>
+__device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l) {
   // each term is rounded before it is added, in every kernel: the value rows
   // of an inverse refresh and of the local energy then agree bit for bit
 #pragma clang fp contract(off)
   typedef typename std::conditional<PREC == 0, double, float>::type T;
-  const int e = threadIdx.x & 15;
-  (void)ne;
+  constexpr int EP = 64 / NB;  // electrons per pass
+  const int e = threadIdx.x & (EP - 1);
   const T* de = (const T*)l.disp() + e * disp_stride(wf);
   T* o = (T*)l.gtab() + e * gtab_stride<GS>(wf);
-  const uint2* sc = (const uint2*)(l.L + wf.l_rsched) + (threadIdx.x >> 4);
+  const unsigned* sc = (const unsigned*)(l.L + (NB == 4 ? wf.l_rsched : wf.l_rsched8)) + (threadIdx.x / EP);
+  const int len = NB == 4 ? wf.rsched_len : wf.rsched_len8;
   const double* pe = l.pe();
   const double* pc = l.pc();
   const double* etab = l.L + wf.l_etab;
-  uint2 n0 = sc[0], n1 = sc[4], m0 = sc[8], m1 = sc[12];
-  double a0 = pe[n0.x & kRsPrim], c0 = pc[n0.x & kRsPrim];
-  double a1 = pe[n1.x & kRsPrim], c1 = pc[n1.x & kRsPrim];
-  T d0 = de[4 * (n0.y >> 16) + 3], d1 = de[4 * (n1.y >> 16) + 3];
+  auto nuc = [](unsigned f) { return (int)((f >> kRsNucShift) & kRsNucMask); };
+  unsigned n0 = sc[0], n1 = sc[NB], m0 = sc[2 * NB], m1 = sc[3 * NB];
+  double a0 = pe[n0 & kRsPrim], c0 = pc[n0 & kRsPrim];
+  double a1 = pe[n1 & kRsPrim], c1 = pc[n1 & kRsPrim];
+  T d0 = de[4 * nuc(n0) + 3], d1 = de[4 * nuc(n1) + 3];
   T g = 0, g1 = 0, g2 = 0;
-  auto add = [&](T ex, T a, unsigned f, unsigned sh) {
+  auto add = [&](T ex, T a, unsigned f) {
     const bool first = f & kRsFirst;
     g = (first ? T(0) : g) + ex;
     if constexpr (GS == 3) {
       g1 = (first ? T(0) : g1) - a * ex;
       g2 = (first ? T(0) : g2) + a * a * ex;
     }
-    T* q = o + GS * sh;
+    T* q = o + GS * (int)((f >> kRsShift) & kRsShMask);
     q[0] = g;
     if constexpr (GS == 3) {
       q[1] = g1;
@@ -421,19 +425,19 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
     }
   };
 #pragma unroll 2
-  for (int j = 0; j < wf.rsched_len; j += 2) {
-    const unsigned f0 = n0.x, f1 = n1.x, h0 = n0.y & 0xFFFFu, h1 = n1.y & 0xFFFFu;
+  for (int j = 0; j < len; j += 2) {
+    const unsigned f0 = n0, f1 = n1;
     const T A0 = (T)a0, C0 = (T)c0, R0 = d0, A1 = (T)a1, C1 = (T)c1, R1 = d1;
     n0 = m0;
     n1 = m1;
-    m0 = sc[4 * (j + 4)];
-    m1 = sc[4 * (j + 5)];
-    a0 = pe[n0.x & kRsPrim];
-    c0 = pc[n0.x & kRsPrim];
-    a1 = pe[n1.x & kRsPrim];
-    c1 = pc[n1.x & kRsPrim];
-    d0 = de[4 * (n0.y >> 16) + 3];
-    d1 = de[4 * (n1.y >> 16) + 3];
+    m0 = sc[NB * (j + 4)];
+    m1 = sc[NB * (j + 5)];
+    a0 = pe[n0 & kRsPrim];
+    c0 = pc[n0 & kRsPrim];
+    a1 = pe[n1 & kRsPrim];
+    c1 = pc[n1 & kRsPrim];
+    d0 = de[4 * nuc(n0) + 3];
+    d1 = de[4 * nuc(n1) + 3];
     T t0 = A0 * R0, t1 = A1 * R1;
     if constexpr (STO) {
       if (f0 & kRsSto) t0 = A0 * (T)sqrt(R0);
@@ -442,8 +446,8 @@ __device__ __forceinline__ void radial_bins(const DevWF& wf, const Ld& l, int ne
     T ex0, ex1;
     exp_neg2<T>(fmin(t0, T(64)), fmin(t1, T(64)), etab, ex0, ex1);
     const T x0 = C0 * ex0, x1 = C1 * ex1;
-    add(((f0 & kRsLive) && t0 < T(50)) ? x0 : T(0), A0, f0, h0);
-    add(((f1 & kRsLive) && t1 < T(50)) ? x1 : T(0), A1, f1, h1);
+    add(((f0 & kRsLive) && t0 < T(50)) ? x0 : T(0), A0, f0);
+    add(((f1 & kRsLive) && t1 < T(50)) ? x1 : T(0), A1, f1);
   }
 }
 
@@ -468,8 +472,13 @@ __device__ void group_radial(const DevWF& wf, const Ld& l, const double* Rsrc, i
   __syncthreads();
   if constexpr (NT == 64) {
     if (wf.rsched_len > 0 && wf.l_rsched < wf.timg_len) {
-      if (wf.rsched_sto) radial_bins<PREC, GS, true>(wf, l, ne);
-      else radial_bins<PREC, GS, false>(wf, l, ne);
+      if (ne <= 8 && wf.rsched_len8 > 0) {
+        if (wf.rsched_sto) radial_bins<PREC, GS, true, 8>(wf, l);
+        else radial_bins<PREC, GS, false, 8>(wf, l);
+      } else {
+        if (wf.rsched_sto) radial_bins<PREC, GS, true, 4>(wf, l);
+        else radial_bins<PREC, GS, false, 4>(wf, l);
+      }
       __syncthreads();
       return;
     }

@@ -130,8 +130,8 @@ struct vbqmc_ctx {
   int N = 0, nup = 0, ndn = 0, nnuc = 0, M = 0, Mpad = 0, norb = 0, nop = 0, nstruct = 0, nshell = 0;
   std::vector<double> nuc, en, pexp, pcoef, lam, c;
   std::vector<int> shtab, fnmap, pshell;
-  std::vector<unsigned> rsched;  // radial schedule of 64-lane blocks, [rows + 2][4][2]
-  int rsched_len = 0;
+  std::vector<unsigned> rsched;  // radial schedules of 64-lane blocks: 4 bins, then 8 bins
+  int rsched_len = 0, rsched_len8 = 0, rsched8_off = 0;
   double ee[8];
   double kappa = 0;
   SpinHost sp[2];
@@ -224,56 +224,73 @@ struct LdsAlloc {
   int ints(int n) { return (*this)((n + 1) / 2); }
 };
 
-// Radial schedule of the 64-lane blocks.  Lane l takes electron l % 16 of a
-// row tile and bin l / 16; the shells are dealt to the four bins longest
-// first, each to the bin with the fewest primitives so far, so every lane
-// walks about a quarter of the primitives in one fixed-length loop.  A bin
-// lists its shells' primitives in shell order (the order of the contraction
-// sums) and flags the first primitive of each shell.  It is padded to the
-// longest bin rounded up to even, plus four rows read ahead, with empty
-// entries (no primitive term) of its last shell, which store that shell's sum
-// again; with fewer than four shells there is no schedule.
-void build_radial_schedule(vbqmc_ctx* x) {
-  x->rsched.clear();
-  x->rsched_len = 0;
-  const int nprim = (int)x->pexp.size();
-  if (nprim >= (int)kRsPrim || x->nshell > 0xFFFF || x->nnuc > 0xFFFF || x->nshell < 4) return;
+// Radial schedules of the 64-lane blocks.  With NB bins, lane l takes
+// electron l % (64 / NB) of a row tile and bin l / (64 / NB); the shells are
+// dealt to the bins longest first, each to the bin with the fewest primitives
+// so far, so every lane walks about 1/NB of the primitives in one
+// fixed-length loop.  A bin lists its shells' primitives in shell order (the
+// order of the contraction sums) and flags the first primitive of each shell.
+// It is padded to the longest bin rounded up to even, plus four rows read
+// ahead, with empty entries (no primitive term) of its last shell, which store
+// that shell's sum again.  Returns the length (0: fewer than NB shells, no
+// schedule).
+static int deal_radial_bins(const vbqmc_ctx* x, int NB, std::vector<unsigned>& out) {
+  out.clear();
+  if (x->nshell < NB) return 0;
   std::vector<int> order(x->nshell);
   for (int s = 0; s < x->nshell; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return x->shtab[8 * a + 5] > x->shtab[8 * b + 5]; });
-  std::vector<int> bins[4];
-  int load[4] = {0, 0, 0, 0};
+  std::vector<std::vector<int>> bins(NB);
+  std::vector<int> load(NB, 0);
   for (int s : order) {
     int b = 0;
-    for (int k = 1; k < 4; ++k)
+    for (int k = 1; k < NB; ++k)
       if (load[k] < load[b]) b = k;
     bins[b].push_back(s);
     load[b] += x->shtab[8 * s + 5];
   }
   int L = 0;
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NB; ++b) {
     std::sort(bins[b].begin(), bins[b].end());
     L = std::max(L, load[b]);
   }
   L += L & 1;  // walked two entries at a time, with two steps loaded ahead
-  x->rsched.assign((size_t)8 * (L + 4), 0u);
-  for (int b = 0; b < 4; ++b) {
+  out.assign((size_t)NB * (L + 4), 0u);
+  auto where = [&](int s) { return ((unsigned)s << kRsShift) | ((unsigned)x->shtab[8 * s] << kRsNucShift); };
+  for (int b = 0; b < NB; ++b) {
     int j = 0;
     for (int s : bins[b]) {
       const int* si = &x->shtab[8 * s];
       for (int k = 0; k < si[5]; ++k, ++j) {
-        unsigned f = (unsigned)(si[4] + k) | kRsLive;
+        unsigned f = (unsigned)(si[4] + k) | where(s) | kRsLive;
         if (si[1] == 1) f |= kRsSto;
         if (k == 0) f |= kRsFirst;
-        x->rsched[(size_t)2 * (4 * j + b)] = f;
-        x->rsched[(size_t)2 * (4 * j + b) + 1] = (unsigned)s | ((unsigned)si[0] << 16);
+        out[(size_t)NB * j + b] = f;
       }
     }
-    const int s = bins[b].back();
-    for (; j < L + 4; ++j) x->rsched[(size_t)2 * (4 * j + b) + 1] = (unsigned)s | ((unsigned)x->shtab[8 * s] << 16);
+    for (; j < L + 4; ++j) out[(size_t)NB * j + b] = where(bins[b].back());
   }
-  x->rsched_len = L;
+  return L;
+}
+
+void build_radial_schedule(vbqmc_ctx* x) {
+  x->rsched.clear();
+  x->rsched_len = x->rsched_len8 = 0;
+  x->rsched8_off = 0;
+  const int nprim = (int)x->pexp.size();
+  if (nprim > (int)kRsPrim + 1 || x->nshell > (int)kRsShMask + 1 || x->nnuc > (int)kRsNucMask + 1) return;
+  std::vector<unsigned> s4, s8;
+  const int L4 = deal_radial_bins(x, 4, s4);
+  if (L4 == 0) return;
+  const int L8 = deal_radial_bins(x, 8, s8);
+  x->rsched = s4;
+  x->rsched_len = L4;
+  if (L8 > 0) {
+    x->rsched8_off = (int)s4.size();  // a multiple of 4 words: whole doubles
+    x->rsched.insert(x->rsched.end(), s8.begin(), s8.end());
+    x->rsched_len8 = L8;
+  }
 }
 
 // Sweep kernel: the tables without the orbital coefficients (read from global
@@ -857,6 +874,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // image: a layout stages the prefix it needs (the row kernel up to the
   // schedule, the sweeps and the tile kernel only the tables before it)
   wf.l_rsched = ilds((int)x->rsched.size());
+  wf.l_rsched8 = wf.l_rsched + x->rsched8_off / 2;
+  wf.rsched_len8 = x->rsched_len8;
   wf.l_psh = ilds(wf.nprim);
   int lam_elems = x->Mpad * x->nop;
   int lam_doubles = wf.precision == 0 ? lam_elems : (wf.precision == 1 ? (lam_elems + 1) / 2 : (lam_elems + 3) / 4);

@@ -8,9 +8,10 @@
 namespace vbqmc {
 
 constexpr int kGroup = 16;     // electrons per MFMA row tile
-// radial schedule entry flags (first int of an entry; the primitive index
-// takes the low 24 bits)
-constexpr unsigned kRsPrim = 0x00FFFFFFu, kRsSto = 1u << 24, kRsFirst = 1u << 25, kRsLive = 1u << 26;
+// radial schedule entry (one 32-bit word): primitive in bits 0-10, shell in
+// bits 11-20, nucleus in bits 21-28, then the flags
+constexpr unsigned kRsPrim = 0x7FFu, kRsShift = 11, kRsShMask = 0x3FFu, kRsNucShift = 21, kRsNucMask = 0xFFu;
+constexpr unsigned kRsSto = 1u << 29, kRsFirst = 1u << 30, kRsLive = 1u << 31;
 constexpr int kChunk = 16;     // basis functions are padded to a multiple of this
 constexpr int kMaxExc = 3;     // columns a spin determinant may differ from its reference
 constexpr int kMaxSpin = 64;   // electrons per spin
@@ -70,10 +71,12 @@ struct DevWF {
   int lam_in_lds;
   int l_fn, l_sh, l_pe, l_pc, l_psh, l_nuc, l_en, l_lam;
   int l_ref[2], l_porb[2], l_ui[2], l_wrow[2], l_woth[2], l_wcoef[2], l_srow, l_slu, l_slc;
-  // radial schedule of a 64-lane block: the shells dealt to four bins, entry j
-  // of bin b at [j][b] (two ints: primitive | flags, shell | nucleus << 16);
-  // rsched_len rows (even) plus four padding rows, none when rsched_len is 0
-  int l_rsched, rsched_len, rsched_sto;
+  // radial schedules of a 64-lane block: the shells dealt to four bins (16
+  // electrons per pass) and to eight bins (8 electrons per pass, for a tile of
+  // at most 8 rows), entry j of bin b at [j][b] (one word, see kRsPrim);
+  // rsched_len / rsched_len8 rows (even) plus four padding rows each, none
+  // when the length is 0
+  int l_rsched, rsched_len, rsched_sto, l_rsched8, rsched_len8;
   int l_etab;  // 2^(j/64), j = 0..63, for the exponentials of the radial sums
   // walker state and scratch
   int l_R, l_B[2], l_T[2], l_PP[2];
