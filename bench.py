@@ -31,7 +31,7 @@ TRAFFIC_BYTES_PER_LAUNCH = (4552.9 * 2.0 + 8256.0) * 1024
 TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
 # launch): FETCH_SIZE 5592 KiB x 2.000 + WRITE_SIZE 10902 KiB x 1.000
-TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5533.7 * 2.0 + 9385.7) * 1024}
+TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5619.0 * 2.0 + 9895.7) * 1024}
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
