@@ -94,6 +94,31 @@ def test_vmc_f2_sherman_morrison(lib, oracle_mod, lanes):
     _check_vmc(ref, acc, R, 12)
 
 
+def _f2_with_slater_shells():
+    """The F2-shaped system with the s and p shells of the second atom made
+    Slater shells (exponents 0.6-4, same primitive counts): more than eight
+    shells, so the row kernel's radial sums take the Slater branch of both
+    radial schedules (four bins for full row tiles, eight for the last one)."""
+    sysd = S.f2_shaped()
+    rng = np.random.default_rng(77)
+    shells = []
+    for sh in sysd["shells"]:
+        sh = dict(sh)
+        if sh["center"] == 1 and sh["l"] <= 1:
+            n = len(sh["exps"])
+            sh["kind"] = "sto"
+            sh["exps"] = sorted(rng.uniform(0.6, 4.0, size=n).tolist(), reverse=True)
+            sh["coefs"] = rng.uniform(0.2, 1.0, size=n).tolist()
+        shells.append(sh)
+    return dict(sysd, shells=shells, name="f2_slater_b")
+
+
+@pytest.mark.parametrize("lanes", ["rows", 32])
+def test_vmc_f2_with_slater_shells(lib, oracle_mod, lanes):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, _f2_with_slater_shells(), 61, 8, 0.3, False, lanes=lanes)
+    _check_vmc(ref, acc, R, 8)
+
+
 @pytest.mark.parametrize("lanes", [32, 64])
 def test_vmc_sweep_then_measure_equals_advance(lib, lanes):
     # a step of vbqmc_vmc_advance is a sweep followed by a measurement: the
