@@ -172,7 +172,10 @@ int vbqmc_get_info(const vbqmc_ctx* ctx, vbqmc_info_t* out);
 /* Replace the variational parameters p = [c (n_structures) | lambda
  * (n_orbitals*M, row-major) | b_anti, b_par, b3..b6 | per nucleus a1..a6]
  * (Sec. 2.2, Eq. PsiJVBp with the orbital coefficients varied directly).
- * p is [host][n_params].  Existing walker states become stale: re-run
+ * p is [host][n_params].  The call first waits for all work queued on the
+ * device (any stream), then replaces the context's device tables, so work
+ * queued before it used the old parameters and work queued after it uses the
+ * new ones.  Existing walker states become stale: re-run
  * vbqmc_walkers_init. */
 int vbqmc_set_params(vbqmc_ctx* ctx, const double* p);
 int vbqmc_get_params(const vbqmc_ctx* ctx, double* p);
@@ -262,12 +265,16 @@ typedef struct {
  * drift-diffusion single-electron moves r' = r + tau v + sqrt(tau) chi with
  * v = grad_i ln|Psi|, accepted with min(1, |Psi'/Psi|^2 G(r<-r')/G(r'<-r)),
  * rejected outright if the sign of Psi changes; then weight
- * w = exp(-tau ((E_L + E_L')/2 - E_T)) with E_L clipped to E_T +- 10/sqrt(tau),
- * floor(w + u) copies (at most 3, children of weight 1, parents' order kept,
- * compaction on the device) and E_T = E_est - (0.1/tau) ln(W/W_target) with
- * E_est the running weighted mean of E_L of this call.  Random numbers as VMC
- * plus purpose 2 (branching, electron index N); the walker index is the slot
- * after compaction.  states: two [dev] buffers of capacity records; the
+ * w = exp(-tau ((E_L + E_L')/2 - E_T)) with E_L clipped to E_T +- sqrt(N/tau);
+ * population control: if the expected next population sum w lies outside
+ * [0.95, 1.05] W_target, every weight of the step is scaled by the one factor
+ * f that brings the sum to the nearer bound (the step's logged E_T is then
+ * E_T + ln(f)/tau); floor(w + u) copies (at most 3, children of weight 1,
+ * parents' order kept, compaction on the device); next
+ * E_T = E_est - (0.1/tau) ln(W/W_target) with E_est the running weighted mean
+ * of the clipped E_L of this call.  Random numbers as VMC plus purpose 2
+ * (branching, electron index N); the walker index is the slot after
+ * compaction.  states: two [dev] buffers of capacity records; the
  * population lives in states[0] on entry and on return.  W_io [host] in/out;
  * e_trial_io [host] in/out.  workspace [dev] of vbqmc_dmc_workspace_bytes.
  * Error EPOPULATION if the population reaches 0 or exceeds capacity (the

@@ -741,10 +741,18 @@ int orc_vmc(void* h, int W, double* R, int nsteps, uint64_t seed, uint32_t step0
 // Fixed-node DMC (Sec. 2.3.2) with per-electron drift-diffusion moves,
 // Metropolis acceptance with the drift-diffusion Green's-function ratio,
 // node-crossing rejection, weights exp(-tau (E_L + E_L')/2 - E_T)) with E_L
-// clipped to E_T +- 10/sqrt(tau), birth/death by floor(w + u) copies (at most
-// 3, children of weight 1, kept in parent order) and trial-energy feedback
-// E_T = E_est - (0.1 / tau) ln(W / W_target), E_est being the running
-// weighted mean of E_L over the steps of this call.
+// clipped to E_T +- sqrt(N / tau) (the size-consistent form of cut-off of Zen
+// et al., Phys. Rev. B 93, 241118 (2016), with their prefactor 0.2 widened to
+// 1 for trial functions without cusps), birth/death by floor(w + u) copies
+// (at most 3, children of weight 1, kept in parent order) and trial-energy
+// feedback E_T = E_est - (0.1 / tau) ln(W / W_target), E_est being the running
+// weighted mean of the clipped E_L over the steps of this call (so that a few
+// walkers with extreme E_L cannot drag E_T away).  Population control: when
+// the expected next population sum_w w falls outside [0.95, 1.05] W_target,
+// every weight of the step is scaled by the one factor f that brings the sum
+// to the nearer bound (the same as using E_T + ln(f) / tau in that step's
+// weights), so the birth/death population stays within +-10 % of W_target up
+// to the rounding noise of floor(w + u).
 // R: [capacity][N][3]; eloc_io: [capacity] local energies of the walkers;
 // per-step outputs (length nsteps): pop (walkers before branching),
 // wsum = sum w, wesum = sum w E_L, etrial (E_T used in the step),
@@ -758,10 +766,11 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
   int W = *W_io;
   double ET = *etrial_io;
   double run_num = 0, run_den = 0;
-  std::vector<double> Rnew((size_t)capacity * N * 3), Enew(capacity), wts(capacity);
+  std::vector<double> Rnew((size_t)capacity * N * 3), Enew(capacity), wts(capacity), ubr(capacity);
   std::vector<int> ncopy(capacity);
   std::vector<double> nacc(capacity), nprop(capacity);
-  const double cap = 10.0 / std::sqrt(tau);
+  const double cap = std::sqrt((double)N / tau);
+  std::vector<double> Eclip(capacity);
   for (int st = 0; st < nsteps; ++st) {
     uint32_t step = step0 + (uint32_t)st;
     int bad = 0;
@@ -809,21 +818,30 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
       double en = std::min(std::max(full.eloc, ET - cap), ET + cap);
       wts[w] = std::exp(-tau * (0.5 * (eo + en) - ET));
       Enew[w] = full.eloc;
-      double u = branch_uniform(seed, (uint32_t)w, step, N);
-      ncopy[w] = std::min(3, (int)std::floor(wts[w] + u));
+      Eclip[w] = en;
+      ubr[w] = branch_uniform(seed, (uint32_t)w, step, N);
     }
     if (bad) return -1;
-    double sw = 0, swe = 0, na = 0, np = 0;
+    // population control: one factor on every weight of the step
+    double sw_raw = 0;
+    for (int w = 0; w < W; ++w) sw_raw += wts[w];
+    double f = 1.0;
+    if (sw_raw > 1.05 * W_target) f = 1.05 * W_target / sw_raw;
+    else if (sw_raw < 0.95 * W_target) f = 0.95 * W_target / sw_raw;
+    double sw = 0, swe = 0, swc = 0, na = 0, np = 0;
     for (int w = 0; w < W; ++w) {
+      wts[w] = f * wts[w];
+      ncopy[w] = std::min(3, (int)std::floor(wts[w] + ubr[w]));
       sw += wts[w];
       swe += wts[w] * Enew[w];
+      swc += wts[w] * Eclip[w];
       na += nacc[w];
       np += nprop[w];
     }
     pop[st] = W;
     wsum[st] = sw;
     wesum[st] = swe;
-    etrial[st] = ET;
+    etrial[st] = ET + std::log(f) / tau;
     acc[st] = na;
     prop[st] = np;
     // stable compaction of the copies
@@ -838,7 +856,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
       }
     std::copy(Rnew.begin(), Rnew.begin() + (size_t)Wn * N * 3, R);
     W = Wn;
-    run_num += swe;
+    run_num += swc;
     run_den += sw;
     ET = run_num / run_den - (0.1 / tau) * std::log((double)W / (double)W_target);
   }

@@ -395,16 +395,19 @@ def _jvb_function():
 
         forward: sets p on the context and runs vbqmc_evaluate.
         backward: runs the hand-written adjoint (vbqmc_param_grad, which
-        recomputes every determinant inverse from R) and contracts the
-        per-walker derivatives with the upstream gradients by the library's
-        fixed-order walker reduction."""
+        recomputes every determinant inverse from R) at the p this forward
+        received, whatever the context holds by then (it is restored after),
+        and contracts the per-walker derivatives with the upstream gradients
+        by the library's fixed-order walker reduction."""
 
         @staticmethod
         def forward(ctx_, p, R, vbctx):
-            vbctx.set_params(p.detach().double().cpu().numpy())
+            p_host = p.detach().double().cpu().numpy().copy()
+            vbctx.set_params(p_host)
             out = vbctx.evaluate(R, want=("eloc",))
             ctx_.save_for_backward(R)
             ctx_.vb = vbctx
+            ctx_.p_host = p_host
             ctx_.p_device = p.device
             return out["logabs"], out["eloc"]
 
@@ -412,7 +415,15 @@ def _jvb_function():
         def backward(ctx_, g_logpsi, g_eloc):
             (R,) = ctx_.saved_tensors
             vb = ctx_.vb
-            dl, de = vb.param_grad(R)
+            held = vb.get_params()
+            swap = not np.array_equal(held, ctx_.p_host)
+            if swap:
+                vb.set_params(ctx_.p_host)
+            try:
+                dl, de = vb.param_grad(R)
+            finally:
+                if swap:
+                    vb.set_params(held)
             gp = None
             if g_logpsi is not None:
                 gp = vb.reduce_walkers(dl, g_logpsi.double().contiguous())

@@ -1472,4 +1472,26 @@ __device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, doub
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// DMC branching inputs of walker w (Sec. 2.3.2, birth/death): the weight
+// exp(-tau ((E_L + E_L') / 2 - E_T)) with both energies clipped to
+// E_T +- sqrt(N / tau), its products with E_L' and with the clipped E_L', and
+// the branching draw (purpose 2, electron index N).  The copy count
+// floor(f w + u) waits for the step's population-control factor f.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dmc_branch_inputs(const DmcBranch& br, int64_t w, bool bad, double E_old, double En,
+                                                  double ET, double tau, int N, uint64_t seed, uint32_t step) {
+  const double cap = sqrt((double)N / tau);
+  const double eo = fmin(fmax(E_old, ET - cap), ET + cap);
+  const double en = fmin(fmax(En, ET - cap), ET + cap);
+  const double wt = exp(-tau * (0.5 * (eo + en) - ET));
+  double ub, dummy;
+  philox_pair(seed, (uint32_t)w, step, 4u * (uint32_t)N + 2u, 0u, ub, dummy);
+  br.w[w] = bad ? NAN : wt;
+  br.we[w] = bad ? NAN : wt * En;
+  br.wc[w] = bad ? NAN : wt * en;
+  br.ub[w] = ub;
+  br.nc[w] = bad ? -1 : 0;
+}
+
 }  // namespace vbqmc

@@ -846,13 +846,12 @@ __global__ __launch_bounds__(64) void k_dmcb_eterm(const DevWF* __restrict__ pwf
   }
 }
 
-// E_L = -1/2 sum_i T_i + V + V_nn, the branching weight
-// w = exp(-tau ((E_L + E_L') / 2 - E_T)) (E_L clipped to E_T +- 10 / sqrt(tau))
-// and floor(w + u) copies, as at the end of k_dmc_step.
+// E_L = -1/2 sum_i T_i + V + V_nn and the branching inputs of the walker, as
+// at the end of k_dmc_step.
 __global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ pwf, double* state,
                                                      const double* ctrl, uint64_t seed, uint32_t step, double tau,
-                                                     const double* ek, const double* ep, double* wts, double* wel,
-                                                     int* ncopy, int only_eloc) {
+                                                     const double* ek, const double* ep, DmcBranch br,
+                                                     int only_eloc) {
   const DevWF& wf = *pwf;
   const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t W = (int64_t)ctrl[DC_W];
@@ -866,16 +865,7 @@ __global__ __launch_bounds__(256) void k_dmcb_weight(const DevWF* __restrict__ p
     sc[SC_ELOC] = En;
     return;
   }
-  const double cap = 10.0 / sqrt(tau);
-  const double eo = fmin(fmax(E_old, ET - cap), ET + cap);
-  const double en = fmin(fmax(En, ET - cap), ET + cap);
-  const double wt = exp(-tau * (0.5 * (eo + en) - ET));
-  double ub, dummy;
-  philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 2u, 0u, ub, dummy);
-  const int nc = bad ? -1 : min(3, (int)floor(wt + ub));
-  wts[w] = bad ? NAN : wt;
-  wel[w] = bad ? NAN : wt * En;
-  ncopy[w] = nc;
+  dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, wf.N, seed, step);
   sc[SC_ELOC] = En;
 }
 
@@ -954,8 +944,8 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
 // and E_L, and no weight is formed.
 hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
                               double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
-                              double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
-                              int rebuild, hipStream_t s) {
+                              double* Vp, double* ek, double* ep, const DmcBranch& br, int rebuild,
+                              hipStream_t s) {
   const unsigned tiles = (unsigned)((cap + kGroup - 1) / kGroup);
   static size_t cur[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   auto rows = [&](auto kern, int prec, int mi, int i) -> hipError_t {
@@ -996,7 +986,7 @@ hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dw
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dmcb_weight, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, dwf, state, ctrl, seed,
-                     step, tau, ek, ep, wts, wel, ncopy, rebuild);
+                     step, tau, ek, ep, br, rebuild);
   return hipGetLastError();
 }
 

@@ -29,18 +29,17 @@ hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
                             double step_size, double* es, double* e2s, double* na, double* el, double* sij,
                             hipStream_t s);
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
-                           uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
+                           uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s);
+hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
+                           int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
+                           double* etrial, double* lacc, double* lprop, const double* src, double* dst, int rec_len,
                            hipStream_t s);
-hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, const int* ncopy, const double* nacc,
-                           int* offs, int64_t cap, int N, int st, double tau, double W_target, double* pop,
-                           double* wsum, double* wesum, double* etrial, double* lacc, double* lprop,
-                           const double* src, double* dst, int rec_len, hipStream_t s);
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s);
 hipError_t launch_dmcb_finish(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds,
                               double* state, double* ctrl, int64_t cap, uint64_t seed, uint32_t step, double tau,
-                              double* Vp, double* ek, double* ep, double* wts, double* wel, int* ncopy,
+                              double* Vp, double* ek, double* ep, const DmcBranch& br,
                               int rebuild, hipStream_t s);
 hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_rows, size_t rows_lds, double* state,
                             double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
@@ -1110,6 +1109,9 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
 
 int vbqmc_set_params(vbqmc_ctx* x, const double* p) {
   if (!x || !p) return VBQMC_EINVAL;
+  // kernels still running on any stream may read the tables replaced below
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hipfail(x, e, "set_params: device synchronisation");
   int k = 0;
   for (int I = 0; I < x->nstruct; ++I) x->c[I] = p[k++];
   for (size_t q = 0; q < x->lam.size(); ++q) x->lam[q] = p[k++];
@@ -1234,10 +1236,10 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
 }
 
-// DMC workspace: ctrl (8 doubles) | wts, wel, nacc [cap] | ncopy [cap] |
+// DMC workspace: ctrl (8 doubles) | w, we, wc, ub, nacc [cap] | ncopy [cap] |
 // offs [cap+1] | (electron-major kernels) P, V [cap][3], Vp [cap][4][nop], ek, ep [cap]
 namespace {
-size_t dmc_ws_base(int64_t cap) { return 64 + 3 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
+size_t dmc_ws_base(int64_t cap) { return 64 + 5 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
 }  // namespace
 
 int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, size_t* bytes) {
@@ -1265,10 +1267,13 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   hipStream_t s = (hipStream_t)stream;
   char* p = (char*)ws;
   double* ctrl = (double*)p; p += 64;
-  double* wts = (double*)p; p += cap * 8;
-  double* wel = (double*)p; p += cap * 8;
+  DmcBranch br;
+  br.w = (double*)p; p += cap * 8;
+  br.we = (double*)p; p += cap * 8;
+  br.wc = (double*)p; p += cap * 8;
+  br.ub = (double*)p; p += cap * 8;
   double* nacc = (double*)p; p += cap * 8;
-  int* ncopy = (int*)p; p += cap * 4;
+  br.nc = (int*)p; p += cap * 4;
   int* offs = (int*)p;
   double h[DC_COUNT] = {0};
   h[DC_W] = (double)W;
@@ -1288,7 +1293,7 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   // the orbital-gradient rows the drift of the first moves reads)
   if (x->dmc_kernel == 2)
     e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, (size_t)dmcb_layout(x).lds_tile_doubles * 8, cur, ctrl, cap,
-                           seed, 0, tau, Vpw, ekw, epw, wts, wel, ncopy, 1, s);
+                           seed, 0, tau, Vpw, ekw, epw, br, 1, s);
   else
     e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
                         nullptr, nullptr, cur, s);
@@ -1302,12 +1307,12 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
                              Vpw, nacc, s);
       if (e == hipSuccess)
         e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, seed, step, tau, Vpw, ekw,
-                               epw, wts, wel, ncopy, 0, s);
+                               epw, br, 0, s);
     } else {
-      e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s);
+      e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, br, nacc, s);
     }
     if (e != hipSuccess) return hipfail(x, e, "dmc: step");
-    e = launch_dmc_tail(ctrl, wts, wel, ncopy, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
+    e = launch_dmc_tail(ctrl, br, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
                         lg->wesum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
     if (e != hipSuccess) return hipfail(x, e, "dmc: branching");
     std::swap(cur, oth);

@@ -114,4 +114,16 @@ enum {
   DC_W = 0, DC_ET, DC_RUN_NUM, DC_RUN_DEN, DC_ERR, DC_WNEW, DC_ERRSTEP, DC_COUNT = 8
 };
 
+// Per-walker branching inputs of one DMC step, in the caller's workspace:
+// weight w (before population control), w E_L, w E_L clipped, the branching
+// draw u, and the copy count (-1 for an invalid walker; set by the scan once
+// the population-control factor of the step is known).
+struct DmcBranch {
+  double* w;
+  double* we;
+  double* wc;
+  double* ub;
+  int* nc;
+};
+
 }  // namespace vbqmc

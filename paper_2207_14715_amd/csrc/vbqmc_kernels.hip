@@ -608,8 +608,8 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
 
 template <int NT, int PREC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_dmc_step(const DevWF* __restrict__ pwf, double* state, const double* ctrl, int nsteps_done,
-                                                 uint64_t seed, uint32_t step, double tau, double* wts,
-                                                 double* wel, int* ncopy, double* nacc) {
+                                                 uint64_t seed, uint32_t step, double tau, DmcBranch br,
+                                                 double* nacc) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   int64_t W = (int64_t)ctrl[DC_W];
@@ -680,17 +680,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (!bad) local_energy<NT, PREC>(wf, l, gc);
   __syncthreads();
   if (threadIdx.x == 0) {
-    double En = bad ? NAN : sc[SC_ELOC];
-    double cap = 10.0 / sqt;
-    double eo = fmin(fmax(E_old, ET - cap), ET + cap);
-    double en = fmin(fmax(En, ET - cap), ET + cap);
-    double wt = exp(-tau * (0.5 * (eo + en) - ET));
-    double ub, dummy;
-    philox_pair(seed, (uint32_t)w, step, 4u * wf.N + 2u, 0u, ub, dummy);
-    int nc = bad ? -1 : min(3, (int)floor(wt + ub));
-    wts[w] = bad ? NAN : wt;
-    wel[w] = bad ? NAN : wt * En;
-    ncopy[w] = nc;
+    const double En = bad ? NAN : sc[SC_ELOC];
+    dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, wf.N, seed, step);
     nacc[w] = na;
     if (bad) sc[SC_FLAGS] = 1.0;
   }
@@ -698,34 +689,65 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   store_record<NT>(wf, l, rec);
 }
 
-// Single-workgroup scan / reduction / trial-energy update of one DMC step.
-// Fixed summation order, so the result is independent of timing.
-__global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* wts, const double* wel,
-                                                   const int* ncopy, const double* nacc, int* offs,
+// Single-workgroup population control, scan, reduction and trial-energy
+// update of one DMC step (Sec. 2.3.2).  Pass 1 sums the weights; if the
+// expected next population sum_w w lies outside [0.95, 1.05] W_target, every
+// weight is scaled by the one factor f that brings the sum to the nearer
+// bound (the step then ran at E_T + ln(f) / tau, which is what the log
+// records).  Pass 2 forms the copy counts min(3, floor(f w + u)), their
+// exclusive scan and the sums of the log.  Each thread sums a contiguous
+// chunk and the chunks are combined by a fixed tree, so the results do not
+// depend on timing.
+__global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, const double* nacc, int* offs,
                                                    int64_t capacity, int N, int st, double tau,
                                                    double W_target, double* pop, double* wsum,
                                                    double* wesum, double* etrial, double* lacc, double* lprop) {
-  __shared__ double sw[1024], swe[1024], sa[1024];
+  __shared__ double sw[1024], swe[1024], swc[1024], sa[1024];
   __shared__ int sc_[1024];
   __shared__ int bad;
-  int t = threadIdx.x;
+  __shared__ double fsh;
+  const int t = threadIdx.x;
   if (ctrl[DC_ERR] != 0.0) return;
-  int64_t W = (int64_t)ctrl[DC_W];
-  int64_t per = (W + 1023) / 1024;
-  int64_t b = t * per, e = min(W, b + per);
-  double a = 0, ae = 0, aa = 0;
-  int cnt = 0, nbad = 0;
+  const int64_t W = (int64_t)ctrl[DC_W];
+  const int64_t per = (W + 1023) / 1024;
+  const int64_t b = t * per, e = min(W, b + per);
+  double a = 0;
+  int nbad = 0;
   for (int64_t k = b; k < e; ++k) {
-    if (ncopy[k] < 0) { ++nbad; continue; }
-    a += wts[k];
-    ae += wel[k];
-    aa += nacc[k];
-    cnt += ncopy[k];
+    if (br.nc[k] < 0) { ++nbad; continue; }
+    a += br.w[k];
   }
   if (t == 0) bad = 0;
+  sw[t] = a;
   __syncthreads();
   if (nbad) atomicAdd(&bad, nbad);
-  sw[t] = a; swe[t] = ae; sa[t] = aa; sc_[t] = cnt;
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) sw[t] += sw[t + off];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double f = 1.0;
+    if (sw[0] > 1.05 * W_target) f = 1.05 * W_target / sw[0];
+    else if (sw[0] < 0.95 * W_target) f = 0.95 * W_target / sw[0];
+    fsh = f;
+  }
+  __syncthreads();
+  const double f = fsh;
+  double aw = 0, ae = 0, ac = 0, aa = 0;
+  int cnt = 0;
+  for (int64_t k = b; k < e; ++k) {
+    if (br.nc[k] < 0) continue;
+    const double wk = f * br.w[k];
+    const int nc = min(3, (int)floor(wk + br.ub[k]));
+    br.nc[k] = nc;
+    aw += wk;
+    ae += f * br.we[k];
+    ac += f * br.wc[k];
+    aa += nacc[k];
+    cnt += nc;
+  }
+  __syncthreads();
+  sw[t] = aw; swe[t] = ae; swc[t] = ac; sa[t] = aa; sc_[t] = cnt;
   __syncthreads();
   // inclusive scan of copy counts (Hillis-Steele) and tree sums
   for (int off = 1; off < 1024; off <<= 1) {
@@ -738,6 +760,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* w
     if (t < off) {
       sw[t] += sw[t + off];
       swe[t] += swe[t + off];
+      swc[t] += swc[t + off];
       sa[t] += sa[t + off];
     }
     __syncthreads();
@@ -745,7 +768,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* w
   int base = t > 0 ? sc_[t - 1] : 0;
   for (int64_t k = b; k < e; ++k) {
     offs[k] = base;
-    base += ncopy[k] > 0 ? ncopy[k] : 0;
+    base += br.nc[k] > 0 ? br.nc[k] : 0;
   }
   if (t == 0) {
     int64_t Wn = sc_[1023];
@@ -753,7 +776,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* w
     pop[st] = (double)W;
     wsum[st] = sw[0];
     wesum[st] = swe[0];
-    etrial[st] = ctrl[DC_ET];
+    etrial[st] = ctrl[DC_ET] + log(f) / tau;
     lacc[st] = sa[0];
     lprop[st] = (double)W * N;
     if (bad || Wn <= 0 || Wn > capacity) {
@@ -761,7 +784,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, const double* w
       ctrl[DC_ERRSTEP] = (double)st;
       ctrl[DC_WNEW] = (double)Wn;
     } else {
-      ctrl[DC_RUN_NUM] += swe[0];
+      ctrl[DC_RUN_NUM] += swc[0];
       ctrl[DC_RUN_DEN] += sw[0];
       ctrl[DC_WNEW] = (double)Wn;
       ctrl[DC_ET] = ctrl[DC_RUN_NUM] / ctrl[DC_RUN_DEN] - (0.1 / tau) * log((double)Wn / W_target);
@@ -864,13 +887,13 @@ static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state,
 
 template <int NT, int PREC>
 static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap, uint64_t seed,
-                                    uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
+                                    uint32_t step, double tau, const DmcBranch& br, double* nacc,
                                     hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_dmc_step<NT, PREC>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dmc_step<NT, PREC>), dim3((unsigned)cap), dim3(NT), lds, s, dwf, state, ctrl, 0, seed, step,
-                     tau, wts, wel, ncopy, nacc);
+                     tau, br, nacc);
   return hipGetLastError();
 }
 
@@ -949,17 +972,16 @@ hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
 }
 
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
-                           uint32_t step, double tau, double* wts, double* wel, int* ncopy, double* nacc,
-                           hipStream_t s) {
-  VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, wts, wel, ncopy, nacc, s)
+                           uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, s)
 }
 
-hipError_t launch_dmc_tail(double* ctrl, const double* wts, const double* wel, const int* ncopy, const double* nacc,
-                           int* offs, int64_t cap, int N, int st, double tau, double W_target, double* pop,
-                           double* wsum, double* wesum, double* etrial, double* lacc, double* lprop,
-                           const double* src, double* dst, int rec_len, hipStream_t s) {
-  hipLaunchKernelGGL(k_dmc_scan, dim3(1), dim3(1024), 0, s, ctrl, wts, wel, ncopy, nacc, offs, cap, N, st, tau,
-                     W_target, pop, wsum, wesum, etrial, lacc, lprop);
+hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
+                           int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
+                           double* etrial, double* lacc, double* lprop, const double* src, double* dst, int rec_len,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_dmc_scan, dim3(1), dim3(1024), 0, s, ctrl, br, nacc, offs, cap, N, st, tau, W_target, pop,
+                     wsum, wesum, etrial, lacc, lprop);
   hipLaunchKernelGGL(k_dmc_copy, dim3((unsigned)cap), dim3(256), 0, s, ctrl, src, dst, offs, rec_len);
   hipLaunchKernelGGL(k_dmc_commit, dim3(1), dim3(1), 0, s, ctrl);
   return hipGetLastError();

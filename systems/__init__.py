@@ -38,6 +38,7 @@ from .generate import (  # noqa: F401
     hydrogen_gaussian,
     helium_gaussian,
     helium_sto,
+    gaussian_multicentre,
     small_random_system,
     initial_walkers,
     named_config,

@@ -311,6 +311,19 @@ def helium_sto(zeta):
                        [[1.0]], [{"c": 1.0, "terms": [{"inactive": [0], "pairs": [], "unpaired": []}]}])
 
 
+def gaussian_multicentre(alpha, Z, pos, n_up=1, n_dn=0):
+    """Electrons in one Gaussian exp(-alpha r^2) centred on the first of
+    several nuclei (charges Z, positions pos), no Jastrow: one electron
+    (n_up = 1) or two in a doubly occupied orbital (n_up = n_dn = 1)."""
+    n_nuc = len(Z)
+    occ = {"inactive": [0], "pairs": [], "unpaired": []} if n_dn else {"inactive": [], "pairs": [], "unpaired": [0]}
+    return {"name": "gaussian_multicentre", "seed": 0,
+            "nuclei": {"Z": [float(z) for z in Z], "pos": [[float(c) for c in p] for p in pos]},
+            "n_up": n_up, "n_dn": n_dn,
+            "shells": [{"center": 0, "kind": "gto", "l": 0, "exps": [alpha], "coefs": [1.0]}],
+            "lam": [[1.0]], "structures": [{"c": 1.0, "terms": [occ]}], "jastrow": _zero_jastrow(n_nuc)}
+
+
 def small_random_system(seed, n_nuc=2, n_inactive=1, n_active=3, n_pairs=1, n_unpaired=0,
                         n_structures=3, lmax=2, kappa=0.8, poly=True):
     """Small random JVB system for parity and pin tests.

@@ -119,3 +119,31 @@ def test_autograd_function_contracts_upstream_gradients(lib, oracle_mod):
     dl, de = ctx.param_grad(R)
     ref = (a[:, None] * dl + b[:, None] * de).sum(0).cpu()
     np.testing.assert_allclose(gp.numpy(), ref.numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_autograd_backward_uses_its_own_parameters(lib, oracle_mod):
+    # two graphs at different parameter points: the backward of the first,
+    # run after the second forward, must give the gradient at the first
+    # point, and leave the context at the parameters it held
+    import torch
+    sysd = S.small_random_system(421, n_inactive=1, n_active=4, n_pairs=1, n_unpaired=1, n_structures=3)
+    ctx = lib.Context(sysd)
+    W = 16
+    R = torch.from_numpy(S.initial_walkers(sysd, W, seed=4)).cuda()
+    p0 = ctx.get_params()
+    p2v = p0.copy()
+    p2v[: ctx.n_struct] *= np.linspace(0.7, 1.3, ctx.n_struct)
+    p2v[ctx.n_struct:ctx.n_struct + 20] += 0.05
+    p1 = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    p2 = torch.tensor(p2v, dtype=torch.float64, requires_grad=True)
+    lp1, el1 = lib.jvb_apply(p1, R, ctx)
+    lp2, el2 = lib.jvb_apply(p2, R, ctx)
+    (g1,) = torch.autograd.grad(lp1.sum() + el1.sum(), p1)
+    np.testing.assert_array_equal(ctx.get_params(), p2v)
+    ctx.set_params(p0)
+    dl, de = ctx.param_grad(R)
+    ref = (dl + de).sum(0).cpu()
+    np.testing.assert_allclose(g1.numpy(), ref.numpy(), rtol=1e-12, atol=1e-12)
+    ctx.set_params(p2v)
+    dl2, de2 = ctx.param_grad(R)
+    assert not np.allclose((dl2 + de2).sum(0).cpu().numpy(), ref.numpy(), rtol=1e-6)

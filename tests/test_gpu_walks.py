@@ -41,6 +41,7 @@ def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=424
     R0 = S.initial_walkers(sysd, W, seed=5)
     o = oracle_mod.Oracle(sysd)
     ref = o.vmc(R0, steps, seed, step0, step_size, all_electron, want_sij=sij)
+    ref["oracle"] = o
     ctx = _context(lib, sysd, lanes)
     print(f"[vmc] {sysd['name']} W={W} steps={steps} all_electron={all_electron} "
           f"lanes={ctx.info['sweep_lanes']} step_kernel={ctx.info['step_kernel']}", flush=True)
@@ -51,18 +52,30 @@ def _vmc_pair(lib, oracle_mod, sysd, W, steps, step_size, all_electron, seed=424
     return ref, acc, R, ctx
 
 
-def _check_vmc(ref, acc, R, steps, tol=1e-9):
+def _eloc_scale(ref):
+    return np.maximum(1.0, np.abs(ref["kin"]) + np.abs(ref["eloc"] - ref["kin"]))
+
+
+def _check_vmc(ref, acc, R, steps, tol=1e-9, oracle_obj=None, el_tol=1e-10):
     same = np.all(np.abs(R - ref["R"]) <= 1e-9 * (1 + np.abs(ref["R"])), axis=(1, 2))
     assert same.all(), f"{(~same).sum()} walkers diverged"
     np.testing.assert_array_equal(acc["n_accept"].cpu().numpy(), ref["n_acc"])
     es = acc["e_sum"].cpu().numpy()
     scale = np.maximum(1.0, np.abs(ref["e2_sum"] / steps) ** 0.5 * steps)
     assert np.max(np.abs(es - ref["e_sum"]) / scale) < tol
+    if oracle_obj is not None:
+        # E_L of the last step, walker by walker, against the oracle's E_L at
+        # the final configuration (scaled as the evaluate parity: |T_L| + |V|)
+        fin = oracle_obj.evaluate(ref["R"])
+        np.testing.assert_array_equal(fin["eloc"], ref["e_last"])
+        el = acc["e_last"].cpu().numpy()
+        worst = np.max(np.abs(el - fin["eloc"]) / _eloc_scale(fin))
+        assert worst <= el_tol, f"e_last: worst scaled error {worst:.3e}"
 
 
 def test_vmc_h2_all_electron(lib, oracle_mod):
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, True)
-    _check_vmc(ref, acc, R, 30)
+    _check_vmc(ref, acc, R, 30, oracle_obj=ref["oracle"])
 
 
 # single-electron steps run on the row kernel (four walkers per wavefront,
@@ -75,14 +88,14 @@ LANES = ["rows", 16, 32, 64]
 @pytest.mark.parametrize("lanes", LANES)
 def test_vmc_h2_single_electron(lib, oracle_mod, lanes):
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.h2_heitler_london(), 256, 30, 0.5, False, lanes=lanes)
-    _check_vmc(ref, acc, R, 30)
+    _check_vmc(ref, acc, R, 30, oracle_obj=ref["oracle"])
 
 
 @pytest.mark.parametrize("lanes", LANES)
 def test_vmc_small_random_with_sij(lib, oracle_mod, lanes):
     sysd = S.small_random_system(211, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
     ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 64, 20, 0.4, False, sij=True, lanes=lanes)
-    _check_vmc(ref, acc, R, 20)
+    _check_vmc(ref, acc, R, 20, oracle_obj=ref["oracle"])
     np.testing.assert_allclose(acc["sij_sum"].cpu().numpy(), ref["sij_sum"], rtol=1e-8, atol=1e-8)
 
 
@@ -91,7 +104,7 @@ def test_vmc_f2_sherman_morrison(lib, oracle_mod, lanes):
     # 12 sweeps at ~57 % acceptance pass the 32-update refresh of both spins;
     # 61 walkers leave a partly filled last wavefront for 16 and 32 lanes
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.f2_shaped(), 61, 12, 0.3, False, lanes=lanes)
-    _check_vmc(ref, acc, R, 12)
+    _check_vmc(ref, acc, R, 12, oracle_obj=ref["oracle"])
 
 
 def _f2_with_slater_shells():
@@ -116,7 +129,19 @@ def _f2_with_slater_shells():
 @pytest.mark.parametrize("lanes", ["rows", 32])
 def test_vmc_f2_with_slater_shells(lib, oracle_mod, lanes):
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, _f2_with_slater_shells(), 61, 8, 0.3, False, lanes=lanes)
-    _check_vmc(ref, acc, R, 8)
+    _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
+
+
+def test_vmc_precision_molecule_refresh_32(lib, oracle_mod):
+    # the 40-electron molecule (20 per spin, 64 determinants) on its default
+    # path: the 32-lane wavefront sweep with Sherman-Morrison updates and the
+    # inverse rebuilt every 32 accepted updates (about every third step at
+    # ~60 % acceptance), then the batched local energy; 8 steps pass two
+    # rebuilds of each spin.  E_L of the last step is checked walker by walker.
+    sysd = S.precision_molecule()
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 32, 8, 0.3, False)
+    assert ctx.info["sweep_lanes"] == 32 and ctx.info["step_kernel"] == 1
+    _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
 
 
 @pytest.mark.parametrize("lanes", [32, 64])
@@ -208,18 +233,28 @@ def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3, dmc_kernel
     ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
     out = ctx.dmc_advance([st0, st1], W, steps, seed, step0, tau, et, W)
     R = ctx.positions(st0, out["W"]).cpu().numpy()
+    e_rec = ctx.record_eloc(st0, out["W"]).cpu().numpy()
     torch.cuda.synchronize()
+    ref["oracle"] = o
+    ref["e_rec"] = e_rec
     return ref, out, R
 
 
-def _check_dmc(ref, out, R):
+def _check_dmc(ref, out, R, e_rec=None, oracle_obj=None):
     assert ref["rc"] == 0
     np.testing.assert_array_equal(out["pop"].cpu().numpy(), ref["pop"])
     assert out["W"] == ref["W"]
     np.testing.assert_allclose(out["wsum"].cpu().numpy(), ref["wsum"], rtol=1e-9)
     np.testing.assert_allclose(out["wesum"].cpu().numpy(), ref["wesum"], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(out["etrial"].cpu().numpy(), ref["etrial"], rtol=1e-9, atol=1e-9)
     np.testing.assert_array_equal(out["n_accept"].cpu().numpy(), ref["acc"])
     np.testing.assert_allclose(R, ref["R"], rtol=1e-8, atol=1e-8)
+    if e_rec is not None:
+        # each surviving walker's E_L against the oracle's at its configuration
+        fin = oracle_obj.evaluate(ref["R"])
+        np.testing.assert_allclose(fin["eloc"], ref["eloc"], rtol=1e-13, atol=1e-13)
+        worst = np.max(np.abs(e_rec - fin["eloc"]) / _eloc_scale(fin))
+        assert worst <= 1e-10, f"E_L of the records: worst scaled error {worst:.3e}"
 
 
 @pytest.mark.parametrize("kern", DMC_KERNELS)
@@ -241,14 +276,14 @@ def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod, kern):
 @pytest.mark.parametrize("kern", DMC_KERNELS)
 def test_dmc_h2_trajectory(lib, oracle_mod, kern):
     ref, out, R = _dmc_pair(lib, oracle_mod, S.h2_heitler_london(), 128, 8, 0.01, dmc_kernel=kern)
-    _check_dmc(ref, out, R)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
 
 
 @pytest.mark.parametrize("kern", DMC_KERNELS)
 def test_dmc_small_random_trajectory(lib, oracle_mod, kern):
     sysd = S.small_random_system(311, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
     ref, out, R = _dmc_pair(lib, oracle_mod, sysd, 64, 5, 0.005, dmc_kernel=kern)
-    _check_dmc(ref, out, R)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
 
 
 @pytest.mark.parametrize("kern", DMC_KERNELS)
@@ -258,11 +293,39 @@ def test_dmc_f2_trajectory(lib, oracle_mod, kern):
     # thousands of hartree: a short time step and the median as trial energy
     # keep the population within the capacity.
     ref, out, R = _dmc_pair(lib, oracle_mod, S.f2_shaped(), 45, 3, 0.002, dmc_kernel=kern, et_median=True)
-    _check_dmc(ref, out, R)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
 
 
-def _eloc_scale(ref):
-    return np.maximum(1.0, np.abs(ref["kin"]) + np.abs(ref["eloc"] - ref["kin"]))
+_DMC64 = {}
+
+
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_64_electron_molecule_trajectory(lib, oracle_mod, kern):
+    # the 64-electron DMC molecule (32 per spin, 83 distinct determinants per
+    # spin: the electron-major acceptance kernel's second determinant slot,
+    # u = lane + 64, holds determinants 64..82), 8 walkers over 2 steps, with
+    # both DMC kernels against one oracle trajectory
+    sysd = S.dmc_molecule()
+    if "ref" not in _DMC64:
+        o = oracle_mod.Oracle(sysd)
+        R0 = S.initial_walkers(sysd, 8, seed=8)
+        e0 = o.evaluate(R0)["eloc"]
+        _DMC64["et"] = float(np.median(e0))
+        _DMC64["R0"] = R0
+        _DMC64["ref"] = o.dmc(R0, e0, 2, 77, 3, 0.005, _DMC64["et"], 8, capacity=32)
+        _DMC64["ref"]["oracle"] = o
+    import torch
+    ref = _DMC64["ref"]
+    ctx = lib.Context(sysd, dmc_kernel=kern)
+    assert ctx.info["n_unique_up"] > 64 and ctx.info["n_unique_dn"] > 64
+    print(f"[dmc] {sysd['name']} W=8 steps=2 dmc_kernel={ctx.info['dmc_kernel']}", flush=True)
+    st0, st1 = ctx.new_state(32), ctx.new_state(32)
+    ctx.walkers_init(torch.from_numpy(_DMC64["R0"]).cuda(), st0)
+    out = ctx.dmc_advance([st0, st1], 8, 2, 77, 3, 0.005, _DMC64["et"], 8)
+    R = ctx.positions(st0, out["W"]).cpu().numpy()
+    e_rec = ctx.record_eloc(st0, out["W"]).cpu().numpy()
+    torch.cuda.synchronize()
+    _check_dmc(ref, out, R, e_rec, ref["oracle"])
 
 
 @pytest.mark.parametrize("kern", ["rows", 32])

@@ -148,6 +148,33 @@ def test_helium_product_forms(oracle_mod):
     np.testing.assert_allclose(o.evaluate(R)["eloc"], ref, rtol=1e-12)
 
 
+def test_multicentre_potential(oracle_mod):
+    """One Gaussian on nucleus A among three nuclei (no Jastrow).  The kinetic
+    part is that of the one-centre Gaussian about A, so
+    E_L = sum_i (3a - 2a^2 r_iA^2) - sum_i sum_alpha Z_alpha / r_i,alpha
+          + sum_{i<j} 1/r_ij + sum_{alpha<beta} Z_alpha Z_beta / R_alpha,beta.
+    Three unequal charges at unequal separations make a dropped, doubled or
+    misassigned nucleus-nucleus pair, or an electron-nucleus term taken from
+    the wrong centre, change the value."""
+    a = 0.45
+    Z = [3.0, 1.0, 2.0]
+    pos = np.array([[0.2, -0.1, 0.3], [1.7, 0.4, -0.6], [-0.9, 2.1, 1.1]])
+    Vnn = sum(Z[p] * Z[q] / np.linalg.norm(pos[p] - pos[q]) for p in range(3) for q in range(p + 1, 3))
+    rng = np.random.default_rng(21)
+    for n_up, n_dn in ((1, 0), (1, 1)):
+        o = oracle_mod.Oracle(S.gaussian_multicentre(a, Z, pos, n_up, n_dn))
+        R = pos[0] + rng.normal(scale=0.9, size=(60, n_up + n_dn, 3))
+        ref = np.full(len(R), Vnn)
+        for i in range(n_up + n_dn):
+            rA2 = ((R[:, i] - pos[0]) ** 2).sum(1)
+            ref += 3 * a - 2 * a * a * rA2
+            for al in range(3):
+                ref -= Z[al] / np.linalg.norm(R[:, i] - pos[al], axis=1)
+        if n_dn:
+            ref += 1 / np.linalg.norm(R[:, 0] - R[:, 1], axis=1)
+        np.testing.assert_allclose(o.evaluate(R)["eloc"], ref, rtol=1e-12)
+
+
 def test_jastrow_only_hydrogen(oracle_mod):
     """Constant orbital (Gaussian exponent 0) and e-n Pade A = -1, B = 0 with kappa = 0
     give Psi = exp(-r), the exact ground state: E_L == -0.5."""

@@ -96,3 +96,39 @@ def test_dmc_nodeless_projection_reaches_exact_energy(oracle_mod):
     m, s = blk.mean(), blk.std(ddof=1) / math.sqrt(len(blk))
     assert abs(m + 0.5) < 3 * s + 0.005, (m, s)
     assert np.all(np.abs(r2["pop"] / 1000 - 1) < 0.1)
+
+
+def test_dmc_population_clamp_factor(oracle_mod):
+    """A trial energy far above the energy makes every weight exceed 1; the
+    population control scales all weights of the step by the one factor that
+    brings their sum to 1.05 W_target, i.e. the step runs at the trial energy
+    E_T + ln(f) / tau (logged as that step's E_T)."""
+    o = oracle_mod.Oracle(S.hydrogen_gaussian(0.3))
+    W, tau, et = 400, 0.01, 5.0
+    R0 = np.random.default_rng(9).normal(size=(W, 1, 3))
+    e0 = o.evaluate(R0)["eloc"]
+    r = o.dmc(R0, e0, 1, 41, 0, tau, et, W)
+    assert r["rc"] == 0
+    assert r["wsum"][0] == pytest.approx(1.05 * W, rel=1e-12)
+    assert r["etrial"][0] < et
+    # a second step starts from the clamped population and stays in the band
+    r2 = o.dmc(r["R"], r["eloc"], 1, 41, 1, tau, r["e_trial"], W)
+    assert abs(r2["pop"][0] / W - 1) <= 0.1
+
+
+def test_dmc_population_stays_in_band(oracle_mod):
+    """The F2-shaped trial function has local energies over several thousand
+    hartree (no cusps, exponents up to 1e4); the birth/death population must
+    still stay within +-10 % of the target at every step, and the trial
+    energy must stay finite and within the range of the sampled energies."""
+    sysd = S.f2_shaped()
+    o = oracle_mod.Oracle(sysd)
+    W = 600
+    R0 = S.initial_walkers(sysd, W, seed=8)
+    e0 = o.evaluate(R0)["eloc"]
+    r = o.dmc(R0, e0, 15, 77, 0, 0.005, float(np.median(e0)), W, capacity=4 * W)
+    assert r["rc"] == 0
+    assert np.all(np.abs(r["pop"] / W - 1) <= 0.1), r["pop"]
+    assert abs(r["W"] / W - 1) <= 0.1
+    lo, hi = np.percentile(e0, [5, 95])
+    assert np.all((r["etrial"] > lo) & (r["etrial"] < hi)), r["etrial"]
