@@ -159,7 +159,12 @@ typedef struct {
 
 /* Build a context: expands the HLSP structures into determinants (Eq. PhiI,
  * N_det,I = 2^{N_pairs}), picks the reference determinant per spin and
- * uploads the constant tables.  Errors: EINVAL (inconsistent counts, more than
+ * uploads the constant tables.  The reference of each spin is that spin's
+ * determinant in the first product of the expansion (structures, their terms,
+ * then the pair orientations, each pair (i, j) first as up i, down j) with no
+ * orbital repeated in either spin; every other spin determinant is handled as
+ * at most 3 replaced columns of it.  Rounding errors of the determinant ratios
+ * grow with the ratio of the largest spin determinant to the reference one.  Errors: EINVAL (inconsistent counts, more than
  * 3 orbitals of a determinant differing from its spin's reference, sizes
  * above the kernel limits: 64 electrons per spin, 1024 basis functions),
  * ENOMEM, EHIP. */

@@ -57,6 +57,7 @@ def _load():
         lib.orc_vmc.restype = ctypes.c_int
         lib.orc_dmc.restype = ctypes.c_int
         lib.orc_lu.restype = ctypes.c_int
+        lib.orc_conditioning.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -165,6 +166,19 @@ class Oracle:
                                      _dp(out["ratio"]), _dp(out["kin"]))
         out["bad"] = int(bad)
         return out
+
+    def conditioning(self, R):
+        """kappa_D = sum_k |c d Delta_up Delta_dn| / |D| per configuration (the
+        cancellation of the determinant sum) and ln|Delta^sigma_k| of every
+        determinant product k per spin ([W][n_dets] each, in the order of
+        ``dets()``)."""
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, self.N, 3)
+        W = R.shape[0]
+        kd = np.zeros(W)
+        lup = np.zeros((W, self.n_dets))
+        ldn = np.zeros((W, self.n_dets))
+        self._lib.orc_conditioning(ctypes.c_void_p(self._h), ctypes.c_int(W), _dp(R), _dp(kd), _dp(lup), _dp(ldn))
+        return kd, lup, ldn
 
     def param_deriv(self, R, idx=None):
         """Per-configuration d lnPsi / dp and d E_L / dp for the listed parameters."""

@@ -309,6 +309,11 @@ template <class T> struct EvalOut {
   std::vector<T> ratio;   // nstruct: Phi_I / sum_J c_J Phi_J
   T kin, pot;
   bool ok = true;
+  // conditioning (reported, not part of Psi): ln|Delta^sigma_k| of every
+  // determinant product k per spin, and the cancellation of the determinant
+  // sum kappa_D = sum_k |c d Delta_up Delta_dn| / |D|
+  std::vector<double> lspin[2];
+  double kappaD = 0.0;
 };
 
 template <class T>
@@ -334,6 +339,8 @@ EvalOut<T> evaluate(const System& s, const Params<T>& P, const double* R, int le
   std::vector<int> sg(nd), alive(nd);
   // op[k][i][c-1]: O_i Delta^sigma(i)_k / Delta^sigma(i)_k for c = 1..4
   std::vector<T> op((size_t)nd * N * 4, T(0.0));
+  o.lspin[0].assign(nd, -INFINITY);
+  o.lspin[1].assign(nd, -INFINITY);
   for (int k = 0; k < nd; ++k) {
     const Det& d = s.dets[k];
     T lsum = T(0.0);
@@ -349,6 +356,7 @@ EvalOut<T> evaluate(const System& s, const Params<T>& P, const double* R, int le
       T la;
       int sgn;
       if (!lu_det_inverse(n, A, la, sgn, inv)) { ok = false; break; }
+      o.lspin[spin][k] = val(la);
       lsum = lsum + la;
       ssum *= sgn;
       // row-i cofactor expansion: O_i Delta / Delta = sum_j O phi_{o_j}(r_i) (A^-1)_{j i}
@@ -376,6 +384,12 @@ EvalOut<T> evaluate(const System& s, const Params<T>& P, const double* R, int le
       Dt = Dt + term[k];
     }
   if (val(Dt) == 0.0) { o.ok = false; return o; }
+  {
+    double sa = 0.0;
+    for (int k = 0; k < nd; ++k)
+      if (alive[k]) sa += std::fabs(val(term[k]));
+    o.kappaD = sa / std::fabs(val(Dt));
+  }
   o.ratio.assign(s.nstruct, T(0.0));
   for (int k = 0; k < nd; ++k)
     if (alive[k]) o.ratio[s.dets[k].structure] = o.ratio[s.dets[k].structure] + (double)sg[k] * exp(L[k] - Lmax) / Dt;
@@ -655,6 +669,27 @@ int orc_evaluate(void* h, int W, const double* R, int level, double* logabs, int
     if (kin && level >= 2) kin[w] = o.kin;
     if (ratio)
       for (int I = 0; I < s.nstruct; ++I) ratio[(size_t)w * s.nstruct + I] = o.ratio[I];
+  }
+  return bad;
+}
+
+// Conditioning of the determinant part at W configurations (reported beside
+// the parity checks): kappa_D [W] and ln|Delta^sigma_k| per spin, [W][n_dets]
+// each (-inf where a spin determinant is singular).
+int orc_conditioning(void* h, int W, const double* R, double* kappaD, double* lup, double* ldn) {
+  const System& s = *(System*)h;
+  Params<double> P = make_params<double>(s, -1);
+  const int nd = (int)s.dets.size();
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic) reduction(+ : bad)
+  for (int w = 0; w < W; ++w) {
+    EvalOut<double> o = evaluate(s, P, R + (size_t)w * s.N * 3, 0);
+    if (!o.ok) ++bad;
+    kappaD[w] = o.ok ? o.kappaD : INFINITY;
+    for (int k = 0; k < nd; ++k) {
+      lup[(size_t)w * nd + k] = o.lspin[0].empty() ? -INFINITY : o.lspin[0][k];
+      ldn[(size_t)w * nd + k] = o.lspin[1].empty() ? -INFINITY : o.lspin[1][k];
+    }
   }
   return bad;
 }

@@ -144,6 +144,71 @@ def test_vmc_precision_molecule_refresh_32(lib, oracle_mod):
     _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
 
 
+def _reference_sets(sysd):
+    """The library's reference determinant of each spin (include/vbqmc.h,
+    vbqmc_create): the spin sets of the first product of the structure
+    expansion, every pair taken as (up i, down j), that has no repeated
+    orbital in either spin."""
+    for st in sysd["structures"]:
+        for t in st["terms"]:
+            up = list(t["inactive"]) + [p[0] for p in t["pairs"]] + list(t["unpaired"])
+            dn = list(t["inactive"]) + [p[1] for p in t["pairs"]]
+            if len(set(up)) == len(up) and len(set(dn)) == len(dn):
+                return sorted(up), sorted(dn)
+    raise AssertionError("no non-vanishing product")
+
+
+def _kappa_ref(oracle_obj, sysd, R):
+    """Per configuration and spin: the largest |Delta| among the spin
+    determinants over |Delta| of the library's reference determinant (from
+    the oracle's own LU determinants), and kappa_D."""
+    kd, lup, ldn = oracle_obj.conditioning(R)
+    _, up, dn = oracle_obj.dets()
+    ref_up, ref_dn = _reference_sets(sysd)
+    ku = next(k for k in range(len(up)) if sorted(up[k].tolist()) == ref_up)
+    kdn = next(k for k in range(len(dn)) if sorted(dn[k].tolist()) == ref_dn)
+    return np.exp(lup.max(axis=1) - lup[:, ku]), np.exp(ldn.max(axis=1) - ldn[:, kdn]), kd
+
+
+def test_fp64_eloc_by_reference_conditioning(lib, oracle_mod):
+    # The FP64 path keeps one reference determinant per spin (its inverse and
+    # a replaced-column table); the table's rounding error grows with
+    # kappa_ref, the largest spin determinant over the reference one.  After
+    # 30 steps of 2048 walkers of the 40-electron molecule at the default
+    # refresh every 32 updates, E_L of the chain and of a fresh evaluation
+    # agree with the oracle to 1e-10 (scaled by |T_L| + |V|) for every walker
+    # with kappa_ref <= 1e3 in both spins and kappa_D <= 1e4; the others are
+    # reported separately and must stay within (1e-10 + 1e-13 kappa_ref
+    # kappa_D) of it.
+    import torch
+    sysd = S.precision_molecule()
+    W = 2048
+    ctx = lib.Context(sysd)
+    print(f"[conditioning] {sysd['name']} W={W}", flush=True)
+    st = ctx.walkers_init(torch.from_numpy(S.initial_walkers(sysd, W, seed=9)).cuda())
+    ctx.vmc_advance(st, 20, 777, 0, 0.3)
+    acc = ctx.new_vmc_acc(W)
+    ctx.vmc_advance(st, 10, 777, 100, 0.3, False, acc)
+    Rg = ctx.positions(st)
+    ev = ctx.evaluate(Rg, want=("eloc",))["eloc"].cpu().numpy()
+    chain = acc["e_last"].cpu().numpy()
+    R = Rg.cpu().numpy()
+    o = oracle_mod.Oracle(sysd)
+    ref = o.evaluate(R)
+    ku, kdn, kd = _kappa_ref(o, sysd, R)
+    kr = np.maximum(ku, kdn)
+    scale = _eloc_scale(ref)
+    well = (kr <= 1e3) & (kd <= 1e4)
+    print(f"[conditioning] {int((~well).sum())} of {W} walkers with kappa_ref > 1e3 or kappa_D > 1e4 "
+          f"(max kappa_ref {kr.max():.2e}, max kappa_D {kd.max():.2e})", flush=True)
+    assert well.mean() > 0.95
+    for name, e in (("chain", chain), ("evaluate", ev)):
+        err = np.abs(e - ref["eloc"]) / scale
+        assert err[well].max() <= 1e-10, (name, float(err[well].max()))
+        bound = 1e-10 + 1e-13 * kr * kd
+        assert np.all(err <= bound), (name, float((err / bound).max()))
+
+
 @pytest.mark.parametrize("lanes", [32, 64])
 def test_vmc_sweep_then_measure_equals_advance(lib, lanes):
     # a step of vbqmc_vmc_advance is a sweep followed by a measurement: the
