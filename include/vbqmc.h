@@ -292,6 +292,23 @@ int vbqmc_dmc_advance(vbqmc_ctx* ctx, void* states[2], int64_t* W_io, int64_t ca
                       vbqmc_stream stream);
 
 /*
+ * vbqmc_dmc_advance without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, semantics and results
+ * as vbqmc_dmc_advance, bit for bit, except that the workspace is a fixed
+ * 32 MiB device array inside the library (one per device, held until the
+ * process ends; its address is taken at vbqmc_create), so the call allocates
+ * nothing.  Capacities whose vbqmc_dmc_workspace_bytes exceeds 32 MiB are
+ * rejected with EWORKSPACE before any work is queued.  Every call on a device
+ * shares that device's array: calls that overlap on one device (other
+ * streams, other contexts or host threads) race and must be serialised by the
+ * caller.  The current device must be the context's (EINVAL otherwise).
+ */
+int vbqmc_dmc_advance_noalloc(vbqmc_ctx* ctx, void* states[2], int64_t* W_io, int64_t capacity, int32_t n_steps,
+                              uint64_t seed, uint64_t step0, double tau, double* e_trial_io, int64_t W_target,
+                              const vbqmc_dmc_log* log, vbqmc_stream stream);
+
+/*
  * Parameter derivatives for W fixed configurations (Sec. 2.2, Eqs. Hi0, H0j):
  * dlogpsi[w][j] = d ln|Psi| / d p_j and deloc[w][j] = d E_L / d p_j, parameter
  * order as vbqmc_set_params.  Computed by a hand-written adjoint (reverse)

@@ -80,7 +80,7 @@ _lib = None
 EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info", "vbqmc_set_params",
            "vbqmc_get_params", "vbqmc_evaluate", "vbqmc_walkers_init", "vbqmc_walkers_positions",
            "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_vmc_sweep", "vbqmc_vmc_measure",
-           "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance",
+           "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance", "vbqmc_dmc_advance_noalloc",
            "vbqmc_param_grad_workspace_bytes", "vbqmc_param_grad", "vbqmc_reduce_walkers",
            "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin"]
 
@@ -114,6 +114,8 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_dmc_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.vbqmc_dmc_advance.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i64, i32, u64, u64, dbl,
                                       ctypes.POINTER(dbl), i64, ctypes.POINTER(_DmcLog), vp, ctypes.c_size_t, vp]
+    lib.vbqmc_dmc_advance_noalloc.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i64, i32, u64, u64, dbl,
+                                              ctypes.POINTER(dbl), i64, ctypes.POINTER(_DmcLog), vp]
     lib.vbqmc_param_grad_workspace_bytes.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.vbqmc_param_grad.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.vbqmc_reduce_walkers.argtypes = [vp, i64, i32, vp, vp, vp, vp]
@@ -323,6 +325,19 @@ class Context:
                                          ctypes.byref(lg), ctypes.c_void_p(workspace.data_ptr()),
                                          workspace.numel() * 8, _stream())
         self._rc(rc)
+        return {"W": Wio.value, "e_trial": et.value, **log}
+
+    def dmc_advance_noalloc(self, states, W, n_steps, seed, step0, tau, e_trial, w_target, log):
+        """vbqmc_dmc_advance on the library's fixed scratch array: the caller
+        passes the records and the per-step log, nothing is allocated."""
+        cap = states[0].shape[0]
+        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")])
+        arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
+        Wio = ctypes.c_int64(W)
+        et = ctypes.c_double(e_trial)
+        self._rc(self._lib.vbqmc_dmc_advance_noalloc(self._h, arr, ctypes.byref(Wio), cap, int(n_steps),
+                                                     ctypes.c_uint64(seed), ctypes.c_uint64(step0), float(tau),
+                                                     ctypes.byref(et), int(w_target), ctypes.byref(lg), _stream()))
         return {"W": Wio.value, "e_trial": et.value, **log}
 
     def param_grad(self, R, workspace=None):

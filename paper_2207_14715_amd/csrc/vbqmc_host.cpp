@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -159,9 +160,37 @@ struct vbqmc_ctx {
   DevWF* d_wf_dmcb = nullptr;   // same tables, layout of the electron-major DMC row tiles
   int dmc_kernel = 1;           // DMC steps: 1 one workgroup per walker, 2 electron-major launches
   double* d_timg = nullptr;     // LDS table image
+  int dev = 0;                  // device the context was created on
+  void* scratch = nullptr;      // that device's copy of the no-alloc scratch array
 };
 
+// Scratch of vbqmc_dmc_advance_noalloc: a file-scope device array of
+// kNoAllocScratchBytes, one copy per device, held until the process ends.
+// Host code never uses the array's name as an address: each device's copy is
+// reached through the pointer hipGetSymbolAddress returns with that device
+// current (taken once per device at vbqmc_create).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+// the device address of the scratch array on device dev (current), looked up
+// once per device
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[256] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 int fail(vbqmc_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -952,6 +981,13 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   he = hipGetDeviceProperties(&prop, dev);
   if (he != hipSuccess) { delete x; return VBQMC_EHIP; }
   x->lds_limit = (int)prop.sharedMemPerBlock;
+  x->dev = dev;
+  he = scratch_address(dev, &x->scratch);
+  if (he != hipSuccess) {
+    std::fprintf(stderr, "vbqmc_create: no address for the scratch array: %s\n", hipGetErrorString(he));
+    delete x;
+    return VBQMC_EHIP;
+  }
   if ((size_t)wf.lds_doubles * 8 > (size_t)x->lds_limit) {
     char b[160];
     std::snprintf(b, sizeof b, "system needs %d bytes of LDS per walker, device allows %d", wf.lds_doubles * 8,
@@ -1251,9 +1287,46 @@ int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, 
   return VBQMC_OK;
 }
 
+namespace {
+int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, int32_t n_steps, uint64_t seed,
+                     uint64_t step0, double tau, double* e_trial_io, int64_t W_target, const vbqmc_dmc_log* lg,
+                     void* ws, size_t ws_bytes, vbqmc_stream stream);
+}  // namespace
+
 int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, int32_t n_steps, uint64_t seed,
                       uint64_t step0, double tau, double* e_trial_io, int64_t W_target, const vbqmc_dmc_log* lg,
                       void* ws, size_t ws_bytes, vbqmc_stream stream) {
+  return dmc_advance_impl(x, states, W_io, cap, n_steps, seed, step0, tau, e_trial_io, W_target, lg, ws, ws_bytes,
+                          stream);
+}
+
+int vbqmc_dmc_advance_noalloc(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, int32_t n_steps,
+                              uint64_t seed, uint64_t step0, double tau, double* e_trial_io, int64_t W_target,
+                              const vbqmc_dmc_log* lg, vbqmc_stream stream) {
+  if (!x) return VBQMC_EINVAL;
+  if (cap < 1) return fail(x, VBQMC_EINVAL, "dmc_noalloc: bad capacity");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hipfail(x, e, "dmc_noalloc: current device");
+  if (dev != x->dev) return fail(x, VBQMC_EINVAL, "dmc_noalloc: the current device is not the context's device");
+  size_t need = 0;
+  vbqmc_dmc_workspace_bytes(x, cap, n_steps, &need);
+  if (need > kNoAllocScratchBytes) {
+    char b[200];
+    std::snprintf(b, sizeof b,
+                  "dmc_noalloc: capacity %lld needs %zu bytes of scratch, above the fixed %zu bytes; lower the "
+                  "capacity or pass a workspace to vbqmc_dmc_advance",
+                  (long long)cap, need, kNoAllocScratchBytes);
+    return fail(x, VBQMC_EWORKSPACE, b);
+  }
+  return dmc_advance_impl(x, states, W_io, cap, n_steps, seed, step0, tau, e_trial_io, W_target, lg, x->scratch,
+                          kNoAllocScratchBytes, stream);
+}
+
+namespace {
+int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, int32_t n_steps, uint64_t seed,
+                     uint64_t step0, double tau, double* e_trial_io, int64_t W_target, const vbqmc_dmc_log* lg,
+                     void* ws, size_t ws_bytes, vbqmc_stream stream) {
   if (!x || !states || !states[0] || !states[1] || !W_io || !e_trial_io || !lg || !ws)
     return fail(x, VBQMC_EINVAL, "dmc: bad arguments");
   if (!lg->pop || !lg->wsum || !lg->wesum || !lg->etrial || !lg->n_accept || !lg->n_prop)
@@ -1344,6 +1417,7 @@ int vbqmc_dmc_advance(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap,
   *e_trial_io = h[DC_ET];
   return VBQMC_OK;
 }
+}  // namespace
 
 int vbqmc_param_grad_workspace_bytes(const vbqmc_ctx* x, int64_t W, size_t* bytes) {
   if (!x || !bytes || W < 0) return VBQMC_EINVAL;
