@@ -1,0 +1,884 @@
+// gfx950 fixed-node DMC step with the walkers resident in a workgroup.
+//
+// A DMC step (Sec. 2.3.2) moves every electron of a walker once with a
+// drift-diffusion proposal, then weighs the walker for birth/death.  Here a
+// workgroup of four wavefronts owns four walkers for the whole step, one
+// walker per wavefront:
+//   * lane k keeps column k of [B | T] of the spin being moved in registers
+//     (B the reference inverse, T the replaced-column table), and lanes
+//     u, u + 64 keep the minor T[J_u, Q_u], R_u and W_u of distinct spin
+//     determinant u, so that a move's determinant ratio, its drift at the
+//     proposal and an accepted Sherman-Morrison update touch no memory but
+//     a few broadcast rows in LDS;
+//   * the four walkers move the same electron together: the value and
+//     gradient orbital rows at their four proposals are one 16-row MFMA tile
+//     (row = walker x channel), contracted with lambda^T on FP64 MFMA;
+//   * the value and gradient rows of an accepted proposal are the rows of
+//     the electron's new position: they are kept in the walker's record
+//     (compact, reference slots then table orbitals), so the drift of the
+//     next step reads them instead of re-evaluating the orbitals, the
+//     inverse refresh after refresh_every updates needs no orbital
+//     evaluation, and the local energy evaluates only the Laplacian rows
+//     (16-row MFMA tiles of four walkers x four electrons).
+// A walker's record then crosses HBM a few times per step instead of once
+// per electron.  The branching weight closes the step; the population
+// control, scan and compaction are the shared kernels of the other DMC paths.
+//
+// Limits (checked by the host): FP64, Gaussian shells, at most 32 electrons,
+// 64 reference slots plus table orbitals and 128 distinct determinants per
+// spin, at most 64 (padded) orbitals.
+
+#include "vbqmc_group.h"
+
+namespace vbqmc {
+
+constexpr int kDwW = 4;            // walkers (wavefronts) of a workgroup
+constexpr int kDwNT = 64 * kDwW;   // threads of a workgroup
+
+// one lane's value of a double from lane src (src the same in every lane)
+__device__ __forceinline__ double dw_readlane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+template <int K>
+__device__ __forceinline__ void dw_wsum(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+}
+
+// Distinct determinants u = lane + 64 h (h = 0, 1) of the spin being moved:
+// replaced slots J, table indices Q, the minor T[J, Q] (XE x XE, XE the
+// largest number of columns a determinant replaces), R_u and W_u.  Lanes
+// past the spin's determinants hold e = 0 and W = 0 (they add nothing).
+template <int XE>
+struct DwDets {
+  int e[2], J[2][XE], Q[2][XE];
+  double m[2][XE * XE];
+  double R[2], W[2];
+};
+
+// determinant of the leading e x e block of an XE x XE matrix (e <= XE)
+template <int XE>
+__device__ __forceinline__ double dw_det(int e, const double* m) {
+  if constexpr (XE == 2) {
+    return e == 0 ? 1.0 : (e == 1 ? m[0] : m[0] * m[3] - m[1] * m[2]);
+  } else {
+    return det_e(e, m);
+  }
+}
+
+// y^T adj(m) b for the leading e x e block
+template <int XE>
+__device__ __forceinline__ double dw_adj(int e, const double* m, const double* y, const double* b) {
+  if constexpr (XE == 2) {
+    if (e == 0) return 0.0;
+    if (e == 1) return y[0] * b[0];
+    return y[0] * (m[3] * b[0] - m[1] * b[1]) + y[1] * (-m[2] * b[0] + m[0] * b[1]);
+  } else {
+    return adj_e(e, m, y, b);
+  }
+}
+
+// from the table T (row-major n x nP, any memory) and R_u, W_u
+template <int XE>
+__device__ __forceinline__ void dw_load_dets(const SpinTab& sp, const double* T, const double* Ru, const double* Wu,
+                                             int lane, DwDets<XE>& d) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = lane + 64 * h;
+    const bool ok = u < sp.nU;
+    const int* ui = sp.uinfo + 8 * (ok ? u : 0);
+    d.e[h] = ok ? ui[0] : 0;
+#pragma unroll
+    for (int r = 0; r < XE; ++r) {
+      d.J[h][r] = ok ? ui[1 + r] : 0;
+      d.Q[h][r] = ok ? ui[4 + r] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < XE; ++r)
+#pragma unroll
+      for (int c = 0; c < XE; ++c) {
+        const double v = T[d.J[h][r] * sp.nP + d.Q[h][c]];
+        d.m[h][r * XE + c] = (r < d.e[h] && c < d.e[h]) ? v : 0.0;
+      }
+    d.R[h] = ok ? Ru[u] : 0.0;
+    d.W[h] = ok ? Wu[u] : 0.0;
+  }
+}
+
+// y (indexed by table orbital) and b (indexed by slot) of determinant h,
+// zero past its e replaced columns
+template <int XE>
+__device__ __forceinline__ void dw_gather(const DwDets<XE>& d, int h, const double* y, const double* b,
+                                          double (&yy)[XE], double (&bb)[XE]) {
+  // (the loads are unconditional: J and Q are valid indices in every lane)
+#pragma unroll
+  for (int r = 0; r < XE; ++r) {
+    const bool in = r < d.e[h];
+    const double yv = y[d.Q[h][r]], bv = b[d.J[h][r]];
+    yy[r] = in ? yv : 0.0;
+    bb[r] = in ? bv : 0.0;
+  }
+}
+
+// sum over this lane's determinants of (rp R_u + y_Q^T adj(T_JQ) b_J) W_u:
+// the numerator of O_i D / D for a row operator O whose row-operator products
+// with the reference columns are rp (at slot il) and y (table residuals)
+template <int XE>
+__device__ __forceinline__ double dw_detsum(const DwDets<XE>& d, double rp, const double* y, const double* b) {
+  double s = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double yy[XE], bb[XE];
+    dw_gather<XE>(d, h, y, b, yy, bb);
+    s += (rp * d.R[h] + dw_adj<XE>(d.e[h], d.m[h], yy, bb)) * d.W[h];
+  }
+  return s;
+}
+
+// t_k = sum_{j < n} row[j] C[j], summed over all NC entries: C[j] is zero
+// for j >= n and every row entry is finite (the broadcast rows are cleared
+// when the kernel starts and after each refresh), so the entries past n add
+// exact zeros
+// The scheduling barrier after each half keeps the compiler from loading the
+// rows of several dot products ahead at once (that would hold 2 NC registers
+// per row beside the columns).
+template <int NC>
+__device__ __forceinline__ double dw_dot(const double* row, const double (&C)[NC]) {
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < NC / 2; j += 2) {
+    a0 += row[j] * C[j];
+    a1 += row[j + 1] * C[j + 1];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = NC / 2; j < NC; j += 2) {
+    a0 += row[j] * C[j];
+    a1 += row[j + 1] * C[j + 1];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  return a0 + a1;
+}
+
+// column lane of [B | T] from the record: lane k < n takes column k of B,
+// lane n + q column q of T; other lanes and rows past n hold zero.  Every
+// load is in the record (row index clamped), the mask zeroes what is unused.
+template <int NC>
+__device__ __forceinline__ void dw_load_columns(const double* Bg, const double* Tg, int n, int nP, int lane,
+                                                double (&C)[NC]) {
+  const bool bl = lane < n, tl = lane >= n && lane < n + nP;
+  const double* src = tl ? Tg + (lane - n) : Bg + (bl ? lane : 0);
+  const int str = tl ? nP : n;
+  const double own = (bl || tl) ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) C[j] = src[min(j, n - 1) * str] * (j < n ? own : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// row tiles
+// ---------------------------------------------------------------------------
+// Radial sums of NPT points for every shell (Gaussian shells only), from the
+// displacement table: MODE 0 stores g = sum c e^{-a r^2} and g1 = dg/d(r^2)
+// per shell (stride 2 nshell + 1 per point), MODE 1 the Laplacian factor
+// sum c e^{-a r^2} a (4 a r^2 - 2 (2l + 3)), so that the Laplacian of a basis
+// function is its angular polynomial times that factor (stride nshell | 1).
+// Each shell's terms are added in the order of its primitives.
+template <int NPT, int MODE>
+__device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
+#pragma clang fp contract(off)
+  const double* disp = l.L + wf.dw_disp;
+  double* gt = l.L + wf.dw_gtab;
+  const int ds = 4 * wf.nnuc + 1;
+  const int gs = MODE == 0 ? 2 * wf.nshell + 1 : (wf.nshell | 1);
+  const double* etab = l.L + wf.l_etab;
+  const float rn = 1.0f / (float)wf.nshell;
+  for (int idx = threadIdx.x; idx < NPT * wf.nshell; idx += kDwNT) {
+    const int p = div_small(idx, rn), sh = idx - p * wf.nshell;
+    const int* si = l.sh() + 8 * sh;
+    const double r2 = disp[p * ds + 4 * si[0] + 3];
+    const int k0 = si[4], nk = si[5];
+    const double c2l = (double)(2 * (2 * si[2] + 3));
+    double g = 0.0, g1 = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      const double a = l.pe()[k0 + k];
+      const double t = a * r2;
+      if (t < 50.0) {
+        const double ex = l.pc()[k0 + k] * exp_neg<double>(t, etab);
+        if constexpr (MODE == 0) {
+          g += ex;
+          g1 -= a * ex;
+        } else {
+          g += ex * a * (4.0 * t - c2l);
+        }
+      }
+    }
+    if constexpr (MODE == 0) {
+      gt[p * gs + 2 * sh] = g;
+      gt[p * gs + 2 * sh + 1] = g1;
+    } else {
+      gt[p * gs + sh] = g;
+    }
+  }
+}
+
+// angular polynomial P of function (m, lq) at displacement (x, y, z) and its
+// derivative along axis c (0..2)
+__device__ __forceinline__ void dw_poly(int lq, int m, double x, double y, double z, int c, double& P, double& Pc) {
+  double Px = 0.0, Py = 0.0, Pz = 0.0;
+  if (lq == 0) {
+    P = 1.0;
+  } else if (lq == 1) {
+    P = m == 0 ? x : (m == 1 ? y : z);
+    Px = m == 0 ? 1.0 : 0.0;
+    Py = m == 1 ? 1.0 : 0.0;
+    Pz = m == 2 ? 1.0 : 0.0;
+  } else {
+    switch (m) {
+      case 0: P = x * y; Px = y; Py = x; break;
+      case 1: P = y * z; Py = z; Pz = y; break;
+      case 2: P = z * x; Px = z; Pz = x; break;
+      case 3: P = x * x - y * y; Px = 2.0 * x; Py = -2.0 * y; break;
+      default: P = 2.0 * z * z - x * x - y * y; Px = -2.0 * x; Py = -2.0 * y; Pz = 4.0 * z;
+    }
+  }
+  Pc = c == 0 ? Px : (c == 1 ? Py : Pz);
+}
+
+// One 16-row tile on MFMA: rows r = 4 p + c of the A operand are built on
+// the fly from the tables (MODE 0: channel c = value, d/dx, d/dy, d/dz of
+// point p; MODE 1: the Laplacian of point r), contracted with lambda^T;
+// wavefront g takes column tiles g, g + 4, ..  Output row 4 q + lane / 16
+// (register q) at orbital column p goes to out[row][slot] with
+// slot = cmap[p] (orbitals a spin does not use are dropped).
+template <int MODE>
+__device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int* cmap, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int p = MODE == 0 ? row >> 2 : row, c = row & 3;
+  const double* disp = l.L + wf.dw_disp + p * (4 * wf.nnuc + 1);
+  const double* gt = l.L + wf.dw_gtab + p * (MODE == 0 ? 2 * wf.nshell + 1 : (wf.nshell | 1));
+  const int nct = wf.nop / 16;
+  const double* lam = wf.lamT;
+  for (int ct = wave; ct < nct; ct += kDwW) {
+    const int col = ct * 16 + (lane & 15);
+    v4d acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+    for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + kq;
+        b[u] = lam[(size_t)k * wf.nop + col];
+        const FnInfo fi = fn_info(l, k);
+        double v = 0.0;
+        if (fi.sh >= 0) {
+          const double* d = disp + 4 * fi.nuc;
+          const double x = d[0], y = d[1], z = d[2];
+          double P, Pc;
+          if constexpr (MODE == 0) {
+            const double gg = gt[2 * fi.sh], g1 = gt[2 * fi.sh + 1];
+            dw_poly(fi.lq, fi.m, x, y, z, c == 0 ? 0 : c - 1, P, Pc);
+            const double dc = c == 1 ? x : (c == 2 ? y : z);
+            v = c == 0 ? P * gg : Pc * gg + 2.0 * g1 * P * dc;
+          } else {
+            dw_poly(fi.lq, fi.m, x, y, z, 0, P, Pc);
+            v = P * gt[fi.sh];
+          }
+        }
+        a[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+    const int slot = cmap[col];
+    if (slot >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[(4 * q + kq) * 64 + slot] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the step kernel
+// ---------------------------------------------------------------------------
+// prep = 1: rebuild each record from its positions (orbital-row caches of
+// every electron, fresh inverses, tables, ratios, E_L) with no move and no
+// weight; prep = 0: one DMC step.
+template <int NC, int XE>
+__global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dmcw(const DevWF* __restrict__ pwf, double* state, const double* ctrl,
+                                                uint64_t seed, uint32_t step, double tau, DmcBranch br, double* nacc,
+                                                int prep) {
+  const DevWF& wf = *pwf;
+  const int64_t W = (int64_t)ctrl[DC_W];
+  const int64_t wbase = (int64_t)blockIdx.x * kDwW;
+  if (ctrl[DC_ERR] != 0.0 || wbase >= W) return;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t w = wbase + g;
+  const bool live = w < W;
+  const int N = wf.N, nn = wf.nnuc, WD = wf.dw_width;
+  Ld l(lds_dyn, wf);
+  stage_tables<kDwNT, 0>(wf, l);
+  // column map of each spin: orbital -> slot (reference slot j, n + table
+  // index q, or -1)
+  int* cmap = (int*)(lds_dyn + wf.dw_cmap);
+  for (int k = threadIdx.x; k < 2 * wf.nop; k += kDwNT) cmap[k] = -1;
+  __syncthreads();
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& sp = wf.sp[s];
+    for (int j = threadIdx.x; j < sp.n + sp.nP; j += kDwNT)
+      cmap[s * wf.nop + (j < sp.n ? sp.ref[j] : sp.porb[j - sp.n])] = j;
+  }
+  double* wa = lds_dyn + wf.dw_wave + g * wf.dw_wstride;  // this walker's area
+  double* Rl = wa + wf.dwo_R;     // positions [N][3]
+  double* bc = wa + wf.dwo_bc;    // column il of B (slot-indexed)
+  double* xr = wa + wf.dwo_x;     // broadcast rows [4][64] (slot-indexed)
+  double* yr = wa + wf.dwo_y;     // table residuals [4][64] (table-indexed)
+  double* Pw = lds_dyn + wf.dw_P; // per walker: proposal x, y, z, drift x, y, z
+  double* V4 = lds_dyn + wf.dw_V4;
+  // records of dead wavefronts (past W) are never read or written
+  double* rec = state + (live ? w : wbase) * wf.rec_len;
+  for (int k = lane; k < 3 * N; k += 64) Rl[k] = rec[wf.r_R + k];
+  // broadcast rows start finite (dw_dot reads all NC entries)
+  for (int k = lane; k < 64; k += 64) bc[k] = 0.0;
+  for (int k = lane; k < 4 * 64; k += 64) {
+    xr[k] = 0.0;
+    yr[k] = 0.0;
+  }
+  for (int k = threadIdx.x; k < 16 * 64; k += kDwNT) V4[k] = 0.0;
+  const int n0 = wf.sp[0].nU, n1 = wf.sp[1].nU;
+  double* RW = rec + wf.r_RW;
+  double S = RW[2 * (n0 + n1)];
+  const double E_old = rec[wf.r_sc + SC_ELOC];
+  bool bad = !live || (!prep && (rec[wf.r_sc + SC_FLAGS] != 0.0 || !(S != 0.0)));
+  double na = 0.0;
+  const double ET = ctrl[DC_ET];
+  const double sqt = sqrt(tau);
+  const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
+  const double kappa = wf.kappa;
+  double* vc = rec + wf.r_vc;  // value rows [N][WD]
+  double* gc = rec + wf.r_gc;  // gradient rows [N][3][WD]
+  __syncthreads();
+
+  // ---- prep: orbital-row caches at every electron's position ----
+  if (prep) {
+#pragma unroll 1
+    for (int i = 0; i < N; ++i) {
+      const int s = spin_of(wf, i);
+      if (lane < 3) Pw[6 * g + lane] = live ? Rl[3 * i + lane] : 0.0;
+      __syncthreads();
+      for (int t = threadIdx.x; t < kDwW * nn; t += kDwNT) {
+        const int p = t / nn, a = t - p * nn;
+        const double* nu = l.nuc() + 4 * a;
+        double* d = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
+        const double x = Pw[6 * p] - nu[0], y = Pw[6 * p + 1] - nu[1], z = Pw[6 * p + 2] - nu[2];
+        d[0] = x; d[1] = y; d[2] = z; d[3] = x * x + y * y + z * z;
+      }
+      __syncthreads();
+      dw_radial<kDwW, 0>(wf, l);
+      __syncthreads();
+      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4);
+      __syncthreads();
+      if (live)
+        for (int k = lane; k < WD; k += 64) {
+          vc[(size_t)i * WD + k] = V4[(4 * g) * 64 + k];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gc[((size_t)i * 3 + c) * WD + k] = V4[(4 * g + 1 + c) * 64 + k];
+        }
+      __syncthreads();
+    }
+  }
+
+  // ---- moves, spin by spin ----
+  double C[NC];
+  DwDets<XE> d;
+#pragma unroll 1
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& sp = wf.sp[s];
+    const int n = sp.n, nP = sp.nP, e0 = sp.e0;
+    if (n == 0) continue;
+    const bool blane = lane < n, tlane = lane >= n && lane < n + nP;
+    double* Bg = rec + wf.r_B[s];
+    double* Tg = rec + wf.r_T[s];
+    double* Ru = RW + (s ? n0 : 0);
+    double* Wu = RW + n0 + n1 + (s ? n0 : 0);
+    // this spin's log|reference determinant|, its sign and update count
+    double ldS = rec[wf.r_sc + SC_LOGDET0 + s];
+    double sgS = rec[wf.r_sc + SC_SGN0 + s];
+    double nuS = prep ? (double)wf.refresh_every : rec[wf.r_sc + SC_NUPD0 + s];
+    dw_load_columns<NC>(Bg, Tg, n, nP, lane, C);
+    dw_load_dets(sp, Tg, Ru, Wu, lane, d);
+    for (int il = 0; il < n && !prep; ++il) {
+      const int i = e0 + il;
+      const bool act = !bad;
+      // (A) drift at the current point from the cached gradient rows
+      if (act) {
+        for (int k = lane; k < WD; k += 64)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xr[c * 64 + k] = gc[((size_t)i * 3 + c) * WD + k];
+        if (lane == il)
+#pragma unroll
+          for (int j = 0; j < NC; ++j) bc[j] = C[j];
+        wave_sync();
+        double t[3], rp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          t[c] = dw_dot<NC>(xr + c * 64, C);
+          rp[c] = dw_readlane(t[c], il);
+          if (tlane) yr[c * 64 + (lane - n)] = xr[c * 64 + lane] - t[c];
+        }
+        wave_sync();
+        double part[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[c] = dw_detsum(d, rp[c], yr + c * 64, bc);
+        part[3] = part[4] = part[5] = 0.0;
+        const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
+        for (int j = lane; j < N + nn; j += 64) {
+          if (j == i) continue;
+          double xj, yj, zj;
+          PairCoef cf;
+          if (j < N) {
+            xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
+            cf = s != spin_of(wf, j) ? c_anti : c_par;
+          } else {
+            const double* nu = l.nuc() + 4 * (j - N);
+            xj = nu[0]; yj = nu[1]; zj = nu[2];
+            cf = en_coef(l.en() + 6 * (j - N));
+          }
+          const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+          const double r = sqrt(dx * dx + dy * dy + dz * dz);
+          double u, u1, u2;
+          pair_fn(r, kappa, cf, u, u1, u2);
+          const double f = u1 / r;
+          part[3] += f * dx;
+          part[4] += f * dy;
+          part[5] += f * dz;
+        }
+        dw_wsum<6>(part);
+        if (lane == 0) {
+          double v[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] = part[3 + c] + part[c] / S;
+          double a0, a1, b0, b1;
+          philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
+          philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
+          const double two_pi = 6.283185307179586476925286766559;
+          const double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
+          const double zx = r0 * cos(two_pi * a1), zy = r0 * sin(two_pi * a1), zz = r1 * cos(two_pi * b1);
+          Pw[6 * g] = xi + tau * v[0] + sqt * zx;
+          Pw[6 * g + 1] = yi + tau * v[1] + sqt * zy;
+          Pw[6 * g + 2] = zi + tau * v[2] + sqt * zz;
+          Pw[6 * g + 3] = v[0];
+          Pw[6 * g + 4] = v[1];
+          Pw[6 * g + 5] = v[2];
+        }
+      } else if (lane < 3) {
+        Pw[6 * g + lane] = 0.0;
+      }
+      __syncthreads();
+      // (B) value and gradient rows at the four proposals
+      for (int t2 = threadIdx.x; t2 < kDwW * nn; t2 += kDwNT) {
+        const int p = t2 / nn, a = t2 - p * nn;
+        const double* nu = l.nuc() + 4 * a;
+        double* dd = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
+        const double x = Pw[6 * p] - nu[0], y = Pw[6 * p + 1] - nu[1], z = Pw[6 * p + 2] - nu[2];
+        dd[0] = x; dd[1] = y; dd[2] = z; dd[3] = x * x + y * y + z * z;
+      }
+      __syncthreads();
+      dw_radial<kDwW, 0>(wf, l);
+      __syncthreads();
+      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4);
+      __syncthreads();
+      // (C) ratio, node check, drift at the proposal, Green's function,
+      // Metropolis decision and the Sherman-Morrison update
+      if (act) {
+        const double* vr = V4 + (4 * g) * 64;  // rows value, x, y, z
+        // value channel first; the gradient channels only once the ratio
+        // passes the node check
+        const double t0 = dw_dot<NC>(vr, C);
+        const double rho = dw_readlane(t0, il);
+        const double yv = tlane ? vr[lane] - t0 : 0.0;
+        if (tlane) yr[lane - n] = yv;
+        wave_sync();
+        double qh[2], part[2] = {0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double yy[XE], bb[XE];
+          dw_gather<XE>(d, h, yr, bc, yy, bb);
+          qh[h] = rho * d.R[h] + dw_adj<XE>(d.e[h], d.m[h], yy, bb);
+          part[0] += qh[h] * d.W[h];
+        }
+        const double px = Pw[6 * g], py = Pw[6 * g + 1], pz = Pw[6 * g + 2];
+        const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
+        double jg[3] = {0.0, 0.0, 0.0};
+        for (int j = lane; j < N + nn; j += 64) {
+          if (j == i) continue;
+          double xj, yj, zj;
+          PairCoef cf;
+          if (j < N) {
+            xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
+            cf = s != spin_of(wf, j) ? c_anti : c_par;
+          } else {
+            const double* nu = l.nuc() + 4 * (j - N);
+            xj = nu[0]; yj = nu[1]; zj = nu[2];
+            cf = en_coef(l.en() + 6 * (j - N));
+          }
+          const double dx = px - xj, dy = py - yj, dz = pz - zj;
+          const double rn = sqrt(dx * dx + dy * dy + dz * dz);
+          const double ro = sqrt((xi - xj) * (xi - xj) + (yi - yj) * (yi - yj) + (zi - zj) * (zi - zj));
+          double u, u1, u2;
+          pair_fn(rn, kappa, cf, u, u1, u2);
+          part[1] += u - pair_val(ro, kappa, cf);
+          const double f = u1 / rn;
+          jg[0] += f * dx;
+          jg[1] += f * dy;
+          jg[2] += f * dz;
+        }
+        dw_wsum<2>(part);
+        const double rdet = part[0] / S, dU = part[1];
+        bool accept = false;
+        const double ir = 1.0 / rho;
+        if (rdet > 0.0 && rho != 0.0) {
+          // drift at r' with the state after the move: B'[:, il] = bc / rho,
+          // T' = T + bc y^T / rho, R'_u = Q_u / rho, S' = S rdet / rho
+          const double Snew = S * rdet / rho;
+          double a[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double tc = dw_dot<NC>(vr + (1 + c) * 64, C);
+            a[c] = dw_readlane(tc, il);
+            if (tlane) yr[(1 + c) * 64 + (lane - n)] = vr[(1 + c) * 64 + lane] - tc - a[c] * yv * ir;
+          }
+          wave_sync();
+          double dp[6] = {0.0, 0.0, 0.0, jg[0], jg[1], jg[2]};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            double yy0[XE], bb[XE], mm[XE * XE];
+            dw_gather<XE>(d, h, yr, bc, yy0, bb);
+#pragma unroll
+            for (int r = 0; r < XE; ++r) {
+#pragma unroll
+              for (int c2 = 0; c2 < XE; ++c2) mm[r * XE + c2] = d.m[h][r * XE + c2] + bb[r] * yy0[c2] * ir;
+              bb[r] *= ir;
+            }
+            const double Rnew = qh[h] * ir;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              double yy[XE], bz[XE];
+              dw_gather<XE>(d, h, yr + (1 + c) * 64, bc, yy, bz);
+              dp[c] += (a[c] * ir * Rnew + dw_adj<XE>(d.e[h], mm, yy, bb)) * d.W[h];
+            }
+          }
+          dw_wsum<6>(dp);
+          double fwd = 0.0, bwd = 0.0;
+          const double dd3[3] = {px - xi, py - yi, pz - zi};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double vn = dp[3 + c] + dp[c] / Snew;
+            const double fa = dd3[c] - tau * Pw[6 * g + 3 + c];
+            const double ba = -dd3[c] - tau * vn;
+            fwd += fa * fa;
+            bwd += ba * ba;
+          }
+          const double prob = rdet * rdet * exp(2.0 * dU + (fwd - bwd) / (2.0 * tau));
+          double ua, dummy;
+          philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
+          accept = ua < prob;
+        }
+        if (accept) {
+          double f = 0.0;
+          if (blane) f = -(t0 - (lane == il ? 1.0 : 0.0)) * ir;
+          else if (tlane) f = yv * ir;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) C[j] += bc[j] * f;
+          double vs[1] = {0.0};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            double yy0[XE], bb[XE];
+            dw_gather<XE>(d, h, yr, bc, yy0, bb);
+            // (bb and yy0 are zero past e: the unused entries stay zero)
+#pragma unroll
+            for (int r = 0; r < XE; ++r)
+#pragma unroll
+              for (int c2 = 0; c2 < XE; ++c2) d.m[h][r * XE + c2] += bb[r] * (yy0[c2] * ir);
+            d.R[h] = dw_det<XE>(d.e[h], d.m[h]);
+            vs[0] += d.R[h] * d.W[h];
+          }
+          dw_wsum<1>(vs);
+          S = vs[0];
+          ldS += log(fabs(rho));
+          if (rho < 0) sgS = -sgS;
+          nuS += 1.0;
+          na += 1.0;
+          if (!(S != 0.0)) bad = true;
+          for (int k = lane; k < WD; k += 64) {
+            vc[(size_t)i * WD + k] = vr[k];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gc[((size_t)i * 3 + c) * WD + k] = vr[(1 + c) * 64 + k];
+          }
+          wave_sync();
+          if (lane == 0) {
+            Rl[3 * i] = px;
+            Rl[3 * i + 1] = py;
+            Rl[3 * i + 2] = pz;
+          }
+        }
+        wave_sync();
+      }
+    }
+    // ---- inverse refresh of this spin from the cached value rows ----
+    __syncthreads();  // the refresh matrices overlay the row-tile tables
+    const bool due = !bad && nuS >= (double)wf.refresh_every;
+    if (due) {
+      double* A = lds_dyn + wf.dw_A + g * wf.dw_Astride;
+      int* piv = (int*)(wa + wf.dwo_piv);
+      double* fz = wa + wf.dwo_f;
+      for (int k = lane; k < n * n; k += 64) {
+        const int ii = k / n, j = k - ii * n;
+        A[k] = vc[(size_t)(e0 + ii) * WD + j];
+      }
+      // the row dot products below read up to NC entries from the last row
+      // start: the 64 doubles past the matrix are part of this area, zeroed
+      A[n * n + lane] = 0.0;
+      wave_sync();
+      double ld = 0.0, sg = 1.0;
+      const bool ok = gj_invert_h<64>(A, n, lane, piv, fz, ld, sg);
+      if (!ok) {
+        bad = true;
+      } else {
+        // B to the reference lanes; T = B PP on the table lanes (lane n + q
+        // takes column q of PP from its cached values, one row at a time);
+        // row indices clamped into the matrix, rows past n masked to zero
+        const double bm = blane ? 1.0 : 0.0, tm = tlane ? 1.0 : 0.0;
+        const int kl = blane ? lane : 0;
+        double pp[NC];  // column q of PP on table lane n + q (zero elsewhere)
+#pragma unroll
+        for (int ii = 0; ii < NC; ++ii)
+          pp[ii] = vc[(size_t)(e0 + min(ii, n - 1)) * WD + (tlane ? lane : 0)] * (ii < n ? tm : 0.0);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const double* Aj = A + min(j, n - 1) * n;
+          double v = Aj[kl] * bm;
+          if (tlane) v = dw_dot<NC>(Aj, pp);
+          C[j] = j < n ? v : 0.0;
+        }
+        wave_sync();
+        // the new table, for the minors (rows past n are not written)
+        if (tlane)
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (j < n) A[j * nP + (lane - n)] = C[j];
+        wave_sync();
+        double vs[1] = {0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int u = lane + 64 * h;
+#pragma unroll
+          for (int r = 0; r < XE; ++r)
+#pragma unroll
+            for (int c2 = 0; c2 < XE; ++c2) {
+              const double v = A[d.J[h][r] * nP + d.Q[h][c2]];
+              d.m[h][r * XE + c2] = (r < d.e[h] && c2 < d.e[h]) ? v : 0.0;
+            }
+          d.R[h] = u < sp.nU ? dw_det<XE>(d.e[h], d.m[h]) : 0.0;
+          vs[0] += d.R[h] * d.W[h];
+        }
+        dw_wsum<1>(vs);
+        S = vs[0];
+        ldS = ld;
+        sgS = sg;
+        nuS = 0.0;
+      }
+    }
+    __syncthreads();
+    // the refresh matrices overwrote the row tiles: clear the rows again
+    if (__syncthreads_or(due))
+      for (int k = threadIdx.x; k < 16 * 64; k += kDwNT) V4[k] = 0.0;
+    // ---- this spin's state back to the record; the other spin's W ----
+    if (live) {
+      if (lane == 0) {
+        rec[wf.r_sc + SC_LOGDET0 + s] = ldS;
+        rec[wf.r_sc + SC_SGN0 + s] = sgS;
+        rec[wf.r_sc + SC_NUPD0 + s] = nuS;
+      }
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j < n) {
+          if (blane) Bg[j * n + lane] = C[j];
+          else if (tlane) Tg[j * nP + (lane - n)] = C[j];
+        }
+      double* Rs = xr;  // R_u of this spin, for the partner sums
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int u = lane + 64 * h;
+        if (u < sp.nU) {
+          Ru[u] = d.R[h];
+          Rs[u] = d.R[h];
+        }
+      }
+      wave_sync();
+      const int o = 1 - s;
+      const SpinTab& so = wf.sp[o];
+      double* Wo = RW + n0 + n1 + (o ? n0 : 0);
+      for (int u = lane; u < so.nU; u += 64) {
+        double a = 0.0;
+        for (int k = so.wrow[u]; k < so.wrow[u + 1]; ++k) a += so.wcoef[k] * Rs[so.wother[k]];
+        Wo[u] = a;
+      }
+      wave_sync();
+    }
+  }
+  if (!(S != 0.0)) bad = true;
+
+  // ---- local energy (Eq. Elav with Psi = e^U D) ----
+  // spin 1's columns are in registers after the moves: its electrons first
+  double tsum = 0.0, vsum = 0.0;
+#pragma unroll 1
+  for (int s2 = 1; s2 >= 0; --s2) {
+    const SpinTab& sp = wf.sp[s2];
+    const int n = sp.n, nP = sp.nP, e0 = sp.e0;
+    if (n == 0) continue;
+    const bool tlane = lane >= n && lane < n + nP;
+    if (s2 == 0) {
+      // spin 0's columns and determinants as its moves left them (its W from
+      // spin 1's final ratios)
+      const double* Tg = rec + wf.r_T[0];
+      dw_load_columns<NC>(rec + wf.r_B[0], Tg, n, nP, lane, C);
+      dw_load_dets(sp, Tg, RW, RW + n0 + n1, lane, d);
+    }
+#pragma unroll 1
+    for (int i0 = 0; i0 < n; i0 += 4) {
+      // Laplacian rows of electrons e0 + i0 .. + 3 of the four walkers
+      if (threadIdx.x < 3 * 16) {
+        const int p = threadIdx.x / 3, c = threadIdx.x - 3 * p;
+        const int gw = p >> 2, il = i0 + (p & 3);
+        const double* Rg = lds_dyn + wf.dw_wave + gw * wf.dw_wstride + wf.dwo_R;
+        Pw[24 + 3 * p + c] = il < n ? Rg[3 * (e0 + il) + c] : 0.0;
+      }
+      __syncthreads();
+      for (int t2 = threadIdx.x; t2 < 16 * nn; t2 += kDwNT) {
+        const int p = t2 / nn, a = t2 - p * nn;
+        const double* nu = l.nuc() + 4 * a;
+        double* dd = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
+        const double x = Pw[24 + 3 * p] - nu[0], y = Pw[24 + 3 * p + 1] - nu[1], z = Pw[24 + 3 * p + 2] - nu[2];
+        dd[0] = x; dd[1] = y; dd[2] = z; dd[3] = x * x + y * y + z * z;
+      }
+      __syncthreads();
+      dw_radial<16, 1>(wf, l);
+      __syncthreads();
+      dw_mfma<1>(wf, l, cmap + s2 * wf.nop, V4);
+      __syncthreads();
+      if (!bad) {
+#pragma unroll 1
+        for (int e4 = 0; e4 < 4 && i0 + e4 < n; ++e4) {
+          const int il = i0 + e4, i = e0 + il;
+          for (int k = lane; k < WD; k += 64)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xr[c * 64 + k] = gc[((size_t)i * 3 + c) * WD + k];
+          if (lane == il)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) bc[j] = C[j];
+          wave_sync();
+          const double* lrow = V4 + (4 * g + e4) * 64;
+          double t[4], rp[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double* row = c < 3 ? xr + c * 64 : lrow;
+            t[c] = dw_dot<NC>(row, C);
+            rp[c] = dw_readlane(t[c], il);
+            if (tlane) yr[c * 64 + (lane - n)] = row[lane] - t[c];
+          }
+          wave_sync();
+          double part[9];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) part[c] = dw_detsum(d, rp[c], yr + c * 64, bc);
+#pragma unroll
+          for (int c = 4; c < 9; ++c) part[c] = 0.0;
+          const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
+          for (int j = lane; j < N + nn; j += 64) {
+            if (j == i) continue;
+            double xj, yj, zj, wv;
+            PairCoef cf;
+            if (j < N) {
+              xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
+              cf = s2 != spin_of(wf, j) ? c_anti : c_par;
+              wv = 0.5;
+            } else {
+              const double* nu = l.nuc() + 4 * (j - N);
+              xj = nu[0]; yj = nu[1]; zj = nu[2];
+              cf = en_coef(l.en() + 6 * (j - N));
+              wv = -nu[3];
+            }
+            const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz), irr = 1.0 / r;
+            double u, u1, u2;
+            pair_fn(r, kappa, cf, u, u1, u2);
+            const double f = u1 * irr;
+            part[4] += f * dx;
+            part[5] += f * dy;
+            part[6] += f * dz;
+            part[7] += u2 + 2.0 * f;
+            part[8] += wv * irr;
+          }
+          dw_wsum<9>(part);
+          const double iS = 1.0 / S;
+          const double gx = part[4], gy = part[5], gz = part[6];
+          tsum += part[7] + part[3] * iS + gx * gx + gy * gy + gz * gz +
+                  2.0 * (gx * part[0] + gy * part[1] + gz * part[2]) * iS;
+          vsum += part[8];
+          wave_sync();
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- E_L, weight, record scalars ----
+  if (live && lane == 0) {
+    const double En = bad ? NAN : -0.5 * tsum + vsum + wf.vnn;
+    if (!prep) {
+      dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, N, seed, step);
+      nacc[w] = na;
+    }
+    double* sc = rec + wf.r_sc;
+    sc[SC_ELOC] = En;
+    sc[SC_FLAGS] = bad ? 1.0 : 0.0;
+    RW[2 * (n0 + n1)] = S;
+  }
+  if (live)
+    for (int k = lane; k < 3 * N; k += 64) rec[wf.r_R + k] = Rl[k];
+}
+
+template <int NC, int XE>
+static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                                uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
+                                hipStream_t s) {
+  const size_t lds = (size_t)wf.lds_dmcw_doubles * sizeof(double);
+  static size_t cur = 0;
+  if (lds > cur) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_dmcw<NC, XE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    cur = lds;
+  }
+  const unsigned blocks = (unsigned)((cap + kDwW - 1) / kDwW);
+  hipLaunchKernelGGL((k_dmcw<NC, XE>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau, br,
+                     nacc, prep);
+  return hipGetLastError();
+}
+
+// one DMC step (prep = 0) or the rebuild of every record from its positions
+// (prep = 1) for the walkers of ctrl[DC_W] in state; wf is the host copy of
+// the layout in dwf (dw_xe: the most columns a determinant replaces)
+hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                       uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
+                       hipStream_t s) {
+  if (wf.dw_xe <= 2) return launch_dmcw_t<32, 2>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s);
+  return launch_dmcw_t<32, 3>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s);
+}
+
+}  // namespace vbqmc

@@ -46,6 +46,9 @@ hipError_t launch_dmcb_move(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
                             double* ctrl, int64_t cap, int i, uint64_t seed, uint32_t step, double tau, double* P,
                             double* V, double* Vp, double* nacc, hipStream_t s);
 hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                       uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
+                       hipStream_t s);
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
 hipError_t launch_reduce(int64_t W, int K, const double* wts, const double* in, double* out, hipStream_t s);
@@ -158,7 +161,8 @@ struct vbqmc_ctx {
   DevWF* d_wf_rows = nullptr;   // same tables, layout of the row step kernel (four walkers per wavefront)
   int step_kernel = 1;          // single-electron VMC steps: 1 sweep + local-energy kernels, 2 row kernel
   DevWF* d_wf_dmcb = nullptr;   // same tables, layout of the electron-major DMC row tiles
-  int dmc_kernel = 1;           // DMC steps: 1 one workgroup per walker, 2 electron-major launches
+  int dmc_kernel = 1;           // DMC steps: 1 one workgroup per walker, 2 electron-major, 3 walker-resident
+  DevWF* d_wf_dmcw = nullptr;   // same tables, layout of the walker-resident DMC kernel
   double* d_timg = nullptr;     // LDS table image
   int dev = 0;                  // device the context was created on
   void* scratch = nullptr;      // that device's copy of the no-alloc scratch array
@@ -501,6 +505,57 @@ bool dmcb_fit(const vbqmc_ctx* x) {
          refresh * 8 <= (size_t)x->lds_limit;
 }
 
+// Walker-resident DMC (four walkers per workgroup, one per wavefront): the
+// tables up to the Jastrow coefficients, proposals, column maps, one area per
+// wavefront, then the row-tile tables and rows, overlaid by the refresh
+// matrices.
+DevWF dmcw_layout(const vbqmc_ctx* x) {
+  DevWF a = x->wf;
+  LdsAlloc lds{a.l_ref[0]};
+  a.timg_len = lds.o;
+  a.lam_in_lds = 0;
+  a.dw_P = lds(24 + 48);
+  a.dw_cmap = lds.ints(2 * x->nop);
+  a.dw_wave = lds.o;
+  LdsAlloc w{0};
+  a.dwo_R = w(3 * x->N);
+  a.dwo_bc = w(64);
+  a.dwo_x = w(4 * 64);
+  a.dwo_y = w(4 * 64);
+  a.dwo_piv = w.ints(64);
+  a.dwo_f = w(64);
+  a.dw_wstride = w.o;
+  lds.o += 4 * a.dw_wstride;
+  const int t0 = lds.o;
+  a.dw_disp = lds(16 * (4 * x->nnuc + 1));
+  a.dw_gtab = lds(std::max(4 * (2 * x->nshell + 1), 16 * (x->nshell | 1)));
+  a.dw_V4 = lds(16 * 64);
+  const int tend = lds.o;
+  lds.o = t0;
+  int astr = 1;
+  for (int sp = 0; sp < 2; ++sp)
+    astr = std::max(astr, x->sp[sp].n * std::max(x->sp[sp].n, (int)x->sp[sp].porb.size()));
+  a.dw_Astride = (astr + 64 + 1) / 2 * 2;  // the matrix and 64 zeroed doubles past it
+  a.dw_A = lds(4 * a.dw_Astride);
+  a.lds_dmcw_doubles = std::max(tend, lds.o);
+  return a;
+}
+
+// the walker-resident DMC kernel handles the system: FP64 rows, Gaussian
+// shells, at most 32 electrons, 64 reference slots plus table orbitals and 128 distinct
+// determinants per spin, at most 64 (padded) orbitals, spin-up electrons
+// present, and its layout fits the device's LDS
+bool dmcw_fit(const vbqmc_ctx* x) {
+  if (x->wf.precision != VBQMC_FP64 || x->wf.trial_prec != VBQMC_FP64 || x->wf.refresh_each_step) return false;
+  if (x->nop > 64 || x->nup < 1 || x->nup > 32 || x->ndn > 32) return false;
+  for (int sh = 0; sh < x->nshell; ++sh)
+    if (x->shtab[8 * sh + 1] != 0) return false;
+  for (int sp = 0; sp < 2; ++sp) {
+    if (x->sp[sp].n + (int)x->sp[sp].porb.size() > 64 || x->sp[sp].sets.size() > 128) return false;
+  }
+  return (size_t)dmcw_layout(x).lds_dmcw_doubles * 8 <= (size_t)x->lds_limit;
+}
+
 // the row step kernel handles the system: at most 16 columns (reference
 // slots + table orbitals) and 16 distinct determinants per spin, at most 24
 // electrons, and its layout fits the device's LDS
@@ -627,6 +682,10 @@ int upload_coefficients(vbqmc_ctx* x) {
   if (e == hipSuccess && x->d_wf_dmcb && x->dmc_kernel == 2) {
     DevWF a = dmcb_layout(x);
     e = hipMemcpy(x->d_wf_dmcb, &a, sizeof(DevWF), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && x->d_wf_dmcw && x->dmc_kernel == 3) {
+    DevWF a = dmcw_layout(x);
+    e = hipMemcpy(x->d_wf_dmcw, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess && x->d_wf_rows && x->step_kernel == 2) {
     DevWF a = rows_layout(x);
@@ -869,6 +928,13 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // gradient cache of the DMC kernel, or the per-electron local-energy terms
   // and structure ratios of the batched local energy
   wf.r_gc = rec(std::max(3 * x->N * x->nop, 4 * x->N + x->nstruct));
+  // value rows of the walker-resident DMC kernel (its gradient rows use r_gc)
+  wf.dw_width = 1;
+  for (int s = 0; s < 2; ++s) wf.dw_width = std::max(wf.dw_width, x->sp[s].n + (int)x->sp[s].porb.size());
+  wf.r_vc = rec(x->N * wf.dw_width);
+  wf.dw_xe = 0;
+  for (int s = 0; s < 2; ++s)
+    for (size_t u = 0; u < x->sp[s].sets.size(); ++u) wf.dw_xe = std::max(wf.dw_xe, x->sp[s].uinfo[8 * u]);
   wf.r_bk = rec(wf.hot_len);
   wf.rec_len = (o + 31) / 32 * 32;
   // LDS: constant tables, walker state, scratch (offsets in doubles, each
@@ -1041,10 +1107,14 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
       x->dmc_kernel = 2;
     } else if (req == 1) {
       x->dmc_kernel = 1;
+    } else if (req == 3) {
+      if (!dmcw_fit(x)) return bad("dmc_kernel 3: the system does not fit the walker-resident DMC kernel");
+      x->dmc_kernel = 3;
     } else if (req == 0) {
-      x->dmc_kernel = (size_t)wf.lds_doubles * 8 > 40960 && dmcb_fit(x) ? 2 : 1;
+      if (dmcw_fit(x)) x->dmc_kernel = 3;
+      else x->dmc_kernel = (size_t)wf.lds_doubles * 8 > 40960 && dmcb_fit(x) ? 2 : 1;
     } else {
-      return bad("dmc_kernel must be 0, 1 or 2");
+      return bad("dmc_kernel must be 0, 1, 2 or 3");
     }
   }
 
@@ -1060,7 +1130,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.wother.size(), 4); add(h.wother.size(), 8); add((size_t)x->nop, 4);
   }
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
-  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
+  add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
   add((size_t)wf.timg_len, 8);
   he = hipMalloc((void**)&x->dmem, bytes);
   if (he != hipSuccess) { delete x; return VBQMC_ENOMEM; }
@@ -1104,6 +1174,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_wf_sweepg = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_rows = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_dmcb = (DevWF*)carve<char>(p, sizeof(DevWF));
+  x->d_wf_dmcw = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_timg = carve<double>(p, (size_t)wf.timg_len);
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
@@ -1364,7 +1435,9 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
   double* epw = ekw + cap;
   // rebuild every record from its positions (fresh inverses, local energy and
   // the orbital-gradient rows the drift of the first moves reads)
-  if (x->dmc_kernel == 2)
+  if (x->dmc_kernel == 3)
+    e = launch_dmcw(dmcw_layout(x), x->d_wf_dmcw, cur, ctrl, cap, seed, 0, tau, br, nacc, 1, s);
+  else if (x->dmc_kernel == 2)
     e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, (size_t)dmcb_layout(x).lds_tile_doubles * 8, cur, ctrl, cap,
                            seed, 0, tau, Vpw, ekw, epw, br, 1, s);
   else
@@ -1373,7 +1446,9 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
-    if (x->dmc_kernel == 2) {
+    if (x->dmc_kernel == 3) {
+      e = launch_dmcw(dmcw_layout(x), x->d_wf_dmcw, cur, ctrl, cap, seed, step, tau, br, nacc, 0, s);
+    } else if (x->dmc_kernel == 2) {
       const size_t rows_lds = (size_t)dmcb_layout(x).lds_tile_doubles * 8;
       for (int i = 0; i < x->N && e == hipSuccess; ++i)
         e = launch_dmcb_move(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, i, seed, step, tau, Pw, Vw,

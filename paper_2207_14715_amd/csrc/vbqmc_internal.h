@@ -100,6 +100,20 @@ struct DevWF {
   // (reference slots, then table orbitals), rows_vw doubles per row, placed
   // by the column map l_cmap ([spin][orbital] -> position or -1)
   int l_cmap, rows_vw;
+  // walker-resident DMC (four walkers per workgroup, one per wavefront):
+  // record caches of the value rows r_vc [N][dw_width] and gradient rows
+  // r_gc [N][3][dw_width] at the electrons' positions, in slot order
+  // (reference slots, then table orbitals; dw_width = max over spins of
+  // n + nP); per wavefront an area at dw_wave + g dw_wstride holding
+  // positions (dwo_R), a column of B (dwo_bc), broadcast rows [4][64]
+  // (dwo_x), table residuals [4][64] (dwo_y) and the pivots and column of a
+  // refresh (dwo_piv, dwo_f); shared: proposals and drifts [4][6] then
+  // local-energy points [16][3] (dw_P), the column maps [2][nop] (dw_cmap),
+  // the row-tile tables (dw_disp [16][4 nnuc + 1], dw_gtab) and rows
+  // (dw_V4 [16][64]), overlaid by the refresh matrices dw_A + g dw_Astride
+  int dw_width, r_vc, dw_xe;  // dw_xe: the most columns a spin determinant replaces
+  int dw_wave, dw_wstride, dwo_R, dwo_bc, dwo_x, dwo_y, dwo_piv, dwo_f;
+  int dw_P, dw_cmap, dw_disp, dw_gtab, dw_V4, dw_A, dw_Astride, lds_dmcw_doubles;
 };
 
 // scalar slots in the record's / LDS scalar block

@@ -279,9 +279,21 @@ def test_vmc_rows_matches_split_kernels(lib):
         np.testing.assert_allclose(a[key].cpu().numpy(), b[key].cpu().numpy(), rtol=1e-9, atol=1e-9, err_msg=key)
 
 
-# DMC steps run with one workgroup per walker (1) or as electron-major
-# launches over all walkers (2); both must give the oracle's walks
-DMC_KERNELS = [1, 2]
+# DMC steps run with one workgroup per walker (1), as electron-major
+# launches over all walkers (2) or with four walkers resident per workgroup
+# (3); all must give the oracle's walks
+DMC_KERNELS = [1, 2, 3]
+
+
+def _dmc_context(lib, sysd, kern, **kw):
+    """A context on DMC kernel `kern`; skips where the walker-resident kernel
+    does not take the system (Slater shells, more than 32 electrons per spin)."""
+    try:
+        return lib.Context(sysd, dmc_kernel=kern, **kw)
+    except lib.VBQMCError as e:
+        if kern == 3 and e.code == -1:
+            pytest.skip("the walker-resident DMC kernel does not take this system")
+        raise
 
 
 def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3, dmc_kernel=0, et_median=False):
@@ -290,8 +302,8 @@ def _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, seed=77, step0=3, dmc_kernel
     R0 = S.initial_walkers(sysd, W, seed=8)
     e0 = o.evaluate(R0)["eloc"]
     et = float(np.median(e0) if et_median else np.mean(e0))
+    ctx = _dmc_context(lib, sysd, dmc_kernel)
     ref = o.dmc(R0, e0, steps, seed, step0, tau, et, W, capacity=4 * W)
-    ctx = lib.Context(sysd, dmc_kernel=dmc_kernel)
     print(f"[dmc] {sysd['name']} W={W} steps={steps} dmc_kernel={ctx.info['dmc_kernel']}", flush=True)
     st0 = ctx.new_state(4 * W)
     st1 = ctx.new_state(4 * W)
@@ -325,13 +337,23 @@ def _check_dmc(ref, out, R, e_rec=None, oracle_obj=None):
 @pytest.mark.parametrize("kern", DMC_KERNELS)
 def test_dmc_hydrogen_exact_population_constant(lib, oracle_mod, kern):
     import torch
-    sysd = S.hydrogen_sto_1s(1.0)
-    ctx = lib.Context(sysd, dmc_kernel=kern)
+    sysd = S.hydrogen_sto_1s(1.0) if kern != 3 else S.hydrogen_gaussian(0.3)
+    ctx = _dmc_context(lib, sysd, kern)
     print(f"[dmc exact H] dmc_kernel={kern}", flush=True)
     W = 512
     R0 = torch.from_numpy(np.random.default_rng(3).normal(size=(W, 1, 3))).cuda()
     st0, st1 = ctx.new_state(2 * W), ctx.new_state(2 * W)
     ctx.walkers_init(R0, st0)
+    if kern == 3:
+        # (no exact Gaussian trial: the walk is checked against the oracle)
+        o = oracle_mod.Oracle(sysd)
+        Rn = R0.cpu().numpy()
+        e0 = o.evaluate(Rn)["eloc"]
+        ref = o.dmc(Rn, e0, 20, 5, 0, 0.01, -0.5, W, capacity=2 * W)
+        out = ctx.dmc_advance([st0, st1], W, 20, 5, 0, 0.01, -0.5, W)
+        R = ctx.positions(st0, out["W"]).cpu().numpy()
+        _check_dmc(ref, out, R, ctx.record_eloc(st0, out["W"]).cpu().numpy(), o)
+        return
     out = ctx.dmc_advance([st0, st1], W, 20, 5, 0, 0.01, -0.5, W)
     assert out["W"] == W
     np.testing.assert_array_equal(out["pop"].cpu().numpy(), W)
@@ -381,7 +403,7 @@ def test_dmc_64_electron_molecule_trajectory(lib, oracle_mod, kern):
         _DMC64["ref"]["oracle"] = o
     import torch
     ref = _DMC64["ref"]
-    ctx = lib.Context(sysd, dmc_kernel=kern)
+    ctx = _dmc_context(lib, sysd, kern)
     assert ctx.info["n_unique_up"] > 64 and ctx.info["n_unique_dn"] > 64
     print(f"[dmc] {sysd['name']} W=8 steps=2 dmc_kernel={ctx.info['dmc_kernel']}", flush=True)
     st0, st1 = ctx.new_state(32), ctx.new_state(32)
