@@ -1,15 +1,19 @@
-"""Benchmark: VMC walker-moves per second (local energy every step) on one MI355X.
+"""Benchmark: DMC walker-moves per second (local energy every step) on one MI355X.
 
-Workload: the F2-shaped diatomic (two Z = 9 nuclei at z = -1.33, +1.33,
-9 up + 9 down electrons, 3s2p1d Gaussian basis per atom (28 functions),
-8 inactive + 2 active sigma orbitals, 3 VB structures / 4 determinant pairs,
-Pade Jastrow), 4096 walkers, single-electron Metropolis moves of 0.3 bohr with
-Sherman-Morrison updates, E_L after every step.  A step is one sweep of all
-18 electrons of every walker followed by the local energy of every walker;
-one walker-move is one walker advanced by one step.  Inputs are seeded and
-synthetic and already resident in device memory when timing starts.
+Default workload (the largest configuration that fits one GPU): fixed-node
+DMC on the 64-electron synthetic molecule -- 16 nuclei (Z in {1, 6, 8}),
+32 up + 32 down electrons, 240 contracted Gaussians (4s2p1d per atom),
+46 orbitals (30 inactive + 16 active), 32 VB structures / 128 determinant
+pairs (83 distinct spin determinants per spin), Pade Jastrow -- with 32768
+target walkers, tau = 0.005, per-electron drift-diffusion moves with
+Metropolis acceptance, E_L every step, branching with population control and
+on-device compaction, FP64.  One walker-move is one walker advanced by one
+step (64 single-electron moves and its local energy).  Inputs are seeded and
+synthetic and resident in device memory when timing starts.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
+Other forms: --form vmc (the F2-shaped VMC row kernel), precision, adjoint.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form ...]
 Prints one JSON line.
 """
 
@@ -117,9 +121,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 2000 for the headline, the form's own for the others)")
-    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default: 100, or the form's own)")
-    ap.add_argument("--walkers", type=int, default=4096)
+                    help="timed steps (default: 20 for the DMC headline, the form's own for the others)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default: 3, or the form's own)")
+    ap.add_argument("--walkers", type=int, default=None,
+                    help="walkers (target population for DMC; default: the workload's)")
     ap.add_argument("--steps-per-launch", type=int, default=100,
                     help="VMC steps per call (warm-up calls, and timed calls of the row kernel)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "mixed"],
@@ -129,16 +134,18 @@ def main():
     ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2],
                     help="single-electron step kernel: 0 library choice, 1 sweep + local-energy kernels, "
                          "2 row kernel")
-    ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2],
-                    help="DMC form: 0 library choice, 1 one workgroup per walker, 2 electron-major launches")
+    ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="DMC: 0 library choice, 1 one workgroup per walker, 2 electron-major launches, "
+                         "3 walker-resident")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-exponent", type=float, default=1e4,
                     help="precision form: cap on the Gaussian exponents of the molecule (default: the workload's 1e4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--form", default="plain", choices=["plain", "precision", "adjoint", "dmc"],
-                    help="plain: the headline VMC line; precision: FP32/BF16 basis+contraction form on the "
-                         "10-nucleus molecule; adjoint: parameter gradients on the 6-nucleus molecule")
+    ap.add_argument("--form", default="dmc", choices=["dmc", "vmc", "plain", "precision", "adjoint"],
+                    help="dmc: the headline DMC line on the 64-electron molecule; vmc (or plain): VMC on the "
+                         "F2-shaped diatomic; precision: FP32/BF16 basis+contraction forms on the 10-nucleus "
+                         "molecule; adjoint: parameter gradients on the 6-nucleus molecule")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the walker-parallel path would shard "
@@ -147,19 +154,7 @@ def main():
 
     import torch
 
-    import paper_2207_14715_amd as vb
-    import systems as S
-
     torch.cuda.set_device(0)
-    if args.form == "plain":
-        args.steps = 2000 if args.steps is None else args.steps
-        args.warmup = 100 if args.warmup is None else args.warmup
-    if args.form == "precision":
-        return precision_form(args)
-    if args.form == "adjoint":
-        return adjoint_form(args)
-    if args.form == "dmc":
-        return dmc_form(args)
     if args.calibrate_copy:
         n = 256 * 1024 * 1024 // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -168,6 +163,25 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
         return
+    if args.form == "precision":
+        return precision_form(args)
+    if args.form == "adjoint":
+        return adjoint_form(args)
+    if args.form == "dmc":
+        return dmc_form(args)
+    return vmc_form(args)
+
+
+def vmc_form(args):
+    """Single-electron VMC on the F2-shaped diatomic (18 electrons, 4096
+    walkers, row kernel): walker-moves/s with E_L every step."""
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    args.steps = 2000 if args.steps is None else args.steps
+    args.warmup = 100 if args.warmup is None else args.warmup
+    args.walkers = 4096 if args.walkers is None else args.walkers
     system = S.f2_shaped()
     W, step_size = args.walkers, 0.3
     ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes,
@@ -316,7 +330,7 @@ def precision_form(args):
     import paper_2207_14715_amd as vb
     import systems as S
     system = S.precision_molecule(max_exponent=args.max_exponent)
-    W = args.walkers if args.walkers != 4096 else 16384
+    W = args.walkers or 16384
     steps, step_size, seed = args.steps if args.steps is not None else 20, 0.3, 777
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=9)).cuda()
     c64 = vb.Context(system, precision="fp64", walker_lanes=args.walker_lanes)
@@ -369,7 +383,7 @@ def adjoint_form(args):
     import paper_2207_14715_amd as vb
     import systems as S
     system = S.adjoint_molecule()
-    W = args.walkers if args.walkers != 4096 else 8192
+    W = args.walkers or 8192
     ctx = vb.Context(system)
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=3)).cuda()
     st = ctx.walkers_init(R0)
@@ -395,21 +409,91 @@ def adjoint_form(args):
                                              "structures / 40 determinants, kappa = 0.8 Jastrow with polynomials"}}))
 
 
+HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"
+DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2>"}
+# HBM bytes of one launch of the walker-resident DMC step kernel on the
+# headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by the copy-kernel calibration (the factors below), with
+# the SHA-256 prefix of the kernel source they were taken on: the value is
+# reported only while the source is unchanged (else null).
+DMCW_TRAFFIC = None  # {"src_sha": "...", "fetch_kib": F, "write_kib": Wr, "fetch_factor": a, "write_factor": b, "walkers": n}
+
+
+def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
+    """Algorithmic FLOPs of one DMC step of one walker on the walker-resident
+    kernel (N drift-diffusion moves, the refreshes, one local energy), from
+    the system's dimensions (P primitives, M basis functions, No orbitals, and
+    per spin n electrons, nP table orbitals, nU distinct determinants).
+
+    Per move of an electron of spin (n, nP, nU): value and gradient basis
+    functions at the proposal (per primitive one exp + 6, per function 15),
+    their contraction (4 channels x 2 M No); the drift at the current point
+    (3 row products 2 n (n + nP) with the cached gradient rows, 3 nU x 10 for
+    the determinant lanes); the ratio and the drift at the proposal (4 row
+    products, nU x 10 + 3 nU x 15); Jastrow: per partner (N - 1 + nuclei) two
+    pair functions with derivatives (25 each) and one value (12); per accepted
+    move the Sherman-Morrison update (2 n (n + nP) + 8 nU).
+    Per electron in the local energy: the Laplacian basis functions (per
+    primitive one exp + 8, per function 3) and their contraction (2 M No),
+    4 row products and 4 nU x 10, and per partner one pair function with
+    derivatives (25) and 10 for the gradient, Laplacian and potential sums.
+    Per refresh of a spin: Gauss-Jordan 2 n^3 and the table 2 n^2 nP."""
+    N, M, norb, nnuc, P, spins = _dims(ctx, system)
+    partners = N - 1 + nnuc
+    tot = 0.0
+    for s, (n, nP, nU) in enumerate(spins):
+        if n == 0:
+            continue
+        row = 2 * n * (n + nP)
+        move = (P * (EXP_FLOPS + 6) + 15 * M) + 4 * 2 * M * norb + (3 * row + 30 * nU) + \
+            (4 * row + 10 * nU + 45 * nU) + partners * (2 * 25 + 12) + accept * (row + 8 * nU)
+        eloc = (P * (EXP_FLOPS + 8) + 3 * M) + 2 * M * norb + 4 * row + 40 * nU + partners * 35
+        tot += n * (move + eloc) + refresh_per_step[s] * (2 * n ** 3 + 2 * n * n * nP)
+    return tot
+
+
+def cpu_baseline_dmc(system, walkers=32, steps=3, seed=13):
+    """The oracle's DMC (plain FP64 CPU code, OpenMP over walkers, every
+    determinant by a fresh LU for every proposal) on a bounded sample of the
+    same workload: `walkers` walkers x `steps` steps from the same start."""
+    import numpy as np
+    import oracle
+    import systems as S
+    o = oracle.Oracle(system)
+    R0 = S.initial_walkers(system, walkers, seed=seed)
+    e0 = o.evaluate(R0)["eloc"]
+    t0 = time.perf_counter()
+    r = o.dmc(R0, e0, steps, 2022, 0, 0.005, float(np.median(e0)), walkers, capacity=4 * walkers)
+    dt = time.perf_counter() - t0
+    moves = float(r["pop"].sum())
+    return {"value": moves / dt, "unit": "walker-moves/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{walkers} walkers x {steps} DMC steps of the same molecule (tau 0.005), {dt:.1f} s"}
+
+
+def _src_sha(name):
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2207_14715_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def dmc_form(args):
-    """Fixed-node DMC on the 16-nucleus, 64-electron, 240-function,
-    32-structure / 128-determinant molecule: 32768 target walkers,
-    tau = 0.005, per-electron drift-diffusion moves with Metropolis
-    acceptance, branching with population control and on-device compaction.
-    Walkers start from a short FP64 VMC burn-in; walker-moves/s counts the
-    walkers present at each timed step."""
+    """The headline: fixed-node DMC on the 16-nucleus, 64-electron,
+    240-function, 32-structure / 128-determinant molecule with 32768 target
+    walkers, tau = 0.005.  Walkers start from a short FP64 VMC burn-in; the
+    warm-up call and the timed call of `steps` steps each begin by rebuilding
+    the records from their positions.  walker-moves/s counts the walkers
+    present at each timed step over the wall time of the timed call; the
+    dominant kernel (the per-step move-and-energy kernel) is timed with HIP
+    events on the launch stream inside the library (log step_ms)."""
+    import numpy as np
     import torch
 
     import paper_2207_14715_amd as vb
     import systems as S
     system = S.dmc_molecule()
-    W = args.walkers if args.walkers != 4096 else 32768
-    steps = args.steps if args.steps is not None else 4
-    warm = args.warmup if args.warmup is not None else 1
+    W = args.walkers or 32768
+    steps = args.steps if args.steps is not None else 20
+    warm = args.warmup if args.warmup is not None else 3
     tau = 0.005
     c64 = vb.Context(system, dmc_kernel=args.dmc_kernel)
     ctx = c64 if args.precision == "fp64" else vb.Context(system, dmc_kernel=args.dmc_kernel,
@@ -418,34 +502,71 @@ def dmc_form(args):
     st = [ctx.new_state(cap), ctx.new_state(cap)]
     R0 = torch.from_numpy(S.initial_walkers(system, W, seed=13)).cuda()
     # FP64 burn-in for every form, so that the forms start from the same walkers
-    # (the records are rebuilt from positions at the start of each DMC call)
     c64.walkers_init(R0, st[0])
     c64.vmc_advance(st[0], 3, 17, 0, 0.3, False, None, W)
     # the synthetic trial function has a wide E_L distribution: start E_T at
-    # the median so that the population does not run away in the first steps
+    # the median
     et = float(c64.record_eloc(st[0], W).median().item())
-    out = ctx.dmc_advance(st, W, warm, 2022, 0, tau, et, W)
-    Wc, et = out["W"], out["e_trial"]
+    Wc = W
+    if warm > 0:
+        out = ctx.dmc_advance(st, W, warm, 2022, 0, tau, et, W)
+        Wc, et = out["W"], out["e_trial"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = ctx.dmc_advance(st, Wc, steps, 2022, warm, tau, et, W)
+    out = ctx.dmc_advance(st, Wc, steps, 2022, warm, tau, et, W, time_steps=True)
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    wall = time.perf_counter() - t0
     pop = out["pop"].cpu().numpy()
     moves = float(pop.sum())
-    # weighted mean E_L over the timed steps (the mixed estimator of Eq. E0DMCweights)
+    accept = float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1))
     e_mixed = float(out["wesum"].sum().item() / out["wsum"].sum().item())
-    print(json.dumps({"metric": "walker-moves/sec incl. E_L (DMC)", "value": moves / t, "unit": "walker-moves/s",
-                      "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": t / steps * 1e3,
-                      "population": [int(p) for p in pop], "e_trial": out["e_trial"], "e_mixed": e_mixed,
-                      "acceptance": float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1)),
-                      "data": "synthetic",
-                      "dtype": _dtype(args.precision),
-                      "dmc_kernel": "electron-major" if ctx.info["dmc_kernel"] == 2 else "workgroup per walker",
-                      "config": {"workload": "16 nuclei (Z in {1,6,8}), 64 electrons, 240 Gaussian basis functions, "
-                                             "32 VB structures / 128 determinants, tau = 0.005, per-electron "
-                                             "drift-diffusion moves, branching and compaction",
-                                 "target_walkers": W}}))
+    kern = ctx.info["dmc_kernel"]
+    step_ms = out["step_ms"]
+    nupd_rate = [accept * n / 32.0 for n in (ctx.info["n_up"], ctx.info["n_dn"])]  # refreshes per step per spin
+    fl_walker = dmc_flops_per_walker_step(ctx, system, accept, nupd_rate)
+    flops_launch = fl_walker * float(pop.mean())
+    kavg = float(np.mean(step_ms)) / 1e3
+    achieved = flops_launch / kavg / 1e12
+    traffic = None
+    if (DMCW_TRAFFIC and kern == 3 and args.precision == "fp64" and W == DMCW_TRAFFIC["walkers"] and
+            _src_sha("vbqmc_dmcw.hip") == DMCW_TRAFFIC["src_sha"]):
+        traffic = (DMCW_TRAFFIC["fetch_kib"] * DMCW_TRAFFIC["fetch_factor"] +
+                   DMCW_TRAFFIC["write_kib"] * DMCW_TRAFFIC["write_factor"]) * 1024
+    line = {
+        "metric": HEADLINE_METRIC,
+        "value": moves / wall,
+        "unit": "walker-moves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": _dtype(args.precision),
+        "data": "synthetic",
+        "config": {"workload": "fixed-node DMC of the 64-electron synthetic molecule: 16 nuclei (Z in {1,6,8}), "
+                               "32 up + 32 down electrons, 240 Gaussian basis functions, 32 VB structures / 128 "
+                               "determinants, Pade Jastrow, 32768 target walkers, tau = 0.005, per-electron "
+                               "drift-diffusion moves, E_L every step, branching with +-10 % population control",
+                   "target_walkers": W, "electrons": ctx.N, "precision": args.precision,
+                   "dmc_kernel": {1: "workgroup per walker", 2: "electron-major", 3: "walker-resident"}[kern]},
+        "electron_moves_per_s": moves * ctx.N / wall,
+        "acceptance": accept,
+        "population": [int(p) for p in pop],
+        "population_band": [float(pop.min() / W - 1), float(pop.max() / W - 1)],
+        "e_trial": out["e_trial"],
+        "e_mixed": e_mixed,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": DMC_KERNEL_NAMES[kern], "kernel_avg_ms_per_launch": kavg * 1e3,
+                     "kernel_share_of_step": float(np.sum(step_ms) / 1e3 / wall),
+                     "flops_per_launch": flops_launch, "flops_per_walker_step": fl_walker,
+                     "walkers_per_launch": float(pop.mean())},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_dmc(system)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

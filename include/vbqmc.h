@@ -131,9 +131,15 @@ typedef struct {
  * each electron a proposal launch, an MFMA launch for the orbital rows at
  * the proposals and an acceptance launch, each over all walkers, then one
  * per-walker launch for refresh, E_L and weight (spins with at most 64
- * reference slots plus table orbitals; EINVAL at create otherwise); 0 = 2
- * when one workgroup per walker would need more than 40 KiB of LDS and the
- * system fits it, else 1.  Results do not depend on it beyond rounding. */
+ * reference slots plus table orbitals; EINVAL at create otherwise);
+ * 3 = walker-resident: one launch per step in which a workgroup keeps four
+ * walkers (one per wavefront) for all their moves, refresh, E_L and weight,
+ * with the value and gradient orbital rows of each electron's position kept
+ * in the walker record (FP64, Gaussian shells, at most 32 electrons and 64
+ * reference slots plus table orbitals per spin, at most 64 orbitals; EINVAL
+ * at create otherwise); 0 = 3 when the system fits it, else 2 when one
+ * workgroup per walker would need more than 40 KiB of LDS and the system fits
+ * it, else 1.  Results do not depend on it beyond rounding. */
 typedef struct {
   int32_t precision;
   int32_t refresh_every;
@@ -255,7 +261,10 @@ int vbqmc_vmc_measure(vbqmc_ctx* ctx, void* state, int64_t W, const vbqmc_vmc_ac
 
 /* DMC per-step records, each [dev][n_steps]: population before branching,
  * sum of weights, sum of weight * E_L, trial energy used, accepted and
- * proposed single-electron moves. */
+ * proposed single-electron moves.  step_ms [host][n_steps] or NULL: when set,
+ * each step's move-and-local-energy kernels are bracketed by HIP events on
+ * the call's stream and their elapsed milliseconds are written here before
+ * the call returns (branching and compaction are not included). */
 typedef struct {
   double* pop;
   double* wsum;
@@ -263,6 +272,7 @@ typedef struct {
   double* etrial;
   double* n_accept;
   double* n_prop;
+  double* step_ms;
 } vbqmc_dmc_log;
 
 /*
@@ -295,7 +305,8 @@ int vbqmc_dmc_advance(vbqmc_ctx* ctx, void* states[2], int64_t* W_io, int64_t ca
  * vbqmc_dmc_advance without a caller workspace, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, semantics and results
- * as vbqmc_dmc_advance, bit for bit, except that the workspace is a fixed
+ * as vbqmc_dmc_advance, bit for bit (log->step_ms must be NULL: timing
+ * events are not created here), except that the workspace is a fixed
  * 32 MiB device array inside the library (one per device, held until the
  * process ends; its address is taken at vbqmc_create), so the call allocates
  * nothing.  Capacities whose vbqmc_dmc_workspace_bytes exceeds 32 MiB are

@@ -72,7 +72,8 @@ class _VmcAcc(ctypes.Structure):
 
 class _DmcLog(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("wesum", ctypes.c_void_p),
-                ("etrial", ctypes.c_void_p), ("n_accept", ctypes.c_void_p), ("n_prop", ctypes.c_void_p)]
+                ("etrial", ctypes.c_void_p), ("n_accept", ctypes.c_void_p), ("n_prop", ctypes.c_void_p),
+                ("step_ms", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -307,7 +308,10 @@ class Context:
         self._rc(self._lib.vbqmc_dmc_workspace_bytes(self._h, capacity, n_steps, ctypes.byref(nb)))
         return torch.zeros((nb.value + 7) // 8, dtype=torch.float64, device=device)
 
-    def dmc_advance(self, states, W, n_steps, seed, step0, tau, e_trial, w_target, workspace=None, log=None):
+    def dmc_advance(self, states, W, n_steps, seed, step0, tau, e_trial, w_target, workspace=None, log=None,
+                    time_steps=False):
+        """time_steps: also return "step_ms", the HIP-event duration of each
+        step's move-and-energy kernels (numpy, host)."""
         import torch
         cap = states[0].shape[0]
         dev = states[0].device
@@ -316,7 +320,9 @@ class Context:
         if log is None:
             log = {k: torch.zeros(n_steps, dtype=torch.float64, device=dev)
                    for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")}
-        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")])
+        step_ms = np.zeros(max(n_steps, 1)) if time_steps else None
+        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")],
+                     _dp(step_ms) if time_steps else None)
         arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
         Wio = ctypes.c_int64(W)
         et = ctypes.c_double(e_trial)
@@ -325,13 +331,16 @@ class Context:
                                          ctypes.byref(lg), ctypes.c_void_p(workspace.data_ptr()),
                                          workspace.numel() * 8, _stream())
         self._rc(rc)
-        return {"W": Wio.value, "e_trial": et.value, **log}
+        out = {"W": Wio.value, "e_trial": et.value, **log}
+        if time_steps:
+            out["step_ms"] = step_ms[:n_steps]
+        return out
 
     def dmc_advance_noalloc(self, states, W, n_steps, seed, step0, tau, e_trial, w_target, log):
         """vbqmc_dmc_advance on the library's fixed scratch array: the caller
         passes the records and the per-step log, nothing is allocated."""
         cap = states[0].shape[0]
-        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")])
+        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")], None)
         arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
         Wio = ctypes.c_int64(W)
         et = ctypes.c_double(e_trial)

@@ -42,12 +42,16 @@ __device__ __forceinline__ double dw_readlane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over the 64 lanes, the same bits in every lane: DPP sums within each
+// 16-lane row (gsum), then the four row sums read from lanes 0, 16, 32 and
+// 48 and added in that order.
 template <int K>
 __device__ __forceinline__ void dw_wsum(double (&v)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k)
+  for (int k = 0; k < K; ++k) v[k] = gsum<16>(v[k]);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  for (int k = 0; k < K; ++k)
+    v[k] = ((dw_readlane(v[k], 0) + dw_readlane(v[k], 16)) + dw_readlane(v[k], 32)) + dw_readlane(v[k], 48);
 }
 
 // Distinct determinants u = lane + 64 h (h = 0, 1) of the spin being moved:
@@ -189,7 +193,7 @@ __device__ __forceinline__ void dw_load_columns(const double* Bg, const double* 
 // function is its angular polynomial times that factor (stride nshell | 1).
 // Each shell's terms are added in the order of its primitives.
 template <int NPT, int MODE>
-__device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
+__device__ __forceinline__ void dw_radial_plain(const DevWF& wf, const Ld& l) {
 #pragma clang fp contract(off)
   const double* disp = l.L + wf.dw_disp;
   double* gt = l.L + wf.dw_gtab;
@@ -226,6 +230,82 @@ __device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
   }
 }
 
+// The same sums from a radial schedule of kDwNT / NPT bins (the shells dealt
+// to bins by the host, longest first, each to the bin with the fewest
+// primitives): thread t takes point t % NPT and bin t / NPT and walks the
+// bin's primitives two at a time in a loop of fixed length, the schedule
+// entries and operands of the next step already loaded.  A shell's running
+// sum restarts at its first primitive and is stored at every entry, so the
+// last store holds the whole sum (padding entries repeat the bin's last shell
+// and add nothing); each shell is still summed in one thread in the order of
+// its primitives, so the sums equal those of dw_radial_plain bit for bit.
+template <int NPT, int MODE>
+__device__ __forceinline__ void dw_radial_bins(const DevWF& wf, const Ld& l) {
+#pragma clang fp contract(off)
+  constexpr int NB = kDwNT / NPT;
+  const int e = threadIdx.x & (NPT - 1);
+  const double* de = l.L + wf.dw_disp + e * (4 * wf.nnuc + 1);
+  double* o = l.L + wf.dw_gtab + e * (MODE == 0 ? 2 * wf.nshell + 1 : (wf.nshell | 1));
+  const unsigned* sc = (const unsigned*)(l.L + wf.dw_rs) + (NPT == 4 ? wf.dw_rs4_off : wf.dw_rs16_off) +
+                       threadIdx.x / NPT;
+  const int len = NPT == 4 ? wf.dw_rs4_len : wf.dw_rs16_len;
+  const double* pe = l.pe();
+  const double* pc = l.pc();
+  const double* etab = l.L + wf.l_etab;
+  const int* sht = l.sh();
+  auto nuc = [](unsigned f) { return (int)((f >> kRsNucShift) & kRsNucMask); };
+  auto shl = [](unsigned f) { return (int)((f >> kRsShift) & kRsShMask); };
+  unsigned n0 = sc[0], n1 = sc[NB], m0 = sc[2 * NB], m1 = sc[3 * NB];
+  double a0 = pe[n0 & kRsPrim], c0 = pc[n0 & kRsPrim], a1 = pe[n1 & kRsPrim], c1 = pc[n1 & kRsPrim];
+  double d0 = de[4 * nuc(n0) + 3], d1 = de[4 * nuc(n1) + 3];
+  int l0 = MODE == 1 ? sht[8 * shl(n0) + 2] : 0, l1 = MODE == 1 ? sht[8 * shl(n1) + 2] : 0;
+  double g = 0.0, g1 = 0.0;
+  auto add = [&](double ex, double a, double r2, int lq, unsigned f) {
+    const bool first = f & kRsFirst;
+    if constexpr (MODE == 0) {
+      g = (first ? 0.0 : g) + ex;
+      g1 = (first ? 0.0 : g1) - a * ex;
+      double* q = o + 2 * shl(f);
+      q[0] = g;
+      q[1] = g1;
+    } else {
+      g = (first ? 0.0 : g) + ex * a * (4.0 * (a * r2) - (double)(2 * (2 * lq + 3)));
+      o[shl(f)] = g;
+    }
+  };
+  for (int j = 0; j < len; j += 2) {
+    const unsigned f0 = n0, f1 = n1;
+    const double A0 = a0, C0 = c0, R0 = d0, A1 = a1, C1 = c1, R1 = d1;
+    const int L0 = l0, L1 = l1;
+    n0 = m0;
+    n1 = m1;
+    m0 = sc[NB * (j + 4)];
+    m1 = sc[NB * (j + 5)];
+    a0 = pe[n0 & kRsPrim];
+    c0 = pc[n0 & kRsPrim];
+    a1 = pe[n1 & kRsPrim];
+    c1 = pc[n1 & kRsPrim];
+    d0 = de[4 * nuc(n0) + 3];
+    d1 = de[4 * nuc(n1) + 3];
+    if constexpr (MODE == 1) {
+      l0 = sht[8 * shl(n0) + 2];
+      l1 = sht[8 * shl(n1) + 2];
+    }
+    const double t0 = A0 * R0, t1 = A1 * R1;
+    double ex0, ex1;
+    exp_neg2<double>(fmin(t0, 64.0), fmin(t1, 64.0), etab, ex0, ex1);
+    const double x0 = C0 * ex0, x1 = C1 * ex1;
+    add(((f0 & kRsLive) && t0 < 50.0) ? x0 : 0.0, A0, R0, L0, f0);
+    add(((f1 & kRsLive) && t1 < 50.0) ? x1 : 0.0, A1, R1, L1, f1);
+  }
+}
+
+template <int NPT, int MODE>
+__device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
+  if ((NPT == 4 ? wf.dw_rs4_len : wf.dw_rs16_len) > 0) dw_radial_bins<NPT, MODE>(wf, l);
+  else dw_radial_plain<NPT, MODE>(wf, l);
+}
+
 // angular polynomial P of function (m, lq) at displacement (x, y, z) and its
 // derivative along axis c (0..2)
 __device__ __forceinline__ void dw_poly(int lq, int m, double x, double y, double z, int c, double& P, double& Pc) {
@@ -249,59 +329,92 @@ __device__ __forceinline__ void dw_poly(int lq, int m, double x, double y, doubl
   Pc = c == 0 ? Px : (c == 1 ? Py : Pz);
 }
 
+// The contraction with lambda^T is split over the basis functions: wavefront
+// g takes k-steps g kper .. (g + 1) kper - 1 (kper = Mpad / 16; a k-step is
+// four functions) for every 16-column tile.  Its slice of lambda^T in the
+// MFMA B-operand layout is loaded into registers once per launch and serves
+// every row tile of the step (lambda is constant).
+constexpr int kDwLK = 16;  // k-steps per wavefront: Mpad <= 4 kDwW kDwLK = 256
+constexpr int kDwLC = 3;   // column tiles: nop <= 48
+
+struct DwLam {
+  double b[kDwLK][kDwLC];
+};
+
+__device__ __forceinline__ void dw_load_lam(const DevWF& wf, DwLam& L) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kper = wf.Mpad / (4 * kDwW), nct = wf.nop / 16;
+#pragma unroll
+  for (int t = 0; t < kDwLK; ++t)
+#pragma unroll
+    for (int c = 0; c < kDwLC; ++c) {
+      const bool in = t < kper && c < nct;
+      const int k = in ? 4 * (wave * kper + t) + (lane >> 4) : 0;
+      const int col = in ? 16 * c + (lane & 15) : 0;
+      const double v = wf.lamT[(size_t)k * wf.nop + col];
+      L.b[t][c] = in ? v : 0.0;
+    }
+}
+
 // One 16-row tile on MFMA: rows r = 4 p + c of the A operand are built on
 // the fly from the tables (MODE 0: channel c = value, d/dx, d/dy, d/dz of
-// point p; MODE 1: the Laplacian of point r), contracted with lambda^T;
-// wavefront g takes column tiles g, g + 4, ..  Output row 4 q + lane / 16
-// (register q) at orbital column p goes to out[row][slot] with
-// slot = cmap[p] (orbitals a spin does not use are dropped).
+// point p; MODE 1: the Laplacian of point r), contracted with lambda^T from
+// registers.  The four wavefronts' partial sums meet in part ([4][kDwLC][4]
+// [64] doubles) and are added in a fixed order; output row 4 q + lane / 16 of
+// register q at orbital column p goes to out[row][slot], slot = cmap[p]
+// (orbitals a spin does not use are dropped).  Ends with a barrier.
 template <int MODE>
-__device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int* cmap, double* out) {
+__device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int* cmap, double* out, double* part,
+                                       const DwLam& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   const int p = MODE == 0 ? row >> 2 : row, c = row & 3;
   const double* disp = l.L + wf.dw_disp + p * (4 * wf.nnuc + 1);
   const double* gt = l.L + wf.dw_gtab + p * (MODE == 0 ? 2 * wf.nshell + 1 : (wf.nshell | 1));
-  const int nct = wf.nop / 16;
-  const double* lam = wf.lamT;
-  for (int ct = wave; ct < nct; ct += kDwW) {
-    const int col = ct * 16 + (lane & 15);
-    v4d acc;
+  const int nct = wf.nop / 16, kper = wf.Mpad / (4 * kDwW), kb = wave * kper;
+  v4d acc[kDwLC];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = 0.0;
-    for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
-      double a[4], b[4];
+  for (int ct = 0; ct < kDwLC; ++ct)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + 4 * u + kq;
-        b[u] = lam[(size_t)k * wf.nop + col];
-        const FnInfo fi = fn_info(l, k);
-        double v = 0.0;
-        if (fi.sh >= 0) {
-          const double* d = disp + 4 * fi.nuc;
-          const double x = d[0], y = d[1], z = d[2];
-          double P, Pc;
-          if constexpr (MODE == 0) {
-            const double gg = gt[2 * fi.sh], g1 = gt[2 * fi.sh + 1];
-            dw_poly(fi.lq, fi.m, x, y, z, c == 0 ? 0 : c - 1, P, Pc);
-            const double dc = c == 1 ? x : (c == 2 ? y : z);
-            v = c == 0 ? P * gg : Pc * gg + 2.0 * g1 * P * dc;
-          } else {
-            dw_poly(fi.lq, fi.m, x, y, z, 0, P, Pc);
-            v = P * gt[fi.sh];
-          }
-        }
-        a[u] = v;
+    for (int r = 0; r < 4; ++r) acc[ct][r] = 0.0;
+#pragma unroll
+  for (int t = 0; t < kDwLK; ++t) {
+    if (t < kper) {
+      const FnInfo fi = fn_info(l, 4 * (kb + t) + kq);
+      // (padding functions read shell 0 of nucleus 0 and are zeroed)
+      const bool fn = fi.sh >= 0;
+      const double* d = disp + 4 * (fn ? fi.nuc : 0);
+      const int sh = fn ? fi.sh : 0;
+      const double x = d[0], y = d[1], z = d[2];
+      double P, Pc, v;
+      if constexpr (MODE == 0) {
+        const double gg = gt[2 * sh], g1 = gt[2 * sh + 1];
+        dw_poly(fi.lq, fi.m, x, y, z, c == 0 ? 0 : c - 1, P, Pc);
+        const double dc = c == 1 ? x : (c == 2 ? y : z);
+        v = c == 0 ? P * gg : Pc * gg + 2.0 * g1 * P * dc;
+      } else {
+        dw_poly(fi.lq, fi.m, x, y, z, 0, P, Pc);
+        v = P * gt[sh];
       }
+      const double a = fn ? v : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-    }
-    const int slot = cmap[col];
-    if (slot >= 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) out[(4 * q + kq) * 64 + slot] = acc[q];
+      for (int ct = 0; ct < kDwLC; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, L.b[t][ct], acc[ct], 0, 0, 0);
     }
   }
+  double* pw = part + wave * (kDwLC * 4 * 64);
+#pragma unroll
+  for (int ct = 0; ct < kDwLC; ++ct)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pw[(ct * 4 + q) * 64 + lane] = acc[ct][q];
+  __syncthreads();
+  constexpr int PW = kDwLC * 4 * 64;
+  for (int e = threadIdx.x; e < nct * 4 * 64; e += kDwNT) {
+    const double v = ((part[e] + part[PW + e]) + part[2 * PW + e]) + part[3 * PW + e];
+    const int ct = e >> 8, q = (e >> 6) & 3, ln = e & 63;
+    const int slot = cmap[16 * ct + (ln & 15)];
+    if (slot >= 0) out[(4 * q + (ln >> 4)) * 64 + slot] = v;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -328,6 +441,10 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   // index q, or -1)
   int* cmap = (int*)(lds_dyn + wf.dw_cmap);
   for (int k = threadIdx.x; k < 2 * wf.nop; k += kDwNT) cmap[k] = -1;
+  {
+    unsigned* rs = (unsigned*)(lds_dyn + wf.dw_rs);
+    for (int k = threadIdx.x; k < wf.dw_rs_words; k += kDwNT) rs[k] = wf.dw_rs_g[k];
+  }
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
     const SpinTab& sp = wf.sp[s];
@@ -341,6 +458,9 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   double* yr = wa + wf.dwo_y;     // table residuals [4][64] (table-indexed)
   double* Pw = lds_dyn + wf.dw_P; // per walker: proposal x, y, z, drift x, y, z
   double* V4 = lds_dyn + wf.dw_V4;
+  double* part = lds_dyn + wf.dw_part;  // partial sums of the row tiles
+  DwLam lam;
+  dw_load_lam(wf, lam);
   // records of dead wavefronts (past W) are never read or written
   double* rec = state + (live ? w : wbase) * wf.rec_len;
   for (int k = lane; k < 3 * N; k += 64) Rl[k] = rec[wf.r_R + k];
@@ -382,8 +502,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       __syncthreads();
       dw_radial<kDwW, 0>(wf, l);
       __syncthreads();
-      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4);
-      __syncthreads();
+      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4, part, lam);
       if (live)
         for (int k = lane; k < WD; k += 64) {
           vc[(size_t)i * WD + k] = V4[(4 * g) * 64 + k];
@@ -413,14 +532,42 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     double nuS = prep ? (double)wf.refresh_every : rec[wf.r_sc + SC_NUPD0 + s];
     dw_load_columns<NC>(Bg, Tg, n, nP, lane, C);
     dw_load_dets(sp, Tg, Ru, Wu, lane, d);
+    // the draws of this spin's moves, lane il for electron e0 + il: the
+    // Box-Muller normals of the proposal and the acceptance uniform
+    double* rnd = wa + wf.dw_rnd;
+    if (!prep && lane < n) {
+      const uint32_t ie = (uint32_t)(e0 + lane);
+      double a0, a1, b0, b1, ua, dummy;
+      philox_pair(seed, (uint32_t)w, step, 4u * ie, 0u, a0, a1);
+      philox_pair(seed, (uint32_t)w, step, 4u * ie, 1u, b0, b1);
+      philox_pair(seed, (uint32_t)w, step, 4u * ie + 1u, 0u, ua, dummy);
+      const double two_pi = 6.283185307179586476925286766559;
+      const double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
+      rnd[4 * lane] = r0 * cos(two_pi * a1);
+      rnd[4 * lane + 1] = r0 * sin(two_pi * a1);
+      rnd[4 * lane + 2] = r1 * cos(two_pi * b1);
+      rnd[4 * lane + 3] = ua;
+    }
+    // the cached gradient rows of the next electron to move, in flight
+    // while the current move runs (electron e0 + il + 1 does not move in
+    // move il, so its rows do not change)
+    double gn[3] = {0.0, 0.0, 0.0};
+    if (!prep && lane < WD)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gn[c] = gc[((size_t)e0 * 3 + c) * WD + lane];
+    wave_sync();
     for (int il = 0; il < n && !prep; ++il) {
       const int i = e0 + il;
       const bool act = !bad;
+      double uo[2] = {0.0, 0.0};  // Jastrow pair values at the current point, per partner lane
       // (A) drift at the current point from the cached gradient rows
       if (act) {
-        for (int k = lane; k < WD; k += 64)
+        if (lane < WD)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) xr[c * 64 + k] = gc[((size_t)i * 3 + c) * WD + k];
+          for (int c = 0; c < 3; ++c) xr[c * 64 + lane] = gn[c];
+        if (il + 1 < n && lane < WD)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gn[c] = gc[((size_t)(i + 1) * 3 + c) * WD + lane];
         if (lane == il)
 #pragma unroll
           for (int j = 0; j < NC; ++j) bc[j] = C[j];
@@ -438,8 +585,10 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         for (int c = 0; c < 3; ++c) part[c] = dw_detsum(d, rp[c], yr + c * 64, bc);
         part[3] = part[4] = part[5] = 0.0;
         const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
-        for (int j = lane; j < N + nn; j += 64) {
-          if (j == i) continue;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const int j = lane + 64 * it;
+          if (j >= N + nn || j == i) continue;
           double xj, yj, zj;
           PairCoef cf;
           if (j < N) {
@@ -454,6 +603,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           const double r = sqrt(dx * dx + dy * dy + dz * dz);
           double u, u1, u2;
           pair_fn(r, kappa, cf, u, u1, u2);
+          uo[it] = u;
           const double f = u1 / r;
           part[3] += f * dx;
           part[4] += f * dy;
@@ -464,12 +614,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           double v[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[c] = part[3 + c] + part[c] / S;
-          double a0, a1, b0, b1;
-          philox_pair(seed, (uint32_t)w, step, 4u * i, 0u, a0, a1);
-          philox_pair(seed, (uint32_t)w, step, 4u * i, 1u, b0, b1);
-          const double two_pi = 6.283185307179586476925286766559;
-          const double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
-          const double zx = r0 * cos(two_pi * a1), zy = r0 * sin(two_pi * a1), zz = r1 * cos(two_pi * b1);
+          const double zx = rnd[4 * il], zy = rnd[4 * il + 1], zz = rnd[4 * il + 2];
           Pw[6 * g] = xi + tau * v[0] + sqt * zx;
           Pw[6 * g + 1] = yi + tau * v[1] + sqt * zy;
           Pw[6 * g + 2] = zi + tau * v[2] + sqt * zz;
@@ -492,8 +637,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       __syncthreads();
       dw_radial<kDwW, 0>(wf, l);
       __syncthreads();
-      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4);
-      __syncthreads();
+      dw_mfma<0>(wf, l, cmap + s * wf.nop, V4, part, lam);
       // (C) ratio, node check, drift at the proposal, Green's function,
       // Metropolis decision and the Sherman-Morrison update
       if (act) {
@@ -516,8 +660,11 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         const double px = Pw[6 * g], py = Pw[6 * g + 1], pz = Pw[6 * g + 2];
         const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
         double jg[3] = {0.0, 0.0, 0.0};
-        for (int j = lane; j < N + nn; j += 64) {
-          if (j == i) continue;
+        (void)xi; (void)yi; (void)zi;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const int j = lane + 64 * it;
+          if (j >= N + nn || j == i) continue;
           double xj, yj, zj;
           PairCoef cf;
           if (j < N) {
@@ -530,10 +677,9 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           }
           const double dx = px - xj, dy = py - yj, dz = pz - zj;
           const double rn = sqrt(dx * dx + dy * dy + dz * dz);
-          const double ro = sqrt((xi - xj) * (xi - xj) + (yi - yj) * (yi - yj) + (zi - zj) * (zi - zj));
           double u, u1, u2;
           pair_fn(rn, kappa, cf, u, u1, u2);
-          part[1] += u - pair_val(ro, kappa, cf);
+          part[1] += u - uo[it];
           const double f = u1 / rn;
           jg[0] += f * dx;
           jg[1] += f * dy;
@@ -586,9 +732,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
             bwd += ba * ba;
           }
           const double prob = rdet * rdet * exp(2.0 * dU + (fwd - bwd) / (2.0 * tau));
-          double ua, dummy;
-          philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
-          accept = ua < prob;
+          accept = rnd[4 * il + 3] < prob;
         }
         if (accept) {
           double f = 0.0;
@@ -771,8 +915,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       __syncthreads();
       dw_radial<16, 1>(wf, l);
       __syncthreads();
-      dw_mfma<1>(wf, l, cmap + s2 * wf.nop, V4);
-      __syncthreads();
+      dw_mfma<1>(wf, l, cmap + s2 * wf.nop, V4, part, lam);
       if (!bad) {
 #pragma unroll 1
         for (int e4 = 0; e4 < 4 && i0 + e4 < n; ++e4) {

@@ -134,6 +134,8 @@ struct vbqmc_ctx {
   std::vector<double> nuc, en, pexp, pcoef, lam, c;
   std::vector<int> shtab, fnmap, pshell;
   std::vector<unsigned> rsched;  // radial schedules of 64-lane blocks: 4 bins, then 8 bins
+  std::vector<unsigned> dw_rs;   // radial schedules of the walker-resident DMC row tiles: 64 bins, then 16
+  int dw_rs4_len = 0, dw_rs16_len = 0, dw_rs16_off = 0;
   int rsched_len = 0, rsched_len8 = 0, rsched8_off = 0;
   double ee[8];
   double kappa = 0;
@@ -304,6 +306,28 @@ static int deal_radial_bins(const vbqmc_ctx* x, int NB, std::vector<unsigned>& o
     for (; j < L + 4; ++j) out[(size_t)NB * j + b] = where(bins[b].back());
   }
   return L;
+}
+
+// schedules of the walker-resident DMC kernel's row tiles (256 threads):
+// four points x 64 bins and sixteen points x 16 bins
+void build_dmcw_schedule(vbqmc_ctx* x) {
+  x->dw_rs.clear();
+  x->dw_rs4_len = x->dw_rs16_len = x->dw_rs16_off = 0;
+  const int nprim = (int)x->pexp.size();
+  if (nprim > (int)kRsPrim + 1 || x->nshell > (int)kRsShMask + 1 || x->nnuc > (int)kRsNucMask + 1) return;
+  std::vector<unsigned> a, b;
+  const int L64 = deal_radial_bins(x, 64, a);
+  const int L16 = deal_radial_bins(x, 16, b);
+  if (L64 > 0) {
+    x->dw_rs = a;
+    x->dw_rs4_len = L64;
+  }
+  if (L16 > 0) {
+    x->dw_rs16_off = (int)x->dw_rs.size();
+    x->dw_rs.insert(x->dw_rs.end(), b.begin(), b.end());
+    x->dw_rs16_len = L16;
+  }
+  if (x->dw_rs.size() & 1) x->dw_rs.push_back(0u);  // whole doubles in LDS
 }
 
 void build_radial_schedule(vbqmc_ctx* x) {
@@ -515,6 +539,12 @@ DevWF dmcw_layout(const vbqmc_ctx* x) {
   a.timg_len = lds.o;
   a.lam_in_lds = 0;
   a.dw_P = lds(24 + 48);
+  a.dw_rs = lds((int)x->dw_rs.size() / 2);
+  a.dw_rs_words = (int)x->dw_rs.size();
+  a.dw_rs4_off = 0;
+  a.dw_rs4_len = x->dw_rs4_len;
+  a.dw_rs16_off = x->dw_rs16_off;
+  a.dw_rs16_len = x->dw_rs16_len;
   a.dw_cmap = lds.ints(2 * x->nop);
   a.dw_wave = lds.o;
   LdsAlloc w{0};
@@ -524,8 +554,10 @@ DevWF dmcw_layout(const vbqmc_ctx* x) {
   a.dwo_y = w(4 * 64);
   a.dwo_piv = w.ints(64);
   a.dwo_f = w(64);
+  a.dw_rnd = w(4 * 64);
   a.dw_wstride = w.o;
   lds.o += 4 * a.dw_wstride;
+  a.dw_part = lds(4 * 3 * 4 * 64);
   const int t0 = lds.o;
   a.dw_disp = lds(16 * (4 * x->nnuc + 1));
   a.dw_gtab = lds(std::max(4 * (2 * x->nshell + 1), 16 * (x->nshell | 1)));
@@ -542,12 +574,13 @@ DevWF dmcw_layout(const vbqmc_ctx* x) {
 }
 
 // the walker-resident DMC kernel handles the system: FP64 rows, Gaussian
-// shells, at most 32 electrons, 64 reference slots plus table orbitals and 128 distinct
+// shells, at most 256 (padded) basis functions and 48 (padded) orbitals, at most
+// 32 electrons, 64 reference slots plus table orbitals and 128 distinct
 // determinants per spin, at most 64 (padded) orbitals, spin-up electrons
 // present, and its layout fits the device's LDS
 bool dmcw_fit(const vbqmc_ctx* x) {
   if (x->wf.precision != VBQMC_FP64 || x->wf.trial_prec != VBQMC_FP64 || x->wf.refresh_each_step) return false;
-  if (x->nop > 64 || x->nup < 1 || x->nup > 32 || x->ndn > 32) return false;
+  if (x->nop > 48 || x->Mpad > 256 || x->nup < 1 || x->nup > 32 || x->ndn > 32 || x->N + x->nnuc > 128) return false;
   for (int sh = 0; sh < x->nshell; ++sh)
     if (x->shtab[8 * sh + 1] != 0) return false;
   for (int sp = 0; sp < 2; ++sp) {
@@ -745,6 +778,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->M = fn;
   if (x->M < 1 || x->M > 1024) return bad("basis size outside 1..1024");
   build_radial_schedule(x);
+  build_dmcw_schedule(x);
   x->Mpad = (x->M + kChunk - 1) / kChunk * kChunk;
   for (int mu = x->M; mu < x->Mpad; ++mu) x->fnmap.insert(x->fnmap.end(), {-1, 0});
   x->norb = wfi->n_orbitals;
@@ -1129,6 +1163,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     add(h.ref.size(), 4); add(h.porb.size(), 4); add(h.uinfo.size(), 4); add(h.wrow.size(), 4);
     add(h.wother.size(), 4); add(h.wother.size(), 8); add((size_t)x->nop, 4);
   }
+  add(x->dw_rs.size(), 4);
   add(x->srow.size(), 4); add(x->slu.size(), 4); add(x->slc.size(), 8); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
   add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1); add(sizeof(DevWF), 1);
   add((size_t)wf.timg_len, 8);
@@ -1176,6 +1211,11 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->d_wf_dmcb = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_wf_dmcw = (DevWF*)carve<char>(p, sizeof(DevWF));
   x->d_timg = carve<double>(p, (size_t)wf.timg_len);
+  {
+    unsigned* a = carve<unsigned>(p, x->dw_rs.size());
+    up(x->dw_rs.data(), x->dw_rs.size(), 4, a);
+    wf.dw_rs_g = a;
+  }
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
   wf.pcoef = d_pcoef; wf.pshell = d_pshell; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
@@ -1390,6 +1430,7 @@ int vbqmc_dmc_advance_noalloc(vbqmc_ctx* x, void* states[2], int64_t* W_io, int6
                   (long long)cap, need, kNoAllocScratchBytes);
     return fail(x, VBQMC_EWORKSPACE, b);
   }
+  if (lg && lg->step_ms) return fail(x, VBQMC_EINVAL, "dmc_noalloc: step timing (log->step_ms) is not available");
   return dmc_advance_impl(x, states, W_io, cap, n_steps, seed, step0, tau, e_trial_io, W_target, lg, x->scratch,
                           kNoAllocScratchBytes, stream);
 }
@@ -1444,8 +1485,27 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
     e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
                         nullptr, nullptr, cur, s);
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
+  // optional per-step timing of the move-and-energy kernels
+  std::vector<hipEvent_t> ev;
+  auto drop_events = [&]() {
+    for (hipEvent_t v : ev) hipEventDestroy(v);
+    ev.clear();
+  };
+  if (lg->step_ms) {
+    ev.resize(2 * (size_t)n_steps, nullptr);
+    for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    if (e != hipSuccess) {
+      drop_events();
+      return hipfail(x, e, "dmc: timing events");
+    }
+  }
   for (int st = 0; st < n_steps; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
+    if (!ev.empty()) e = hipEventRecord(ev[2 * st], s);
+    if (e != hipSuccess) {
+      drop_events();
+      return hipfail(x, e, "dmc: timing event");
+    }
     if (x->dmc_kernel == 3) {
       e = launch_dmcw(dmcw_layout(x), x->d_wf_dmcw, cur, ctrl, cap, seed, step, tau, br, nacc, 0, s);
     } else if (x->dmc_kernel == 2) {
@@ -1459,14 +1519,27 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
     } else {
       e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, br, nacc, s);
     }
-    if (e != hipSuccess) return hipfail(x, e, "dmc: step");
+    if (e == hipSuccess && !ev.empty()) e = hipEventRecord(ev[2 * st + 1], s);
+    if (e != hipSuccess) {
+      drop_events();
+      return hipfail(x, e, "dmc: step");
+    }
     e = launch_dmc_tail(ctrl, br, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
                         lg->wesum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
-    if (e != hipSuccess) return hipfail(x, e, "dmc: branching");
+    if (e != hipSuccess) {
+      drop_events();
+      return hipfail(x, e, "dmc: branching");
+    }
     std::swap(cur, oth);
   }
   e = hipMemcpyAsync(h, ctrl, sizeof h, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (int st = 0; st < n_steps && e == hipSuccess && !ev.empty(); ++st) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]);
+    lg->step_ms[st] = ms;
+  }
+  drop_events();
   if (e != hipSuccess) return hipfail(x, e, "dmc: control download");
   if (h[DC_ERR] != 0.0) {
     // the failing step's branching did not run: its walkers (after that

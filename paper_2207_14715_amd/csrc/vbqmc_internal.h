@@ -114,6 +114,13 @@ struct DevWF {
   int dw_width, r_vc, dw_xe;  // dw_xe: the most columns a spin determinant replaces
   int dw_wave, dw_wstride, dwo_R, dwo_bc, dwo_x, dwo_y, dwo_piv, dwo_f;
   int dw_P, dw_cmap, dw_disp, dw_gtab, dw_V4, dw_A, dw_Astride, lds_dmcw_doubles;
+  int dw_part;  // partial sums of the row-tile contraction [4][3][4][64]
+  int dw_rnd;   // per wavefront, the draws of a spin's moves [64][4] (normals, acceptance uniform)
+  // radial schedules of the row tiles (four points x 64 bins; sixteen
+  // points x 16 bins; entry j of bin b at [j][b], words as kRsPrim), staged
+  // from dw_rs_g to LDS offset dw_rs; a length of 0 means no schedule
+  const unsigned* dw_rs_g;
+  int dw_rs, dw_rs_words, dw_rs4_off, dw_rs4_len, dw_rs16_off, dw_rs16_len;
 };
 
 // scalar slots in the record's / LDS scalar block
