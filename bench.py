@@ -148,8 +148,8 @@ def main():
                          "molecule; adjoint: parameter gradients on the 6-nucleus molecule")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the walker-parallel path would shard "
-                          "walkers across GPUs (see DESIGN.md) but no multi-GPU run is provided"}))
+        print(json.dumps({"error": "one GPU only: walkers are independent between branching steps, so the "
+                          "path would shard them across GPUs, but no multi-GPU run is provided"}))
         sys.exit(2)
 
     import torch

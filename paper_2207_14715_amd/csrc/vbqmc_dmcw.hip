@@ -169,6 +169,20 @@ __device__ __forceinline__ double dw_dot(const double* row, const double (&C)[NC
   return a0 + a1;
 }
 
+// The same sum with the row held across the lanes (lane j holds row[j]):
+// each entry reaches every lane through readlane, so the dot product needs
+// no LDS round trip.  Same summation order as dw_dot.
+template <int NC>
+__device__ __forceinline__ double dw_dotl(double r, const double (&C)[NC]) {
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < NC; j += 2) {
+    a0 += dw_readlane(r, j) * C[j];
+    a1 += dw_readlane(r, j + 1) * C[j + 1];
+  }
+  return a0 + a1;
+}
+
 // column lane of [B | T] from the record: lane k < n takes column k of B,
 // lane n + q column q of T; other lanes and rows past n hold zero.  Every
 // load is in the record (row index clamped), the mask zeroes what is unused.
@@ -306,46 +320,26 @@ __device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
   else dw_radial_plain<NPT, MODE>(wf, l);
 }
 
-// angular polynomial P of function (m, lq) at displacement (x, y, z) and its
-// derivative along axis c (0..2)
-__device__ __forceinline__ void dw_poly(int lq, int m, double x, double y, double z, int c, double& P, double& Pc) {
-  double Px = 0.0, Py = 0.0, Pz = 0.0;
-  if (lq == 0) {
-    P = 1.0;
-  } else if (lq == 1) {
-    P = m == 0 ? x : (m == 1 ? y : z);
-    Px = m == 0 ? 1.0 : 0.0;
-    Py = m == 1 ? 1.0 : 0.0;
-    Pz = m == 2 ? 1.0 : 0.0;
-  } else {
-    switch (m) {
-      case 0: P = x * y; Px = y; Py = x; break;
-      case 1: P = y * z; Py = z; Pz = y; break;
-      case 2: P = z * x; Px = z; Pz = x; break;
-      case 3: P = x * x - y * y; Px = 2.0 * x; Py = -2.0 * y; break;
-      default: P = 2.0 * z * z - x * x - y * y; Px = -2.0 * x; Py = -2.0 * y; Pz = 4.0 * z;
-    }
-  }
-  Pc = c == 0 ? Px : (c == 1 ? Py : Pz);
-}
-
 // The contraction with lambda^T is split over the basis functions: wavefront
 // g takes k-steps g kper .. (g + 1) kper - 1 (kper = Mpad / 16; a k-step is
 // four functions) for every 16-column tile.  Its slice of lambda^T in the
 // MFMA B-operand layout is loaded into registers once per launch and serves
-// every row tile of the step (lambda is constant).
-constexpr int kDwLK = 16;  // k-steps per wavefront: Mpad <= 4 kDwW kDwLK = 256
+// every row tile of the step (lambda is constant).  LK (4, 8 or 16) is the
+// smallest of those that holds kper: k-steps past kper carry zeros.
+constexpr int kDwLK = 16;  // most k-steps per wavefront: Mpad <= 4 kDwW kDwLK = 256
 constexpr int kDwLC = 3;   // column tiles: nop <= 48
 
+template <int LK>
 struct DwLam {
-  double b[kDwLK][kDwLC];
+  double b[LK][kDwLC];
 };
 
-__device__ __forceinline__ void dw_load_lam(const DevWF& wf, DwLam& L) {
+template <int LK>
+__device__ __forceinline__ void dw_load_lam(const DevWF& wf, DwLam<LK>& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kper = wf.Mpad / (4 * kDwW), nct = wf.nop / 16;
 #pragma unroll
-  for (int t = 0; t < kDwLK; ++t)
+  for (int t = 0; t < LK; ++t)
 #pragma unroll
     for (int c = 0; c < kDwLC; ++c) {
       const bool in = t < kper && c < nct;
@@ -356,49 +350,139 @@ __device__ __forceinline__ void dw_load_lam(const DevWF& wf, DwLam& L) {
     }
 }
 
+// a choice between two values already formed, kept as a select (marked
+// unpredictable so that the compiler does not turn it into a branch)
+__device__ __forceinline__ double dw_sel(bool c, double a, double b) { return __builtin_unpredictable(c) ? a : b; }
+
+// Tables of a row tile of NPT points (point p at pts + ps p): the
+// displacement from each nucleus a with its square, and the harmonic table,
+// for harmonic h = m + l^2 of the unnormalised set (1; x, y, z; xy, yz, zx,
+// x^2 - y^2, 2z^2 - x^2 - y^2) the polynomial at the displacement and, for
+// MODE 0, its x, y, z derivatives.  With the harmonic table an element of
+// the contraction is a lookup, not a branch over harmonics.  MODE 0: wave
+// ch forms channel ch (value, d/dx, d/dy, d/dz) of every (p, a), so that the
+// channel's formulas are the same across the wave.
+template <int NPT, int MODE>
+__device__ __forceinline__ void dw_tile_tables(const DevWF& wf, const Ld& l, const double* pts, int ps) {
+  const int nn = wf.nnuc;
+  double* H = l.L + wf.dw_harm;
+  const int ch = MODE == 0 ? (int)(threadIdx.x >> 6) : 0;
+  const int first = MODE == 0 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int stride = MODE == 0 ? 64 : kDwNT;
+  for (int pa = first; pa < NPT * nn; pa += stride) {
+    const int p = pa / nn, a = pa - p * nn;
+    const double* nu = l.nuc() + 4 * a;
+    const double x = pts[ps * p] - nu[0], y = pts[ps * p + 1] - nu[1], z = pts[ps * p + 2] - nu[2];
+    if (ch == 0) {
+      double* d = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
+      d[0] = x; d[1] = y; d[2] = z; d[3] = x * x + y * y + z * z;
+    }
+    double v[9];
+    if (ch == 0) {
+      v[0] = 1.0; v[1] = x; v[2] = y; v[3] = z;
+      v[4] = x * y; v[5] = y * z; v[6] = z * x; v[7] = x * x - y * y; v[8] = 2.0 * z * z - x * x - y * y;
+    } else if (ch == 1) {
+      v[0] = 0.0; v[1] = 1.0; v[2] = 0.0; v[3] = 0.0;
+      v[4] = y; v[5] = 0.0; v[6] = z; v[7] = 2.0 * x; v[8] = -2.0 * x;
+    } else if (ch == 2) {
+      v[0] = 0.0; v[1] = 0.0; v[2] = 1.0; v[3] = 0.0;
+      v[4] = x; v[5] = z; v[6] = 0.0; v[7] = -2.0 * y; v[8] = -2.0 * y;
+    } else {
+      v[0] = 0.0; v[1] = 0.0; v[2] = 0.0; v[3] = 1.0;
+      v[4] = 0.0; v[5] = y; v[6] = x; v[7] = 0.0; v[8] = 4.0 * z;
+    }
+#pragma unroll
+    for (int h = 0; h < 9; ++h) {
+      if constexpr (MODE == 0) H[(pa * 9 + h) * 4 + ch] = v[h];
+      else H[pa * 9 + h] = v[h];
+    }
+  }
+}
+
 // One 16-row tile on MFMA: rows r = 4 p + c of the A operand are built on
-// the fly from the tables (MODE 0: channel c = value, d/dx, d/dy, d/dz of
-// point p; MODE 1: the Laplacian of point r), contracted with lambda^T from
-// registers.  The four wavefronts' partial sums meet in part ([4][kDwLC][4]
+// the fly from the radial and harmonic tables (MODE 0: channel c = value,
+// d/dx, d/dy, d/dz of point p; MODE 1: the Laplacian of point r), contracted
+// with lambda^T from registers.  The element of k-step t + 1 is formed while the products of
+// k-step t run; the LK steps carry no branch (steps past kper add zeros).  The four wavefronts' partial sums meet in part ([4][kDwLC][4]
 // [64] doubles) and are added in a fixed order; output row 4 q + lane / 16 of
 // register q at orbital column p goes to out[row][slot], slot = cmap[p]
 // (orbitals a spin does not use are dropped).  Ends with a barrier.
-template <int MODE>
+template <int MODE, int LK>
 __device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int* cmap, double* out, double* part,
-                                       const DwLam& L) {
+                                       const DwLam<LK>& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   const int p = MODE == 0 ? row >> 2 : row, c = row & 3;
+  const int ax = c == 0 ? 0 : c - 1;
   const double* disp = l.L + wf.dw_disp + p * (4 * wf.nnuc + 1);
   const double* gt = l.L + wf.dw_gtab + p * (MODE == 0 ? 2 * wf.nshell + 1 : (wf.nshell | 1));
   const int nct = wf.nop / 16, kper = wf.Mpad / (4 * kDwW), kb = wave * kper;
+  // A element of k-step t (function 4 (kb + t) + kq; padding functions and
+  // steps past kper read function 0 and give 0), in three stages so that
+  // loads can be issued ahead of their use: the function word, the table
+  // entries (harmonic, its derivative along this lane's axis, the
+  // displacement along it, the radial entries), then the element
+  struct Src {
+    double P, D, dc, g0, g1;
+    bool fn;
+  };
+  const double* harm = l.L + wf.dw_harm;
+  const int nn = wf.nnuc;
+  auto word = [&](int t) -> int2 {
+    // (one 8-byte load, so that the second word is not loaded under a branch)
+    const long long v = ((const long long*)l.fn())[t < kper ? 4 * (kb + t) + kq : 0];
+    return make_int2((int)v, (int)(v >> 32));
+  };
+  auto fetch = [&](int t, int2 w) -> Src {
+    Src q;
+    q.fn = t < kper && w.x >= 0;
+    const int sh = q.fn ? w.x : 0, nuc = q.fn ? (w.y >> 8) : 0;
+    const int lq = (w.y >> 4) & 3, h = q.fn ? (w.y & 15) + lq * lq : 0;
+    if constexpr (MODE == 0) {
+      const double* hp = harm + ((p * nn + nuc) * 9 + h) * 4;
+      q.P = hp[0];
+      q.D = hp[c];
+      q.dc = disp[4 * nuc + ax];
+      q.g0 = gt[2 * sh];
+      q.g1 = gt[2 * sh + 1];
+    } else {
+      q.P = harm[(p * nn + nuc) * 9 + h];
+      q.D = q.dc = q.g1 = 0.0;
+      q.g0 = gt[sh];
+    }
+    return q;
+  };
+  auto elem = [&](const Src& q) -> double {
+    double v;
+    if constexpr (MODE == 0) {
+      const double v0 = q.P * q.g0, vd = q.D * q.g0 + 2.0 * q.g1 * q.P * q.dc;
+      v = dw_sel(c == 0, v0, vd);
+    } else {
+      v = q.P * q.g0;
+    }
+    return dw_sel(q.fn, v, 0.0);
+  };
   v4d acc[kDwLC];
 #pragma unroll
   for (int ct = 0; ct < kDwLC; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[ct][r] = 0.0;
+  int2 wn = word(0);
+  Src q = fetch(0, wn);
+  if (LK > 1) wn = word(1);
+  double a = elem(q);
+  if (LK > 1) q = fetch(1, wn);
+  if (LK > 2) wn = word(2);
 #pragma unroll
-  for (int t = 0; t < kDwLK; ++t) {
-    if (t < kper) {
-      const FnInfo fi = fn_info(l, 4 * (kb + t) + kq);
-      // (padding functions read shell 0 of nucleus 0 and are zeroed)
-      const bool fn = fi.sh >= 0;
-      const double* d = disp + 4 * (fn ? fi.nuc : 0);
-      const int sh = fn ? fi.sh : 0;
-      const double x = d[0], y = d[1], z = d[2];
-      double P, Pc, v;
-      if constexpr (MODE == 0) {
-        const double gg = gt[2 * sh], g1 = gt[2 * sh + 1];
-        dw_poly(fi.lq, fi.m, x, y, z, c == 0 ? 0 : c - 1, P, Pc);
-        const double dc = c == 1 ? x : (c == 2 ? y : z);
-        v = c == 0 ? P * gg : Pc * gg + 2.0 * g1 * P * dc;
-      } else {
-        dw_poly(fi.lq, fi.m, x, y, z, 0, P, Pc);
-        v = P * gt[sh];
+  for (int t = 0; t < LK; ++t) {
+#pragma unroll
+    for (int ct = 0; ct < kDwLC; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, L.b[t][ct], acc[ct], 0, 0, 0);
+    if (t + 1 < LK) {
+      a = elem(q);
+      if (t + 2 < LK) {
+        q = fetch(t + 2, wn);
+        if (t + 3 < LK) wn = word(t + 3);
       }
-      const double a = fn ? v : 0.0;
-#pragma unroll
-      for (int ct = 0; ct < kDwLC; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, L.b[t][ct], acc[ct], 0, 0, 0);
     }
   }
   double* pw = part + wave * (kDwLC * 4 * 64);
@@ -423,7 +507,7 @@ __device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int*
 // prep = 1: rebuild each record from its positions (orbital-row caches of
 // every electron, fresh inverses, tables, ratios, E_L) with no move and no
 // weight; prep = 0: one DMC step.
-template <int NC, int XE>
+template <int NC, int XE, int LK>
 __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dmcw(const DevWF* __restrict__ pwf, double* state, const double* ctrl,
                                                 uint64_t seed, uint32_t step, double tau, DmcBranch br, double* nacc,
                                                 int prep) {
@@ -459,8 +543,8 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   double* Pw = lds_dyn + wf.dw_P; // per walker: proposal x, y, z, drift x, y, z
   double* V4 = lds_dyn + wf.dw_V4;
   double* part = lds_dyn + wf.dw_part;  // partial sums of the row tiles
-  DwLam lam;
-  dw_load_lam(wf, lam);
+  DwLam<LK> lam;
+  dw_load_lam<LK>(wf, lam);
   // records of dead wavefronts (past W) are never read or written
   double* rec = state + (live ? w : wbase) * wf.rec_len;
   for (int k = lane; k < 3 * N; k += 64) Rl[k] = rec[wf.r_R + k];
@@ -492,13 +576,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       const int s = spin_of(wf, i);
       if (lane < 3) Pw[6 * g + lane] = live ? Rl[3 * i + lane] : 0.0;
       __syncthreads();
-      for (int t = threadIdx.x; t < kDwW * nn; t += kDwNT) {
-        const int p = t / nn, a = t - p * nn;
-        const double* nu = l.nuc() + 4 * a;
-        double* d = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
-        const double x = Pw[6 * p] - nu[0], y = Pw[6 * p + 1] - nu[1], z = Pw[6 * p + 2] - nu[2];
-        d[0] = x; d[1] = y; d[2] = z; d[3] = x * x + y * y + z * z;
-      }
+      dw_tile_tables<kDwW, 0>(wf, l, Pw, 6);
       __syncthreads();
       dw_radial<kDwW, 0>(wf, l);
       __syncthreads();
@@ -562,22 +640,19 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       double uo[2] = {0.0, 0.0};  // Jastrow pair values at the current point, per partner lane
       // (A) drift at the current point from the cached gradient rows
       if (act) {
-        if (lane < WD)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) xr[c * 64 + lane] = gn[c];
+        const double g3[3] = {gn[0], gn[1], gn[2]};
         if (il + 1 < n && lane < WD)
 #pragma unroll
           for (int c = 0; c < 3; ++c) gn[c] = gc[((size_t)(i + 1) * 3 + c) * WD + lane];
         if (lane == il)
 #pragma unroll
           for (int j = 0; j < NC; ++j) bc[j] = C[j];
-        wave_sync();
         double t[3], rp[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          t[c] = dw_dot<NC>(xr + c * 64, C);
+          t[c] = dw_dotl<NC>(g3[c], C);
           rp[c] = dw_readlane(t[c], il);
-          if (tlane) yr[c * 64 + (lane - n)] = xr[c * 64 + lane] - t[c];
+          if (tlane) yr[c * 64 + (lane - n)] = g3[c] - t[c];
         }
         wave_sync();
         double part[6];
@@ -627,13 +702,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       }
       __syncthreads();
       // (B) value and gradient rows at the four proposals
-      for (int t2 = threadIdx.x; t2 < kDwW * nn; t2 += kDwNT) {
-        const int p = t2 / nn, a = t2 - p * nn;
-        const double* nu = l.nuc() + 4 * a;
-        double* dd = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
-        const double x = Pw[6 * p] - nu[0], y = Pw[6 * p + 1] - nu[1], z = Pw[6 * p + 2] - nu[2];
-        dd[0] = x; dd[1] = y; dd[2] = z; dd[3] = x * x + y * y + z * z;
-      }
+      dw_tile_tables<kDwW, 0>(wf, l, Pw, 6);
       __syncthreads();
       dw_radial<kDwW, 0>(wf, l);
       __syncthreads();
@@ -644,9 +713,10 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         const double* vr = V4 + (4 * g) * 64;  // rows value, x, y, z
         // value channel first; the gradient channels only once the ratio
         // passes the node check
-        const double t0 = dw_dot<NC>(vr, C);
+        const double v0 = vr[lane];
+        const double t0 = dw_dotl<NC>(v0, C);
         const double rho = dw_readlane(t0, il);
-        const double yv = tlane ? vr[lane] - t0 : 0.0;
+        const double yv = tlane ? v0 - t0 : 0.0;
         if (tlane) yr[lane - n] = yv;
         wave_sync();
         double qh[2], part[2] = {0.0, 0.0};
@@ -696,9 +766,10 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           double a[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double tc = dw_dot<NC>(vr + (1 + c) * 64, C);
+            const double vg = vr[(1 + c) * 64 + lane];
+            const double tc = dw_dotl<NC>(vg, C);
             a[c] = dw_readlane(tc, il);
-            if (tlane) yr[(1 + c) * 64 + (lane - n)] = vr[(1 + c) * 64 + lane] - tc - a[c] * yv * ir;
+            if (tlane) yr[(1 + c) * 64 + (lane - n)] = vg - tc - a[c] * yv * ir;
           }
           wave_sync();
           double dp[6] = {0.0, 0.0, 0.0, jg[0], jg[1], jg[2]};
@@ -895,8 +966,12 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       dw_load_columns<NC>(rec + wf.r_B[0], Tg, n, nP, lane, C);
       dw_load_dets(sp, Tg, RW, RW + n0 + n1, lane, d);
     }
+    double ge[3] = {0.0, 0.0, 0.0};  // cached gradient rows of the next electron, in flight
 #pragma unroll 1
     for (int i0 = 0; i0 < n; i0 += 4) {
+      if (!bad && lane < WD)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ge[c] = gc[((size_t)(e0 + i0) * 3 + c) * WD + lane];
       // Laplacian rows of electrons e0 + i0 .. + 3 of the four walkers
       if (threadIdx.x < 3 * 16) {
         const int p = threadIdx.x / 3, c = threadIdx.x - 3 * p;
@@ -905,13 +980,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         Pw[24 + 3 * p + c] = il < n ? Rg[3 * (e0 + il) + c] : 0.0;
       }
       __syncthreads();
-      for (int t2 = threadIdx.x; t2 < 16 * nn; t2 += kDwNT) {
-        const int p = t2 / nn, a = t2 - p * nn;
-        const double* nu = l.nuc() + 4 * a;
-        double* dd = l.L + wf.dw_disp + p * (4 * nn + 1) + 4 * a;
-        const double x = Pw[24 + 3 * p] - nu[0], y = Pw[24 + 3 * p + 1] - nu[1], z = Pw[24 + 3 * p + 2] - nu[2];
-        dd[0] = x; dd[1] = y; dd[2] = z; dd[3] = x * x + y * y + z * z;
-      }
+      dw_tile_tables<16, 1>(wf, l, Pw + 24, 3);
       __syncthreads();
       dw_radial<16, 1>(wf, l);
       __syncthreads();
@@ -920,21 +989,19 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
 #pragma unroll 1
         for (int e4 = 0; e4 < 4 && i0 + e4 < n; ++e4) {
           const int il = i0 + e4, i = e0 + il;
-          for (int k = lane; k < WD; k += 64)
+          const double rw[4] = {ge[0], ge[1], ge[2], V4[(4 * g + e4) * 64 + lane]};
+          if (e4 + 1 < 4 && il + 1 < n && lane < WD)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) xr[c * 64 + k] = gc[((size_t)i * 3 + c) * WD + k];
+            for (int c = 0; c < 3; ++c) ge[c] = gc[((size_t)(i + 1) * 3 + c) * WD + lane];
           if (lane == il)
 #pragma unroll
             for (int j = 0; j < NC; ++j) bc[j] = C[j];
-          wave_sync();
-          const double* lrow = V4 + (4 * g + e4) * 64;
           double t[4], rp[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const double* row = c < 3 ? xr + c * 64 : lrow;
-            t[c] = dw_dot<NC>(row, C);
+            t[c] = dw_dotl<NC>(rw[c], C);
             rp[c] = dw_readlane(t[c], il);
-            if (tlane) yr[c * 64 + (lane - n)] = row[lane] - t[c];
+            if (tlane) yr[c * 64 + (lane - n)] = rw[c] - t[c];
           }
           wave_sync();
           double part[9];
@@ -996,7 +1063,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     for (int k = lane; k < 3 * N; k += 64) rec[wf.r_R + k] = Rl[k];
 }
 
-template <int NC, int XE>
+template <int NC, int XE, int LK>
 static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
                                 uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
                                 hipStream_t s) {
@@ -1004,12 +1071,12 @@ static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state
   static size_t cur = 0;
   if (lds > cur) {
     hipError_t e =
-        hipFuncSetAttribute((const void*)k_dmcw<NC, XE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipFuncSetAttribute((const void*)k_dmcw<NC, XE, LK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     cur = lds;
   }
   const unsigned blocks = (unsigned)((cap + kDwW - 1) / kDwW);
-  hipLaunchKernelGGL((k_dmcw<NC, XE>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau, br,
+  hipLaunchKernelGGL((k_dmcw<NC, XE, LK>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau, br,
                      nacc, prep);
   return hipGetLastError();
 }
@@ -1020,8 +1087,17 @@ static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state
 hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
                        uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
                        hipStream_t s) {
-  if (wf.dw_xe <= 2) return launch_dmcw_t<32, 2>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s);
-  return launch_dmcw_t<32, 3>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s);
+  const int kper = wf.Mpad / (4 * kDwW);
+#define VBQMC_DMCW(XE, LK) return launch_dmcw_t<32, XE, LK>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s)
+  if (wf.dw_xe <= 2) {
+    if (kper <= 4) VBQMC_DMCW(2, 4);
+    if (kper <= 8) VBQMC_DMCW(2, 8);
+    VBQMC_DMCW(2, 16);
+  }
+  if (kper <= 4) VBQMC_DMCW(3, 4);
+  if (kper <= 8) VBQMC_DMCW(3, 8);
+  VBQMC_DMCW(3, 16);
+#undef VBQMC_DMCW
 }
 
 }  // namespace vbqmc

@@ -562,6 +562,7 @@ DevWF dmcw_layout(const vbqmc_ctx* x) {
   a.dw_disp = lds(16 * (4 * x->nnuc + 1));
   a.dw_gtab = lds(std::max(4 * (2 * x->nshell + 1), 16 * (x->nshell | 1)));
   a.dw_V4 = lds(16 * 64);
+  a.dw_harm = lds(std::max(4 * 9 * 4, 16 * 9) * x->nnuc);
   const int tend = lds.o;
   lds.o = t0;
   int astr = 1;

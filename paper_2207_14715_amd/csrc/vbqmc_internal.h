@@ -115,6 +115,10 @@ struct DevWF {
   int dw_wave, dw_wstride, dwo_R, dwo_bc, dwo_x, dwo_y, dwo_piv, dwo_f;
   int dw_P, dw_cmap, dw_disp, dw_gtab, dw_V4, dw_A, dw_Astride, lds_dmcw_doubles;
   int dw_part;  // partial sums of the row-tile contraction [4][3][4][64]
+  // harmonic table of a row tile (in the tile region): per point p and
+  // nucleus a the nine angular polynomials h = m + l^2 at the displacement,
+  // with (four points) their x, y, z derivatives: [p][a][9][4], else [p][a][9]
+  int dw_harm;
   int dw_rnd;   // per wavefront, the draws of a spin's moves [64][4] (normals, acceptance uniform)
   // radial schedules of the row tiles (four points x 64 bins; sixteen
   // points x 16 bins; entry j of bin b at [j][b], words as kRsPrim), staged

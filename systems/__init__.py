@@ -24,7 +24,7 @@ A system is a plain dict:
                   "poly": [b3, b4, b5, b6]},
                   "en": [{"a1", "a2", "poly": [a3, a4, a5, a6]} per nucleus]}
 
-The generator recipes (seeds, distributions, shapes) are listed in the design doc.
+Each generator's docstring gives its recipe (seed, distributions, shapes).
 """
 
 from .generate import (  # noqa: F401
