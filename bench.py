@@ -410,13 +410,14 @@ def adjoint_form(args):
 
 
 HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"
-DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2>"}
+DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16>"}
 # HBM bytes of one launch of the walker-resident DMC step kernel on the
 # headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the copy-kernel calibration (the factors below), with
 # the SHA-256 prefix of the kernel source they were taken on: the value is
 # reported only while the source is unchanged (else null).
-DMCW_TRAFFIC = None  # {"src_sha": "...", "fetch_kib": F, "write_kib": Wr, "fetch_factor": a, "write_factor": b, "walkers": n}
+DMCW_TRAFFIC = {"src_sha": "ec776ce21bcf5d81", "fetch_kib": 3263307.0, "write_kib": 3951291.6, "fetch_factor": 2.000,
+                "write_factor": 1.000, "walkers": 32768}
 
 
 def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
@@ -452,7 +453,7 @@ def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
     return tot
 
 
-def cpu_baseline_dmc(system, walkers=32, steps=3, seed=13):
+def cpu_baseline_dmc(system, walkers=64, steps=5, seed=13):
     """The oracle's DMC (plain FP64 CPU code, OpenMP over walkers, every
     determinant by a fresh LU for every proposal) on a bounded sample of the
     same workload: `walkers` walkers x `steps` steps from the same start."""
@@ -520,6 +521,7 @@ def dmc_form(args):
     moves = float(pop.sum())
     accept = float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1))
     e_mixed = float(out["wesum"].sum().item() / out["wsum"].sum().item())
+    e_mixed_clipped = float(out["wcsum"].sum().item() / out["wsum"].sum().item())
     kern = ctx.info["dmc_kernel"]
     step_ms = out["step_ms"]
     nupd_rate = [accept * n / 32.0 for n in (ctx.info["n_up"], ctx.info["n_dn"])]  # refreshes per step per spin
@@ -557,6 +559,7 @@ def dmc_form(args):
         "population_band": [float(pop.min() / W - 1), float(pop.max() / W - 1)],
         "e_trial": out["e_trial"],
         "e_mixed": e_mixed,
+        "e_mixed_clipped": e_mixed_clipped,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": DMC_KERNEL_NAMES[kern], "kernel_avg_ms_per_launch": kavg * 1e3,

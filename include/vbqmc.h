@@ -264,7 +264,9 @@ int vbqmc_vmc_measure(vbqmc_ctx* ctx, void* state, int64_t W, const vbqmc_vmc_ac
  * proposed single-electron moves.  step_ms [host][n_steps] or NULL: when set,
  * each step's move-and-local-energy kernels are bracketed by HIP events on
  * the call's stream and their elapsed milliseconds are written here before
- * the call returns (branching and compaction are not included). */
+ * the call returns (branching and compaction are not included).  wcsum
+ * [dev][n_steps] or NULL: sum of weight * E_L clipped to E_T +- sqrt(N/tau),
+ * the estimator the trial-energy feedback uses. */
 typedef struct {
   double* pop;
   double* wsum;
@@ -273,6 +275,7 @@ typedef struct {
   double* n_accept;
   double* n_prop;
   double* step_ms;
+  double* wcsum;
 } vbqmc_dmc_log;
 
 /*

@@ -790,11 +790,12 @@ int orc_vmc(void* h, int W, double* R, int nsteps, uint64_t seed, uint32_t step0
 // to the rounding noise of floor(w + u).
 // R: [capacity][N][3]; eloc_io: [capacity] local energies of the walkers;
 // per-step outputs (length nsteps): pop (walkers before branching),
-// wsum = sum w, wesum = sum w E_L, etrial (E_T used in the step),
-// acc / prop (accepted / proposed single-electron moves).
+// wsum = sum w, wesum = sum w E_L, wcsum = sum w E_L clipped (the estimator
+// of the E_T feedback), etrial (E_T used in the step), acc / prop
+// (accepted / proposed single-electron moves).
 int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int nsteps,
             uint64_t seed, uint32_t step0, double tau, double* etrial_io, int W_target,
-            double* pop, double* wsum, double* wesum, double* etrial, double* acc, double* prop) {
+            double* pop, double* wsum, double* wesum, double* wcsum, double* etrial, double* acc, double* prop) {
   const System& s = *(System*)h;
   Params<double> P = make_params<double>(s, -1);
   const int N = s.N;
@@ -876,6 +877,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
     pop[st] = W;
     wsum[st] = sw;
     wesum[st] = swe;
+    wcsum[st] = swc;
     etrial[st] = ET + std::log(f) / tau;
     acc[st] = na;
     prop[st] = np;

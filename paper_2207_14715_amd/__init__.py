@@ -73,7 +73,16 @@ class _VmcAcc(ctypes.Structure):
 class _DmcLog(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("wesum", ctypes.c_void_p),
                 ("etrial", ctypes.c_void_p), ("n_accept", ctypes.c_void_p), ("n_prop", ctypes.c_void_p),
-                ("step_ms", ctypes.POINTER(ctypes.c_double))]
+                ("step_ms", ctypes.POINTER(ctypes.c_double)), ("wcsum", ctypes.c_void_p)]
+
+
+# per-step DMC records (device tensors); "wcsum" may be left out
+_DMC_LOG_KEYS = ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop", "wcsum")
+
+
+def _dmc_log(log, step_ms):
+    return _DmcLog(*[log[k].data_ptr() for k in _DMC_LOG_KEYS[:6]], step_ms,
+                   log["wcsum"].data_ptr() if "wcsum" in log else None)
 
 
 _lib = None
@@ -318,11 +327,9 @@ class Context:
         if workspace is None:
             workspace = self.dmc_workspace(cap, n_steps, dev)
         if log is None:
-            log = {k: torch.zeros(n_steps, dtype=torch.float64, device=dev)
-                   for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")}
+            log = {k: torch.zeros(n_steps, dtype=torch.float64, device=dev) for k in _DMC_LOG_KEYS}
         step_ms = np.zeros(max(n_steps, 1)) if time_steps else None
-        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")],
-                     _dp(step_ms) if time_steps else None)
+        lg = _dmc_log(log, _dp(step_ms) if time_steps else None)
         arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
         Wio = ctypes.c_int64(W)
         et = ctypes.c_double(e_trial)
@@ -340,7 +347,7 @@ class Context:
         """vbqmc_dmc_advance on the library's fixed scratch array: the caller
         passes the records and the per-step log, nothing is allocated."""
         cap = states[0].shape[0]
-        lg = _DmcLog(*[log[k].data_ptr() for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")], None)
+        lg = _dmc_log(log, None)
         arr = (ctypes.c_void_p * 2)(states[0].data_ptr(), states[1].data_ptr())
         Wio = ctypes.c_int64(W)
         et = ctypes.c_double(e_trial)

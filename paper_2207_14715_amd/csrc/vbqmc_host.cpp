@@ -33,8 +33,8 @@ hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* st
                            uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s);
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
                            int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
-                           double* etrial, double* lacc, double* lprop, const double* src, double* dst, int rec_len,
-                           hipStream_t s);
+                           double* wcsum, double* etrial, double* lacc, double* lprop, const double* src,
+                           double* dst, int rec_len, hipStream_t s);
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s);
@@ -1526,7 +1526,7 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
       return hipfail(x, e, "dmc: step");
     }
     e = launch_dmc_tail(ctrl, br, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
-                        lg->wesum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
+                        lg->wesum, lg->wcsum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
     if (e != hipSuccess) {
       drop_events();
       return hipfail(x, e, "dmc: branching");

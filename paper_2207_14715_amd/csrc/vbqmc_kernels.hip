@@ -701,7 +701,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, const double* nacc, int* offs,
                                                    int64_t capacity, int N, int st, double tau,
                                                    double W_target, double* pop, double* wsum,
-                                                   double* wesum, double* etrial, double* lacc, double* lprop) {
+                                                   double* wesum, double* wcsum, double* etrial, double* lacc,
+                                                   double* lprop) {
   __shared__ double sw[1024], swe[1024], swc[1024], sa[1024];
   __shared__ int sc_[1024];
   __shared__ int bad;
@@ -776,6 +777,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
     pop[st] = (double)W;
     wsum[st] = sw[0];
     wesum[st] = swe[0];
+    if (wcsum) wcsum[st] = swc[0];
     etrial[st] = ctrl[DC_ET] + log(f) / tau;
     lacc[st] = sa[0];
     lprop[st] = (double)W * N;
@@ -978,10 +980,10 @@ hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* st
 
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
                            int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
-                           double* etrial, double* lacc, double* lprop, const double* src, double* dst, int rec_len,
-                           hipStream_t s) {
+                           double* wcsum, double* etrial, double* lacc, double* lprop, const double* src,
+                           double* dst, int rec_len, hipStream_t s) {
   hipLaunchKernelGGL(k_dmc_scan, dim3(1), dim3(1024), 0, s, ctrl, br, nacc, offs, cap, N, st, tau, W_target, pop,
-                     wsum, wesum, etrial, lacc, lprop);
+                     wsum, wesum, wcsum, etrial, lacc, lprop);
   hipLaunchKernelGGL(k_dmc_copy, dim3((unsigned)cap), dim3(256), 0, s, ctrl, src, dst, offs, rec_len);
   hipLaunchKernelGGL(k_dmc_commit, dim3(1), dim3(1), 0, s, ctrl);
   return hipGetLastError();

@@ -323,6 +323,7 @@ def _check_dmc(ref, out, R, e_rec=None, oracle_obj=None):
     assert out["W"] == ref["W"]
     np.testing.assert_allclose(out["wsum"].cpu().numpy(), ref["wsum"], rtol=1e-9)
     np.testing.assert_allclose(out["wesum"].cpu().numpy(), ref["wesum"], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(out["wcsum"].cpu().numpy(), ref["wcsum"], rtol=1e-8, atol=1e-8)
     np.testing.assert_allclose(out["etrial"].cpu().numpy(), ref["etrial"], rtol=1e-9, atol=1e-9)
     np.testing.assert_array_equal(out["n_accept"].cpu().numpy(), ref["acc"])
     np.testing.assert_allclose(R, ref["R"], rtol=1e-8, atol=1e-8)

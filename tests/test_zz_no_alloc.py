@@ -25,10 +25,10 @@ def lib():
 def _log(n, dev="cuda"):
     import torch
     return {k: torch.zeros(n, dtype=torch.float64, device=dev)
-            for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop")}
+            for k in ("pop", "wsum", "wesum", "wcsum", "etrial", "n_accept", "n_prop")}
 
 
-@pytest.mark.parametrize("kern", [1, 2])
+@pytest.mark.parametrize("kern", [1, 2, 3])
 def test_noalloc_matches_workspace_entry_point(lib, oracle_mod, kern):
     import torch
     sysd = S.small_random_system(311, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1, n_structures=4)
@@ -56,7 +56,7 @@ def test_noalloc_matches_workspace_entry_point(lib, oracle_mod, kern):
     got = [run(c, True) for c in cases]  # two no-alloc calls in a row, the second smaller
     for (a, Ra, ea), (b, Rb, eb) in zip(ref, got):
         assert a["W"] == b["W"] and a["e_trial"] == b["e_trial"]
-        for k in ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop"):
+        for k in ("pop", "wsum", "wesum", "wcsum", "etrial", "n_accept", "n_prop"):
             assert torch.equal(a[k], b[k]), k
         np.testing.assert_array_equal(Ra, Rb)
         np.testing.assert_array_equal(ea, eb)
