@@ -348,6 +348,58 @@ int vbqmc_reduce_walkers(vbqmc_ctx* ctx, int64_t W, int32_t K, const double* wei
 int vbqmc_weights_chirgwin_coulson(int32_t n, const double* S, const double* c, double* w);
 int vbqmc_weights_lowdin(int32_t n, const double* S, const double* c, double* w);
 
+/*
+ * Linear optimisation method (Sec. 2.2, Eqs. Psiblin, geneigeq; its sampled
+ * form Sec. 2.3.1, Eqs. geneigeqM, Hi0, H0j, Hij, Sij).
+ *
+ * Sample sums.  With O_kj = Psi_j/Psi_0 = d ln|Psi|/dp_j and
+ * D_kj = E_L,j = d E_L/dp_j of sample k (vbqmc_param_grad), E_k its local
+ * energy and w_k its weight (1 for VMC samples), the accumulator holds three
+ * row-major (P+1) x (P+1) matrices, P = n_params, of the augmented rows
+ * X_k = [1 | O_k] and Y_k = [E_k^2 | D_k]:
+ *   S'[i][j] = sum_k w_k X_ki X_kj,  H'[i][j] = sum_k w_k E_k X_ki X_kj,
+ *   D'[i][j] = sum_k w_k X_ki Y_kj
+ * (so row 0 holds sum w, sum w O_j, sum w E, sum w E O_j, sum w E^2,
+ * sum w D_j).  vbqmc_lm_acc_doubles gives the length 3 (P+1)^2.
+ * vbqmc_lm_accumulate adds W samples to acc [dev] (the caller zeroes it
+ * before the first call; calls on one stream accumulate in a fixed order,
+ * FP64 MFMA products): dlogpsi, deloc [dev][W][P], eloc [dev][W],
+ * weight [dev][W] or NULL for unit weights.
+ */
+int vbqmc_lm_acc_doubles(int32_t n_params, int64_t* n);
+int vbqmc_lm_accumulate(vbqmc_ctx* ctx, int64_t W, const double* dlogpsi, const double* deloc, const double* eloc,
+                        const double* weight, double* acc, vbqmc_stream stream);
+
+/*
+ * Estimators from an accumulator copied to the host (acc [host], length
+ * vbqmc_lm_acc_doubles(P)), all averages weighted by w: E0 = <E_L>,
+ *   g_L,i = 2 (<O_i E_L> - <O_i><E_L>)                        (Eq. Hi0)
+ *   g_R,j = 2 (<O_j E_L> - <O_j><E_L> + <E_L,j>)              (Eq. H0j)
+ *   Hbar_ij = <O_i O_j E_L> - <O_i><O_j E_L> - <O_j><O_i E_L>
+ *             + <O_i><O_j><E_L> + <O_i E_L,j> - <O_i><E_L,j>  (Eq. Hij)
+ *   Sbar_ij = <O_i O_j> - <O_i><O_j>                          (Eq. Sij)
+ * Outputs [host]: e0 (1), g_l, g_r (P), h_bar, s_bar (P x P row-major),
+ * var (1, <E_L^2> - <E_L>^2) or NULL.  EINVAL if sum w <= 0.
+ */
+int vbqmc_lm_estimators(int32_t n_params, const double* acc, double* e0, double* g_l, double* g_r, double* h_bar,
+                        double* s_bar, double* var);
+
+/*
+ * One linear-method step (Eq. geneigeqM): the eigenvector (1, dp) of
+ *   [[E0, g_R^T/2], [g_L/2, Hbar + a_diag I]] v = E_lin [[1, 0], [0, Sbar]] v
+ * that continues the current wave function, found as the root of
+ * E_lin = E0 - g_R^T (Hbar + a_diag I - E_lin Sbar)^-1 g_L / 4 next to E0
+ * (Newton's method on E_lin, one LU with partial pivoting of the n x n
+ * matrix per iteration), then dp = -(Hbar + a_diag I - E_lin Sbar)^-1 g_L / 2.
+ * a_diag >= 0 is the usual stabilising shift of the diagonal.  Host only:
+ * n the number of parameters in the (sub)problem, g_l, g_r [host][n],
+ * h_bar, s_bar [host][n][n] row-major; outputs dp [host][n], e_lin [host].
+ * ESINGULAR if a matrix becomes singular, ENONFINITE if the iteration does
+ * not converge within 100 steps.
+ */
+int vbqmc_lm_solve(int32_t n, double e0, const double* g_l, const double* g_r, const double* h_bar,
+                   const double* s_bar, double a_diag, double* dp, double* e_lin);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,7 +92,8 @@ EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info"
            "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_vmc_sweep", "vbqmc_vmc_measure",
            "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance", "vbqmc_dmc_advance_noalloc",
            "vbqmc_param_grad_workspace_bytes", "vbqmc_param_grad", "vbqmc_reduce_walkers",
-           "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin"]
+           "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin", "vbqmc_lm_acc_doubles",
+           "vbqmc_lm_accumulate", "vbqmc_lm_estimators", "vbqmc_lm_solve"]
 
 
 def load_library(path=LIB_PATH):
@@ -132,6 +133,11 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_weights_chirgwin_coulson.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                                    ctypes.POINTER(dbl)]
     lib.vbqmc_weights_lowdin.argtypes = lib.vbqmc_weights_chirgwin_coulson.argtypes
+    pd = ctypes.POINTER(dbl)
+    lib.vbqmc_lm_acc_doubles.argtypes = [i32, ctypes.POINTER(i64)]
+    lib.vbqmc_lm_accumulate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.vbqmc_lm_estimators.argtypes = [i32, pd, pd, pd, pd, pd, pd, pd]
+    lib.vbqmc_lm_solve.argtypes = [i32, dbl, pd, pd, pd, pd, dbl, pd, pd]
     _lib = lib
     return lib
 
@@ -383,6 +389,27 @@ class Context:
                                                 _ptr(out), _stream()))
         return out.reshape(x.shape[1:])
 
+    def new_lm_acc(self, device="cuda"):
+        """A zeroed accumulator of the linear-method sample sums (3 (P+1)^2 doubles)."""
+        import torch
+        n = ctypes.c_int64()
+        self._rc(self._lib.vbqmc_lm_acc_doubles(self.n_params, ctypes.byref(n)))
+        return torch.zeros(n.value, dtype=torch.float64, device=device)
+
+    def lm_accumulate(self, dlogpsi, deloc, eloc, acc, weight=None):
+        """Add W samples (vbqmc_param_grad outputs, their E_L, optional weights)
+        to the accumulator acc."""
+        import torch
+        W = dlogpsi.shape[0]
+        _check_cuda(dlogpsi, "dlogpsi", torch.float64, (W, self.n_params))
+        _check_cuda(deloc, "deloc", torch.float64, (W, self.n_params))
+        _check_cuda(eloc, "eloc", torch.float64, (W,))
+        _check_cuda(acc, "acc", torch.float64, (3 * (self.n_params + 1) ** 2,))
+        if weight is not None:
+            _check_cuda(weight, "weight", torch.float64, (W,))
+        self._rc(self._lib.vbqmc_lm_accumulate(self._h, W, _ptr(dlogpsi), _ptr(deloc), _ptr(eloc), _ptr(weight),
+                                               _ptr(acc), _stream()))
+
     def get_params(self):
         p = np.zeros(self.n_params)
         self._rc(self._lib.vbqmc_get_params(self._h, _dp(p)))
@@ -415,6 +442,39 @@ def weights_lowdin(S, c):
     if rc != 0:
         raise VBQMCError(rc, "weights_lowdin")
     return w
+
+
+def lm_estimators(acc, n_params):
+    """E0, g_L, g_R, Hbar, Sbar (and the E_L variance) from an accumulator
+    (numpy or tensor; copied to the host)."""
+    lib = load_library()
+    a = np.ascontiguousarray(acc.cpu().numpy() if hasattr(acc, "cpu") else acc, np.float64)
+    P = int(n_params)
+    if a.shape != (3 * (P + 1) ** 2,):
+        raise ValueError("accumulator has the wrong length")
+    e0, var = np.zeros(1), np.zeros(1)
+    gl, gr = np.zeros(P), np.zeros(P)
+    H, Sb = np.zeros((P, P)), np.zeros((P, P))
+    rc = lib.vbqmc_lm_estimators(P, _dp(a), _dp(e0), _dp(gl), _dp(gr), _dp(H), _dp(Sb), _dp(var))
+    if rc != 0:
+        raise VBQMCError(rc, "lm_estimators")
+    return {"e0": float(e0[0]), "g_l": gl, "g_r": gr, "h_bar": H, "s_bar": Sb, "var": float(var[0])}
+
+
+def lm_solve(e0, g_l, g_r, h_bar, s_bar, a_diag=0.0):
+    """(dp, E_lin) of one linear-method step (vbqmc_lm_solve)."""
+    lib = load_library()
+    g_l, g_r = np.ascontiguousarray(g_l, np.float64), np.ascontiguousarray(g_r, np.float64)
+    h_bar, s_bar = np.ascontiguousarray(h_bar, np.float64), np.ascontiguousarray(s_bar, np.float64)
+    n = len(g_l)
+    if g_r.shape != (n,) or h_bar.shape != (n, n) or s_bar.shape != (n, n):
+        raise ValueError("inconsistent shapes")
+    dp, el = np.zeros(n), np.zeros(1)
+    rc = lib.vbqmc_lm_solve(n, float(e0), _dp(g_l), _dp(g_r), _dp(h_bar), _dp(s_bar), float(a_diag), _dp(dp),
+                            _dp(el))
+    if rc != 0:
+        raise VBQMCError(rc, "lm_solve")
+    return dp, float(el[0])
 
 
 def _jvb_function():

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvbqmc.so")
-SOURCES = ["vbqmc_kernels.hip", "vbqmc_sweep.hip", "vbqmc_rows.hip", "vbqmc_dmcb.hip", "vbqmc_dmcw.hip", "vbqmc_adjoint.hip", "vbqmc_host.cpp"]
+SOURCES = ["vbqmc_kernels.hip", "vbqmc_sweep.hip", "vbqmc_rows.hip", "vbqmc_dmcb.hip", "vbqmc_dmcw.hip", "vbqmc_adjoint.hip", "vbqmc_lm.hip", "vbqmc_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

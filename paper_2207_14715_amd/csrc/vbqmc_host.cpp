@@ -52,6 +52,8 @@ hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const d
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
 hipError_t launch_reduce(int64_t W, int K, const double* wts, const double* in, double* out, hipStream_t s);
+hipError_t launch_lm_accumulate(int P, int64_t W, const double* O, const double* D, const double* E,
+                                const double* w, double* acc, hipStream_t s);
 hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi, double* deloc,
                              double* ws, size_t ws_doubles, hipStream_t s);
 size_t param_grad_ws_doubles(const DevWF& wf, int64_t W);
@@ -1593,6 +1595,160 @@ int vbqmc_reduce_walkers(vbqmc_ctx* x, int64_t W, int32_t K, const double* weigh
   if (K == 0) return VBQMC_OK;
   hipError_t e = launch_reduce(W, K, weights, in, out, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "reduce");
+}
+
+// ---------------------------------------------------------------------------
+// linear optimisation method: sample sums on the device, estimators and the
+// step on the host
+// ---------------------------------------------------------------------------
+int vbqmc_lm_acc_doubles(int32_t P, int64_t* n) {
+  if (P < 1 || !n) return VBQMC_EINVAL;
+  *n = 3 * (int64_t)(P + 1) * (P + 1);
+  return VBQMC_OK;
+}
+
+int vbqmc_lm_accumulate(vbqmc_ctx* x, int64_t W, const double* dlogpsi, const double* deloc, const double* eloc,
+                        const double* weight, double* acc, vbqmc_stream stream) {
+  if (!x || W < 0 || !acc || (W > 0 && (!dlogpsi || !deloc || !eloc)))
+    return fail(x, VBQMC_EINVAL, "lm_accumulate: bad arguments");
+  if (W == 0) return VBQMC_OK;
+  const int P = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
+  hipError_t e = launch_lm_accumulate(P, W, dlogpsi, deloc, eloc, weight, acc, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "lm_accumulate");
+}
+
+int vbqmc_lm_estimators(int32_t P, const double* acc, double* e0, double* g_l, double* g_r, double* h_bar,
+                        double* s_bar, double* var) {
+  if (P < 1 || !acc || !e0 || !g_l || !g_r || !h_bar || !s_bar) return VBQMC_EINVAL;
+  const int64_t P1 = P + 1;
+  const double* S1 = acc;
+  const double* H1 = acc + P1 * P1;
+  const double* D1 = acc + 2 * P1 * P1;
+  const double sw = S1[0];
+  if (!(sw > 0)) return VBQMC_EINVAL;
+  std::vector<double> mO(P), mOE(P), mD(P);
+  const double mE = H1[0] / sw;
+  for (int i = 0; i < P; ++i) {
+    mO[i] = S1[i + 1] / sw;
+    mOE[i] = H1[i + 1] / sw;
+    mD[i] = D1[i + 1] / sw;
+  }
+  *e0 = mE;
+  if (var) *var = D1[0] / sw - mE * mE;
+  for (int i = 0; i < P; ++i) {
+    g_l[i] = 2.0 * (mOE[i] - mO[i] * mE);
+    g_r[i] = 2.0 * (mOE[i] - mO[i] * mE + mD[i]);
+  }
+  for (int i = 0; i < P; ++i)
+    for (int j = 0; j < P; ++j) {
+      const double oo = S1[(i + 1) * P1 + j + 1] / sw, ooe = H1[(i + 1) * P1 + j + 1] / sw;
+      const double od = D1[(i + 1) * P1 + j + 1] / sw;
+      h_bar[(int64_t)i * P + j] = ooe - mO[i] * mOE[j] - mO[j] * mOE[i] + mO[i] * mO[j] * mE + od - mO[i] * mD[j];
+      s_bar[(int64_t)i * P + j] = oo - mO[i] * mO[j];
+    }
+  return VBQMC_OK;
+}
+
+// LU with partial pivoting of the n x n row-major A in place (row swaps in
+// piv); false if a pivot is exactly zero
+static bool lu_factor(int n, std::vector<double>& A, std::vector<int>& piv) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int r = k + 1; r < n; ++r) {
+      const double v = std::fabs(A[(size_t)r * n + k]);
+      if (v > best) { best = v; p = r; }
+    }
+    piv[k] = p;
+    if (!(best > 0)) return false;
+    if (p != k)
+      for (int c = 0; c < n; ++c) std::swap(A[(size_t)k * n + c], A[(size_t)p * n + c]);
+    const double inv = 1.0 / A[(size_t)k * n + k];
+    double* rk = &A[(size_t)k * n];
+    for (int r = k + 1; r < n; ++r) {
+      double* rr = &A[(size_t)r * n];
+      const double l = rr[k] * inv;
+      rr[k] = l;
+      if (l != 0.0)
+        for (int c = k + 1; c < n; ++c) rr[c] -= l * rk[c];
+    }
+  }
+  return true;
+}
+
+// solve A x = b (trans = false) or A^T x = b (trans = true) from lu_factor
+static void lu_solve(int n, const std::vector<double>& A, const std::vector<int>& piv, std::vector<double>& b,
+                     bool trans) {
+  if (!trans) {
+    for (int k = 0; k < n; ++k) std::swap(b[k], b[piv[k]]);
+    for (int r = 0; r < n; ++r) {
+      double a = b[r];
+      for (int c = 0; c < r; ++c) a -= A[(size_t)r * n + c] * b[c];
+      b[r] = a;
+    }
+    for (int r = n - 1; r >= 0; --r) {
+      double a = b[r];
+      for (int c = r + 1; c < n; ++c) a -= A[(size_t)r * n + c] * b[c];
+      b[r] = a / A[(size_t)r * n + r];
+    }
+  } else {
+    // A = P^T L U: U^T t = b, L^T v = t, x = P^T v
+    for (int r = 0; r < n; ++r) {
+      double a = b[r];
+      for (int c = 0; c < r; ++c) a -= A[(size_t)c * n + r] * b[c];
+      b[r] = a / A[(size_t)r * n + r];
+    }
+    for (int r = n - 1; r >= 0; --r) {
+      double a = b[r];
+      for (int c = r + 1; c < n; ++c) a -= A[(size_t)c * n + r] * b[c];
+      b[r] = a;
+    }
+    for (int k = n - 1; k >= 0; --k) std::swap(b[k], b[piv[k]]);
+  }
+}
+
+int vbqmc_lm_solve(int32_t n, double e0, const double* g_l, const double* g_r, const double* h_bar,
+                   const double* s_bar, double a_diag, double* dp, double* e_lin) {
+  if (n < 1 || !g_l || !g_r || !h_bar || !s_bar || !dp || !e_lin || !(a_diag >= 0)) return VBQMC_EINVAL;
+  const size_t nn = (size_t)n * n;
+  std::vector<double> A(nn), x(n), y(n);
+  std::vector<int> piv;
+  // x(E) = (Hbar + a I - E Sbar)^-1 g_L; f(E) = E - E0 + g_R.x / 4; f'(E) = 1 + y^T Sbar x / 4 with
+  // y = (Hbar + a I - E Sbar)^-T g_R
+  auto build = [&](double E) {
+    for (size_t k = 0; k < nn; ++k) A[k] = h_bar[k] - E * s_bar[k];
+    for (int i = 0; i < n; ++i) A[(size_t)i * n + i] += a_diag;
+    return lu_factor(n, A, piv);
+  };
+  double E = e0;
+  for (int it = 0; it < 100; ++it) {
+    if (!build(E)) return VBQMC_ESINGULAR;
+    for (int i = 0; i < n; ++i) { x[i] = g_l[i]; y[i] = g_r[i]; }
+    lu_solve(n, A, piv, x, false);
+    lu_solve(n, A, piv, y, true);
+    double gx = 0, ysx = 0;
+    for (int i = 0; i < n; ++i) {
+      gx += g_r[i] * x[i];
+      double a = 0;
+      for (int j = 0; j < n; ++j) a += s_bar[(size_t)i * n + j] * x[j];
+      ysx += y[i] * a;
+    }
+    const double f = E - e0 + 0.25 * gx, fp = 1.0 + 0.25 * ysx;
+    if (!std::isfinite(f) || !std::isfinite(fp) || fp == 0.0) return VBQMC_ENONFINITE;
+    const double En = E - f / fp;
+    const bool done = std::fabs(En - E) <= 1e-13 * std::max(1.0, std::fabs(E));
+    E = En;
+    if (done) {
+      if (!build(E)) return VBQMC_ESINGULAR;
+      for (int i = 0; i < n; ++i) x[i] = g_l[i];
+      lu_solve(n, A, piv, x, false);
+      for (int i = 0; i < n; ++i) dp[i] = -0.5 * x[i];
+      *e_lin = E;
+      return VBQMC_OK;
+    }
+  }
+  return VBQMC_ENONFINITE;
 }
 
 // ---------------------------------------------------------------------------

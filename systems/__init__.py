@@ -35,6 +35,7 @@ from .generate import (  # noqa: F401
     dmc_molecule,
     hydrogen_sto_1s,
     hydrogen_sto_2p,
+    hydrogen_sto_mix,
     hydrogen_gaussian,
     helium_gaussian,
     helium_sto,

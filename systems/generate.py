@@ -284,6 +284,18 @@ def hydrogen_sto_1s(zeta=1.0):
                        [[1.0]], [{"c": 1.0, "terms": [{"inactive": [], "pairs": [], "unpaired": [0]}]}])
 
 
+def hydrogen_sto_mix(zetas=(1.0, 2.0, 3.0), coefs=(0.7, 0.2, 0.1)):
+    """Hydrogen atom, one spin-up electron in sum_k coefs[k] exp(-zetas[k] r)
+    (one Slater s shell per exponent, a single orbital, no Jastrow); the
+    zeta = 1 function alone is the exact ground state."""
+    shells = [{"center": 0, "kind": "sto", "l": 0, "exps": [float(z)], "coefs": [1.0]} for z in zetas]
+    return {"name": "hydrogen_sto_mix", "seed": 0,
+            "nuclei": {"Z": [1.0], "pos": [[0.0, 0.0, 0.0]]},
+            "n_up": 1, "n_dn": 0, "shells": shells, "lam": [[float(c) for c in coefs]],
+            "structures": [{"c": 1.0, "terms": [{"inactive": [], "pairs": [], "unpaired": [0]}]}],
+            "jastrow": _zero_jastrow(1)}
+
+
 def hydrogen_sto_2p(zeta=0.5):
     """Hydrogen atom, one electron in z exp(-zeta r)."""
     return _one_centre(1, 1, 0, {"center": 0, "kind": "sto", "l": 1, "exps": [zeta], "coefs": [1.0]},
