@@ -398,10 +398,22 @@ def adjoint_form(args):
     npar = ctx.n_params
     fd = W / (te * (2 * npar + 1))
     gfl = adjoint_flops_per_gradient(ctx, system) * W / t / 1e12
+    # linear-method sample sums of the same gradients (FP64 MFMA over the
+    # walkers: three (P+1) x W x (P+1) products, 6 (P+1)^2 W FLOP)
+    dl, de = ctx.param_grad(R)
+    el = ctx.evaluate(R, want=("eloc",))["eloc"]
+    acc = ctx.new_lm_acc()
+    ctx.lm_accumulate(dl, de, el, acc)
+    _, tl = _timed(lambda: [ctx.lm_accumulate(dl, de, el, acc) for _ in range(reps)])
+    tl /= reps
+    lm_tf = 6.0 * (npar + 1) ** 2 * W / tl / 1e12
     print(json.dumps({"metric": "walker-gradients/s (d lnPsi/dp and d E_L/dp)", "value": W / t,
                       "unit": "gradients/s", "n_gpus": 1, "walkers": W, "n_params": npar,
                       "ms_per_call": t * 1e3, "fp64_central_difference_gradients_per_s": fd,
                       "speedup_vs_fd": (W / t) / fd, "evaluate_ms": te * 1e3,
+                      "lm_accumulate": {"ms_per_call": tl * 1e3, "achieved": lm_tf, "unit": "TFLOP/s",
+                                        "peak": FP64_VECTOR_PEAK_TFLOPS, "frac": lm_tf / FP64_VECTOR_PEAK_TFLOPS,
+                                        "bound": "mfma"},
                       "roofline": {"bound": "alu", "achieved": gfl, "peak": FP64_VECTOR_PEAK_TFLOPS,
                                    "unit": "TFLOP/s", "frac": gfl / FP64_VECTOR_PEAK_TFLOPS,
                                    "flops_per_gradient": adjoint_flops_per_gradient(ctx, system)},
