@@ -502,6 +502,149 @@ __device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int*
 }
 
 // ---------------------------------------------------------------------------
+// inverse refresh on MFMA
+// ---------------------------------------------------------------------------
+// largest residual entry for which a refresh takes the Newton-Schulz step
+// (the error after the step is of the order of its square plus rounding)
+constexpr double kDwNsTol = 1e-8;
+
+__device__ __forceinline__ double dw_wmax(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Refresh of a spin's reference inverse from the cached value rows: with A
+// (electron x reference slot, rows at vrow with stride WD, n <= 32) and the
+// current inverse B (column k in register array C of lane k < n),
+// R = I - A B and B' = B + B R (one Newton-Schulz step, which squares the
+// error of B); then T = B' PP with PP the table orbitals' cached values.  All
+// three products are 32 x 32 (x nP) FP64 MFMA tiles.  The accumulator layout
+// of the 16x16x4 FP64 MFMA (register r of lane l: row 4 r + l / 16, column
+// l % 16) is the B-operand layout of k-step 4 mt + r (k = l / 16,
+// n = l % 16), so R feeds the second product from registers.  B goes
+// through the wavefront's LDS area Wm (n x n, then T as n x nP).  Returns
+// false (and changes nothing but Wm) when max |R| > kDwNsTol, when it is not
+// finite or when nP > 32: the caller then takes a Gauss-Jordan refresh.  On
+// success lane k < n holds column k of B' in C, lane n + q column q of T,
+// and Wm holds T row-major (stride nP).
+template <int NC>
+__device__ bool dw_refresh_ns(double* Wm, const double* vrow, int WD, int n, int nP, int lane, double (&C)[NC]) {
+  if (nP > 32) return false;
+  const int m = lane & 15, kq = lane >> 4;
+  const bool bl = lane < n, tl = lane >= n && lane < n + nP;
+  if (bl)
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < n) Wm[j * n + lane] = C[j];
+  wave_sync();
+  // operands with every index clamped into the matrices, zero outside
+  auto aop = [&](int i, int k) -> double {
+    const bool in = i < n && k < n;
+    const double v = vrow[(size_t)(in ? i : 0) * WD + (in ? k : 0)];
+    return in ? v : 0.0;
+  };
+  auto bop = [&](int j, int k) -> double {
+    const bool in = j < n && k < n;
+    const double v = Wm[(in ? j : 0) * n + (in ? k : 0)];
+    return in ? v : 0.0;
+  };
+  auto pop = [&](int k, int q) -> double {
+    const bool in = k < n && q < nP;
+    const double v = vrow[(size_t)(in ? k : 0) * WD + (in ? n + q : 0)];
+    return in ? v : 0.0;
+  };
+  v4d P[2][2], D[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[a][b][r] = D[a][b][r] = 0.0;
+  // P = A B
+#pragma unroll
+  for (int kt = 0; kt < 8; ++kt) {
+    const int k = 4 * kt + kq;
+    const double a0 = aop(m, k), a1 = aop(16 + m, k), b0 = bop(k, m), b1 = bop(k, 16 + m);
+    P[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, P[0][0], 0, 0, 0);
+    P[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, P[0][1], 0, 0, 0);
+    P[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, P[1][0], 0, 0, 0);
+    P[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, P[1][1], 0, 0, 0);
+  }
+  // R = I - P (the padding block past n is the identity, which adds nothing below)
+  double rmax = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * a + 4 * r + kq, col = 16 * b + m;
+        P[a][b][r] = (row == col ? 1.0 : 0.0) - P[a][b][r];
+        if (row < n && col < n) rmax = fmax(rmax, fabs(P[a][b][r]));
+      }
+  rmax = dw_wmax(rmax);
+  if (!(rmax <= kDwNsTol)) return false;
+  // D = B R, then B' = B + D in place
+#pragma unroll
+  for (int kt = 0; kt < 8; ++kt) {
+    const int k = 4 * kt + kq;
+    const double a0 = bop(m, k), a1 = bop(16 + m, k);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      D[0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, P[kt >> 2][b][kt & 3], D[0][b], 0, 0, 0);
+      D[1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, P[kt >> 2][b][kt & 3], D[1][b], 0, 0, 0);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * a + 4 * r + kq, col = 16 * b + m;
+        if (row < n && col < n) Wm[row * n + col] += D[a][b][r];
+      }
+  wave_sync();
+  // T = B' PP (reuses D)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) D[a][b][r] = 0.0;
+#pragma unroll
+  for (int kt = 0; kt < 8; ++kt) {
+    const int k = 4 * kt + kq;
+    const double a0 = bop(m, k), a1 = bop(16 + m, k), p0 = pop(k, m), p1 = pop(k, 16 + m);
+    D[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, p0, D[0][0], 0, 0, 0);
+    D[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p0, D[1][0], 0, 0, 0);
+    D[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, p1, D[0][1], 0, 0, 0);
+    D[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p1, D[1][1], 0, 0, 0);
+  }
+  // columns of B' to the reference lanes, then T over Wm for the table lanes and the minors
+  if (bl)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) C[j] = j < n ? Wm[min(j, n - 1) * n + lane] : 0.0;
+  wave_sync();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * a + 4 * r + kq, col = 16 * b + m;
+        if (row < n && col < nP) Wm[row * nP + col] = D[a][b][r];
+      }
+  wave_sync();
+  if (tl)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) C[j] = j < n ? Wm[min(j, n - 1) * nP + (lane - n)] : 0.0;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // the step kernel
 // ---------------------------------------------------------------------------
 // prep = 1: rebuild each record from its positions (orbital-row caches of
@@ -851,44 +994,53 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     const bool due = !bad && nuS >= (double)wf.refresh_every;
     if (due) {
       double* A = lds_dyn + wf.dw_A + g * wf.dw_Astride;
-      int* piv = (int*)(wa + wf.dwo_piv);
-      double* fz = wa + wf.dwo_f;
-      for (int k = lane; k < n * n; k += 64) {
-        const int ii = k / n, j = k - ii * n;
-        A[k] = vc[(size_t)(e0 + ii) * WD + j];
+      // a Newton-Schulz step from the current inverse when it is close
+      // (not when the records are being rebuilt); else Gauss-Jordan
+      const bool ns = !prep && dw_refresh_ns<NC>(A, vc + (size_t)e0 * WD, WD, n, nP, lane, C);
+      bool ok = true;
+      double ld = ldS, sg = sgS;
+      if (!ns) {
+        int* piv = (int*)(wa + wf.dwo_piv);
+        double* fz = wa + wf.dwo_f;
+        for (int k = lane; k < n * n; k += 64) {
+          const int ii = k / n, j = k - ii * n;
+          A[k] = vc[(size_t)(e0 + ii) * WD + j];
+        }
+        // the row dot products below read up to NC entries from the last row
+        // start: the 64 doubles past the matrix are part of this area, zeroed
+        A[n * n + lane] = 0.0;
+        wave_sync();
+        ok = gj_invert_h<64>(A, n, lane, piv, fz, ld, sg);
+        if (ok) {
+          // B to the reference lanes; T = B PP on the table lanes (lane n + q
+          // takes column q of PP from its cached values, one row at a time);
+          // row indices clamped into the matrix, rows past n masked to zero
+          const double bm = blane ? 1.0 : 0.0, tm = tlane ? 1.0 : 0.0;
+          const int kl = blane ? lane : 0;
+          double pp[NC];  // column q of PP on table lane n + q (zero elsewhere)
+#pragma unroll
+          for (int ii = 0; ii < NC; ++ii)
+            pp[ii] = vc[(size_t)(e0 + min(ii, n - 1)) * WD + (tlane ? lane : 0)] * (ii < n ? tm : 0.0);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const double* Aj = A + min(j, n - 1) * n;
+            double v = Aj[kl] * bm;
+            if (tlane) v = dw_dot<NC>(Aj, pp);
+            C[j] = j < n ? v : 0.0;
+          }
+          wave_sync();
+          // the new table, for the minors (rows past n are not written)
+          if (tlane)
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+              if (j < n) A[j * nP + (lane - n)] = C[j];
+          wave_sync();
+        }
       }
-      // the row dot products below read up to NC entries from the last row
-      // start: the 64 doubles past the matrix are part of this area, zeroed
-      A[n * n + lane] = 0.0;
-      wave_sync();
-      double ld = 0.0, sg = 1.0;
-      const bool ok = gj_invert_h<64>(A, n, lane, piv, fz, ld, sg);
       if (!ok) {
         bad = true;
       } else {
-        // B to the reference lanes; T = B PP on the table lanes (lane n + q
-        // takes column q of PP from its cached values, one row at a time);
-        // row indices clamped into the matrix, rows past n masked to zero
-        const double bm = blane ? 1.0 : 0.0, tm = tlane ? 1.0 : 0.0;
-        const int kl = blane ? lane : 0;
-        double pp[NC];  // column q of PP on table lane n + q (zero elsewhere)
-#pragma unroll
-        for (int ii = 0; ii < NC; ++ii)
-          pp[ii] = vc[(size_t)(e0 + min(ii, n - 1)) * WD + (tlane ? lane : 0)] * (ii < n ? tm : 0.0);
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const double* Aj = A + min(j, n - 1) * n;
-          double v = Aj[kl] * bm;
-          if (tlane) v = dw_dot<NC>(Aj, pp);
-          C[j] = j < n ? v : 0.0;
-        }
-        wave_sync();
-        // the new table, for the minors (rows past n are not written)
-        if (tlane)
-#pragma unroll
-          for (int j = 0; j < NC; ++j)
-            if (j < n) A[j * nP + (lane - n)] = C[j];
-        wave_sync();
+        // minors of the new table (row-major in A), R_u and S
         double vs[1] = {0.0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -905,6 +1057,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         }
         dw_wsum<1>(vs);
         S = vs[0];
+        // (a Newton-Schulz step keeps the running ln|det| and sign of the moves)
         ldS = ld;
         sgS = sg;
         nuS = 0.0;
@@ -951,6 +1104,42 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   if (!(S != 0.0)) bad = true;
 
   // ---- local energy (Eq. Elav with Psi = e^U D) ----
+  // Jastrow gradient and Laplacian and the potential of electron i = lane
+  // (i < N), each lane summing over all its partners (the same partner in
+  // every lane at a time, so nothing is reduced across lanes here)
+  double jg[3] = {0.0, 0.0, 0.0}, jl = 0.0, jv = 0.0;
+  if (!bad) {
+    const bool el = lane < N;
+    const int si = spin_of(wf, el ? lane : 0);
+    const double xi = Rl[3 * (el ? lane : 0)], yi = Rl[3 * (el ? lane : 0) + 1], zi = Rl[3 * (el ? lane : 0) + 2];
+#pragma unroll 2
+    for (int j = 0; j < N + nn; ++j) {
+      double xj, yj, zj, wv;
+      PairCoef cf;
+      if (j < N) {
+        xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
+        cf = si != spin_of(wf, j) ? c_anti : c_par;
+        wv = 0.5;
+      } else {
+        const double* nu = l.nuc() + 4 * (j - N);
+        xj = nu[0]; yj = nu[1]; zj = nu[2];
+        cf = en_coef(l.en() + 6 * (j - N));
+        wv = -nu[3];
+      }
+      const bool on = el && j != lane;
+      const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+      const double r = sqrt(on ? dx * dx + dy * dy + dz * dz : 1.0), irr = 1.0 / r;
+      double u, u1, u2;
+      pair_fn(r, kappa, cf, u, u1, u2);
+      const double m = on ? 1.0 : 0.0;
+      const double f = m * (u1 * irr);
+      jg[0] += f * dx;
+      jg[1] += f * dy;
+      jg[2] += f * dz;
+      jl += m * (u2 + 2.0 * (u1 * irr));
+      jv += m * (wv * irr);
+    }
+  }
   // spin 1's columns are in registers after the moves: its electrons first
   double tsum = 0.0, vsum = 0.0;
 #pragma unroll 1
@@ -1004,48 +1193,26 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
             if (tlane) yr[c * 64 + (lane - n)] = rw[c] - t[c];
           }
           wave_sync();
-          double part[9];
+          double part[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) part[c] = dw_detsum(d, rp[c], yr + c * 64, bc);
-#pragma unroll
-          for (int c = 4; c < 9; ++c) part[c] = 0.0;
-          const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
-          for (int j = lane; j < N + nn; j += 64) {
-            if (j == i) continue;
-            double xj, yj, zj, wv;
-            PairCoef cf;
-            if (j < N) {
-              xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
-              cf = s2 != spin_of(wf, j) ? c_anti : c_par;
-              wv = 0.5;
-            } else {
-              const double* nu = l.nuc() + 4 * (j - N);
-              xj = nu[0]; yj = nu[1]; zj = nu[2];
-              cf = en_coef(l.en() + 6 * (j - N));
-              wv = -nu[3];
-            }
-            const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-            const double r = sqrt(dx * dx + dy * dy + dz * dz), irr = 1.0 / r;
-            double u, u1, u2;
-            pair_fn(r, kappa, cf, u, u1, u2);
-            const double f = u1 * irr;
-            part[4] += f * dx;
-            part[5] += f * dy;
-            part[6] += f * dz;
-            part[7] += u2 + 2.0 * f;
-            part[8] += wv * irr;
-          }
-          dw_wsum<9>(part);
+          dw_wsum<4>(part);
           const double iS = 1.0 / S;
-          const double gx = part[4], gy = part[5], gz = part[6];
-          tsum += part[7] + part[3] * iS + gx * gx + gy * gy + gz * gz +
-                  2.0 * (gx * part[0] + gy * part[1] + gz * part[2]) * iS;
-          vsum += part[8];
+          const double gx = dw_readlane(jg[0], i), gy = dw_readlane(jg[1], i), gz = dw_readlane(jg[2], i);
+          tsum += part[3] * iS + 2.0 * (gx * part[0] + gy * part[1] + gz * part[2]) * iS;
           wave_sync();
         }
       }
       __syncthreads();
     }
+  }
+  {
+    // the Jastrow-only terms of every electron: sum of Lap U + |grad U|^2, and the potential
+    const bool el = lane < N;
+    double q[2] = {el ? jl + jg[0] * jg[0] + jg[1] * jg[1] + jg[2] * jg[2] : 0.0, el ? jv : 0.0};
+    dw_wsum<2>(q);
+    tsum += q[0];
+    vsum += q[1];
   }
   // ---- E_L, weight, record scalars ----
   if (live && lane == 0) {
