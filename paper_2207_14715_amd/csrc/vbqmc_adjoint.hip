@@ -73,6 +73,252 @@ __device__ __forceinline__ int slot_orbital(const Ld& l, int s, const int* ui, i
   return l.ref(s)[j];
 }
 
+// ---------------------------------------------------------------------------
+// Both passes through each spin's reference determinant.  A spin
+// determinant u differs from the reference A_0 (electron x slot) in the e <= 3
+// slots J_u, which hold the table orbitals Q_u; with B = A_0^-1 and
+// T = B Phi_P (Phi_P: the table orbitals' values),
+//   A_u^-1 = B - (T[:, Q] - E_J) V_u,   V_u = m_u^-1 B[J, :],  m_u = T[J, Q],
+// det A_u = det A_0 det m_u, and with the kinetic rows K (K_0 and K_P as A_0
+// and Phi_P), S = K_0 B and Xi = K_P - K_0 T:
+//   K_u A_u^-1 = S + Xi[:, Q] V_u,   e_u = tr(A_u^-1 K_u) = tr S + tr(V_u Xi[:, Q]).
+// The scatters of the second pass then collapse onto sums per table orbital q:
+//   W_q = sum omega_u V_u[d, :], Wbar_q = sum lbar_u V_u[d, :],
+//   X_q = sum omega_u (V_u K_u A_u^-1)[d, :]   (over u, d with Q_ud = q)
+// (the terms a scatter would skip, the slots J_u of a reference row, vanish
+// identically, since m_u V_u = B[J, :]), so the work per determinant is on
+// e x e and e x n blocks and one inversion per spin replaces one per
+// determinant.
+// ---------------------------------------------------------------------------
+
+// the kinetic-row entry -(grad U . grad phi_o) - Lap phi_o / 2 at electron e
+__device__ __forceinline__ double adj_kin(const DevWF& wf, const Ld& l, const double* aPhi, int e, int o) {
+  const int N = wf.N, nop = wf.nop;
+  const double* gu = l.gU() + 3 * e;
+  return -(gu[0] * aPhi[(1 * N + e) * nop + o] + gu[1] * aPhi[(2 * N + e) * nop + o] +
+           gu[2] * aPhi[(3 * N + e) * nop + o]) - 0.5 * aPhi[(4 * N + e) * nop + o];
+}
+
+// spin s's reference quantities: B (in A, [slot][electron]), K_0, S = K_0 B,
+// T, Xi, B S, B Xi; false if the reference is singular (block-uniform)
+template <int NT>
+__device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, int s, double* B, double* K0,
+                             double* S, double& ld0, double& sg0, double& trS) {
+  const SpinTab& st = wf.sp[s];
+  const int n = st.n, nP = st.nP, e0 = st.e0, N = wf.N, nop = wf.nop;
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  double* BS = l.L + wf.l_aBS;
+  double* T = l.L + wf.l_aT;
+  double* Xi = l.L + wf.l_aXi;
+  double* BXi = l.L + wf.l_aBXi;
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int i = idx / n, j = idx - i * n;
+    B[idx] = aPhi[(0 * N + e0 + i) * nop + ref[j]];
+    K0[idx] = adj_kin(wf, l, aPhi, e0 + i, ref[j]);
+  }
+  __syncthreads();
+  if (!gj_invert<NT>(l, B, n, ld0, sg0)) return false;
+  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+    const int j = idx / nP, q = idx - j * nP;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += B[j * n + i] * aPhi[(0 * N + e0 + i) * nop + porb[q]];
+    T[idx] = t;
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int i = idx / n, a = idx - i * n;
+    double t = 0.0;
+    for (int j = 0; j < n; ++j) t += K0[i * n + j] * B[j * n + a];
+    S[idx] = t;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+    const int i = idx / nP, q = idx - i * nP;
+    double t = adj_kin(wf, l, aPhi, e0 + i, porb[q]);
+    for (int k = 0; k < n; ++k) t -= K0[i * n + k] * T[k * nP + q];
+    Xi[idx] = t;
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+    const int b = idx / n, a = idx - b * n;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += B[b * n + i] * S[i * n + a];
+    BS[idx] = t;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+    const int b = idx / nP, q = idx - b * nP;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += B[b * n + i] * Xi[i * nP + q];
+    BXi[idx] = t;
+  }
+  trS = 0.0;
+  for (int i = 0; i < n; ++i) trS += S[i * n + i];
+  __syncthreads();
+  return true;
+}
+
+// first pass: ln|Delta_u|, sign and e_u of every distinct spin determinant,
+// and per determinant m_u^-1 and V_u Xi[:, Q] ([nU][18]); false if a
+// reference is singular
+template <int NT>
+__device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, double* B, double* K0, double* S) {
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    const int nP = st.nP;
+    double* uinf = l.L + wf.l_aU[s];
+    double* V = l.L + wf.l_aV[s];
+    double ld0 = 0.0, sg0 = 1.0, trS = 0.0;
+    if (st.n > 0 && !adj_ref_spin<NT>(wf, l, aPhi, s, B, K0, S, ld0, sg0, trS)) return false;
+    const double* T = l.L + wf.l_aT;
+    const double* BXi = l.L + wf.l_aBXi;
+    for (int u = threadIdx.x; u < st.nU; u += NT) {
+      const int* ui = l.ui(s) + 8 * u;
+      const int e = st.n > 0 ? ui[0] : 0;
+      double m[9], mi[9], vx[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int r = k / 3, c = k - 3 * r;
+        m[k] = (r < e && c < e) ? T[ui[1 + r] * nP + ui[4 + c]] : (r == c ? 1.0 : 0.0);
+      }
+      // det and inverse of the leading e x e block (identity past e)
+      const double c00 = m[4] * m[8] - m[5] * m[7], c01 = m[5] * m[6] - m[3] * m[8], c02 = m[3] * m[7] - m[4] * m[6];
+      const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+      const double id = det != 0.0 ? 1.0 / det : 0.0;
+      mi[0] = c00 * id;
+      mi[1] = (m[2] * m[7] - m[1] * m[8]) * id;
+      mi[2] = (m[1] * m[5] - m[2] * m[4]) * id;
+      mi[3] = c01 * id;
+      mi[4] = (m[0] * m[8] - m[2] * m[6]) * id;
+      mi[5] = (m[2] * m[3] - m[0] * m[5]) * id;
+      mi[6] = c02 * id;
+      mi[7] = (m[1] * m[6] - m[0] * m[7]) * id;
+      mi[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+      double tr = trS;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int d = k / 3, c = k - 3 * d;
+        double t = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2)
+          if (c2 < e && c < e) t += mi[3 * d + c2] * BXi[ui[1 + c2] * nP + ui[4 + c]];
+        vx[k] = (d < e && c < e) ? t : 0.0;
+        if (d == c && d < e) tr += t;
+      }
+      const bool ok = det != 0.0;
+      uinf[5 * u + 0] = ok ? ld0 + log(fabs(det)) : -INFINITY;
+      uinf[5 * u + 1] = ok ? (det < 0.0 ? -sg0 : sg0) : 0.0;
+      uinf[5 * u + 2] = ok ? tr : 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        V[18 * u + k] = mi[k];
+        V[18 * u + 9 + k] = vx[k];
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// second pass: the references again (recomputed, not stored), the sums
+// W, Wbar, X per table orbital, their scatter onto the orbital rows G0
+// (d E_L / d phi) and G (d ln|D| / d phi) of each spin's electrons, and the
+// drift and Laplacian ratios of D from G
+template <int NT>
+__device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, double* B, double* K0, double* S,
+                              double* G0, double* G) {
+  const int N = wf.N, nop = wf.nop;
+  for (int s = 0; s < 2; ++s) {
+    const SpinTab& st = wf.sp[s];
+    const int n = st.n, nP = st.nP, e0 = st.e0;
+    if (n == 0) continue;
+    double ld0, sg0, trS;
+    adj_ref_spin<NT>(wf, l, aPhi, s, B, K0, S, ld0, sg0, trS);
+    const double* uinf = l.L + wf.l_aU[s];
+    const double* V = l.L + wf.l_aV[s];
+    const double* BS = l.L + wf.l_aBS;
+    const double* T = l.L + wf.l_aT;
+    const double* BXi = l.L + wf.l_aBXi;
+    double* Wq = l.L + wf.l_aW;
+    double* Wb = Wq + nP * n;
+    double* Xq = Wq + 2 * nP * n;
+    const int* ref = l.ref(s);
+    const int* porb = l.porb(s);
+    for (int idx = threadIdx.x; idx < nP * n; idx += NT) {
+      const int q = idx / n, a = idx - q * n;
+      double w = 0.0, wb = 0.0, x = 0.0;
+      for (int u = 0; u < st.nU; ++u) {
+        if (uinf[5 * u + 1] == 0.0) continue;  // singular: no contribution
+        const int* ui = l.ui(s) + 8 * u;
+        const int e = ui[0];
+        bool has = false;
+        for (int d = 0; d < e; ++d) has = has || ui[4 + d] == q;
+        if (!has) continue;
+        const double om = uinf[5 * u + 3], lb = uinf[5 * u + 4];
+        const double* mi = V + 18 * u;
+        const double* vx = mi + 9;
+        double va[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < e; ++c)
+          for (int c2 = 0; c2 < e; ++c2) va[c] += mi[3 * c + c2] * B[ui[1 + c2] * n + a];
+        for (int d = 0; d < e; ++d) {
+          if (ui[4 + d] != q) continue;
+          double U = 0.0;
+          for (int c = 0; c < e; ++c) U += mi[3 * d + c] * BS[ui[1 + c] * n + a] + vx[3 * d + c] * va[c];
+          w += om * va[d];
+          wb += lb * va[d];
+          x += om * U;
+        }
+      }
+      Wq[idx] = w;
+      Wb[idx] = wb;
+      Xq[idx] = x;
+    }
+    double Om = 0.0, Lb = 0.0;
+    for (int u = 0; u < st.nU; ++u)
+      if (uinf[5 * u + 1] != 0.0) {
+        Om += uinf[5 * u + 3];
+        Lb += uinf[5 * u + 4];
+      }
+    __syncthreads();
+    const int nc = n + nP;
+    for (int idx = threadIdx.x; idx < n * nc; idx += NT) {
+      const int a = idx / nc, col = idx - a * nc, e = e0 + a;
+      double g, g0;
+      int o;
+      if (col < n) {
+        const int b = col;
+        o = ref[b];
+        double sT = 0.0, sTb = 0.0, sTX = 0.0, sBX = 0.0;
+        for (int q = 0; q < nP; ++q) {
+          const double t = T[b * nP + q];
+          sT += t * Wq[q * n + a];
+          sTb += t * Wb[q * n + a];
+          sTX += t * Xq[q * n + a];
+          sBX += BXi[b * nP + q] * Wq[q * n + a];
+        }
+        g = Om * B[b * n + a] - sT;
+        g0 = Lb * B[b * n + a] - sTb - Om * BS[b * n + a] - sBX + sTX;
+      } else {
+        const int q = col - n;
+        o = porb[q];
+        g = Wq[q * n + a];
+        g0 = Wb[q * n + a] - Xq[q * n + a];
+      }
+      G[e * nop + o] += g;
+      G0[e * nop + o] += g0;
+    }
+    __syncthreads();
+  }
+  // drift and Laplacian ratios of D: sum over orbitals of the channel rows times G
+  for (int idx = threadIdx.x; idx < 4 * N; idx += NT) {
+    const int e = idx >> 2, c = 1 + (idx & 3);
+    double t = 0.0;
+    for (int o = 0; o < nop; ++o) t += aPhi[(c * N + e) * nop + o] * G[e * nop + o];
+    if (c < 4) l.gD()[3 * e + c - 1] = t;
+    else l.lD()[e] = t;
+  }
+  __syncthreads();
+}
+
 template <int NT, int PREC>
 __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf, int64_t W,
                                                    const double* __restrict__ Rin, double* dlog, double* del) {
@@ -112,8 +358,11 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   // B. Jastrow factor, its gradients and Laplacians, potential
   jastrow_full<NT>(wf, l, l.R());
 
-  // C. first pass over the spin determinants: ln|Delta_u|, sign, e_u
-  for (int s = 0; s < 2; ++s) {
+  // C. first pass over the spin determinants: ln|Delta_u|, sign, e_u,
+  // through each spin's reference (one inversion per spin); if a reference
+  // is singular, one inversion per determinant instead
+  const bool lowrank = adj_ref_pass1<NT>(wf, l, aPhi, A, K, M1);
+  for (int s = 0; s < 2 && !lowrank; ++s) {
     const SpinTab& st = wf.sp[s];
     const int n = st.n;
     double* uinf = l.L + wf.l_aU[s];  // [nU][5]: L, sign, e, omega, lbar
@@ -194,9 +443,10 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   }
   __syncthreads();
 
-  // E. second pass: recompute each inverse, accumulate the drift and
+  // E. second pass: recompute the inverses, accumulate the drift and
   // Laplacian ratios and scatter the adjoint onto orbital rows
-  for (int s = 0; s < 2; ++s) {
+  if (lowrank) adj_ref_pass2<NT>(wf, l, aPhi, A, K, M1, G0, G);
+  for (int s = 0; s < 2 && !lowrank; ++s) {
     const SpinTab& st = wf.sp[s];
     const int n = st.n;
     const double* uinf = l.L + wf.l_aU[s];

@@ -467,23 +467,32 @@ __device__ __forceinline__ void dw_mfma(const DevWF& wf, const Ld& l, const int*
   for (int ct = 0; ct < kDwLC; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[ct][r] = 0.0;
+  // software pipeline: at step t the table entries of step t + 2 are
+  // requested, the products of step t issued and the element of step t + 1
+  // formed; the scheduling barriers keep the compiler from moving the loads
+  // back next to their use
   int2 wn = word(0);
-  Src q = fetch(0, wn);
-  if (LK > 1) wn = word(1);
-  double a = elem(q);
-  if (LK > 1) q = fetch(1, wn);
+  Src q1 = fetch(0, wn);
+  double a = elem(q1);
+  if (LK > 1) q1 = fetch(1, word(1));
   if (LK > 2) wn = word(2);
 #pragma unroll
   for (int t = 0; t < LK; ++t) {
+    // (the word load first: the next step waits for it without waiting for
+    // the table loads behind it, the LDS counter being in order)
+    int2 w3 = wn;
+    if (t + 3 < LK) w3 = word(t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    Src q2 = q1;
+    if (t + 2 < LK) q2 = fetch(t + 2, wn);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ct = 0; ct < kDwLC; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, L.b[t][ct], acc[ct], 0, 0, 0);
-    if (t + 1 < LK) {
-      a = elem(q);
-      if (t + 2 < LK) {
-        q = fetch(t + 2, wn);
-        if (t + 3 < LK) wn = word(t + 3);
-      }
-    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < LK) a = elem(q1);
+    __builtin_amdgcn_sched_barrier(0);
+    q1 = q2;
+    wn = w3;
   }
   double* pw = part + wave * (kDwLC * 4 * 64);
 #pragma unroll

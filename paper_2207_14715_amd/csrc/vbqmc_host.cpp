@@ -1067,6 +1067,13 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   wf.l_aM = lds(nmax * nmax);
   wf.l_aU[0] = lds(5 * (int)x->sp[0].sets.size());
   wf.l_aU[1] = lds(5 * (int)x->sp[1].sets.size());
+  wf.l_aBS = lds(nmax * nmax);
+  wf.l_aT = lds(nmax * nPm);
+  wf.l_aXi = lds(nmax * nPm);
+  wf.l_aBXi = lds(nmax * nPm);
+  wf.l_aW = lds(3 * nPm * nmax);
+  wf.l_aV[0] = lds(18 * (int)x->sp[0].sets.size());
+  wf.l_aV[1] = lds(18 * (int)x->sp[1].sets.size());
   wf.lds_adj_doubles = o;
   o = full_end;
   wf.lds_doubles = o;

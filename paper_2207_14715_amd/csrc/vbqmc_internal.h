@@ -87,6 +87,10 @@ struct DevWF {
   int l_Rp, l_ua, l_Vn;  // sweep kernel: trial positions, acceptance draws, trial orbital rows
   // adjoint kernel
   int l_aPhi, l_aG0, l_aG, l_aA, l_aP, l_aM, l_aU[2];
+  // adjoint through each spin's reference: B S [n][n], T, Xi = K_P - K_0 T,
+  // B Xi [n][nP], the sums W, Wbar, X [3][nP][n], and per distinct spin
+  // determinant the inverse of its minor and V Xi_Q ([nU][18])
+  int l_aBS, l_aT, l_aXi, l_aBXi, l_aW, l_aV[2];
   int lds_doubles, lds_sweep_doubles, lds_finish_doubles, lds_tile_doubles, lds_adj_doubles;
   // wavefront sweep (several walkers per wavefront): walker g's state starts
   // at gw_base + g * gw_stride, and the state offsets of that layout are
