@@ -85,18 +85,25 @@ def vmc_flops_per_walker_move(ctx, system, accept_rate):
 
 
 def adjoint_flops_per_gradient(ctx, system):
-    """Algorithmic FLOPs of one walker's full gradient: 5-channel basis values
-    (per primitive 6 flops + one exp, per function 16) and contraction for all
-    electrons, per spin determinant two inversions (2 n^3 each), the kinetic
-    rows (8 n^2), A^-1 K A^-1 (4 n^3) and the scatter (4 n^2), the Jastrow
-    pair derivatives (12 parameters x 12 flops per pair), and the two
+    """Algorithmic FLOPs of one walker's full gradient with the adjoint through
+    each spin's reference determinant: 5-channel basis values (per primitive
+    6 flops + one exp, per function 16) and their contraction for all
+    electrons; per spin, in each of the two passes, the reference inversion
+    (2 n^3), S = K_0 B and B S (2 n^3 each), T, Xi and B Xi (2 n^2 n_P each)
+    and the kinetic rows (8 n (n + n_P)); per distinct determinant the e x e
+    minor, its inverse and V Xi_Q (about 60) and its share of the sums per
+    table orbital (20 n); the scatter onto orbital rows (8 n (n + n_P) n_P)
+    and the drift and Laplacian ratios from it (8 N_orb per electron); the
+    Jastrow pair derivatives (12 parameters x 12 flops per pair); and the two
     orbital-coefficient contractions (3 x 2 N N_orb M)."""
     info = ctx.info
     N, M, norb, nnuc = info["n_electrons"], info["n_basis"], info["n_orbitals"], info["n_nuclei"]
     P = sum(len(s["exps"]) for s in system["shells"])
     total = N * (P * (6 + EXP_FLOPS) + 16 * M) + 2 * 5 * N * M * norb
-    for n, u in ((info["n_up"], info["n_unique_up"]), (info["n_dn"], info["n_unique_dn"])):
-        total += u * (2 * 2 * n ** 3 + 8 * n * n + 4 * n ** 3 + 4 * n * n)
+    for n, nP, u in ((info["n_up"], info["n_table_up"], info["n_unique_up"]),
+                     (info["n_dn"], info["n_table_dn"], info["n_unique_dn"])):
+        total += 2 * (6 * n ** 3 + 6 * n * n * nP + 8 * n * (n + nP))
+        total += u * (60 + 20 * n) + 8 * n * (n + nP) * nP + 8 * norb * n
     total += (N * (N - 1) / 2 + N * nnuc) * 12 * 12
     total += 3 * 2 * N * norb * M
     return total
@@ -428,7 +435,7 @@ DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb
 # dispatch) scaled by the copy-kernel calibration (the factors below), with
 # the SHA-256 prefix of the kernel source they were taken on: the value is
 # reported only while the source is unchanged (else null).
-DMCW_TRAFFIC = {"src_sha": "ec776ce21bcf5d81", "fetch_kib": 3263307.0, "write_kib": 3951291.6, "fetch_factor": 2.000,
+DMCW_TRAFFIC = {"src_sha": "79dd26a5761d9d71", "fetch_kib": 3382906.8, "write_kib": 4277161.2, "fetch_factor": 2.000,
                 "write_factor": 1.000, "walkers": 32768}
 
 
