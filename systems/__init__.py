@@ -30,6 +30,7 @@ Each generator's docstring gives its recipe (seed, distributions, shapes).
 from .generate import (  # noqa: F401
     h2_heitler_london,
     f2_shaped,
+    f2_bovb,
     precision_molecule,
     adjoint_molecule,
     dmc_molecule,

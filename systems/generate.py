@@ -184,6 +184,33 @@ def f2_shaped(seed=1001):
             "structures": structures, "jastrow": _pade_jastrow(2)}
 
 
+def f2_bovb(seed=1001, breathing=0.3):
+    """BOVB form (Eq. PsiJBOVB) of the F2-shaped system: every structure has
+    its own active orbitals, the 8 inactive ones are shared.  Covalent
+    (sA, sB) = orbitals 8, 9 as in f2_shaped; the ionic structures pair sA'
+    (orbital 10) and sB' (orbital 11) with themselves.  The breathing orbitals
+    are sA, sB plus N(0, breathing^2)/sqrt(14) on their own atom's block
+    (breathing = 0 gives back the f2_shaped wave function)."""
+    base = f2_shaped(seed)
+    rng = np.random.default_rng(seed + 500)
+    lam = np.array(base["lam"])
+    blocks = _atom_blocks(base["shells"], 2)
+    extra = []
+    for p, a in ((8, 0), (9, 1)):
+        row = lam[p].copy()
+        row[blocks[a]] += breathing * rng.normal(size=len(blocks[a])) / np.sqrt(len(blocks[a]))
+        extra.append(row)
+    lam = np.vstack([lam, np.array(extra)])
+    st = base["structures"]
+    inact = list(range(8))
+    structures = [
+        st[0],
+        {"c": st[1]["c"], "terms": [{"inactive": inact, "pairs": [[10, 10]], "unpaired": []}]},
+        {"c": st[2]["c"], "terms": [{"inactive": inact, "pairs": [[11, 11]], "unpaired": []}]},
+    ]
+    return {**base, "name": "f2_bovb", "lam": lam.tolist(), "structures": structures}
+
+
 def _molecule(seed, name, n_nuc, zchoices, ztotal, side, shell_spec, n_inactive,
               n_active_per_atom, active_atoms, struct_counts, jastrow_kind,
               delocal_sigma=0.1, active_perturb=0.0, max_exponent=1e4):

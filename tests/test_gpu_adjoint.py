@@ -58,6 +58,11 @@ def test_h2_all_parameters(lib, oracle_mod):
     _compare(lib, oracle_mod, S.h2_heitler_london(), 8)
 
 
+def test_f2_bovb_all_parameters(lib, oracle_mod):
+    # the breathing orbitals' coefficients are parameters of their own
+    _compare(lib, oracle_mod, S.f2_bovb(), 4)
+
+
 def test_adjoint_molecule_sampled_parameters(lib, oracle_mod):
     sysd = S.adjoint_molecule()
     o = oracle_mod.Oracle(sysd)

@@ -60,6 +60,11 @@ def test_f2_shaped(lib, oracle_mod):
     _run(lib, oracle_mod, S.f2_shaped(), 128, 2)
 
 
+def test_f2_bovb(lib, oracle_mod):
+    # per-structure active orbitals (Eq. PsiJBOVB): 12 orbitals, 3 table orbitals per spin
+    _run(lib, oracle_mod, S.f2_bovb(), 96, 7)
+
+
 @pytest.mark.parametrize("name", ["precision", "adjoint", "dmc"])
 def test_workload_systems(lib, oracle_mod, name):
     _run(lib, oracle_mod, S.named_config(name), 8, 3)

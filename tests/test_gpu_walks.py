@@ -107,6 +107,14 @@ def test_vmc_f2_sherman_morrison(lib, oracle_mod, lanes):
     _check_vmc(ref, acc, R, 12, oracle_obj=ref["oracle"])
 
 
+@pytest.mark.parametrize("lanes", ["rows", 32])
+def test_vmc_f2_bovb(lib, oracle_mod, lanes):
+    # per-structure active orbitals (Eq. PsiJBOVB): each ionic structure's own
+    # orbital is a table orbital of both spins; past the 32-update refresh
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.f2_bovb(), 53, 12, 0.3, False, lanes=lanes)
+    _check_vmc(ref, acc, R, 12, oracle_obj=ref["oracle"])
+
+
 def _f2_with_slater_shells():
     """The F2-shaped system with the s and p shells of the second atom made
     Slater shells (exponents 0.6-4, same primitive counts): more than eight
@@ -381,6 +389,12 @@ def test_dmc_f2_trajectory(lib, oracle_mod, kern):
     # thousands of hartree: a short time step and the median as trial energy
     # keep the population within the capacity.
     ref, out, R = _dmc_pair(lib, oracle_mod, S.f2_shaped(), 45, 3, 0.002, dmc_kernel=kern, et_median=True)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
+
+
+@pytest.mark.parametrize("kern", DMC_KERNELS)
+def test_dmc_f2_bovb_trajectory(lib, oracle_mod, kern):
+    ref, out, R = _dmc_pair(lib, oracle_mod, S.f2_bovb(), 45, 3, 0.002, dmc_kernel=kern, et_median=True)
     _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
 
 

@@ -417,6 +417,22 @@ def test_translation_invariance(oracle_mod):
     np.testing.assert_allclose(b["grad"], a["grad"], rtol=1e-9, atol=1e-10)
 
 
+def test_bovb_without_breathing_is_the_shared_orbital_function(oracle_mod):
+    # Eq. PsiJBOVB with every structure's own active orbitals equal to the
+    # shared ones is the VBSCF wave function of the same structures (a
+    # mistake in the per-structure orbital bookkeeping breaks this); with
+    # breathing the functions differ
+    R = S.initial_walkers(S.f2_shaped(), 24, seed=31)
+    a = oracle_mod.Oracle(S.f2_shaped()).evaluate(R)
+    b = oracle_mod.Oracle(S.f2_bovb(breathing=0.0)).evaluate(R)
+    np.testing.assert_allclose(b["logabs"], a["logabs"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(b["eloc"], a["eloc"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(b["grad"], a["grad"], rtol=1e-10, atol=1e-11)
+    np.testing.assert_allclose(b["ratio"], a["ratio"], rtol=1e-10, atol=1e-12)
+    c = oracle_mod.Oracle(S.f2_bovb()).evaluate(R)
+    assert np.max(np.abs(c["logabs"] - a["logabs"])) > 1e-3
+
+
 def test_coefficient_scaling_invariance(oracle_mod):
     sysd = S.small_random_system(42)
     o = oracle_mod.Oracle(sysd)
