@@ -763,8 +763,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   int off = 0, fn = 0;
   for (int s = 0; s < x->nshell; ++s) {
     int cen = wfi->shell_center[s], kind = wfi->shell_kind[s], l = wfi->shell_l[s], np = wfi->shell_nprim[s];
-    if (cen < 0 || cen >= x->nnuc || (kind != 0 && kind != 1) || l < 0 || l > 2 || np < 1 ||
-        (kind == 1 && l > 1))
+    if (cen < 0 || cen >= x->nnuc || (kind != 0 && kind != 1) || l < 0 || l > 2 || np < 1)
       return bad("bad shell description");
     x->shtab.insert(x->shtab.end(), {cen, kind, l, fn, off, np, 0, 0});
     for (int k = 0; k < np; ++k) {

@@ -58,6 +58,23 @@ def test_h2_all_parameters(lib, oracle_mod):
     _compare(lib, oracle_mod, S.h2_heitler_london(), 8)
 
 
+def test_slater_d_shells_all_parameters(lib, oracle_mod):
+    # Slater s, p, d shells on the second F2 atom (the five basis channels of
+    # a Slater d function feed both orbital-coefficient contractions)
+    sysd = S.f2_shaped()
+    rng = np.random.default_rng(78)
+    shells = []
+    for sh in sysd["shells"]:
+        sh = dict(sh)
+        if sh["center"] == 1:
+            n = len(sh["exps"])
+            sh["kind"] = "sto"
+            sh["exps"] = sorted(rng.uniform(0.6, 4.0, size=n).tolist(), reverse=True)
+            sh["coefs"] = rng.uniform(0.2, 1.0, size=n).tolist()
+        shells.append(sh)
+    _compare(lib, oracle_mod, dict(sysd, shells=shells, name="f2_slater_spd"), 4)
+
+
 def test_f2_bovb_all_parameters(lib, oracle_mod):
     # the breathing orbitals' coefficients are parameters of their own
     _compare(lib, oracle_mod, S.f2_bovb(), 4)

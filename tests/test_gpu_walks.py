@@ -115,8 +115,8 @@ def test_vmc_f2_bovb(lib, oracle_mod, lanes):
     _check_vmc(ref, acc, R, 12, oracle_obj=ref["oracle"])
 
 
-def _f2_with_slater_shells():
-    """The F2-shaped system with the s and p shells of the second atom made
+def _f2_with_slater_shells(lmax=1):
+    """The F2-shaped system with the shells of the second atom up to lmax made
     Slater shells (exponents 0.6-4, same primitive counts): more than eight
     shells, so the row kernel's radial sums take the Slater branch of both
     radial schedules (four bins for full row tiles, eight for the last one)."""
@@ -125,7 +125,7 @@ def _f2_with_slater_shells():
     shells = []
     for sh in sysd["shells"]:
         sh = dict(sh)
-        if sh["center"] == 1 and sh["l"] <= 1:
+        if sh["center"] == 1 and sh["l"] <= lmax:
             n = len(sh["exps"])
             sh["kind"] = "sto"
             sh["exps"] = sorted(rng.uniform(0.6, 4.0, size=n).tolist(), reverse=True)
@@ -138,6 +138,21 @@ def _f2_with_slater_shells():
 def test_vmc_f2_with_slater_shells(lib, oracle_mod, lanes):
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, _f2_with_slater_shells(), 61, 8, 0.3, False, lanes=lanes)
     _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
+
+
+@pytest.mark.parametrize("lanes", ["rows", 32])
+def test_vmc_f2_with_slater_d_shells(lib, oracle_mod, lanes):
+    # Slater s, p and d shells on the second atom: the Laplacian of a Slater
+    # function P e^{-ar} is P (g'' + 2 (l + 1) g' / r) for l = 2 as well
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, _f2_with_slater_shells(2), 61, 8, 0.3, False, lanes=lanes)
+    _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
+
+
+@pytest.mark.parametrize("kern", [1, 2])
+def test_dmc_f2_with_slater_d_shells(lib, oracle_mod, kern):
+    ref, out, R = _dmc_pair(lib, oracle_mod, _f2_with_slater_shells(2), 37, 2, 0.002, dmc_kernel=kern,
+                            et_median=True)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
 
 
 def test_vmc_precision_molecule_refresh_32(lib, oracle_mod):
