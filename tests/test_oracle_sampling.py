@@ -132,3 +132,24 @@ def test_dmc_population_stays_in_band(oracle_mod):
     assert abs(r["W"] / W - 1) <= 0.1
     lo, hi = np.percentile(e0, [5, 95])
     assert np.all((r["etrial"] > lo) & (r["etrial"] < hi)), r["etrial"]
+
+
+def test_blocking_error_of_a_correlated_series():
+    """bench.reblock against the closed-form error of an AR(1) series
+    x_k = phi x_{k-1} + eps_k (unit noise): sigma_mean = 1 / ((1 - phi) sqrt(n))
+    for long series, while the naive estimate is far too small."""
+    import bench
+    rng = np.random.default_rng(3)
+    n, phi = 1 << 14, 0.8
+    x = np.zeros(n)
+    for k in range(1, n):
+        x[k] = phi * x[k - 1] + rng.normal()
+    mean, err, levels = bench.reblock(x, np.ones(n))
+    exact = 1.0 / ((1.0 - phi) * np.sqrt(n))
+    assert abs(mean - x.mean()) < 1e-12
+    assert 0.8 * exact < err < 1.3 * exact, (err, exact)
+    assert x.std() / np.sqrt(n) < 0.5 * exact
+    # a constant series has that constant as its weighted mean, whatever the weights
+    w = rng.uniform(0.5, 2.0, 64)
+    m2, _, _ = bench.reblock(np.full(64, 3.0), w)
+    assert abs(m2 - 3.0) < 1e-14
