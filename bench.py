@@ -532,8 +532,9 @@ def dmc_form(args):
     """The headline: fixed-node DMC on the 16-nucleus, 64-electron,
     240-function, 32-structure / 128-determinant molecule with 32768 target
     walkers, tau = 0.005.  Walkers start from a short FP64 VMC burn-in; the
-    warm-up call and the timed call of `steps` steps each begin by rebuilding
-    the records from their positions.  walker-moves/s counts the walkers
+    warm-up call and the timed call of `steps` steps (default 100, against
+    the workload's 5000-step runs) each begin by rebuilding the records from
+    their positions (one launch, amortised over the call).  walker-moves/s counts the walkers
     present at each timed step over the wall time of the timed call; the
     dominant kernel (the per-step move-and-energy kernel) is timed with HIP
     events on the launch stream inside the library (log step_ms)."""
@@ -544,7 +545,7 @@ def dmc_form(args):
     import systems as S
     system = S.dmc_molecule()
     W = args.walkers or 32768
-    steps = args.steps if args.steps is not None else 20
+    steps = args.steps if args.steps is not None else 100
     warm = args.warmup if args.warmup is not None else 3
     tau = 0.005
     c64 = vb.Context(system, dmc_kernel=args.dmc_kernel)

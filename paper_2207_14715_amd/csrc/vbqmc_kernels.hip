@@ -806,9 +806,12 @@ __global__ void k_dmc_copy(const double* ctrl, const double* src, double* dst, c
     int64_t mid = (lo + hi + 1) / 2;
     if (offs[mid] <= d) lo = mid; else hi = mid - 1;
   }
-  const double* s = src + lo * rec_len;
-  double* o = dst + d * rec_len;
-  for (int k = threadIdx.x; k < rec_len; k += blockDim.x) o[k] = s[k];
+  // records are 256-byte multiples at 256-byte aligned bases: 16-byte copies
+  const double2* s = (const double2*)(src + lo * rec_len);
+  double2* o = (double2*)(dst + d * rec_len);
+  const int n2 = rec_len >> 1;
+#pragma unroll 4
+  for (int k = threadIdx.x; k < n2; k += blockDim.x) o[k] = s[k];
 }
 
 __global__ void k_dmc_commit(double* ctrl) {
