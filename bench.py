@@ -36,6 +36,9 @@ TRAFFIC_LANES = 32
 # the same for one launch of the row kernel (4096 walkers, 100 steps per
 # launch): FETCH_SIZE 5592 KiB x 2.000 + WRITE_SIZE 10902 KiB x 1.000
 TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5619.0 * 2.0 + 9895.7) * 1024}
+# the walker-resident kernel in VMC mode on the 40-electron molecule (two
+# replaced columns at most per determinant, 160 padded basis functions)
+WRES_VMC_KERNEL = "k_dmcw<32, 2, 16, true>"
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
@@ -138,9 +141,11 @@ def main():
                     help="mixed: FP32 trial/proposal rows, FP64 inverse rebuilt before every E_L and FP64 E_L")
     ap.add_argument("--walker-lanes", type=int, default=0, choices=[0, 16, 32, 64],
                     help="lanes per walker in the single-electron sweep (0: library choice)")
-    ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2, 3],
                     help="single-electron step kernel: 0 library choice, 1 sweep + local-energy kernels, "
-                         "2 row kernel")
+                         "2 row kernel, 3 walker-resident kernel")
+    ap.add_argument("--system", default="f2", choices=["f2", "precision"],
+                    help="vmc form: the F2-shaped diatomic or the 40-electron molecule of the precision form")
     ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2, 3],
                     help="DMC: 0 library choice, 1 one workgroup per walker, 2 electron-major launches, "
                          "3 walker-resident")
@@ -180,16 +185,19 @@ def main():
 
 
 def vmc_form(args):
-    """Single-electron VMC on the F2-shaped diatomic (18 electrons, 4096
-    walkers, row kernel): walker-moves/s with E_L every step."""
+    """Single-electron VMC, walker-moves/s with E_L every step: on the
+    F2-shaped diatomic (18 electrons, 4096 walkers, row kernel), or with
+    --system precision on the 10-nucleus, 40-electron molecule (16384
+    walkers, walker-resident kernel)."""
     import torch
 
     import paper_2207_14715_amd as vb
     import systems as S
-    args.steps = 2000 if args.steps is None else args.steps
-    args.warmup = 100 if args.warmup is None else args.warmup
-    args.walkers = 4096 if args.walkers is None else args.walkers
-    system = S.f2_shaped()
+    big = args.system == "precision"
+    args.steps = (200 if big else 2000) if args.steps is None else args.steps
+    args.warmup = (20 if big else 100) if args.warmup is None else args.warmup
+    args.walkers = (16384 if big else 4096) if args.walkers is None else args.walkers
+    system = S.precision_molecule() if big else S.f2_shaped()
     W, step_size = args.walkers, 0.3
     ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes,
                      step_kernel=args.step_kernel)
@@ -207,11 +215,14 @@ def vmc_form(args):
     acc = ctx.new_vmc_acc(W)
     stream = torch.cuda.current_stream()
     rows = ctx.info["step_kernel"] == 2
+    wres = ctx.info["step_kernel"] == 3
     lanes = ctx.info["sweep_lanes"]
-    if rows:
+    if rows or wres:
         # timed region: calls of `spl` steps, each one launch of the row
-        # kernel (moves and E_L of every step), bracketed by events on the
-        # launch stream; a shorter last call is timed but not averaged
+        # kernel (moves and E_L of every step), or for the walker-resident
+        # kernel 1 + spl launches (the record rebuild that opens the call,
+        # then one per step), bracketed by events on the launch stream; a
+        # shorter last call is timed but not averaged
         chunks = [spl] * (args.steps // spl) + ([args.steps % spl] if args.steps % spl else [])
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(chunks))]
         torch.cuda.synchronize()
@@ -225,8 +236,8 @@ def vmc_form(args):
         wall = time.perf_counter() - t0
         full = [k for k, c in enumerate(chunks) if c == spl] or [0]
         kernel_s = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in full) / 1e3
-        launches = len(full)
-        steps_launch = chunks[full[0]]
+        launches = len(full) * (chunks[full[0]] + 1 if wres else 1)
+        steps_launch = chunks[full[0]] / (chunks[full[0]] + 1) if wres else chunks[full[0]]
         measure_s = None
     else:
         # timed region: per step one sweep (the dominant kernel, bracketed by
@@ -253,7 +264,13 @@ def vmc_form(args):
     sweep_flops = sweep_flops_per_walker_move(ctx, system, accept_rate) * W
     measure_flops = measure_flops_per_walker(ctx, system) * W
     prec_tag = {"fp64": 0, "fp32": 1, "bf16": 2, "mixed": 0}[args.precision]
-    if rows:
+    if wres:
+        # every launch but the rebuild makes the moves and E_L of one step;
+        # the rebuild's work is not counted (steps_launch = spl / (spl + 1))
+        kernel = WRES_VMC_KERNEL
+        flops_launch = (sweep_flops + measure_flops) * steps_launch
+        traffic = None
+    elif rows:
         # the dominant (and only) kernel makes moves and E_L of every step
         ne = 10 if max(ctx.info["n_up"], ctx.info["n_dn"]) <= 10 else 16  # register columns per lane
         kernel = f"k_vmc_rows<1, 0, {ne}>" if args.precision == "mixed" else f"k_vmc_rows<{prec_tag}, {prec_tag}, {ne}>"
@@ -281,11 +298,16 @@ def vmc_form(args):
         "vs_baseline": None,
         "dtype": _dtype(args.precision),
         "data": "synthetic",
-        "config": {"workload": "F2-shaped diatomic VMC: 18 electrons (9 up, 9 down), 28 Gaussian basis "
-                               "functions, 3 VB structures / 4 determinants, 4096 walkers, single-electron "
-                               "moves of 0.3 bohr with Sherman-Morrison updates, E_L every step",
+        "config": {"workload": ("40-electron molecule VMC: 10 nuclei (Z in {1,6,7,8}), 20 up + 20 down "
+                                "electrons, 150 Gaussian basis functions, 20 VB structures / 64 determinants, "
+                                f"{W} walkers, single-electron moves of 0.3 bohr with Sherman-Morrison "
+                                "updates, E_L every step" if big else
+                                "F2-shaped diatomic VMC: 18 electrons (9 up, 9 down), 28 Gaussian basis "
+                                "functions, 3 VB structures / 4 determinants, 4096 walkers, single-electron "
+                                "moves of 0.3 bohr with Sherman-Morrison updates, E_L every step"),
                    "walkers": W, "electrons": ctx.N, "precision": args.precision,
-                   "step_kernel": "rows" if rows else f"sweep {lanes} lanes + local energy"},
+                   "step_kernel": "rows" if rows else "walker-resident" if wres else
+                   f"sweep {lanes} lanes + local energy"},
         "electron_moves_per_s": moves * ctx.N / wall,
         "acceptance": accept_rate,
         "mean_eloc": e_mean,
@@ -300,7 +322,8 @@ def vmc_form(args):
                            "avg_ms_per_step": measure_s / args.steps * 1e3, "flops_per_step": measure_flops,
                            "achieved_tflops": measure_flops / (measure_s / args.steps) / 1e12}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(system, step_size)
+        line["cpu_baseline"] = (cpu_baseline(system, step_size, steps=4, walkers=256) if big else
+                                cpu_baseline(system, step_size))
     print(json.dumps(line))
 
 
@@ -437,7 +460,7 @@ def adjoint_form(args):
 
 
 HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"
-DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16>"}
+DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16, false>"}
 # HBM bytes of one launch of the walker-resident DMC step kernel on the
 # headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the copy-kernel calibration (the factors below), with

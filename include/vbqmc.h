@@ -123,9 +123,15 @@ typedef struct {
  * launches, per step; 2 = the row kernel: four walkers per wavefront, 16
  * lanes each, moves and E_L of all n_steps steps in one launch (systems with
  * at most 24 electrons and, per spin, at most 16 reference slots plus table
- * orbitals and 16 distinct determinants; EINVAL at create otherwise); 0 =
- * 2 when the system fits it and walker_lanes is 0, else 1.  Results do not
- * depend on it beyond rounding.
+ * orbitals and 16 distinct determinants; EINVAL at create otherwise); 3 =
+ * the walker-resident kernel of dmc_kernel 3 in its Metropolis form: each
+ * call rebuilds the records from their positions (one launch) and then runs
+ * one launch per step (moves, refresh and E_L of four walkers per
+ * workgroup), with the same limits as dmc_kernel 3 (EINVAL at create
+ * otherwise); a call that asks for S_IJ sums (sij_sum set) runs the sweep
+ * and local-energy kernels instead.  0 = 2 when the system fits it and
+ * walker_lanes is 0, else 3 when it fits that and walker_lanes is 0, else 1.
+ * Results do not depend on it beyond rounding.
  * dmc_kernel: how vbqmc_dmc_advance runs a step: 1 = one workgroup per walker
  * makes all of the walker's moves, E_L and weight; 2 = electron-major: for
  * each electron a proposal launch, an MFMA launch for the orbital rows at
@@ -251,7 +257,7 @@ int vbqmc_vmc_advance(vbqmc_ctx* ctx, void* state, int64_t W, int32_t n_steps, u
  * used).  vbqmc_vmc_advance with all_electron = 0 equals, per step, a sweep
  * followed by a measure: bit for bit when it runs the sweep and local-energy
  * kernels (step_kernel 1), with the same moves and E_L to rounding when it
- * runs the row kernel (step_kernel 2).  Both need the system to fit the sweep and
+ * runs the row or the walker-resident kernel (step_kernel 2 or 3).  Both need the system to fit the sweep and
  * local-energy kernels (EINVAL otherwise, where vbqmc_vmc_advance still
  * runs); state [dev] is any record written by this library.
  */

@@ -659,14 +659,18 @@ __device__ bool dw_refresh_ns(double* Wm, const double* vrow, int WD, int n, int
 // prep = 1: rebuild each record from its positions (orbital-row caches of
 // every electron, fresh inverses, tables, ratios, E_L) with no move and no
 // weight; prep = 0: one DMC step.
-template <int NC, int XE, int LK>
+// VMC = true: one single-electron Metropolis step (Sec. 2.3.1) instead: a
+// uniform-cube proposal r' = r + s (2u - 1) per component, accepted iff
+// u' < |Psi'/Psi|^2 (no drift, no node rejection, no weight), E_L added to
+// the walker's VMC accumulators (vm; ctrl, tau, br and nacc unused).
+template <int NC, int XE, int LK, bool VMC>
 __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dmcw(const DevWF* __restrict__ pwf, double* state, const double* ctrl,
                                                 uint64_t seed, uint32_t step, double tau, DmcBranch br, double* nacc,
-                                                int prep) {
+                                                int prep, DwVmc vm) {
   const DevWF& wf = *pwf;
-  const int64_t W = (int64_t)ctrl[DC_W];
+  const int64_t W = VMC ? vm.W : (int64_t)ctrl[DC_W];
   const int64_t wbase = (int64_t)blockIdx.x * kDwW;
-  if (ctrl[DC_ERR] != 0.0 || wbase >= W) return;
+  if ((!VMC && ctrl[DC_ERR] != 0.0) || wbase >= W) return;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t w = wbase + g;
   const bool live = w < W;
@@ -711,10 +715,11 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   double* RW = rec + wf.r_RW;
   double S = RW[2 * (n0 + n1)];
   const double E_old = rec[wf.r_sc + SC_ELOC];
-  bool bad = !live || (!prep && (rec[wf.r_sc + SC_FLAGS] != 0.0 || !(S != 0.0)));
+  // (VMC keeps a walker flagged by an earlier call flagged through the rebuild)
+  bool bad = !live || ((!prep || VMC) && rec[wf.r_sc + SC_FLAGS] != 0.0) || (!prep && !(S != 0.0));
   double na = 0.0;
-  const double ET = ctrl[DC_ET];
-  const double sqt = sqrt(tau);
+  const double ET = VMC ? 0.0 : ctrl[DC_ET];
+  const double sqt = VMC ? 0.0 : sqrt(tau);
   const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
   const double kappa = wf.kappa;
   double* vc = rec + wf.r_vc;  // value rows [N][WD]
@@ -771,18 +776,25 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       philox_pair(seed, (uint32_t)w, step, 4u * ie, 0u, a0, a1);
       philox_pair(seed, (uint32_t)w, step, 4u * ie, 1u, b0, b1);
       philox_pair(seed, (uint32_t)w, step, 4u * ie + 1u, 0u, ua, dummy);
-      const double two_pi = 6.283185307179586476925286766559;
-      const double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
-      rnd[4 * lane] = r0 * cos(two_pi * a1);
-      rnd[4 * lane + 1] = r0 * sin(two_pi * a1);
-      rnd[4 * lane + 2] = r1 * cos(two_pi * b1);
+      if constexpr (VMC) {
+        // (the displacement of the uniform cube)
+        rnd[4 * lane] = vm.step * (2.0 * a0 - 1.0);
+        rnd[4 * lane + 1] = vm.step * (2.0 * a1 - 1.0);
+        rnd[4 * lane + 2] = vm.step * (2.0 * b0 - 1.0);
+      } else {
+        const double two_pi = 6.283185307179586476925286766559;
+        const double r0 = sqrt(-2.0 * log(1.0 - a0)), r1 = sqrt(-2.0 * log(1.0 - b0));
+        rnd[4 * lane] = r0 * cos(two_pi * a1);
+        rnd[4 * lane + 1] = r0 * sin(two_pi * a1);
+        rnd[4 * lane + 2] = r1 * cos(two_pi * b1);
+      }
       rnd[4 * lane + 3] = ua;
     }
     // the cached gradient rows of the next electron to move, in flight
     // while the current move runs (electron e0 + il + 1 does not move in
     // move il, so its rows do not change)
     double gn[3] = {0.0, 0.0, 0.0};
-    if (!prep && lane < WD)
+    if (!VMC && !prep && lane < WD)
 #pragma unroll
       for (int c = 0; c < 3; ++c) gn[c] = gc[((size_t)e0 * 3 + c) * WD + lane];
     wave_sync();
@@ -790,6 +802,38 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       const int i = e0 + il;
       const bool act = !bad;
       double uo[2] = {0.0, 0.0};  // Jastrow pair values at the current point, per partner lane
+      if constexpr (VMC) {
+        // (A) the uniform-cube proposal and the Jastrow pair values at the
+        // current point
+        if (act) {
+          if (lane == il)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) bc[j] = C[j];
+          const double xi = Rl[3 * i], yi = Rl[3 * i + 1], zi = Rl[3 * i + 2];
+#pragma unroll
+          for (int it = 0; it < 2; ++it) {
+            const int j = lane + 64 * it;
+            if (j >= N + nn || j == i) continue;
+            double xj, yj, zj;
+            PairCoef cf;
+            if (j < N) {
+              xj = Rl[3 * j]; yj = Rl[3 * j + 1]; zj = Rl[3 * j + 2];
+              cf = s != spin_of(wf, j) ? c_anti : c_par;
+            } else {
+              const double* nu = l.nuc() + 4 * (j - N);
+              xj = nu[0]; yj = nu[1]; zj = nu[2];
+              cf = en_coef(l.en() + 6 * (j - N));
+            }
+            const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            double u, u1, u2;
+            pair_fn(sqrt(dx * dx + dy * dy + dz * dz), kappa, cf, u, u1, u2);
+            uo[it] = u;
+          }
+          if (lane < 3) Pw[6 * g + lane] = Rl[3 * i + lane] + rnd[4 * il + lane];
+        } else if (lane < 3) {
+          Pw[6 * g + lane] = 0.0;
+        }
+      } else {
       // (A) drift at the current point from the cached gradient rows
       if (act) {
         const double g3[3] = {gn[0], gn[1], gn[2]};
@@ -852,6 +896,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       } else if (lane < 3) {
         Pw[6 * g + lane] = 0.0;
       }
+      }
       __syncthreads();
       // (B) value and gradient rows at the four proposals
       dw_tile_tables<kDwW, 0>(wf, l, Pw, 6);
@@ -911,7 +956,11 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         const double rdet = part[0] / S, dU = part[1];
         bool accept = false;
         const double ir = 1.0 / rho;
-        if (rdet > 0.0 && rho != 0.0) {
+        if constexpr (VMC) {
+          // |Psi'/Psi|^2 (either sign; a move that makes the reference
+          // determinant exactly singular, a set of measure zero, is refused)
+          accept = rho != 0.0 && rnd[4 * il + 3] < rdet * rdet * exp(2.0 * dU);
+        } else if (rdet > 0.0 && rho != 0.0) {
           // drift at r' with the state after the move: B'[:, il] = bc / rho,
           // T' = T + bc y^T / rho, R'_u = Q_u / rho, S' = S rdet / rho
           const double Snew = S * rdet / rho;
@@ -1226,7 +1275,16 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   // ---- E_L, weight, record scalars ----
   if (live && lane == 0) {
     const double En = bad ? NAN : -0.5 * tsum + vsum + wf.vnn;
-    if (!prep) {
+    if constexpr (VMC) {
+      if (!prep) {
+        if (!bad) {
+          vm.e_sum[w] += En;
+          vm.e2_sum[w] += En * En;
+        }
+        vm.n_accept[w] += na;
+        vm.e_last[w] = En;
+      }
+    } else if (!prep) {
       dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, N, seed, step);
       nacc[w] = na;
     }
@@ -1239,32 +1297,31 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     for (int k = lane; k < 3 * N; k += 64) rec[wf.r_R + k] = Rl[k];
 }
 
-template <int NC, int XE, int LK>
+template <int NC, int XE, int LK, bool VMC>
 static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
                                 uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
-                                hipStream_t s) {
+                                const DwVmc& vm, hipStream_t s) {
   const size_t lds = (size_t)wf.lds_dmcw_doubles * sizeof(double);
   static size_t cur = 0;
   if (lds > cur) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_dmcw<NC, XE, LK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_dmcw<NC, XE, LK, VMC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     cur = lds;
   }
   const unsigned blocks = (unsigned)((cap + kDwW - 1) / kDwW);
-  hipLaunchKernelGGL((k_dmcw<NC, XE, LK>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau, br,
-                     nacc, prep);
+  hipLaunchKernelGGL((k_dmcw<NC, XE, LK, VMC>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau,
+                     br, nacc, prep, vm);
   return hipGetLastError();
 }
 
-// one DMC step (prep = 0) or the rebuild of every record from its positions
-// (prep = 1) for the walkers of ctrl[DC_W] in state; wf is the host copy of
-// the layout in dwf (dw_xe: the most columns a determinant replaces)
-hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
-                       uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
-                       hipStream_t s) {
+template <bool VMC>
+static hipError_t launch_dmcw_any(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                                  uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc,
+                                  int prep, const DwVmc& vm, hipStream_t s) {
   const int kper = wf.Mpad / (4 * kDwW);
-#define VBQMC_DMCW(XE, LK) return launch_dmcw_t<32, XE, LK>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, s)
+#define VBQMC_DMCW(XE, LK) \
+  return launch_dmcw_t<32, XE, LK, VMC>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, vm, s)
   if (wf.dw_xe <= 2) {
     if (kper <= 4) VBQMC_DMCW(2, 4);
     if (kper <= 8) VBQMC_DMCW(2, 8);
@@ -1274,6 +1331,22 @@ hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const d
   if (kper <= 8) VBQMC_DMCW(3, 8);
   VBQMC_DMCW(3, 16);
 #undef VBQMC_DMCW
+}
+
+// one DMC step (prep = 0) or the rebuild of every record from its positions
+// (prep = 1) for the walkers of ctrl[DC_W] in state; wf is the host copy of
+// the layout in dwf (dw_xe: the most columns a determinant replaces)
+hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
+                       uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
+                       hipStream_t s) {
+  return launch_dmcw_any<false>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, DwVmc{}, s);
+}
+
+// one single-electron VMC step (prep = 0) or the rebuild of every record
+// (prep = 1) for the vm.W walkers of state, accumulating into vm
+hipError_t launch_dmcw_vmc(const DevWF& wf, const DevWF* dwf, double* state, uint64_t seed, uint32_t step, int prep,
+                           const DwVmc& vm, hipStream_t s) {
+  return launch_dmcw_any<true>(wf, dwf, state, nullptr, vm.W, seed, step, 0.0, DmcBranch{}, nullptr, prep, vm, s);
 }
 
 }  // namespace vbqmc

@@ -49,6 +49,8 @@ hipError_t launch_copy_records(const double* src, double* dst, int64_t n, hipStr
 hipError_t launch_dmcw(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
                        uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
                        hipStream_t s);
+hipError_t launch_dmcw_vmc(const DevWF& wf, const DevWF* dwf, double* state, uint64_t seed, uint32_t step, int prep,
+                           const DwVmc& vm, hipStream_t s);
 hipError_t launch_positions(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* R, hipStream_t s);
 hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, const double* state, double* e, hipStream_t s);
 hipError_t launch_reduce(int64_t W, int K, const double* wts, const double* in, double* out, hipStream_t s);
@@ -163,7 +165,8 @@ struct vbqmc_ctx {
   int sweep_g = 64;             // lanes per walker in the single-electron sweep
   DevWF* d_wf_aux = nullptr;    // same tables, compact LDS layout of the batched local-energy kernels
   DevWF* d_wf_rows = nullptr;   // same tables, layout of the row step kernel (four walkers per wavefront)
-  int step_kernel = 1;          // single-electron VMC steps: 1 sweep + local-energy kernels, 2 row kernel
+  int step_kernel = 1;          // single-electron VMC steps: 1 sweep + local-energy kernels, 2 row kernel,
+                                // 3 walker-resident kernel
   DevWF* d_wf_dmcb = nullptr;   // same tables, layout of the electron-major DMC row tiles
   int dmc_kernel = 1;           // DMC steps: 1 one workgroup per walker, 2 electron-major, 3 walker-resident
   DevWF* d_wf_dmcw = nullptr;   // same tables, layout of the walker-resident DMC kernel
@@ -719,7 +722,7 @@ int upload_coefficients(vbqmc_ctx* x) {
     DevWF a = dmcb_layout(x);
     e = hipMemcpy(x->d_wf_dmcb, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess && x->d_wf_dmcw && x->dmc_kernel == 3) {
+  if (e == hipSuccess && x->d_wf_dmcw && (x->dmc_kernel == 3 || x->step_kernel == 3)) {
     DevWF a = dmcw_layout(x);
     e = hipMemcpy(x->d_wf_dmcw, &a, sizeof(DevWF), hipMemcpyHostToDevice);
   }
@@ -1124,20 +1127,24 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     }
     if (x->sweep_g < 64) wf.lds_sweepg_doubles = sweepg_layout(x, x->sweep_g).lds_sweepg_doubles;
   }
-  // kernel of single-electron VMC steps: the row kernel when the system fits
-  // it and no lane count was asked for, else the sweep + local-energy kernels
+  // kernel of single-electron VMC steps: with no lane count asked for, the
+  // row kernel when the system fits it, else the walker-resident kernel when
+  // it fits that; else the sweep + local-energy kernels
   {
     const int req = opt ? opt->step_kernel : 0;
     const int lanes = opt ? opt->walker_lanes : 0;
     if (req == 2) {
       if (!rows_fit(x)) return bad("step_kernel 2: the system does not fit the row kernel");
       x->step_kernel = 2;
+    } else if (req == 3) {
+      if (!dmcw_fit(x)) return bad("step_kernel 3: the system does not fit the walker-resident kernel");
+      x->step_kernel = 3;
     } else if (req == 1) {
       x->step_kernel = 1;
     } else if (req == 0) {
-      x->step_kernel = lanes == 0 && rows_fit(x) ? 2 : 1;
+      x->step_kernel = lanes != 0 ? 1 : rows_fit(x) ? 2 : dmcw_fit(x) ? 3 : 1;
     } else {
-      return bad("step_kernel must be 0, 1 or 2");
+      return bad("step_kernel must be 0, 1, 2 or 3");
     }
     if (x->step_kernel == 2) wf.lds_rows_doubles = rows_layout(x).lds_rows_doubles;
   }
@@ -1378,6 +1385,17 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
     hipError_t e = launch_vmc_rows(x->wf, x->d_wf_rows, (double*)state, W, n_steps, seed, step0, step_size,
                                    acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum,
                                    (hipStream_t)stream);
+    return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
+  }
+  if (!all_electron && x->step_kernel == 3 && !acc->sij_sum) {
+    // rebuild the records (orbital-row caches at every electron), then one
+    // walker-resident launch per step: moves, refresh and E_L
+    DwVmc vm{step_size, W, acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last};
+    const DevWF lay = dmcw_layout(x);
+    hipError_t e = launch_dmcw_vmc(lay, x->d_wf_dmcw, (double*)state, seed, 0, 1, vm, (hipStream_t)stream);
+    for (int st = 0; st < n_steps && e == hipSuccess; ++st)
+      e = launch_dmcw_vmc(lay, x->d_wf_dmcw, (double*)state, seed, (uint32_t)(step0 + st), 0, vm,
+                          (hipStream_t)stream);
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
   if (!all_electron && split_fits(x)) {

@@ -155,4 +155,15 @@ struct DmcBranch {
   int* nc;
 };
 
+// Walker-resident kernel in VMC mode (single-electron Metropolis steps):
+// step size, walker count and the per-walker accumulators of vbqmc_vmc_acc.
+struct DwVmc {
+  double step;
+  int64_t W;
+  double* e_sum;
+  double* e2_sum;
+  double* n_accept;
+  double* e_last;
+};
+
 }  // namespace vbqmc

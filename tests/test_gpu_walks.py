@@ -25,11 +25,13 @@ def lib():
 
 
 def _context(lib, sysd, kernel):
-    """kernel: "rows" (row step kernel), an int lane count (sweep +
-    local-energy kernels with that many lanes per walker) or 0 (library
-    choice)."""
+    """kernel: "rows" (row step kernel), "wres" (walker-resident kernel), an
+    int lane count (sweep + local-energy kernels with that many lanes per
+    walker) or 0 (library choice)."""
     if kernel == "rows":
         return lib.Context(sysd, step_kernel=2)
+    if kernel == "wres":
+        return lib.Context(sysd, step_kernel=3)
     if kernel == 0:
         return lib.Context(sysd)
     return lib.Context(sysd, walker_lanes=kernel, step_kernel=1)
@@ -79,10 +81,13 @@ def test_vmc_h2_all_electron(lib, oracle_mod):
 
 
 # single-electron steps run on the row kernel (four walkers per wavefront,
-# moves and E_L of all steps in one launch) or as sweeps with 16 or 32 lanes
-# per walker (several walkers per wavefront) or one walker per workgroup,
-# followed by the batched local energy; all four must give the walks
-LANES = ["rows", 16, 32, 64]
+# moves and E_L of all steps in one launch), on the walker-resident kernel
+# (one walker per wavefront, orbital rows cached in the record, one launch
+# per step; with S_IJ sums asked for, the sweep kernels instead) or as sweeps
+# with 16 or 32 lanes per walker (several walkers per wavefront) or one
+# walker per workgroup, followed by the batched local energy; all must give
+# the walks
+LANES = ["rows", "wres", 16, 32, 64]
 
 
 @pytest.mark.parametrize("lanes", LANES)
@@ -107,7 +112,7 @@ def test_vmc_f2_sherman_morrison(lib, oracle_mod, lanes):
     _check_vmc(ref, acc, R, 12, oracle_obj=ref["oracle"])
 
 
-@pytest.mark.parametrize("lanes", ["rows", 32])
+@pytest.mark.parametrize("lanes", ["rows", "wres", 32])
 def test_vmc_f2_bovb(lib, oracle_mod, lanes):
     # per-structure active orbitals (Eq. PsiJBOVB): each ionic structure's own
     # orbital is a table orbital of both spins; past the 32-update refresh
@@ -156,15 +161,45 @@ def test_dmc_f2_with_slater_d_shells(lib, oracle_mod, kern):
 
 
 def test_vmc_precision_molecule_refresh_32(lib, oracle_mod):
-    # the 40-electron molecule (20 per spin, 64 determinants) on its default
-    # path: the 32-lane wavefront sweep with Sherman-Morrison updates and the
-    # inverse rebuilt every 32 accepted updates (about every third step at
-    # ~60 % acceptance), then the batched local energy; 8 steps pass two
-    # rebuilds of each spin.  E_L of the last step is checked walker by walker.
+    # the 40-electron molecule (20 per spin, 64 determinants) on the 32-lane
+    # wavefront sweep with Sherman-Morrison updates and the inverse rebuilt
+    # every 32 accepted updates (about every third step at ~60 % acceptance),
+    # then the batched local energy; 8 steps pass two rebuilds of each spin.
+    # E_L of the last step is checked walker by walker.
     sysd = S.precision_molecule()
-    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 32, 8, 0.3, False)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 32, 8, 0.3, False, lanes=32)
     assert ctx.info["sweep_lanes"] == 32 and ctx.info["step_kernel"] == 1
     _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
+
+
+def test_vmc_precision_molecule_walker_resident(lib, oracle_mod):
+    # the 40-electron molecule on the walker-resident kernel: 20 electrons per
+    # spin in registers, 64 determinants, the inverse refreshed every 32
+    # accepted updates (Newton-Schulz from the running inverse, Gauss-Jordan
+    # at the rebuild that opens the call); 35 walkers leave a partly filled
+    # last workgroup.  Two calls continue one walk (the second call's rebuild
+    # starts from the first call's records).
+    import torch
+    sysd = S.precision_molecule()
+    W, steps, seed, step0, step_size = 35, 8, 4242, 17, 0.3
+    R0 = S.initial_walkers(sysd, W, seed=5)
+    o = oracle_mod.Oracle(sysd)
+    ref = o.vmc(R0, steps, seed, step0, step_size, False)
+    ctx = lib.Context(sysd, step_kernel=3)
+    assert ctx.info["step_kernel"] == 3
+    print(f"[vmc wres] {sysd['name']} W={W} steps={steps}", flush=True)
+    state = ctx.walkers_init(torch.from_numpy(R0).cuda())
+    acc = ctx.new_vmc_acc(W)
+    ctx.vmc_advance(state, 5, seed, step0, step_size, False, acc=acc)
+    ctx.vmc_advance(state, steps - 5, seed, step0 + 5, step_size, False, acc=acc)
+    R = ctx.positions(state).cpu().numpy()
+    torch.cuda.synchronize()
+    _check_vmc(ref, acc, R, steps, oracle_obj=o)
+
+
+def test_vmc_walker_resident_rejects_slater_shells(lib):
+    with pytest.raises(lib.VBQMCError):
+        lib.Context(_f2_with_slater_shells(), step_kernel=3)
 
 
 def _reference_sets(sysd):
@@ -486,12 +521,12 @@ def test_refreshed_walkers_match_a_fresh_evaluation(lib):
     sysd = S.precision_molecule()
     W = 4096
     R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=9)).cuda()
-    c64 = lib.Context(sysd)
+    c64 = lib.Context(sysd, step_kernel=1)
     print(f"[refresh vs evaluate] {sysd['name']} W={W}", flush=True)
     st = c64.walkers_init(R0)
     c64.vmc_advance(st, 20, 777, 0, 0.3)
     R = c64.positions(st)
-    ctx = lib.Context(sysd, refresh_every=1)
+    ctx = lib.Context(sysd, refresh_every=1, step_kernel=1)
     s1 = ctx.walkers_init(R.clone())
     acc = ctx.new_vmc_acc(W)
     ctx.vmc_advance(s1, 1, 777, 1001, 0.3, False, acc)
