@@ -269,7 +269,10 @@ def vmc_form(args):
         # the rebuild's work is not counted (steps_launch = spl / (spl + 1))
         kernel = WRES_VMC_KERNEL
         flops_launch = (sweep_flops + measure_flops) * steps_launch
-        traffic = None
+        t = WRES_VMC_TRAFFIC
+        traffic = ((t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024
+                   if (big and W == t["walkers"] and args.precision == "fp64" and
+                       _src_sha("vbqmc_dmcw.hip") == t["src_sha"]) else None)
     elif rows:
         # the dominant (and only) kernel makes moves and E_L of every step
         ne = 10 if max(ctx.info["n_up"], ctx.info["n_dn"]) <= 10 else 16  # register columns per lane
@@ -322,7 +325,7 @@ def vmc_form(args):
                            "avg_ms_per_step": measure_s / args.steps * 1e3, "flops_per_step": measure_flops,
                            "achieved_tflops": measure_flops / (measure_s / args.steps) / 1e12}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = (cpu_baseline(system, step_size, steps=4, walkers=256) if big else
+        line["cpu_baseline"] = (cpu_baseline(system, step_size, steps=8, walkers=512) if big else
                                 cpu_baseline(system, step_size))
     print(json.dumps(line))
 
@@ -466,8 +469,12 @@ DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb
 # dispatch) scaled by the copy-kernel calibration (the factors below), with
 # the SHA-256 prefix of the kernel source they were taken on: the value is
 # reported only while the source is unchanged (else null).
-DMCW_TRAFFIC = {"src_sha": "79dd26a5761d9d71", "fetch_kib": 3382906.8, "write_kib": 4277161.2, "fetch_factor": 2.000,
+DMCW_TRAFFIC = {"src_sha": "5de393447ea0330f", "fetch_kib": 3380337.4, "write_kib": 4278335.5, "fetch_factor": 2.000,
                 "write_factor": 1.000, "walkers": 32768}
+# the same for one step launch of that kernel in VMC mode on the 40-electron
+# molecule (16384 walkers; the mean of 12 step dispatches)
+WRES_VMC_TRAFFIC = {"src_sha": "5de393447ea0330f", "fetch_kib": 343249.9, "write_kib": 576914.2, "fetch_factor": 2.000,
+                    "write_factor": 1.000, "walkers": 16384}
 
 
 def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
