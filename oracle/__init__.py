@@ -62,6 +62,17 @@ def _load():
     return _lib
 
 
+def een_terms():
+    """The f_een terms (k, l, m) in the oracle's order (Sec. 2.1)."""
+    klm = np.zeros((64, 3), dtype=np.int32)
+    n = int(_load().orc_een_terms(_ip(klm)))
+    return [tuple(int(x) for x in r) for r in klm[:n]]
+
+
+def een_term_count():
+    return len(een_terms())
+
+
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -119,16 +130,23 @@ class Oracle:
         self._en = np.ascontiguousarray([[e["a1"], e["a2"]] + list(e["poly"]) for e in jas["en"]],
                                         dtype=np.float64).reshape(-1)
         self.kappa = float(jas["kappa"])
+        # f_een coefficients (Sec. 2.1), per nucleus in the oracle's term
+        # order, or none
+        self.n_een = een_term_count() if jas.get("een") is not None else 0
+        self._een = (np.ascontiguousarray(jas["een"], dtype=np.float64).reshape(-1) if self.n_een else None)
+        if self.n_een:
+            assert self._een.size == self.n_een * self.n_nuc, "een: one row of coefficients per nucleus"
         self._h = lib.orc_create(
             ctypes.c_int(self.n_nuc), _dp(self.Z), _dp(self.pos), ctypes.c_int(self.n_up), ctypes.c_int(self.n_dn),
             ctypes.c_int(len(sh)), _ip(self._sh[0]), _ip(self._sh[1]), _ip(self._sh[2]), _ip(self._sh[3]),
             _dp(self._pexp), _dp(self._pcoef), ctypes.c_int(self.n_orb), _dp(self.lam),
             ctypes.c_int(self.n_struct), _dp(self.c), ctypes.c_int(len(tstruct)), _ip(self._tstruct),
-            _ip(self._tcounts), _ip(self._torbs), ctypes.c_double(self.kappa), _dp(self._ee), _dp(self._en))
+            _ip(self._tcounts), _ip(self._torbs), ctypes.c_double(self.kappa), _dp(self._ee), _dp(self._en),
+            _dp(self._een) if self.n_een else None)
         self._lib = lib
         self.n_dets = int(lib.orc_num_dets(ctypes.c_void_p(self._h)))
         self.n_params = int(lib.orc_num_params(ctypes.c_void_p(self._h)))
-        self.n_jastrow = 6 + 6 * self.n_nuc
+        self.n_jastrow = 6 + 6 * self.n_nuc + self.n_een * self.n_nuc
 
     def __del__(self):
         if getattr(self, "_h", None):

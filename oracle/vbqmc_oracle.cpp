@@ -13,8 +13,10 @@
 //     unpaired active orbitals; expansion into 2^{N_pairs} determinants.
 //   Sec. 2.1: orbitals phi_p = sum_mu lambda_{p,mu} chi_mu; Gaussian / Slater
 //     basis functions.
-//   Sec. 2.1: Jastrow J = exp(f_en + f_ee (+ f_een)), scaled variable
-//     R(r) = r / (1 + kappa r), Pade plus R^p polynomial pair terms.
+//   Sec. 2.1: Jastrow J = exp(f_en + f_ee + f_een), scaled variables
+//     R(r) = r / (1 + kappa r) and Rbar(r) = 1 / (1 + kappa r), Pade plus
+//     R^p polynomial pair terms and the electron-electron-nucleus expansion
+//     in Rbar (optional: a system without its coefficients has no f_een).
 //   Sec. 2.3.1, Eq. (Elav): local energy E_L = H Psi / Psi, spins fixed,
 //     Metropolis-Hastings sampling of Psi^2.
 //   Sec. 2.3.2, Eq. (E0DMCweights): fixed-node DMC with weighted walkers and a
@@ -96,8 +98,9 @@ struct System {
   // Jastrow
   double kappa = 0;
   double ee_a_anti = 0, ee_a_par = 0;
-  std::vector<double> jas;  // [b_anti, b_par, b3..b6 | per nucleus a1..a6]
+  std::vector<double> jas;  // [b_anti, b_par, b3..b6 | per nucleus a1..a6 | per nucleus f_een c_t]
   int njas = 0;
+  bool een = false;         // f_een present (its coefficients close jas)
   int nparam() const { return nstruct + norb * M + njas; }
 };
 
@@ -298,6 +301,116 @@ void pair_u(double r, double kappa, T a, T b, const T* q, T& u, T& u1, T& u2) {
 }
 
 // ---------------------------------------------------------------------------
+// Electron-electron-nucleus terms f_een (Sec. 2.1).  For p = 2..5,
+// k = 0..p-1 and l = 0..l_max, l_max = p - k for k > 0 and p - k - 2 for
+// k = 0, the terms with m = (p - k - l) / 2 a whole number, in that loop
+// order; term t of nucleus alpha contributes, for every electron pair i < j,
+//   c_{t,alpha} Rbar(r_ij)^k [Rbar(r_ia)^l + Rbar(r_ja)^l] [Rbar(r_ia) Rbar(r_ja)]^m.
+// ---------------------------------------------------------------------------
+struct EenTerm {
+  int k, l, m;
+};
+
+std::vector<EenTerm> een_terms() {
+  std::vector<EenTerm> t;
+  for (int p = 2; p <= 5; ++p)
+    for (int k = 0; k < p; ++k) {
+      int lmax = k > 0 ? p - k : p - k - 2;
+      for (int l = 0; l <= lmax; ++l)
+        if ((p - k - l) % 2 == 0) t.push_back({k, l, (p - k - l) / 2});
+    }
+  return t;
+}
+
+// Second-order jets along one coordinate direction: value, first and second
+// derivative in the displacement t of one electron (the Laplacian of f_een is
+// the sum of the second derivatives over the three axes).
+struct Jet {
+  double v, d, dd;
+};
+inline Jet jmul(Jet a, Jet b) { return {a.v * b.v, a.d * b.v + a.v * b.d, a.dd * b.v + 2 * a.d * b.d + a.v * b.dd}; }
+inline Jet jadd(Jet a, Jet b) { return {a.v + b.v, a.d + b.d, a.dd + b.dd}; }
+inline Jet jpow(Jet a, int n) {
+  Jet r{1.0, 0.0, 0.0};
+  for (int q = 0; q < n; ++q) r = jmul(r, a);
+  return r;
+}
+inline Jet jsqrt(Jet a) {
+  double s = std::sqrt(a.v);
+  return {s, a.d / (2 * s), a.dd / (2 * s) - a.d * a.d / (4 * s * a.v)};
+}
+inline Jet jinv(Jet a) {  // 1 / a
+  double i = 1.0 / a.v;
+  return {i, -a.d * i * i, -a.dd * i * i + 2 * a.d * a.d * i * i * i};
+}
+
+// Rbar(|x - y|) as a jet: x moves along axis `ax` with x(t) = x + t e_ax
+// (mv = true), or stays (mv = false); y is fixed.
+Jet rbar_jet(const double* x, const double* y, int ax, bool mv, double kappa) {
+  Jet q{0.0, 0.0, 0.0};
+  for (int c = 0; c < 3; ++c) {
+    double dv = x[c] - y[c];
+    Jet e{dv, (mv && c == ax) ? 1.0 : 0.0, 0.0};
+    q = jadd(q, jmul(e, e));
+  }
+  Jet r = jsqrt(q);
+  return jinv({1.0 + kappa * r.v, kappa * r.d, kappa * r.dd});
+}
+
+// sum over the terms of nucleus alpha for one pair: a = Rbar(r_ij),
+// b = Rbar(r_ia), c = Rbar(r_ja); coefficients cf[t]
+template <class T>
+void een_pair(const std::vector<EenTerm>& terms, Jet a, Jet b, Jet c, const T* cf, T& v, T& d, T& dd) {
+  Jet bc = jmul(b, c);
+  for (size_t t = 0; t < terms.size(); ++t) {
+    const EenTerm& e = terms[t];
+    Jet f = jmul(jmul(jpow(a, e.k), jadd(jpow(b, e.l), jpow(c, e.l))), jpow(bc, e.m));
+    v = v + cf[t] * f.v;
+    d = d + cf[t] * f.d;
+    dd = dd + cf[t] * f.dd;
+  }
+}
+
+// f_een of the configuration (U), and per electron its gradient and
+// Laplacian (added into gU, lU) when want_derivs.
+template <class T>
+void een_all(const System& s, const T* cf, const double* R, bool want_derivs, T& U, std::vector<T>& gU,
+             std::vector<T>& lU) {
+  const std::vector<EenTerm> terms = een_terms();
+  const int nt = (int)terms.size(), N = s.N;
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j)
+      for (int a = 0; a < s.nnuc; ++a) {
+        const double* A = &s.pos[3 * a];
+        Jet ra = rbar_jet(&R[3 * i], &R[3 * j], 0, false, s.kappa);
+        Jet rb = rbar_jet(&R[3 * i], A, 0, false, s.kappa);
+        Jet rc = rbar_jet(&R[3 * j], A, 0, false, s.kappa);
+        T v = T(0.0), d = T(0.0), dd = T(0.0);
+        een_pair(terms, ra, rb, rc, cf + nt * a, v, d, dd);
+        U = U + v;
+      }
+  if (!want_derivs) return;
+  // derivatives in electron i: every pair (i, j), j != i, each nucleus
+  for (int i = 0; i < N; ++i)
+    for (int ax = 0; ax < 3; ++ax) {
+      T d = T(0.0), dd = T(0.0);
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        for (int a = 0; a < s.nnuc; ++a) {
+          const double* A = &s.pos[3 * a];
+          Jet ra = rbar_jet(&R[3 * i], &R[3 * j], ax, true, s.kappa);
+          Jet rb = rbar_jet(&R[3 * i], A, ax, true, s.kappa);
+          Jet rc = rbar_jet(&R[3 * j], A, ax, false, s.kappa);
+          T v = T(0.0);
+          een_pair(terms, ra, rb, rc, cf + nt * a, v, d, dd);
+        }
+      }
+      gU[3 * i + ax] = gU[3 * i + ax] + d;
+      lU[i] = lU[i] + dd;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Full evaluation of one configuration.
 // level 0: ln|Psi| and sign; 1: + gradient; 2: + local energy.
 // ---------------------------------------------------------------------------
@@ -425,6 +538,7 @@ EvalOut<T> evaluate(const System& s, const Params<T>& P, const double* R, int le
       lU[j] = lU[j] + u2 + u1 * (2.0 / r);
     }
   }
+  if (s.een) een_all(s, &P.jas[6 + 6 * s.nnuc], R, level >= 1, U, gU, lU);
   o.logabs = U + Lmax + log_abs(Dt);
   o.sign = val(Dt) > 0 ? 1 : -1;
   if (level == 0) return o;
@@ -567,7 +681,8 @@ void* orc_create(int nnuc, const double* Z, const double* pos, int nup, int ndn,
                  int nstruct, const double* c, int nterm, const int* term_struct,
                  const int* term_counts, const int* term_orbs,
                  double kappa, const double* ee /* a_anti, a_par, b_anti, b_par, b3..b6 */,
-                 const double* en /* per nucleus a1..a6 */) {
+                 const double* en /* per nucleus a1..a6 */,
+                 const double* een /* per nucleus the f_een coefficients in term order, or NULL */) {
   System* s = new System();
   s->nnuc = nnuc;
   s->Z.assign(Z, Z + nnuc);
@@ -606,6 +721,12 @@ void* orc_create(int nnuc, const double* Z, const double* pos, int nup, int ndn,
   for (int k = 2; k < 8; ++k) s->jas.push_back(ee[k]);
   for (int a = 0; a < nnuc; ++a)
     for (int k = 0; k < 6; ++k) s->jas.push_back(en[6 * a + k]);
+  if (een) {
+    const int nt = (int)een_terms().size();
+    s->een = true;
+    for (int a = 0; a < nnuc; ++a)
+      for (int t = 0; t < nt; ++t) s->jas.push_back(een[nt * a + t]);
+  }
   s->njas = (int)s->jas.size();
   return s;
 }
@@ -615,6 +736,17 @@ void orc_destroy(void* h) { delete (System*)h; }
 int orc_num_dets(void* h) { return (int)((System*)h)->dets.size(); }
 int orc_num_params(void* h) { return ((System*)h)->nparam(); }
 int orc_max_threads() { return max_threads(); }
+
+// the f_een term list: (k, l, m) per term, returns the count
+int orc_een_terms(int* klm) {
+  std::vector<EenTerm> t = een_terms();
+  for (size_t q = 0; q < t.size(); ++q) {
+    klm[3 * q] = t[q].k;
+    klm[3 * q + 1] = t[q].l;
+    klm[3 * q + 2] = t[q].m;
+  }
+  return (int)t.size();
+}
 
 // determinant list: structure[k], up[k*nup..], dn[k*ndn..]
 void orc_dets(void* h, int* structure, int* up, int* dn) {

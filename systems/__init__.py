@@ -22,7 +22,8 @@ A system is a plain dict:
                   (a structure is the unit-weight sum of its HLSP terms)
     jastrow     : {"kappa", "ee": {"a_anti", "a_par", "b_anti", "b_par",
                   "poly": [b3, b4, b5, b6]},
-                  "en": [{"a1", "a2", "poly": [a3, a4, a5, a6]} per nucleus]}
+                  "en": [{"a1", "a2", "poly": [a3, a4, a5, a6]} per nucleus],
+                  optional "een": [[c_1 .. c_23] per nucleus] (f_een terms)}
 
 Each generator's docstring gives its recipe (seed, distributions, shapes).
 """
@@ -31,6 +32,8 @@ from .generate import (  # noqa: F401
     h2_heitler_london,
     f2_shaped,
     f2_bovb,
+    with_een,
+    N_EEN_TERMS,
     precision_molecule,
     adjoint_molecule,
     dmc_molecule,

@@ -211,6 +211,26 @@ def f2_bovb(seed=1001, breathing=0.3):
     return {**base, "name": "f2_bovb", "lam": lam.tolist(), "structures": structures}
 
 
+# terms of the f_een expansion per nucleus (Sec. 2.1: p = 2..5 with the
+# paper's l_max and integer-m rules)
+N_EEN_TERMS = 23
+
+
+def with_een(system, seed=2207, scale=0.05, kappa=0.8):
+    """The system with an f_een three-body Jastrow: per chemical element
+    N_EEN_TERMS coefficients ~ N(0, scale^2), shared by the nuclei of that
+    element (Sec. 2.1), in the term order of the library's f_een
+    coefficients; kappa set to the paper's 0.8 where it was 0."""
+    rng = np.random.default_rng(seed)
+    Z = system["nuclei"]["Z"]
+    per_z = {z: (scale * rng.normal(size=N_EEN_TERMS)).tolist() for z in sorted(set(Z))}
+    jas = dict(system["jastrow"])
+    if jas["kappa"] == 0.0:
+        jas["kappa"] = kappa
+    jas["een"] = [list(per_z[z]) for z in Z]
+    return {**system, "name": system["name"] + "_een", "jastrow": jas}
+
+
 def _molecule(seed, name, n_nuc, zchoices, ztotal, side, shell_spec, n_inactive,
               n_active_per_atom, active_atoms, struct_counts, jastrow_kind,
               delocal_sigma=0.1, active_perturb=0.0, max_exponent=1e4):
