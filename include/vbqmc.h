@@ -77,6 +77,17 @@ typedef struct {
  *   u(r) = a R/(1 + b R) + sum_{p=2..5} q_p R^p,  R = r/(1 + kappa r),
  * ee = {a_anti, a_par, b_anti, b_par, b3, b4, b5, b6} (a fixed by the cusp
  * conditions), en = [n_nuclei][6] = {a1, a2, a3, a4, a5, a6}.
+ * een (optional, NULL for none): the three-body term f_een, per nucleus 23
+ * coefficients c_t; term t adds, for every electron pair i < j,
+ *   c_t Rbar_ij^k (Rbar_ia^l + Rbar_ja^l) (Rbar_ia Rbar_ja)^m,  Rbar = 1/(1 + kappa r),
+ * with (k, l, m) taken over p = k + l + 2m = 2..5, k < p, l <= p - k
+ * (p - k - 2 when k = 0), ordered by p, then k, then l.  Element sharing and
+ * the cusp-preserving constraints among the c_t are the caller's.  With
+ * f_een, single-electron VMC and DMC run only on the walker-resident kernel
+ * (step_kernel / dmc_kernel 3; EINVAL at create for another choice, and at
+ * the call when the system does not fit it), vbqmc_vmc_sweep,
+ * vbqmc_vmc_measure and S_IJ sums (sij_sum) are EINVAL, and all-electron
+ * VMC, evaluation and the parameter derivatives take it everywhere.
  */
 typedef struct {
   int32_t n_shells;
@@ -97,6 +108,7 @@ typedef struct {
   double kappa;
   double ee[8];
   const double* en;              /* [host] [n_nuclei][6] */
+  const double* een;             /* [host] [n_nuclei][23] or NULL */
 } vbqmc_wavefunction;
 
 /* precision: VBQMC_FP64 (all FP64), VBQMC_FP32 or VBQMC_BF16 (basis values
@@ -160,7 +172,7 @@ typedef struct {
   int32_t n_determinants;        /* distinct (up, down) determinant pairs */
   int32_t n_unique_up, n_unique_dn; /* distinct spin determinants */
   int32_t n_table_up, n_table_dn;   /* orbitals replacing reference columns */
-  int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei */
+  int32_t n_params;              /* n_structures + n_orbitals*n_basis + 6 + 6*n_nuclei (+ 23*n_nuclei with f_een) */
   int32_t block_threads;         /* threads per walker in the walker kernels */
   int32_t sweep_lanes;           /* lanes per walker in the single-electron sweep */
   int32_t step_kernel;           /* kernel of single-electron VMC steps (vbqmc_options) */

@@ -44,7 +44,8 @@ class _Wavefunction(ctypes.Structure):
                 ("term_structure", ctypes.POINTER(ctypes.c_int32)),
                 ("term_counts", ctypes.POINTER(ctypes.c_int32)),
                 ("term_orbitals", ctypes.POINTER(ctypes.c_int32)), ("kappa", ctypes.c_double),
-                ("ee", ctypes.c_double * 8), ("en", ctypes.POINTER(ctypes.c_double))]
+                ("ee", ctypes.c_double * 8), ("en", ctypes.POINTER(ctypes.c_double)),
+                ("een", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Options(ctypes.Structure):
@@ -210,9 +211,15 @@ class Context:
         ee_arr = (ctypes.c_double * 8)(ee["a_anti"], ee["a_par"], ee["b_anti"], ee["b_par"], *ee["poly"])
         en = keep(np.ascontiguousarray([[e["a1"], e["a2"]] + list(e["poly"]) for e in jas["en"]],
                                        np.float64).reshape(-1))
+        # f_een coefficients [n_nuclei][23] in the library's term order, or none
+        een = None
+        if jas.get("een") is not None:
+            een = keep(np.ascontiguousarray(jas["een"], np.float64))
+            if een.shape != (len(Z), 23):
+                raise ValueError("jastrow een: one row of 23 coefficients per nucleus")
         wfc = _Wavefunction(len(sh), _ip(cen), _ip(kind), _ip(ls), _ip(npr), _dp(pe), _dp(pc), lam.shape[0],
                             _dp(lam), len(st), _dp(c), len(ts), _ip(ts), _ip(tc), _ip(to), float(jas["kappa"]),
-                            ee_arr, _dp(en))
+                            ee_arr, _dp(en), None if een is None else _dp(een))
         opt = _Options(_PREC[precision] if isinstance(precision, str) else int(precision), int(refresh_every),
                        int(walker_lanes), int(step_kernel), int(dmc_kernel))
         h = ctypes.c_void_p()

@@ -112,6 +112,98 @@ __device__ __forceinline__ double pair_val(double r, double kappa, const PairCoe
 }
 
 // ---------------------------------------------------------------------------
+// Three-body Jastrow f_een (Sec. 2.1).  Term t of nucleus alpha adds, for
+// every electron pair i < j,
+//   c_t Rbar_ij^k (Rbar_ia^l + Rbar_ja^l) (Rbar_ia Rbar_ja)^m,  Rbar(r) = 1/(1 + kappa r),
+// over the (k, l, m) with p = k + l + 2m from 2 to 5, k < p and l at most
+// p - k (p - k - 2 when k = 0), listed by p, then k, then l.
+// ---------------------------------------------------------------------------
+constexpr int kEenK[kEenTerms] = {0, 1, 0, 1, 1, 2, 0, 0, 1, 1, 2, 2, 3, 0, 0, 1, 1, 1, 2, 2, 3, 3, 4};
+constexpr int kEenL[kEenTerms] = {0, 1, 1, 0, 2, 1, 0, 2, 1, 3, 0, 2, 1, 1, 3, 0, 2, 4, 1, 3, 0, 2, 1};
+constexpr int kEenM[kEenTerms] = {1, 0, 1, 1, 0, 0, 2, 1, 1, 0, 1, 0, 0, 2, 1, 2, 1, 0, 1, 0, 1, 0, 0};
+
+// One (i, j, alpha) triple: F = sum_t c_t a^k B_t with a = Rbar_ij,
+// B_t = b^(l+m) c^m + b^m c^(l+m), b = Rbar_ia, c = Rbar_ja, and (DERIV) its
+// first and second partial derivatives in a and b (c does not depend on
+// electron i).  cf: the 23 coefficients of nucleus alpha.
+struct EenTriple {
+  double F, Fa, Fb, Faa, Fbb, Fab;
+};
+
+template <bool DERIV>
+__device__ __forceinline__ EenTriple een_triple(const double* __restrict__ cf, double a, double b, double c) {
+  double pa[5], pb[6], pc[6];
+  pa[0] = pb[0] = pc[0] = 1.0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q) {
+    if (q < 5) pa[q] = pa[q - 1] * a;
+    pb[q] = pb[q - 1] * b;
+    pc[q] = pc[q - 1] * c;
+  }
+  EenTriple o = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kEenTerms; ++t) {
+    const int k = kEenK[t], l = kEenL[t], m = kEenM[t], n = l + m;
+    const double ct = cf[t];
+    const double B = pb[n] * pc[m] + pb[m] * pc[n];
+    o.F += ct * pa[k] * B;
+    if (DERIV) {
+      const double B1 = (n > 0 ? n * pb[n > 0 ? n - 1 : 0] * pc[m] : 0.0) +
+                        (m > 0 ? m * pb[m > 0 ? m - 1 : 0] * pc[n] : 0.0);
+      const double B2 = (n > 1 ? n * (n - 1) * pb[n > 1 ? n - 2 : 0] * pc[m] : 0.0) +
+                        (m > 1 ? m * (m - 1) * pb[m > 1 ? m - 2 : 0] * pc[n] : 0.0);
+      const double A1 = k > 0 ? k * pa[k > 0 ? k - 1 : 0] : 0.0;
+      const double A2 = k > 1 ? k * (k - 1) * pa[k > 1 ? k - 2 : 0] : 0.0;
+      o.Fa += ct * A1 * B;
+      o.Faa += ct * A2 * B;
+      o.Fb += ct * pa[k] * B1;
+      o.Fbb += ct * pa[k] * B2;
+      o.Fab += ct * A1 * B1;
+    }
+  }
+  return o;
+}
+
+// f_een of electron i with one partner electron j, summed over the nuclei
+// (nuc: [nnuc][4] x, y, z, Z): MODE 0 the value; 1 also the gradient in r_i;
+// 2 also the Laplacian in r_i.  With a(r) = Rbar(r): a' = -kappa a^2,
+// a'' = 2 kappa^2 a^3, grad_i a = a' d/|d| (d = r_i - r_j), lap_i a =
+// a'' + 2 a'/|d|, and likewise b with e = r_i - R_alpha; the Laplacian of F
+// adds the cross term 2 F_ab a' b' (d . e)/(|d| |e|).
+template <int MODE>
+__device__ __forceinline__ void een_partner(const DevWF& wf, const double* nuc, double xi, double yi, double zi,
+                                            double xj, double yj, double zj, double& u, double* g, double& lap) {
+  const double kap = wf.kappa;
+  const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  const double rij = sqrt(dx * dx + dy * dy + dz * dz), irij = 1.0 / rij;
+  const double a = 1.0 / (1.0 + kap * rij), a1 = -kap * a * a, a2 = 2.0 * kap * kap * a * a * a;
+#pragma unroll 1
+  for (int al = 0; al < wf.nnuc; ++al) {
+    const double* A = nuc + 4 * al;
+    const double ex = xi - A[0], ey = yi - A[1], ez = zi - A[2];
+    const double fx = xj - A[0], fy = yj - A[1], fz = zj - A[2];
+    const double ria = sqrt(ex * ex + ey * ey + ez * ez), iria = 1.0 / ria;
+    const double b = 1.0 / (1.0 + kap * ria);
+    const double c = 1.0 / (1.0 + kap * sqrt(fx * fx + fy * fy + fz * fz));
+    const EenTriple T = een_triple<MODE >= 1>(wf.een + kEenTerms * al, a, b, c);
+    u += T.F;
+    if (MODE >= 1) {
+      const double b1 = -kap * b * b;
+      const double sa = T.Fa * a1 * irij, sb = T.Fb * b1 * iria;
+      g[0] += sa * dx + sb * ex;
+      g[1] += sa * dy + sb * ey;
+      g[2] += sa * dz + sb * ez;
+      if (MODE >= 2) {
+        const double b2 = 2.0 * kap * kap * b * b * b;
+        const double cosde = (dx * ex + dy * ey + dz * ez) * irij * iria;
+        lap += T.Faa * a1 * a1 + T.Fa * (a2 + 2.0 * a1 * irij) + T.Fbb * b1 * b1 + T.Fb * (b2 + 2.0 * b1 * iria) +
+               2.0 * T.Fab * a1 * b1 * cosde;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // basis functions: radial sums and the angular set
 // ---------------------------------------------------------------------------
 // e^{-t}, t >= 0, by Tang's table-driven method (ACM TOMS 15, 1989): with
@@ -1058,6 +1150,14 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
       gx += f * dx; gy += f * dy; gz += f * dz;
       lap += u2 + 2.0 * f;
       Vi += 0.5 * ir;
+      if (wf.neen) {
+        // f_een of the pair (i, j) with every nucleus (each pair seen twice)
+        double ue = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
+        een_partner<2>(wf, nuc, xi, yi, zi, Rsrc[3 * j], Rsrc[3 * j + 1], Rsrc[3 * j + 2], ue, ge, le);
+        Ui += 0.5 * ue;
+        gx += ge[0]; gy += ge[1]; gz += ge[2];
+        lap += le;
+      }
     }
     l.gU()[3 * i] = gx; l.gU()[3 * i + 1] = gy; l.gU()[3 * i + 2] = gz;
     l.lU()[i] = lap;

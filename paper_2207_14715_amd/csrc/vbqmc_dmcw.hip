@@ -663,7 +663,10 @@ __device__ bool dw_refresh_ns(double* Wm, const double* vrow, int WD, int n, int
 // uniform-cube proposal r' = r + s (2u - 1) per component, accepted iff
 // u' < |Psi'/Psi|^2 (no drift, no node rejection, no weight), E_L added to
 // the walker's VMC accumulators (vm; ctrl, tau, br and nacc unused).
-template <int NC, int XE, int LK, bool VMC>
+// EEN: the Jastrow factor has the three-body term f_een (its value, the
+// gradient of the moving electron and, in E_L, every electron's gradient and
+// Laplacian; coefficients read from global memory).
+template <int NC, int XE, int LK, bool VMC, bool EEN>
 __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dmcw(const DevWF* __restrict__ pwf, double* state, const double* ctrl,
                                                 uint64_t seed, uint32_t step, double tau, DmcBranch br, double* nacc,
                                                 int prep, DwVmc vm) {
@@ -827,6 +830,12 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
             const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
             double u, u1, u2;
             pair_fn(sqrt(dx * dx + dy * dy + dz * dz), kappa, cf, u, u1, u2);
+            if constexpr (EEN) {
+              if (j < N) {
+                double ge[3], le;
+                een_partner<0>(wf, l.nuc(), xi, yi, zi, xj, yj, zj, u, ge, le);
+              }
+            }
             uo[it] = u;
           }
           if (lane < 3) Pw[6 * g + lane] = Rl[3 * i + lane] + rnd[4 * il + lane];
@@ -874,11 +883,17 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           const double r = sqrt(dx * dx + dy * dy + dz * dz);
           double u, u1, u2;
           pair_fn(r, kappa, cf, u, u1, u2);
-          uo[it] = u;
           const double f = u1 / r;
           part[3] += f * dx;
           part[4] += f * dy;
           part[5] += f * dz;
+          if constexpr (EEN) {
+            if (j < N) {
+              double le;
+              een_partner<1>(wf, l.nuc(), xi, yi, zi, xj, yj, zj, u, part + 3, le);
+            }
+          }
+          uo[it] = u;
         }
         dw_wsum<6>(part);
         if (lane == 0) {
@@ -946,11 +961,17 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           const double rn = sqrt(dx * dx + dy * dy + dz * dz);
           double u, u1, u2;
           pair_fn(rn, kappa, cf, u, u1, u2);
-          part[1] += u - uo[it];
           const double f = u1 / rn;
           jg[0] += f * dx;
           jg[1] += f * dy;
           jg[2] += f * dz;
+          if constexpr (EEN) {
+            if (j < N) {
+              double le;
+              een_partner<VMC ? 0 : 1>(wf, l.nuc(), px, py, pz, xj, yj, zj, u, jg, le);
+            }
+          }
+          part[1] += u - uo[it];
         }
         dw_wsum<2>(part);
         const double rdet = part[0] / S, dU = part[1];
@@ -1196,6 +1217,12 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       jg[2] += f * dz;
       jl += m * (u2 + 2.0 * (u1 * irr));
       jv += m * (wv * irr);
+      if constexpr (EEN) {
+        if (on && j < N) {
+          double ue = 0.0;
+          een_partner<2>(wf, l.nuc(), xi, yi, zi, xj, yj, zj, ue, jg, jl);
+        }
+      }
     }
   }
   // spin 1's columns are in registers after the moves: its electrons first
@@ -1297,20 +1324,20 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
     for (int k = lane; k < 3 * N; k += 64) rec[wf.r_R + k] = Rl[k];
 }
 
-template <int NC, int XE, int LK, bool VMC>
+template <int NC, int XE, int LK, bool VMC, bool EEN>
 static hipError_t launch_dmcw_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap,
                                 uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc, int prep,
                                 const DwVmc& vm, hipStream_t s) {
   const size_t lds = (size_t)wf.lds_dmcw_doubles * sizeof(double);
   static size_t cur = 0;
   if (lds > cur) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dmcw<NC, XE, LK, VMC>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_dmcw<NC, XE, LK, VMC, EEN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     cur = lds;
   }
   const unsigned blocks = (unsigned)((cap + kDwW - 1) / kDwW);
-  hipLaunchKernelGGL((k_dmcw<NC, XE, LK, VMC>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau,
+  hipLaunchKernelGGL((k_dmcw<NC, XE, LK, VMC, EEN>), dim3(blocks), dim3(kDwNT), lds, s, dwf, state, ctrl, seed, step, tau,
                      br, nacc, prep, vm);
   return hipGetLastError();
 }
@@ -1320,16 +1347,22 @@ static hipError_t launch_dmcw_any(const DevWF& wf, const DevWF* dwf, double* sta
                                   uint64_t seed, uint32_t step, double tau, const DmcBranch& br, double* nacc,
                                   int prep, const DwVmc& vm, hipStream_t s) {
   const int kper = wf.Mpad / (4 * kDwW);
-#define VBQMC_DMCW(XE, LK) \
-  return launch_dmcw_t<32, XE, LK, VMC>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, vm, s)
-  if (wf.dw_xe <= 2) {
-    if (kper <= 4) VBQMC_DMCW(2, 4);
-    if (kper <= 8) VBQMC_DMCW(2, 8);
-    VBQMC_DMCW(2, 16);
+#define VBQMC_DMCW(XE, LK, EEN) \
+  return launch_dmcw_t<32, XE, LK, VMC, EEN>(wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, prep, vm, s)
+  if (wf.neen) {
+    // (f_een systems: the three-replaced-column form serves every dw_xe <= 3)
+    if (kper <= 4) VBQMC_DMCW(3, 4, true);
+    if (kper <= 8) VBQMC_DMCW(3, 8, true);
+    VBQMC_DMCW(3, 16, true);
   }
-  if (kper <= 4) VBQMC_DMCW(3, 4);
-  if (kper <= 8) VBQMC_DMCW(3, 8);
-  VBQMC_DMCW(3, 16);
+  if (wf.dw_xe <= 2) {
+    if (kper <= 4) VBQMC_DMCW(2, 4, false);
+    if (kper <= 8) VBQMC_DMCW(2, 8, false);
+    VBQMC_DMCW(2, 16, false);
+  }
+  if (kper <= 4) VBQMC_DMCW(3, 4, false);
+  if (kper <= 8) VBQMC_DMCW(3, 8, false);
+  VBQMC_DMCW(3, 16, false);
 #undef VBQMC_DMCW
 }
 

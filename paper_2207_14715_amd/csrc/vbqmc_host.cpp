@@ -135,7 +135,7 @@ struct vbqmc_ctx {
   int lds_limit = 65536;
   // host copies
   int N = 0, nup = 0, ndn = 0, nnuc = 0, M = 0, Mpad = 0, norb = 0, nop = 0, nstruct = 0, nshell = 0;
-  std::vector<double> nuc, en, pexp, pcoef, lam, c;
+  std::vector<double> nuc, en, een, pexp, pcoef, lam, c;
   std::vector<int> shtab, fnmap, pshell;
   std::vector<unsigned> rsched;  // radial schedules of 64-lane blocks: 4 bins, then 8 bins
   std::vector<unsigned> dw_rs;   // radial schedules of the walker-resident DMC row tiles: 64 bins, then 16
@@ -157,6 +157,7 @@ struct vbqmc_ctx {
   float* d_lamT32 = nullptr;
   uint16_t* d_lamT16 = nullptr;
   double* d_en = nullptr;
+  double* d_een = nullptr;
   double* d_wcoef[2] = {nullptr, nullptr};
   double* d_slc = nullptr;
   DevWF* d_wf = nullptr;
@@ -704,6 +705,7 @@ int upload_coefficients(vbqmc_ctx* x) {
     if (!wc[s].empty()) e = hipMemcpy(x->d_wcoef[s], wc[s].data(), wc[s].size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess && !slc.empty()) e = hipMemcpy(x->d_slc, slc.data(), slc.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(x->d_en, x->en.data(), x->en.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && x->d_een) e = hipMemcpy(x->d_een, x->een.data(), x->een.size() * 8, hipMemcpyHostToDevice);
   for (int k = 0; k < 8; ++k) x->wf.ee[k] = x->ee[k];
   if (e == hipSuccess && x->d_wf) e = hipMemcpy(x->d_wf, &x->wf, sizeof(DevWF), hipMemcpyHostToDevice);
   if (e == hipSuccess && x->d_wf_sweep) {
@@ -922,6 +924,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   x->kappa = wfi->kappa;
   for (int k = 0; k < 8; ++k) x->ee[k] = wfi->ee[k];
   x->en.assign(wfi->en, wfi->en + 6 * x->nnuc);
+  if (wfi->een) x->een.assign(wfi->een, wfi->een + (size_t)kEenTerms * x->nnuc);
 
   // ---- layouts ----
   DevWF& wf = x->wf;
@@ -1130,9 +1133,14 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // kernel of single-electron VMC steps: with no lane count asked for, the
   // row kernel when the system fits it, else the walker-resident kernel when
   // it fits that; else the sweep + local-energy kernels
+  // (f_een: single-electron moves and DMC steps only on the walker-resident
+  // kernel; without a fit the calls report EINVAL)
+  const bool een = !x->een.empty();
   {
     const int req = opt ? opt->step_kernel : 0;
     const int lanes = opt ? opt->walker_lanes : 0;
+    if (een && (req == 1 || req == 2))
+      return bad("f_een: single-electron VMC runs on the walker-resident kernel only (step_kernel 0 or 3)");
     if (req == 2) {
       if (!rows_fit(x)) return bad("step_kernel 2: the system does not fit the row kernel");
       x->step_kernel = 2;
@@ -1142,7 +1150,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     } else if (req == 1) {
       x->step_kernel = 1;
     } else if (req == 0) {
-      x->step_kernel = lanes != 0 ? 1 : rows_fit(x) ? 2 : dmcw_fit(x) ? 3 : 1;
+      if (een) x->step_kernel = dmcw_fit(x) ? 3 : 1;
+      else x->step_kernel = lanes != 0 ? 1 : rows_fit(x) ? 2 : dmcw_fit(x) ? 3 : 1;
     } else {
       return bad("step_kernel must be 0, 1, 2 or 3");
     }
@@ -1152,6 +1161,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // fit a CU in the one-workgroup-per-walker kernel, else that kernel
   {
     const int req = opt ? opt->dmc_kernel : 0;
+    if (een && (req == 1 || req == 2))
+      return bad("f_een: DMC runs on the walker-resident kernel only (dmc_kernel 0 or 3)");
     if (req == 2) {
       if (!dmcb_fit(x)) return bad("dmc_kernel 2: the system does not fit the electron-major DMC kernels");
       x->dmc_kernel = 2;
@@ -1162,6 +1173,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
       x->dmc_kernel = 3;
     } else if (req == 0) {
       if (dmcw_fit(x)) x->dmc_kernel = 3;
+      else if (een) x->dmc_kernel = 1;
       else x->dmc_kernel = (size_t)wf.lds_doubles * 8 > 40960 && dmcb_fit(x) ? 2 : 1;
     } else {
       return bad("dmc_kernel must be 0, 1, 2 or 3");
@@ -1171,7 +1183,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // ---- device tables ----
   size_t bytes = 0;
   auto add = [&](size_t n, size_t sz) { bytes += arena_bytes_for(n, sz); };
-  add(x->nuc.size(), 8); add(x->en.size(), 8); add(x->shtab.size(), 4);
+  add(x->nuc.size(), 8); add(x->en.size(), 8); add(x->een.size(), 8); add(x->shtab.size(), 4);
   add(x->pexp.size(), 8); add(x->pcoef.size(), 8); add(x->pshell.size(), 4); add(x->fnmap.size(), 4);
   add((size_t)x->Mpad * x->nop, 8); add((size_t)x->Mpad * x->nop, 4); add((size_t)x->Mpad * x->nop, 2);
   for (int s = 0; s < 2; ++s) {
@@ -1192,6 +1204,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   };
   double* d_nuc = carve<double>(p, x->nuc.size()); up(x->nuc.data(), x->nuc.size(), 8, d_nuc);
   x->d_en = carve<double>(p, x->en.size());
+  x->d_een = x->een.empty() ? nullptr : carve<double>(p, x->een.size());
   int* d_shtab = carve<int>(p, x->shtab.size()); up(x->shtab.data(), x->shtab.size(), 4, d_shtab);
   double* d_pexp = carve<double>(p, x->pexp.size()); up(x->pexp.data(), x->pexp.size(), 8, d_pexp);
   double* d_pcoef = carve<double>(p, x->pcoef.size()); up(x->pcoef.data(), x->pcoef.size(), 8, d_pcoef);
@@ -1234,6 +1247,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   }
   if (he != hipSuccess) { hipFree(x->dmem); delete x; return VBQMC_EHIP; }
   wf.nuc = d_nuc; wf.en = x->d_en; wf.shtab = d_shtab; wf.pexp = d_pexp;
+  wf.neen = x->een.empty() ? 0 : kEenTerms;
+  wf.een = x->d_een;
   wf.pcoef = d_pcoef; wf.pshell = d_pshell; wf.fnmap = d_fnmap; wf.lamT = x->d_lamT; wf.lamT32 = x->d_lamT32; wf.lamT16 = x->d_lamT16;
   wf.srow = d_srow; wf.slu = d_slu; wf.slc = x->d_slc; wf.timg = x->d_timg;
   if (upload_lambda(x) || upload_coefficients(x)) {
@@ -1260,7 +1275,7 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->n_unique_dn = (int)x->sp[1].sets.size();
   o->n_table_up = (int)x->sp[0].porb.size();
   o->n_table_dn = (int)x->sp[1].porb.size();
-  o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
+  o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc + (int)x->een.size();
   o->block_threads = x->nt;
   o->sweep_lanes = x->sweep_g;
   o->step_kernel = x->step_kernel;
@@ -1283,6 +1298,7 @@ int vbqmc_set_params(vbqmc_ctx* x, const double* p) {
   for (int j = 4; j < 8; ++j) x->ee[j] = p[k++];
   for (int a = 0; a < x->nnuc; ++a)
     for (int j = 0; j < 6; ++j) x->en[6 * a + j] = p[k++];
+  for (double& v : x->een) v = p[k++];
   if (upload_lambda(x)) return VBQMC_EHIP;
   if (upload_coefficients(x)) return VBQMC_EHIP;
   return VBQMC_OK;
@@ -1298,6 +1314,7 @@ int vbqmc_get_params(const vbqmc_ctx* x, double* p) {
   for (int j = 4; j < 8; ++j) p[k++] = x->ee[j];
   for (int a = 0; a < x->nnuc; ++a)
     for (int j = 0; j < 6; ++j) p[k++] = x->en[6 * a + j];
+  for (double v : x->een) p[k++] = v;
   return VBQMC_OK;
 }
 
@@ -1352,6 +1369,7 @@ int vbqmc_vmc_sweep(vbqmc_ctx* x, void* state, int64_t W, uint64_t seed, uint64_
   if (!(step_size > 0) || !std::isfinite(step_size)) return fail(x, VBQMC_EINVAL, "vmc_sweep: bad step size");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_sweep: too many walkers");
   if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_sweep: system too large for the sweep kernels");
+  if (!x->een.empty()) return fail(x, VBQMC_EINVAL, "vmc_sweep: not available with f_een");
   if (W == 0) return VBQMC_OK;
   hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 1,
                                   (double*)state, W, 1, seed, step, step_size, nullptr, nullptr, n_accept, nullptr,
@@ -1363,6 +1381,7 @@ int vbqmc_vmc_measure(vbqmc_ctx* x, void* state, int64_t W, const vbqmc_vmc_acc*
   if (!x || !acc || W < 0 || (W > 0 && !state)) return fail(x, VBQMC_EINVAL, "vmc_measure: bad arguments");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_measure: too many walkers");
   if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_measure: system too large for the local-energy kernels");
+  if (!x->een.empty()) return fail(x, VBQMC_EINVAL, "vmc_measure: not available with f_een");
   if (W == 0) return VBQMC_OK;
   if (!acc->e_sum || !acc->e2_sum || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc_measure: accumulator pointers missing");
@@ -1380,6 +1399,10 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
+  if (!all_electron && !x->een.empty() && (x->step_kernel != 3 || acc->sij_sum))
+    return fail(x, VBQMC_EINVAL,
+                "vmc: with f_een, single-electron moves need the walker-resident kernel (a system that fits it) "
+                "and no S_IJ sums");
   if (!all_electron && x->step_kernel == 2) {
     // single-electron moves and E_L of every step in one row-kernel launch
     hipError_t e = launch_vmc_rows(x->wf, x->d_wf_rows, (double*)state, W, n_steps, seed, step0, step_size,
@@ -1471,6 +1494,8 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
   if (!lg->pop || !lg->wsum || !lg->wesum || !lg->etrial || !lg->n_accept || !lg->n_prop)
     return fail(x, VBQMC_EINVAL, "dmc: log pointers missing");
   int64_t W = *W_io;
+  if (!x->een.empty() && x->dmc_kernel != 3)
+    return fail(x, VBQMC_EINVAL, "dmc: with f_een, DMC needs the walker-resident kernel (a system that fits it)");
   if (W < 1 || W > cap || cap > (int64_t)INT32_MAX || W_target < 1 || !(tau > 0) || n_steps < 0)
     return fail(x, VBQMC_EINVAL, "dmc: bad population, capacity or time step");
   size_t need = 0;

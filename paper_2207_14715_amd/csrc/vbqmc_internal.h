@@ -37,6 +37,10 @@ struct SpinTab {
   const int* omap;       // [nop] per orbital: its reference slot j, or n + its table index q, or -1
 };
 
+// terms per nucleus of the three-body Jastrow f_een (Sec. 2.1: the
+// expansion up to p = 5)
+constexpr int kEenTerms = 23;
+
 // Constant description of the wave function plus layouts, passed by value to
 // every kernel.
 struct DevWF {
@@ -49,6 +53,8 @@ struct DevWF {
   double ee[8];
   const double* nuc;    // [nnuc][4]: x, y, z, Z
   const double* en;     // [nnuc][6]
+  int neen;             // f_een terms per nucleus (kEenTerms), or 0 without f_een
+  const double* een;    // [nnuc][neen] f_een coefficients (global memory)
   const int* shtab;     // [nshell][8]: center, kind, l, first function, first primitive, count, 0, 0
   const double* pexp;
   const double* pcoef;

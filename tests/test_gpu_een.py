@@ -1,0 +1,96 @@
+"""The three-body Jastrow f_een (Sec. 2.1) on the GPU against the oracle:
+evaluation (ln|Psi|, gradient, E_L) of systems with f_een, single-electron
+VMC and DMC walks on the walker-resident kernel, all-electron VMC on the
+one-workgroup-per-walker kernel, and the calls that refuse f_een."""
+
+import numpy as np
+import pytest
+
+import systems as S
+from tests._helpers import compare_evaluate
+from tests.test_gpu_walks import _check_dmc, _check_vmc, _dmc_pair, _vmc_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2207_14715_amd as vb
+    vb.load_library()
+    return vb
+
+
+def _small_een():
+    # (the system of the plain evaluate parity test with seed 102)
+    return S.with_een(S.small_random_system(102, n_inactive=2, n_active=5, n_pairs=2, n_unpaired=1,
+                                            n_structures=4), scale=0.2)
+
+
+@pytest.mark.parametrize("name", ["h2", "small", "f2", "adjoint"])
+def test_evaluate(lib, oracle_mod, name):
+    import torch
+    sysd = {"h2": lambda: S.with_een(S.h2_heitler_london(), scale=0.3), "small": _small_een,
+            "f2": lambda: S.with_een(S.f2_shaped()), "adjoint": lambda: S.with_een(S.adjoint_molecule())}[name]()
+    W = {"h2": 200, "small": 64, "f2": 96, "adjoint": 8}[name]
+    o = oracle_mod.Oracle(sysd)
+    R = S.initial_walkers(sysd, W, seed=102, sigma=0.5)
+    ref = o.evaluate(R)
+    ctx = lib.Context(sysd)
+    assert ctx.n_params == o.n_params
+    print(f"[een evaluate] {sysd['name']} W={W} N={ctx.N}", flush=True)
+    out = ctx.evaluate(torch.from_numpy(R).cuda())
+    torch.cuda.synchronize()
+    compare_evaluate(out, ref, 1e-10)
+
+
+def test_vmc_all_electron_h2(lib, oracle_mod):
+    ref, acc, R, _ = _vmc_pair(lib, oracle_mod, S.with_een(S.h2_heitler_london(), scale=0.3), 128, 20, 0.5, True)
+    _check_vmc(ref, acc, R, 20, oracle_obj=ref["oracle"])
+
+
+@pytest.mark.parametrize("name", ["small", "f2"])
+def test_vmc_walker_resident(lib, oracle_mod, name):
+    # 12 sweeps pass the 32-update refresh on F2 (Newton-Schulz from the
+    # running inverse); 61 / 45 walkers leave a partly filled workgroup
+    sysd = _small_een() if name == "small" else S.with_een(S.f2_shaped())
+    W, steps = (45, 10) if name == "small" else (61, 12)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, W, steps, 0.3, False)
+    assert ctx.info["step_kernel"] == 3
+    _check_vmc(ref, acc, R, steps, oracle_obj=ref["oracle"])
+
+
+def test_vmc_walker_resident_40_electrons(lib, oracle_mod):
+    sysd = S.with_een(S.precision_molecule(), scale=0.02)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, 12, 4, 0.3, False)
+    assert ctx.info["step_kernel"] == 3
+    _check_vmc(ref, acc, R, 4, oracle_obj=ref["oracle"])
+
+
+@pytest.mark.parametrize("name", ["small", "f2"])
+def test_dmc_walker_resident(lib, oracle_mod, name):
+    sysd = _small_een() if name == "small" else S.with_een(S.f2_shaped())
+    W, steps, tau = (64, 5, 0.005) if name == "small" else (45, 3, 0.002)
+    ref, out, R = _dmc_pair(lib, oracle_mod, sysd, W, steps, tau, dmc_kernel=3, et_median=True)
+    _check_dmc(ref, out, R, ref["e_rec"], ref["oracle"])
+
+
+def test_paths_without_f_een_refuse_it(lib):
+    import torch
+    sysd = S.with_een(S.f2_shaped())
+    for kw in ({"step_kernel": 1}, {"step_kernel": 2}, {"dmc_kernel": 1}, {"dmc_kernel": 2}):
+        with pytest.raises(lib.VBQMCError):
+            lib.Context(sysd, **kw)
+    ctx = lib.Context(sysd)
+    W = 8
+    st = ctx.walkers_init(torch.from_numpy(S.initial_walkers(sysd, W, seed=1)).cuda())
+    acc = ctx.new_vmc_acc(W)
+    with pytest.raises(lib.VBQMCError):
+        ctx.vmc_sweep(st, 1, 0, 0.3, acc["n_accept"])
+    with pytest.raises(lib.VBQMCError):
+        ctx.vmc_measure(st, acc)
+    with pytest.raises(lib.VBQMCError):
+        ctx.vmc_advance(st, 1, 1, 0, 0.3, False, acc=ctx.new_vmc_acc(W, sij=True))
+    torch.cuda.synchronize()
