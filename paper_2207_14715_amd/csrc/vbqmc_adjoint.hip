@@ -319,7 +319,7 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
   __syncthreads();
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN>
 __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf, int64_t W,
                                                    const double* __restrict__ Rin, double* dlog, double* del) {
   const DevWF& wf = *pwf;
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   Ld l(lds_adj, wf);
   stage_tables<NT, PREC>(wf, l);
   const int N = wf.N, nop = wf.nop, M = wf.M;
-  const int np = wf.nstruct + wf.norb * M + 6 + 6 * wf.nnuc;
+  const int np = wf.nstruct + wf.norb * M + 6 + 6 * wf.nnuc + wf.neen * wf.nnuc;
   double* oL = dlog + w * np;
   double* oE = del + w * np;
   for (int k = threadIdx.x; k < 3 * N; k += NT) l.R()[k] = Rin[w * 3 * N + k];
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
     G[idx] = 0.0;
   }
   // B. Jastrow factor, its gradients and Laplacians, potential
-  jastrow_full<NT>(wf, l, l.R());
+  jastrow_full<NT, EEN>(wf, l, l.R());
 
   // C. first pass over the spin determinants: ln|Delta_u|, sign, e_u,
   // through each spin's reference (one inversion per spin); if a reference
@@ -592,6 +592,80 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
       }
     __syncthreads();
   }
+  // f_een coefficients [c_1..c_23] per nucleus: d ln|Psi|/dc_t is the sum
+  // over pairs of term t, T_t = a^k B_t (a = Rbar_ij, B_t = b^(l+m) c^m +
+  // b^m c^(l+m), b = Rbar_ia, c = Rbar_ja); d E_L/dc_t =
+  // -1/2 sum_i (lap_i T_t + 2 grad_i T_t . grad_i ln|Psi|), each ordered
+  // pair (i, j) giving electron i's derivatives (and half the value)
+  if constexpr (EEN) {
+    const int je = jb + 6 + 6 * wf.nnuc;
+    const double kap = wf.kappa;
+    for (int al = 0; al < wf.nnuc; ++al) {
+      double acc[2 * kEenTerms];
+#pragma unroll
+      for (int k = 0; k < 2 * kEenTerms; ++k) acc[k] = 0.0;
+      const double* nu = l.nuc() + 4 * al;
+      for (int i = threadIdx.x; i < N; i += NT) {
+        const double* Ri = l.R() + 3 * i;
+        const double ex = Ri[0] - nu[0], ey = Ri[1] - nu[1], ez = Ri[2] - nu[2];
+        const double ria = sqrt(ex * ex + ey * ey + ez * ez), iria = 1.0 / ria;
+        const double b = 1.0 / (1.0 + kap * ria), b1 = -kap * b * b, b2 = 2.0 * kap * kap * b * b * b;
+        const double* gi = l.gU() + 3 * i;
+        const double* di = l.gD() + 3 * i;
+        const double G0 = gi[0] + di[0], G1 = gi[1] + di[1], G2 = gi[2] + di[2];
+        const double eG = (ex * G0 + ey * G1 + ez * G2) * iria;
+        for (int j = 0; j < N; ++j) {
+          if (j == i) continue;
+          const double* Rj = l.R() + 3 * j;
+          const double dx = Ri[0] - Rj[0], dy = Ri[1] - Rj[1], dz = Ri[2] - Rj[2];
+          const double rij = sqrt(dx * dx + dy * dy + dz * dz), irij = 1.0 / rij;
+          const double a = 1.0 / (1.0 + kap * rij), a1 = -kap * a * a, a2 = 2.0 * kap * kap * a * a * a;
+          const double fx = Rj[0] - nu[0], fy = Rj[1] - nu[1], fz = Rj[2] - nu[2];
+          const double c = 1.0 / (1.0 + kap * sqrt(fx * fx + fy * fy + fz * fz));
+          const double dG = (dx * G0 + dy * G1 + dz * G2) * irij;
+          const double cosde = (dx * ex + dy * ey + dz * ez) * irij * iria;
+          double pa[5], pb[6], pc[6];
+          pa[0] = pb[0] = pc[0] = 1.0;
+#pragma unroll
+          for (int q = 1; q < 6; ++q) {
+            if (q < 5) pa[q] = pa[q - 1] * a;
+            pb[q] = pb[q - 1] * b;
+            pc[q] = pc[q - 1] * c;
+          }
+#pragma unroll
+          for (int t = 0; t < kEenTerms; ++t) {
+            const int k = kEenK[t], m = kEenM[t], n = kEenL[t] + m;
+            const double B = pb[n] * pc[m] + pb[m] * pc[n];
+            const double B1 = (n > 0 ? n * pb[n > 0 ? n - 1 : 0] * pc[m] : 0.0) +
+                              (m > 0 ? m * pb[m > 0 ? m - 1 : 0] * pc[n] : 0.0);
+            const double B2 = (n > 1 ? n * (n - 1) * pb[n > 1 ? n - 2 : 0] * pc[m] : 0.0) +
+                              (m > 1 ? m * (m - 1) * pb[m > 1 ? m - 2 : 0] * pc[n] : 0.0);
+            const double A1 = k > 0 ? k * pa[k > 0 ? k - 1 : 0] : 0.0;
+            const double A2 = k > 1 ? k * (k - 1) * pa[k > 1 ? k - 2 : 0] : 0.0;
+            const double gT = A1 * B * a1 * dG + pa[k] * B1 * b1 * eG;
+            const double lT = A2 * B * a1 * a1 + A1 * B * (a2 + 2.0 * a1 * irij) + pa[k] * B2 * b1 * b1 +
+                              pa[k] * B1 * (b2 + 2.0 * b1 * iria) + 2.0 * A1 * B1 * a1 * b1 * cosde;
+            acc[t] += 0.5 * pa[k] * B;
+            acc[kEenTerms + t] += -0.5 * (lT + 2.0 * gT);
+          }
+        }
+      }
+      // (reduced 16 at a time: the reduction scratch holds 64 doubles)
+      for (int q0 = 0; q0 < 2 * kEenTerms; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = q0 + k < 2 * kEenTerms ? acc[min(q0 + k, 2 * kEenTerms - 1)] : 0.0;
+        block_sum<NT, 16>(v, l.red());
+        if (threadIdx.x == 0)
+          for (int k = 0; k < 16 && q0 + k < 2 * kEenTerms; ++k) {
+            const int q = q0 + k;
+            if (q < kEenTerms) oL[je + kEenTerms * al + q] = v[k];
+            else oE[je + kEenTerms * al + q - kEenTerms] = v[k];
+          }
+      }
+      __syncthreads();
+    }
+  }
 
   // G. orbital-coefficient derivatives: contractions over electrons on MFMA,
   // one 16 (orbital) x 16 (basis function) output tile per wave at a time
@@ -649,14 +723,14 @@ size_t param_grad_ws_doubles(const DevWF& wf, int64_t W) {
   return 0;
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_pg(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, double* dl, double* de,
                             hipStream_t s) {
   size_t lds = (size_t)wf.lds_adj_doubles * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_param_grad<NT, PREC>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_param_grad<NT, PREC, EEN>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_param_grad<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, dl, de);
+  hipLaunchKernelGGL((k_param_grad<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, dl, de);
   return hipGetLastError();
 }
 
@@ -666,6 +740,12 @@ hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t 
   (void)ws_doubles;
   // the adjoint runs its determinant algebra and contractions in FP64 for
   // every precision form; the orbital rows follow the context's precision
+  // (f_een systems are FP64 only)
+  if (wf.neen) {
+    if (nt == 64) return launch_pg<64, 0, true>(wf, dwf, W, R, dlogpsi, deloc, s);
+    if (nt == 128) return launch_pg<128, 0, true>(wf, dwf, W, R, dlogpsi, deloc, s);
+    return launch_pg<256, 0, true>(wf, dwf, W, R, dlogpsi, deloc, s);
+  }
   if (nt == 64) {
     if (wf.precision == 0) return launch_pg<64, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
     return launch_pg<64, 1>(wf, dwf, W, R, dlogpsi, deloc, s);

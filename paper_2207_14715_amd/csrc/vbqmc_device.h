@@ -1118,9 +1118,10 @@ __device__ bool build_state(const DevWF& wf, const Ld& l, const double* Rsrc, do
 }
 
 // ---------------------------------------------------------------------------
-// Jastrow factor and potential for all electrons: U, grad_i U, lap_i U, V.
+// Jastrow factor and potential for all electrons: U, grad_i U, lap_i U, V
+// (EEN: with the three-body term f_een).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, bool EEN = false>
 __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
   double part[2] = {0.0, 0.0};  // U, V
   const double* nuc = l.nuc();
@@ -1150,7 +1151,7 @@ __device__ void jastrow_full(const DevWF& wf, const Ld& l, const double* Rsrc) {
       gx += f * dx; gy += f * dy; gz += f * dz;
       lap += u2 + 2.0 * f;
       Vi += 0.5 * ir;
-      if (wf.neen) {
+      if constexpr (EEN) {
         // f_een of the pair (i, j) with every nucleus (each pair seen twice)
         double ue = 0.0, ge[3] = {0.0, 0.0, 0.0}, le = 0.0;
         een_partner<2>(wf, nuc, xi, yi, zi, Rsrc[3 * j], Rsrc[3 * j + 1], Rsrc[3 * j + 2], ue, ge, le);
@@ -1267,7 +1268,7 @@ __device__ __forceinline__ double row_op_sum(const DevWF& wf, const Ld& l, int s
 // Fills gD, lD, gU, lU and SC_ELOC, SC_LOGPSI, SC_SIGN.  gc (the DMC
 // gradient cache in the walker record) may be null.
 // ---------------------------------------------------------------------------
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 __device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
   const double* R = l.R();
   const double S = l.sc()[SC_S];
@@ -1295,7 +1296,7 @@ __device__ void local_energy(const DevWF& wf, const Ld& l, double* gc) {
       __syncthreads();
     }
   }
-  jastrow_full<NT>(wf, l, R);
+  jastrow_full<NT, EEN>(wf, l, R);
   double part[1] = {0.0};
   for (int i = threadIdx.x; i < wf.N; i += NT) {
     double t = l.lU()[i] + l.lD()[i];

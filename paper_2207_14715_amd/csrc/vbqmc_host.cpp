@@ -1136,6 +1136,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // (f_een: single-electron moves and DMC steps only on the walker-resident
   // kernel; without a fit the calls report EINVAL)
   const bool een = !x->een.empty();
+  if (een && wf.precision != VBQMC_FP64) return bad("f_een: the FP64 form only");
   {
     const int req = opt ? opt->step_kernel : 0;
     const int lanes = opt ? opt->walker_lanes : 0;
@@ -1266,6 +1267,13 @@ void vbqmc_destroy(vbqmc_ctx* ctx) {
   delete ctx;
 }
 
+namespace {
+// [c | lambda | b_anti, b_par, b3..b6 | a1..a6 per nucleus | f_een per nucleus]
+int n_params(const vbqmc_ctx* x) {
+  return x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc + (int)x->een.size();
+}
+}  // namespace
+
 int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   if (!x || !o) return VBQMC_EINVAL;
   o->n_electrons = x->N; o->n_up = x->nup; o->n_dn = x->ndn; o->n_nuclei = x->nnuc;
@@ -1275,7 +1283,7 @@ int vbqmc_get_info(const vbqmc_ctx* x, vbqmc_info_t* o) {
   o->n_unique_dn = (int)x->sp[1].sets.size();
   o->n_table_up = (int)x->sp[0].porb.size();
   o->n_table_dn = (int)x->sp[1].porb.size();
-  o->n_params = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc + (int)x->een.size();
+  o->n_params = n_params(x);
   o->block_threads = x->nt;
   o->sweep_lanes = x->sweep_g;
   o->step_kernel = x->step_kernel;
@@ -1661,7 +1669,7 @@ int vbqmc_lm_accumulate(vbqmc_ctx* x, int64_t W, const double* dlogpsi, const do
   if (!x || W < 0 || !acc || (W > 0 && (!dlogpsi || !deloc || !eloc)))
     return fail(x, VBQMC_EINVAL, "lm_accumulate: bad arguments");
   if (W == 0) return VBQMC_OK;
-  const int P = x->nstruct + x->norb * x->M + 6 + 6 * x->nnuc;
+  const int P = n_params(x);
   hipError_t e = launch_lm_accumulate(P, W, dlogpsi, deloc, eloc, weight, acc, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "lm_accumulate");
 }

@@ -71,7 +71,7 @@ __device__ void store_record(const DevWF& wf, const Ld& l, double* rec) {
 // ---------------------------------------------------------------------------
 extern __shared__ double lds_dyn[];
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
                                                  int64_t rstride, double* logabs, int32_t* sign, double* grad,
                                                  double* eloc, double* ratio, double* state) {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     return;
   }
-  local_energy<NT, PREC>(wf, l, state ? state + w * wf.rec_len + wf.r_gc : nullptr);
+  local_energy<NT, PREC, EEN>(wf, l, state ? state + w * wf.rec_len + wf.r_gc : nullptr);
   if (ratio) structure_ratios<NT>(wf, l);
   double* sc = l.sc();
   if (threadIdx.x == 0) {
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 }
 
 // all-electron Metropolis move (one per step)
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN>
 __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint64_t seed, uint32_t step,
                                   double step_size) {
   double* sc = l.sc();
@@ -155,7 +155,7 @@ __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint6
   bool accept = false;
   if (ok) {
     compute_RWS<NT>(wf, l);
-    jastrow_full<NT>(wf, l, l.R());
+    jastrow_full<NT, EEN>(wf, l, l.R());
     if (sc[SC_S] != 0.0) {
       double new_log = sc[SC_U] + sc[SC_LOGDET0] + sc[SC_LOGDET1] + log(fabs(sc[SC_S]));
       accept = ua < exp(2.0 * (new_log - old_log));
@@ -181,7 +181,7 @@ __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint6
   return accept;
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_vmc(const DevWF* __restrict__ pwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                             uint64_t step0, double step_size, int all_electron, double* e_sum,
                                             double* e2_sum, double* n_acc, double* e_last, double* sij_sum) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   load_record<NT>(wf, l, rec);
   compute_RWS<NT>(wf, l);
   double* sc = l.sc();
-  if (all_electron) jastrow_full<NT>(wf, l, l.R());
+  if (all_electron) jastrow_full<NT, EEN>(wf, l, l.R());
   const int nv = wf.nstruct;
   if (sij_sum)
     for (int k = threadIdx.x; k < nv * nv; k += NT) l.sij()[k] = 0.0;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int st = 0; st < nsteps && !bad; ++st) {
     uint32_t step = (uint32_t)(step0 + st);
     if (all_electron) {
-      if (all_electron_move<NT, PREC>(wf, l, w, seed, step, step_size)) na += 1.0;
+      if (all_electron_move<NT, PREC, EEN>(wf, l, w, seed, step, step_size)) na += 1.0;
     } else {
       for (int i = 0; i < wf.N; ++i) {
         double a0, a1, b0, b1;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       }
     }
     if (!(sc[SC_S] != 0.0)) { bad = true; break; }
-    local_energy<NT, PREC>(wf, l, nullptr);
+    local_energy<NT, PREC, EEN>(wf, l, nullptr);
     double el = sc[SC_ELOC];
     es += el;
     e2s += el * el;
@@ -866,26 +866,26 @@ static hipError_t set_lds(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, int64_t rstride,
                                     double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio,
                                     double* state, hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
-  hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC>, lds);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_evaluate<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, rstride, logabs, sign, grad,
+  hipLaunchKernelGGL((k_evaluate<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, rstride, logabs, sign, grad,
                      eloc, ratio, state);
   return hipGetLastError();
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                uint64_t step0, double step_size, int all_e, double* es, double* e2s,
                                double* na, double* el, double* sij, hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
-  hipError_t e = set_lds<NT, PREC>((const void*)k_vmc<NT, PREC>, lds);
+  hipError_t e = set_lds<NT, PREC>((const void*)k_vmc<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_vmc<NT, PREC>), dim3((unsigned)W), dim3(NT), lds, s, dwf, state, W, nsteps, seed, step0,
+  hipLaunchKernelGGL((k_vmc<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, state, W, nsteps, seed, step0,
                      step_size, all_e, es, e2s, na, el, sij);
   return hipGetLastError();
 }
@@ -916,15 +916,26 @@ static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* s
     default: VB_DISPATCH(256, FN, __VA_ARGS__)                                 \
   }
 
+// (f_een: FP64 only, its own instantiations)
+#define VB_DISPATCH_EEN(NT, FN, ...)                                           \
+  switch (NT) {                                                                \
+    case 64: return FN<64, 0, true>(__VA_ARGS__);                              \
+    case 128: return FN<128, 0, true>(__VA_ARGS__);                            \
+    default: return FN<256, 0, true>(__VA_ARGS__);                             \
+  }
+
 hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, int64_t rstride,
                            double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio, double* state,
                            hipStream_t s) {
+  if (wf.neen) VB_DISPATCH_EEN(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, s)
   VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, s)
 }
 
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
                       hipStream_t s) {
+  if (wf.neen)
+    VB_DISPATCH_EEN(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
   VB_DISPATCH_NT(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
 }
 

@@ -94,3 +94,50 @@ def test_paths_without_f_een_refuse_it(lib):
     with pytest.raises(lib.VBQMCError):
         ctx.vmc_advance(st, 1, 1, 0, 0.3, False, acc=ctx.new_vmc_acc(W, sij=True))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["small", "f2"])
+def test_parameter_derivatives_all_parameters(lib, oracle_mod, name):
+    """vbqmc_param_grad with f_een: every parameter (the 23 f_een
+    coefficients per nucleus close the vector) against the oracle's dual
+    numbers; the f_een gradient also enters every other dE_L/dp."""
+    from tests.test_gpu_adjoint import _compare
+    sysd = _small_een() if name == "small" else S.with_een(S.f2_shaped())
+    ctx, o, R, dl, de = _compare(lib, oracle_mod, sysd, 6 if name == "small" else 4)
+    assert ctx.n_params == o.n_params == o.param_slices()[2].stop
+
+
+def test_parameter_derivatives_30_electrons(lib, oracle_mod):
+    """The 6-nucleus, 30-electron molecule with f_een: structure coefficients,
+    sampled orbital coefficients and every Jastrow parameter (138 f_een)."""
+    from tests.test_gpu_adjoint import _compare
+    sysd = S.with_een(S.adjoint_molecule(), scale=0.02)
+    o = oracle_mod.Oracle(sysd)
+    cs, ls, js = o.param_slices()
+    rng = np.random.default_rng(1)
+    lam_nz = np.flatnonzero(np.asarray(sysd["lam"]).reshape(-1) != 0) + ls.start
+    idx = np.concatenate([np.arange(cs.start, cs.stop), rng.choice(lam_nz, 30, replace=False),
+                          np.arange(js.start, js.stop)])
+    _compare(lib, oracle_mod, sysd, 2, idx)
+
+
+def test_linear_method_sums_cover_the_een_parameters(lib):
+    """The linear-method accumulator of a system with f_een spans all its
+    parameters: it equals the weighted products of its own inputs."""
+    import torch
+    sysd = _small_een()
+    ctx = lib.Context(sysd)
+    P = ctx.n_params
+    W = 21
+    R = torch.from_numpy(S.initial_walkers(sysd, W, seed=21)).cuda()
+    dl, de = ctx.param_grad(R)
+    el = ctx.evaluate(R, want=("eloc",))["eloc"]
+    acc = ctx.new_lm_acc()
+    ctx.lm_accumulate(dl, de, el, acc)
+    torch.cuda.synchronize()
+    O, D, E = dl.cpu().numpy(), de.cpu().numpy(), el.cpu().numpy()
+    X = np.hstack([np.ones((W, 1)), O])
+    Y = np.hstack([(E * E)[:, None], D])
+    a = acc.cpu().numpy().reshape(3, P + 1, P + 1)
+    for k, ref in enumerate([X.T @ X, (X * E[:, None]).T @ X, X.T @ Y]):
+        assert np.max(np.abs(a[k] - ref)) <= 1e-12 * np.abs(ref).max(), k
