@@ -144,6 +144,10 @@ def main():
     ap.add_argument("--step-kernel", type=int, default=0, choices=[0, 1, 2, 3],
                     help="single-electron step kernel: 0 library choice, 1 sweep + local-energy kernels, "
                          "2 row kernel, 3 walker-resident kernel")
+    ap.add_argument("--een", action="store_true",
+                    help="dmc and vmc forms: add the three-body Jastrow f_een to the workload's wave function")
+    ap.add_argument("--een-scale", type=float, default=0.01,
+                    help="standard deviation of the f_een coefficients (default 0.01)")
     ap.add_argument("--system", default="f2", choices=["f2", "precision"],
                     help="vmc form: the F2-shaped diatomic or the 40-electron molecule of the precision form")
     ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2, 3],
@@ -198,6 +202,8 @@ def vmc_form(args):
     args.warmup = (20 if big else 100) if args.warmup is None else args.warmup
     args.walkers = (16384 if big else 4096) if args.walkers is None else args.walkers
     system = S.precision_molecule() if big else S.f2_shaped()
+    if args.een:
+        system = S.with_een(system, scale=args.een_scale)
     W, step_size = args.walkers, 0.3
     ctx = vb.Context(system, precision=args.precision, walker_lanes=args.walker_lanes,
                      step_kernel=args.step_kernel)
@@ -267,11 +273,13 @@ def vmc_form(args):
     if wres:
         # every launch but the rebuild makes the moves and E_L of one step;
         # the rebuild's work is not counted (steps_launch = spl / (spl + 1))
-        kernel = WRES_VMC_KERNEL
+        kernel = wres_kernel_name(ctx, True) if args.een else WRES_VMC_KERNEL
+        if args.een:
+            sweep_flops += een_flops_per_walker_step(ctx, False) * W
         flops_launch = (sweep_flops + measure_flops) * steps_launch
         t = WRES_VMC_TRAFFIC
         traffic = ((t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024
-                   if (big and W == t["walkers"] and args.precision == "fp64" and
+                   if (big and W == t["walkers"] and args.precision == "fp64" and not args.een and
                        _src_sha("vbqmc_dmcw.hip") == t["src_sha"]) else None)
     elif rows:
         # the dominant (and only) kernel makes moves and E_L of every step
@@ -302,8 +310,10 @@ def vmc_form(args):
         "dtype": _dtype(args.precision),
         "data": "synthetic",
         "config": {"workload": ("40-electron molecule VMC: 10 nuclei (Z in {1,6,7,8}), 20 up + 20 down "
-                                "electrons, 150 Gaussian basis functions, 20 VB structures / 64 determinants, "
-                                f"{W} walkers, single-electron moves of 0.3 bohr with Sherman-Morrison "
+                                "electrons, 150 Gaussian basis functions, 20 VB structures / 64 determinants" +
+                                (f", three-body f_een (23 coefficients per element ~ N(0, {args.een_scale}^2))"
+                                 if args.een else "") +
+                                f", {W} walkers, single-electron moves of 0.3 bohr with Sherman-Morrison "
                                 "updates, E_L every step" if big else
                                 "F2-shaped diatomic VMC: 18 electrons (9 up, 9 down), 28 Gaussian basis "
                                 "functions, 3 VB structures / 4 determinants, 4096 walkers, single-electron "
@@ -510,6 +520,33 @@ def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
     return tot
 
 
+# f_een (Sec. 2.1) cost per (electron i, partner j, nucleus) triple: the
+# powers of the three scaled distances (12) and, per term of the 23, the
+# value (5 FLOP), with the first partial derivatives (14), or with the first
+# and second ones and the chain rule into grad_i and lap_i (26, plus 30)
+EEN_TRIPLE_FLOPS = {"value": 12 + 23 * 5, "grad": 12 + 23 * 14, "lap": 12 + 23 * 26 + 30}
+
+
+def wres_kernel_name(ctx, vmc):
+    """The walker-resident kernel a system with f_een launches: three
+    replaced columns, the k-steps per wave of its basis padded to 16
+    functions (one k-step of four per 16), VMC or DMC form."""
+    kper = -(-ctx.info["n_basis"] // 16)
+    lk = 4 if kper <= 4 else 8 if kper <= 8 else 16
+    return f"k_dmcw<32, 3, {lk}, {'true' if vmc else 'false'}, true>"
+
+
+def een_flops_per_walker_step(ctx, dmc):
+    """f_een FLOPs of one step of one walker on the walker-resident kernel:
+    per move the pair sums of the moving electron at its current point and at
+    the proposal ((N - 1) partners x nuclei triples each, with the gradient
+    for the DMC drift, values only for VMC), and in E_L every electron's
+    gradient and Laplacian (N (N - 1) x nuclei triples)."""
+    N, nn = ctx.N, ctx.info["n_nuclei"]
+    move = EEN_TRIPLE_FLOPS["grad" if dmc else "value"]
+    return 2 * N * (N - 1) * nn * move + N * (N - 1) * nn * EEN_TRIPLE_FLOPS["lap"]
+
+
 def cpu_baseline_dmc(system, walkers=64, steps=5, seed=13):
     """The oracle's DMC (plain FP64 CPU code, OpenMP over walkers, every
     determinant by a fresh LU for every proposal) on a bounded sample of the
@@ -574,8 +611,10 @@ def dmc_form(args):
     import paper_2207_14715_amd as vb
     import systems as S
     system = S.dmc_molecule()
+    if args.een:
+        system = S.with_een(system, scale=args.een_scale)
     W = args.walkers or 32768
-    steps = args.steps if args.steps is not None else 100
+    steps = args.steps if args.steps is not None else (20 if args.een else 100)
     warm = args.warmup if args.warmup is not None else 3
     tau = 0.005
     c64 = vb.Context(system, dmc_kernel=args.dmc_kernel)
@@ -610,11 +649,13 @@ def dmc_form(args):
     step_ms = out["step_ms"]
     nupd_rate = [accept * n / 32.0 for n in (ctx.info["n_up"], ctx.info["n_dn"])]  # refreshes per step per spin
     fl_walker = dmc_flops_per_walker_step(ctx, system, accept, nupd_rate)
+    if args.een:
+        fl_walker += een_flops_per_walker_step(ctx, True)
     flops_launch = fl_walker * float(pop.mean())
     kavg = float(np.mean(step_ms)) / 1e3
     achieved = flops_launch / kavg / 1e12
     traffic = None
-    if (DMCW_TRAFFIC and kern == 3 and args.precision == "fp64" and W == DMCW_TRAFFIC["walkers"] and
+    if (DMCW_TRAFFIC and kern == 3 and args.precision == "fp64" and W == DMCW_TRAFFIC["walkers"] and not args.een and
             _src_sha("vbqmc_dmcw.hip") == DMCW_TRAFFIC["src_sha"]):
         traffic = (DMCW_TRAFFIC["fetch_kib"] * DMCW_TRAFFIC["fetch_factor"] +
                    DMCW_TRAFFIC["write_kib"] * DMCW_TRAFFIC["write_factor"]) * 1024
@@ -633,7 +674,10 @@ def dmc_form(args):
         "data": "synthetic",
         "config": {"workload": "fixed-node DMC of the 64-electron synthetic molecule: 16 nuclei (Z in {1,6,8}), "
                                "32 up + 32 down electrons, 240 Gaussian basis functions, 32 VB structures / 128 "
-                               "determinants, Pade Jastrow, 32768 target walkers, tau = 0.005, per-electron "
+                               "determinants, Pade Jastrow" +
+                               (f" with the three-body f_een (23 coefficients per element ~ N(0, {args.een_scale}^2))"
+                                if args.een else "") +
+                               ", 32768 target walkers, tau = 0.005, per-electron "
                                "drift-diffusion moves, E_L every step, branching with +-10 % population control",
                    "target_walkers": W, "electrons": ctx.N, "precision": args.precision,
                    "dmc_kernel": {1: "workgroup per walker", 2: "electron-major", 3: "walker-resident"}[kern]},
@@ -648,13 +692,15 @@ def dmc_form(args):
         "e_mixed_clipped_blocking_levels": e_clip_levels,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": DMC_KERNEL_NAMES[kern], "kernel_avg_ms_per_launch": kavg * 1e3,
+                     "kernel": wres_kernel_name(ctx, False) if args.een else DMC_KERNEL_NAMES[kern],
+                     "kernel_avg_ms_per_launch": kavg * 1e3,
                      "kernel_share_of_step": float(np.sum(step_ms) / 1e3 / wall),
                      "flops_per_launch": flops_launch, "flops_per_walker_step": fl_walker,
                      "walkers_per_launch": float(pop.mean())},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_dmc(system)
+        # (the oracle's f_een gradients by jets cost about 50x: a smaller sample)
+        line["cpu_baseline"] = cpu_baseline_dmc(system, walkers=32, steps=2) if args.een else cpu_baseline_dmc(system)
     print(json.dumps(line))
 
 
