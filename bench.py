@@ -520,11 +520,12 @@ def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
     return tot
 
 
-# f_een (Sec. 2.1) cost per (electron i, partner j, nucleus) triple: the
-# powers of the three scaled distances (12) and, per term of the 23, the
-# value (5 FLOP), with the first partial derivatives (14), or with the first
-# and second ones and the chain rule into grad_i and lap_i (26, plus 30)
-EEN_TRIPLE_FLOPS = {"value": 12 + 23 * 5, "grad": 12 + 23 * 14, "lap": 12 + 23 * 26 + 30}
+# f_een (Sec. 2.1) cost per (electron i, partner j, nucleus) triple, counted
+# low: the powers of the three scaled distances (12) and, per term of the
+# 23, the value (5 FLOP), with the first partial derivatives in a and b (11)
+# plus the chain rule into grad_i (15), or with the second ones as well (18)
+# plus the chain rule into grad_i and lap_i (30)
+EEN_TRIPLE_FLOPS = {"value": 12 + 23 * 5, "grad": 12 + 23 * 11 + 15, "lap": 12 + 23 * 18 + 30}
 
 
 def wres_kernel_name(ctx, vmc):
