@@ -153,7 +153,7 @@ typedef struct {
  * 3 = walker-resident: one launch per step in which a workgroup keeps four
  * walkers (one per wavefront) for all their moves, refresh, E_L and weight,
  * with the value and gradient orbital rows of each electron's position kept
- * in the walker record (FP64, Gaussian shells, at most 32 electrons and 64
+ * in the walker record (FP64, at most 32 electrons and 64
  * reference slots plus table orbitals per spin, at most 64 orbitals; EINVAL
  * at create otherwise); 0 = 3 when the system fits it, else 2 when one
  * workgroup per walker would need more than 40 KiB of LDS and the system fits

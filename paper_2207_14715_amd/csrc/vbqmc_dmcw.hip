@@ -200,12 +200,15 @@ __device__ __forceinline__ void dw_load_columns(const double* Bg, const double* 
 // ---------------------------------------------------------------------------
 // row tiles
 // ---------------------------------------------------------------------------
-// Radial sums of NPT points for every shell (Gaussian shells only), from the
-// displacement table: MODE 0 stores g = sum c e^{-a r^2} and g1 = dg/d(r^2)
-// per shell (stride 2 nshell + 1 per point), MODE 1 the Laplacian factor
+// Radial sums of NPT points for every shell, from the displacement table:
+// MODE 0 stores g = sum c e^{-a r^2} and g1 = dg/d(r^2) per shell (stride
+// 2 nshell + 1 per point), MODE 1 the Laplacian factor
 // sum c e^{-a r^2} a (4 a r^2 - 2 (2l + 3)), so that the Laplacian of a basis
 // function is its angular polynomial times that factor (stride nshell | 1).
-// Each shell's terms are added in the order of its primitives.
+// A Slater shell (sum c e^{-a r}) stores g1 = sum -a c e^{-a r} / (2r) and the
+// factor sum c e^{-a r} a (a - 2 (l + 1) / r) (the harmonic polynomial P of
+// degree l has lap(P g) = P (g'' + 2 (l + 1) g' / r)).  Each shell's terms
+// are added in the order of its primitives.
 template <int NPT, int MODE>
 __device__ __forceinline__ void dw_radial_plain(const DevWF& wf, const Ld& l) {
 #pragma clang fp contract(off)
@@ -220,18 +223,22 @@ __device__ __forceinline__ void dw_radial_plain(const DevWF& wf, const Ld& l) {
     const int* si = l.sh() + 8 * sh;
     const double r2 = disp[p * ds + 4 * si[0] + 3];
     const int k0 = si[4], nk = si[5];
+    const bool sto = si[1] == 1;
+    const double r = sto ? sqrt(r2) : 0.0, ir = sto ? 1.0 / r : 0.0;
     const double c2l = (double)(2 * (2 * si[2] + 3));
     double g = 0.0, g1 = 0.0;
     for (int k = 0; k < nk; ++k) {
       const double a = l.pe()[k0 + k];
-      const double t = a * r2;
+      const double t = sto ? a * r : a * r2;
       if (t < 50.0) {
         const double ex = l.pc()[k0 + k] * exp_neg<double>(t, etab);
         if constexpr (MODE == 0) {
           g += ex;
-          g1 -= a * ex;
+          if (sto) g1 -= a * ex * (0.5 * ir);
+          else g1 -= a * ex;
         } else {
-          g += ex * a * (4.0 * t - c2l);
+          if (sto) g += ex * a * (a - (double)(2 * (si[2] + 1)) * ir);
+          else g += ex * a * (4.0 * t - c2l);
         }
       }
     }
@@ -253,7 +260,7 @@ __device__ __forceinline__ void dw_radial_plain(const DevWF& wf, const Ld& l) {
 // last store holds the whole sum (padding entries repeat the bin's last shell
 // and add nothing); each shell is still summed in one thread in the order of
 // its primitives, so the sums equal those of dw_radial_plain bit for bit.
-template <int NPT, int MODE>
+template <int NPT, int MODE, bool STO>
 __device__ __forceinline__ void dw_radial_bins(const DevWF& wf, const Ld& l) {
 #pragma clang fp contract(off)
   constexpr int NB = kDwNT / NPT;
@@ -274,16 +281,19 @@ __device__ __forceinline__ void dw_radial_bins(const DevWF& wf, const Ld& l) {
   double d0 = de[4 * nuc(n0) + 3], d1 = de[4 * nuc(n1) + 3];
   int l0 = MODE == 1 ? sht[8 * shl(n0) + 2] : 0, l1 = MODE == 1 ? sht[8 * shl(n1) + 2] : 0;
   double g = 0.0, g1 = 0.0;
-  auto add = [&](double ex, double a, double r2, int lq, unsigned f) {
+  // ir: 1/r of a Slater entry (STO only)
+  auto add = [&](double ex, double a, double r2, double ir, int lq, unsigned f) {
     const bool first = f & kRsFirst;
     if constexpr (MODE == 0) {
       g = (first ? 0.0 : g) + ex;
-      g1 = (first ? 0.0 : g1) - a * ex;
+      if (STO && (f & kRsSto)) g1 = (first ? 0.0 : g1) - a * ex * (0.5 * ir);
+      else g1 = (first ? 0.0 : g1) - a * ex;
       double* q = o + 2 * shl(f);
       q[0] = g;
       q[1] = g1;
     } else {
-      g = (first ? 0.0 : g) + ex * a * (4.0 * (a * r2) - (double)(2 * (2 * lq + 3)));
+      if (STO && (f & kRsSto)) g = (first ? 0.0 : g) + ex * a * (a - (double)(2 * (lq + 1)) * ir);
+      else g = (first ? 0.0 : g) + ex * a * (4.0 * (a * r2) - (double)(2 * (2 * lq + 3)));
       o[shl(f)] = g;
     }
   };
@@ -305,19 +315,35 @@ __device__ __forceinline__ void dw_radial_bins(const DevWF& wf, const Ld& l) {
       l0 = sht[8 * shl(n0) + 2];
       l1 = sht[8 * shl(n1) + 2];
     }
-    const double t0 = A0 * R0, t1 = A1 * R1;
+    double t0 = A0 * R0, t1 = A1 * R1, ir0 = 0.0, ir1 = 0.0;
+    if constexpr (STO) {
+      if (f0 & kRsSto) {
+        const double r = sqrt(R0);
+        t0 = A0 * r;
+        ir0 = 1.0 / r;
+      }
+      if (f1 & kRsSto) {
+        const double r = sqrt(R1);
+        t1 = A1 * r;
+        ir1 = 1.0 / r;
+      }
+    }
     double ex0, ex1;
     exp_neg2<double>(fmin(t0, 64.0), fmin(t1, 64.0), etab, ex0, ex1);
     const double x0 = C0 * ex0, x1 = C1 * ex1;
-    add(((f0 & kRsLive) && t0 < 50.0) ? x0 : 0.0, A0, R0, L0, f0);
-    add(((f1 & kRsLive) && t1 < 50.0) ? x1 : 0.0, A1, R1, L1, f1);
+    add(((f0 & kRsLive) && t0 < 50.0) ? x0 : 0.0, A0, R0, ir0, L0, f0);
+    add(((f1 & kRsLive) && t1 < 50.0) ? x1 : 0.0, A1, R1, ir1, L1, f1);
   }
 }
 
 template <int NPT, int MODE>
 __device__ __forceinline__ void dw_radial(const DevWF& wf, const Ld& l) {
-  if ((NPT == 4 ? wf.dw_rs4_len : wf.dw_rs16_len) > 0) dw_radial_bins<NPT, MODE>(wf, l);
-  else dw_radial_plain<NPT, MODE>(wf, l);
+  if ((NPT == 4 ? wf.dw_rs4_len : wf.dw_rs16_len) > 0) {
+    if (wf.rsched_sto) dw_radial_bins<NPT, MODE, true>(wf, l);
+    else dw_radial_bins<NPT, MODE, false>(wf, l);
+  } else {
+    dw_radial_plain<NPT, MODE>(wf, l);
+  }
 }
 
 // The contraction with lambda^T is split over the basis functions: wavefront

@@ -580,16 +580,14 @@ DevWF dmcw_layout(const vbqmc_ctx* x) {
   return a;
 }
 
-// the walker-resident DMC kernel handles the system: FP64 rows, Gaussian
-// shells, at most 256 (padded) basis functions and 48 (padded) orbitals, at most
+// the walker-resident DMC kernel handles the system: FP64 rows, at most 256
+// (padded) basis functions and 48 (padded) orbitals, at most
 // 32 electrons, 64 reference slots plus table orbitals and 128 distinct
 // determinants per spin, at most 64 (padded) orbitals, spin-up electrons
 // present, and its layout fits the device's LDS
 bool dmcw_fit(const vbqmc_ctx* x) {
   if (x->wf.precision != VBQMC_FP64 || x->wf.trial_prec != VBQMC_FP64 || x->wf.refresh_each_step) return false;
   if (x->nop > 48 || x->Mpad > 256 || x->nup < 1 || x->nup > 32 || x->ndn > 32 || x->N + x->nnuc > 128) return false;
-  for (int sh = 0; sh < x->nshell; ++sh)
-    if (x->shtab[8 * sh + 1] != 0) return false;
   for (int sp = 0; sp < 2; ++sp) {
     if (x->sp[sp].n + (int)x->sp[sp].porb.size() > 64 || x->sp[sp].sets.size() > 128) return false;
   }

@@ -139,13 +139,13 @@ def _f2_with_slater_shells(lmax=1):
     return dict(sysd, shells=shells, name="f2_slater_b")
 
 
-@pytest.mark.parametrize("lanes", ["rows", 32])
+@pytest.mark.parametrize("lanes", ["rows", "wres", 32])
 def test_vmc_f2_with_slater_shells(lib, oracle_mod, lanes):
     ref, acc, R, _ = _vmc_pair(lib, oracle_mod, _f2_with_slater_shells(), 61, 8, 0.3, False, lanes=lanes)
     _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
 
 
-@pytest.mark.parametrize("lanes", ["rows", 32])
+@pytest.mark.parametrize("lanes", ["rows", "wres", 32])
 def test_vmc_f2_with_slater_d_shells(lib, oracle_mod, lanes):
     # Slater s, p and d shells on the second atom: the Laplacian of a Slater
     # function P e^{-ar} is P (g'' + 2 (l + 1) g' / r) for l = 2 as well
@@ -153,7 +153,7 @@ def test_vmc_f2_with_slater_d_shells(lib, oracle_mod, lanes):
     _check_vmc(ref, acc, R, 8, oracle_obj=ref["oracle"])
 
 
-@pytest.mark.parametrize("kern", [1, 2])
+@pytest.mark.parametrize("kern", [1, 2, 3])
 def test_dmc_f2_with_slater_d_shells(lib, oracle_mod, kern):
     ref, out, R = _dmc_pair(lib, oracle_mod, _f2_with_slater_shells(2), 37, 2, 0.002, dmc_kernel=kern,
                             et_median=True)
@@ -195,11 +195,6 @@ def test_vmc_precision_molecule_walker_resident(lib, oracle_mod):
     R = ctx.positions(state).cpu().numpy()
     torch.cuda.synchronize()
     _check_vmc(ref, acc, R, steps, oracle_obj=o)
-
-
-def test_vmc_walker_resident_rejects_slater_shells(lib):
-    with pytest.raises(lib.VBQMCError):
-        lib.Context(_f2_with_slater_shells(), step_kernel=3)
 
 
 def _reference_sets(sysd):
@@ -345,7 +340,7 @@ DMC_KERNELS = [1, 2, 3]
 
 def _dmc_context(lib, sysd, kern, **kw):
     """A context on DMC kernel `kern`; skips where the walker-resident kernel
-    does not take the system (Slater shells, more than 32 electrons per spin)."""
+    does not take the system (more than 32 electrons per spin)."""
     try:
         return lib.Context(sysd, dmc_kernel=kern, **kw)
     except lib.VBQMCError as e:
