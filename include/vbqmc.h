@@ -85,9 +85,9 @@ typedef struct {
  * the cusp-preserving constraints among the c_t are the caller's.  With
  * f_een, single-electron VMC and DMC run only on the walker-resident kernel
  * (step_kernel / dmc_kernel 3; EINVAL at create for another choice, and at
- * the call when the system does not fit it), vbqmc_vmc_sweep,
- * vbqmc_vmc_measure and S_IJ sums (sij_sum) are EINVAL, and all-electron
- * VMC, evaluation and the parameter derivatives take it everywhere.
+ * the call when the system does not fit it), vbqmc_vmc_sweep and
+ * vbqmc_vmc_measure are EINVAL, and all-electron VMC, evaluation and the
+ * parameter derivatives take it everywhere.
  */
 typedef struct {
   int32_t n_shells;
@@ -140,8 +140,8 @@ typedef struct {
  * call rebuilds the records from their positions (one launch) and then runs
  * one launch per step (moves, refresh and E_L of four walkers per
  * workgroup), with the same limits as dmc_kernel 3 (EINVAL at create
- * otherwise); a call that asks for S_IJ sums (sij_sum set) runs the sweep
- * and local-energy kernels instead.  0 = 2 when the system fits it and
+ * otherwise), S_IJ sums included for up to 256 structures (a call with more
+ * runs the sweep and local-energy kernels).  0 = 2 when the system fits it and
  * walker_lanes is 0, else 3 when it fits that and walker_lanes is 0, else 1.
  * Results do not depend on it beyond rounding.
  * dmc_kernel: how vbqmc_dmc_advance runs a step: 1 = one workgroup per walker

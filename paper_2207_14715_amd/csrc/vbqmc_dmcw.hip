@@ -1348,6 +1348,28 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   }
   if (live)
     for (int k = lane; k < 3 * N; k += 64) rec[wf.r_R + k] = Rl[k];
+  if constexpr (VMC) {
+    // S_IJ sums (Sec. 2.4): the structure ratios r_I = sum over the
+    // structure's determinant pairs of d R_up R_dn / S from the ratios this
+    // step left in the record, then r_I r_J into the walker's matrix (the
+    // host sends at most 256 structures here: r_I sits in the broadcast rows)
+    if (!prep && vm.sij && live && !bad) {
+      const int nv = wf.nstruct;
+      double* rI = xr;
+      for (int I = lane; I < nv; I += 64) {
+        double a = 0.0;
+        for (int k = wf.srow[I]; k < wf.srow[I + 1]; ++k)
+          a += wf.slc[k] * RW[wf.slu[2 * k]] * RW[n0 + wf.slu[2 * k + 1]];
+        rI[I] = a / S;
+      }
+      wave_sync();
+      double* sj = vm.sij + (size_t)w * nv * nv;
+      for (int k = lane; k < nv * nv; k += 64) {
+        const int I = k / nv, J = k - I * nv;
+        sj[k] += rI[I] * rI[J];
+      }
+    }
+  }
 }
 
 template <int NC, int XE, int LK, bool VMC, bool EEN>

@@ -1405,10 +1405,9 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!acc->e_sum || !acc->e2_sum || !acc->n_accept || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc: accumulator pointers missing");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc: too many walkers");
-  if (!all_electron && !x->een.empty() && (x->step_kernel != 3 || acc->sij_sum))
+  if (!all_electron && !x->een.empty() && x->step_kernel != 3)
     return fail(x, VBQMC_EINVAL,
-                "vmc: with f_een, single-electron moves need the walker-resident kernel (a system that fits it) "
-                "and no S_IJ sums");
+                "vmc: with f_een, single-electron moves need the walker-resident kernel (a system that fits it)");
   if (!all_electron && x->step_kernel == 2) {
     // single-electron moves and E_L of every step in one row-kernel launch
     hipError_t e = launch_vmc_rows(x->wf, x->d_wf_rows, (double*)state, W, n_steps, seed, step0, step_size,
@@ -1416,10 +1415,10 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
                                    (hipStream_t)stream);
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
-  if (!all_electron && x->step_kernel == 3 && !acc->sij_sum) {
+  if (!all_electron && x->step_kernel == 3 && (!acc->sij_sum || x->nstruct <= 256)) {
     // rebuild the records (orbital-row caches at every electron), then one
     // walker-resident launch per step: moves, refresh and E_L
-    DwVmc vm{step_size, W, acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last};
+    DwVmc vm{step_size, W, acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum};
     const DevWF lay = dmcw_layout(x);
     hipError_t e = launch_dmcw_vmc(lay, x->d_wf_dmcw, (double*)state, seed, 0, 1, vm, (hipStream_t)stream);
     for (int st = 0; st < n_steps && e == hipSuccess; ++st)

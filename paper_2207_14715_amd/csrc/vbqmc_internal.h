@@ -162,7 +162,8 @@ struct DmcBranch {
 };
 
 // Walker-resident kernel in VMC mode (single-electron Metropolis steps):
-// step size, walker count and the per-walker accumulators of vbqmc_vmc_acc.
+// step size, walker count and the per-walker accumulators of vbqmc_vmc_acc
+// (sij: [W][nstruct][nstruct] or null).
 struct DwVmc {
   double step;
   int64_t W;
@@ -170,6 +171,7 @@ struct DwVmc {
   double* e2_sum;
   double* n_accept;
   double* e_last;
+  double* sij;
 };
 
 }  // namespace vbqmc

@@ -1,7 +1,8 @@
 """The three-body Jastrow f_een (Sec. 2.1) on the GPU against the oracle:
 evaluation (ln|Psi|, gradient, E_L) of systems with f_een, single-electron
 VMC and DMC walks on the walker-resident kernel, all-electron VMC on the
-one-workgroup-per-walker kernel, and the calls that refuse f_een."""
+one-workgroup-per-walker kernel (S_IJ sums included), the parameter
+derivatives and linear-method sums, and the calls that refuse f_een."""
 
 import numpy as np
 import pytest
@@ -55,11 +56,14 @@ def test_vmc_all_electron_h2(lib, oracle_mod):
 def test_vmc_walker_resident(lib, oracle_mod, name):
     # 12 sweeps pass the 32-update refresh on F2 (Newton-Schulz from the
     # running inverse); 61 / 45 walkers leave a partly filled workgroup
+    # (with S_IJ sums on the small system)
     sysd = _small_een() if name == "small" else S.with_een(S.f2_shaped())
     W, steps = (45, 10) if name == "small" else (61, 12)
-    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, W, steps, 0.3, False)
+    ref, acc, R, ctx = _vmc_pair(lib, oracle_mod, sysd, W, steps, 0.3, False, sij=name == "small")
     assert ctx.info["step_kernel"] == 3
     _check_vmc(ref, acc, R, steps, oracle_obj=ref["oracle"])
+    if name == "small":
+        np.testing.assert_allclose(acc["sij_sum"].cpu().numpy(), ref["sij_sum"], rtol=1e-8, atol=1e-8)
 
 
 def test_vmc_walker_resident_40_electrons(lib, oracle_mod):
@@ -91,8 +95,6 @@ def test_paths_without_f_een_refuse_it(lib):
         ctx.vmc_sweep(st, 1, 0, 0.3, acc["n_accept"])
     with pytest.raises(lib.VBQMCError):
         ctx.vmc_measure(st, acc)
-    with pytest.raises(lib.VBQMCError):
-        ctx.vmc_advance(st, 1, 1, 0, 0.3, False, acc=ctx.new_vmc_acc(W, sij=True))
     torch.cuda.synchronize()
 
 
