@@ -38,7 +38,7 @@ TRAFFIC_LANES = 32
 TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5619.0 * 2.0 + 9895.7) * 1024}
 # the walker-resident kernel in VMC mode on the 40-electron molecule (two
 # replaced columns at most per determinant, 160 padded basis functions)
-WRES_VMC_KERNEL = "k_dmcw<32, 2, 16, true>"
+WRES_VMC_KERNEL = "k_dmcw<32, 2, 16, true, false>"
 EXP_FLOPS = 20                  # one double-precision exp counted as 20 flops
 
 
@@ -473,7 +473,7 @@ def adjoint_form(args):
 
 
 HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"
-DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16, false>"}
+DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16, false, false>"}
 # HBM bytes of one launch of the walker-resident DMC step kernel on the
 # headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the copy-kernel calibration (the factors below), with
