@@ -644,6 +644,8 @@ def dmc_form(args):
     accept = float(out["n_accept"].sum().item() / max(out["n_prop"].sum().item(), 1))
     e_mixed = float(out["wesum"].sum().item() / out["wsum"].sum().item())
     e_mixed_clipped = float(out["wcsum"].sum().item() / out["wsum"].sum().item())
+    # effective time step of the moves with rejections: tau <|dr|^2 accepted> / <|dr|^2 proposed>
+    tau_eff = tau * float(out["dr2_acc"].sum().item() / out["dr2_prop"].sum().item())
     ws_np = out["wsum"].cpu().numpy()
     _, e_clip_err, e_clip_levels = reblock(out["wcsum"].cpu().numpy() / ws_np, ws_np)
     kern = ctx.info["dmc_kernel"]
@@ -684,6 +686,7 @@ def dmc_form(args):
                    "dmc_kernel": {1: "workgroup per walker", 2: "electron-major", 3: "walker-resident"}[kern]},
         "electron_moves_per_s": moves * ctx.N / wall,
         "acceptance": accept,
+        "tau_eff": tau_eff,
         "population": [int(p) for p in pop],
         "population_band": [float(pop.min() / W - 1), float(pop.max() / W - 1)],
         "e_trial": out["e_trial"],

@@ -284,7 +284,11 @@ int vbqmc_vmc_measure(vbqmc_ctx* ctx, void* state, int64_t W, const vbqmc_vmc_ac
  * the call's stream and their elapsed milliseconds are written here before
  * the call returns (branching and compaction are not included).  wcsum
  * [dev][n_steps] or NULL: sum of weight * E_L clipped to E_T +- sqrt(N/tau),
- * the estimator the trial-energy feedback uses. */
+ * the estimator the trial-energy feedback uses.  dr2_acc, dr2_prop
+ * [dev][n_steps] or NULL: sums over the walkers and their electrons of
+ * |r' - r|^2 of the accepted moves and of all proposed moves, so that
+ * tau_eff = tau dr2_acc / dr2_prop (the effective time step of the
+ * drift-diffusion moves with rejections; the weights use the nominal tau). */
 typedef struct {
   double* pop;
   double* wsum;
@@ -294,6 +298,8 @@ typedef struct {
   double* n_prop;
   double* step_ms;
   double* wcsum;
+  double* dr2_acc;
+  double* dr2_prop;
 } vbqmc_dmc_log;
 
 /*

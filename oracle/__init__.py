@@ -234,13 +234,14 @@ class Oracle:
         Eb[:W] = eloc
         Wio = ctypes.c_int(W)
         et = ctypes.c_double(e_trial)
-        hist = {k: np.zeros(n_steps) for k in ("pop", "wsum", "wesum", "wcsum", "etrial", "acc", "prop")}
+        hist = {k: np.zeros(n_steps) for k in ("pop", "wsum", "wesum", "wcsum", "etrial", "acc", "prop", "dr2_acc",
+                                                "dr2_prop")}
         rc = self._lib.orc_dmc(ctypes.c_void_p(self._h), ctypes.byref(Wio), ctypes.c_int(cap), _dp(Rb), _dp(Eb),
                                ctypes.c_int(n_steps), ctypes.c_uint64(seed), ctypes.c_uint32(step0),
                                ctypes.c_double(tau), ctypes.byref(et), ctypes.c_int(w_target),
                                _dp(hist["pop"]), _dp(hist["wsum"]), _dp(hist["wesum"]), _dp(hist["wcsum"]),
                                _dp(hist["etrial"]),
-                               _dp(hist["acc"]), _dp(hist["prop"]))
+                               _dp(hist["acc"]), _dp(hist["prop"]), _dp(hist["dr2_acc"]), _dp(hist["dr2_prop"]))
         Wn = Wio.value
         return {"rc": int(rc), "R": Rb[:Wn].copy(), "eloc": Eb[:Wn].copy(), "W": Wn, "e_trial": et.value, **hist}
 

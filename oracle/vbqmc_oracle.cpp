@@ -927,7 +927,8 @@ int orc_vmc(void* h, int W, double* R, int nsteps, uint64_t seed, uint32_t step0
 // (accepted / proposed single-electron moves).
 int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int nsteps,
             uint64_t seed, uint32_t step0, double tau, double* etrial_io, int W_target,
-            double* pop, double* wsum, double* wesum, double* wcsum, double* etrial, double* acc, double* prop) {
+            double* pop, double* wsum, double* wesum, double* wcsum, double* etrial, double* acc, double* prop,
+            double* d2acc, double* d2prop) {
   const System& s = *(System*)h;
   Params<double> P = make_params<double>(s, -1);
   const int N = s.N;
@@ -936,7 +937,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
   double run_num = 0, run_den = 0;
   std::vector<double> Rnew((size_t)capacity * N * 3), Enew(capacity), wts(capacity), ubr(capacity);
   std::vector<int> ncopy(capacity);
-  std::vector<double> nacc(capacity), nprop(capacity);
+  std::vector<double> nacc(capacity), nprop(capacity), sacc(capacity), sprop(capacity);
   const double cap = std::sqrt((double)N / tau);
   std::vector<double> Eclip(capacity);
   for (int st = 0; st < nsteps; ++st) {
@@ -947,6 +948,8 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
       double* Rw = R + (size_t)w * N * 3;
       nacc[w] = 0;
       nprop[w] = 0;
+      sacc[w] = 0;
+      sprop[w] = 0;
       EvalOut<double> cur = evaluate(s, P, Rw, 1);
       if (!cur.ok) { ++bad; continue; }
       std::vector<double> Rn(Rw, Rw + 3 * N);
@@ -959,6 +962,11 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
           Rn[3 * e + x] = rp[x];
         }
         nprop[w] += 1;
+        // squared length of the proposed move (the effective time step is
+        // tau times the accepted over the proposed sums)
+        double d2 = 0;
+        for (int x = 0; x < 3; ++x) d2 += (rp[x] - Rw[3 * e + x]) * (rp[x] - Rw[3 * e + x]);
+        sprop[w] += d2;
         EvalOut<double> nw = evaluate(s, P, Rn.data(), 1);
         bool accept = false;
         if (nw.ok && nw.sign == cur.sign) {
@@ -976,6 +984,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
           for (int x = 0; x < 3; ++x) Rw[3 * e + x] = rp[x];
           cur = nw;
           nacc[w] += 1;
+          sacc[w] += d2;
         } else {
           for (int x = 0; x < 3; ++x) Rn[3 * e + x] = Rw[3 * e + x];
         }
@@ -996,7 +1005,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
     double f = 1.0;
     if (sw_raw > 1.05 * W_target) f = 1.05 * W_target / sw_raw;
     else if (sw_raw < 0.95 * W_target) f = 0.95 * W_target / sw_raw;
-    double sw = 0, swe = 0, swc = 0, na = 0, np = 0;
+    double sw = 0, swe = 0, swc = 0, na = 0, np = 0, s2a = 0, s2p = 0;
     for (int w = 0; w < W; ++w) {
       wts[w] = f * wts[w];
       ncopy[w] = std::min(3, (int)std::floor(wts[w] + ubr[w]));
@@ -1005,6 +1014,8 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
       swc += wts[w] * Eclip[w];
       na += nacc[w];
       np += nprop[w];
+      s2a += sacc[w];
+      s2p += sprop[w];
     }
     pop[st] = W;
     wsum[st] = sw;
@@ -1013,6 +1024,8 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
     etrial[st] = ET + std::log(f) / tau;
     acc[st] = na;
     prop[st] = np;
+    d2acc[st] = s2a;
+    d2prop[st] = s2p;
     // stable compaction of the copies
     int Wn = 0;
     for (int w = 0; w < W; ++w) Wn += ncopy[w];

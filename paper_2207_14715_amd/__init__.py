@@ -74,16 +74,18 @@ class _VmcAcc(ctypes.Structure):
 class _DmcLog(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("wesum", ctypes.c_void_p),
                 ("etrial", ctypes.c_void_p), ("n_accept", ctypes.c_void_p), ("n_prop", ctypes.c_void_p),
-                ("step_ms", ctypes.POINTER(ctypes.c_double)), ("wcsum", ctypes.c_void_p)]
+                ("step_ms", ctypes.POINTER(ctypes.c_double)), ("wcsum", ctypes.c_void_p),
+                ("dr2_acc", ctypes.c_void_p), ("dr2_prop", ctypes.c_void_p)]
 
 
-# per-step DMC records (device tensors); "wcsum" may be left out
-_DMC_LOG_KEYS = ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop", "wcsum")
+# per-step DMC records (device tensors); "wcsum", "dr2_acc" and "dr2_prop"
+# may be left out
+_DMC_LOG_KEYS = ("pop", "wsum", "wesum", "etrial", "n_accept", "n_prop", "wcsum", "dr2_acc", "dr2_prop")
 
 
 def _dmc_log(log, step_ms):
-    return _DmcLog(*[log[k].data_ptr() for k in _DMC_LOG_KEYS[:6]], step_ms,
-                   log["wcsum"].data_ptr() if "wcsum" in log else None)
+    opt = [log[k].data_ptr() if k in log else None for k in _DMC_LOG_KEYS[6:]]
+    return _DmcLog(*[log[k].data_ptr() for k in _DMC_LOG_KEYS[:6]], step_ms, *opt)
 
 
 _lib = None

@@ -145,7 +145,9 @@ __global__ __launch_bounds__(64) void k_dmcb_propose(const DevWF* __restrict__ p
     // a step starts: clear the acceptance count; a walker whose
     // determinant sum vanishes is dropped at branching
     if (lane == 0) {
-      nacc[w] = 0.0;
+      nacc[3 * w] = 0.0;
+      nacc[3 * w + 1] = 0.0;
+      nacc[3 * w + 2] = 0.0;
       if (!(rw.S != 0.0)) rec[wf.r_sc + SC_FLAGS] = 1.0;
     }
     __syncthreads();
@@ -559,6 +561,12 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
     philox_pair(seed, (uint32_t)w, step, 4u * i + 1u, 0u, ua, dummy);
     accept = ua < prob;
   }
+  if (lane == 0) {
+    // squared displacement of the proposal (effective time step)
+    const double d2 = (p[0] - x[0]) * (p[0] - x[0]) + (p[1] - x[1]) * (p[1] - x[1]) + (p[2] - x[2]) * (p[2] - x[2]);
+    nacc[3 * w + 1] += d2;
+    if (accept) nacc[3 * w + 2] += d2;
+  }
   if (!accept) return;
   // R_u from the updated minors (old table + bcol y^T / rho, as the column
   // update below forms it) and S
@@ -615,7 +623,7 @@ __global__ __launch_bounds__(64) void k_dmcb_accept(const DevWF* __restrict__ pw
     Rw[3 * i] = p[0];
     Rw[3 * i + 1] = p[1];
     Rw[3 * i + 2] = p[2];
-    nacc[w] += 1.0;
+    nacc[3 * w] += 1.0;
   }
 }
 

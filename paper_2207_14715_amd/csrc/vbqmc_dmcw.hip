@@ -747,6 +747,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
   // (VMC keeps a walker flagged by an earlier call flagged through the rebuild)
   bool bad = !live || ((!prep || VMC) && rec[wf.r_sc + SC_FLAGS] != 0.0) || (!prep && !(S != 0.0));
   double na = 0.0;
+  double d2p = 0.0, d2a = 0.0;  // squared displacements proposed / accepted (DMC)
   const double ET = VMC ? 0.0 : ctrl[DC_ET];
   const double sqt = VMC ? 0.0 : sqrt(tau);
   const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
@@ -1003,6 +1004,7 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
         const double rdet = part[0] / S, dU = part[1];
         bool accept = false;
         const double ir = 1.0 / rho;
+        const double d2 = (px - xi) * (px - xi) + (py - yi) * (py - yi) + (pz - zi) * (pz - zi);
         if constexpr (VMC) {
           // |Psi'/Psi|^2 (either sign; a move that makes the reference
           // determinant exactly singular, a set of measure zero, is refused)
@@ -1053,7 +1055,9 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
           const double prob = rdet * rdet * exp(2.0 * dU + (fwd - bwd) / (2.0 * tau));
           accept = rnd[4 * il + 3] < prob;
         }
+        d2p += d2;
         if (accept) {
+          d2a += d2;
           double f = 0.0;
           if (blane) f = -(t0 - (lane == il ? 1.0 : 0.0)) * ir;
           else if (tlane) f = yv * ir;
@@ -1339,7 +1343,9 @@ __global__ __launch_bounds__(kDwNT) __attribute__((amdgpu_waves_per_eu(1, 1))) v
       }
     } else if (!prep) {
       dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, N, seed, step);
-      nacc[w] = na;
+      nacc[3 * w] = na;
+      nacc[3 * w + 1] = d2p;
+      nacc[3 * w + 2] = d2a;
     }
     double* sc = rec + wf.r_sc;
     sc[SC_ELOC] = En;

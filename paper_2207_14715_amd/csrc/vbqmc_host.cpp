@@ -33,8 +33,8 @@ hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* st
                            uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s);
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
                            int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
-                           double* wcsum, double* etrial, double* lacc, double* lprop, const double* src,
-                           double* dst, int rec_len, hipStream_t s);
+                           double* wcsum, double* etrial, double* lacc, double* lprop, double* ld2a, double* ld2p,
+                           const double* src, double* dst, int rec_len, hipStream_t s);
 hipError_t launch_vmc_rows(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                            uint64_t step0, double step_size, double* es, double* e2s, double* na, double* el,
                            double* sij, hipStream_t s);
@@ -1438,10 +1438,10 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
 }
 
-// DMC workspace: ctrl (8 doubles) | w, we, wc, ub, nacc [cap] | ncopy [cap] |
+// DMC workspace: ctrl (8 doubles) | w, we, wc, ub [cap] | nacc [cap][3] | ncopy [cap] |
 // offs [cap+1] | (electron-major kernels) P, V [cap][3], Vp [cap][4][nop], ek, ep [cap]
 namespace {
-size_t dmc_ws_base(int64_t cap) { return 64 + 5 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
+size_t dmc_ws_base(int64_t cap) { return 64 + 7 * (size_t)cap * 8 + (size_t)cap * 4 + ((size_t)cap + 1) * 4; }
 }  // namespace
 
 int vbqmc_dmc_workspace_bytes(const vbqmc_ctx* x, int64_t cap, int32_t n_steps, size_t* bytes) {
@@ -1514,7 +1514,9 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
   br.we = (double*)p; p += cap * 8;
   br.wc = (double*)p; p += cap * 8;
   br.ub = (double*)p; p += cap * 8;
-  double* nacc = (double*)p; p += cap * 8;
+  // per walker: accepted moves, sum of the proposals' and of the accepted
+  // moves' squared displacements
+  double* nacc = (double*)p; p += 3 * cap * 8;
   br.nc = (int*)p; p += cap * 4;
   int* offs = (int*)p;
   double h[DC_COUNT] = {0};
@@ -1582,7 +1584,8 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
       return hipfail(x, e, "dmc: step");
     }
     e = launch_dmc_tail(ctrl, br, nacc, offs, cap, x->N, st, tau, (double)W_target, lg->pop, lg->wsum,
-                        lg->wesum, lg->wcsum, lg->etrial, lg->n_accept, lg->n_prop, cur, oth, x->wf.rec_len, s);
+                        lg->wesum, lg->wcsum, lg->etrial, lg->n_accept, lg->n_prop, lg->dr2_acc, lg->dr2_prop, cur,
+                        oth, x->wf.rec_len, s);
     if (e != hipSuccess) {
       drop_events();
       return hipfail(x, e, "dmc: branching");

@@ -624,7 +624,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const double ET = ctrl[DC_ET];
   const double E_old = sc[SC_ELOC];
   const double sqt = sqrt(tau);
-  double na = 0.0;
+  double na = 0.0, d2p = 0.0, d2a = 0.0;
   bool bad = !(sc[SC_S] != 0.0);
   for (int i = 0; i < wf.N && !bad; ++i) {
     const double* R = l.R();
@@ -648,6 +648,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double dU = sc[SC_TMP0];
     double rho = sc[SC_TMP1];
     bool accept = false;
+    const double d2 = (px - rx) * (px - rx) + (py - ry) * (py - ry) + (pz - rz) * (pz - rz);
+    d2p += d2;
     if (rdet > 0.0 && rho != 0.0) {
       double vn[3];
       double Snew = sc[SC_S] * rdet / rho;  // S' relative to the updated reference
@@ -669,6 +671,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       accept_move<NT>(wf, l, i, px, py, pz);
       for (int k = threadIdx.x; k < 3 * wf.nop; k += NT) gc[(size_t)i * 3 * wf.nop + k] = l.v()[wf.nop + k];
       na += 1.0;
+      d2a += d2;
       __syncthreads();
     }
     if (!(sc[SC_S] != 0.0)) bad = true;
@@ -682,7 +685,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (threadIdx.x == 0) {
     const double En = bad ? NAN : sc[SC_ELOC];
     dmc_branch_inputs(br, w, bad, E_old, En, ET, tau, wf.N, seed, step);
-    nacc[w] = na;
+    nacc[3 * w] = na;
+    nacc[3 * w + 1] = d2p;
+    nacc[3 * w + 2] = d2a;
     if (bad) sc[SC_FLAGS] = 1.0;
   }
   __syncthreads();
@@ -702,8 +707,8 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
                                                    int64_t capacity, int N, int st, double tau,
                                                    double W_target, double* pop, double* wsum,
                                                    double* wesum, double* wcsum, double* etrial, double* lacc,
-                                                   double* lprop) {
-  __shared__ double sw[1024], swe[1024], swc[1024], sa[1024];
+                                                   double* lprop, double* ld2a, double* ld2p) {
+  __shared__ double sw[1024], swe[1024], swc[1024], sa[1024], sdp[1024], sda[1024];
   __shared__ int sc_[1024];
   __shared__ int bad;
   __shared__ double fsh;
@@ -734,7 +739,7 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
   }
   __syncthreads();
   const double f = fsh;
-  double aw = 0, ae = 0, ac = 0, aa = 0;
+  double aw = 0, ae = 0, ac = 0, aa = 0, adp = 0, ada = 0;
   int cnt = 0;
   for (int64_t k = b; k < e; ++k) {
     if (br.nc[k] < 0) continue;
@@ -744,11 +749,13 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
     aw += wk;
     ae += f * br.we[k];
     ac += f * br.wc[k];
-    aa += nacc[k];
+    aa += nacc[3 * k];
+    adp += nacc[3 * k + 1];
+    ada += nacc[3 * k + 2];
     cnt += nc;
   }
   __syncthreads();
-  sw[t] = aw; swe[t] = ae; swc[t] = ac; sa[t] = aa; sc_[t] = cnt;
+  sw[t] = aw; swe[t] = ae; swc[t] = ac; sa[t] = aa; sdp[t] = adp; sda[t] = ada; sc_[t] = cnt;
   __syncthreads();
   // inclusive scan of copy counts (Hillis-Steele) and tree sums
   for (int off = 1; off < 1024; off <<= 1) {
@@ -763,6 +770,8 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
       swe[t] += swe[t + off];
       swc[t] += swc[t + off];
       sa[t] += sa[t + off];
+      sdp[t] += sdp[t + off];
+      sda[t] += sda[t + off];
     }
     __syncthreads();
   }
@@ -781,6 +790,8 @@ __global__ __launch_bounds__(1024) void k_dmc_scan(double* ctrl, DmcBranch br, c
     etrial[st] = ctrl[DC_ET] + log(f) / tau;
     lacc[st] = sa[0];
     lprop[st] = (double)W * N;
+    if (ld2a) ld2a[st] = sda[0];
+    if (ld2p) ld2p[st] = sdp[0];
     if (bad || Wn <= 0 || Wn > capacity) {
       ctrl[DC_ERR] = bad ? 1.0 : 2.0;
       ctrl[DC_ERRSTEP] = (double)st;
@@ -994,10 +1005,10 @@ hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* st
 
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
                            int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
-                           double* wcsum, double* etrial, double* lacc, double* lprop, const double* src,
-                           double* dst, int rec_len, hipStream_t s) {
+                           double* wcsum, double* etrial, double* lacc, double* lprop, double* ld2a, double* ld2p,
+                           const double* src, double* dst, int rec_len, hipStream_t s) {
   hipLaunchKernelGGL(k_dmc_scan, dim3(1), dim3(1024), 0, s, ctrl, br, nacc, offs, cap, N, st, tau, W_target, pop,
-                     wsum, wesum, wcsum, etrial, lacc, lprop);
+                     wsum, wesum, wcsum, etrial, lacc, lprop, ld2a, ld2p);
   hipLaunchKernelGGL(k_dmc_copy, dim3((unsigned)cap), dim3(256), 0, s, ctrl, src, dst, offs, rec_len);
   hipLaunchKernelGGL(k_dmc_commit, dim3(1), dim3(1), 0, s, ctrl);
   return hipGetLastError();

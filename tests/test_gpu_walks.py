@@ -379,6 +379,9 @@ def _check_dmc(ref, out, R, e_rec=None, oracle_obj=None):
     np.testing.assert_allclose(out["wcsum"].cpu().numpy(), ref["wcsum"], rtol=1e-8, atol=1e-8)
     np.testing.assert_allclose(out["etrial"].cpu().numpy(), ref["etrial"], rtol=1e-9, atol=1e-9)
     np.testing.assert_array_equal(out["n_accept"].cpu().numpy(), ref["acc"])
+    # squared move lengths, proposed and accepted (the effective time step)
+    np.testing.assert_allclose(out["dr2_prop"].cpu().numpy(), ref["dr2_prop"], rtol=1e-10)
+    np.testing.assert_allclose(out["dr2_acc"].cpu().numpy(), ref["dr2_acc"], rtol=1e-10)
     np.testing.assert_allclose(R, ref["R"], rtol=1e-8, atol=1e-8)
     if e_rec is not None:
         # each surviving walker's E_L against the oracle's at its configuration

@@ -83,6 +83,30 @@ def test_dmc_exact_trial_function_keeps_population(oracle_mod):
     np.testing.assert_allclose(r["wesum"] / r["wsum"], -0.5, atol=1e-13)
 
 
+def test_dmc_move_lengths_give_the_effective_time_step(oracle_mod):
+    """Hydrogen with its exact trial orbital e^-r: the drift is -r/|r| (unit
+    length), so a proposal r' = r + tau v + sqrt(tau) chi has mean squared
+    length 3 tau + tau^2; the accepted moves are a subset, so
+    tau_eff = tau dr2_acc / dr2_prop lies below tau and above tau times the
+    acceptance's lower part."""
+    sysd = S.hydrogen_sto_1s(1.0)
+    o = oracle_mod.Oracle(sysd)
+    W, tau, steps = 2000, 0.05, 5
+    R0 = np.random.default_rng(5).normal(size=(W, 1, 3))
+    e0 = o.evaluate(R0)["eloc"]
+    r = o.dmc(R0, e0, steps, 23, 0, tau, -0.5, W)
+    n = r["pop"].sum()  # one electron per walker: proposals = walker-steps
+    np.testing.assert_array_equal(r["prop"], r["pop"])
+    mean = r["dr2_prop"].sum() / n
+    # chi^2 with 3 degrees of freedom: variance of |sqrt(tau) chi + tau v|^2
+    # about 6 tau^2 (plus O(tau^3)); 5 sigma
+    assert abs(mean - (3 * tau + tau * tau)) < 5 * np.sqrt(6 * tau * tau / n) + 4 * tau ** 2, mean
+    ratio = r["dr2_acc"] / r["dr2_prop"]
+    acc = r["acc"] / r["prop"]
+    assert np.all(ratio < 1.0) and np.all(ratio > 0.9), ratio
+    assert np.all(np.abs(ratio - acc) < 0.05), (ratio, acc)
+
+
 def test_dmc_nodeless_projection_reaches_exact_energy(oracle_mod):
     """Gaussian trial (VMC energy -0.424) projects to the exact -0.5 within the time-step error."""
     o = oracle_mod.Oracle(S.hydrogen_gaussian(0.3))
