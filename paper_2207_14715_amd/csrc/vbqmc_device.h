@@ -1574,7 +1574,8 @@ __device__ void accept_move(const DevWF& wf, const Ld& l, int i, double px, doub
 }
 
 // ---------------------------------------------------------------------------
-// DMC branching inputs of walker w (Sec. 2.3.2, birth/death): the weight
+// DMC branching inputs of walker w (Sec. 2.3.2, birth/death; a walker that
+// is flagged or whose new E_L is not finite gets no copies): the weight
 // exp(-tau ((E_L + E_L') / 2 - E_T)) with both energies clipped to
 // E_T +- sqrt(N / tau), its products with E_L' and with the clipped E_L', and
 // the branching draw (purpose 2, electron index N).  The copy count
@@ -1586,6 +1587,8 @@ __device__ __forceinline__ void dmc_branch_inputs(const DmcBranch& br, int64_t w
   const double eo = fmin(fmax(E_old, ET - cap), ET + cap);
   const double en = fmin(fmax(En, ET - cap), ET + cap);
   const double wt = exp(-tau * (0.5 * (eo + en) - ET));
+  // a non-finite local energy drops the walker like a singular one
+  bad = bad || !isfinite(En);
   double ub, dummy;
   philox_pair(seed, (uint32_t)w, step, 4u * (uint32_t)N + 2u, 0u, ub, dummy);
   br.w[w] = bad ? NAN : wt;

@@ -80,9 +80,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (w >= W) return;
   Ld l(lds_dyn, wf);
   stage_tables<NT, PREC>(wf, l);
-  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) l.R()[k] = Rin[w * rstride + k];
-  __syncthreads();
-  bool ok = build_state<NT, PREC>(wf, l, l.R());
+  bool nonfinite = false;
+  for (int k = threadIdx.x; k < 3 * wf.N; k += NT) {
+    const double x = Rin[w * rstride + k];
+    nonfinite |= !isfinite(x);
+    l.R()[k] = x;
+  }
+  // a configuration with a non-finite coordinate is reported like Psi = 0
+  // (and its record flagged) without being evaluated
+  bool ok = !__syncthreads_or(nonfinite) && build_state<NT, PREC>(wf, l, l.R());
   if (ok) {
     compute_RWS<NT>(wf, l);
     ok = l.sc()[SC_S] != 0.0;
