@@ -1,4 +1,4 @@
-"""Failure handling, forced from the host with inputs the library checks:
+"""Failure handling and resumption, forced from the host with inputs the library checks:
 a configuration with a non-finite coordinate, two same-spin electrons at one
 point (Psi = 0) and two opposite-spin electrons at one point (a non-finite
 E_L).  Evaluation reports such walkers (sign 0, a rounding-level |Psi| or a
@@ -90,3 +90,30 @@ def test_dmc_stops_on_a_non_finite_walker(lib, kern):
         ctx.dmc_advance([st0, st1], W, 2, 3, 0, 0.002, -200.0, W)
     assert ei.value.code == -6
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kernel", [2, 3])
+def test_vmc_resumes_from_positions(lib, kernel):
+    """Checkpoint = the walker positions (vbqmc_walkers_positions); there is
+    no random-number state, the Philox counters come from (seed, walker,
+    step).  Six steps in one call equal three steps, a checkpoint, a fresh
+    vbqmc_walkers_init from the saved positions (fresh inverses) and three
+    more steps, to rounding: same acceptances, same positions and energies
+    (row kernel and walker-resident kernel)."""
+    import torch
+    sysd = S.f2_shaped()
+    W, seed = 61, 99
+    R0 = torch.from_numpy(S.initial_walkers(sysd, W, seed=2)).cuda()
+    ctx = lib.Context(sysd, step_kernel=kernel)
+    st_a = ctx.walkers_init(R0)
+    a = ctx.vmc_advance(st_a, 6, seed, 0, 0.3)
+    st = ctx.walkers_init(R0)
+    b = ctx.vmc_advance(st, 3, seed, 0, 0.3)
+    saved = ctx.positions(st).cpu().numpy()          # the checkpoint
+    st2 = ctx.walkers_init(torch.from_numpy(saved).cuda())
+    ctx.vmc_advance(st2, 3, seed, 3, 0.3, False, b)
+    Ra, Rb = ctx.positions(st_a).cpu().numpy(), ctx.positions(st2).cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a["n_accept"].cpu().numpy(), b["n_accept"].cpu().numpy())
+    np.testing.assert_allclose(Rb, Ra, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(b["e_sum"].cpu().numpy(), a["e_sum"].cpu().numpy(), rtol=1e-9, atol=1e-9)
