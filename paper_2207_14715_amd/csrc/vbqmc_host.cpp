@@ -1642,7 +1642,10 @@ int vbqmc_param_grad(vbqmc_ctx* x, int64_t W, const double* R, double* dlogpsi, 
   if ((size_t)x->wf.lds_adj_doubles * 8 > (size_t)x->lds_limit)
     return fail(x, VBQMC_EINVAL, "param_grad: system too large for the adjoint kernel's LDS budget");
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "param_grad: too many walkers");
-  hipError_t e = launch_param_grad(x->wf, x->d_wf, x->nt, W, R, dlogpsi, deloc, (double*)ws, need / 8, (hipStream_t)stream);
+  // a workgroup whose LDS leaves no room for a second one on the CU runs
+  // with four wavefronts, one per SIMD
+  const int nt = (size_t)x->wf.lds_adj_doubles * 8 * 2 > (size_t)x->lds_limit ? 256 : x->nt;
+  hipError_t e = launch_param_grad(x->wf, x->d_wf, nt, W, R, dlogpsi, deloc, (double*)ws, need / 8, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "param_grad");
 }
 
