@@ -754,6 +754,7 @@ hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t 
     if (wf.precision == 0) return launch_pg<128, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
     return launch_pg<128, 1>(wf, dwf, W, R, dlogpsi, deloc, s);
   }
+  if (nt == 512 && wf.precision == 0) return launch_pg<512, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
   if (wf.precision == 0) return launch_pg<256, 0>(wf, dwf, W, R, dlogpsi, deloc, s);
   return launch_pg<256, 1>(wf, dwf, W, R, dlogpsi, deloc, s);
 }

@@ -1021,7 +1021,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
   // regions used by every walker kernel
   wf.l_R = lds(std::max(3 * x->N, 3 * kGroup));
   wf.l_sc = lds(SC_COUNT);
-  wf.l_red = lds(kRedSlots);
+  wf.l_red = lds(2 * kRedSlots);  // (the adjoint's 512-thread reductions of 12 values)
   int nmax = std::max(x->nup, x->ndn);
   wf.l_ipiv = ilds(nmax);
   wf.l_f = lds(nmax);
@@ -1644,7 +1644,9 @@ int vbqmc_param_grad(vbqmc_ctx* x, int64_t W, const double* R, double* dlogpsi, 
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "param_grad: too many walkers");
   // a workgroup whose LDS leaves no room for a second one on the CU runs
   // with four wavefronts, one per SIMD
-  const int nt = (size_t)x->wf.lds_adj_doubles * 8 * 2 > (size_t)x->lds_limit ? 256 : x->nt;
+  const int nt = (size_t)x->wf.lds_adj_doubles * 8 * 2 > (size_t)x->lds_limit
+                     ? (x->wf.precision == VBQMC_FP64 && x->een.empty() ? 512 : 256)
+                     : x->nt;
   hipError_t e = launch_param_grad(x->wf, x->d_wf, nt, W, R, dlogpsi, deloc, (double*)ws, need / 8, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "param_grad");
 }
