@@ -668,47 +668,63 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   }
 
   // G. orbital-coefficient derivatives: contractions over electrons on MFMA,
-  // one 16 (orbital) x 16 (basis function) output tile per wave at a time
+  // 16 (basis function) columns x up to two 16-orbital row tiles per wave at
+  // a time, so that each basis function's channels at an electron are formed
+  // once for both row tiles
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
-  const int npt = nop / 16, nmt = wf.Mpad / 16;
+  const int npt = nop / 16, nmt = wf.Mpad / 16, npc = (npt + 1) / 2;
   double* oLl = oL + wf.nstruct;
   double* oEl = oE + wf.nstruct;
   for (int g0 = 0; g0 < N; g0 += kGroup) {
     int ne = min(kGroup, N - g0);
     group_radial<NT, 0>(wf, l, l.R(), g0, ne);  // FP64 basis rows for the contraction
-    for (int tile = wave; tile < npt * nmt; tile += NW) {
-      int pt = tile / nmt, mt = tile - pt * nmt;
-      int pcol = pt * 16 + (lane & 15), mcol = mt * 16 + (lane & 15);
-      v4d accE = {0, 0, 0, 0}, accL = {0, 0, 0, 0};
+    for (int tile = wave; tile < npc * nmt; tile += NW) {
+      const int pc = tile / nmt, mt = tile - pc * nmt;
+      const int pt0 = 2 * pc;
+      const bool two = pt0 + 1 < npt;  // (the same in the whole wave)
+      const int pcol = pt0 * 16 + (lane & 15), mcol = mt * 16 + (lane & 15);
+      v4d accE[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, accL[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
       for (int k0 = 0; k0 < kGroup; k0 += 4) {
         int e = k0 + (lane >> 4);
-        double a0 = 0.0, aG = 0.0, bv = 0.0, bk = 0.0;
+        double a0[2] = {0.0, 0.0}, aG[2] = {0.0, 0.0}, bv = 0.0, bk = 0.0;
         if (e < ne) {
-          a0 = G0[(g0 + e) * nop + pcol];
-          aG = G[(g0 + e) * nop + pcol];
+          a0[0] = G0[(g0 + e) * nop + pcol];
+          aG[0] = G[(g0 + e) * nop + pcol];
+          if (two) {
+            a0[1] = G0[(g0 + e) * nop + pcol + 16];
+            aG[1] = G[(g0 + e) * nop + pcol + 16];
+          }
           double ch[5];
           chan_all<double>(wf, l, e, mcol, ch);
           const double* gu = l.gU() + 3 * (g0 + e);
           bv = ch[0];
           bk = -(gu[0] * ch[1] + gu[1] * ch[2] + gu[2] * ch[3]) - 0.5 * ch[4];
         }
-        accE = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, accE, 0, 0, 0);
-        accE = __builtin_amdgcn_mfma_f64_16x16x4f64(aG, bk, accE, 0, 0, 0);
-        accL = __builtin_amdgcn_mfma_f64_16x16x4f64(aG, bv, accL, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !two) break;
+          accE[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[h], bv, accE[h], 0, 0, 0);
+          accE[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(aG[h], bk, accE[h], 0, 0, 0);
+          accL[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(aG[h], bv, accL[h], 0, 0, 0);
+        }
       }
       // f64 output layout: register r of lane l holds row 4r + l/16
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int p = pt * 16 + 4 * r + (lane >> 4), mu = mt * 16 + (lane & 15);
-        if (p < wf.norb && mu < M) {
-          size_t o = (size_t)p * M + mu;
-          if (g0 == 0) {
-            oEl[o] = accE[r];
-            oLl[o] = accL[r];
-          } else {
-            oEl[o] += accE[r];
-            oLl[o] += accL[r];
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int p = (pt0 + h) * 16 + 4 * r + (lane >> 4), mu = mt * 16 + (lane & 15);
+          if (p < wf.norb && mu < M) {
+            size_t o = (size_t)p * M + mu;
+            if (g0 == 0) {
+              oEl[o] = accE[h][r];
+              oLl[o] = accL[h][r];
+            } else {
+              oEl[o] += accE[h][r];
+              oLl[o] += accL[h][r];
+            }
           }
         }
       }
