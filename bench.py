@@ -479,11 +479,11 @@ DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb
 # dispatch) scaled by the copy-kernel calibration (the factors below), with
 # the SHA-256 prefix of the kernel source they were taken on: the value is
 # reported only while the source is unchanged (else null).
-DMCW_TRAFFIC = {"src_sha": "0a41074ea2c07520", "fetch_kib": 3371230.0, "write_kib": 4269713.3, "fetch_factor": 2.000,
+DMCW_TRAFFIC = {"src_sha": "c8d889ae30b559f6", "fetch_kib": 3407345.3, "write_kib": 4309999.3, "fetch_factor": 2.000,
                 "write_factor": 1.000, "walkers": 32768}
 # the same for one step launch of that kernel in VMC mode on the 40-electron
 # molecule (16384 walkers; the mean of 12 step dispatches)
-WRES_VMC_TRAFFIC = {"src_sha": "0a41074ea2c07520", "fetch_kib": 352489.8, "write_kib": 593317.4, "fetch_factor": 2.000,
+WRES_VMC_TRAFFIC = {"src_sha": "c8d889ae30b559f6", "fetch_kib": 353236.2, "write_kib": 593294.2, "fetch_factor": 2.000,
                     "write_factor": 1.000, "walkers": 16384}
 
 
