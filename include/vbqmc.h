@@ -424,6 +424,72 @@ int vbqmc_lm_estimators(int32_t n_params, const double* acc, double* e0, double*
 int vbqmc_lm_solve(int32_t n, double e0, const double* g_l, const double* g_r, const double* h_bar,
                    const double* s_bar, double a_diag, double* dp, double* e_lin);
 
+/*
+ * Orbital rotations (Sec. 2.2, Eq. PsiJVBp, and the partition of the
+ * orbitals that follows it).  The rotation exp(kappa) with kappa =
+ * sum kappa_kl E_kl, E_kl the singlet excitation from orbital l to orbital
+ * k, adds kappa_kl phi_k to orbital l to first order.  Orbital classes come
+ * from the determinants: inactive (in both spins of every determinant),
+ * active (in some), virtual (in none).  An excitation E_kl is kept iff it
+ * acts on the wave function (some determinant holds l and not k in one
+ * spin; no cancellation between determinants is looked for) and k, l share a
+ * localization class; this keeps exactly inactive -> active, inactive ->
+ * virtual, active -> virtual and the acting active -> active excitations.
+ * A pair whose reverse excitation E_lk does not act is one parameter with
+ * kappa_lk = -kappa_kl (kind 1); when both act, kappa_kl and kappa_lk are
+ * two independent parameters (kind 0), each listed once.  Redundancies
+ * among the derivatives (between orbital parameters, or with structure
+ * coefficients) are found from the samples with vbqmc_lm_redundant.
+ *
+ * vbqmc_det_occupancy: the context's determinant products (those a
+ * structure holds with a nonzero coefficient) as occupancies occ [host]
+ * [n][2][n_orbitals] (1 if the orbital is in the spin-up (0) or spin-down
+ * (1) determinant).  occ NULL: only *n_dets is written; EINVAL if max_dets
+ * is smaller than the count.
+ *
+ * vbqmc_rotation_pairs (host only): the kept excitations as pairs [host]
+ * [n][3] = (k, l, kind), ordered by l, then k; loc_class [host][n_orb] or
+ * NULL (one class).  *n_pairs is the count even when it exceeds max_pairs
+ * (then EINVAL and only max_pairs are written).
+ *
+ * vbqmc_orbital_classes (host only): localization classes of the orbitals
+ * of lambda [host][n_orb][M]: orbitals expanded on the same set of basis
+ * functions (the same nonzero pattern) share a class, numbered by the first
+ * orbital of the class.
+ *
+ * vbqmc_rotate_orbitals (host only): lambda_out = exp(K)^T lambda with
+ * K[k][l] = theta_q for each pair q = (k, l, kind) (and K[l][k] = -theta_q
+ * for kind 1), so that orbital l becomes sum_k exp(K)[k][l] phi_k (the
+ * matrix exponential by scaling and squaring of its Taylor series); all
+ * arrays [host], lambda and lambda_out [n_orb][M] (may alias).  EINVAL for
+ * an out-of-range or diagonal pair or a non-finite theta.
+ *
+ * vbqmc_rotation_grad: d/d kappa of ln|Psi| and of E_L from the
+ * per-walker outputs of vbqmc_param_grad at the context's current
+ * parameters, d/d kappa_kl = sum_mu lambda[k][mu] d/d lambda[l][mu] (minus
+ * the same with k and l exchanged for kind 1): dlogpsi, deloc [dev][W][P],
+ * pairs [dev][n_pairs][3], outputs [dev][W][n_pairs]; a pair out of range
+ * gives NaN in its column.  Stream-ordered, FP64.
+ *
+ * vbqmc_lm_redundant (host only): with the parameters taken in order, keep
+ * [host][n] = 1 for a parameter whose residual variance after projection on
+ * the kept earlier ones exceeds tol times its variance Sbar_ii (a Cholesky
+ * factorisation of s_bar [host][n][n] in the given order that skips the
+ * dropped parameters), 0 otherwise (also for Sbar_ii <= 0).  With the
+ * structure coefficients placed first, an orbital parameter whose
+ * derivative lies in their span (and the span of the kept orbital
+ * parameters before it) is dropped.
+ */
+int vbqmc_det_occupancy(const vbqmc_ctx* ctx, int32_t max_dets, uint8_t* occ, int32_t* n_dets);
+int vbqmc_rotation_pairs(int32_t n_orb, int32_t n_dets, const uint8_t* occ, const int32_t* loc_class,
+                         int32_t max_pairs, int32_t* pairs, int32_t* n_pairs);
+int vbqmc_orbital_classes(int32_t n_orb, int32_t M, const double* lam, int32_t* cls);
+int vbqmc_rotate_orbitals(int32_t n_orb, int32_t M, const double* lam, int32_t n_pairs, const int32_t* pairs,
+                          const double* theta, double* lam_out);
+int vbqmc_rotation_grad(vbqmc_ctx* ctx, int64_t W, int32_t n_pairs, const int32_t* pairs, const double* dlogpsi,
+                        const double* deloc, double* out_dlogpsi, double* out_deloc, vbqmc_stream stream);
+int vbqmc_lm_redundant(int32_t n, const double* s_bar, double tol, int32_t* keep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,7 +96,9 @@ EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info"
            "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance", "vbqmc_dmc_advance_noalloc",
            "vbqmc_param_grad_workspace_bytes", "vbqmc_param_grad", "vbqmc_reduce_walkers",
            "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin", "vbqmc_lm_acc_doubles",
-           "vbqmc_lm_accumulate", "vbqmc_lm_estimators", "vbqmc_lm_solve"]
+           "vbqmc_lm_accumulate", "vbqmc_lm_estimators", "vbqmc_lm_solve", "vbqmc_det_occupancy",
+           "vbqmc_rotation_pairs", "vbqmc_orbital_classes", "vbqmc_rotate_orbitals", "vbqmc_rotation_grad",
+           "vbqmc_lm_redundant"]
 
 
 def load_library(path=LIB_PATH):
@@ -141,6 +143,13 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_lm_accumulate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     lib.vbqmc_lm_estimators.argtypes = [i32, pd, pd, pd, pd, pd, pd, pd]
     lib.vbqmc_lm_solve.argtypes = [i32, dbl, pd, pd, pd, pd, dbl, pd, pd]
+    pi32, pu8 = ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_uint8)
+    lib.vbqmc_det_occupancy.argtypes = [vp, i32, pu8, pi32]
+    lib.vbqmc_rotation_pairs.argtypes = [i32, i32, pu8, pi32, i32, pi32, pi32]
+    lib.vbqmc_orbital_classes.argtypes = [i32, i32, pd, pi32]
+    lib.vbqmc_rotate_orbitals.argtypes = [i32, i32, pd, i32, pi32, pd, pd]
+    lib.vbqmc_rotation_grad.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp]
+    lib.vbqmc_lm_redundant.argtypes = [i32, pd, dbl, pi32]
     _lib = lib
     return lib
 
@@ -151,6 +160,10 @@ def _dp(a):
 
 def _ip(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
 def _ptr(t):
@@ -419,6 +432,30 @@ class Context:
         self._rc(self._lib.vbqmc_lm_accumulate(self._h, W, _ptr(dlogpsi), _ptr(deloc), _ptr(eloc), _ptr(weight),
                                                _ptr(acc), _stream()))
 
+    def det_occupancy(self):
+        """The context's determinant products as occupancies [n][2][n_orbitals]
+        (vbqmc_det_occupancy)."""
+        n = ctypes.c_int32()
+        self._rc(self._lib.vbqmc_det_occupancy(self._h, 0, None, ctypes.byref(n)))
+        occ = np.zeros((n.value, 2, self.info["n_orbitals"]), np.uint8)
+        self._rc(self._lib.vbqmc_det_occupancy(self._h, n.value, _up(occ), ctypes.byref(n)))
+        return occ
+
+    def rotation_grad(self, dlogpsi, deloc, pairs):
+        """d/d kappa of ln|Psi| and E_L for the rotation pairs [n][3] (numpy
+        or tensor) from vbqmc_param_grad outputs (vbqmc_rotation_grad)."""
+        import torch
+        W = dlogpsi.shape[0]
+        _check_cuda(dlogpsi, "dlogpsi", torch.float64, (W, self.n_params))
+        _check_cuda(deloc, "deloc", torch.float64, (W, self.n_params))
+        pr = torch.as_tensor(np.ascontiguousarray(pairs, np.int32).reshape(-1, 3), device=dlogpsi.device)
+        n = pr.shape[0]
+        odl = torch.empty(W, n, dtype=torch.float64, device=dlogpsi.device)
+        ode = torch.empty(W, n, dtype=torch.float64, device=dlogpsi.device)
+        self._rc(self._lib.vbqmc_rotation_grad(self._h, W, n, _ptr(pr), _ptr(dlogpsi), _ptr(deloc), _ptr(odl),
+                                               _ptr(ode), _stream()))
+        return odl, ode
+
     def get_params(self):
         p = np.zeros(self.n_params)
         self._rc(self._lib.vbqmc_get_params(self._h, _dp(p)))
@@ -484,6 +521,68 @@ def lm_solve(e0, g_l, g_r, h_bar, s_bar, a_diag=0.0):
     if rc != 0:
         raise VBQMCError(rc, "lm_solve")
     return dp, float(el[0])
+
+
+def rotation_pairs(occ, loc_class=None):
+    """Kept orbital excitations (k, l, kind) [n][3] of a determinant
+    occupancy [n_dets][2][n_orb] (vbqmc_rotation_pairs)."""
+    lib = load_library()
+    occ = np.ascontiguousarray(occ, np.uint8)
+    nd, _, no = occ.shape
+    cls = None if loc_class is None else np.ascontiguousarray(loc_class, np.int32)
+    if cls is not None and cls.shape != (no,):
+        raise ValueError("loc_class needs one entry per orbital")
+    n = ctypes.c_int32()
+    rc = lib.vbqmc_rotation_pairs(no, nd, _up(occ), None if cls is None else _ip(cls), 0, None, ctypes.byref(n))
+    if rc != 0 and n.value == 0:
+        raise VBQMCError(rc, "rotation_pairs")
+    pairs = np.zeros((max(1, n.value), 3), np.int32)
+    rc = lib.vbqmc_rotation_pairs(no, nd, _up(occ), None if cls is None else _ip(cls), n.value, _ip(pairs),
+                                  ctypes.byref(n))
+    if rc != 0:
+        raise VBQMCError(rc, "rotation_pairs")
+    return pairs[:n.value]
+
+
+def orbital_classes(lam):
+    """Localization class of each orbital (same nonzero pattern, same class)."""
+    lib = load_library()
+    lam = np.ascontiguousarray(lam, np.float64)
+    cls = np.zeros(lam.shape[0], np.int32)
+    rc = lib.vbqmc_orbital_classes(lam.shape[0], lam.shape[1], _dp(lam), _ip(cls))
+    if rc != 0:
+        raise VBQMCError(rc, "orbital_classes")
+    return cls
+
+
+def rotate_orbitals(lam, pairs, theta):
+    """lambda' = exp(K)^T lambda for the rotation parameters theta of pairs."""
+    lib = load_library()
+    lam = np.ascontiguousarray(lam, np.float64)
+    pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 3)
+    theta = np.ascontiguousarray(theta, np.float64)
+    if theta.shape != (pairs.shape[0],):
+        raise ValueError("one theta per pair")
+    out = np.zeros_like(lam)
+    rc = lib.vbqmc_rotate_orbitals(lam.shape[0], lam.shape[1], _dp(lam), pairs.shape[0], _ip(pairs), _dp(theta),
+                                   _dp(out))
+    if rc != 0:
+        raise VBQMCError(rc, "rotate_orbitals")
+    return out
+
+
+def lm_redundant(s_bar, tol=1e-8):
+    """Mask of the parameters kept (in order) by vbqmc_lm_redundant."""
+    lib = load_library()
+    s_bar = np.ascontiguousarray(s_bar, np.float64)
+    n = s_bar.shape[0]
+    if s_bar.shape != (n, n):
+        raise ValueError("s_bar must be square")
+    keep = np.zeros(n, np.int32)
+    rc = lib.vbqmc_lm_redundant(n, _dp(s_bar), float(tol), _ip(keep))
+    if rc != 0:
+        raise VBQMCError(rc, "lm_redundant")
+    return keep.astype(bool)
 
 
 def _jvb_function():

@@ -56,6 +56,9 @@ hipError_t launch_record_eloc(const DevWF& wf, const DevWF* dwf, int64_t W, cons
 hipError_t launch_reduce(int64_t W, int K, const double* wts, const double* in, double* out, hipStream_t s);
 hipError_t launch_lm_accumulate(int P, int64_t W, const double* O, const double* D, const double* E,
                                 const double* w, double* acc, hipStream_t s);
+hipError_t launch_rotation_grad(int P, int lam_off, int M, int nop, int norb, int64_t W, int npair,
+                                const int* pairs, const double* lamT, const double* dl, const double* de,
+                                double* odl, double* ode, hipStream_t s);
 hipError_t launch_param_grad(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, double* dlogpsi, double* deloc,
                              double* ws, size_t ws_doubles, hipStream_t s);
 size_t param_grad_ws_doubles(const DevWF& wf, int64_t W);
@@ -1816,6 +1819,194 @@ int vbqmc_lm_solve(int32_t n, double e0, const double* g_l, const double* g_r, c
 // ---------------------------------------------------------------------------
 // structure weights (host)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Orbital rotations (Sec. 2.2, Eq. PsiJVBp and the passage on orbital classes)
+// ---------------------------------------------------------------------------
+
+int vbqmc_det_occupancy(const vbqmc_ctx* x, int32_t max_dets, uint8_t* occ, int32_t* n_dets) {
+  if (!x || !n_dets) return VBQMC_EINVAL;
+  // determinant pairs that some structure holds with a nonzero coefficient
+  std::vector<int> live;
+  for (size_t k = 0; k < x->pair_up.size(); ++k) {
+    bool nz = false;
+    for (auto& pr : x->pair_links[k]) nz = nz || pr.second != 0.0;
+    if (nz) live.push_back((int)k);
+  }
+  *n_dets = (int32_t)live.size();
+  if (!occ) return VBQMC_OK;
+  if (max_dets < (int32_t)live.size()) return VBQMC_EINVAL;
+  const size_t no = (size_t)x->norb;
+  std::fill(occ, occ + live.size() * 2 * no, (uint8_t)0);
+  for (size_t t = 0; t < live.size(); ++t) {
+    const int k = live[t];
+    for (int o : x->sp[0].sets[x->pair_up[k]]) occ[(t * 2 + 0) * no + o] = 1;
+    for (int o : x->sp[1].sets[x->pair_dn[k]]) occ[(t * 2 + 1) * no + o] = 1;
+  }
+  return VBQMC_OK;
+}
+
+namespace {
+// E_kl (orbital l -> orbital k, either spin) acting on a determinant gives a
+// nonzero determinant iff some spin holds l and not k; on the sum of
+// determinants it is taken as nonzero iff that holds for one of them
+bool excitation_nonzero(int no, int nd, const uint8_t* occ, int k, int l) {
+  for (int t = 0; t < nd; ++t)
+    for (int s = 0; s < 2; ++s) {
+      const uint8_t* o = occ + ((size_t)t * 2 + s) * no;
+      if (o[l] && !o[k]) return true;
+    }
+  return false;
+}
+}  // namespace
+
+int vbqmc_rotation_pairs(int32_t n_orb, int32_t n_dets, const uint8_t* occ, const int32_t* loc_class,
+                         int32_t max_pairs, int32_t* pairs, int32_t* n_pairs) {
+  if (n_orb < 1 || n_dets < 1 || !occ || !n_pairs || max_pairs < 0 || (max_pairs > 0 && !pairs))
+    return VBQMC_EINVAL;
+  int32_t np = 0;
+  for (int l = 0; l < n_orb; ++l)
+    for (int k = 0; k < n_orb; ++k) {
+      if (k == l || (loc_class && loc_class[k] != loc_class[l])) continue;
+      if (!excitation_nonzero(n_orb, n_dets, occ, k, l)) continue;
+      // both directions act: two independent parameters, each listed from
+      // its own source orbital; one direction only: kappa_lk = -kappa_kl
+      const int kind = excitation_nonzero(n_orb, n_dets, occ, l, k) ? 0 : 1;
+      if (np < max_pairs) {
+        pairs[3 * np] = k;
+        pairs[3 * np + 1] = l;
+        pairs[3 * np + 2] = kind;
+      }
+      ++np;
+    }
+  *n_pairs = np;
+  return np <= max_pairs ? VBQMC_OK : VBQMC_EINVAL;
+}
+
+int vbqmc_orbital_classes(int32_t n_orb, int32_t M, const double* lam, int32_t* cls) {
+  if (n_orb < 1 || M < 1 || !lam || !cls) return VBQMC_EINVAL;
+  for (int p = 0; p < n_orb; ++p) {
+    cls[p] = p;
+    for (int q = 0; q < p; ++q) {
+      bool same = true;
+      for (int mu = 0; mu < M && same; ++mu)
+        same = (lam[(size_t)p * M + mu] != 0.0) == (lam[(size_t)q * M + mu] != 0.0);
+      if (same) {
+        cls[p] = cls[q];
+        break;
+      }
+    }
+  }
+  return VBQMC_OK;
+}
+
+int vbqmc_rotate_orbitals(int32_t n_orb, int32_t M, const double* lam, int32_t n_pairs, const int32_t* pairs,
+                          const double* theta, double* lam_out) {
+  if (n_orb < 1 || M < 1 || !lam || !lam_out || n_pairs < 0 || (n_pairs > 0 && (!pairs || !theta)))
+    return VBQMC_EINVAL;
+  const int n = n_orb;
+  // generator K: orbital l gains K[k][l] phi_k
+  std::vector<double> K((size_t)n * n, 0.0);
+  for (int q = 0; q < n_pairs; ++q) {
+    const int k = pairs[3 * q], l = pairs[3 * q + 1], kind = pairs[3 * q + 2];
+    if (k < 0 || k >= n || l < 0 || l >= n || k == l || kind < 0 || kind > 1 || !std::isfinite(theta[q]))
+      return VBQMC_EINVAL;
+    K[(size_t)k * n + l] += theta[q];
+    if (kind == 1) K[(size_t)l * n + k] -= theta[q];
+  }
+  // exp(K) by scaling and squaring: the Taylor series of exp(K / 2^j) with
+  // ||K / 2^j||_1 <= 1/2, summed until the terms stop changing the sum
+  double nrm = 0.0;
+  for (int c = 0; c < n; ++c) {
+    double a = 0.0;
+    for (int r = 0; r < n; ++r) a += std::fabs(K[(size_t)r * n + c]);
+    nrm = std::max(nrm, a);
+  }
+  int j = 0;
+  while (nrm > 0.5 && j < 1000) {
+    nrm *= 0.5;
+    ++j;
+  }
+  const double sc = std::ldexp(1.0, -j);
+  std::vector<double> A((size_t)n * n), E((size_t)n * n, 0.0), T((size_t)n * n, 0.0), U((size_t)n * n);
+  for (size_t i = 0; i < A.size(); ++i) A[i] = K[i] * sc;
+  for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = T[(size_t)i * n + i] = 1.0;
+  auto matmul = [n](const std::vector<double>& X, const std::vector<double>& Y, std::vector<double>& Z) {
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        double a = 0.0;
+        for (int m = 0; m < n; ++m) a += X[(size_t)r * n + m] * Y[(size_t)m * n + c];
+        Z[(size_t)r * n + c] = a;
+      }
+  };
+  for (int t = 1; t <= 40; ++t) {
+    matmul(T, A, U);  // T = A^t / t!
+    double tn = 0.0;
+    for (size_t i = 0; i < U.size(); ++i) {
+      T[i] = U[i] / t;
+      E[i] += T[i];
+      tn = std::max(tn, std::fabs(T[i]));
+    }
+    if (tn == 0.0 || tn < 1e-18) break;
+  }
+  for (int r = 0; r < j; ++r) {
+    matmul(E, E, U);
+    E.swap(U);
+  }
+  // lambda'_l = sum_k exp(K)[k][l] lambda_k
+  std::vector<double> out((size_t)n * M, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int k = 0; k < n; ++k) {
+      const double e = E[(size_t)k * n + l];
+      if (e == 0.0) continue;
+      for (int mu = 0; mu < M; ++mu) out[(size_t)l * M + mu] += e * lam[(size_t)k * M + mu];
+    }
+  std::copy(out.begin(), out.end(), lam_out);
+  return VBQMC_OK;
+}
+
+int vbqmc_rotation_grad(vbqmc_ctx* x, int64_t W, int32_t n_pairs, const int32_t* pairs, const double* dlogpsi,
+                        const double* deloc, double* out_dlogpsi, double* out_deloc, vbqmc_stream stream) {
+  if (!x || W < 0 || n_pairs < 0) return fail(x, VBQMC_EINVAL, "rotation_grad: bad arguments");
+  if (W == 0 || n_pairs == 0) return VBQMC_OK;
+  if (!pairs || !dlogpsi || !deloc || !out_dlogpsi || !out_deloc || W > 0x7fffffff)
+    return fail(x, VBQMC_EINVAL, "rotation_grad: bad arguments");
+  hipError_t e = launch_rotation_grad(n_params(x), x->nstruct, x->M, x->nop, x->norb, W, n_pairs, pairs, x->d_lamT,
+                                      dlogpsi, deloc, out_dlogpsi, out_deloc, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "rotation_grad");
+}
+
+int vbqmc_lm_redundant(int32_t n, const double* s_bar, double tol, int32_t* keep) {
+  if (n < 1 || !s_bar || !keep || !(tol >= 0.0) || !std::isfinite(tol)) return VBQMC_EINVAL;
+  // Cholesky factor of Sbar over the parameters kept so far (row i of L
+  // stored for each kept i, columns in kept order)
+  std::vector<int> kept;
+  std::vector<double> L;  // kept.size() rows of length n
+  std::vector<double> y;
+  for (int i = 0; i < n; ++i) {
+    const double d = s_bar[(size_t)i * n + i];
+    keep[i] = 0;
+    if (!(d > 0.0) || !std::isfinite(d)) continue;
+    const size_t m = kept.size();
+    y.assign(m, 0.0);
+    double r = d;
+    for (size_t a = 0; a < m; ++a) {
+      double v = s_bar[(size_t)i * n + kept[a]];
+      for (size_t b = 0; b < a; ++b) v -= L[a * n + b] * y[b];
+      y[a] = v / L[a * n + a];
+      r -= y[a] * y[a];
+    }
+    // residual variance of parameter i after its projection on the kept ones
+    if (r > tol * d) {
+      keep[i] = 1;
+      L.resize((m + 1) * n, 0.0);
+      for (size_t b = 0; b < m; ++b) L[m * n + b] = y[b];
+      L[m * n + m] = std::sqrt(r);
+      kept.push_back(i);
+    }
+  }
+  return VBQMC_OK;
+}
+
 int vbqmc_weights_chirgwin_coulson(int32_t n, const double* S, const double* c, double* w) {
   if (n < 1 || !S || !c || !w) return VBQMC_EINVAL;
   double tot = 0;

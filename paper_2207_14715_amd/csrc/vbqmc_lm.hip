@@ -81,4 +81,49 @@ hipError_t launch_lm_accumulate(int P, int64_t W, const double* O, const double*
   return hipGetLastError();
 }
 
+// Orbital-rotation derivatives (Sec. 2.2, Eq. PsiJVBp) from the orbital
+// coefficient derivatives of the adjoint.  To first order the rotation
+// exp(kappa_kl E_kl) adds kappa_kl phi_k to orbital l, i.e. lambda_l +=
+// kappa_kl lambda_k, so d/d kappa_kl = sum_mu lambda_k,mu d/d lambda_l,mu; a
+// pair tied by kappa_lk = -kappa_kl (kind 1) takes the difference of its two
+// directions.  One workgroup per walker and array (blockIdx.y 0: d lnPsi,
+// 1: d E_L), one thread per pair; a pair whose orbitals or kind are out of
+// range gives NaN (nothing is read for it).
+constexpr int kRotT = 256;
+
+__global__ __launch_bounds__(kRotT) void k_rotation_grad(int P, int lam_off, int M, int nop, int norb, int npair,
+                                                        const int* __restrict__ pairs,
+                                                        const double* __restrict__ lamT,
+                                                        const double* __restrict__ dl, const double* __restrict__ de,
+                                                        double* __restrict__ odl, double* __restrict__ ode) {
+  const int64_t w = blockIdx.x;
+  const double* src = (blockIdx.y == 0 ? dl : de) + w * P + lam_off;
+  double* dst = (blockIdx.y == 0 ? odl : ode) + w * npair;
+  for (int q = threadIdx.x; q < npair; q += kRotT) {
+    const int k = pairs[3 * q], l = pairs[3 * q + 1], kind = pairs[3 * q + 2];
+    if ((unsigned)k >= (unsigned)norb || (unsigned)l >= (unsigned)norb || (unsigned)kind > 1u) {
+      dst[q] = __builtin_nan("");
+      continue;
+    }
+    const double* rl = src + (size_t)l * M;
+    double a = 0.0;
+    for (int mu = 0; mu < M; ++mu) a += lamT[(size_t)mu * nop + k] * rl[mu];
+    if (kind == 1) {
+      const double* rk = src + (size_t)k * M;
+      double b = 0.0;
+      for (int mu = 0; mu < M; ++mu) b += lamT[(size_t)mu * nop + l] * rk[mu];
+      a -= b;
+    }
+    dst[q] = a;
+  }
+}
+
+hipError_t launch_rotation_grad(int P, int lam_off, int M, int nop, int norb, int64_t W, int npair,
+                                const int* pairs, const double* lamT, const double* dl, const double* de,
+                                double* odl, double* ode, hipStream_t s) {
+  hipLaunchKernelGGL(k_rotation_grad, dim3((unsigned)W, 2), dim3(kRotT), 0, s, P, lam_off, M, nop, norb, npair,
+                     pairs, lamT, dl, de, odl, ode);
+  return hipGetLastError();
+}
+
 }  // namespace vbqmc
