@@ -393,6 +393,14 @@ int vbqmc_weights_lowdin(int32_t n, const double* S, const double* c, double* w)
 int vbqmc_lm_acc_doubles(int32_t n_params, int64_t* n);
 int vbqmc_lm_accumulate(vbqmc_ctx* ctx, int64_t W, const double* dlogpsi, const double* deloc, const double* eloc,
                         const double* weight, double* acc, vbqmc_stream stream);
+/*
+ * The same sums for any parameter set the caller assembles per sample
+ * (for instance structure coefficients, orbital-rotation parameters from
+ * vbqmc_rotation_grad and Jastrow parameters): P columns, dlogpsi, deloc
+ * [dev][W][P], acc [dev] of vbqmc_lm_acc_doubles(P).  EINVAL for P < 1.
+ */
+int vbqmc_lm_accumulate_cols(int32_t P, int64_t W, const double* dlogpsi, const double* deloc, const double* eloc,
+                             const double* weight, double* acc, vbqmc_stream stream);
 
 /*
  * Estimators from an accumulator copied to the host (acc [host], length

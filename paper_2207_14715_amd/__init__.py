@@ -98,7 +98,7 @@ EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info"
            "vbqmc_weights_chirgwin_coulson", "vbqmc_weights_lowdin", "vbqmc_lm_acc_doubles",
            "vbqmc_lm_accumulate", "vbqmc_lm_estimators", "vbqmc_lm_solve", "vbqmc_det_occupancy",
            "vbqmc_rotation_pairs", "vbqmc_orbital_classes", "vbqmc_rotate_orbitals", "vbqmc_rotation_grad",
-           "vbqmc_lm_redundant"]
+           "vbqmc_lm_redundant", "vbqmc_lm_accumulate_cols"]
 
 
 def load_library(path=LIB_PATH):
@@ -150,6 +150,7 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_rotate_orbitals.argtypes = [i32, i32, pd, i32, pi32, pd, pd]
     lib.vbqmc_rotation_grad.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp]
     lib.vbqmc_lm_redundant.argtypes = [i32, pd, dbl, pi32]
+    lib.vbqmc_lm_accumulate_cols.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -521,6 +522,23 @@ def lm_solve(e0, g_l, g_r, h_bar, s_bar, a_diag=0.0):
     if rc != 0:
         raise VBQMCError(rc, "lm_solve")
     return dp, float(el[0])
+
+
+def lm_accumulate_cols(dlogpsi, deloc, eloc, acc, weight=None):
+    """vbqmc_lm_accumulate over a caller-assembled parameter set (P = the
+    number of columns of dlogpsi)."""
+    import torch
+    W, P = dlogpsi.shape
+    _check_cuda(dlogpsi, "dlogpsi", torch.float64, (W, P))
+    _check_cuda(deloc, "deloc", torch.float64, (W, P))
+    _check_cuda(eloc, "eloc", torch.float64, (W,))
+    _check_cuda(acc, "acc", torch.float64, (3 * (P + 1) ** 2,))
+    if weight is not None:
+        _check_cuda(weight, "weight", torch.float64, (W,))
+    rc = load_library().vbqmc_lm_accumulate_cols(P, W, _ptr(dlogpsi), _ptr(deloc), _ptr(eloc), _ptr(weight),
+                                                 _ptr(acc), _stream())
+    if rc != 0:
+        raise VBQMCError(rc, "lm_accumulate_cols")
 
 
 def rotation_pairs(occ, loc_class=None):

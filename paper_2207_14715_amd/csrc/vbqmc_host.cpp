@@ -1682,6 +1682,14 @@ int vbqmc_lm_accumulate(vbqmc_ctx* x, int64_t W, const double* dlogpsi, const do
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "lm_accumulate");
 }
 
+int vbqmc_lm_accumulate_cols(int32_t P, int64_t W, const double* dlogpsi, const double* deloc, const double* eloc,
+                             const double* weight, double* acc, vbqmc_stream stream) {
+  if (P < 1 || W < 0 || !acc || (W > 0 && (!dlogpsi || !deloc || !eloc))) return VBQMC_EINVAL;
+  if (W == 0) return VBQMC_OK;
+  hipError_t e = launch_lm_accumulate(P, W, dlogpsi, deloc, eloc, weight, acc, (hipStream_t)stream);
+  return e == hipSuccess ? VBQMC_OK : VBQMC_EHIP;
+}
+
 int vbqmc_lm_estimators(int32_t P, const double* acc, double* e0, double* g_l, double* g_r, double* h_bar,
                         double* s_bar, double* var) {
   if (P < 1 || !acc || !e0 || !g_l || !g_r || !h_bar || !s_bar) return VBQMC_EINVAL;
