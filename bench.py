@@ -137,6 +137,8 @@ def main():
                     help="walkers (target population for DMC; default: the workload's)")
     ap.add_argument("--steps-per-launch", type=int, default=100,
                     help="VMC steps per call (warm-up calls, and timed calls of the row kernel)")
+    ap.add_argument("--no-precision-compare", action="store_true",
+                    help="dmc form: skip the short mixed-precision run reported beside the FP64 line")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "mixed"],
                     help="mixed: FP32 trial/proposal rows, FP64 inverse rebuilt before every E_L and FP64 E_L")
     ap.add_argument("--walker-lanes", type=int, default=0, choices=[0, 16, 32, 64],
@@ -596,6 +598,38 @@ def _src_sha(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def _dmc_mixed_compare(vb, system, c64, R_burn, W, tau, fp64_value, steps=10):
+    """The mixed-precision DMC form (FP32 proposal rows, FP64 determinants and
+    E_L) from the same burn-in walkers: walker-moves/s over `steps` timed
+    steps (after one warm-up step) and, at the configurations those steps
+    leave, each walker's recorded E_L against an FP64 evaluation."""
+    import numpy as np
+    import torch
+    cm = vb.Context(system, precision="mixed")
+    st = [cm.new_state(3 * W), cm.new_state(3 * W)]
+    cm.walkers_init(R_burn, st[0])
+    et = float(cm.record_eloc(st[0], W).median().item())
+    out = cm.dmc_advance(st, W, 1, 4044, 0, tau, et, W)
+    Wc, et = out["W"], out["e_trial"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = cm.dmc_advance(st, Wc, steps, 4044, 1, tau, et, W)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    moves = float(out["pop"].sum().item())
+    Wn = out["W"]
+    e_rec = cm.record_eloc(st[0], Wn)
+    e_64 = c64.evaluate(cm.positions(st[0], Wn).contiguous(), want=("eloc",))["eloc"]
+    d = (e_rec - e_64).abs().cpu().numpy()
+    del st
+    torch.cuda.empty_cache()
+    return {"value": moves / wall, "unit": "walker-moves/s", "steps": steps,
+            "dmc_kernel": {1: "workgroup per walker", 2: "electron-major", 3: "walker-resident"}[cm.info["dmc_kernel"]],
+            "speed_vs_fp64": moves / wall / fp64_value,
+            "abs_dEL_max": float(np.nanmax(d)), "abs_dEL_p99": float(np.nanpercentile(d, 99)),
+            "abs_dEL_median": float(np.nanmedian(d)), "meets_1e-5": bool(np.nanmax(d) <= 1e-5)}
+
+
 def dmc_form(args):
     """The headline: fixed-node DMC on the 16-nucleus, 64-electron,
     240-function, 32-structure / 128-determinant molecule with 32768 target
@@ -627,6 +661,7 @@ def dmc_form(args):
     # FP64 burn-in for every form, so that the forms start from the same walkers
     c64.walkers_init(R0, st[0])
     c64.vmc_advance(st[0], 3, 17, 0, 0.3, False, None, W)
+    R_burn = c64.positions(st[0], W).clone()
     # the synthetic trial function has a wide E_L distribution: start E_T at
     # the median
     et = float(c64.record_eloc(st[0], W).median().item())
@@ -702,6 +737,10 @@ def dmc_form(args):
                      "flops_per_launch": flops_launch, "flops_per_walker_step": fl_walker,
                      "walkers_per_launch": float(pop.mean())},
     }
+    if args.precision == "fp64" and not args.een and not args.no_precision_compare:
+        del st
+        torch.cuda.empty_cache()
+        line["mixed_precision"] = _dmc_mixed_compare(vb, system, c64, R_burn, W, tau, line["value"])
     if not args.no_cpu_baseline:
         # (the oracle's f_een gradients by jets cost about 50x: a smaller sample)
         line["cpu_baseline"] = cpu_baseline_dmc(system, walkers=32, steps=2) if args.een else cpu_baseline_dmc(system)
