@@ -522,37 +522,38 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
       oE[I] = re - r * ebar;
     }
   }
-  // Jastrow: electron-electron parameters [b_anti, b_par, b3..b6]
+  // Jastrow: electron-electron parameters [b_anti, b_par, b3..b6], one
+  // electron pair per thread
   const int jb = wf.nstruct + wf.norb * M;
   {
     double acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     const double* R = l.R();
-    for (int i = threadIdx.x; i < N; i += NT) {
-      for (int j = i + 1; j < N; ++j) {
-        double dx = R[3 * i] - R[3 * j], dy = R[3 * i + 1] - R[3 * j + 1], dz = R[3 * i + 2] - R[3 * j + 2];
-        double r = sqrt(dx * dx + dy * dy + dz * dz);
-        bool anti = spin_of(wf, i) != spin_of(wf, j);
-        double a = anti ? wf.ee[0] : wf.ee[1], b = anti ? wf.ee[2] : wf.ee[3];
-        double proj = 0.0;
-        {
-          const double* gi = l.gU() + 3 * i;
-          const double* gj = l.gU() + 3 * j;
-          const double* di = l.gD() + 3 * i;
-          const double* dj = l.gD() + 3 * j;
-          proj = (dx * (gi[0] + di[0] - gj[0] - dj[0]) + dy * (gi[1] + di[1] - gj[1] - dj[1]) +
-                  dz * (gi[2] + di[2] - gj[2] - dj[2])) / r;
-        }
+    for (int pidx = threadIdx.x; pidx < N * N; pidx += NT) {
+      const int i = pidx / N, j = pidx - i * N;
+      if (j <= i) continue;
+      double dx = R[3 * i] - R[3 * j], dy = R[3 * i + 1] - R[3 * j + 1], dz = R[3 * i + 2] - R[3 * j + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      bool anti = spin_of(wf, i) != spin_of(wf, j);
+      double a = anti ? wf.ee[0] : wf.ee[1], b = anti ? wf.ee[2] : wf.ee[3];
+      double proj = 0.0;
+      {
+        const double* gi = l.gU() + 3 * i;
+        const double* gj = l.gU() + 3 * j;
+        const double* di = l.gD() + 3 * i;
+        const double* dj = l.gD() + 3 * j;
+        proj = (dx * (gi[0] + di[0] - gj[0] - dj[0]) + dy * (gi[1] + di[1] - gj[1] - dj[1]) +
+                dz * (gi[2] + di[2] - gj[2] - dj[2])) / r;
+      }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          if (q == 0 && !anti) continue;
-          if (q == 1 && anti) continue;
-          double du, du1, du2;
-          pair_param(r, wf.kappa, a, b, q < 2 ? 1 : q, du, du1, du2);
-          acc[q] += du;
-          acc[6 + q] += -0.5 * (2.0 * (du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
-        }
+      for (int q = 0; q < 6; ++q) {
+        if (q == 0 && !anti) continue;
+        if (q == 1 && anti) continue;
+        double du, du1, du2;
+        pair_param(r, wf.kappa, a, b, q < 2 ? 1 : q, du, du1, du2);
+        acc[q] += du;
+        acc[6 + q] += -0.5 * (2.0 * (du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
       }
     }
     block_sum<NT, 12>(acc, l.red());
@@ -562,35 +563,77 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
         oE[jb + q] = acc[6 + q];
       }
   }
-  // electron-nucleus parameters [a1..a6] per nucleus
-  for (int al = 0; al < wf.nnuc; ++al) {
-    double acc[12];
+  // electron-nucleus parameters [a1..a6] per nucleus: nucleus al on a
+  // segment of SEG lanes (lane i of the segment takes electron i), summed
+  // within the segment; more than 64 electrons: one nucleus at a time over
+  // the block
+  const int SEG = N <= 16 ? 16 : (N <= 32 ? 32 : 64);
+  if (N <= 64) {
+    const int per = NT / SEG;  // nuclei per pass over the block
+    const int i = threadIdx.x % SEG;
+    for (int base = 0; base < wf.nnuc; base += per) {
+      const int al = base + threadIdx.x / SEG;
+      double acc[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-    const double* ja = l.en() + 6 * al;
-    const double* nu = l.nuc() + 4 * al;
-    for (int i = threadIdx.x; i < N; i += NT) {
-      const double* R = l.R() + 3 * i;
-      double dx = R[0] - nu[0], dy = R[1] - nu[1], dz = R[2] - nu[2];
-      double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double* gi = l.gU() + 3 * i;
-      const double* di = l.gD() + 3 * i;
-      double proj = (dx * (gi[0] + di[0]) + dy * (gi[1] + di[1]) + dz * (gi[2] + di[2])) / r;
+      for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+      if (al < wf.nnuc && i < N) {
+        const double* ja = l.en() + 6 * al;
+        const double* nu = l.nuc() + 4 * al;
+        const double* R = l.R() + 3 * i;
+        double dx = R[0] - nu[0], dy = R[1] - nu[1], dz = R[2] - nu[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double* gi = l.gU() + 3 * i;
+        const double* di = l.gD() + 3 * i;
+        double proj = (dx * (gi[0] + di[0]) + dy * (gi[1] + di[1]) + dz * (gi[2] + di[2])) / r;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        double du, du1, du2;
-        pair_param(r, wf.kappa, ja[0], ja[1], q, du, du1, du2);
-        acc[q] += du;
-        acc[6 + q] += -0.5 * ((du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
+        for (int q = 0; q < 6; ++q) {
+          double du, du1, du2;
+          pair_param(r, wf.kappa, ja[0], ja[1], q, du, du1, du2);
+          acc[q] = du;
+          acc[6 + q] = -0.5 * ((du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
+        }
       }
+      // (every lane of the wavefront takes part; xor offsets below SEG stay
+      // inside the segment)
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        for (int off = SEG / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+      if (i == 0 && al < wf.nnuc)
+        for (int q = 0; q < 6; ++q) {
+          oL[jb + 6 + 6 * al + q] = acc[q];
+          oE[jb + 6 + 6 * al + q] = acc[6 + q];
+        }
     }
-    block_sum<NT, 12>(acc, l.red());
-    if (threadIdx.x == 0)
-      for (int q = 0; q < 6; ++q) {
-        oL[jb + 6 + 6 * al + q] = acc[q];
-        oE[jb + 6 + 6 * al + q] = acc[6 + q];
+  } else {
+    for (int al = 0; al < wf.nnuc; ++al) {
+      double acc[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+      const double* ja = l.en() + 6 * al;
+      const double* nu = l.nuc() + 4 * al;
+      for (int i = threadIdx.x; i < N; i += NT) {
+        const double* R = l.R() + 3 * i;
+        double dx = R[0] - nu[0], dy = R[1] - nu[1], dz = R[2] - nu[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double* gi = l.gU() + 3 * i;
+        const double* di = l.gD() + 3 * i;
+        double proj = (dx * (gi[0] + di[0]) + dy * (gi[1] + di[1]) + dz * (gi[2] + di[2])) / r;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          double du, du1, du2;
+          pair_param(r, wf.kappa, ja[0], ja[1], q, du, du1, du2);
+          acc[q] += du;
+          acc[6 + q] += -0.5 * ((du2 + 2.0 * du1 / r) + 2.0 * du1 * proj);
+        }
       }
-    __syncthreads();
+      block_sum<NT, 12>(acc, l.red());
+      if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) {
+          oL[jb + 6 + 6 * al + q] = acc[q];
+          oE[jb + 6 + 6 * al + q] = acc[6 + q];
+        }
+      __syncthreads();
+    }
   }
   // f_een coefficients [c_1..c_23] per nucleus: d ln|Psi|/dc_t is the sum
   // over pairs of term t, T_t = a^k B_t (a = Rbar_ij, B_t = b^(l+m) c^m +
