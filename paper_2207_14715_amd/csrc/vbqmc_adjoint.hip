@@ -345,10 +345,14 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   for (int g0 = 0; g0 < N; g0 += kGroup) {
     int ne = min(kGroup, N - g0);
     group_radial<NT, PREC>(wf, l, l.R(), g0, ne);
-    for (int c = 0; c < 5; ++c) {
-      group_channel<NT, PREC>(wf, l, ne, c);
-      for (int idx = threadIdx.x; idx < ne * nop; idx += NT) aPhi[(c * N + g0) * nop + idx] = l.Phi()[idx];
-      __syncthreads();
+    if constexpr (PREC == 0) {
+      group_channels_tiles<NT>(wf, l, ne, 0, 5, aPhi + g0 * nop, N * nop);
+    } else {
+      for (int c = 0; c < 5; ++c) {
+        group_channel<NT, PREC>(wf, l, ne, c);
+        for (int idx = threadIdx.x; idx < ne * nop; idx += NT) aPhi[(c * N + g0) * nop + idx] = l.Phi()[idx];
+        __syncthreads();
+      }
     }
   }
   for (int idx = threadIdx.x; idx < N * nop; idx += NT) {
