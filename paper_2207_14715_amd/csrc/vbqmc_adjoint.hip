@@ -214,6 +214,14 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
         V[18 * u + 9 + k] = vx[k];
       }
     }
+    if (wf.adj_save && st.n > 0) {
+      // B, B S, T, B Xi of this spin for the second pass
+      const int n = st.n, nn = n * n, np = n * nP;
+      double* sv = l.L + wf.l_aSave[s];
+      const double* BS = l.L + wf.l_aBS;
+      for (int k = threadIdx.x; k < 2 * nn + 2 * np; k += NT)
+        sv[k] = k < nn ? B[k] : (k < 2 * nn ? BS[k - nn] : (k < 2 * nn + np ? T[k - 2 * nn] : BXi[k - 2 * nn - np]));
+    }
     __syncthreads();
   }
   return true;
@@ -231,13 +239,22 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
     const SpinTab& st = wf.sp[s];
     const int n = st.n, nP = st.nP, e0 = st.e0;
     if (n == 0) continue;
-    double ld0, sg0, trS;
-    adj_ref_spin<NT>(wf, l, aPhi, s, B, K0, S, ld0, sg0, trS);
-    const double* uinf = l.L + wf.l_aU[s];
-    const double* V = l.L + wf.l_aV[s];
+    const double* Bp = B;
     const double* BS = l.L + wf.l_aBS;
     const double* T = l.L + wf.l_aT;
     const double* BXi = l.L + wf.l_aBXi;
+    if (wf.adj_save) {
+      const double* sv = l.L + wf.l_aSave[s];
+      Bp = sv;
+      BS = sv + n * n;
+      T = sv + 2 * n * n;
+      BXi = T + n * nP;
+    } else {
+      double ld0, sg0, trS;
+      adj_ref_spin<NT>(wf, l, aPhi, s, B, K0, S, ld0, sg0, trS);
+    }
+    const double* uinf = l.L + wf.l_aU[s];
+    const double* V = l.L + wf.l_aV[s];
     double* Wq = l.L + wf.l_aW;
     double* Wb = Wq + nP * n;
     double* Xq = Wq + 2 * nP * n;
@@ -258,7 +275,7 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
         const double* vx = mi + 9;
         double va[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < e; ++c)
-          for (int c2 = 0; c2 < e; ++c2) va[c] += mi[3 * c + c2] * B[ui[1 + c2] * n + a];
+          for (int c2 = 0; c2 < e; ++c2) va[c] += mi[3 * c + c2] * Bp[ui[1 + c2] * n + a];
         for (int d = 0; d < e; ++d) {
           if (ui[4 + d] != q) continue;
           double U = 0.0;
@@ -295,8 +312,8 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
           sTX += t * Xq[q * n + a];
           sBX += BXi[b * nP + q] * Wq[q * n + a];
         }
-        g = Om * B[b * n + a] - sT;
-        g0 = Lb * B[b * n + a] - sTb - Om * BS[b * n + a] - sBX + sTX;
+        g = Om * Bp[b * n + a] - sT;
+        g0 = Lb * Bp[b * n + a] - sTb - Om * BS[b * n + a] - sBX + sTX;
       } else {
         const int q = col - n;
         o = porb[q];

@@ -1104,6 +1104,28 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     delete x;
     return VBQMC_EHIP;
   }
+  // the adjoint keeps each spin's first-pass B, B S, T and B Xi for its
+  // second pass when they fit the LDS beside its own regions and do not
+  // take a second resident workgroup per CU away (else the second pass
+  // recomputes them)
+  {
+    int need[2], tot = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
+      need[s] = (2 * n * n + 2 * n * nP + 1) / 2 * 2;
+      tot += need[s];
+    }
+    wf.adj_save = 0;
+    wf.l_aSave[0] = wf.l_aSave[1] = 0;
+    const size_t lim = (size_t)x->lds_limit, before = (size_t)wf.lds_adj_doubles * 8,
+                 after = (size_t)(wf.lds_adj_doubles + tot) * 8;
+    if (after <= lim && (2 * before > lim || 2 * after <= lim)) {
+      wf.adj_save = 1;
+      wf.l_aSave[0] = wf.lds_adj_doubles;
+      wf.l_aSave[1] = wf.lds_adj_doubles + need[0];
+      wf.lds_adj_doubles += tot;
+    }
+  }
   if ((size_t)wf.lds_doubles * 8 > (size_t)x->lds_limit) {
     char b[160];
     std::snprintf(b, sizeof b, "system needs %d bytes of LDS per walker, device allows %d", wf.lds_doubles * 8,

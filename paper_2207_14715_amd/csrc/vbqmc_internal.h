@@ -97,6 +97,7 @@ struct DevWF {
   // B Xi [n][nP], the sums W, Wbar, X [3][nP][n], and per distinct spin
   // determinant the inverse of its minor and V Xi_Q ([nU][18])
   int l_aBS, l_aT, l_aXi, l_aBXi, l_aW, l_aV[2];
+  int adj_save, l_aSave[2];  // the first pass's B, B S, T, B Xi per spin, kept for the second (if they fit)
   int lds_doubles, lds_sweep_doubles, lds_finish_doubles, lds_tile_doubles, lds_adj_doubles;
   // wavefront sweep (several walkers per wavefront): walker g's state starts
   // at gw_base + g * gw_stride, and the state offsets of that layout are
