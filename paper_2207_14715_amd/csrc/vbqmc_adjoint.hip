@@ -26,6 +26,7 @@
 // their closed forms (Euler form in c; pair-function derivatives).
 
 #include "vbqmc_device.h"
+#include "vbqmc_group.h"
 
 namespace vbqmc {
 
@@ -118,7 +119,26 @@ __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, i
     K0[idx] = adj_kin(wf, l, aPhi, e0 + i, ref[j]);
   }
   __syncthreads();
-  if (!gj_invert<NT>(l, B, n, ld0, sg0)) return false;
+  if (n <= 64) {
+    // one wavefront inverts (no block barrier per pivot); its outcome
+    // reaches the block through the scalar slots
+    double* sc = l.sc();
+    if (threadIdx.x < 64) {
+      double ld, sg;
+      const bool ok = gj_invert_h<64>(B, n, threadIdx.x, l.ipiv(), l.f(), ld, sg);
+      if (threadIdx.x == 0) {
+        sc[SC_GJ_OK] = ok ? 1.0 : 0.0;
+        sc[SC_GJ_LD] = ok ? ld : 0.0;
+        sc[SC_GJ_SG] = ok ? sg : 0.0;
+      }
+    }
+    __syncthreads();
+    if (sc[SC_GJ_OK] == 0.0) return false;
+    ld0 = sc[SC_GJ_LD];
+    sg0 = sc[SC_GJ_SG];
+  } else if (!gj_invert<NT>(l, B, n, ld0, sg0)) {
+    return false;
+  }
   for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
     const int j = idx / nP, q = idx - j * nP;
     double t = 0.0;
