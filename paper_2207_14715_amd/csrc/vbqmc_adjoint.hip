@@ -104,7 +104,7 @@ __device__ __forceinline__ double adj_kin(const DevWF& wf, const Ld& l, const do
 // T, Xi, B S, B Xi; false if the reference is singular (block-uniform)
 template <int NT>
 __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, int s, double* B, double* K0,
-                             double* S, double& ld0, double& sg0, double& trS) {
+                             double* S, double& ld0, double& sg0, double& trS, bool pre = false) {
   const SpinTab& st = wf.sp[s];
   const int n = st.n, nP = st.nP, e0 = st.e0, N = wf.N, nop = wf.nop;
   const int* ref = l.ref(s);
@@ -113,13 +113,15 @@ __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, i
   double* T = l.L + wf.l_aT;
   double* Xi = l.L + wf.l_aXi;
   double* BXi = l.L + wf.l_aBXi;
+  // (pre: B already holds the inverse, ld0 and sg0 are given)
   for (int idx = threadIdx.x; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx - i * n;
-    B[idx] = aPhi[(0 * N + e0 + i) * nop + ref[j]];
+    if (!pre) B[idx] = aPhi[(0 * N + e0 + i) * nop + ref[j]];
     K0[idx] = adj_kin(wf, l, aPhi, e0 + i, ref[j]);
   }
   __syncthreads();
-  if (n <= 64) {
+  if (pre) {
+  } else if (n <= 64) {
     // one wavefront inverts (no block barrier per pivot); its outcome
     // reaches the block through the scalar slots
     double* sc = l.sc();
@@ -182,13 +184,55 @@ __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, i
 // reference is singular
 template <int NT>
 __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, double* B, double* K0, double* S) {
+  // with the first-pass copies kept, both spins' references are staged in
+  // their keep areas and inverted at once, wavefront s taking spin s
+  bool pre = false;
+  if constexpr (NT >= 128) {
+    pre = wf.adj_save && wf.sp[0].n <= 64 && wf.sp[1].n <= 64;
+    if (pre) {
+      double* sc = l.sc();
+      for (int s = 0; s < 2; ++s) {
+        const int n = wf.sp[s].n, e0 = wf.sp[s].e0;
+        const int* ref = l.ref(s);
+        double* sv = l.L + wf.l_aSave[s];
+        for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+          const int i = idx / n, j = idx - i * n;
+          sv[idx] = aPhi[(e0 + i) * wf.nop + ref[j]];
+        }
+      }
+      __syncthreads();
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      if (wave < 2 && wf.sp[wave].n > 0) {
+        const int n = wf.sp[wave].n, nP = wf.sp[wave].nP;
+        double* sv = l.L + wf.l_aSave[wave];
+        double* f = sv + 2 * n * n + 2 * n * nP;
+        int* piv = (int*)(f + n);
+        double ld, sg;
+        const bool ok = gj_invert_h<64>(sv, n, lane, piv, f, ld, sg);
+        if (lane == 0) {
+          sc[SC_GJ_OK + 3 * wave] = ok ? 1.0 : 0.0;
+          sc[SC_GJ_LD + 3 * wave] = ok ? ld : 0.0;
+          sc[SC_GJ_SG + 3 * wave] = ok ? sg : 0.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
   for (int s = 0; s < 2; ++s) {
     const SpinTab& st = wf.sp[s];
     const int nP = st.nP;
     double* uinf = l.L + wf.l_aU[s];
     double* V = l.L + wf.l_aV[s];
     double ld0 = 0.0, sg0 = 1.0, trS = 0.0;
-    if (st.n > 0 && !adj_ref_spin<NT>(wf, l, aPhi, s, B, K0, S, ld0, sg0, trS)) return false;
+    double* Bs = B;
+    if (pre && st.n > 0) {
+      const double* sc = l.sc();
+      if (sc[SC_GJ_OK + 3 * s] == 0.0) return false;
+      ld0 = sc[SC_GJ_LD + 3 * s];
+      sg0 = sc[SC_GJ_SG + 3 * s];
+      Bs = l.L + wf.l_aSave[s];
+    }
+    if (st.n > 0 && !adj_ref_spin<NT>(wf, l, aPhi, s, Bs, K0, S, ld0, sg0, trS, pre)) return false;
     const double* T = l.L + wf.l_aT;
     const double* BXi = l.L + wf.l_aBXi;
     for (int u = threadIdx.x; u < st.nU; u += NT) {
@@ -239,7 +283,7 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
       const int n = st.n, nn = n * n, np = n * nP;
       double* sv = l.L + wf.l_aSave[s];
       const double* BS = l.L + wf.l_aBS;
-      for (int k = threadIdx.x; k < 2 * nn + 2 * np; k += NT)
+      for (int k = threadIdx.x + (pre ? nn : 0); k < 2 * nn + 2 * np; k += NT)
         sv[k] = k < nn ? B[k] : (k < 2 * nn ? BS[k - nn] : (k < 2 * nn + np ? T[k - 2 * nn] : BXi[k - 2 * nn - np]));
     }
     __syncthreads();

@@ -1112,7 +1112,8 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
     int need[2], tot = 0;
     for (int s = 0; s < 2; ++s) {
       const int n = x->sp[s].n, nP = (int)x->sp[s].porb.size();
-      need[s] = (2 * n * n + 2 * n * nP + 1) / 2 * 2;
+      // B, B S, T, B Xi, then the pivot column and pivots of its inversion
+      need[s] = (2 * n * n + 2 * n * nP + n + (n + 1) / 2 + 1) / 2 * 2;
       tot += need[s];
     }
     wf.adj_save = 0;

@@ -143,6 +143,7 @@ enum {
   SC_LOGDET0 = 0, SC_LOGDET1, SC_SGN0, SC_SGN1, SC_NUPD0, SC_NUPD1, SC_ELOC, SC_FLAGS,
   SC_S, SC_U, SC_V, SC_LOGPSI, SC_SIGN, SC_RATIO, SC_ACC, SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3,
   SC_GJ_OK, SC_GJ_LD, SC_GJ_SG,  // a one-wavefront inversion's outcome, ln|det| and sign for the block
+  SC_GJ_OK1, SC_GJ_LD1, SC_GJ_SG1,  // (the same for a second spin inverted at the same time)
   SC_COUNT = 32
 };
 
