@@ -299,10 +299,19 @@ template <int NT>
 __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, double* B, double* K0, double* S,
                               double* G0, double* G) {
   const int N = wf.N, nop = wf.nop;
-  for (int s = 0; s < 2; ++s) {
+  // with the first-pass copies kept, the two spins run at once on the two
+  // halves of the block (their rows of G, G0 are disjoint), spin 1's sums
+  // in the space of the reference matrices, which this pass then leaves
+  // unused
+  const bool par = NT >= 128 && wf.adj_save && 3 * wf.sp[1].n * wf.sp[1].nP <= wf.l_aU[0] - wf.l_aA;
+  const int nth = par ? NT / 2 : NT;
+  const int grp = par ? (int)threadIdx.x / (NT / 2) : 0;
+  const int tid = par ? (int)threadIdx.x - grp * (NT / 2) : (int)threadIdx.x;
+  for (int it = 0; it < (par ? 1 : 2); ++it) {
+    const int s = par ? grp : it;
     const SpinTab& st = wf.sp[s];
     const int n = st.n, nP = st.nP, e0 = st.e0;
-    if (n == 0) continue;
+    if (!par && n == 0) continue;  // (uniform)
     const double* Bp = B;
     const double* BS = l.L + wf.l_aBS;
     const double* T = l.L + wf.l_aT;
@@ -319,12 +328,12 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
     }
     const double* uinf = l.L + wf.l_aU[s];
     const double* V = l.L + wf.l_aV[s];
-    double* Wq = l.L + wf.l_aW;
+    double* Wq = l.L + (par && s == 1 ? wf.l_aA : wf.l_aW);
     double* Wb = Wq + nP * n;
     double* Xq = Wq + 2 * nP * n;
     const int* ref = l.ref(s);
     const int* porb = l.porb(s);
-    for (int idx = threadIdx.x; idx < nP * n; idx += NT) {
+    for (int idx = tid; idx < nP * n; idx += nth) {
       const int q = idx / n, a = idx - q * n;
       double w = 0.0, wb = 0.0, x = 0.0;
       for (int u = 0; u < st.nU; ++u) {
@@ -361,7 +370,7 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
       }
     __syncthreads();
     const int nc = n + nP;
-    for (int idx = threadIdx.x; idx < n * nc; idx += NT) {
+    for (int idx = tid; idx < n * nc; idx += nth) {
       const int a = idx / nc, col = idx - a * nc, e = e0 + a;
       double g, g0;
       int o;
