@@ -32,11 +32,83 @@ namespace vbqmc {
 
 extern __shared__ double lds_adj[];
 
-// all five basis channels of function mu at electron e of the current tile
+// all five basis channels of function mu at electron e of the current tile,
+// from one load of the function's operands
 template <typename T>
 __device__ __forceinline__ void chan_all(const DevWF& wf, const Ld& l, int e, int mu, T* out) {
+  const FnInfo fi = fn_info(l, mu);
+  if (fi.sh < 0) {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) out[c] = chan_value<T>(wf, l, e, mu, c);
+    for (int c = 0; c < 5; ++c) out[c] = T(0);
+    return;
+  }
+  const ChanIn<T> in = chan_load<T, 3>(wf, l, e, fi);
+  out[0] = chan_eval<T>(fi, in, 0);
+  T o4[4];
+  chan_eval4<T>(fi, in, o4);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[1 + c] = o4[c];
+}
+
+// The five orbital-row channels of a group of ne electrons (rows e < ne of
+// channel c to out + c * cstride + e * nop), FP64 on MFMA: a wavefront takes
+// one 16-orbital column tile and a share of the basis functions, forming
+// all five channels of each function from one load; when the column tiles
+// leave wavefronts over, the functions are split among them and the shares
+// are added into the rows in a fixed order (one block barrier per share).
+template <int NT>
+__device__ void adj_rows5(const DevWF& wf, const Ld& l, int ne, double* out, int cstride) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const int nct = wf.nop / 16;
+  const int KQ = max(1, NW / nct);
+  const int nch = wf.Mpad / 16;  // chunks of 16 functions (four k-steps)
+  const double* lam = l.lam<double>();
+  const int e = lane & 15;
+  const bool live = e < ne;
+  // work items: (column tile, share of the functions); with KQ > 1 there is
+  // one item per wavefront (nct * KQ <= NW) and the shares are added in
+  // order
+  const int nitem = nct * KQ;
+  for (int item0 = 0; item0 < nitem; item0 += NW) {
+    const int item = item0 + wave;
+    const bool has = item < nitem;
+    const int ct = has ? item % nct : 0, kq = has ? item / nct : 0;
+    const int col = ct * 16 + (lane & 15);
+    v4d acc0 = {0, 0, 0, 0}, acc1 = acc0, acc2 = acc0, acc3 = acc0, acc4 = acc0;
+    if (has) {
+      const int k_lo = 16 * (kq * nch / KQ), k_hi = 16 * ((kq + 1) * nch / KQ);
+      for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          double ch[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+          if (live) chan_all<double>(wf, l, e, k, ch);
+          const double b = lam[(size_t)k * wf.nop + col];
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ch[0], b, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ch[1], b, acc1, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ch[2], b, acc2, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ch[3], b, acc3, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f64_16x16x4f64(ch[4], b, acc4, 0, 0, 0);
+        }
+      }
+    }
+    // f64 16x16x4 output: register r of lane l holds row 4r + l/16
+    for (int r = 0; r < KQ; ++r) {
+      if (has && kq == r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 4 * q + (lane >> 4);
+          if (row < ne) {
+            double* o = out + row * wf.nop + col;
+            const double v[5] = {acc0[q], acc1[q], acc2[q], acc3[q], acc4[q]};
+#pragma unroll
+            for (int c = 0; c < 5; ++c) o[(size_t)c * cstride] = r > 0 ? o[(size_t)c * cstride] + v[c] : v[c];
+          }
+        }
+      __syncthreads();
+    }
+  }
 }
 
 // derivatives (du, du', du'') of a pair function with respect to one of its
@@ -436,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
     int ne = min(kGroup, N - g0);
     group_radial<NT, PREC>(wf, l, l.R(), g0, ne);
     if constexpr (PREC == 0) {
-      group_channels_tiles<NT>(wf, l, ne, 0, 5, aPhi + g0 * nop, N * nop);
+      adj_rows5<NT>(wf, l, ne, aPhi + g0 * nop, N * nop);
     } else {
       for (int c = 0; c < 5; ++c) {
         group_channel<NT, PREC>(wf, l, ne, c);

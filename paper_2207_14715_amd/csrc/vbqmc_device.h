@@ -785,57 +785,6 @@ __device__ void group_channel(const DevWF& wf, const Ld& l, int ne, int c, doubl
   __syncthreads();
 }
 
-// FP64 channels c_lo .. c_hi - 1 of a group in one sweep: the (channel,
-// 16-orbital column tile) pairs are dealt to the wavefronts, so that more
-// wavefronts than a channel's column tiles have work; channel c's rows
-// e < ne go to out + c * cstride + e * nop (each tile summed as in
-// group_channel, the same bits).
-template <int NT, int GS = 3>
-__device__ void group_channels_tiles(const DevWF& wf, const Ld& l, int ne, int c_lo, int c_hi, double* out,
-                                     int cstride) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int NW = NT / 64;
-  const int nct = wf.nop / 16;
-  const double* lam = l.lam<double>();
-  for (int tile = wave; tile < (c_hi - c_lo) * nct; tile += NW) {
-    const int c = c_lo + tile / nct, ct = tile - (tile / nct) * nct;
-    const int col = ct * 16 + (lane & 15);
-    const int e = lane & 15;
-    const bool live = e < ne;
-    v4d acc = {0, 0, 0, 0};
-    int2 wd[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) wd[u] = fn_word(l, 4 * u + (lane >> 4));
-    for (int k0 = 0; k0 < wf.Mpad; k0 += 16) {
-      double a[4], b[4];
-      FnInfo fi[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        fi[u] = fn_decode(wd[u]);
-        wd[u] = fn_word(l, min(k0 + 16, wf.Mpad - 16) + 4 * u + (lane >> 4));
-      }
-      ChanIn<double> in[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + 4 * u + (lane >> 4);
-        in[u] = chan_load<double, GS>(wf, l, e, fi[u]);
-        b[u] = lam[(size_t)k * wf.nop + col];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = live ? chan_eval<double>(fi[u], in[u], c) : 0.0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-    }
-    // register r of lane l holds row 4r + l/16
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 4 * r + (lane >> 4);
-      if (row < ne) out[(size_t)c * cstride + row * wf.nop + col] = acc[r];
-    }
-  }
-  __syncthreads();
-}
-
 // Channels 1..4 (gradient x, y, z and Laplacian) of function fi from its
 // operands (radial sums with both derivatives).
 template <typename T>
