@@ -199,7 +199,7 @@ __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, i
     double* sc = l.sc();
     if (threadIdx.x < 64) {
       double ld, sg;
-      const bool ok = gj_invert_h<64>(B, n, threadIdx.x, l.ipiv(), l.f(), ld, sg);
+      const bool ok = gj_invert_h<64, true>(B, n, threadIdx.x, l.ipiv(), l.f(), ld, sg);
       if (threadIdx.x == 0) {
         sc[SC_GJ_OK] = ok ? 1.0 : 0.0;
         sc[SC_GJ_LD] = ok ? ld : 0.0;
@@ -280,7 +280,7 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
         double* f = sv + 2 * n * n + 2 * n * nP;
         int* piv = (int*)(f + n);
         double ld, sg;
-        const bool ok = gj_invert_h<64>(sv, n, lane, piv, f, ld, sg);
+        const bool ok = gj_invert_h<64, true>(sv, n, lane, piv, f, ld, sg);
         if (lane == 0) {
           sc[SC_GJ_OK + 3 * wave] = ok ? 1.0 : 0.0;
           sc[SC_GJ_LD + 3 * wave] = ok ? ld : 0.0;

@@ -134,8 +134,11 @@ __device__ void compute_RWS_g(const DevWF& wf, const Lg& l) {
 // (rows electrons, columns reference slots) -> A^{-1} by the H lanes qh of a
 // half group.  log|det A| is accumulated as a mantissa product and an
 // exponent sum (one log at the end).  Returns false if a pivot is exactly
-// zero.
-template <int H>
+// zero.  The pivot of column k is the largest |A[i][k]|, i >= k, the lowest
+// row on ties: found by a butterfly over the lanes' partial maxima, or
+// (SCAN) by every lane scanning the column itself (broadcast reads, no
+// cross-lane steps; the same pivot).
+template <int H, bool SCAN = false>
 __device__ bool gj_invert_h(double* A, int n, int qh, int* piv, double* f, double& logdet, double& sgn) {
   const float rn = 1.0f / (float)n;
   double mant = 1.0;
@@ -144,15 +147,22 @@ __device__ bool gj_invert_h(double* A, int n, int qh, int* piv, double* f, doubl
   for (int k = 0; k < n; ++k) {
     double best = -1.0;
     int bi = n;
-    for (int i = k + qh; i < n; i += H) {
-      double v = fabs(A[i * n + k]);
-      if (v > best) { best = v; bi = i; }
-    }
+    if constexpr (SCAN) {
+      for (int i = k; i < n; ++i) {
+        const double v = fabs(A[i * n + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+    } else {
+      for (int i = k + qh; i < n; i += H) {
+        double v = fabs(A[i * n + k]);
+        if (v > best) { best = v; bi = i; }
+      }
 #pragma unroll
-    for (int off = H / 2; off > 0; off >>= 1) {
-      double ob = __shfl_xor(best, off, H);
-      int oi = __shfl_xor(bi, off, H);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      for (int off = H / 2; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, H);
+        int oi = __shfl_xor(bi, off, H);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
     }
     if (!(best > 0.0)) return false;
     const int p = bi;
