@@ -28,14 +28,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (published)
-# HBM bytes per sweep launch (4096 walkers, TRAFFIC_LANES lanes per walker,
-# FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
-# calibration: FETCH_SIZE 4570 KiB x 2.000 + WRITE_SIZE 8256 KiB x 1.000
-TRAFFIC_BYTES_PER_LAUNCH = (4552.9 * 2.0 + 8256.0) * 1024
-TRAFFIC_LANES = 32
-# the same for one launch of the row kernel (4096 walkers, 100 steps per
-# launch): FETCH_SIZE 5592 KiB x 2.000 + WRITE_SIZE 10902 KiB x 1.000
-TRAFFIC_ROWS = {"walkers": 4096, "steps_per_launch": 100, "bytes": (5619.0 * 2.0 + 9895.7) * 1024}
+# HBM bytes per launch of the dominant kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel calibration (the
+# factors), each with the SHA-256 prefix of the kernel's source file and the
+# shared headers it was taken on (traffic_bytes reports it only while they
+# are unchanged, else null).  The sweep: k_sweep_g<32, 0, 0> on the F2-shaped
+# workload (4096 walkers, one step per launch); the row kernel: one launch of
+# 100 steps on the same workload.
+SWEEP_TRAFFIC = {"src": "vbqmc_sweep.hip", "src_sha": "7bce33b7a54dd23e", "fetch_kib": 4567.5, "write_kib": 8256.0,
+                 "fetch_factor": 2.000, "write_factor": 1.000, "walkers": 4096, "lanes": 32}
+ROWS_TRAFFIC = {"src": "vbqmc_rows.hip", "src_sha": "f1cf94c2b2c6a6d1", "fetch_kib": 5603.6, "write_kib": 9861.4,
+                "fetch_factor": 2.000, "write_factor": 1.000, "walkers": 4096, "steps_per_launch": 100}
 # the walker-resident kernel in VMC mode on the 40-electron molecule (two
 # replaced columns at most per determinant, 160 padded basis functions)
 WRES_VMC_KERNEL = "k_dmcw<32, 2, 16, true, false>"
@@ -280,21 +283,22 @@ def vmc_form(args):
             sweep_flops += een_flops_per_walker_step(ctx, False) * W
         flops_launch = (sweep_flops + measure_flops) * steps_launch
         t = WRES_VMC_TRAFFIC
-        traffic = ((t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024
-                   if (big and W == t["walkers"] and args.precision == "fp64" and not args.een and
-                       _src_sha("vbqmc_dmcw.hip") == t["src_sha"]) else None)
+        traffic = (traffic_bytes(t) if (big and W == t["walkers"] and args.precision == "fp64" and not args.een)
+                   else None)
     elif rows:
         # the dominant (and only) kernel makes moves and E_L of every step
         ne = 10 if max(ctx.info["n_up"], ctx.info["n_dn"]) <= 10 else 16  # register columns per lane
         kernel = f"k_vmc_rows<1, 0, {ne}>" if args.precision == "mixed" else f"k_vmc_rows<{prec_tag}, {prec_tag}, {ne}>"
         flops_launch = (sweep_flops + measure_flops) * steps_launch
-        traffic = TRAFFIC_ROWS["bytes"] if (W == TRAFFIC_ROWS["walkers"] and args.precision == "fp64" and
-                                            steps_launch == TRAFFIC_ROWS["steps_per_launch"]) else None
+        t = ROWS_TRAFFIC
+        traffic = (traffic_bytes(t) if (W == t["walkers"] and args.precision == "fp64" and
+                                        steps_launch == t["steps_per_launch"]) else None)
     else:
         pt = 1 if args.precision == "mixed" else prec_tag
         kernel = f"k_sweep_g<{lanes}, {pt}, {prec_tag}>" if lanes < 64 else f"k_sweep<64, {prec_tag}>"
         flops_launch = sweep_flops
-        traffic = (TRAFFIC_BYTES_PER_LAUNCH if lanes == TRAFFIC_LANES and W == 4096 and args.precision == "fp64"
+        t = SWEEP_TRAFFIC
+        traffic = (traffic_bytes(t) if lanes == t["lanes"] and W == t["walkers"] and args.precision == "fp64"
                    else None)
     kernel_avg = kernel_s / launches
     achieved = flops_launch / kernel_avg / 1e12
@@ -477,16 +481,23 @@ def adjoint_form(args):
 HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"
 DMC_KERNEL_NAMES = {1: "k_dmc_step<256, 0>", 2: "electron-major launches (k_dmcb_*)", 3: "k_dmcw<32, 2, 16, false, false>"}
 # HBM bytes of one launch of the walker-resident DMC step kernel on the
-# headline workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch) scaled by the copy-kernel calibration (the factors below), with
-# the SHA-256 prefix of the kernel source they were taken on: the value is
-# reported only while the source is unchanged (else null).
-DMCW_TRAFFIC = {"src_sha": "c8d889ae30b559f6", "fetch_kib": 3407345.3, "write_kib": 4309999.3, "fetch_factor": 2.000,
-                "write_factor": 1.000, "walkers": 32768}
-# the same for one step launch of that kernel in VMC mode on the 40-electron
-# molecule (16384 walkers; the mean of 12 step dispatches)
-WRES_VMC_TRAFFIC = {"src_sha": "c8d889ae30b559f6", "fetch_kib": 353236.2, "write_kib": 593294.2, "fetch_factor": 2.000,
-                    "write_factor": 1.000, "walkers": 16384}
+# the headline workload (32768 walkers, one step launch of the walker-resident
+# kernel), and one step launch of that kernel in VMC mode on the 40-electron
+# molecule (16384 walkers; the mean of 12 step dispatches); see SWEEP_TRAFFIC
+DMCW_TRAFFIC = {"src": "vbqmc_dmcw.hip", "src_sha": "aa2f209f56d80e78", "fetch_kib": 3408928.9, "write_kib": 4309978.0,
+                "fetch_factor": 2.000, "write_factor": 1.000, "walkers": 32768}
+WRES_VMC_TRAFFIC = {"src": "vbqmc_dmcw.hip", "src_sha": "aa2f209f56d80e78", "fetch_kib": 353397.0, "write_kib": 593276.6,
+                    "fetch_factor": 2.000, "write_factor": 1.000, "walkers": 16384}
+# headers every kernel source includes (their layouts and device helpers)
+SHARED_HEADERS = ("vbqmc_internal.h", "vbqmc_device.h", "vbqmc_group.h")
+
+
+def traffic_bytes(t):
+    """Calibrated HBM bytes per launch of a traffic record, or None when its
+    kernel source or a shared header changed since the counters were taken."""
+    if not t.get("src_sha") or _src_sha(t["src"]) != t["src_sha"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024
 
 
 def dmc_flops_per_walker_step(ctx, system, accept, refresh_per_step):
@@ -593,9 +604,13 @@ def reblock(x, w):
 
 
 def _src_sha(name):
+    """SHA-256 prefix of a kernel source file followed by the shared headers."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2207_14715_amd", "csrc", name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for n in (name,) + SHARED_HEADERS:
+        with open(os.path.join(ROOT, "paper_2207_14715_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _dmc_mixed_compare(vb, system, c64, R_burn, W, tau, fp64_value, steps=10):
@@ -693,10 +708,8 @@ def dmc_form(args):
     kavg = float(np.mean(step_ms)) / 1e3
     achieved = flops_launch / kavg / 1e12
     traffic = None
-    if (DMCW_TRAFFIC and kern == 3 and args.precision == "fp64" and W == DMCW_TRAFFIC["walkers"] and not args.een and
-            _src_sha("vbqmc_dmcw.hip") == DMCW_TRAFFIC["src_sha"]):
-        traffic = (DMCW_TRAFFIC["fetch_kib"] * DMCW_TRAFFIC["fetch_factor"] +
-                   DMCW_TRAFFIC["write_kib"] * DMCW_TRAFFIC["write_factor"]) * 1024
+    if kern == 3 and args.precision == "fp64" and W == DMCW_TRAFFIC["walkers"] and not args.een:
+        traffic = traffic_bytes(DMCW_TRAFFIC)
     line = {
         "metric": HEADLINE_METRIC,
         "value": moves / wall,
