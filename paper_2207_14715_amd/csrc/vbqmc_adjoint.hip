@@ -111,6 +111,75 @@ __device__ void adj_rows5(const DevWF& wf, const Ld& l, int ne, double* out, int
   }
 }
 
+// The Jastrow factor's gradient and Laplacian per electron, U and the
+// potential (as jastrow_full without f_een), with each electron's partners
+// spread over a segment of SEG lanes (SEG a power of two, N * SEG <= NT)
+// and summed within the segment
+template <int NT>
+__device__ void adj_jastrow(const DevWF& wf, const Ld& l, const double* Rsrc) {
+  const int N = wf.N, nn = wf.nnuc;
+  int SEG = 64;
+  while (SEG > 1 && N * SEG > NT) SEG >>= 1;
+  const double* nuc = l.nuc();
+  double part[2] = {0.0, 0.0};  // U, V
+  for (int t0 = 0; t0 < N * SEG; t0 += NT) {
+    const int t = t0 + (int)threadIdx.x;
+    const int i = t / SEG, sub = t - i * SEG;
+    const bool el = i < N;
+    const int ii = el ? i : 0;
+    const double xi = Rsrc[3 * ii], yi = Rsrc[3 * ii + 1], zi = Rsrc[3 * ii + 2];
+    const int si = spin_of(wf, ii);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // gx, gy, gz, lap, U, V
+    if (el)
+      for (int pidx = sub; pidx < nn + N; pidx += SEG) {
+        double dx, dy, dz, wu, wv;
+        PairCoef cf;
+        if (pidx < nn) {
+          dx = xi - nuc[4 * pidx]; dy = yi - nuc[4 * pidx + 1]; dz = zi - nuc[4 * pidx + 2];
+          cf = en_coef(l.en() + 6 * pidx);
+          wu = 1.0;
+          wv = -nuc[4 * pidx + 3];
+        } else {
+          const int j = pidx - nn;
+          if (j == i) continue;
+          dx = xi - Rsrc[3 * j]; dy = yi - Rsrc[3 * j + 1]; dz = zi - Rsrc[3 * j + 2];
+          cf = ee_coef(wf, si != spin_of(wf, j));
+          wu = 0.5;
+          wv = 0.5;
+        }
+        const double r = sqrt(dx * dx + dy * dy + dz * dz), ir = 1.0 / r;
+        double u, u1, u2;
+        pair_fn(r, wf.kappa, cf, u, u1, u2);
+        const double f = u1 * ir;
+        v[0] += f * dx;
+        v[1] += f * dy;
+        v[2] += f * dz;
+        v[3] += u2 + 2.0 * f;
+        v[4] += wu * u;
+        v[5] += wv * ir;
+      }
+    // (every lane of the wavefront takes part; xor offsets below SEG stay
+    // inside the segment)
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      for (int off = SEG / 2; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if (el && sub == 0) {
+      l.gU()[3 * i] = v[0];
+      l.gU()[3 * i + 1] = v[1];
+      l.gU()[3 * i + 2] = v[2];
+      l.lU()[i] = v[3];
+      part[0] += v[4];
+      part[1] += v[5];
+    }
+  }
+  block_sum<NT, 2>(part, l.red());
+  if (threadIdx.x == 0) {
+    l.sc()[SC_U] = part[0];
+    l.sc()[SC_V] = part[1] + wf.vnn;
+  }
+  __syncthreads();
+}
+
 // derivatives (du, du', du'') of a pair function with respect to one of its
 // parameters: kind 0 numerator a, 1 denominator b, 2..5 coefficient of R^kind
 __device__ __forceinline__ void pair_param(double r, double kappa, double a, double b, int kind, double& du,
@@ -522,7 +591,11 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
     G[idx] = 0.0;
   }
   // B. Jastrow factor, its gradients and Laplacians, potential
-  jastrow_full<NT, EEN>(wf, l, l.R());
+  if constexpr (EEN) {
+    jastrow_full<NT, EEN>(wf, l, l.R());
+  } else {
+    adj_jastrow<NT>(wf, l, l.R());
+  }
 
   // C. first pass over the spin determinants: ln|Delta_u|, sign, e_u,
   // through each spin's reference (one inversion per spin); if a reference
