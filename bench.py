@@ -11,7 +11,8 @@ on-device compaction, FP64.  One walker-move is one walker advanced by one
 step (64 single-electron moves and its local energy).  Inputs are seeded and
 synthetic and resident in device memory when timing starts.
 
-Other forms: --form vmc (the F2-shaped VMC row kernel), precision, adjoint.
+Other forms: --form vmc (the F2-shaped VMC row kernel; --system precision the 40-electron molecule,
+--system h2 the all-electron H2 workload), precision, adjoint.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form ...]
 Prints one JSON line.
@@ -153,7 +154,7 @@ def main():
                     help="dmc and vmc forms: add the three-body Jastrow f_een to the workload's wave function")
     ap.add_argument("--een-scale", type=float, default=0.01,
                     help="standard deviation of the f_een coefficients (default 0.01)")
-    ap.add_argument("--system", default="f2", choices=["f2", "precision"],
+    ap.add_argument("--system", default="f2", choices=["f2", "precision", "h2"],
                     help="vmc form: the F2-shaped diatomic or the 40-electron molecule of the precision form")
     ap.add_argument("--dmc-kernel", type=int, default=0, choices=[0, 1, 2, 3],
                     help="DMC: 0 library choice, 1 one workgroup per walker, 2 electron-major launches, "
@@ -190,7 +191,75 @@ def main():
         return adjoint_form(args)
     if args.form == "dmc":
         return dmc_form(args)
+    if args.system == "h2":
+        return h2_form(args)
     return vmc_form(args)
+
+
+def h2_form(args):
+    """All-electron VMC on the H2 Heitler-London function (2 protons at
+    +-0.7 bohr, covalent and ionic structures, Pade Jastrow): 1024 walkers,
+    Metropolis moves of all electrons at once in a 0.5-bohr cube, E_L every
+    step, 1000 steps in one launch of the all-electron kernel (bracketed by
+    events on the launch stream) after a warm-up call."""
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    system = S.h2_heitler_london()
+    W = args.walkers or 1024
+    steps = args.steps if args.steps is not None else 1000
+    warm = args.warmup if args.warmup is not None else 100
+    step_size, seed = 0.5, 20220728
+    ctx = vb.Context(system)
+    state = ctx.walkers_init(torch.from_numpy(S.initial_walkers(system, W, seed=5)).cuda())
+    acc = ctx.new_vmc_acc(W)
+    if warm > 0:
+        ctx.vmc_advance(state, warm, seed, 0, step_size, True, acc)
+    acc = ctx.new_vmc_acc(W)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.vmc_advance(state, steps, seed, warm, step_size, True, acc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = e0.elapsed_time(e1) / 1e3
+    moves = W * steps
+    accept = float(acc["n_accept"].sum().item()) / moves
+    # per walker-step: one full evaluation at the proposal (basis values,
+    # gradients and Laplacians, the determinants and E_L)
+    _, _, _, _, _, spins = _dims(ctx, system)
+    fl = measure_flops_per_walker(ctx, system) + sum(2.0 * n ** 3 / 3 + 2.0 * n * n * nP for n, nP, _ in spins)
+    achieved = fl * moves / kernel_s / 1e12
+    line = {
+        "metric": "walker-moves/sec incl. E_L", "value": moves / wall, "unit": "walker-moves/s", "n_gpus": 1,
+        "steps": steps, "warmup": warm, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "H2 Heitler-London VMC: 2 protons at +-0.7 bohr, 1 up + 1 down electron, 3 "
+                               "contracted s Gaussians per atom, covalent + ionic structures (0.9, 0.3), Pade "
+                               f"Jastrow, {W} walkers, all-electron Metropolis moves of 0.5 bohr, E_L every step",
+                   "walkers": W, "electrons": ctx.N, "precision": "fp64", "step_kernel": "all-electron"},
+        "acceptance": accept,
+        "mean_eloc": float(acc["e_sum"].sum().item()) / moves,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_vmc (all-electron)", "kernel_avg_ms_per_launch": kernel_s * 1e3,
+                     "flops_per_walker_step": fl, "walkers_per_launch": W, "steps_per_launch": steps},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Oracle(system)
+        R0 = S.initial_walkers(system, W, seed=11)
+        t0 = time.perf_counter()
+        o.vmc(R0, steps, 1234, 0, step_size, True)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": W * steps / dt, "unit": "walker-moves/s", "cores": oracle.max_threads(),
+                                "kind": "oracle",
+                                "sample": f"the whole workload: {W} walkers x {steps} all-electron steps, {dt:.1f} s"}
+    print(json.dumps(line))
 
 
 def vmc_form(args):
