@@ -638,12 +638,12 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
   {
     const double* U0 = l.L + wf.l_aU[0];
     const double* U1 = l.L + wf.l_aU[1];
-    double lmax = -INFINITY;
-    for (int u = 0; u < wf.sp[0].nU; ++u)
-      for (int k = l.wrow(0)[u]; k < l.wrow(0)[u + 1]; ++k) {
-        int ub = l.woth(0)[k];
-        if (l.wcoef(0)[k] != 0.0) lmax = fmax(lmax, U0[5 * u] + U1[5 * ub]);
-      }
+    // the scale of the exponentials: the largest ln|Delta| of each spin
+    // summed (a bound on every pair's, the same in both uses below)
+    double m0 = -INFINITY, m1 = -INFINITY;
+    for (int u = 0; u < wf.sp[0].nU; ++u) m0 = fmax(m0, U0[5 * u]);
+    for (int u = 0; u < wf.sp[1].nU; ++u) m1 = fmax(m1, U1[5 * u]);
+    const double lmax = m0 + m1;
     double acc[2] = {0.0, 0.0};  // D~, sum t_k e_k
     for (int u = threadIdx.x; u < wf.sp[0].nU; u += NT)
       for (int k = l.wrow(0)[u]; k < l.wrow(0)[u + 1]; ++k) {
@@ -652,7 +652,16 @@ __global__ __launch_bounds__(NT) void k_param_grad(const DevWF* __restrict__ pwf
         acc[0] += t;
         acc[1] += t * (U0[5 * u + 2] + U1[5 * ub + 2]);
       }
-    block_sum<NT, 2>(acc, l.red());
+    if (wf.sp[0].nU <= 64) {
+      // (every contribution is in wavefront 0)
+      if (threadIdx.x < 64)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    } else {
+      block_sum<NT, 2>(acc, l.red());
+    }
     if (threadIdx.x == 0) {
       sc[SC_TMP0] = lmax;
       sc[SC_S] = acc[0];
