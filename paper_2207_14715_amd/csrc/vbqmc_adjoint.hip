@@ -446,6 +446,10 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
   // unused
   const bool par = NT >= 128 && wf.adj_save && 3 * wf.sp[1].n * wf.sp[1].nP <= wf.l_aU[0] - wf.l_aA;
   const int nth = par ? NT / 2 : NT;
+  // masks of determinants per table orbital: at most 64 determinants per
+  // spin, the masks of the spins that run at once fit the space of Xi
+  const bool masks = wf.adj_save && wf.sp[0].nU <= 64 && wf.sp[1].nU <= 64 &&
+                     wf.sp[0].nP + wf.sp[1].nP <= wf.l_aBXi - wf.l_aXi;
   const int grp = par ? (int)threadIdx.x / (NT / 2) : 0;
   const int tid = par ? (int)threadIdx.x - grp * (NT / 2) : (int)threadIdx.x;
   for (int it = 0; it < (par ? 1 : 2); ++it) {
@@ -474,16 +478,42 @@ __device__ void adj_ref_pass2(const DevWF& wf, const Ld& l, const double* aPhi, 
     double* Xq = Wq + 2 * nP * n;
     const int* ref = l.ref(s);
     const int* porb = l.porb(s);
+    // per table orbital q, the mask of the (nonsingular) determinants that
+    // put it in one of their replaced columns, so that a (q, a) sum visits
+    // only those (in the space of Xi, which this pass leaves unused when the
+    // first pass's copies are kept)
+    unsigned long long* qmask = (unsigned long long*)(l.L + wf.l_aXi) + (par && s == 1 ? wf.sp[0].nP : 0);
+    if (masks) {
+      for (int q = tid; q < nP; q += nth) {
+        unsigned long long m = 0;
+        for (int u = 0; u < st.nU; ++u) {
+          if (uinf[5 * u + 1] == 0.0) continue;
+          const int* ui = l.ui(s) + 8 * u;
+          for (int d = 0; d < ui[0]; ++d)
+            if (ui[4 + d] == q) m |= 1ull << u;
+        }
+        qmask[q] = m;
+      }
+      __syncthreads();
+    }
     for (int idx = tid; idx < nP * n; idx += nth) {
       const int q = idx / n, a = idx - q * n;
       double w = 0.0, wb = 0.0, x = 0.0;
-      for (int u = 0; u < st.nU; ++u) {
-        if (uinf[5 * u + 1] == 0.0) continue;  // singular: no contribution
+      unsigned long long m = masks ? qmask[q] : 0ull;
+      for (int u0 = 0; masks ? m != 0ull : u0 < st.nU; ++u0) {
+        int u = u0;
+        if (masks) {
+          u = __builtin_ctzll(m);
+          m &= m - 1;
+        }
         const int* ui = l.ui(s) + 8 * u;
         const int e = ui[0];
-        bool has = false;
-        for (int d = 0; d < e; ++d) has = has || ui[4 + d] == q;
-        if (!has) continue;
+        if (!masks) {
+          if (uinf[5 * u + 1] == 0.0) continue;  // singular: no contribution
+          bool has = false;
+          for (int d = 0; d < e; ++d) has = has || ui[4 + d] == q;
+          if (!has) continue;
+        }
         const double om = uinf[5 * u + 3], lb = uinf[5 * u + 4];
         const double* mi = V + 18 * u;
         const double* vx = mi + 9;
