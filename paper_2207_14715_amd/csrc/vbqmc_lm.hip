@@ -10,12 +10,15 @@
 //   D'[i][j] += sum_k w_k X_ki Y_kj
 // (row 0 holds sum w, sum w O_j, sum w E, sum w E O_j, sum w E^2 and
 // sum w D_j).  Each is a dense (P+1) x W by W x (P+1) product, here on FP64
-// MFMA: a 256-thread workgroup owns a 64 x 64 block of one matrix, wavefront
-// g rows 16 g .. 16 g + 15 of it as four 16 x 16 tiles, and walks the
-// samples four at a time (one 16x16x4 k-step).  Operands come straight from
-// the row-major per-sample arrays (16 consecutive doubles per sample row per
-// lane quarter); the sample sum runs in one fixed order, so the sums are
-// reproducible, and each block adds its result to the accumulator it owns.
+// MFMA: a 256-thread workgroup owns a 128 x 128 block of one matrix, each
+// wavefront a 64 x 64 quarter of it as 4 x 4 tiles of 16 x 16, and walks the
+// samples four at a time (one 16x16x4 k-step: eight operand loads per lane
+// for sixteen MFMAs).  S' and H' are symmetric: only the blocks on and above
+// the diagonal are formed, each element also written to its mirror.
+// Operands come straight from the row-major per-sample arrays (16
+// consecutive doubles per sample row per lane quarter); the sample sum runs
+// in one fixed order, so the sums are reproducible, and each block adds its
+// result to the elements it owns.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,7 +27,7 @@ namespace vbqmc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kLmB = 64;   // block edge
+constexpr int kLmB = 128;  // block edge
 constexpr int kLmT = 256;  // threads per workgroup
 
 // mat 0: S', 1: H', 2: D'.  acc: three (P+1) x (P+1) row-major matrices.
@@ -33,45 +36,92 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
                                                          const double* __restrict__ wt, double* __restrict__ acc) {
   const int P1 = P + 1;
   const int mat = blockIdx.z;
+  // the symmetric products: blocks below the diagonal come from their mirrors
+  if (mat < 2 && blockIdx.y > blockIdx.x) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const int i = blockIdx.y * kLmB + 16 * wave + m;  // A row (X column)
-  const int j0 = blockIdx.x * kLmB;
-  v4d c[4];
+  const int i0 = blockIdx.y * kLmB + 64 * (wave >> 1);  // rows of this wavefront's quarter
+  const int j0 = blockIdx.x * kLmB + 64 * (wave & 1);   // columns
+  v4d c[4][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) c[t][r] = 0.0;
-  const bool iin = i < P1;
-  for (int64_t k0 = 0; k0 < W; k0 += 4) {
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[rt][ct][r] = 0.0;
+  // operands of k-step k0 (samples k0 .. k0 + 3): the raw row entries and
+  // the sample's weight and energy; the next step's are loaded while the
+  // current step's MFMAs run
+  auto load = [&](int64_t k0, double (&a)[4], double (&z)[4], double& w, double& e) {
     const int64_t k = k0 + kq;
     const bool kin = k < W;
     const int64_t kk = kin ? k : 0;
-    const double w = kin ? (wt ? wt[kk] : 1.0) : 0.0;
-    const double e = E[kk];
+    w = kin ? (wt ? wt[kk] : 1.0) : 0.0;
+    e = E[kk];
     const double* Ok = O + kk * P;
-    // A: X_ki
-    const double a = (iin && i > 0) ? Ok[i - 1] : (iin ? 1.0 : 0.0);
-    const double s = mat == 1 ? w * e : w;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = j0 + 16 * t + m;
-      double z;
-      if (mat < 2) z = (j < P1 && j > 0) ? Ok[j - 1] : (j == 0 ? 1.0 : 0.0);
-      else z = (j < P1 && j > 0) ? D[kk * P + j - 1] : (j == 0 ? e * e : 0.0);
-      c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z * s, c[t], 0, 0, 0);
+    for (int rt = 0; rt < 4; ++rt) {  // A: X_ki
+      const int i = i0 + 16 * rt + m;
+      a[rt] = i < P1 ? (i > 0 ? Ok[i - 1] : 1.0) : 0.0;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {  // B before scaling: X_kj or Y_kj (E_k^2 in column 0)
+      const int j = j0 + 16 * ct + m;
+      if (mat < 2) z[ct] = j < P1 ? (j > 0 ? Ok[j - 1] : 1.0) : 0.0;
+      else z[ct] = j < P1 && j > 0 ? D[kk * P + j - 1] : 0.0;
+    }
+  };
+  // two k-steps per pass, the next pass's operands in flight meanwhile
+  double an[2][4], zn[2][4], wn[2], en[2];
+  load(0, an[0], zn[0], wn[0], en[0]);
+  load(4, an[1], zn[1], wn[1], en[1]);
+  for (int64_t k0 = 0; k0 < W; k0 += 8) {
+    double a[2][4], z[2][4], w[2], e[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[h][r] = an[h][r];
+        z[h][r] = zn[h][r];
+      }
+      w[h] = wn[h];
+      e[h] = en[h];
+    }
+    if (k0 + 8 < W) load(k0 + 8, an[0], zn[0], wn[0], en[0]);
+    if (k0 + 12 < W) load(k0 + 12, an[1], zn[1], wn[1], en[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (k0 + 4 * h >= W) break;  // (the same in every lane)
+      const double sc = mat == 1 ? w[h] * e[h] : w[h];
+      double b[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int j = j0 + 16 * ct + m;
+        b[ct] = (mat == 2 && j == 0 ? e[h] * e[h] : z[h][ct]) * sc;
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          c[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][rt], b[ct], c[rt][ct], 0, 0, 0);
     }
   }
   // register q of lane l holds row 4 q + l / 16, column l % 16 of a tile
   double* out = acc + (size_t)mat * P1 * P1;
+  const bool mirror = mat < 2 && blockIdx.y < blockIdx.x;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = blockIdx.y * kLmB + 16 * wave + 4 * q + kq;
-      const int col = j0 + 16 * t + m;
-      if (row < P1 && col < P1) out[(size_t)row * P1 + col] += c[t][q];
-    }
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = i0 + 16 * rt + 4 * q + kq;
+        const int col = j0 + 16 * ct + m;
+        if (row < P1 && col < P1) {
+          out[(size_t)row * P1 + col] += c[rt][ct][q];
+          if (mirror) out[(size_t)col * P1 + row] += c[rt][ct][q];
+        }
+      }
 }
 
 hipError_t launch_lm_accumulate(int P, int64_t W, const double* O, const double* D, const double* E,
