@@ -10,10 +10,11 @@
 //   D'[i][j] += sum_k w_k X_ki Y_kj
 // (row 0 holds sum w, sum w O_j, sum w E, sum w E O_j, sum w E^2 and
 // sum w D_j).  Each is a dense (P+1) x W by W x (P+1) product, here on FP64
-// MFMA: a 256-thread workgroup owns a 128 x 128 block of one matrix, each
-// wavefront a 64 x 64 quarter of it as 4 x 4 tiles of 16 x 16, and walks the
-// samples four at a time (one 16x16x4 k-step: eight operand loads per lane
-// for sixteen MFMAs).  S' and H' are symmetric: only the blocks on and above
+// MFMA: a 512-thread workgroup owns a 128 x 128 block of one matrix, each
+// wavefront a 32 x 64 part of it as 2 x 4 tiles of 16 x 16 (two wavefronts
+// per SIMD), and walks the samples four at a time (one 16x16x4 k-step: six
+// operand loads per lane for eight MFMAs), the operands of the next two
+// k-steps in flight.  S' and H' are symmetric: only the blocks on and above
 // the diagonal are formed, each element also written to its mirror.
 // Operands come straight from the row-major per-sample arrays (16
 // consecutive doubles per sample row per lane quarter); the sample sum runs
@@ -28,7 +29,8 @@ namespace vbqmc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kLmB = 128;  // block edge
-constexpr int kLmT = 256;  // threads per workgroup
+constexpr int kLmRT = 2;   // 16-row tiles per wavefront (a wavefront owns 16 kLmRT x 64)
+constexpr int kLmT = 64 * (kLmB / (16 * kLmRT)) * (kLmB / 64);  // threads per workgroup
 
 // mat 0: S', 1: H', 2: D'.  acc: three (P+1) x (P+1) row-major matrices.
 __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const double* __restrict__ O,
@@ -40,11 +42,11 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
   if (mat < 2 && blockIdx.y > blockIdx.x) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const int i0 = blockIdx.y * kLmB + 64 * (wave >> 1);  // rows of this wavefront's quarter
-  const int j0 = blockIdx.x * kLmB + 64 * (wave & 1);   // columns
-  v4d c[4][4];
+  const int i0 = blockIdx.y * kLmB + 16 * kLmRT * (wave >> 1);  // rows of this wavefront's part
+  const int j0 = blockIdx.x * kLmB + 64 * (wave & 1);           // columns
+  v4d c[kLmRT][4];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < kLmRT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
   // operands of k-step k0 (samples k0 .. k0 + 3): the raw row entries and
   // the sample's weight and energy; the next step's are loaded while the
   // current step's MFMAs run
-  auto load = [&](int64_t k0, double (&a)[4], double (&z)[4], double& w, double& e) {
+  auto load = [&](int64_t k0, double (&a)[kLmRT], double (&z)[4], double& w, double& e) {
     const int64_t k = k0 + kq;
     const bool kin = k < W;
     const int64_t kk = kin ? k : 0;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
     e = E[kk];
     const double* Ok = O + kk * P;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {  // A: X_ki
+    for (int rt = 0; rt < kLmRT; ++rt) {  // A: X_ki
       const int i = i0 + 16 * rt + m;
       a[rt] = i < P1 ? (i > 0 ? Ok[i - 1] : 1.0) : 0.0;
     }
@@ -72,18 +74,17 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
     }
   };
   // two k-steps per pass, the next pass's operands in flight meanwhile
-  double an[2][4], zn[2][4], wn[2], en[2];
+  double an[2][kLmRT], zn[2][4], wn[2], en[2];
   load(0, an[0], zn[0], wn[0], en[0]);
   load(4, an[1], zn[1], wn[1], en[1]);
   for (int64_t k0 = 0; k0 < W; k0 += 8) {
-    double a[2][4], z[2][4], w[2], e[2];
+    double a[2][kLmRT], z[2][4], w[2], e[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[h][r] = an[h][r];
-        z[h][r] = zn[h][r];
-      }
+      for (int r = 0; r < kLmRT; ++r) a[h][r] = an[h][r];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[h][r] = zn[h][r];
       w[h] = wn[h];
       e[h] = en[h];
     }
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
         b[ct] = (mat == 2 && j == 0 ? e[h] * e[h] : z[h][ct]) * sc;
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < kLmRT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
           c[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][rt], b[ct], c[rt][ct], 0, 0, 0);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kLmT) void k_lm_accumulate(int P, int64_t W, const 
   double* out = acc + (size_t)mat * P1 * P1;
   const bool mirror = mat < 2 && blockIdx.y < blockIdx.x;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < kLmRT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
