@@ -245,17 +245,22 @@ __device__ __forceinline__ double adj_kin(const DevWF& wf, const Ld& l, const do
 // T, Xi, B S, B Xi; false if the reference is singular (block-uniform)
 template <int NT>
 __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, int s, double* B, double* K0,
-                             double* S, double& ld0, double& sg0, double& trS, bool pre = false) {
+                             double* S, double& ld0, double& sg0, double& trS, bool pre = false, int tid = -1,
+                             int nth = NT, double* T = nullptr, double* Xi = nullptr, double* BS = nullptr,
+                             double* BXi = nullptr) {
+  // (tid, nth: the threads that take part, all of the block by default; T,
+  // Xi, B S, B Xi: the outputs, the shared regions by default)
+  if (tid < 0) tid = (int)threadIdx.x;
+  if (!T) T = l.L + wf.l_aT;
+  if (!Xi) Xi = l.L + wf.l_aXi;
+  if (!BS) BS = l.L + wf.l_aBS;
+  if (!BXi) BXi = l.L + wf.l_aBXi;
   const SpinTab& st = wf.sp[s];
   const int n = st.n, nP = st.nP, e0 = st.e0, N = wf.N, nop = wf.nop;
   const int* ref = l.ref(s);
   const int* porb = l.porb(s);
-  double* BS = l.L + wf.l_aBS;
-  double* T = l.L + wf.l_aT;
-  double* Xi = l.L + wf.l_aXi;
-  double* BXi = l.L + wf.l_aBXi;
   // (pre: B already holds the inverse, ld0 and sg0 are given)
-  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+  for (int idx = tid; idx < n * n; idx += nth) {
     const int i = idx / n, j = idx - i * n;
     if (!pre) B[idx] = aPhi[(0 * N + e0 + i) * nop + ref[j]];
     K0[idx] = adj_kin(wf, l, aPhi, e0 + i, ref[j]);
@@ -282,33 +287,33 @@ __device__ bool adj_ref_spin(const DevWF& wf, const Ld& l, const double* aPhi, i
   } else if (!gj_invert<NT>(l, B, n, ld0, sg0)) {
     return false;
   }
-  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+  for (int idx = tid; idx < n * nP; idx += nth) {
     const int j = idx / nP, q = idx - j * nP;
     double t = 0.0;
     for (int i = 0; i < n; ++i) t += B[j * n + i] * aPhi[(0 * N + e0 + i) * nop + porb[q]];
     T[idx] = t;
   }
-  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+  for (int idx = tid; idx < n * n; idx += nth) {
     const int i = idx / n, a = idx - i * n;
     double t = 0.0;
     for (int j = 0; j < n; ++j) t += K0[i * n + j] * B[j * n + a];
     S[idx] = t;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+  for (int idx = tid; idx < n * nP; idx += nth) {
     const int i = idx / nP, q = idx - i * nP;
     double t = adj_kin(wf, l, aPhi, e0 + i, porb[q]);
     for (int k = 0; k < n; ++k) t -= K0[i * n + k] * T[k * nP + q];
     Xi[idx] = t;
   }
-  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
+  for (int idx = tid; idx < n * n; idx += nth) {
     const int b = idx / n, a = idx - b * n;
     double t = 0.0;
     for (int i = 0; i < n; ++i) t += B[b * n + i] * S[i * n + a];
     BS[idx] = t;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nP; idx += NT) {
+  for (int idx = tid; idx < n * nP; idx += nth) {
     const int b = idx / nP, q = idx - b * nP;
     double t = 0.0;
     for (int i = 0; i < n; ++i) t += B[b * n + i] * Xi[i * nP + q];
@@ -359,13 +364,39 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
       __syncthreads();
     }
   }
-  for (int s = 0; s < 2; ++s) {
+  // with both inverses formed at once, the two spins' products and
+  // determinants also run at once on the two halves of the block: spin s's
+  // B S, T, B Xi straight into its keep area, its K_0, S, Xi in regions this
+  // pass leaves free (spin 1: those of A, B S and T)
+  const bool par = pre;
+  if (par)
+    for (int s = 0; s < 2; ++s)
+      if (wf.sp[s].n > 0 && l.sc()[SC_GJ_OK + 3 * s] == 0.0) return false;
+  const int nth = par ? NT / 2 : NT;
+  const int grp = par ? (int)threadIdx.x / (NT / 2) : 0;
+  const int tid = par ? (int)threadIdx.x - grp * (NT / 2) : (int)threadIdx.x;
+  for (int it = 0; it < (par ? 1 : 2); ++it) {
+    const int s = par ? grp : it;
     const SpinTab& st = wf.sp[s];
     const int nP = st.nP;
     double* uinf = l.L + wf.l_aU[s];
     double* V = l.L + wf.l_aV[s];
     double ld0 = 0.0, sg0 = 1.0, trS = 0.0;
     double* Bs = B;
+    double *K0s = K0, *Ss = S, *Ts = l.L + wf.l_aT, *Xis = l.L + wf.l_aXi, *BSs = l.L + wf.l_aBS,
+           *BXis = l.L + wf.l_aBXi;
+    if (par) {
+      const int n = st.n;
+      double* sv = l.L + wf.l_aSave[s];
+      BSs = sv + n * n;
+      Ts = sv + 2 * n * n;
+      BXis = Ts + n * nP;
+      if (s == 1) {
+        K0s = l.L + wf.l_aA;
+        Ss = l.L + wf.l_aBS;
+        Xis = l.L + wf.l_aT;
+      }
+    }
     if (pre && st.n > 0) {
       const double* sc = l.sc();
       if (sc[SC_GJ_OK + 3 * s] == 0.0) return false;
@@ -373,10 +404,14 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
       sg0 = sc[SC_GJ_SG + 3 * s];
       Bs = l.L + wf.l_aSave[s];
     }
-    if (st.n > 0 && !adj_ref_spin<NT>(wf, l, aPhi, s, Bs, K0, S, ld0, sg0, trS, pre)) return false;
-    const double* T = l.L + wf.l_aT;
-    const double* BXi = l.L + wf.l_aBXi;
-    for (int u = threadIdx.x; u < st.nU; u += NT) {
+    // (in the parallel form both halves pass the same barriers, a spin
+    // without electrons with empty loops)
+    if ((st.n > 0 || par) &&
+        !adj_ref_spin<NT>(wf, l, aPhi, s, Bs, K0s, Ss, ld0, sg0, trS, pre, tid, nth, Ts, Xis, BSs, BXis))
+      return false;
+    const double* T = Ts;
+    const double* BXi = BXis;
+    for (int u = tid; u < st.nU; u += nth) {
       const int* ui = l.ui(s) + 8 * u;
       const int e = st.n > 0 ? ui[0] : 0;
       double m[9], mi[9], vx[9];
@@ -419,7 +454,7 @@ __device__ bool adj_ref_pass1(const DevWF& wf, const Ld& l, const double* aPhi, 
         V[18 * u + 9 + k] = vx[k];
       }
     }
-    if (wf.adj_save && st.n > 0) {
+    if (wf.adj_save && st.n > 0 && !par) {
       // B, B S, T, B Xi of this spin for the second pass
       const int n = st.n, nn = n * n, np = n * nP;
       double* sv = l.L + wf.l_aSave[s];
