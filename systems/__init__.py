@@ -24,6 +24,11 @@ A system is a plain dict:
                   "poly": [b3, b4, b5, b6]},
                   "en": [{"a1", "a2", "poly": [a3, a4, a5, a6]} per nucleus],
                   optional "een": [[c_1 .. c_23] per nucleus] (f_een terms)}
+    ecp         : optional list of pseudopotentials, one per pseudo-nucleus:
+                  {"center", "r_cut", "local": [[c, n, alpha], ..],
+                  "channels": [[[c, n, alpha], ..] for l = 0, 1, ..]}, each
+                  radial part sum_k c r^(n-2) exp(-alpha r^2); the nucleus's
+                  "Z" is then its effective (valence) charge
 
 Each generator's docstring gives its recipe (seed, distributions, shapes).
 """
@@ -32,6 +37,9 @@ from .generate import (  # noqa: F401
     h2_heitler_london,
     f2_shaped,
     f2_bovb,
+    f2_valence_ecp,
+    synthetic_ecp,
+    ecp_one_centre,
     with_een,
     N_EEN_TERMS,
     precision_molecule,

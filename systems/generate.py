@@ -216,6 +216,62 @@ def f2_bovb(seed=1001, breathing=0.3):
 N_EEN_TERMS = 23
 
 
+def synthetic_ecp(center, z_eff, scale=1.0, r_cut=2.5):
+    """A pseudopotential record of the energy-consistent shape (no tabulated
+    potential is used): local part Z/r e^(-a r^2) + Z a r e^(-b r^2) + g e^(-d r^2)
+    (cancelling the -Z/r singularity at the nucleus) and s and p channels of
+    one and two Gaussian terms; the numbers are made up at the magnitude of
+    first-row valence potentials, times scale."""
+    return {"center": int(center), "r_cut": float(r_cut),
+            "local": [[z_eff * scale, 1, 12.0], [z_eff * 12.0 * scale, 3, 10.0], [-20.0 * scale, 2, 9.0]],
+            "channels": [[[60.0 * scale, 2, 15.0], [-4.0 * scale, 2, 3.0]], [[-10.0 * scale, 2, 8.0]]]}
+
+
+def ecp_one_centre(l, lam, alpha=0.7, z_eff=1.0, jastrow=None, r_cut=2.5):
+    """One electron in a Gaussian shell of angular momentum l (combination lam
+    of its functions) at a pseudo-nucleus of charge z_eff carrying s, p and d
+    channels with different radial parts."""
+    sysd = _one_centre(z_eff, 1, 0, {"center": 0, "kind": "gto", "l": l, "exps": [alpha], "coefs": [1.0]},
+                       [list(map(float, lam))],
+                       [{"c": 1.0, "terms": [{"inactive": [], "pairs": [], "unpaired": [0]}]}], jastrow)
+    sysd["name"] = f"ecp_one_centre_l{l}"
+    sysd["ecp"] = [{"center": 0, "r_cut": float(r_cut), "local": [[z_eff, 1, 5.0], [-2.0, 2, 1.5]],
+                    "channels": [[[3.0, 2, 1.1]], [[-1.7, 2, 0.8], [0.6, 3, 2.0]], [[0.9, 2, 0.5]]]}]
+    return sysd
+
+
+def f2_valence_ecp(seed=1005):
+    """F2-shaped diatomic with the 1s cores replaced by pseudopotentials:
+    Z = 7 at z = -1.33, +1.33; 7 up + 7 down electrons.  Basis per atom
+    3s2p1d, 2-5 primitives per shell, exponents log-uniform in [0.08, 30]
+    (valence range).  Orbitals: 6 inactive (3 per atom) and the two active
+    sigma orbitals, N(0,1)/sqrt(14) on their own atom's block; covalent and
+    two ionic structures, c ~ N(0,1) normalised; Pade Jastrow; per atom the
+    synthetic_ecp record (r_cut 2.5 bohr)."""
+    rng = np.random.default_rng(seed)
+    pos = np.array([[0.0, 0.0, -1.33], [0.0, 0.0, 1.33]])
+    shells = []
+    for a in range(2):
+        shells += _gto_shells(rng, a, [(0, 3), (1, 2), (2, 1)], 2, 5, 0.08, 30.0)
+    blocks = _atom_blocks(shells, 2)
+    lam = np.zeros((8, 28))
+    owner = [0, 0, 0, 1, 1, 1, 0, 1]
+    for p, a in enumerate(owner):
+        lam[p, blocks[a]] = rng.normal(size=len(blocks[a])) / np.sqrt(len(blocks[a]))
+    c = _normalised_normal(rng, 3)
+    inact = list(range(6))
+    structures = [
+        {"c": float(c[0]), "terms": [{"inactive": inact, "pairs": [[6, 7]], "unpaired": []}]},
+        {"c": float(c[1]), "terms": [{"inactive": inact, "pairs": [[6, 6]], "unpaired": []}]},
+        {"c": float(c[2]), "terms": [{"inactive": inact, "pairs": [[7, 7]], "unpaired": []}]},
+    ]
+    return {"name": "f2_valence_ecp", "seed": seed,
+            "nuclei": {"Z": [7.0, 7.0], "pos": pos.tolist()},
+            "n_up": 7, "n_dn": 7, "shells": shells, "lam": lam.tolist(),
+            "structures": structures, "jastrow": _pade_jastrow(2),
+            "ecp": [synthetic_ecp(0, 7.0), synthetic_ecp(1, 7.0)]}
+
+
 def with_een(system, seed=2207, scale=0.05, kappa=0.8):
     """The system with an f_een three-body Jastrow: per chemical element
     N_EEN_TERMS coefficients ~ N(0, scale^2), shared by the nuclei of that
