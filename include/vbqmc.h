@@ -24,7 +24,7 @@
  *     vbqmc_create / vbqmc_set_params; it never frees caller memory.  Device
  *     memory for walker states, outputs and workspaces is always the
  *     caller's; the library allocates only its own small constant tables at
- *     vbqmc_create and frees them at vbqmc_destroy.
+ *     vbqmc_create (and vbqmc_set_ecp) and frees them at vbqmc_destroy.
  */
 #ifndef VBQMC_H
 #define VBQMC_H
@@ -197,6 +197,42 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wf, const vb
 void vbqmc_destroy(vbqmc_ctx* ctx);
 const char* vbqmc_last_error(const vbqmc_ctx* ctx);
 int vbqmc_get_info(const vbqmc_ctx* ctx, vbqmc_info_t* out);
+/*
+ * Pseudopotentials (Sec. 2.1, basis choice: the valence calculations use
+ * energy-consistent pseudopotentials, whose form the paper does not give;
+ * this is the usual semilocal form).  For a pseudo-nucleus a, whose charge in
+ * vbqmc_system is its effective (valence) charge Z_a, each electron at
+ * distance r adds to the potential energy
+ *   V_loc(r) + sum_{l < L} V_l(r) P_l-projection,
+ *   V(r) = sum_k c_k r^(n_k - 2) exp(-alpha_k r^2)   (each radial part),
+ * besides the -Z_a / r of the Hamiltonian.  The projection of channel l is
+ * taken in E_L as (2l + 1) times the mean, over the 12 directions u_q to the
+ * vertices of an icosahedron (fixed orientation; exact for spherical
+ * harmonics to degree 5), of P_l(u_q . (r_i - a) / r) times the ratio
+ * Psi(r_i -> a + r u_q) / Psi, and only for r < r_cut.
+ * terms: per centre, n_terms[] gives L + 1 counts (local part, then channel
+ * 0 .. L-1), and terms[] concatenates their [c, n, alpha] (n an integer
+ * 0..6, alpha >= 0).
+ */
+typedef struct {
+  int32_t n_centers;          /* 0 removes the pseudopotentials */
+  const int32_t* center;      /* [host] [n_centers] nucleus index, each at most once */
+  const int32_t* n_channels;  /* [host] [n_centers] L <= 4 */
+  const double* r_cut;        /* [host] [n_centers] bohr */
+  const int32_t* n_terms;     /* [host] sum over centres of (L + 1) */
+  const double* terms;        /* [host] [sum of n_terms][3] */
+} vbqmc_ecp;
+
+/* Attach pseudopotentials to a context (replacing earlier ones; NULL or
+ * n_centers = 0 removes them).  Synchronises the device first.  With them,
+ * vbqmc_evaluate, vbqmc_walkers_init and vbqmc_vmc_advance (all-electron
+ * and single-electron moves, both run by the one-workgroup-per-walker
+ * kernel) include the pseudopotential energy in E_L; vbqmc_vmc_sweep,
+ * vbqmc_vmc_measure, the DMC entry points and vbqmc_param_grad return
+ * EINVAL.  Errors: EINVAL (bad centre, channel count, r_cut or term; a
+ * precision form other than FP64; f_een), ENOMEM, EHIP. */
+int vbqmc_set_ecp(vbqmc_ctx* ctx, const vbqmc_ecp* ecp);
+
 
 /* Replace the variational parameters p = [c (n_structures) | lambda
  * (n_orbitals*M, row-major) | b_anti, b_par, b3..b6 | per nucleus a1..a6]

@@ -48,6 +48,12 @@ class _Wavefunction(ctypes.Structure):
                 ("een", ctypes.POINTER(ctypes.c_double))]
 
 
+class _Ecp(ctypes.Structure):
+    _fields_ = [("n_centers", ctypes.c_int32), ("center", ctypes.POINTER(ctypes.c_int32)),
+                ("n_channels", ctypes.POINTER(ctypes.c_int32)), ("r_cut", ctypes.POINTER(ctypes.c_double)),
+                ("n_terms", ctypes.POINTER(ctypes.c_int32)), ("terms", ctypes.POINTER(ctypes.c_double))]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
                 ("walker_lanes", ctypes.c_int32), ("step_kernel", ctypes.c_int32),
@@ -90,7 +96,7 @@ def _dmc_log(log, step_ms):
 
 _lib = None
 
-EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info", "vbqmc_set_params",
+EXPORTS = ["vbqmc_create", "vbqmc_destroy", "vbqmc_last_error", "vbqmc_get_info", "vbqmc_set_params", "vbqmc_set_ecp",
            "vbqmc_get_params", "vbqmc_evaluate", "vbqmc_walkers_init", "vbqmc_walkers_positions",
            "vbqmc_walkers_eloc", "vbqmc_vmc_advance", "vbqmc_vmc_sweep", "vbqmc_vmc_measure",
            "vbqmc_dmc_workspace_bytes", "vbqmc_dmc_advance", "vbqmc_dmc_advance_noalloc",
@@ -119,6 +125,7 @@ def load_library(path=LIB_PATH):
     lib.vbqmc_last_error.restype = ctypes.c_char_p
     lib.vbqmc_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.vbqmc_set_params.argtypes = [vp, ctypes.POINTER(dbl)]
+    lib.vbqmc_set_ecp.argtypes = [vp, ctypes.POINTER(_Ecp)]
     lib.vbqmc_get_params.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.vbqmc_evaluate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.vbqmc_walkers_init.argtypes = [vp, i64, vp, vp, vp]
@@ -251,6 +258,8 @@ class Context:
         self.n_params = info.n_params
         self.rec_doubles = info.walker_state_bytes // 8
         self.precision = precision
+        if system.get("ecp"):
+            self.set_ecp(system["ecp"])
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -461,6 +470,20 @@ class Context:
         p = np.zeros(self.n_params)
         self._rc(self._lib.vbqmc_get_params(self._h, _dp(p)))
         return p
+
+    def set_ecp(self, ecp):
+        """Attach pseudopotentials (vbqmc_set_ecp): a list of {"center",
+        "r_cut", "local": [[c, n, alpha], ..], "channels": [[[c, n, alpha],
+        ..] per l]}, or None / [] to remove them."""
+        ecp = ecp or []
+        cen = np.ascontiguousarray([e["center"] for e in ecp] or [0], np.int32)
+        nch = np.ascontiguousarray([len(e["channels"]) for e in ecp] or [0], np.int32)
+        rc = np.ascontiguousarray([e["r_cut"] for e in ecp] or [0.0], np.float64)
+        parts = [p for e in ecp for p in [e["local"]] + list(e["channels"])]
+        nt = np.ascontiguousarray([len(p) for p in parts] or [0], np.int32)
+        terms = np.ascontiguousarray([t for p in parts for t in p] or [[0.0, 0.0, 0.0]], np.float64).reshape(-1)
+        arg = _Ecp(len(ecp), _ip(cen), _ip(nch), _dp(rc), _ip(nt), _dp(terms))
+        self._rc(self._lib.vbqmc_set_ecp(self._h, ctypes.byref(arg)))
 
     def set_params(self, p):
         p = np.ascontiguousarray(p, np.float64)

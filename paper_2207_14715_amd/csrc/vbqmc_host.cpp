@@ -17,14 +17,15 @@
 
 #include "../../include/vbqmc.h"
 #include "vbqmc_internal.h"
+#include "vbqmc_ecp.h"
 
 namespace vbqmc {
 hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, int64_t rstride,
                            double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio, double* state,
-                           hipStream_t s);
+                           const DevEcp& ecp, hipStream_t s);
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
-                      hipStream_t s);
+                      const DevEcp& ecp, hipStream_t s);
 hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_g, int G, const DevWF* dwf_aux,
                             int nt, int phases, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                             double step_size, double* es, double* e2s, double* na, double* el, double* sij,
@@ -164,6 +165,8 @@ struct vbqmc_ctx {
   double* d_wcoef[2] = {nullptr, nullptr};
   double* d_slc = nullptr;
   DevWF* d_wf = nullptr;
+  DevEcp ecp{};                 // pseudopotentials (vbqmc_set_ecp); ncen = 0 for none
+  char* d_ecp = nullptr;        // their tables
   DevWF* d_wf_sweep = nullptr;  // same tables, compact LDS layout of the sweep kernel
   DevWF* d_wf_sweepg = nullptr; // same tables, layout of the wavefront sweep (several walkers per wavefront)
   int sweep_g = 64;             // lanes per walker in the single-electron sweep
@@ -1288,6 +1291,7 @@ int vbqmc_create(const vbqmc_system* sys, const vbqmc_wavefunction* wfi, const v
 void vbqmc_destroy(vbqmc_ctx* ctx) {
   if (!ctx) return;
   if (ctx->dmem) (void)hipFree(ctx->dmem);
+  if (ctx->d_ecp) (void)hipFree(ctx->d_ecp);
   delete ctx;
 }
 
@@ -1336,6 +1340,67 @@ int vbqmc_set_params(vbqmc_ctx* x, const double* p) {
   return VBQMC_OK;
 }
 
+int vbqmc_set_ecp(vbqmc_ctx* x, const vbqmc_ecp* ecp) {
+  if (!x) return VBQMC_EINVAL;
+  const int nc = ecp ? ecp->n_centers : 0;
+  if (nc < 0 || nc > x->nnuc) return fail(x, VBQMC_EINVAL, "set_ecp: bad number of centres");
+  if (nc && (x->wf.precision != VBQMC_FP64 || x->wf.trial_prec != VBQMC_FP64))
+    return fail(x, VBQMC_EINVAL, "set_ecp: pseudopotentials need the FP64 precision form");
+  if (nc && !x->een.empty()) return fail(x, VBQMC_EINVAL, "set_ecp: not available with f_een");
+  if (nc && (!ecp->center || !ecp->n_channels || !ecp->r_cut || !ecp->n_terms || !ecp->terms))
+    return fail(x, VBQMC_EINVAL, "set_ecp: arrays missing");
+  std::vector<int> info(8 * (size_t)nc, 0);
+  std::vector<double> rcut(nc), terms;
+  std::vector<char> seen(x->nnuc, 0);
+  int k = 0, t = 0;
+  for (int c = 0; c < nc; ++c) {
+    const int a = ecp->center[c], L = ecp->n_channels[c];
+    if (a < 0 || a >= x->nnuc || seen[a]) return fail(x, VBQMC_EINVAL, "set_ecp: bad or repeated centre");
+    seen[a] = 1;
+    if (L < 0 || L > kEcpMaxL) return fail(x, VBQMC_EINVAL, "set_ecp: at most 4 nonlocal channels");
+    if (!(ecp->r_cut[c] >= 0.0) || !std::isfinite(ecp->r_cut[c])) return fail(x, VBQMC_EINVAL, "set_ecp: bad r_cut");
+    rcut[c] = ecp->r_cut[c];
+    info[8 * c] = a;
+    info[8 * c + 1] = L;
+    info[8 * c + 2] = (int)(terms.size() / 3);
+    for (int q = 0; q <= L; ++q) {
+      const int nt = ecp->n_terms[k++];
+      if (nt < 0 || nt > 64) return fail(x, VBQMC_EINVAL, "set_ecp: bad term count");
+      for (int j = 0; j < nt; ++j, ++t) {
+        const double cc = ecp->terms[3 * t], n = ecp->terms[3 * t + 1], al = ecp->terms[3 * t + 2];
+        if (!std::isfinite(cc) || !(al >= 0.0) || !std::isfinite(al) || n != std::floor(n) || n < 0 || n > 6)
+          return fail(x, VBQMC_EINVAL, "set_ecp: a term needs finite c, integer n in 0..6 and alpha >= 0");
+        terms.insert(terms.end(), {cc, n, al});
+      }
+      info[8 * c + 3 + q] = (int)(terms.size() / 3);
+    }
+  }
+  // kernels still running on any stream may read the tables replaced below
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hipfail(x, e, "set_ecp: device synchronisation");
+  if (x->d_ecp) (void)hipFree(x->d_ecp);
+  x->d_ecp = nullptr;
+  x->ecp = DevEcp{};
+  if (!nc) return VBQMC_OK;
+  const size_t bi = info.size() * sizeof(int), br = rcut.size() * 8, bt = std::max<size_t>(terms.size(), 1) * 8;
+  const size_t oi = 0, orc = (bi + 255) / 256 * 256, ot = orc + (br + 255) / 256 * 256;
+  e = hipMalloc((void**)&x->d_ecp, ot + bt);
+  if (e != hipSuccess) {
+    x->d_ecp = nullptr;
+    return fail(x, VBQMC_ENOMEM, "set_ecp: device allocation");
+  }
+  e = hipMemcpy(x->d_ecp + oi, info.data(), bi, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->d_ecp + orc, rcut.data(), br, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !terms.empty()) e = hipMemcpy(x->d_ecp + ot, terms.data(), terms.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(x->d_ecp);
+    x->d_ecp = nullptr;
+    return hipfail(x, e, "set_ecp: upload");
+  }
+  x->ecp = DevEcp{nc, (const int*)(x->d_ecp + oi), (const double*)(x->d_ecp + orc), (const double*)(x->d_ecp + ot)};
+  return VBQMC_OK;
+}
+
 int vbqmc_get_params(const vbqmc_ctx* x, double* p) {
   if (!x || !p) return VBQMC_EINVAL;
   int k = 0;
@@ -1357,7 +1422,7 @@ int vbqmc_evaluate(vbqmc_ctx* x, int64_t W, const double* R, double* logabs, int
   if (W == 0) return VBQMC_OK;
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "evaluate: too many walkers");
   hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, 3 * x->N, logabs, sign, grad, eloc, ratio, nullptr,
-                                 (hipStream_t)stream);
+                                 x->ecp, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "evaluate");
 }
 
@@ -1366,7 +1431,7 @@ int vbqmc_walkers_init(vbqmc_ctx* x, int64_t W, const double* R, void* state, vb
   if (W == 0) return VBQMC_OK;
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "walkers_init: too many walkers");
   hipError_t e = launch_evaluate(x->wf, x->d_wf, x->nt, W, R, 3 * x->N, nullptr, nullptr, nullptr, nullptr, nullptr, (double*)state,
-                                 (hipStream_t)stream);
+                                 x->ecp, (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "walkers_init");
 }
 
@@ -1402,6 +1467,7 @@ int vbqmc_vmc_sweep(vbqmc_ctx* x, void* state, int64_t W, uint64_t seed, uint64_
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_sweep: too many walkers");
   if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_sweep: system too large for the sweep kernels");
   if (!x->een.empty()) return fail(x, VBQMC_EINVAL, "vmc_sweep: not available with f_een");
+  if (x->ecp.ncen) return fail(x, VBQMC_EINVAL, "vmc_sweep: not available with pseudopotentials");
   if (W == 0) return VBQMC_OK;
   hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 1,
                                   (double*)state, W, 1, seed, step, step_size, nullptr, nullptr, n_accept, nullptr,
@@ -1414,6 +1480,7 @@ int vbqmc_vmc_measure(vbqmc_ctx* x, void* state, int64_t W, const vbqmc_vmc_acc*
   if (W > (int64_t)INT32_MAX) return fail(x, VBQMC_EINVAL, "vmc_measure: too many walkers");
   if (!split_fits(x)) return fail(x, VBQMC_EINVAL, "vmc_measure: system too large for the local-energy kernels");
   if (!x->een.empty()) return fail(x, VBQMC_EINVAL, "vmc_measure: not available with f_een");
+  if (x->ecp.ncen) return fail(x, VBQMC_EINVAL, "vmc_measure: not available with pseudopotentials");
   if (W == 0) return VBQMC_OK;
   if (!acc->e_sum || !acc->e2_sum || !acc->e_last)
     return fail(x, VBQMC_EINVAL, "vmc_measure: accumulator pointers missing");
@@ -1434,14 +1501,15 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
   if (!all_electron && !x->een.empty() && x->step_kernel != 3)
     return fail(x, VBQMC_EINVAL,
                 "vmc: with f_een, single-electron moves need the walker-resident kernel (a system that fits it)");
-  if (!all_electron && x->step_kernel == 2) {
+  // with pseudopotentials every step runs on the one-workgroup-per-walker kernel
+  if (!all_electron && x->step_kernel == 2 && !x->ecp.ncen) {
     // single-electron moves and E_L of every step in one row-kernel launch
     hipError_t e = launch_vmc_rows(x->wf, x->d_wf_rows, (double*)state, W, n_steps, seed, step0, step_size,
                                    acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum,
                                    (hipStream_t)stream);
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
-  if (!all_electron && x->step_kernel == 3 && (!acc->sij_sum || x->nstruct <= 256)) {
+  if (!all_electron && x->step_kernel == 3 && (!acc->sij_sum || x->nstruct <= 256) && !x->ecp.ncen) {
     // rebuild the records (orbital-row caches at every electron), then one
     // walker-resident launch per step: moves, refresh and E_L
     DwVmc vm{step_size, W, acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum};
@@ -1452,7 +1520,7 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
                           (hipStream_t)stream);
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
-  if (!all_electron && split_fits(x)) {
+  if (!all_electron && split_fits(x) && !x->ecp.ncen) {
     // single-electron moves: walker-resident sweep + batched local energy
     hipError_t e = launch_vmc_split(x->wf, x->d_wf_sweep, x->d_wf_sweepg, x->sweep_g, x->d_wf_aux, x->nt, 3,
                                     (double*)state, W, n_steps, seed, step0, step_size, acc->e_sum, acc->e2_sum,
@@ -1460,7 +1528,8 @@ int vbqmc_vmc_advance(vbqmc_ctx* x, void* state, int64_t W, int32_t n_steps, uin
     return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
   }
   hipError_t e = launch_vmc(x->wf, x->d_wf, x->nt, (double*)state, W, n_steps, seed, step0, step_size, all_electron ? 1 : 0,
-                            acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum, (hipStream_t)stream);
+                            acc->e_sum, acc->e2_sum, acc->n_accept, acc->e_last, acc->sij_sum, x->ecp,
+                            (hipStream_t)stream);
   return e == hipSuccess ? VBQMC_OK : hipfail(x, e, "vmc");
 }
 
@@ -1524,6 +1593,7 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
     return fail(x, VBQMC_EINVAL, "dmc: bad arguments");
   if (!lg->pop || !lg->wsum || !lg->wesum || !lg->etrial || !lg->n_accept || !lg->n_prop)
     return fail(x, VBQMC_EINVAL, "dmc: log pointers missing");
+  if (x->ecp.ncen) return fail(x, VBQMC_EINVAL, "dmc: not available with pseudopotentials");
   int64_t W = *W_io;
   if (!x->een.empty() && x->dmc_kernel != 3)
     return fail(x, VBQMC_EINVAL, "dmc: with f_een, DMC needs the walker-resident kernel (a system that fits it)");
@@ -1568,7 +1638,7 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
                            seed, 0, tau, Vpw, ekw, epw, br, 1, s);
   else
     e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
-                        nullptr, nullptr, cur, s);
+                        nullptr, nullptr, cur, DevEcp{}, s);
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   // optional per-step timing of the move-and-energy kernels
   std::vector<hipEvent_t> ev;
@@ -1662,6 +1732,7 @@ int vbqmc_param_grad_workspace_bytes(const vbqmc_ctx* x, int64_t W, size_t* byte
 int vbqmc_param_grad(vbqmc_ctx* x, int64_t W, const double* R, double* dlogpsi, double* deloc, void* ws,
                      size_t ws_bytes, vbqmc_stream stream) {
   if (!x || W < 0 || (W > 0 && (!R || !dlogpsi || !deloc))) return fail(x, VBQMC_EINVAL, "param_grad: bad arguments");
+  if (x->ecp.ncen) return fail(x, VBQMC_EINVAL, "param_grad: not available with pseudopotentials");
   if (W == 0) return VBQMC_OK;
   size_t need = param_grad_ws_doubles(x->wf, W) * 8;
   if (need && (!ws || ws_bytes < need)) return fail(x, VBQMC_EWORKSPACE, "param_grad: workspace too small");

@@ -30,6 +30,7 @@
 // and an accepted move updates B and T by Sherman-Morrison rank-1 steps.
 
 #include "vbqmc_device.h"
+#include "vbqmc_ecp.h"
 
 namespace vbqmc {
 
@@ -71,10 +72,86 @@ __device__ void store_record(const DevWF& wf, const Ld& l, double* rec) {
 // ---------------------------------------------------------------------------
 extern __shared__ double lds_dyn[];
 
+// ---------------------------------------------------------------------------
+// Pseudopotential part of the local energy (Sec. 2.1: valence calculations
+// with energy-consistent pseudopotentials; the semilocal form).  Per
+// pseudo-nucleus a and electron i at distance r: the local radial part, and
+// for r < r_cut each nonlocal channel l as (2l + 1) times the mean over the
+// 12 icosahedron directions u_q of P_l(u_q . (r_i - a) / r) Psi(r_i -> a +
+// r u_q) / Psi, the ratio formed like a single-electron move (orbital row at
+// the point, determinant-table ratio, Jastrow change).  The whole workgroup
+// runs every point; thread 0 sums.  Returns the energy in every thread.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ecp_radial(const double* t, int k0, int k1, double r) {
+  double v = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const int n = (int)t[3 * k + 1];
+    double p = 1.0;
+    for (int e = 2; e < n; ++e) p *= r;
+    for (int e = n; e < 2; ++e) p /= r;
+    v += t[3 * k] * p * exp(-t[3 * k + 2] * r * r);
+  }
+  return v;
+}
+
+template <int NT, int PREC>
+__device__ double ecp_energy(const DevWF& wf, const Ld& l, const DevEcp& ep) {
+  const double g = 1.6180339887498949, un = 1.0 / sqrt(1.0 + g * g);
+  const double* nuc = l.nuc();
+  double* sc = l.sc();
+  double part[1] = {0.0};  // local parts (all threads) + nonlocal points (thread 0)
+  for (int c = 0; c < ep.ncen; ++c) {
+    const int* inf = ep.info + 8 * c;
+    const int a = inf[0], L = inf[1];
+    const double ax = nuc[4 * a], ay = nuc[4 * a + 1], az = nuc[4 * a + 2];
+    for (int i = threadIdx.x; i < wf.N; i += NT) {
+      const double dx = l.R()[3 * i] - ax, dy = l.R()[3 * i + 1] - ay, dz = l.R()[3 * i + 2] - az;
+      part[0] += ecp_radial(ep.terms, inf[2], inf[3], sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    if (L == 0) continue;
+    const double rc = ep.rcut[c];
+    for (int i = 0; i < wf.N; ++i) {
+      const double dx = l.R()[3 * i] - ax, dy = l.R()[3 * i + 1] - ay, dz = l.R()[3 * i + 2] - az;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (!(r < rc)) continue;  // (the same decision in every thread)
+      double vl[kEcpMaxL];
+      for (int q = 0; q < L; ++q) vl[q] = (2 * q + 1) * ecp_radial(ep.terms, inf[3 + q], inf[4 + q], r) / kEcpPts;
+      for (int q = 0; q < kEcpPts; ++q) {
+        // vertex q: the cyclic form q >> 2 of (0, +-1, +-g), signs from the low bits
+        const double s1 = (q & 1) ? un : -un, s2 = (q & 2) ? g * un : -g * un;
+        const int k = q >> 2;
+        const double ux = k == 0 ? 0.0 : (k == 1 ? s1 : s2);
+        const double uy = k == 0 ? s1 : (k == 1 ? s2 : 0.0);
+        const double uz = k == 0 ? s2 : (k == 1 ? 0.0 : s1);
+        const double px = ax + r * ux, py = ay + r * uy, pz = az + r * uz;
+        point_orbitals<NT, PREC>(wf, l, px, py, pz, 1);
+        move_ratio<NT>(wf, l, i, px, py, pz, l.v());
+        if (threadIdx.x == 0) {
+          const double x = (ux * dx + uy * dy + uz * dz) / r;
+          const double P[kEcpMaxL] = {1.0, x, 0.5 * (3.0 * x * x - 1.0), 0.5 * (5.0 * x * x * x - 3.0 * x)};
+          double wq = 0.0;
+          for (int m = 0; m < L; ++m) wq += vl[m] * P[m];
+          part[0] += wq * sc[SC_RATIO] * exp(sc[SC_TMP0]);
+        }
+      }
+    }
+  }
+  block_sum<NT, 1>(part, l.red());
+  return part[0];
+}
+
+// E_L (SC_ELOC) += the pseudopotential energy
+template <int NT, int PREC>
+__device__ void ecp_add(const DevWF& wf, const Ld& l, const DevEcp& ep) {
+  const double e = ecp_energy<NT, PREC>(wf, l, ep);
+  if (threadIdx.x == 0) l.sc()[SC_ELOC] += e;
+  __syncthreads();
+}
+
 template <int NT, int PREC, bool EEN = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_evaluate(const DevWF* __restrict__ pwf, int64_t W, const double* __restrict__ Rin,
                                                  int64_t rstride, double* logabs, int32_t* sign, double* grad,
-                                                 double* eloc, double* ratio, double* state) {
+                                                 double* eloc, double* ratio, double* state, DevEcp ecp) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   if (w >= W) return;
@@ -114,6 +191,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     return;
   }
   local_energy<NT, PREC, EEN>(wf, l, state ? state + w * wf.rec_len + wf.r_gc : nullptr);
+  if (ecp.ncen) ecp_add<NT, PREC>(wf, l, ecp);
   if (ratio) structure_ratios<NT>(wf, l);
   double* sc = l.sc();
   if (threadIdx.x == 0) {
@@ -190,7 +268,8 @@ __device__ bool all_electron_move(const DevWF& wf, const Ld& l, int64_t w, uint6
 template <int NT, int PREC, bool EEN = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_vmc(const DevWF* __restrict__ pwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                             uint64_t step0, double step_size, int all_electron, double* e_sum,
-                                            double* e2_sum, double* n_acc, double* e_last, double* sij_sum) {
+                                            double* e2_sum, double* n_acc, double* e_last, double* sij_sum,
+                                            DevEcp ecp) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   if (w >= W) return;
@@ -238,6 +317,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     if (!(sc[SC_S] != 0.0)) { bad = true; break; }
     local_energy<NT, PREC, EEN>(wf, l, nullptr);
+    if (ecp.ncen) ecp_add<NT, PREC>(wf, l, ecp);
     double el = sc[SC_ELOC];
     es += el;
     e2s += el * el;
@@ -886,24 +966,24 @@ static hipError_t set_lds(const void* fn, size_t bytes) {
 template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, int64_t rstride,
                                     double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio,
-                                    double* state, hipStream_t s) {
+                                    double* state, const DevEcp& ecp, hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_evaluate<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, rstride, logabs, sign, grad,
-                     eloc, ratio, state);
+                     eloc, ratio, state, ecp);
   return hipGetLastError();
 }
 
 template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                uint64_t step0, double step_size, int all_e, double* es, double* e2s,
-                               double* na, double* el, double* sij, hipStream_t s) {
+                               double* na, double* el, double* sij, const DevEcp& ecp, hipStream_t s) {
   size_t lds = (size_t)wf.lds_doubles * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_vmc<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_vmc<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, state, W, nsteps, seed, step0,
-                     step_size, all_e, es, e2s, na, el, sij);
+                     step_size, all_e, es, e2s, na, el, sij, ecp);
   return hipGetLastError();
 }
 
@@ -943,17 +1023,20 @@ static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* s
 
 hipError_t launch_evaluate(const DevWF& wf, const DevWF* dwf, int nt, int64_t W, const double* R, int64_t rstride,
                            double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio, double* state,
-                           hipStream_t s) {
-  if (wf.neen) VB_DISPATCH_EEN(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, s)
-  VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, s)
+                           const DevEcp& ecp, hipStream_t s) {
+  if (wf.neen)
+    VB_DISPATCH_EEN(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, ecp, s)
+  VB_DISPATCH_NT(nt, launch_evaluate_t, wf, dwf, W, R, rstride, logabs, sign, grad, eloc, ratio, state, ecp, s)
 }
 
 hipError_t launch_vmc(const DevWF& wf, const DevWF* dwf, int nt, double* state, int64_t W, int nsteps, uint64_t seed, uint64_t step0,
                       double step_size, int all_e, double* es, double* e2s, double* na, double* el, double* sij,
-                      hipStream_t s) {
+                      const DevEcp& ecp, hipStream_t s) {
   if (wf.neen)
-    VB_DISPATCH_EEN(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
-  VB_DISPATCH_NT(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, s)
+    VB_DISPATCH_EEN(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij,
+                    ecp, s)
+  VB_DISPATCH_NT(nt, launch_vmc_t, wf, dwf, state, W, nsteps, seed, step0, step_size, all_e, es, e2s, na, el, sij, ecp,
+                 s)
 }
 
 
