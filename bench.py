@@ -12,7 +12,7 @@ step (64 single-electron moves and its local energy).  Inputs are seeded and
 synthetic and resident in device memory when timing starts.
 
 Other forms: --form vmc (the F2-shaped VMC row kernel; --system precision the 40-electron molecule,
---system h2 the all-electron H2 workload), precision, adjoint.
+--system h2 the all-electron H2 workload), precision, adjoint, ecp.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form ...]
 Prints one JSON line.
@@ -164,7 +164,7 @@ def main():
                     help="precision form: cap on the Gaussian exponents of the molecule (default: the workload's 1e4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--form", default="dmc", choices=["dmc", "vmc", "plain", "precision", "adjoint"],
+    ap.add_argument("--form", default="dmc", choices=["dmc", "vmc", "plain", "precision", "adjoint", "ecp"],
                     help="dmc: the headline DMC line on the 64-electron molecule; vmc (or plain): VMC on the "
                          "F2-shaped diatomic; precision: FP32/BF16 basis+contraction forms on the 10-nucleus "
                          "molecule; adjoint: parameter gradients on the 6-nucleus molecule")
@@ -189,6 +189,8 @@ def main():
         return precision_form(args)
     if args.form == "adjoint":
         return adjoint_form(args)
+    if args.form == "ecp":
+        return ecp_form(args)
     if args.form == "dmc":
         return dmc_form(args)
     if args.system == "h2":
@@ -545,6 +547,73 @@ def adjoint_form(args):
                                    "flops_per_gradient": adjoint_flops_per_gradient(ctx, system)},
                       "config": {"workload": "6 nuclei, 30 electrons, 120 Gaussian basis functions, 12 VB "
                                              "structures / 40 determinants, kappa = 0.8 Jastrow with polynomials"}}))
+
+
+def ecp_points(system, R):
+    """(electron, pseudo-nucleus) pairs within r_cut per configuration, times
+    the 12 points of the angular rule: the ratio evaluations of one E_L."""
+    import numpy as np
+    pos = np.asarray(system["nuclei"]["pos"], np.float64)
+    n = 0
+    for cen in system["ecp"]:
+        if cen["channels"]:
+            d = np.linalg.norm(R - pos[cen["center"]], axis=-1)
+            n += int((d < cen["r_cut"]).sum())
+    return 12 * n / R.shape[0]
+
+
+def ecp_flops_per_point(ctx, system):
+    """One ratio of the nonlocal projection: the work of a single-electron
+    move's ratio (basis values and contraction at the point, determinant-table
+    ratio, Jastrow change; averaged over the two spins) plus the Legendre
+    weights (15)."""
+    N, M, norb, nnuc, P, spins = _dims(ctx, system)
+    per = [(P * (4 + EXP_FLOPS) + 2 * M) + 2 * M * norb + (2 * n + 2 * n * nP + 6 * u) + (N - 1 + nnuc) * 2 * 12
+           for n, nP, u in spins]
+    return sum(per) / len(per) + 15
+
+
+def ecp_form(args):
+    """E_L with semilocal pseudopotentials on the F2 valence system (14
+    electrons, Z_eff = 7 per atom, s and p nonlocal channels, r_cut 2.5 bohr,
+    12-point rule): evaluate calls of the one-workgroup-per-walker kernel on
+    8192 VMC-equilibrated configurations, with and without the
+    pseudopotential term, and VMC steps with it."""
+    import torch
+
+    import paper_2207_14715_amd as vb
+    import systems as S
+    system = S.f2_valence_ecp()
+    plain = {k: v for k, v in system.items() if k != "ecp"}
+    W = args.walkers or 8192
+    ctx = vb.Context(system)
+    ctx0 = vb.Context(plain)
+    # the pseudopotential does not change Psi: sample with the plain context
+    st = ctx0.walkers_init(torch.from_numpy(S.initial_walkers(system, W, seed=3)).cuda())
+    ctx0.vmc_advance(st, max(args.warmup if args.warmup is not None else 30, 1), 5, 0, 0.4)
+    R = ctx0.positions(st)
+    reps = 3
+    ctx.evaluate(R, want=("eloc",))
+    _, t = _timed(lambda: [ctx.evaluate(R, want=("eloc",)) for _ in range(reps)])
+    t /= reps
+    _, t0 = _timed(lambda: [ctx0.evaluate(R, want=("eloc",)) for _ in range(reps)])
+    t0 /= reps
+    pts = ecp_points(system, R.cpu().numpy())
+    fl = measure_flops_per_walker(ctx, system) + pts * ecp_flops_per_point(ctx, system)
+    tf = fl * W / t / 1e12
+    # VMC steps (single-electron moves + E_L with the term) on the same walkers
+    st1 = ctx.walkers_init(R)
+    nst = 2
+    _, tv = _timed(lambda: ctx.vmc_advance(st1, nst, 7, 100, 0.4))
+    print(json.dumps({"metric": "configurations/s (E_L with pseudopotentials)", "value": W / t,
+                      "unit": "configurations/s", "n_gpus": 1, "walkers": W, "dtype": "f64",
+                      "evaluate_ms": t * 1e3, "evaluate_without_ecp_ms": t0 * 1e3,
+                      "ratio_points_per_config": pts, "vmc_walker_steps_per_s": W * nst / tv,
+                      "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+                                   "flops_per_config": fl, "traffic": None},
+                      "config": {"workload": "F2 valence: 2 pseudo-nuclei (Z_eff 7), 14 electrons, 28 Gaussian "
+                                             "basis functions, 3 VB structures, s + p nonlocal channels"}}))
 
 
 HEADLINE_METRIC = "walker-moves/sec incl. E_L; mixed-prec & adjoint vs FP64 plain at \u0394E\u22641e-5 Ha"

@@ -1397,7 +1397,13 @@ int vbqmc_set_ecp(vbqmc_ctx* x, const vbqmc_ecp* ecp) {
     x->d_ecp = nullptr;
     return hipfail(x, e, "set_ecp: upload");
   }
-  x->ecp = DevEcp{nc, (const int*)(x->d_ecp + oi), (const double*)(x->d_ecp + orc), (const double*)(x->d_ecp + ot)};
+  // scratch of the batched projection (12 points of one electron and centre)
+  // beyond the walker kernels' LDS layout, when it fits the device's LDS
+  const int K = kEcpPts, C = std::max(1, x->nt / K), nPm = std::max(1, std::max(x->wf.sp[0].nP, x->wf.sp[1].nP));
+  const int scr = K * (4 + x->wf.Mpad + x->wf.nop + nPm + 3) + 3 * C * K;
+  const bool fits = (size_t)(x->wf.lds_doubles + scr) * 8 <= (size_t)x->lds_limit;
+  x->ecp = DevEcp{nc, (const int*)(x->d_ecp + oi), (const double*)(x->d_ecp + orc), (const double*)(x->d_ecp + ot),
+                  fits ? x->wf.lds_doubles : -1, fits ? scr : 0, nPm};
   return VBQMC_OK;
 }
 
@@ -1638,7 +1644,7 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
                            seed, 0, tau, Vpw, ekw, epw, br, 1, s);
   else
     e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
-                        nullptr, nullptr, cur, DevEcp{}, s);
+                        nullptr, nullptr, cur, DevEcp{0, nullptr, nullptr, nullptr, -1, 0, 0}, s);
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   // optional per-step timing of the move-and-energy kernels
   std::vector<hipEvent_t> ev;

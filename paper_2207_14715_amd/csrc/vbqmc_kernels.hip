@@ -94,9 +94,167 @@ __device__ __forceinline__ double ecp_radial(const double* t, int k0, int k1, do
   return v;
 }
 
+// direction q of the rule: the cyclic form q >> 2 of (0, +-1, +-g) / |.|,
+// signs from the low bits
+__device__ __forceinline__ void ecp_dir(int q, double& ux, double& uy, double& uz) {
+  const double g = 1.6180339887498949, un = 1.0 / sqrt(1.0 + g * g);
+  const double s1 = (q & 1) ? un : -un, s2 = (q & 2) ? g * un : -g * un;
+  const int k = q >> 2;
+  ux = k == 0 ? 0.0 : (k == 1 ? s1 : s2);
+  uy = k == 0 ? s1 : (k == 1 ? s2 : 0.0);
+  uz = k == 0 ? s2 : (k == 1 ? 0.0 : s1);
+}
+
+// The 12 ratios of electron i moved onto the sphere about a, all at once in
+// the scratch: basis values of the points (one thread per point and
+// function), their orbital rows, per point rho = sum_j v[ref_j] B[j][i],
+// the table residuals y, the Jastrow change and S'' = sum_u Q_u W_u, the
+// per-point sums split over C thread groups and added in a fixed order.
+// Returns sum_q w_q Psi_q / Psi in thread 0.
+template <int NT>
+__device__ double ecp_pair_batched(const DevWF& wf, const Ld& l, const DevEcp& ep, int i, double ax, double ay,
+                                   double az, double dx, double dy, double dz, double r, const double* vl, int L) {
+  constexpr int K = kEcpPts;
+  constexpr int C = NT / K > 0 ? NT / K : 1;
+  const int s = spin_of(wf, i);
+  const SpinTab& st = wf.sp[s];
+  const int n = st.n, nP = st.nP, il = i - st.e0, nPm = ep.nPmax > 0 ? ep.nPmax : 1;
+  const double* B = l.B(s);
+  const double* T = l.T(s);
+  const int* ref = l.ref(s);
+  const int* porb = l.porb(s);
+  const double* nuc = l.nuc();
+  double* Pq = l.L + ep.l_scr;          // [K][4]
+  double* chi = Pq + 4 * K;             // [K][Mpad]
+  double* v = chi + K * wf.Mpad;        // [K][nop]
+  double* y = v + K * wf.nop;           // [K][nPm]
+  double* part = y + K * nPm;           // [3][C][K]
+  double* res = part + 3 * C * K;       // [K][3]
+  if (threadIdx.x < K) {
+    double ux, uy, uz;
+    ecp_dir(threadIdx.x, ux, uy, uz);
+    Pq[4 * threadIdx.x] = ax + r * ux;
+    Pq[4 * threadIdx.x + 1] = ay + r * uy;
+    Pq[4 * threadIdx.x + 2] = az + r * uz;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < K * wf.Mpad; idx += NT) {
+    const int q = idx / wf.Mpad, mu = idx - q * wf.Mpad;
+    const int sh = l.fn()[2 * mu];
+    double o = 0.0;
+    if (sh >= 0) {
+      const int* si = l.sh() + 8 * sh;
+      const int a = si[0], kind = si[1], lq = si[2], p0 = si[4], np = si[5];
+      const double x = Pq[4 * q] - nuc[4 * a], yy = Pq[4 * q + 1] - nuc[4 * a + 1], z = Pq[4 * q + 2] - nuc[4 * a + 2];
+      const double r2 = x * x + yy * yy + z * z, rr = sqrt(r2);
+      double g = 0.0;
+      for (int k = 0; k < np; ++k) {
+        const double t = kind == 0 ? l.pe()[p0 + k] * r2 : l.pe()[p0 + k] * rr;
+        if (t < 50.0) g += l.pc()[p0 + k] * exp_neg<double>(t, l.L + wf.l_etab);
+      }
+      channels<double>(kind, lq, l.fn()[2 * mu + 1] & 15, x, yy, z, r2, rr, g, 0.0, 0.0, 1, &o);
+    }
+    chi[idx] = o;
+  }
+  __syncthreads();
+  const double* lam = l.lam<double>();
+  for (int idx = threadIdx.x; idx < K * wf.nop; idx += NT) {
+    const int q = idx / wf.nop, o = idx - q * wf.nop;
+    const double* ch = chi + q * wf.Mpad;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int mu = 0; mu < wf.Mpad; ++mu) acc += ch[mu] * lam[(size_t)mu * wf.nop + o];
+    v[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < K * nP; idx += NT) {
+    const int q = idx / nP, p = idx - q * nP;
+    const double* vq = v + q * wf.nop;
+    double a = vq[porb[p]];
+    for (int k = 0; k < n; ++k) a -= vq[ref[k]] * T[k * nP + p];
+    y[q * nPm + p] = a;
+  }
+  const double* R = l.R();
+  const double xo = R[3 * i], yo = R[3 * i + 1], zo = R[3 * i + 2];
+  const PairCoef c_anti = ee_coef(wf, true), c_par = ee_coef(wf, false);
+  for (int t = threadIdx.x; t < C * K; t += NT) {
+    const int q = t % K, c = t / K;
+    const double* vq = v + q * wf.nop;
+    double rho = 0.0, du = 0.0;
+    for (int j = c; j < n; j += C) rho += vq[ref[j]] * B[j * n + il];
+    const double px = Pq[4 * q], py = Pq[4 * q + 1], pz = Pq[4 * q + 2];
+    for (int j = c; j < wf.N + wf.nnuc; j += C) {
+      if (j == i) continue;
+      double xj, yj, zj;
+      PairCoef cf;
+      if (j < wf.N) {
+        xj = R[3 * j]; yj = R[3 * j + 1]; zj = R[3 * j + 2];
+        cf = s != spin_of(wf, j) ? c_anti : c_par;
+      } else {
+        const int nn = j - wf.N;
+        xj = nuc[4 * nn]; yj = nuc[4 * nn + 1]; zj = nuc[4 * nn + 2];
+        cf = en_coef(l.en() + 6 * nn);
+      }
+      const double rn = sqrt((px - xj) * (px - xj) + (py - yj) * (py - yj) + (pz - zj) * (pz - zj));
+      const double ro = sqrt((xo - xj) * (xo - xj) + (yo - yj) * (yo - yj) + (zo - zj) * (zo - zj));
+      du += pair_val(rn, wf.kappa, cf) - pair_val(ro, wf.kappa, cf);
+    }
+    part[c * K + q] = rho;
+    part[(C + c) * K + q] = du;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    const int q = threadIdx.x;
+    double rho = 0.0, du = 0.0;
+    for (int c = 0; c < C; ++c) {
+      rho += part[c * K + q];
+      du += part[(C + c) * K + q];
+    }
+    res[3 * q] = rho;
+    res[3 * q + 1] = du;
+  }
+  __syncthreads();
+  const int* uit = l.ui(s);
+  for (int t = threadIdx.x; t < C * K; t += NT) {
+    const int q = t % K, c = t / K;
+    const double rho = res[3 * q];
+    double acc = 0.0;
+    for (int u = c; u < st.nU; u += C) {
+      const int* ui = uit + 8 * u;
+      double m[9], yy[3], bb[3];
+      const int e = gather_u(ui, T, nP, m, nullptr, nullptr, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k < e) {
+          yy[k] = y[q * nPm + ui[4 + k]];
+          bb[k] = B[ui[1 + k] * n + il];
+        }
+      acc += (rho * l.Ru(s)[u] + adj_e(e, m, yy, bb)) * l.Wu(s)[u];
+    }
+    part[(2 * C + c) * K + q] = acc;
+  }
+  __syncthreads();
+  double e = 0.0;
+  if (threadIdx.x == 0) {
+    const double S = l.sc()[SC_S];
+    for (int q = 0; q < K; ++q) {
+      double ux, uy, uz;
+      ecp_dir(q, ux, uy, uz);
+      const double x = (ux * dx + uy * dy + uz * dz) / r;
+      const double P[kEcpMaxL] = {1.0, x, 0.5 * (3.0 * x * x - 1.0), 0.5 * (5.0 * x * x * x - 3.0 * x)};
+      double wq = 0.0;
+      for (int k = 0; k < L; ++k) wq += vl[k] * P[k];
+      double Sq = 0.0;
+      for (int c = 0; c < C; ++c) Sq += part[(2 * C + c) * K + q];
+      e += wq * (Sq / S) * exp(res[3 * q + 1]);
+    }
+  }
+  __syncthreads();  // the scratch is reused by the next pair
+  return e;
+}
+
 template <int NT, int PREC>
 __device__ double ecp_energy(const DevWF& wf, const Ld& l, const DevEcp& ep) {
-  const double g = 1.6180339887498949, un = 1.0 / sqrt(1.0 + g * g);
   const double* nuc = l.nuc();
   double* sc = l.sc();
   double part[1] = {0.0};  // local parts (all threads) + nonlocal points (thread 0)
@@ -116,13 +274,13 @@ __device__ double ecp_energy(const DevWF& wf, const Ld& l, const DevEcp& ep) {
       if (!(r < rc)) continue;  // (the same decision in every thread)
       double vl[kEcpMaxL];
       for (int q = 0; q < L; ++q) vl[q] = (2 * q + 1) * ecp_radial(ep.terms, inf[3 + q], inf[4 + q], r) / kEcpPts;
+      if (PREC == 0 && ep.l_scr >= 0) {
+        part[0] += ecp_pair_batched<NT>(wf, l, ep, i, ax, ay, az, dx, dy, dz, r, vl, L);
+        continue;
+      }
       for (int q = 0; q < kEcpPts; ++q) {
-        // vertex q: the cyclic form q >> 2 of (0, +-1, +-g), signs from the low bits
-        const double s1 = (q & 1) ? un : -un, s2 = (q & 2) ? g * un : -g * un;
-        const int k = q >> 2;
-        const double ux = k == 0 ? 0.0 : (k == 1 ? s1 : s2);
-        const double uy = k == 0 ? s1 : (k == 1 ? s2 : 0.0);
-        const double uz = k == 0 ? s2 : (k == 1 ? 0.0 : s1);
+        double ux, uy, uz;
+        ecp_dir(q, ux, uy, uz);
         const double px = ax + r * ux, py = ay + r * uy, pz = az + r * uz;
         point_orbitals<NT, PREC>(wf, l, px, py, pz, 1);
         move_ratio<NT>(wf, l, i, px, py, pz, l.v());
@@ -967,7 +1125,7 @@ template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_evaluate_t(const DevWF& wf, const DevWF* dwf, int64_t W, const double* R, int64_t rstride,
                                     double* logabs, int32_t* sign, double* grad, double* eloc, double* ratio,
                                     double* state, const DevEcp& ecp, hipStream_t s) {
-  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+  size_t lds = (size_t)(wf.lds_doubles + (ecp.ncen && ecp.l_scr >= 0 ? ecp.scr_doubles : 0)) * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_evaluate<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_evaluate<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, W, R, rstride, logabs, sign, grad,
@@ -979,7 +1137,7 @@ template <int NT, int PREC, bool EEN = false>
 static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state, int64_t W, int nsteps, uint64_t seed,
                                uint64_t step0, double step_size, int all_e, double* es, double* e2s,
                                double* na, double* el, double* sij, const DevEcp& ecp, hipStream_t s) {
-  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+  size_t lds = (size_t)(wf.lds_doubles + (ecp.ncen && ecp.l_scr >= 0 ? ecp.scr_doubles : 0)) * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_vmc<NT, PREC, EEN>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_vmc<NT, PREC, EEN>), dim3((unsigned)W), dim3(NT), lds, s, dwf, state, W, nsteps, seed, step0,
