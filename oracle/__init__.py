@@ -92,7 +92,11 @@ def max_threads():
 class Oracle:
     """The oracle for one system dict (see ``systems``)."""
 
-    def __init__(self, system):
+    def __init__(self, system, native_ecp=False):
+        """native_ecp: include the system's pseudopotentials (its "ecp" list)
+        in E_L of evaluate, vmc and dmc, computed in the C++ oracle (ratios by
+        fresh evaluation, as oracle.ecp does in numpy); off by default, so
+        that oracle.ecp can add the term itself."""
         lib = _load()
         self.system = system
         nuc = system["nuclei"]
@@ -144,6 +148,16 @@ class Oracle:
             _ip(self._tcounts), _ip(self._torbs), ctypes.c_double(self.kappa), _dp(self._ee), _dp(self._en),
             _dp(self._een) if self.n_een else None)
         self._lib = lib
+        if native_ecp and system.get("ecp"):
+            ecp = system["ecp"]
+            cen = np.ascontiguousarray([e["center"] for e in ecp], np.int32)
+            nch = np.ascontiguousarray([len(e["channels"]) for e in ecp], np.int32)
+            rc = np.ascontiguousarray([e["r_cut"] for e in ecp], np.float64)
+            parts = [p for e in ecp for p in [e["local"]] + list(e["channels"])]
+            nt = np.ascontiguousarray([len(p) for p in parts], np.int32)
+            terms = np.ascontiguousarray([t for p in parts for t in p] or [[0.0] * 3], np.float64).reshape(-1)
+            lib.orc_set_ecp(ctypes.c_void_p(self._h), ctypes.c_int(len(ecp)), _ip(cen), _ip(nch), _dp(rc), _ip(nt),
+                            _dp(terms))
         self.n_dets = int(lib.orc_num_dets(ctypes.c_void_p(self._h)))
         self.n_params = int(lib.orc_num_params(ctypes.c_void_p(self._h)))
         self.n_jastrow = 6 + 6 * self.n_nuc + self.n_een * self.n_nuc

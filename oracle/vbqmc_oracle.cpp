@@ -101,6 +101,14 @@ struct System {
   std::vector<double> jas;  // [b_anti, b_par, b3..b6 | per nucleus a1..a6 | per nucleus f_een c_t]
   int njas = 0;
   bool een = false;         // f_een present (its coefficients close jas)
+  // semilocal pseudopotentials: per centre the nucleus, r_cut and the radial
+  // parts (local, then channel l = 0, 1, ..) as [c, n, alpha] triples
+  struct EcpCentre {
+    int center = 0;
+    double rcut = 0;
+    std::vector<std::vector<double>> parts;
+  };
+  std::vector<EcpCentre> ecp;
   int nparam() const { return nstruct + norb * M + njas; }
 };
 
@@ -586,6 +594,65 @@ EvalOut<T> evaluate(const System& s, const Params<T>& P, const double* R, int le
 }
 
 // ---------------------------------------------------------------------------
+// Pseudopotential energy (semilocal form, Sec. 2.1 basis choice): per centre
+// and electron the local radial part, and for r < r_cut each channel l as
+// (2l + 1) times the mean over the 12 icosahedron directions of P_l(cos)
+// times Psi(moved) / Psi, every moved configuration evaluated afresh.
+// ---------------------------------------------------------------------------
+double ecp_radial(const std::vector<double>& t, double r) {
+  double v = 0;
+  for (size_t k = 0; k + 2 < t.size(); k += 3) {
+    v += t[k] * std::pow(r, t[k + 1] - 2.0) * std::exp(-t[k + 2] * r * r);
+  }
+  return v;
+}
+
+double ecp_energy(const System& s, const Params<double>& P, const double* R, const EvalOut<double>& base) {
+  const double g = (1.0 + std::sqrt(5.0)) / 2.0, nrm = std::sqrt(1.0 + g * g);
+  double u[12][3];
+  int q = 0;
+  for (double s1 : {-1.0, 1.0})
+    for (double s2 : {-1.0, 1.0}) {
+      const double v[3][3] = {{0.0, s1, s2 * g}, {s1, s2 * g, 0.0}, {s2 * g, 0.0, s1}};
+      for (int k = 0; k < 3; ++k, ++q)
+        for (int x = 0; x < 3; ++x) u[q][x] = v[k][x] / nrm;
+    }
+  double e = 0;
+  std::vector<double> Rq(R, R + 3 * s.N);
+  for (const System::EcpCentre& c : s.ecp) {
+    const double* a = &s.pos[3 * c.center];
+    for (int i = 0; i < s.N; ++i) {
+      double d[3] = {R[3 * i] - a[0], R[3 * i + 1] - a[1], R[3 * i + 2] - a[2]};
+      const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      e += ecp_radial(c.parts[0], r);
+      if (!(r < c.rcut) || c.parts.size() < 2) continue;
+      for (int k = 0; k < 12; ++k) {
+        const double x = (u[k][0] * d[0] + u[k][1] * d[1] + u[k][2] * d[2]) / r;
+        const double Pl[4] = {1.0, x, 0.5 * (3 * x * x - 1), 0.5 * (5 * x * x * x - 3 * x)};
+        double w = 0;
+        for (size_t l = 0; l + 1 < c.parts.size(); ++l) w += (2.0 * l + 1.0) / 12.0 * ecp_radial(c.parts[l + 1], r) * Pl[l];
+        for (int x3 = 0; x3 < 3; ++x3) Rq[3 * i + x3] = a[x3] + r * u[k][x3];
+        EvalOut<double> o = evaluate(s, P, Rq.data(), 0);
+        for (int x3 = 0; x3 < 3; ++x3) Rq[3 * i + x3] = R[3 * i + x3];
+        if (o.ok) e += w * o.sign * base.sign * std::exp(o.logabs - base.logabs);
+      }
+    }
+  }
+  return e;
+}
+
+// evaluate() with the pseudopotential energy in E_L (level 2)
+EvalOut<double> evaluate_h(const System& s, const Params<double>& P, const double* R, int level) {
+  EvalOut<double> o = evaluate(s, P, R, level);
+  if (level >= 2 && o.ok && !s.ecp.empty()) {
+    const double e = ecp_energy(s, P, R, o);
+    o.eloc += e;
+    o.pot += e;
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
 // published definition: ten rounds of two 32x32->64 multiplies with the
 // round constants M0 = 0xD2511F53, M1 = 0xCD9E8D57 and a Weyl key schedule
@@ -733,6 +800,25 @@ void* orc_create(int nnuc, const double* Z, const double* pos, int nup, int ndn,
 
 void orc_destroy(void* h) { delete (System*)h; }
 
+int orc_set_ecp(void* h, int ncen, const int* center, const int* nch, const double* rcut, const int* nterms,
+                const double* terms) {
+  System& s = *(System*)h;
+  s.ecp.clear();
+  int k = 0, t = 0;
+  for (int c = 0; c < ncen; ++c) {
+    System::EcpCentre e;
+    e.center = center[c];
+    e.rcut = rcut[c];
+    for (int q = 0; q <= nch[c]; ++q) {
+      std::vector<double> part(terms + 3 * t, terms + 3 * (t + nterms[k]));
+      t += nterms[k++];
+      e.parts.push_back(part);
+    }
+    s.ecp.push_back(e);
+  }
+  return 0;
+}
+
 int orc_num_dets(void* h) { return (int)((System*)h)->dets.size(); }
 int orc_num_params(void* h) { return ((System*)h)->nparam(); }
 int orc_max_threads() { return max_threads(); }
@@ -786,7 +872,7 @@ int orc_evaluate(void* h, int W, const double* R, int level, double* logabs, int
   int bad = 0;
 #pragma omp parallel for schedule(dynamic) reduction(+ : bad)
   for (int w = 0; w < W; ++w) {
-    EvalOut<double> o = evaluate(s, P, R + (size_t)w * s.N * 3, level);
+    EvalOut<double> o = evaluate_h(s, P, R + (size_t)w * s.N * 3, level);
     if (!o.ok) {
       ++bad;
       logabs[w] = -INFINITY;
@@ -892,7 +978,7 @@ int orc_vmc(void* h, int W, double* R, int nsteps, uint64_t seed, uint32_t step0
           }
         }
       }
-      EvalOut<double> full = evaluate(s, P, Rw, 2);
+      EvalOut<double> full = evaluate_h(s, P, Rw, 2);
       if (!full.ok) { ++bad; break; }
       e_sum[w] += full.eloc;
       e2_sum[w] += full.eloc * full.eloc;
@@ -989,7 +1075,7 @@ int orc_dmc(void* h, int* W_io, int capacity, double* R, double* eloc_io, int ns
           for (int x = 0; x < 3; ++x) Rn[3 * e + x] = Rw[3 * e + x];
         }
       }
-      EvalOut<double> full = evaluate(s, P, Rw, 2);
+      EvalOut<double> full = evaluate_h(s, P, Rw, 2);
       if (!full.ok) { ++bad; continue; }
       double eo = std::min(std::max(eloc_io[w], ET - cap), ET + cap);
       double en = std::min(std::max(full.eloc, ET - cap), ET + cap);

@@ -55,17 +55,22 @@ def _closed_form(sysd, R, l, alpha):
     return e + np.where(near, ECP.radial(cen["channels"][l], r), 0.0)
 
 
+@pytest.mark.parametrize("native", [False, True])
 @pytest.mark.parametrize("l,lam", [(0, [1.0]), (1, [0.0, 0.0, 1.0]), (1, [0.3, -0.5, 0.8]),
                                    (2, [1.0, 0.0, 0.0, 0.0, 0.0]), (2, [0.2, -0.7, 0.4, 0.5, -0.3])])
-def test_one_electron_channels_in_closed_form(oracle_mod, l, lam):
+def test_one_electron_channels_in_closed_form(oracle_mod, l, lam, native):
+    """Both implementations of the oracle: numpy (oracle.ecp) and the C++
+    oracle's own (native_ecp, used by its VMC and DMC loops)."""
     alpha = 0.7
     sysd = S.ecp_one_centre(l, lam, alpha)
-    o = oracle_mod.Oracle(sysd)
     rng = np.random.default_rng(10 + l)
     d = rng.normal(size=(40, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     R = (d * rng.uniform(0.05, 3.5, size=(40, 1)))[:, None, :]  # both sides of r_cut = 2.5
-    got = ECP.evaluate(o, sysd, R)["eloc"]
+    if native:
+        got = oracle_mod.Oracle(sysd, native_ecp=True).evaluate(R)["eloc"]
+    else:
+        got = ECP.evaluate(oracle_mod.Oracle(sysd), sysd, R)["eloc"]
     want = _closed_form(sysd, R, l, alpha)
     err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
     assert err.max() < 1e-10, err.max()
@@ -118,3 +123,13 @@ def test_f2_valence_system_is_consistent(oracle_mod):
     far["ecp"] = [dict(c, channels=[]) for c in sysd["ecp"]]
     Rf = R + np.array([0.0, 9.0, 0.0])
     np.testing.assert_allclose(ECP.ecp_energy(o, sysd, Rf), ECP.ecp_energy(o, far, Rf), rtol=0, atol=1e-15)
+
+
+def test_native_term_matches_numpy_on_f2_valence(oracle_mod):
+    """The C++ oracle's term (native_ecp) against oracle.ecp on the
+    many-electron system, where no closed form exists."""
+    sysd = S.f2_valence_ecp()
+    R = S.initial_walkers(sysd, 4, seed=6, sigma=1.2)
+    a = oracle_mod.Oracle(sysd, native_ecp=True).evaluate(R)["eloc"]
+    b = ECP.evaluate(oracle_mod.Oracle(sysd), sysd, R)["eloc"]
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
