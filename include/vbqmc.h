@@ -225,11 +225,13 @@ typedef struct {
 
 /* Attach pseudopotentials to a context (replacing earlier ones; NULL or
  * n_centers = 0 removes them).  Synchronises the device first.  With them,
- * vbqmc_evaluate, vbqmc_walkers_init and vbqmc_vmc_advance (all-electron
- * and single-electron moves, both run by the one-workgroup-per-walker
- * kernel) include the pseudopotential energy in E_L; vbqmc_vmc_sweep,
- * vbqmc_vmc_measure, the DMC entry points and vbqmc_param_grad return
- * EINVAL.  Errors: EINVAL (bad centre, channel count, r_cut or term; a
+ * vbqmc_evaluate, vbqmc_walkers_init, vbqmc_vmc_advance (all-electron and
+ * single-electron moves) and the DMC entry points include the
+ * pseudopotential energy in E_L, all on the one-workgroup-per-walker
+ * kernels (step and dmc kernel 1 whatever the options say); in DMC the term
+ * is taken with the trial function (the locality approximation: the nonlocal
+ * part enters the branching weights through E_L only).  vbqmc_vmc_sweep,
+ * vbqmc_vmc_measure and vbqmc_param_grad return EINVAL.  Errors: EINVAL (bad centre, channel count, r_cut or term; a
  * precision form other than FP64; f_een), ENOMEM, EHIP. */
 int vbqmc_set_ecp(vbqmc_ctx* ctx, const vbqmc_ecp* ecp);
 

@@ -31,7 +31,8 @@ hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
                             double step_size, double* es, double* e2s, double* na, double* el, double* sij,
                             hipStream_t s);
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
-                           uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s);
+                           uint32_t step, double tau, const DmcBranch& br, double* nacc, const DevEcp& ecp,
+                           hipStream_t s);
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,
                            int st, double tau, double W_target, double* pop, double* wsum, double* wesum,
                            double* wcsum, double* etrial, double* lacc, double* lprop, double* ld2a, double* ld2p,
@@ -1599,7 +1600,8 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
     return fail(x, VBQMC_EINVAL, "dmc: bad arguments");
   if (!lg->pop || !lg->wsum || !lg->wesum || !lg->etrial || !lg->n_accept || !lg->n_prop)
     return fail(x, VBQMC_EINVAL, "dmc: log pointers missing");
-  if (x->ecp.ncen) return fail(x, VBQMC_EINVAL, "dmc: not available with pseudopotentials");
+  // with pseudopotentials every step runs on the one-workgroup-per-walker kernel
+  const int dk = x->ecp.ncen ? 1 : x->dmc_kernel;
   int64_t W = *W_io;
   if (!x->een.empty() && x->dmc_kernel != 3)
     return fail(x, VBQMC_EINVAL, "dmc: with f_een, DMC needs the walker-resident kernel (a system that fits it)");
@@ -1637,14 +1639,14 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
   double* epw = ekw + cap;
   // rebuild every record from its positions (fresh inverses, local energy and
   // the orbital-gradient rows the drift of the first moves reads)
-  if (x->dmc_kernel == 3)
+  if (dk == 3)
     e = launch_dmcw(dmcw_layout(x), x->d_wf_dmcw, cur, ctrl, cap, seed, 0, tau, br, nacc, 1, s);
-  else if (x->dmc_kernel == 2)
+  else if (dk == 2)
     e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, (size_t)dmcb_layout(x).lds_tile_doubles * 8, cur, ctrl, cap,
                            seed, 0, tau, Vpw, ekw, epw, br, 1, s);
   else
     e = launch_evaluate(x->wf, x->d_wf, x->nt, W, cur + x->wf.r_R, x->wf.rec_len, nullptr, nullptr, nullptr,
-                        nullptr, nullptr, cur, DevEcp{0, nullptr, nullptr, nullptr, -1, 0, 0}, s);
+                        nullptr, nullptr, cur, x->ecp, s);
   if (e != hipSuccess) return hipfail(x, e, "dmc: record refresh");
   // optional per-step timing of the move-and-energy kernels
   std::vector<hipEvent_t> ev;
@@ -1667,9 +1669,9 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
       drop_events();
       return hipfail(x, e, "dmc: timing event");
     }
-    if (x->dmc_kernel == 3) {
+    if (dk == 3) {
       e = launch_dmcw(dmcw_layout(x), x->d_wf_dmcw, cur, ctrl, cap, seed, step, tau, br, nacc, 0, s);
-    } else if (x->dmc_kernel == 2) {
+    } else if (dk == 2) {
       const size_t rows_lds = (size_t)dmcb_layout(x).lds_tile_doubles * 8;
       for (int i = 0; i < x->N && e == hipSuccess; ++i)
         e = launch_dmcb_move(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, i, seed, step, tau, Pw, Vw,
@@ -1678,7 +1680,7 @@ int dmc_advance_impl(vbqmc_ctx* x, void* states[2], int64_t* W_io, int64_t cap, 
         e = launch_dmcb_finish(x->wf, x->d_wf, x->d_wf_dmcb, rows_lds, cur, ctrl, cap, seed, step, tau, Vpw, ekw,
                                epw, br, 0, s);
     } else {
-      e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, br, nacc, s);
+      e = launch_dmc_step(x->wf, x->d_wf, x->nt, cur, ctrl, cap, seed, step, tau, br, nacc, x->ecp, s);
     }
     if (e == hipSuccess && !ev.empty()) e = hipEventRecord(ev[2 * st + 1], s);
     if (e != hipSuccess) {

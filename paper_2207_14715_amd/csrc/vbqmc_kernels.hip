@@ -853,7 +853,7 @@ __device__ void drift(const DevWF& wf, const Ld& l, int i, const double* rows, i
 template <int NT, int PREC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_dmc_step(const DevWF* __restrict__ pwf, double* state, const double* ctrl, int nsteps_done,
                                                  uint64_t seed, uint32_t step, double tau, DmcBranch br,
-                                                 double* nacc) {
+                                                 double* nacc, DevEcp ecp) {
   const DevWF& wf = *pwf;
   int64_t w = blockIdx.x;
   int64_t W = (int64_t)ctrl[DC_W];
@@ -925,6 +925,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     else compute_RWS<NT>(wf, l);
   }
   if (!bad) local_energy<NT, PREC>(wf, l, gc);
+  // pseudopotentials: the projected term with the trial function (locality approximation)
+  if (!bad && ecp.ncen) ecp_add<NT, PREC>(wf, l, ecp);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double En = bad ? NAN : sc[SC_ELOC];
@@ -1148,12 +1150,12 @@ static hipError_t launch_vmc_t(const DevWF& wf, const DevWF* dwf, double* state,
 template <int NT, int PREC>
 static hipError_t launch_dmc_step_t(const DevWF& wf, const DevWF* dwf, double* state, const double* ctrl, int64_t cap, uint64_t seed,
                                     uint32_t step, double tau, const DmcBranch& br, double* nacc,
-                                    hipStream_t s) {
-  size_t lds = (size_t)wf.lds_doubles * sizeof(double);
+                                    const DevEcp& ecp, hipStream_t s) {
+  size_t lds = (size_t)(wf.lds_doubles + (ecp.ncen && ecp.l_scr >= 0 ? ecp.scr_doubles : 0)) * sizeof(double);
   hipError_t e = set_lds<NT, PREC>((const void*)k_dmc_step<NT, PREC>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dmc_step<NT, PREC>), dim3((unsigned)cap), dim3(NT), lds, s, dwf, state, ctrl, 0, seed, step,
-                     tau, br, nacc);
+                     tau, br, nacc, ecp);
   return hipGetLastError();
 }
 
@@ -1246,8 +1248,9 @@ hipError_t launch_vmc_split(const DevWF& wf, const DevWF* dwf, const DevWF* dwf_
 }
 
 hipError_t launch_dmc_step(const DevWF& wf, const DevWF* dwf, int nt, double* state, const double* ctrl, int64_t cap, uint64_t seed,
-                           uint32_t step, double tau, const DmcBranch& br, double* nacc, hipStream_t s) {
-  VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, s)
+                           uint32_t step, double tau, const DmcBranch& br, double* nacc, const DevEcp& ecp,
+                           hipStream_t s) {
+  VB_DISPATCH_NT(nt, launch_dmc_step_t, wf, dwf, state, ctrl, cap, seed, step, tau, br, nacc, ecp, s)
 }
 
 hipError_t launch_dmc_tail(double* ctrl, const DmcBranch& br, const double* nacc, int* offs, int64_t cap, int N,

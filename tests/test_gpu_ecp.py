@@ -4,8 +4,10 @@ ABI on the GPU against the oracle (oracle/ecp.py, which re-evaluates every
 moved configuration from scratch): vbqmc_evaluate on one-electron s, p and d
 systems (closed-form pinned in the oracle's tests) and on the F2 valence
 system; VMC walks (single-electron and all-electron moves) step by step,
-positions and acceptances draw for draw and E_L of every step; the entry
-points that do not take pseudopotentials refuse them."""
+positions and acceptances draw for draw and E_L of every step; a DMC
+trajectory with the term in E_L (locality approximation) against the C++
+oracle's (native_ecp); the entry points that do not take pseudopotentials
+refuse them."""
 
 import numpy as np
 import pytest
@@ -120,8 +122,6 @@ def test_entry_points_without_pseudopotentials_refuse(lib):
         ctx.vmc_sweep(state, 1, 0, 0.3, torch.zeros(4, dtype=torch.float64, device="cuda"))
     with pytest.raises(lib.VBQMCError):
         ctx.param_grad(R)
-    with pytest.raises(lib.VBQMCError):
-        ctx.dmc_advance([state, ctx.walkers_init(R)], 4, 1, 1, 0, 0.01, -30.0, 4)
     bad = [dict(sysd["ecp"][0], center=5)]
     with pytest.raises(lib.VBQMCError):
         ctx.set_ecp(bad)
@@ -133,3 +133,29 @@ def test_entry_points_without_pseudopotentials_refuse(lib):
     with pytest.raises(lib.VBQMCError):
         lib.Context(sysd, precision="fp32")
     torch.cuda.synchronize()
+
+
+def test_dmc_trajectory_with_pseudopotentials(lib, oracle_mod):
+    """Fixed-node DMC on the F2 valence system: E_L with the projected term
+    drives the weights (the locality approximation).  Populations, weights,
+    acceptances, positions and every surviving walker's E_L against the C++
+    oracle with the same term."""
+    import torch
+    from tests.test_gpu_walks import _check_dmc
+    sysd = S.f2_valence_ecp()
+    o = oracle_mod.Oracle(sysd, native_ecp=True)
+    W, steps, tau, seed, step0 = 8, 3, 0.01, 77, 3
+    R0 = _walkers(sysd, W, 8)
+    e0 = o.evaluate(R0)["eloc"]
+    et = float(np.mean(e0))
+    ref = o.dmc(R0, e0, steps, seed, step0, tau, et, W, capacity=4 * W)
+    ctx = lib.Context(sysd)
+    print(f"[ecp dmc] f2 valence W={W} steps={steps}", flush=True)
+    st0 = ctx.new_state(4 * W)
+    st1 = ctx.new_state(4 * W)
+    ctx.walkers_init(torch.from_numpy(R0).cuda(), st0)
+    out = ctx.dmc_advance([st0, st1], W, steps, seed, step0, tau, et, W)
+    R = ctx.positions(st0, out["W"]).cpu().numpy()
+    e_rec = ctx.record_eloc(st0, out["W"]).cpu().numpy()
+    torch.cuda.synchronize()
+    _check_dmc(ref, out, R, e_rec, o)
