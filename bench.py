@@ -578,7 +578,7 @@ def ecp_form(args):
     electrons, Z_eff = 7 per atom, s and p nonlocal channels, r_cut 2.5 bohr,
     12-point rule): evaluate calls of the one-workgroup-per-walker kernel on
     8192 VMC-equilibrated configurations, with and without the
-    pseudopotential term, and VMC steps with it."""
+    pseudopotential term, and VMC and DMC steps with it."""
     import torch
 
     import paper_2207_14715_amd as vb
@@ -605,10 +605,17 @@ def ecp_form(args):
     st1 = ctx.walkers_init(R)
     nst = 2
     _, tv = _timed(lambda: ctx.vmc_advance(st1, nst, 7, 100, 0.4))
+    # DMC steps with the term in the branching E_L (locality approximation)
+    d0, d1 = ctx.new_state(2 * W), ctx.new_state(2 * W)
+    ctx.walkers_init(R, d0)
+    et = float(ctx.evaluate(R, want=("eloc",))["eloc"].mean())
+    ctx.dmc_advance([d0, d1], W, 1, 9, 0, 0.01, et, W)
+    out, td = _timed(lambda: ctx.dmc_advance([d0, d1], W, nst, 9, 1, 0.01, et, W))
     print(json.dumps({"metric": "configurations/s (E_L with pseudopotentials)", "value": W / t,
                       "unit": "configurations/s", "n_gpus": 1, "walkers": W, "dtype": "f64",
                       "evaluate_ms": t * 1e3, "evaluate_without_ecp_ms": t0 * 1e3,
                       "ratio_points_per_config": pts, "vmc_walker_steps_per_s": W * nst / tv,
+                      "dmc_walker_steps_per_s": W * nst / td,
                       "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
                                    "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
                                    "flops_per_config": fl, "traffic": None},
